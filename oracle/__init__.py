@@ -1,0 +1,307 @@
+"""Plain FP64 CPU oracle for the bivariate parsimonious-Matern likelihood path.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It never imports
+the GPU package and the GPU package never imports it; the two share only the
+seeded input generators in ``synthetic/``.
+
+Each function states the passage of the paper it follows:
+
+* ``gamma``, ``bessel_k``, ``matern`` -- the special functions inside Eq. (2)
+  (Section 4.2); the paper gives no evaluation method, the methods used are
+  named in ``oracle.c``.
+* ``theta_scalars`` / ``rho12`` -- Section 4.2, colocated correlation.
+* ``cov_dense`` / ``cov_entries`` -- Eq. (2) laid out as Representation I
+  (Section 5.2).
+* ``potrf`` / ``trsv_lower`` -- the Cholesky factorisation (Section 5.2).
+* ``loglik`` -- Eq. (1).
+* ``cokrige`` -- Eq. (3)-(4), with the predictor MSE of Eq. (5).
+* ``morton_order`` -- the Morton (Z-order) ordering of Section 5.3.
+* ``tlr_truncate_tiles`` -- the per-tile SVD truncation of Section 5.3 (dense
+  SVD, a library primitive), used to separate compression error from
+  factorisation error.
+* ``round_to`` -- emulation of FP32 / BF16 round-to-nearest-even, used to size
+  the mixed-precision error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               "-fno-fast-math", _SRC, "-o", _SO + ".tmp", "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build(force=True)
+    lib = ctypes.CDLL(_SO)
+    D, I64, I = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    P = ctypes.c_void_p
+    sig = {
+        "orc_rgamma1p": (D, [D]),
+        "orc_gamma": (D, [D]),
+        "orc_bessel_k": (D, [D, D]),
+        "orc_matern": (D, [D, D]),
+        "orc_theta_check": (I, [P]),
+        "orc_rho12": (D, [P]),
+        "orc_cross_cov": (D, [P, I, I, D]),
+        "orc_cov_entries": (None, [P, P, P, P, P, I64, P]),
+        "orc_cov_dense": (None, [P, P, I64, P, P]),
+        "orc_potrf": (I64, [P, I64]),
+        "orc_trsv_lower": (None, [P, I64, P]),
+        "orc_trsv_lower_trans": (None, [P, I64, P]),
+        "orc_loglik": (I64, [P, P, P, I64, P, P]),
+        "orc_cokrige": (I64, [P, P, P, I64, P, P, P, I64, P, P]),
+        "orc_num_threads": (I, []),
+        "orc_bessel_k_vec": (None, [D, P, I64, P]),
+        "orc_matern_vec": (None, [D, P, I64, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _theta(theta):
+    t = _f64(theta).reshape(-1)
+    if t.size != 6:
+        raise ValueError("theta must be (sigma11^2, sigma22^2, a, nu11, nu22, beta)")
+    return t
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+# ----------------------------------------------------------- special functions
+
+def rgamma1p(z: float) -> float:
+    """1/Gamma(1+z) for |z| <= 1/2."""
+    return float(_load().orc_rgamma1p(float(z)))
+
+
+def gamma(x: float) -> float:
+    """Gamma(x), x > 0."""
+    return float(_load().orc_gamma(float(x)))
+
+
+def bessel_k(nu: float, x) -> np.ndarray:
+    """Modified Bessel function of the second kind K_nu(x), x > 0."""
+    xa = _f64(np.atleast_1d(x))
+    out = np.empty_like(xa)
+    _load().orc_bessel_k_vec(float(nu), _ptr(xa), xa.size, _ptr(out))
+    return out
+
+
+def matern(x, nu: float) -> np.ndarray:
+    """M(x; nu) = x^nu K_nu(x) / (2^(nu-1) Gamma(nu)), M(0; nu) = 1 (Eq. 2)."""
+    xa = _f64(np.atleast_1d(x))
+    out = np.empty_like(xa)
+    _load().orc_matern_vec(float(nu), _ptr(xa), xa.size, _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------------- theta
+
+def theta_check(theta) -> int:
+    """0 if theta is admissible, else -(1-based index of the offending entry)."""
+    t = _theta(theta)
+    return int(_load().orc_theta_check(_ptr(t)))
+
+
+def rho12(theta) -> float:
+    """Colocated correlation rho_12 (Section 4.2, d = 2)."""
+    t = _theta(theta)
+    return float(_load().orc_rho12(_ptr(t)))
+
+
+def cross_cov(theta, i: int, j: int, h: float) -> float:
+    """C_ij(h), 0-based i, j (Eq. 2)."""
+    t = _theta(theta)
+    return float(_load().orc_cross_cov(_ptr(t), int(i), int(j), float(h)))
+
+
+# ------------------------------------------------------------------ covariance
+
+def cov_dense(x, y, theta) -> np.ndarray:
+    """Dense 2n x 2n Sigma in Representation I (Section 5.2)."""
+    xa, ya, t = _f64(x), _f64(y), _theta(theta)
+    n = xa.size
+    S = np.empty((2 * n, 2 * n), dtype=np.float64)
+    _load().orc_cov_dense(_ptr(xa), _ptr(ya), n, _ptr(t), _ptr(S))
+    return S
+
+
+def cov_entries(x, y, theta, rows, cols) -> np.ndarray:
+    """Sigma[rows[t], cols[t]] one by one (0-based)."""
+    xa, ya, t = _f64(x), _f64(y), _theta(theta)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.empty(r.size, dtype=np.float64)
+    _load().orc_cov_entries(_ptr(xa), _ptr(ya), _ptr(t), _ptr(r), _ptr(c), r.size, _ptr(out))
+    return out
+
+
+# -------------------------------------------------------------- linear algebra
+
+def potrf(A):
+    """Lower Cholesky factor of a dense SPD matrix; returns (L, info)."""
+    L = np.array(A, dtype=np.float64, order="C", copy=True)
+    info = int(_load().orc_potrf(_ptr(L), L.shape[0]))
+    return L, info
+
+
+def trsv_lower(L, b, trans: bool = False) -> np.ndarray:
+    """L^-1 b, or L^-T b with trans=True."""
+    La = _f64(L)
+    out = _f64(b).copy()
+    fn = _load().orc_trsv_lower_trans if trans else _load().orc_trsv_lower
+    fn(_ptr(La), La.shape[0], _ptr(out))
+    return out
+
+
+# ------------------------------------------------------------------ likelihood
+
+def loglik(x, y, z, theta) -> dict:
+    """Eq. (1): {'loglik', 'logdet', 'quad', 'info'}; loglik = -inf if Sigma is
+    not positive definite (info = 1-based first failing pivot)."""
+    xa, ya, za, t = _f64(x), _f64(y), _f64(z), _theta(theta)
+    n = xa.size
+    if za.size != 2 * n:
+        raise ValueError("z must have 2n entries (Representation I)")
+    out = np.zeros(3, dtype=np.float64)
+    info = int(_load().orc_loglik(_ptr(xa), _ptr(ya), _ptr(za), n, _ptr(t), _ptr(out)))
+    if info < 0:
+        raise ValueError("invalid theta (code %d)" % info)
+    return {"loglik": float(out[0]), "logdet": float(out[1]), "quad": float(out[2]),
+            "info": info}
+
+
+def cokrige(x, y, z, theta, x0, y0, with_mse: bool = False):
+    """Eq. (3)-(4): predictions (m, 2); with_mse adds the Eq. (5) MSE per target."""
+    xa, ya, za, t = _f64(x), _f64(y), _f64(z), _theta(theta)
+    x0a, y0a = _f64(x0), _f64(y0)
+    n, m = xa.size, x0a.size
+    zhat = np.empty(2 * m, dtype=np.float64)
+    mse = np.empty(m, dtype=np.float64) if with_mse else None
+    info = int(_load().orc_cokrige(_ptr(xa), _ptr(ya), _ptr(za), n, _ptr(t), _ptr(x0a),
+                                   _ptr(y0a), m, _ptr(zhat),
+                                   _ptr(mse) if with_mse else None))
+    if info != 0:
+        raise ValueError("cokrige failed (code %d)" % info)
+    zhat = zhat.reshape(m, 2)
+    return (zhat, mse) if with_mse else zhat
+
+
+def simulate_z(x, y, theta, eps) -> np.ndarray:
+    """Z = L eps with L the oracle Cholesky factor of Sigma(theta) (data
+    generation for the likelihood workloads)."""
+    L, info = potrf(cov_dense(x, y, theta))
+    if info:
+        raise ValueError("Sigma(theta) is not positive definite (pivot %d)" % info)
+    return L @ _f64(eps)
+
+
+# --------------------------------------------------------------------- ordering
+
+def morton_keys(x, y) -> np.ndarray:
+    """Z-order keys: floor(coord * 2^16) clamped to [0, 2^16 - 1], x bits at even
+    and y bits at odd positions (Section 5.3 names the ordering; the
+    quantisation is this implementation's reading)."""
+    qx = np.clip(np.floor(_f64(x) * 65536.0), 0, 65535).astype(np.uint64)
+    qy = np.clip(np.floor(_f64(y) * 65536.0), 0, 65535).astype(np.uint64)
+    key = np.zeros(qx.shape, dtype=np.uint64)
+    for b in range(16):
+        key |= ((qx >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        key |= ((qy >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return key
+
+
+def morton_order(x, y) -> np.ndarray:
+    """Permutation sorting locations by Morton key; ties keep input order."""
+    return np.argsort(morton_keys(x, y), kind="stable")
+
+
+# -------------------------------------------------------------- approximations
+
+def tlr_truncate_tiles(S: np.ndarray, nb: int, acc: float, max_rank: int):
+    """Section 5.3 TLR compression by per-tile SVD: every off-diagonal tile of
+    the (padded) matrix keeps the singular triplets with s_i > acc (absolute
+    2-norm rule); a tile whose rank would exceed max_rank stays dense.
+    Returns (S_tilde, ranks) with ranks[I, J] (-1 for dense tiles)."""
+    N = S.shape[0]
+    T = (N + nb - 1) // nb
+    St = np.array(S, copy=True)
+    ranks = np.full((T, T), -1, dtype=np.int64)
+    for J in range(T):
+        for I in range(J + 1, T):
+            r0, r1 = I * nb, min(N, (I + 1) * nb)
+            c0, c1 = J * nb, min(N, (J + 1) * nb)
+            U, s, Vt = np.linalg.svd(S[r0:r1, c0:c1], full_matrices=False)
+            k = int(np.sum(s > acc))
+            if k > max_rank:
+                continue
+            ranks[I, J] = k
+            blk = (U[:, :k] * s[:k]) @ Vt[:k, :]
+            St[r0:r1, c0:c1] = blk
+            St[c0:c1, r0:r1] = blk.T
+    return St, ranks
+
+
+def loglik_from_matrix(S: np.ndarray, z) -> dict:
+    """Eq. (1) for an explicitly given covariance matrix (oracle Cholesky)."""
+    N = S.shape[0]
+    L, info = potrf(S)
+    if info:
+        return {"loglik": float("-inf"), "logdet": float("nan"), "quad": float("nan"),
+                "info": info}
+    logdet = 2.0 * float(np.sum(np.log(np.diag(L))))
+    yv = trsv_lower(L, z)
+    q = float(np.dot(yv, yv))
+    return {"loglik": -(N / 2.0) * np.log(2.0 * np.pi) - 0.5 * logdet - 0.5 * q,
+            "logdet": logdet, "quad": q, "info": 0}
+
+
+def round_to(a, fmt: str) -> np.ndarray:
+    """Round FP64 values to FP32 or BF16 (round to nearest, ties to even) and
+    return them as FP64."""
+    a = _f64(a)
+    if fmt == "fp32":
+        return a.astype(np.float32).astype(np.float64)
+    if fmt == "bf16":
+        f = a.astype(np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        lsb = (u >> np.uint64(16)) & np.uint64(1)
+        u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    raise ValueError(fmt)

@@ -1,0 +1,323 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle:
+closed forms, mpmath / scipy / LAPACK routines, the paper's printed numbers,
+invariants and brute force on tiny inputs.  CPU only."""
+import json
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+import scipy.stats
+
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------- Gamma, K_nu
+
+def test_rgamma_series_matches_mpmath(orc):
+    mp.mp.dps = 40
+    for z in np.linspace(-0.5, 0.5, 41):
+        ref = float(mp.rgamma(1 + mp.mpf(float(z))))
+        assert abs(orc.rgamma1p(z) - ref) <= 5e-16 * abs(ref)   # a few ulp of Horner rounding
+
+
+@pytest.mark.parametrize("x", [1e-3, 0.1, 0.3, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.5, 6.0, 9.75])
+def test_gamma_matches_library(orc, x):
+    mp.mp.dps = 40
+    ref = float(mp.gamma(x))
+    assert abs(orc.gamma(x) - ref) <= 4e-16 * ref
+    assert abs(orc.gamma(x) - scipy.special.gamma(x)) <= 1e-15 * ref
+
+
+def test_bessel_k_matches_mpmath_grid(orc):
+    mp.mp.dps = 40
+    xs = np.concatenate([np.logspace(-10, math.log10(700.0), 70), [1.999999, 2.0, 2.000001]])
+    for nu in [0.0, 0.1, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 2.5, 3.0, 3.7]:
+        got = orc.bessel_k(nu, xs)
+        for x, g in zip(xs, got):
+            ref = float(mp.besselk(nu, x))
+            assert abs(g - ref) <= 1e-14 * abs(ref), (nu, x, g, ref)
+
+
+def test_bessel_k_half_integer_closed_forms(orc):
+    x = np.logspace(-6, 2.5, 200)
+    k12 = np.sqrt(np.pi / (2 * x)) * np.exp(-x)
+    np.testing.assert_allclose(orc.bessel_k(0.5, x), k12, rtol=1e-14)
+    np.testing.assert_allclose(orc.bessel_k(1.5, x), k12 * (1 + 1 / x), rtol=1e-14)
+    np.testing.assert_allclose(orc.bessel_k(2.5, x), k12 * (1 + 3 / x + 3 / x ** 2), rtol=1e-14)
+
+
+def test_bessel_k_recurrence_and_scipy(orc):
+    x = np.logspace(-3, 2, 50)
+    for nu in [0.3, 0.75, 1.0, 1.6]:
+        lhs = orc.bessel_k(nu + 1, x)
+        rhs = orc.bessel_k(nu - 1, x) + (2 * nu / x) * orc.bessel_k(nu, x)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-13)
+        np.testing.assert_allclose(orc.bessel_k(nu, x), scipy.special.kv(nu, x), rtol=1e-13)
+
+
+# --------------------------------------------------------------------- Matern
+
+def test_matern_reductions(orc):
+    x = np.concatenate([[0.0, 1e-10], np.logspace(-4, 2.5, 100)])
+    np.testing.assert_allclose(orc.matern(x, 0.5), np.exp(-x), rtol=1e-14)
+    np.testing.assert_allclose(orc.matern(x, 1.5), (1 + x) * np.exp(-x), rtol=1e-14)
+    np.testing.assert_allclose(orc.matern(x, 2.5), (1 + x + x * x / 3) * np.exp(-x), rtol=1e-14)
+    for nu in [0.25, 0.75, 1.0, 2.2]:
+        assert orc.matern(0.0, nu)[0] == 1.0
+        # near 0, M(x) = 1 - O(x^(2 nu)) for nu < 1: compare with mpmath
+        mp.mp.dps = 40
+        ref = float(mp.mpf(1e-10) ** nu * mp.besselk(nu, 1e-10) / (2 ** (nu - 1) * mp.gamma(nu)))
+        assert abs(orc.matern(1e-10, nu)[0] - ref) <= 1e-14
+        # monotone decreasing in x
+        m = orc.matern(np.linspace(0, 10, 400), nu)
+        assert np.all(np.diff(m) < 0)
+
+
+def test_paper_printed_drop_to_0p05(orc):
+    pins = json.load(open(os.path.join(GOLDEN, "paper_pins.json")))["marginal_drop_to_0p05"]
+    th = pins["theta"]
+    for case in pins["cases"]:
+        i = case["variable"]
+        v = orc.cross_cov(th, i, i, case["h"])
+        assert abs(v - case["value"]) <= pins["printed_precision"], (case, v)
+
+
+def test_paper_effective_range_mapping(orc):
+    """ER (distance where the marginal covariance falls to 0.05) grows with a as
+    the paper's ER table says: within 15 % for the two smoothness values used."""
+    pins = json.load(open(os.path.join(GOLDEN, "paper_pins.json")))["effective_range"]
+    for a, er in zip(pins["a"], pins["er"]):
+        ers = []
+        for nu in pins["nu"]:
+            h = scipy.optimize.brentq(lambda h: orc.matern(h / a, nu)[0] - 0.05, 1e-6, 10.0)
+            ers.append(h)
+        assert abs(np.mean(ers) - er) <= 0.15 * er, (a, ers, er)
+
+
+# ---------------------------------------------------------------------- theta
+
+def test_rho12_closed_form_d2(orc):
+    for th in [(1, 1, 0.1, 0.5, 1.0, 0.5), (2, 0.5, 0.3, 1.5, 0.5, -0.8), (1, 1, 0.1, 0.7, 2.2, 0.3)]:
+        nu12 = 0.5 * (th[3] + th[4])
+        ref = th[5] * math.sqrt(th[3] * th[4]) / nu12   # Gamma(v+1)/Gamma(v) = v
+        assert abs(orc.rho12(th) - ref) <= 2e-16 * 4
+    assert abs(orc.rho12(synthetic.THETA_CFG0) - 0.4714045207910317) < 1e-16
+
+
+def test_theta_check(orc):
+    assert orc.theta_check((1, 1, 0.1, 0.5, 1, 0.5)) == 0
+    assert orc.theta_check((0, 1, 0.1, 0.5, 1, 0.5)) == -1
+    assert orc.theta_check((1, -1, 0.1, 0.5, 1, 0.5)) == -2
+    assert orc.theta_check((1, 1, 0.0, 0.5, 1, 0.5)) == -3
+    assert orc.theta_check((1, 1, 0.1, 0.0, 1, 0.5)) == -4
+    assert orc.theta_check((1, 1, 0.1, 0.5, -1, 0.5)) == -5
+    assert orc.theta_check((1, 1, 0.1, 0.5, 1, 1.0)) == -6
+
+
+# ------------------------------------------------------------------ covariance
+
+def test_sigma_structure(orc):
+    x, y = synthetic.jittered_grid(90, seed=3)
+    th = (1.3, 0.7, 0.15, 0.5, 1.0, 0.6)
+    S = orc.cov_dense(x, y, th)
+    assert np.array_equal(S, S.T)
+    assert np.linalg.eigvalsh(S).min() > 0
+    r = orc.rho12(th)
+    blk = np.array([[th[0], r * math.sqrt(th[0] * th[1])], [r * math.sqrt(th[0] * th[1]), th[1]]])
+    for l in range(0, 90, 17):
+        np.testing.assert_allclose(S[2 * l:2 * l + 2, 2 * l:2 * l + 2], blk, rtol=1e-15)
+    # Representation I entry layout, with nu = 1/2 closed form for C_11
+    h = math.hypot(x[5] - x[2], y[5] - y[2])
+    assert abs(S[10, 4] - th[0] * math.exp(-h / th[2])) <= 1e-15 * S[10, 4] * 4
+    rows = np.array([10, 11, 11, 3])
+    cols = np.array([4, 4, 5, 0])
+    np.testing.assert_array_equal(orc.cov_entries(x, y, th, rows, cols), S[rows, cols])
+
+
+# -------------------------------------------------------------- linear algebra
+
+def test_potrf_matches_lapack(orc):
+    g = np.random.default_rng(0)
+    A = g.standard_normal((150, 150))
+    A = A @ A.T + 150 * np.eye(150)
+    L, info = orc.potrf(A)
+    assert info == 0
+    np.testing.assert_allclose(L, np.linalg.cholesky(A), rtol=1e-12, atol=1e-13)
+    b = g.standard_normal(150)
+    np.testing.assert_allclose(orc.trsv_lower(L, b), scipy.linalg.solve_triangular(L, b, lower=True), rtol=1e-12)
+    np.testing.assert_allclose(orc.trsv_lower(L, b, trans=True),
+                               scipy.linalg.solve_triangular(L, b, lower=True, trans="T"), rtol=1e-12)
+
+
+def test_potrf_reports_first_failing_pivot(orc):
+    A = np.diag([4.0, 9.0, -1.0, 5.0])
+    L, info = orc.potrf(A)
+    assert info == 3
+
+
+# ------------------------------------------------------------------ likelihood
+
+def _data(n, seed, th):
+    import oracle
+    x, y = synthetic.jittered_grid(n, seed)
+    p = oracle.morton_order(x, y)
+    x, y = x[p], y[p]
+    z = oracle.simulate_z(x, y, th, synthetic.normal_eps(2 * n, seed))
+    return x, y, z
+
+
+def test_loglik_brute_force_eigen(orc):
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y, z = _data(100, 1, th)
+    r = orc.loglik(x, y, z, th)
+    S = orc.cov_dense(x, y, th)
+    ev = np.linalg.eigvalsh(S)
+    assert abs(r["logdet"] - np.sum(np.log(ev))) <= 1e-10 * abs(r["logdet"]) + 1e-10
+    q = float(z @ np.linalg.solve(S, z))
+    assert abs(r["quad"] - q) <= 1e-9 * q
+    ref = scipy.stats.multivariate_normal(mean=np.zeros(200), cov=S).logpdf(z)
+    assert abs(r["loglik"] - ref) <= 1e-9 * abs(ref)
+
+
+def test_loglik_single_location_closed_form(orc):
+    th = (1.7, 0.4, 0.2, 0.8, 1.3, -0.45)
+    z = np.array([0.3, -1.1])
+    r = orc.loglik([0.5], [0.5], z, th)
+    rho = th[5] * math.sqrt(th[3] * th[4]) / (0.5 * (th[3] + th[4]))
+    c = rho * math.sqrt(th[0] * th[1])
+    det = th[0] * th[1] - c * c
+    q = (th[1] * z[0] ** 2 - 2 * c * z[0] * z[1] + th[0] * z[1] ** 2) / det
+    assert abs(r["logdet"] - math.log(det)) <= 1e-15 * 8
+    assert abs(r["quad"] - q) <= 1e-14 * q
+    assert abs(r["loglik"] - (-math.log(2 * math.pi) - 0.5 * math.log(det) - 0.5 * q)) < 1e-14
+
+
+def test_loglik_beta0_splits_into_univariate_exponential(orc):
+    """beta = 0, nu11 = nu22 = 1/2: the bivariate likelihood is the sum of two
+    univariate exponential-kernel Gaussian likelihoods (scipy, built by hand)."""
+    th = (1.4, 0.6, 0.12, 0.5, 0.5, 0.0)
+    x, y = synthetic.jittered_grid(120, 5)
+    z = synthetic.normal_eps(240, 5)
+    r = orc.loglik(x, y, z, th)
+    D = np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :])
+    tot = 0.0
+    for i in range(2):
+        C = th[i] * np.exp(-D / th[2])
+        tot += scipy.stats.multivariate_normal(mean=np.zeros(120), cov=C).logpdf(z[i::2])
+    assert abs(r["loglik"] - tot) <= 1e-10 * abs(tot)
+
+
+def test_loglik_permutation_invariance_and_scaling(orc):
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y, z = _data(80, 2, th)
+    r = orc.loglik(x, y, z, th)
+    p = np.random.default_rng(1).permutation(80)
+    zp = z.reshape(80, 2)[p].reshape(-1)
+    rp = orc.loglik(x[p], y[p], zp, th)
+    assert abs(rp["loglik"] - r["loglik"]) <= 1e-10 * abs(r["loglik"])
+    c = 2.5
+    rc = orc.loglik(x, y, z, (c, c, 0.1, 0.5, 1.0, 0.5))
+    assert abs(rc["logdet"] - (r["logdet"] + 160 * math.log(c))) <= 1e-10 * abs(rc["logdet"])
+    assert abs(rc["quad"] - r["quad"] / c) <= 1e-10 * r["quad"]
+
+
+def test_loglik_non_spd_duplicate_location(orc):
+    x = np.array([0.1, 0.5, 0.5, 0.9])
+    y = np.array([0.2, 0.3, 0.3, 0.7])
+    r = orc.loglik(x, y, np.ones(8), (1, 1, 0.1, 0.5, 1.0, 0.5))
+    assert r["loglik"] == -np.inf and r["info"] > 0
+
+
+# ------------------------------------------------------------------- cokriging
+
+def test_cokrige_interpolates_observed_sites(orc):
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y, z = _data(60, 4, th)
+    idx = np.array([0, 17, 59])
+    zhat, mse = orc.cokrige(x, y, z, th, x[idx], y[idx], with_mse=True)
+    np.testing.assert_allclose(zhat, z.reshape(60, 2)[idx], rtol=1e-8, atol=1e-8)
+    assert np.all(np.abs(mse) < 1e-8)
+
+
+def test_cokrige_far_target_and_mse_bounds(orc):
+    th = (1.0, 1.0, 0.05, 0.5, 1.0, 0.5)
+    x, y, z = _data(60, 4, th)
+    zhat, mse = orc.cokrige(x, y, z, th, [50.0], [50.0], with_mse=True)
+    assert np.all(np.abs(zhat) < 1e-100)
+    assert abs(mse[0] - 2.0) < 1e-12
+    x0, y0 = synthetic.uniform_targets(20, 9)
+    _, mse = orc.cokrige(x, y, z, th, x0, y0, with_mse=True)
+    assert np.all(mse > -1e-12) and np.all(mse <= 2.0 + 1e-12)
+
+
+def test_cokrige_beta0_is_univariate_kriging(orc):
+    th = (1.0, 2.0, 0.1, 0.5, 0.5, 0.0)
+    x, y = synthetic.jittered_grid(70, 8)
+    z = synthetic.normal_eps(140, 8)
+    x0, y0 = synthetic.uniform_targets(5, 8)
+    zhat = orc.cokrige(x, y, z, th, x0, y0)
+    D = np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :])
+    D0 = np.hypot(x0[:, None] - x[None, :], y0[:, None] - y[None, :])
+    for i in range(2):
+        C = th[i] * np.exp(-D / th[2])
+        c0 = th[i] * np.exp(-D0 / th[2])
+        ref = c0 @ np.linalg.solve(C, z[i::2])
+        np.testing.assert_allclose(zhat[:, i], ref, rtol=1e-9, atol=1e-12)
+
+
+# -------------------------------------------------------------------- ordering
+
+def test_morton_brute_force():
+    import oracle
+    # 4 x 4 lattice at cell centres: the Z-curve visits x fastest within each 2x2 block
+    xs, ys = np.meshgrid((np.arange(4) + 0.5) / 4, (np.arange(4) + 0.5) / 4, indexing="xy")
+    x, y = xs.reshape(-1), ys.reshape(-1)
+    p = oracle.morton_order(x, y)
+    qx = (x[p] * 4).astype(int)
+    qy = (y[p] * 4).astype(int)
+    want = []
+    for k in range(16):
+        bx = (k & 1) | ((k >> 2) & 1) << 1
+        by = ((k >> 1) & 1) | ((k >> 3) & 1) << 1
+        want.append((bx, by))
+    assert list(zip(qx, qy)) == want
+    # ties keep input order; clamp at 1.0
+    p2 = oracle.morton_order([0.3, 0.3, 1.0, 0.0], [0.3, 0.3, 1.0, 0.0])
+    assert list(p2) == [3, 0, 1, 2]
+
+
+# ------------------------------------------------------------- approximations
+
+def test_tlr_truncation_tight_accuracy_is_exact(orc):
+    th = (1.0, 1.0, 0.09, 0.5, 1.0, 0.5)
+    x, y, z = _data(96, 6, th)
+    S = orc.cov_dense(x, y, th)
+    St, ranks = orc.tlr_truncate_tiles(S, 48, 1e-300, 48)
+    np.testing.assert_allclose(St, S, atol=1e-13)
+    r_exact = orc.loglik_from_matrix(S, z)
+    r_ref = orc.loglik(x, y, z, th)
+    assert abs(r_exact["loglik"] - r_ref["loglik"]) <= 1e-10 * abs(r_ref["loglik"])
+    # looser accuracy: smaller ranks, errors shrink as accuracy tightens
+    errs = []
+    for acc in (1e-3, 1e-5, 1e-7, 1e-9):
+        St, rk = orc.tlr_truncate_tiles(S, 48, acc, 48)
+        errs.append(abs(orc.loglik_from_matrix(St, z)["loglik"] - r_ref["loglik"]))
+    assert errs[-1] <= errs[0]
+
+
+def test_round_to_formats(orc):
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, 3.14159265358979, -2.0 ** -130])
+    b = orc.round_to(v, "bf16")
+    assert b[0] == 1.0
+    assert b[1] == 1.0 + 2 ** -7 or b[1] == 1.0   # tie to even -> 1.0
+    assert b[1] == 1.0
+    assert b[2] == 1.0 + 2 ** -7                  # tie to even (odd -> up)
+    assert abs(b[3] - 3.140625) < 1e-12
+    f = orc.round_to(v, "fp32")
+    assert f[3] == float(np.float32(3.14159265358979))
