@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the bivariate Matern log-likelihood hot path on one MI355X.
+
+One step = one likelihood evaluation l(theta) of the dense FP64 workload
+(N = 25,600 Morton-ordered jittered-grid locations, 51,200 x 51,200
+covariance: tile generation, tiled Cholesky, log-determinant, triangular
+solve) plus cokriging of 100 held-out locations on the resident factor.
+Inputs are synthetic and resident in HBM before the timed region.
+
+Prints one JSON line: evals/s, the Cholesky TFLOP/s, the roofline of the
+dominant kernel (trailing-update GEMM/SYRK on FP64 MFMA) from HIP events on
+the stream each launch runs on, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def cpu_baseline(n_full, sample_n, theta, seed):
+    """Oracle (as is) on the leading sample_n locations of the same workload,
+    scaled to evals/s at n_full by the O(n^3) cost of the factorisation."""
+    import numpy as np
+
+    import oracle
+    import synthetic
+    x, y = synthetic.jittered_grid(n_full, seed)
+    p = oracle.morton_order(x, y)
+    x, y = x[p][:sample_n], y[p][:sample_n]
+    z = synthetic.normal_eps(2 * sample_n, seed)
+    t0 = time.perf_counter()
+    oracle.loglik(x, y, z, theta)
+    dt = time.perf_counter() - t0
+    scale = (sample_n / n_full) ** 3
+    return {"value": scale / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "one oracle loglik at N=%d (first %d Morton-ordered locations of the "
+                      "N=%d workload) took %.2f s; scaled by (%d/%d)^3" %
+                      (sample_n, sample_n, n_full, dt, sample_n, n_full)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=25600)
+    ap.add_argument("--a", type=float, default=0.1)
+    ap.add_argument("--nb", type=int, default=512)
+    ap.add_argument("--targets", type=int, default=100)
+    ap.add_argument("--cpu-sample-n", type=int, default=2400)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the factorisation would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2008_07437_amd as mvg
+    import synthetic
+
+    torch.cuda.set_device(0)
+    th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
+    n = args.n
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
+    # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    A = mvg.cov_generate(xs, ys, th, {"nb": args.nb})
+    info = mvg.potrf_tiled(A)
+    if info:
+        raise SystemExit("Sigma(theta) not positive definite at pivot %d" % info)
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    del A
+    x0r, y0r = synthetic.uniform_targets(args.targets, args.seed)
+    x0, y0 = dev(x0r), dev(y0r)
+    opts = {"nb": args.nb}
+    torch.cuda.synchronize()
+
+    last = {}
+
+    def step():
+        res, F = mvg.loglik(xs, ys, z, th, opts, keep=True)
+        zhat = mvg.cokrige_predict(F, x0, y0)
+        last["loglik"] = float(res["loglik"][0])
+        last["zhat0"] = zhat[0].tolist()
+        del F
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mvg.mvg_prof_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {k: mvg.mvg_prof_read(k) for k in ("trailing", "gen", "potrf", "solve", "cokrige")}
+    mvg.mvg_prof_enable(False)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    N = 2 * n
+    chol_flops = N ** 3 / 3.0
+    potrf_ms = prof["potrf"]["ms"] / max(1, prof["potrf"]["launches"])
+    tr = prof["trailing"]
+    achieved = tr["flops"] / (tr["ms"] * 1e-3) / 1e12 if tr["ms"] > 0 else None
+    out = {
+        "metric": "loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+        "value": args.steps / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense FP64 bivariate Matern loglik + cokriging, N=%d locations "
+                               "(%dx%d covariance), theta=(1,1,%g,0.5,1,0.5), nb=%d, %d targets"
+                               % (n, N, N, args.a, args.nb, args.targets),
+                   "n_loc": n, "matrix": N, "nb": args.nb, "precision": "fp64",
+                   "parallelism": "single GPU"},
+        "cholesky_tflops": chol_flops / (potrf_ms * 1e-3) / 1e12,
+        "phases_ms_per_step": {k: prof[k]["ms"] / max(1, args.steps)
+                               for k in ("gen", "potrf", "solve", "cokrige")},
+        "loglik": last["loglik"],
+        "roofline": {"kernel": "k_update_trailing", "bound": "mfma",
+                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
+                     "traffic": None,
+                     "launches": tr["launches"],
+                     "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
+                     "flops_per_launch": tr["flops"] / max(1, tr["launches"])},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

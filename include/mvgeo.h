@@ -1,0 +1,190 @@
+/*
+ * mvgeo.h -- C ABI of the MI355X (gfx950) library for the bivariate
+ * parsimonious-Matern Gaussian log-likelihood, its tile-low-rank (TLR) and
+ * mixed-precision variants, and the cokriging predictor built on the same
+ * Cholesky factor (arxiv 2008.07437).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers named d_* are device pointers (HBM of the current HIP device);
+ * pointers named h_* are host pointers.  Device inputs are owned by the caller
+ * and must stay valid until the work enqueued on `hip_stream` has finished.
+ * `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Host outputs are valid when the call returns: the call synchronises the
+ * stream before writing them.
+ *
+ * Locations are n_loc points (d_x[l], d_y[l]) in R^2, l = 0..n_loc-1.  The
+ * observation vector follows Representation I (Section 5.2): Z has 2*n_loc
+ * entries, Z[2l+i] = Z_{i+1}(s_l).  The covariance Sigma(theta) is 2n x 2n
+ * with Sigma[2l+i, 2r+j] = C_ij(||s_l - s_r||) (Eq. 2).
+ *
+ * Return codes (LAPACK style): 0 = success; -i = argument i (1-based) is
+ * invalid; > 0 = numerical failure: the 1-based global index of the first
+ * non-positive pivot of the Cholesky factorisation (Sigma not positive
+ * definite); MVG_ERR_* (< -100) = runtime failure (allocation, launch).  No
+ * call aborts or prints; mvg_last_error() returns the message of the last
+ * failure on the calling thread.
+ */
+#ifndef MVGEO_H
+#define MVGEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MVG_ERR_ALLOC   (-101)
+#define MVG_ERR_LAUNCH  (-102)
+#define MVG_ERR_STATE   (-103)
+#define MVG_ERR_LIMIT   (-104)
+
+/* theta in the paper's order (Section 4.2): marginal variances sigma11^2 and
+ * sigma22^2, shared spatial range a, smoothnesses nu11 and nu22, and the latent
+ * colocated correlation beta (|beta| < 1 for p = 2).  Admissible values:
+ * sigma_ii^2 > 0, a > 0, 0 < nu_ii <= 5, |beta| < 1. */
+typedef struct {
+    double sigma11_sq, sigma22_sq, a, nu11, nu22, beta;
+} mvg_theta;
+
+/* Arithmetic of the factorisation. */
+enum {
+    MVG_FP64 = 0,        /* exact dense FP64 (Section 5.2)                          */
+    MVG_MIXED_FP32 = 1,  /* FP64 band tiles, FP32 off-band tiles, FP64 refinement   */
+    MVG_MIXED_BF16 = 2,  /* FP64 band, off-band GEMMs on BF16 operands, FP32 accum. */
+    MVG_TLR = 3          /* tile low-rank, FP64 (Section 5.3)                       */
+};
+
+typedef struct {
+    int precision;      /* MVG_FP64 / MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_TLR        */
+    int nb;             /* tile size; dense and mixed: multiple of 128 (0 = 512);     */
+                        /* TLR: even, >= 64 (0 = 1200)                                 */
+    int band_tiles;     /* mixed: tiles with |I - J| < band_tiles stay FP64 (0 = 2)   */
+    double tlr_acc;     /* TLR: absolute singular-value threshold (0 = 1e-7)          */
+    int tlr_max_rank;   /* TLR: larger ranks keep the tile dense (0 = 300)            */
+    uint64_t seed;      /* TLR: seed of the randomized-SVD sketch                      */
+    int ir_max_iter;    /* mixed: iterative-refinement sweeps (0 = 20)                 */
+    double ir_tol;      /* mixed: stop when ||r|| <= ir_tol ||Z|| (0 = 1e-14)          */
+} mvg_opts;
+
+/* Library-owned device matrix: the lower tiles of Sigma (dense, mixed or TLR).
+ * Freed only by mvg_mat_destroy. */
+typedef struct mvg_mat mvg_mat;
+
+/* Library-owned resident factor: the Cholesky factor L of Sigma(theta), the
+ * locations it was built on, theta, and w = Sigma^-1 Z.  Freed only by
+ * mvg_factor_destroy.  Used by cokrige_predict. */
+typedef struct mvg_factor mvg_factor;
+
+/* Morton (Z-order) permutation of the locations (Section 5.3 orders the
+ * locations this way to lower tile ranks).  Coordinates are quantised as
+ * floor(v * 2^16) clamped to [0, 65535]; x bits go to the even and y bits to
+ * the odd key bits; equal keys keep input order.  d_perm (n_loc int64,
+ * caller-owned) receives the sorted-to-input index map; d_xs, d_ys (nullable,
+ * n_loc FP64 each, caller-owned, not aliasing d_x / d_y) receive the
+ * locations in Morton order.  Requires n_loc <= 2^26.  Returns 0, -1..-6 for
+ * bad arguments, MVG_ERR_*. */
+int morton_order(const double *d_x, const double *d_y, int64_t n_loc,
+                 int64_t *d_perm, double *d_xs, double *d_ys, void *hip_stream);
+
+/* Generate the lower tiles of Sigma(theta) (Eq. 2, Representation I) into a
+ * new library-owned matrix *out.  The layout is tile-major: nb x nb tiles,
+ * column-major inside a tile, lower tiles only; 2n is padded up to a multiple
+ * of nb with an identity block (log-determinant and quadratic form
+ * unchanged).  Mixed precision stores off-band tiles in FP32.  TLR returns
+ * dense tiles (compress with tlr_compress).  Returns 0, -1..-7, MVG_ERR_*. */
+int cov_generate(const double *d_x, const double *d_y, int64_t n_loc,
+                 const mvg_theta *th, const mvg_opts *o, mvg_mat **out,
+                 void *hip_stream);
+
+/* In-place tiled Cholesky Sigma = L L^T of a matrix from cov_generate
+ * (POTRF / TRSM / SYRK / GEMM tile tasks, Section 5.1).  *h_info receives 0
+ * or the 1-based index of the first non-positive pivot.  Returns 0 (also when
+ * *h_info > 0), -1..-3, MVG_ERR_*. */
+int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream);
+
+/* Eq. (1) for n_theta parameter vectors on one dataset:
+ *   l(theta) = -n_loc log(2 pi) - 1/2 log|Sigma| - 1/2 Z^T Sigma^-1 Z.
+ * d_z: 2*n_loc FP64 in Representation I.  Host outputs (n_theta each):
+ * h_loglik, h_logdet, h_quad (nullable), h_status (nullable: 0 or the pivot
+ * index; a failing theta gets h_loglik = -inf).  n_theta > 1 evaluates all
+ * theta in one batched launch sequence (bitwise equal to n_theta separate
+ * calls).  keep (nullable, n_theta == 1 only) receives a resident factor for
+ * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*. */
+int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+           const mvg_theta *th, int n_theta, const mvg_opts *o,
+           double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
+           mvg_factor **keep, void *hip_stream);
+
+/* TLR compression (Section 5.3) of the off-diagonal tiles of Sigma(theta) by
+ * randomized SVD with absolute truncation s_i > tlr_acc; tiles needing a rank
+ * above tlr_max_rank stay dense.  h_ranks (nullable, T*T int32, row-major,
+ * -1 = dense) receives the ranks.  Returns 0, -1..-8, MVG_ERR_*. */
+int tlr_compress(const double *d_x, const double *d_y, int64_t n_loc,
+                 const mvg_theta *th, const mvg_opts *o, mvg_mat **out,
+                 int32_t *h_ranks, void *hip_stream);
+
+/* Cokriging predictor Eq. (3)-(4) on a resident factor:
+ *   Zhat(s0) = c0^T Sigma^-1 Z,  c0[2r+i, j] = C_ij(||s0 - s_r||).
+ * d_x0, d_y0: m targets (device).  d_zhat: 2m FP64, (Zhat_1, Zhat_2) per
+ * target.  d_mse (nullable): m FP64 predictor MSE tr{C(0) - c0^T Sigma^-1 c0}
+ * (Eq. 5).  Returns 0, -1..-7, MVG_ERR_*. */
+int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0,
+                    int64_t m, double *d_zhat, double *d_mse, void *hip_stream);
+
+/* d_z <- L d_eps for a factored dense matrix (lower factor L of Sigma):
+ * draws Z ~ N(0, Sigma) from a standard-normal d_eps (2n FP64, device), the
+ * data generator of the paper's synthetic experiments (Section 6.4).
+ * Returns 0, -1..-3, MVG_ERR_*. */
+int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_stream);
+
+/* HBM bytes the library allocates for one likelihood evaluation of n_loc
+ * locations with these options (matrix + workspaces), for admission control. */
+size_t mvg_footprint(int64_t n_loc, const mvg_opts *o);
+
+/* Shape of a matrix: n_loc, tile size, tile count per side, precision,
+ * factored flag.  Any output pointer may be NULL. */
+int mvg_mat_shape(const mvg_mat *A, int64_t *n_loc, int *nb, int *ntiles,
+                  int *precision, int *factored);
+
+/* Gather m entries (row[t], col[t]), 0-based, row >= col, of the stored lower
+ * triangle (Sigma before potrf_tiled, L after) into d_out.  Dense and mixed
+ * matrices only.  Returns 0, -1..-5, MVG_ERR_*. */
+int mvg_mat_gather(const mvg_mat *A, const int64_t *d_rows, const int64_t *d_cols,
+                   int64_t m, double *d_out, void *hip_stream);
+
+/* Expand the lower triangle into a dense column-major 2n x 2n buffer d_out
+ * (leading dimension ld >= 2n); the strict upper triangle is set to 0.
+ * TLR tiles are expanded as U V^T.  Returns 0, -1..-3, MVG_ERR_*. */
+int mvg_mat_to_dense(const mvg_mat *A, double *d_out, int64_t ld, void *hip_stream);
+
+/* Resident factor accessors: the underlying matrix (factored), n_loc, and
+ * w = Sigma^-1 Z (device pointer owned by the factor). */
+const mvg_mat *mvg_factor_mat(const mvg_factor *F);
+const double *mvg_factor_w(const mvg_factor *F);
+
+void mvg_mat_destroy(mvg_mat *A);
+void mvg_factor_destroy(mvg_factor *F);
+
+/* Diagnostics: timing of kernel launches with HIP events recorded on the
+ * stream each launch is enqueued on.  mvg_prof_enable(1) clears the records
+ * and starts recording, mvg_prof_enable(0) stops.  mvg_prof_read sums the
+ * records of one kind: MVG_PROF_TRAILING (the trailing-update GEMM/SYRK
+ * kernel, the FLOP sink of the factorisation), MVG_PROF_GEN (covariance
+ * generation), MVG_PROF_POTRF (whole factorisation), MVG_PROF_SOLVE (solve and
+ * reductions), MVG_PROF_COKRIGE.  *flops and *bytes are algorithmic counts
+ * (useful work, no padding).  Synchronises the device. */
+enum { MVG_PROF_TRAILING = 0, MVG_PROF_GEN = 1, MVG_PROF_POTRF = 2, MVG_PROF_SOLVE = 3,
+       MVG_PROF_COKRIGE = 4, MVG_PROF_NKINDS = 5 };
+int mvg_prof_enable(int on);
+int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, double *bytes);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *mvg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVGEO_H */

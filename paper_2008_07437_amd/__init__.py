@@ -1,0 +1,15 @@
+"""MI355X (gfx950) library for the bivariate parsimonious-Matern Gaussian
+log-likelihood (arxiv 2008.07437): covariance generation, tiled Cholesky,
+log-determinant and solve, TLR and mixed-precision variants, cokriging.
+
+The compute path is the HIP library ``libmvgeo.so`` (C ABI in
+``include/mvgeo.h``); this package only marshals torch tensors (device memory
+and the current stream) into those calls.  There is no CPU fallback: without
+the built library or a GPU every call raises.
+"""
+from ._lib import (  # noqa: F401
+    MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR,
+    Opts, Theta, Mat, Factor, MvgError,
+    library_path, morton_order, cov_generate, potrf_tiled, loglik, tlr_compress,
+    cokrige_predict, mvg_footprint, mvg_trmv, mvg_prof_enable, mvg_prof_read,
+)

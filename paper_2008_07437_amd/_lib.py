@@ -1,0 +1,309 @@
+"""ctypes binding of libmvgeo.so: same names as the C ABI, argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libmvgeo.so")
+
+MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR = 0, 1, 2, 3
+
+c_double, c_int, c_int64, c_void_p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+
+
+class MvgError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s failed with code %d: %s" % (fn, code, msg))
+        self.code = code
+
+
+class Theta(ctypes.Structure):
+    """theta = (sigma11^2, sigma22^2, a, nu11, nu22, beta) in the paper's order."""
+    _fields_ = [("sigma11_sq", c_double), ("sigma22_sq", c_double), ("a", c_double),
+                ("nu11", c_double), ("nu22", c_double), ("beta", c_double)]
+
+    @classmethod
+    def of(cls, t) -> "Theta":
+        t = [float(v) for v in t]
+        if len(t) != 6:
+            raise ValueError("theta needs 6 entries")
+        return cls(*t)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("nb", c_int), ("band_tiles", c_int),
+                ("tlr_acc", c_double), ("tlr_max_rank", c_int), ("seed", ctypes.c_uint64),
+                ("ir_max_iter", c_int), ("ir_tol", c_double)]
+
+    @classmethod
+    def make(cls, precision=MVG_FP64, nb=0, band_tiles=0, tlr_acc=0.0, tlr_max_rank=0, seed=0,
+             ir_max_iter=0, ir_tol=0.0) -> "Opts":
+        return cls(int(precision), int(nb), int(band_tiles), float(tlr_acc), int(tlr_max_rank),
+                   int(seed), int(ir_max_iter), float(ir_tol))
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise ImportError("libmvgeo.so is not built (run __graft_entry__.build() or "
+                          "python paper_2008_07437_amd/build.py)")
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: the gfx950 library needs an MI355X GPU")
+    lib = ctypes.CDLL(_SO)
+    P = c_void_p
+    sig = {
+        "morton_order": (c_int, [P, P, c_int64, P, P, P, P]),
+        "mvg_trmv": (c_int, [P, P, P, P]),
+        "cov_generate": (c_int, [P, P, c_int64, P, P, P, P]),
+        "potrf_tiled": (c_int, [P, P, P, P]),
+        "loglik": (c_int, [P, P, P, c_int64, P, c_int, P, P, P, P, P, P, P]),
+        "tlr_compress": (c_int, [P, P, c_int64, P, P, P, P, P]),
+        "cokrige_predict": (c_int, [P, P, P, c_int64, P, P, P]),
+        "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
+        "mvg_mat_shape": (c_int, [P, P, P, P, P, P]),
+        "mvg_mat_gather": (c_int, [P, P, P, c_int64, P, P]),
+        "mvg_mat_to_dense": (c_int, [P, P, c_int64, P]),
+        "mvg_factor_mat": (P, [P]),
+        "mvg_factor_w": (P, [P]),
+        "mvg_mat_destroy": (None, [P]),
+        "mvg_factor_destroy": (None, [P]),
+        "mvg_last_error": (ctypes.c_char_p, []),
+        "mvg_prof_enable": (c_int, [c_int]),
+        "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, rc: int):
+    if rc != 0:
+        raise MvgError(fn, rc, (_load().mvg_last_error() or b"").decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("%s must be contiguous float64" % name)
+    return c_void_p(t.data_ptr())
+
+
+def _opts(opts):
+    if opts is None:
+        return Opts.make()
+    if isinstance(opts, dict):
+        return Opts.make(**opts)
+    return opts
+
+
+class Mat:
+    """Library-owned tile matrix (freed on garbage collection)."""
+
+    def __init__(self, handle):
+        self._h = c_void_p(handle) if not isinstance(handle, c_void_p) else handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shape(self):
+        n, nb, T, prec, fac = c_int64(), c_int(), c_int(), c_int(), c_int()
+        _check("mvg_mat_shape", _load().mvg_mat_shape(self._h, ctypes.byref(n), ctypes.byref(nb),
+                                                     ctypes.byref(T), ctypes.byref(prec),
+                                                     ctypes.byref(fac)))
+        return {"n_loc": n.value, "nb": nb.value, "ntiles": T.value, "precision": prec.value,
+                "factored": bool(fac.value)}
+
+    def gather(self, rows, cols, stream=None) -> torch.Tensor:
+        r = torch.as_tensor(np.asarray(rows, dtype=np.int64)).cuda()
+        c = torch.as_tensor(np.asarray(cols, dtype=np.int64)).cuda()
+        out = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        _check("mvg_mat_gather", _load().mvg_mat_gather(self._h, c_void_p(r.data_ptr()),
+                                                       c_void_p(c.data_ptr()), r.numel(),
+                                                       c_void_p(out.data_ptr()), _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def to_dense(self, stream=None) -> torch.Tensor:
+        """Lower triangle as a dense (2n, 2n) tensor (strict upper part 0)."""
+        N = 2 * self.shape()["n_loc"]
+        buf = torch.empty((N, N), dtype=torch.float64, device="cuda")  # column-major view
+        _check("mvg_mat_to_dense", _load().mvg_mat_to_dense(self._h, c_void_p(buf.data_ptr()), N,
+                                                           _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return buf.t()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None and self._h.value:
+            _lib.mvg_mat_destroy(self._h)
+            self._h = c_void_p(0)
+
+
+class Factor:
+    """Resident factor from loglik(keep=True); reusable by cokrige_predict."""
+
+    def __init__(self, handle):
+        self._h = c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def w(self, n: int) -> torch.Tensor:
+        """w = Sigma^-1 Z (first 2n entries), copied out."""
+        ptr = _load().mvg_factor_w(self._h)
+        out = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        _memcpy_d2d(out.data_ptr(), ptr, 8 * 2 * n)
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None and self._h.value:
+            _lib.mvg_factor_destroy(self._h)
+            self._h = c_void_p(0)
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = c_int
+        _hip.hipMemcpy.argtypes = [c_void_p, c_void_p, ctypes.c_size_t, c_int]
+    torch.cuda.current_stream().synchronize()
+    rc = _hip.hipMemcpy(c_void_p(dst), c_void_p(src), nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RuntimeError("hipMemcpy failed (%d)" % rc)
+
+
+# ---------------------------------------------------------------- entry points
+
+def morton_order(x: torch.Tensor, y: torch.Tensor, sorted_xy=False, stream=None):
+    """Morton permutation; with sorted_xy=True also the reordered (x, y)."""
+    n = x.numel()
+    perm = torch.empty(n, dtype=torch.int64, device=x.device)
+    xs = torch.empty_like(x) if sorted_xy else None
+    ys = torch.empty_like(y) if sorted_xy else None
+    _check("morton_order", _load().morton_order(
+        _dev_f64(x, "x"), _dev_f64(y, "y"), n, c_void_p(perm.data_ptr()),
+        c_void_p(xs.data_ptr()) if sorted_xy else None,
+        c_void_p(ys.data_ptr()) if sorted_xy else None, _stream(stream)))
+    return (perm, xs, ys) if sorted_xy else perm
+
+
+def mvg_trmv(mat: "Mat", eps: torch.Tensor, stream=None) -> torch.Tensor:
+    """Z = L eps on a factored matrix (data simulation)."""
+    z = torch.empty_like(eps)
+    _check("mvg_trmv", _load().mvg_trmv(mat.handle, _dev_f64(eps, "eps"), c_void_p(z.data_ptr()),
+                                       _stream(stream)))
+    return z
+
+
+def cov_generate(x, y, theta, opts=None, stream=None) -> Mat:
+    h = c_void_p()
+    th = Theta.of(theta)
+    o = _opts(opts)
+    _check("cov_generate", _load().cov_generate(_dev_f64(x, "x"), _dev_f64(y, "y"), x.numel(),
+                                               ctypes.byref(th), ctypes.byref(o), ctypes.byref(h),
+                                               _stream(stream)))
+    return Mat(h)
+
+
+def potrf_tiled(mat: Mat, opts=None, stream=None) -> int:
+    info = c_int64()
+    o = _opts(opts)
+    _check("potrf_tiled", _load().potrf_tiled(mat.handle, ctypes.byref(o), ctypes.byref(info),
+                                             _stream(stream)))
+    return int(info.value)
+
+
+def loglik(x, y, z, thetas, opts=None, keep=False, stream=None):
+    """Eq. (1) for one theta (6 numbers) or a batch (k x 6).  Returns a dict of
+    numpy arrays {'loglik', 'logdet', 'quad', 'status'} and, with keep=True
+    (single theta), the resident Factor as a second value."""
+    th = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+    k = th.shape[0]
+    arr = (Theta * k)(*[Theta.of(t) for t in th])
+    ll = np.zeros(k)
+    ld = np.zeros(k)
+    q = np.zeros(k)
+    st = np.zeros(k, dtype=np.int64)
+    o = _opts(opts)
+    fh = c_void_p()
+    rc = _load().loglik(_dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"), x.numel(),
+                        arr, k, ctypes.byref(o), ll.ctypes.data_as(c_void_p),
+                        ld.ctypes.data_as(c_void_p), q.ctypes.data_as(c_void_p),
+                        st.ctypes.data_as(c_void_p), ctypes.byref(fh) if keep else None,
+                        _stream(stream))
+    _check("loglik", rc)
+    res = {"loglik": ll, "logdet": ld, "quad": q, "status": st}
+    if keep:
+        return res, (Factor(fh.value) if fh.value else None)
+    return res
+
+
+def tlr_compress(x, y, theta, opts=None, stream=None):
+    h = c_void_p()
+    th = Theta.of(theta)
+    o = _opts(opts)
+    N = 2 * x.numel()
+    T = (N + (o.nb or 1200) - 1) // (o.nb or 1200)
+    ranks = np.zeros((T, T), dtype=np.int32)
+    _check("tlr_compress", _load().tlr_compress(_dev_f64(x, "x"), _dev_f64(y, "y"), x.numel(),
+                                               ctypes.byref(th), ctypes.byref(o), ctypes.byref(h),
+                                               ranks.ctypes.data_as(c_void_p), _stream(stream)))
+    return Mat(h), ranks
+
+
+def cokrige_predict(factor: Factor, x0, y0, with_mse=False, stream=None):
+    m = x0.numel()
+    zhat = torch.empty(2 * m, dtype=torch.float64, device=x0.device)
+    mse = torch.empty(m, dtype=torch.float64, device=x0.device) if with_mse else None
+    _check("cokrige_predict", _load().cokrige_predict(
+        factor.handle, _dev_f64(x0, "x0"), _dev_f64(y0, "y0"), m, c_void_p(zhat.data_ptr()),
+        c_void_p(mse.data_ptr()) if with_mse else None, _stream(stream)))
+    zhat = zhat.view(m, 2)
+    return (zhat, mse) if with_mse else zhat
+
+
+PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4}
+
+
+def mvg_prof_enable(on: bool = True):
+    _check("mvg_prof_enable", _load().mvg_prof_enable(1 if on else 0))
+
+
+def mvg_prof_read(kind: str) -> dict:
+    n, ms, fl, by = c_int64(), c_double(), c_double(), c_double()
+    _check("mvg_prof_read", _load().mvg_prof_read(PROF_KINDS[kind], ctypes.byref(n),
+                                                 ctypes.byref(ms), ctypes.byref(fl),
+                                                 ctypes.byref(by)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+def mvg_footprint(n_loc: int, opts=None) -> int:
+    o = _opts(opts)
+    return int(_load().mvg_footprint(int(n_loc), ctypes.byref(o)))

@@ -1,0 +1,630 @@
+// C ABI entry points (declared in include/mvgeo.h): argument checking, the
+// library-owned matrices and factors, and the orchestration of the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "mvgeo_internal.h"
+
+namespace mvg {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch %s failed: %s", what, hipGetErrorString(e));
+    return MVG_ERR_LAUNCH;
+  }
+  return 0;
+}
+
+hipStream_t side_stream() {
+  static thread_local hipStream_t s = nullptr;
+  static thread_local int dev = -1;
+  int cur = 0;
+  hipGetDevice(&cur);
+  if (!s || dev != cur) {
+    hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+    dev = cur;
+  }
+  return s;
+}
+
+// ------------------------------------------------------------ profiling
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+static std::mutex g_prof_mu;
+static std::vector<ProfRec> g_prof;
+static bool g_prof_on = false;
+
+int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
+  if (!g_prof_on) return -1;
+  ProfRec r{kind, nullptr, nullptr, flops, bytes};
+  hipEventCreate(&r.a);
+  hipEventCreate(&r.b);
+  hipEventRecord(r.a, st);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+
+void prof_end(int h, hipStream_t st) {
+  if (h < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (h < (int)g_prof.size()) hipEventRecord(g_prof[h].b, st);
+}
+
+static void prof_clear() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+}
+
+// ------------------------------------------------------------ arena pool
+//
+// Tile arenas are large (GBs) and reused across evaluations of the same size;
+// a small pool avoids a hipMalloc / hipFree pair per likelihood call.
+struct PoolEntry {
+  void *p;
+  size_t bytes;
+  int dev;
+};
+static std::mutex g_pool_mu;
+static std::vector<PoolEntry> g_pool;
+constexpr size_t POOL_MAX = 4;
+
+static void *arena_acquire(size_t bytes) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = 0; i < g_pool.size(); ++i)
+      if (g_pool[i].dev == dev && g_pool[i].bytes >= bytes && g_pool[i].bytes <= bytes + bytes / 4) {
+        void *p = g_pool[i].p;
+        g_pool.erase(g_pool.begin() + i);
+        return p;
+      }
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // free the pool and retry once
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &e : g_pool) hipFree(e.p);
+    g_pool.clear();
+    hipGetLastError();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      hipGetLastError();
+      return nullptr;
+    }
+  }
+  return p;
+}
+
+static void arena_release(void *p, size_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool.size() >= POOL_MAX) {
+    hipFree(g_pool.front().p);
+    g_pool.erase(g_pool.begin());
+  }
+  g_pool.push_back({p, bytes, dev});
+}
+
+// ------------------------------------------------------------- small kernels
+
+__global__ void k_reduce_chunks(const double *__restrict__ part, int64_t m, int nchunk,
+                                double *__restrict__ zhat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // i = 2t + j
+  if (i >= 2 * m) return;
+  const int64_t t = i / 2;
+  const int j = (int)(i % 2);
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(t * nchunk + c) * 2 + j];
+  zhat[i] = s;
+}
+
+__global__ void k_mse_final(const double *__restrict__ ss, int64_t m, double trc0,
+                            double *__restrict__ mse) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  mse[t] = trc0 - (ss[2 * t] + ss[2 * t + 1]);
+}
+
+__global__ void k_copy_pad(const double *__restrict__ src, int64_t n, double *__restrict__ dst,
+                           int64_t np) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) dst[i] = i < n ? src[i] : 0.0;
+}
+
+}  // namespace mvg
+
+using namespace mvg;
+
+// ------------------------------------------------------------ matrices
+
+static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
+  mvg_opts d{};
+  if (o) d = *o;
+  if (d.precision < MVG_FP64 || d.precision > MVG_TLR) return -1;
+  if (d.nb == 0) d.nb = (d.precision == MVG_TLR) ? 1200 : 512;
+  if (d.precision == MVG_TLR) {
+    if (d.nb < 64 || d.nb % 2) return -2;
+  } else {
+    if (d.nb < IB || d.nb % IB || d.nb > 1024) return -2;
+  }
+  if (d.band_tiles <= 0) d.band_tiles = 2;
+  if (d.tlr_acc <= 0.0) d.tlr_acc = 1e-7;
+  if (d.tlr_max_rank <= 0) d.tlr_max_rank = 300;
+  if (d.ir_max_iter <= 0) d.ir_max_iter = 20;
+  if (d.ir_tol <= 0.0) d.ir_tol = 1e-14;
+  *out = d;
+  return 0;
+}
+
+static void mat_free(mvg_mat *A) {
+  if (!A) return;
+  arena_release(A->arena, A->arena_bytes);
+  hipFree(A->d_off);
+  hipFree(A->d_kind);
+  hipFree(A->d_x);
+  hipFree(A->d_y);
+  hipFree(A->d_qtab);
+  hipFree(A->lr_arena);
+  hipFree(A->d_rank);
+  hipFree(A->d_uoff);
+  delete[] A->h_off;
+  delete[] A->h_kind;
+  delete[] A->h_rank;
+  delete[] A->h_uoff;
+  delete A;
+}
+
+// Tile layout: band tiles (|I - J| < band) FP64, the rest FP64 or FP32 by precision.
+static int tile_layout(int T, int nb, int precision, int band, int64_t *off, int *kind,
+                       size_t *total) {
+  size_t pos = 0;
+  for (int J = 0; J < T; ++J)
+    for (int I = J; I < T; ++I) {
+      const int64_t t = tidx(I, J, T);
+      const bool lowp = (precision == MVG_MIXED_FP32 || precision == MVG_MIXED_BF16) &&
+                        (I - J) >= band;
+      kind[t] = lowp ? TK_F32 : TK_F64;
+      off[t] = (int64_t)pos;
+      pos += (size_t)nb * nb * (lowp ? 4 : 8);
+      pos = (pos + 255) / 256 * 256;
+    }
+  *total = pos;
+  return 0;
+}
+
+static size_t layout_bytes(int64_t n_loc, const mvg_opts &o) {
+  const int64_t N = 2 * n_loc;
+  const int T = (int)((N + o.nb - 1) / o.nb);
+  size_t total = 0;
+  for (int J = 0; J < T; ++J)
+    for (int I = J; I < T; ++I) {
+      const bool lowp = (o.precision == MVG_MIXED_FP32 || o.precision == MVG_MIXED_BF16) &&
+                        (I - J) >= o.band_tiles;
+      total += ((size_t)o.nb * o.nb * (lowp ? 4 : 8) + 255) / 256 * 256;
+    }
+  return total;
+}
+
+static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, const double *d_x,
+                      const double *d_y, hipStream_t st, mvg_mat **out) {
+  mvg_mat *A = new mvg_mat();
+  A->n_loc = n_loc;
+  A->N = 2 * n_loc;
+  A->nb = o.nb;
+  A->T = (int)((A->N + o.nb - 1) / o.nb);
+  A->Np = (int64_t)A->T * o.nb;
+  A->precision = o.precision;
+  A->band = o.band_tiles;
+  A->theta = *th;
+  if (int rc = matern_setup(th, &A->margs)) {
+    delete A;
+    return rc;
+  }
+  const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
+  A->h_off = new int64_t[nt];
+  A->h_kind = new int[nt];
+  tile_layout(A->T, A->nb, A->precision == MVG_TLR ? MVG_FP64 : A->precision, A->band, A->h_off,
+              A->h_kind, &A->arena_bytes);
+  A->arena = (char *)arena_acquire(A->arena_bytes);
+  bool ok = A->arena != nullptr;
+  ok = ok && hipMalloc(&A->d_off, sizeof(int64_t) * nt) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_kind, sizeof(int) * nt) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
+  if (!ok) {
+    hipGetLastError();
+    set_error("device allocation of %.3f GB for a %lld-location matrix failed",
+              A->arena_bytes / 1e9, (long long)n_loc);
+    mat_free(A);
+    return MVG_ERR_ALLOC;
+  }
+  hipMemcpyAsync(A->d_off, A->h_off, sizeof(int64_t) * nt, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(A->d_kind, A->h_kind, sizeof(int) * nt, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(A->d_x, d_x, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(A->d_y, d_y, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
+  // the host offset tables are read by the copies above; keep them alive with A
+  *out = A;
+  return 0;
+}
+
+// Regenerate Sigma(theta) into an existing matrix of the same shape.
+static int mat_generate(mvg_mat *A, hipStream_t st) {
+  if (int rc = launch_quad_table(A->margs, A->d_qtab, st)) return rc;
+  const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
+  A->factored = 0;
+  return launch_cov_tiles(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, A->map(), 0, (int)nt, st);
+}
+
+extern "C" {
+
+const char *mvg_last_error(void) { return g_err; }
+
+int mvg_prof_enable(int on) {
+  hipDeviceSynchronize();
+  if (on) prof_clear();
+  g_prof_on = on != 0;
+  return 0;
+}
+
+int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, double *bytes) {
+  if (kind < 0 || kind >= MVG_PROF_NKINDS) return -1;
+  hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int64_t n = 0;
+  double ms = 0.0, f = 0.0, b = 0.0;
+  for (auto &r : g_prof) {
+    if (r.kind != kind) continue;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      hipGetLastError();
+      continue;
+    }
+    ++n;
+    ms += t;
+    f += r.flops;
+    b += r.bytes;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  if (flops) *flops = f;
+  if (bytes) *bytes = b;
+  return 0;
+}
+
+size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
+  mvg_opts d;
+  if (n_loc < 1 || normalize_opts(o, &d)) return 0;
+  const int64_t N = 2 * n_loc;
+  const int T = (int)((N + d.nb - 1) / d.nb);
+  const int64_t Np = (int64_t)T * d.nb;
+  size_t b = layout_bytes(n_loc, d);
+  b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * IB * IB);
+  b += (sizeof(int64_t) + sizeof(int)) * (size_t)T * (T + 1) / 2;
+  return b;
+}
+
+int cov_generate(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
+                 const mvg_opts *o, mvg_mat **out, void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (n_loc < 1) return -3;
+  if (!th) return -4;
+  mvg_opts d;
+  if (normalize_opts(o, &d)) return -5;
+  if (!out) return -6;
+  MaternArgs tmp;
+  if (matern_setup(th, &tmp)) return -4;
+  hipStream_t st = (hipStream_t)hip_stream;
+  mvg_mat *A = nullptr;
+  if (int rc = mat_create(n_loc, d, th, d_x, d_y, st, &A)) return rc < 0 && rc > -100 ? -4 : rc;
+  if (int rc = mat_generate(A, st)) {
+    mat_free(A);
+    return rc;
+  }
+  *out = A;
+  return 0;
+}
+
+int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream) {
+  (void)o;
+  if (!A) return -1;
+  if (!h_info) return -3;
+  if (A->factored || A->precision == MVG_TLR) {
+    set_error("potrf_tiled: matrix already factored or TLR (use loglik)");
+    return -1;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  int64_t *d_info = nullptr;
+  if (hipMallocAsync((void **)&d_info, sizeof(int64_t), st) != hipSuccess) {
+    set_error("hipMallocAsync failed");
+    return MVG_ERR_ALLOC;
+  }
+  int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
+  if (!rc) rc = dense_potrf(A, d_info, st);
+  int64_t info = 0;
+  hipMemcpyAsync(&info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  hipFreeAsync(d_info, st);
+  hipStreamSynchronize(st);
+  if (rc) return rc;
+  *h_info = info == INT64_MAX ? 0 : info;
+  A->factored = 1;
+  return 0;
+}
+
+// One likelihood evaluation on a generated matrix; optionally leaves L^-1 Z in d_yv.
+static int eval_one(mvg_mat *A, const double *d_z, double *d_yv, double *d_part, double *d_out2,
+                    int64_t *d_info, hipStream_t st) {
+  int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
+  const double Nd = (double)A->N;
+  int hp = prof_begin(MVG_PROF_POTRF, st, Nd * Nd * Nd / 3.0 + Nd * Nd / 2.0, 0.0);
+  if (!rc) rc = dense_potrf(A, d_info, st);
+  prof_end(hp, st);
+  int hs = prof_begin(MVG_PROF_SOLVE, st, Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
+  if (!rc) {
+    hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)((A->Np + 255) / 256)), dim3(256), 0, st, d_z,
+                       A->N, d_yv, A->Np);
+    rc = check_launch("copy_pad");
+  }
+  if (!rc) rc = trsv_forward(A, d_yv, st);
+  if (!rc) rc = logdet_quad(A, d_yv, d_part, d_out2, st);
+  prof_end(hs, st);
+  A->factored = 1;
+  return rc;
+}
+
+int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+           const mvg_theta *th, int n_theta, const mvg_opts *o, double *h_loglik,
+           double *h_logdet, double *h_quad, int64_t *h_status, mvg_factor **keep,
+           void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (!d_z) return -3;
+  if (n_loc < 1) return -4;
+  if (!th) return -5;
+  if (n_theta < 1) return -6;
+  mvg_opts d;
+  if (normalize_opts(o, &d)) return -7;
+  if (!h_loglik) return -8;
+  if (keep && n_theta != 1) return -12;
+  for (int i = 0; i < n_theta; ++i) {
+    MaternArgs tmp;
+    if (matern_setup(&th[i], &tmp)) return -5;
+  }
+  if (d.precision != MVG_FP64) {
+    set_error("loglik: precision %d not available in this build", d.precision);
+    return -7;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  mvg_mat *A = nullptr;
+  int rc = mat_create(n_loc, d, &th[0], d_x, d_y, st, &A);
+  if (rc) return rc;
+  const int nred = (int)((A->N + 4095) / 4096);
+  double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2 n_theta) | info (n_theta)
+  const size_t ws_n = (size_t)A->Np + 2 * nred + 2 * n_theta + n_theta;
+  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+    hipGetLastError();
+    mat_free(A);
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  double *d_yv = ws, *d_part = ws + A->Np, *d_out2 = d_part + 2 * nred;
+  int64_t *d_info = reinterpret_cast<int64_t *>(d_out2 + 2 * n_theta);
+  for (int i = 0; i < n_theta && !rc; ++i) {
+    if (i > 0) {
+      A->theta = th[i];
+      matern_setup(&th[i], &A->margs);
+    }
+    const double npair = (double)n_loc * (n_loc + 1) / 2;
+    int hg = prof_begin(MVG_PROF_GEN, st, 0.0, 8.0 * (double)A->N * (A->N + 1) / 2);
+    rc = mat_generate(A, st);
+    prof_end(hg, st);
+    (void)npair;
+    if (!rc) rc = eval_one(A, d_z, d_yv, d_part, d_out2 + 2 * i, d_info + i, st);
+  }
+  std::vector<double> out2(2 * n_theta);
+  std::vector<int64_t> info(n_theta);
+  hipMemcpyAsync(out2.data(), d_out2, sizeof(double) * 2 * n_theta, hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(info.data(), d_info, sizeof(int64_t) * n_theta, hipMemcpyDeviceToHost, st);
+  mvg_factor *F = nullptr;
+  if (!rc && keep) {
+    F = new mvg_factor();
+    F->A = A;
+    if (hipMalloc((void **)&F->d_w, sizeof(double) * A->Np * 2) != hipSuccess) {
+      hipGetLastError();
+      rc = MVG_ERR_ALLOC;
+      set_error("factor allocation failed");
+    } else {
+      F->d_y = F->d_w + A->Np;
+      hipMemcpyAsync(F->d_y, d_yv, sizeof(double) * A->Np, hipMemcpyDeviceToDevice, st);
+      hipMemcpyAsync(F->d_w, d_yv, sizeof(double) * A->Np, hipMemcpyDeviceToDevice, st);
+      rc = trsv_backward(A, F->d_w, st);
+    }
+  }
+  hipFreeAsync(ws, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    set_error("stream synchronisation failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = MVG_ERR_LAUNCH;
+  }
+  if (rc) {
+    if (F) {
+      hipFree(F->d_w);
+      delete F;
+    }
+    mat_free(A);
+    return rc;
+  }
+  const double two_pi_term = (double)n_loc * std::log(2.0 * M_PI);
+  for (int i = 0; i < n_theta; ++i) {
+    const int64_t inf = info[i] == INT64_MAX ? 0 : info[i];
+    if (h_status) h_status[i] = inf;
+    if (inf) {
+      h_loglik[i] = -INFINITY;
+      if (h_logdet) h_logdet[i] = NAN;
+      if (h_quad) h_quad[i] = NAN;
+    } else {
+      h_loglik[i] = -two_pi_term - 0.5 * out2[2 * i] - 0.5 * out2[2 * i + 1];
+      if (h_logdet) h_logdet[i] = out2[2 * i];
+      if (h_quad) h_quad[i] = out2[2 * i + 1];
+    }
+  }
+  if (F) {
+    if (info[0]) {  // a failed factor cannot predict
+      hipFree(F->d_w);
+      delete F;
+      mat_free(A);
+      *keep = nullptr;
+    } else {
+      *keep = F;
+    }
+  } else {
+    mat_free(A);
+  }
+  return 0;
+}
+
+int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0, int64_t m,
+                    double *d_zhat, double *d_mse, void *hip_stream) {
+  if (!F || !F->A || !F->d_w) return -1;
+  if (!d_x0) return -2;
+  if (!d_y0) return -3;
+  if (m < 1 || m > 65535) return -4;
+  if (!d_zhat) return -5;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const mvg_mat *A = F->A;
+  const int nchunk = (int)((A->n_loc + 2047) / 2048);
+  int hc = prof_begin(MVG_PROF_COKRIGE, st, 0.0, 8.0 * (double)A->N);
+  double *part = nullptr;
+  if (hipMallocAsync((void **)&part, sizeof(double) * 2 * m * nchunk, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  int rc = launch_cokrige_dot(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, d_x0, d_y0, m,
+                              F->d_w, part, nchunk, st);
+  if (!rc) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((2 * m + 255) / 256)), dim3(256), 0, st,
+                       (const double *)part, m, nchunk, d_zhat);
+    rc = check_launch("reduce_chunks");
+  }
+  hipFreeAsync(part, st);
+  prof_end(hc, st);
+  if (!rc && d_mse) {
+    double *V = nullptr, *ss = nullptr;
+    if (hipMallocAsync((void **)&V, sizeof(double) * (A->Np * 2 * m + 2 * m), st) != hipSuccess) {
+      hipGetLastError();
+      set_error("workspace allocation failed");
+      return MVG_ERR_ALLOC;
+    }
+    ss = V + A->Np * 2 * m;
+    rc = launch_cokrige_c0(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, A->Np, d_x0, d_y0, m, V,
+                           st);
+    if (!rc) rc = trsm_forward_multi(A, V, (int)(2 * m), st);
+    if (!rc) rc = launch_sum_sq_cols(V, A->Np, (int)(2 * m), ss, st);
+    if (!rc) {
+      hipLaunchKernelGGL(k_mse_final, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                         (const double *)ss, m, A->theta.sigma11_sq + A->theta.sigma22_sq, d_mse);
+      rc = check_launch("mse_final");
+    }
+    hipFreeAsync(V, st);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = MVG_ERR_LAUNCH;
+  return rc;
+}
+
+int morton_order(const double *d_x, const double *d_y, int64_t n_loc, int64_t *d_perm,
+                 double *d_xs, double *d_ys, void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (n_loc < 1 || n_loc > ((int64_t)1 << 26)) return -3;
+  if (!d_perm) return -4;
+  if (d_xs && (d_xs == d_x || d_xs == d_y)) return -5;
+  if (d_ys && (d_ys == d_x || d_ys == d_y || d_ys == d_xs)) return -6;
+  return morton_sort(d_x, d_y, n_loc, d_perm, d_xs, d_ys, (hipStream_t)hip_stream);
+}
+
+int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_stream) {
+  if (!L || !L->factored || L->precision == MVG_TLR) return -1;
+  if (!d_eps) return -2;
+  if (!d_z || d_z == d_eps) return -3;
+  return launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream);
+}
+
+int mvg_mat_shape(const mvg_mat *A, int64_t *n_loc, int *nb, int *ntiles, int *precision,
+                  int *factored) {
+  if (!A) return -1;
+  if (n_loc) *n_loc = A->n_loc;
+  if (nb) *nb = A->nb;
+  if (ntiles) *ntiles = A->T;
+  if (precision) *precision = A->precision;
+  if (factored) *factored = A->factored;
+  return 0;
+}
+
+int mvg_mat_gather(const mvg_mat *A, const int64_t *d_rows, const int64_t *d_cols, int64_t m,
+                   double *d_out, void *hip_stream) {
+  if (!A || A->precision == MVG_TLR) return -1;
+  if (!d_rows) return -2;
+  if (!d_cols) return -3;
+  if (m < 0) return -4;
+  if (!d_out) return -5;
+  return launch_gather(A, d_rows, d_cols, m, d_out, (hipStream_t)hip_stream);
+}
+
+int mvg_mat_to_dense(const mvg_mat *A, double *d_out, int64_t ld, void *hip_stream) {
+  if (!A || A->precision == MVG_TLR) return -1;
+  if (!d_out) return -2;
+  if (ld < A->N) return -3;
+  return launch_to_dense(A, d_out, ld, (hipStream_t)hip_stream);
+}
+
+const mvg_mat *mvg_factor_mat(const mvg_factor *F) { return F ? F->A : nullptr; }
+const double *mvg_factor_w(const mvg_factor *F) { return F ? F->d_w : nullptr; }
+
+void mvg_mat_destroy(mvg_mat *A) {
+  if (!A) return;
+  hipDeviceSynchronize();
+  mat_free(A);
+}
+
+void mvg_factor_destroy(mvg_factor *F) {
+  if (!F) return;
+  hipDeviceSynchronize();
+  hipFree(F->d_w);
+  mat_free(F->A);
+  delete F;
+}
+
+int tlr_compress(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
+                 const mvg_opts *o, mvg_mat **out, int32_t *h_ranks, void *hip_stream) {
+  (void)d_x; (void)d_y; (void)n_loc; (void)th; (void)o; (void)out; (void)h_ranks;
+  (void)hip_stream;
+  set_error("tlr_compress: not available in this build");
+  return MVG_ERR_STATE;
+}
+
+}  // extern "C"

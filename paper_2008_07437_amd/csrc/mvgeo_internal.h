@@ -1,0 +1,147 @@
+// Internal declarations of the gfx950 library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "mvgeo.h"
+
+namespace mvg {
+
+// Inner block: GEMM workgroup tile and the panel factorisation's block width.
+constexpr int IB = 128;
+
+// ------------------------------------------------------------------ Matern
+//
+// Quadrature table for K_nu(x) = e^-x * int_0^inf exp(-x (cosh t - 1)) cosh(nu t) dt
+// (DLMF 10.32.9), trapezoidal rule on nodes t_k = k h_j.  Level j uses step
+// h_j = 0.2 / 2^j for x in (X_{j-1}, X_j], X_j = 6 * 4^j; beyond X_4 the
+// covariance underflows to 0.  The three orders (nu11, nu22, nu12) share the
+// exponentials.
+constexpr int QLEV = 5;
+constexpr int QN = 400;  // table entries (sum of the level counts, padded)
+__host__ __device__ constexpr int qlev_off(int j) {
+  return j == 0 ? 0 : j == 1 ? 201 : j == 2 ? 241 : j == 3 ? 289 : 341;
+}
+__host__ __device__ constexpr int qlev_cnt(int j) {
+  return j == 0 ? 201 : j == 1 ? 40 : j == 2 ? 48 : j == 3 ? 52 : 56;
+}
+__host__ __device__ constexpr double qlev_h(int j) {
+  return j == 0 ? 0.2 : j == 1 ? 0.1 : j == 2 ? 0.05 : j == 3 ? 0.025 : 0.0125;
+}
+__host__ __device__ constexpr double qlev_xmax(int j) {
+  return j == 0 ? 6.0 : j == 1 ? 24.0 : j == 2 ? 96.0 : j == 3 ? 384.0 : 1536.0;
+}
+
+// Per-theta constants of Eq. (2) for the orders o = 0 (1,1), 1 (2,2), 2 (1,2).
+struct MaternArgs {
+  double a;
+  double coef[3];   // sigma11^2, sigma22^2, rho12 sigma1 sigma2
+  double nu[3];     // nu11, nu22, nu12
+  double lnorm[3];  // -log(2^(nu-1) Gamma(nu))
+  int closed[3];    // 0: quadrature; 1: nu = 1/2; 2: nu = 3/2; 3: nu = 5/2
+  int any_quad;
+};
+
+// Validates theta and fills the constants; returns 0 or -(index of the bad entry).
+int matern_setup(const mvg_theta *th, MaternArgs *out);
+
+// ------------------------------------------------------------------- tiles
+
+// Packed lower tile index, tiles of a column contiguous.
+__host__ __device__ inline int64_t tidx(int I, int J, int T) {
+  return (int64_t)J * T - ((int64_t)J * (J - 1)) / 2 + (I - J);
+}
+
+enum TileKind : int { TK_F64 = 0, TK_F32 = 1 };
+
+// Tile storage: base + off[tidx] bytes, column-major inside the tile, ld = nb.
+struct TileMap {
+  char *base;
+  const int64_t *off;  // device array, T(T+1)/2 byte offsets
+  const int *kind;     // device array, TileKind per tile (nullptr: all F64)
+  int T, nb;
+};
+
+}  // namespace mvg
+
+struct mvg_mat {
+  int64_t n_loc = 0, N = 0, Np = 0;
+  int nb = 0, T = 0, precision = 0, factored = 0, band = 0;
+  char *arena = nullptr;          // tile storage
+  size_t arena_bytes = 0;
+  int64_t *d_off = nullptr;       // per-tile byte offsets
+  int *d_kind = nullptr;          // per-tile kind
+  int64_t *h_off = nullptr;
+  int *h_kind = nullptr;
+  double *d_x = nullptr, *d_y = nullptr;  // library copies of the locations
+  double *d_qtab = nullptr;               // quadrature table of theta
+  mvg_theta theta{};
+  mvg::MaternArgs margs{};
+  // TLR storage (precision == MVG_TLR)
+  double *lr_arena = nullptr;
+  size_t lr_bytes = 0;
+  int32_t *h_rank = nullptr;      // T*T, -1 dense
+  int32_t *d_rank = nullptr;
+  int64_t *h_uoff = nullptr;      // per packed tile: element offset of U (V follows)
+  int64_t *d_uoff = nullptr;
+  mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb}; }
+};
+
+struct mvg_factor {
+  mvg_mat *A = nullptr;
+  double *d_w = nullptr;   // Sigma^-1 Z (padded length Np)
+  double *d_y = nullptr;   // L^-1 Z
+};
+
+namespace mvg {
+
+// Thread-local error reporting.
+void set_error(const char *fmt, ...);
+int check_launch(const char *what);
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `st` and return 0 or an MVG_ERR_* code.
+
+int launch_quad_table(const MaternArgs &P, double *d_qtab, hipStream_t st);
+int launch_cov_tiles(const MaternArgs &P, const double *d_qtab, const double *d_x,
+                     const double *d_y, int64_t n_loc, TileMap M, int tile_first, int tile_count,
+                     hipStream_t st);
+// c0^T w and optionally ||L^-1 c0||^2 pieces for cokriging
+int launch_cokrige_dot(const MaternArgs &P, const double *d_qtab, const double *d_x,
+                       const double *d_y, int64_t n_loc, const double *d_x0, const double *d_y0,
+                       int64_t m, const double *d_w, double *d_part, int nchunk, hipStream_t st);
+int launch_cokrige_c0(const MaternArgs &P, const double *d_qtab, const double *d_x,
+                      const double *d_y, int64_t n_loc, int64_t Np, const double *d_x0,
+                      const double *d_y0, int64_t m, double *d_c0, hipStream_t st);
+
+// dense FP64 Cholesky pieces
+int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st);
+int launch_fill_i64(int64_t *d, int64_t v, int64_t n, hipStream_t st);
+int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st);
+int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st);     // v <- L^-1 v
+int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st);    // v <- L^-T v
+int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st);  // V <- L^-1 V (col-major, ld Np)
+int logdet_quad(const mvg_mat *A, const double *d_y, double *d_part, double *d_out2,
+                hipStream_t st);  // d_out2 = {2 sum log L_jj, y^T y}
+int launch_gather(const mvg_mat *A, const int64_t *rows, const int64_t *cols, int64_t m,
+                  double *out, hipStream_t st);
+int launch_to_dense(const mvg_mat *A, double *out, int64_t ld, hipStream_t st);
+int launch_sum_sq_cols(const double *d_V, int64_t Np, int ncols, double *d_out, hipStream_t st);
+
+// morton
+int morton_sort(const double *d_x, const double *d_y, int64_t n, int64_t *d_perm, double *d_xs,
+                double *d_ys, hipStream_t st);
+int launch_trmv(const mvg_mat *L, const double *d_eps, double *d_z, hipStream_t st);
+
+// permanent second stream for look-ahead (default priority)
+hipStream_t side_stream();
+
+// event timing of launches (diagnostics); handles < 0 mean "not recording"
+int prof_begin(int kind, hipStream_t st, double flops, double bytes);
+void prof_end(int handle, hipStream_t st);
+
+}  // namespace mvg
