@@ -20,8 +20,9 @@
  *
  * Return codes (LAPACK style): 0 = success; -i = argument i (1-based) is
  * invalid; > 0 = numerical failure: the 1-based global index of the first
- * non-positive pivot of the Cholesky factorisation (Sigma not positive
- * definite); MVG_ERR_* (< -100) = runtime failure (allocation, launch).  No
+ * Cholesky pivot that is not above 2^-40 times its original diagonal entry
+ * (Sigma not positive definite, or singular to working precision, as with a
+ * duplicated location); MVG_ERR_* (< -100) = runtime failure (allocation, launch).  No
  * call aborts or prints; mvg_last_error() returns the message of the last
  * failure on the calling thread.
  */

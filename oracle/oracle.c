@@ -249,16 +249,23 @@ void orc_cov_dense(const double *xs, const double *ys, int64_t n, const double *
 
 /* ------------------------------------------------------ linear algebra */
 
+/* A pivot at or below this fraction of its original diagonal entry is
+ * treated as a failure: the matrix is singular to working precision (a
+ * duplicated location gives a pivot that is zero up to rounding, and the sign
+ * of that rounding must not decide the result). */
+#define ORC_SINGULAR_REL 0x1p-40
+
 /* In-place Cholesky A = L L^T of a row-major n x n SPD matrix (lower factor;
  * the strict upper triangle is zeroed).  Column-by-column (Cholesky-Crout)
  * with dot products in index order.  Returns 0, or the 1-based index of the
- * first non-positive pivot. */
+ * first pivot that is not above ORC_SINGULAR_REL times its diagonal entry. */
 int64_t orc_potrf(double *A, int64_t n) {
     for (int64_t j = 0; j < n; ++j) {
         double *rj = A + j * n;
         double d = rj[j];
+        const double tol = ORC_SINGULAR_REL * d;
         for (int64_t k = 0; k < j; ++k) d -= rj[k] * rj[k];
-        if (!(d > 0.0)) return j + 1;
+        if (!(d > tol) || !(d > 0.0)) return j + 1;
         double ljj = sqrt(d);
         rj[j] = ljj;
 #pragma omp parallel for schedule(static)

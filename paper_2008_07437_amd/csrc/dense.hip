@@ -212,8 +212,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // (1-based global row) to *d_info via atomicMin.
 constexpr int PLD = IB + 1;  // padded LDS leading dimension
 
+// A pivot at or below 2^-40 of its original diagonal entry (sigma11^2 or
+// sigma22^2 by row parity, 1 in the padding) counts as a failure: the matrix is
+// singular to working precision, and the sign of rounding noise must not decide.
 __global__ __launch_bounds__(256) void k_potrf_inner(TileMap M, int k, int b, double *__restrict__ d_w,
-                                                     int64_t *__restrict__ d_info) {
+                                                     int64_t *__restrict__ d_info, double tol0,
+                                                     double tol1, int64_t N) {
   extern __shared__ double L[];  // IB * PLD
   __shared__ double tmp[IB];
   __shared__ int fail;
@@ -230,7 +234,9 @@ __global__ __launch_bounds__(256) void k_potrf_inner(TileMap M, int k, int b, do
   for (int j = 0; j < IB; ++j) {
     if (tid == 0) {
       const double d = L[j * PLD + j];
-      if (!(d > 0.0) && !fail) {
+      const int64_t g = (int64_t)k * nb + (int64_t)b * IB + j;
+      const double tol = g >= N ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
+      if ((!(d > tol) || !(d > 0.0)) && !fail) {
         fail = 1;
         atomicMin((unsigned long long *)d_info,
                   (unsigned long long)((int64_t)k * nb + (int64_t)b * IB + j + 1));
@@ -275,11 +281,18 @@ __global__ __launch_bounds__(256) void k_potrf_inner(TileMap M, int k, int b, do
 
 constexpr size_t POTRF_LDS = sizeof(double) * IB * PLD;
 
-static int panel_factor(const TileMap &M, int k, double *d_w, int64_t *d_info, hipStream_t st) {
+struct PivotTol {
+  double t0, t1;
+  int64_t N;
+};
+
+static int panel_factor(const TileMap &M, int k, double *d_w, int64_t *d_info, const PivotTol &pt,
+                        hipStream_t st) {
   const int s = M.nb / IB;
   const int nrb = (M.T - k) * s;  // row blocks of panel k
   for (int b = 0; b < s; ++b) {
-    hipLaunchKernelGGL(k_potrf_inner, dim3(1), dim3(256), POTRF_LDS, st, M, k, b, d_w, d_info);
+    hipLaunchKernelGGL(k_potrf_inner, dim3(1), dim3(256), POTRF_LDS, st, M, k, b, d_w, d_info,
+                       pt.t0, pt.t1, pt.N);
     if (int rc = check_launch("potrf_inner")) return rc;
     const int nbelow = nrb - (b + 1);
     if (nbelow > 0) {
@@ -366,9 +379,10 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
   int rc = 0;
   double *w_side = d_w + IB * IB;  // panel workspace used on the side stream
+  const PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
   hipEventRecord(ev0, st);
   hipStreamWaitEvent(side, ev0, 0);
-  rc = panel_factor(M, 0, w_side, d_info, side);
+  rc = panel_factor(M, 0, w_side, d_info, pt, side);
   hipEventRecord(evP, side);
   for (int k = 0; k < T && !rc; ++k) {
     hipStreamWaitEvent(st, evP, 0);
@@ -377,7 +391,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
     if (rc) break;
     if (k + 1 < T) {
       rc = trailing(M, A->N, k, k + 1, k + 1, side);
-      if (!rc) rc = panel_factor(M, k + 1, w_side, d_info, side);
+      if (!rc) rc = panel_factor(M, k + 1, w_side, d_info, pt, side);
       hipEventRecord(evP, side);
       hipStreamWaitEvent(side, evR, 0);
     }

@@ -159,6 +159,24 @@ def test_potrf_reports_first_failing_pivot(orc):
     A = np.diag([4.0, 9.0, -1.0, 5.0])
     L, info = orc.potrf(A)
     assert info == 3
+    # singular to working precision: the third row repeats the first
+    B = np.array([[2.0, 1.0, 2.0], [1.0, 3.0, 1.0], [2.0, 1.0, 2.0]])
+    assert orc.potrf(B)[1] == 3
+    # a small but clearly resolved pivot (1e-9 relative) is not a failure
+    C = np.array([[1.0, 1.0 - 5e-10], [1.0 - 5e-10, 1.0]])
+    assert orc.potrf(C)[1] == 0
+
+
+def test_pivot_rule_leaves_workload_matrices_alone(orc):
+    """The smallest relative pivot of the strongest-correlation workload
+    (a = 0.3) is orders of magnitude above the 2^-40 singularity rule."""
+    th = (1.0, 1.0, 0.3, 0.5, 1.0, 0.9)
+    x, y = synthetic.jittered_grid(400, 0)
+    S = orc.cov_dense(x, y, th)
+    L, info = orc.potrf(S)
+    assert info == 0
+    ratio = np.min(np.diag(L) ** 2 / np.diag(S))
+    assert ratio > 1e4 * 2.0 ** -40, ratio
 
 
 # ------------------------------------------------------------------ likelihood
