@@ -493,7 +493,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
     }
   }
   if (F) {
-    if (info[0]) {  // a failed factor cannot predict
+    if (info[0] != INT64_MAX) {  // a failed factor cannot predict
       hipFree(F->d_w);
       delete F;
       mat_free(A);
