@@ -188,6 +188,7 @@ static void mat_free(mvg_mat *A) {
   hipFree(A->d_x);
   hipFree(A->d_y);
   hipFree(A->d_qtab);
+  hipFree(A->d_winv);
   hipFree(A->lr_arena);
   hipFree(A->d_rank);
   hipFree(A->d_uoff);
@@ -256,6 +257,7 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   ok = ok && hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
   ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
   ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_winv, sizeof(double) * (size_t)A->Np * 64) == hipSuccess;
   if (!ok) {
     hipGetLastError();
     set_error("device allocation of %.3f GB for a %lld-location matrix failed",
@@ -323,7 +325,7 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
   const int T = (int)((N + d.nb - 1) / d.nb);
   const int64_t Np = (int64_t)T * d.nb;
   size_t b = layout_bytes(n_loc, d);
-  b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * IB * IB);
+  b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 64 * Np);
   b += (sizeof(int64_t) + sizeof(int)) * (size_t)T * (T + 1) / 2;
   return b;
 }

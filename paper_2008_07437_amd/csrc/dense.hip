@@ -172,12 +172,207 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   (void)jhi;
 }
 
-// Panel-internal update after inner block b of panel k: for inner column
-// blocks cb in (b, s) and panel row blocks R >= cb (R counted from the
-// diagonal tile down), P[R, cb] -= P[R, b] P[cb, b]^T.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_panel_update(TileMap M, int k, int b, int nrb) {
-  extern __shared__ double smem[];
-  const int s = M.nb / IB;
+// ------------------------------------------------------------ panel kernels
+//
+// The panel of tile column k (rows k nb .. Np, width nb) is factored in
+// 64-wide inner blocks.  Every panel kernel is small (<= 32 KB LDS, about 100
+// VGPRs per lane) so that it can be resident on a CU next to two
+// trailing-update workgroups: the look-ahead panel never waits for the
+// trailing GEMM to drain.
+constexpr int PB = 64;
+constexpr int SMALL_LDS = 2 * 2 * PB * KB;  // doubles (32 KB)
+
+// C (64x64) = or -= A (64xK) B (64xK)^T, column-major, K % 16 == 0.  256
+// threads, 4 waves in a 2x2 grid, each 32x32 = 2x2 MFMA 16x16 tiles.  C may
+// alias A (in-place TRSM): all reads of A happen before the epilogue.
+template <bool SUB>
+__device__ __forceinline__ void gemm_block64(double *C, int ldc, const double *A, int lda,
+                                             const double *__restrict__ B, int ldb, int K,
+                                             double *__restrict__ smem) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int kk = tid >> 4, r4 = (tid & 15) * 4;
+  const double *ga = A + (int64_t)kk * lda + r4;
+  const double *gb = B + (int64_t)kk * ldb + r4;
+  double *la = smem + kk * PB + r4;
+  double *lb = smem + PB * KB + kk * PB + r4;
+  const int64_t stepa = (int64_t)KB * lda, stepb = (int64_t)KB * ldb;
+  double2 ra0, ra1, rb0, rb1;
+#define MVG_GLOAD64(pa, pb)                                        \
+  do {                                                             \
+    const double2 *qa_ = reinterpret_cast<const double2 *>(pa);    \
+    const double2 *qb_ = reinterpret_cast<const double2 *>(pb);    \
+    ra0 = qa_[0]; ra1 = qa_[1]; rb0 = qb_[0]; rb1 = qb_[1];        \
+  } while (0)
+#define MVG_SSTORE64(off)                                          \
+  do {                                                             \
+    double2 *sa_ = reinterpret_cast<double2 *>(la + (off));        \
+    double2 *sb_ = reinterpret_cast<double2 *>(lb + (off));        \
+    sa_[0] = ra0; sa_[1] = ra1; sb_[0] = rb0; sb_[1] = rb1;        \
+  } while (0)
+  const int nk = K / KB;
+  MVG_GLOAD64(ga, gb);
+  MVG_SSTORE64(0);
+  __syncthreads();
+  const int l16 = lane & 15, lk = lane >> 4;
+  for (int kb = 0; kb < nk; ++kb) {
+    const int buf = kb & 1;
+    const bool more = kb + 1 < nk;
+    if (more) MVG_GLOAD64(ga + (kb + 1) * stepa, gb + (kb + 1) * stepb);
+    const double *a = smem + buf * 2 * PB * KB + wr * 32 + l16;
+    const double *b = smem + buf * 2 * PB * KB + PB * KB + wc * 32 + l16;
+#pragma unroll
+    for (int ks = 0; ks < KB; ks += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = a[(ks + lk) * PB + t * 16];
+        bf[t] = b[(ks + lk) * PB + t * 16];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[tj], af[ti], acc[ti][tj], 0, 0, 0);
+    }
+    if (more) MVG_SSTORE64((buf ^ 1) * 2 * PB * KB);
+    __syncthreads();
+  }
+#undef MVG_GLOAD64
+#undef MVG_SSTORE64
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wr * 32 + ti * 16 + l16;
+        const int col = wc * 32 + tj * 16 + lk + 4 * e;
+        double *p = C + (int64_t)col * ldc + row;
+        if (SUB) *p -= acc[ti][tj][e];
+        else *p = acc[ti][tj][e];
+      }
+}
+
+// Cholesky of the 64 x 64 diagonal block b of tile (k, k) and, in the same
+// sweep, its inverse W = L^-1 by forward elimination on the identity.  The
+// block lives in registers: thread (ty, tx) = (tid % 16, tid / 16) holds rows
+// ty + 16 i and columns tx + 16 jj (i, jj < 4), of the factor and of W.  Each
+// step broadcasts column j of the factor and row j of W through LDS (double
+// buffered, one barrier per step).  A pivot at or below 2^-40 of its original
+// diagonal entry (sigma11^2 or sigma22^2 by row parity, 1 in the padding) is a
+// failure: the matrix is singular to working precision, and the sign of
+// rounding noise must not decide; the first such global row (1-based) goes to
+// *d_info.
+__global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double *__restrict__ winv,
+                                                 int64_t *__restrict__ d_info, double tol0,
+                                                 double tol1, int64_t N) {
+  __shared__ double scol[2][PB];
+  __shared__ double srow[2][PB];
+  const int tid = threadIdx.x;
+  const int ty = tid & 15, tx = tid >> 4;
+  const int nb = M.nb;
+  double *G = tile_ptr(M, k, k) + (int64_t)b * PB * nb + b * PB;
+  double a[4][4], x[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = ty + 16 * i, c = tx + 16 * jj;
+      a[i][jj] = (r >= c) ? G[(int64_t)c * nb + r] : 0.0;
+      x[i][jj] = (r == c) ? 1.0 : 0.0;
+    }
+  bool failed = false;
+  const int64_t g0 = (int64_t)k * nb + (int64_t)b * PB;
+  for (int j = 0; j < PB; ++j) {
+    const int buf = j & 1, jq = j >> 4, jr = j & 15;
+    if (tx == jr) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) scol[buf][ty + 16 * i] = a[i][jq];
+    }
+    if (ty == jr) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) srow[buf][tx + 16 * jj] = x[jq][jj];
+    }
+    __syncthreads();
+    const double d = scol[buf][j];
+    if (tid == 0 && !failed) {
+      const int64_t g = g0 + j;
+      const double tol = g >= N ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
+      if (!(d > tol) || !(d > 0.0)) {
+        failed = true;
+        atomicMin((unsigned long long *)d_info, (unsigned long long)(g + 1));
+      }
+    }
+    const double ljj = sqrt(d);
+    const double rinv = 1.0 / ljj;
+    double lr[4], lc[4], xr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 16 * i;
+      lr[i] = (r > j) ? scol[buf][r] * rinv : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int c = tx + 16 * jj;
+      lc[jj] = (c > j) ? scol[buf][c] * rinv : 0.0;
+      xr[jj] = srow[buf][c] * rinv;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        a[i][jj] -= lr[i] * lc[jj];
+        x[i][jj] -= lr[i] * xr[jj];
+      }
+    if (tx == jr) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = ty + 16 * i;
+        if (r == j) a[i][jq] = ljj;
+        else if (r > j) a[i][jq] = lr[i];
+      }
+    }
+    if (ty == jr) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) x[jq][jj] = xr[jj];
+    }
+  }
+  double *W = winv + (int64_t)(g0 / PB) * PB * PB;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = ty + 16 * i, c = tx + 16 * jj;
+      if (r >= c) G[(int64_t)c * nb + r] = a[i][jj];
+      W[c * PB + r] = (r >= c) ? x[i][jj] : 0.0;
+    }
+}
+
+// Panel TRSM for inner block b: 64-row blocks R in (b, nrb) of panel k:
+// P[R, b] <- P[R, b] W_b^T, in place (each workgroup owns its 64 x 64 block).
+__global__ __launch_bounds__(256) void k_trsm64(TileMap M, int k, int b,
+                                                const double *__restrict__ W) {
+  __shared__ double smem[SMALL_LDS];
+  const int s = M.nb / PB;
+  const int R = b + 1 + blockIdx.x;
+  const int nb = M.nb;
+  const int i = k + R / s, rl = R % s;
+  double *C = tile_ptr(M, i, k) + (int64_t)b * PB * nb + rl * PB;
+  gemm_block64<false>(C, nb, C, nb, W, PB, PB, smem);
+}
+
+// Panel update after inner block b: inner column blocks cb in (b, s), row
+// blocks R >= cb: P[R, cb] -= P[R, b] P[cb, b]^T (rank-64).
+__global__ __launch_bounds__(256) void k_panel_update64(TileMap M, int k, int b, int nrb) {
+  __shared__ double smem[SMALL_LDS];
+  const int s = M.nb / PB;
   const int ncb = s - (b + 1);
   const int R = b + 1 + blockIdx.x / ncb;
   const int cb = b + 1 + blockIdx.x % ncb;
@@ -185,126 +380,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int nb = M.nb;
   const int i = k + R / s, rl = R % s;
   double *P = tile_ptr(M, i, k);
-  double *D = tile_ptr(M, k, k);
-  double *C = P + (int64_t)cb * IB * nb + rl * IB;
-  const double *A = P + (int64_t)b * IB * nb + rl * IB;
-  const double *B = D + (int64_t)b * IB * nb + cb * IB;
-  gemm_block<true>(C, nb, A, nb, B, nb, IB, smem);
+  const double *D = tile_ptr(M, k, k);
+  gemm_block64<true>(P + (int64_t)cb * PB * nb + rl * PB, nb, P + (int64_t)b * PB * nb + rl * PB, nb,
+                     D + (int64_t)b * PB * nb + cb * PB, nb, PB, smem);
 }
-
-// Panel TRSM for inner block b: rows R in (b, nrb): P[R, b] <- P[R, b] W^T with
-// W = L_bb^-1 (128 x 128, lower, upper part zero).  In place: each workgroup
-// owns its full 128 x 128 output block and has read all of it before writing.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_trsm_inner(TileMap M, int k, int b,
-                                                    const double *__restrict__ W) {
-  extern __shared__ double smem[];
-  const int s = M.nb / IB;
-  const int R = b + 1 + blockIdx.x;
-  const int nb = M.nb;
-  const int i = k + R / s, rl = R % s;
-  double *C = tile_ptr(M, i, k) + (int64_t)b * IB * nb + rl * IB;
-  gemm_block<false>(C, nb, C, nb, W, IB, IB, smem);
-}
-
-// Cholesky + triangular inverse of the 128 x 128 diagonal block b of tile
-// (k, k), in LDS, one workgroup.  Writes L (lower part only) back in place,
-// W = L^-1 (full 128 x 128, zero upper) to d_w, and the first failing pivot
-// (1-based global row) to *d_info via atomicMin.
-constexpr int PLD = IB + 1;  // padded LDS leading dimension
-
-// A pivot at or below 2^-40 of its original diagonal entry (sigma11^2 or
-// sigma22^2 by row parity, 1 in the padding) counts as a failure: the matrix is
-// singular to working precision, and the sign of rounding noise must not decide.
-__global__ __launch_bounds__(256) void k_potrf_inner(TileMap M, int k, int b, double *__restrict__ d_w,
-                                                     int64_t *__restrict__ d_info, double tol0,
-                                                     double tol1, int64_t N) {
-  extern __shared__ double L[];  // IB * PLD
-  __shared__ double tmp[IB];
-  __shared__ int fail;
-  const int tid = threadIdx.x;
-  const int nb = M.nb;
-  double *G = tile_ptr(M, k, k) + (int64_t)b * IB * nb + b * IB;
-  if (tid == 0) fail = 0;
-  for (int e = tid; e < IB * IB; e += 256) {
-    const int r = e % IB, c = e / IB;
-    L[c * PLD + r] = (r >= c) ? G[(int64_t)c * nb + r] : 0.0;
-  }
-  __syncthreads();
-  // right-looking unblocked Cholesky
-  for (int j = 0; j < IB; ++j) {
-    if (tid == 0) {
-      const double d = L[j * PLD + j];
-      const int64_t g = (int64_t)k * nb + (int64_t)b * IB + j;
-      const double tol = g >= N ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
-      if ((!(d > tol) || !(d > 0.0)) && !fail) {
-        fail = 1;
-        atomicMin((unsigned long long *)d_info,
-                  (unsigned long long)((int64_t)k * nb + (int64_t)b * IB + j + 1));
-      }
-      L[j * PLD + j] = sqrt(d);
-    }
-    __syncthreads();
-    const double djj = L[j * PLD + j];
-    for (int r = j + 1 + tid; r < IB; r += 256) L[j * PLD + r] /= djj;
-    __syncthreads();
-    const int m = IB - 1 - j;
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = j + 1 + e % m, c = j + 1 + e / m;
-      if (r >= c) L[c * PLD + r] -= L[j * PLD + r] * L[j * PLD + c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < IB * IB; e += 256) {
-    const int r = e % IB, c = e / IB;
-    if (r >= c) G[(int64_t)c * nb + r] = L[c * PLD + r];
-  }
-  // in-place inverse of the lower factor, columns right to left:
-  // W[i][j] = -(sum_{m=j+1..i} W[i][m] L[m][j]) / L[j][j]
-  for (int j = IB - 1; j >= 0; --j) {
-    const double ljj = L[j * PLD + j];
-    for (int i = j + 1 + tid; i < IB; i += 256) {
-      double s = 0.0;
-      for (int m = j + 1; m <= i; ++m) s += L[m * PLD + i] * L[j * PLD + m];
-      tmp[i] = s;
-    }
-    __syncthreads();
-    const double wjj = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < IB; i += 256) L[j * PLD + i] = -tmp[i] * wjj;
-    if (tid == 0) L[j * PLD + j] = wjj;
-    __syncthreads();
-  }
-  for (int e = tid; e < IB * IB; e += 256) {
-    const int r = e % IB, c = e / IB;
-    d_w[c * IB + r] = (r >= c) ? L[c * PLD + r] : 0.0;
-  }
-}
-
-constexpr size_t POTRF_LDS = sizeof(double) * IB * PLD;
 
 struct PivotTol {
   double t0, t1;
   int64_t N;
 };
 
-static int panel_factor(const TileMap &M, int k, double *d_w, int64_t *d_info, const PivotTol &pt,
+static int panel_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
                         hipStream_t st) {
-  const int s = M.nb / IB;
-  const int nrb = (M.T - k) * s;  // row blocks of panel k
+  const int s = M.nb / PB;
+  const int nrb = (M.T - k) * s;  // 64-row blocks of panel k
   for (int b = 0; b < s; ++b) {
-    hipLaunchKernelGGL(k_potrf_inner, dim3(1), dim3(256), POTRF_LDS, st, M, k, b, d_w, d_info,
-                       pt.t0, pt.t1, pt.N);
-    if (int rc = check_launch("potrf_inner")) return rc;
+    hipLaunchKernelGGL(k_potrf64, dim3(1), dim3(256), 0, st, M, k, b, winv, d_info, pt.t0, pt.t1,
+                       pt.N);
+    if (int rc = check_launch("potrf64")) return rc;
     const int nbelow = nrb - (b + 1);
     if (nbelow > 0) {
-      hipLaunchKernelGGL(k_trsm_inner, dim3(nbelow), dim3(256), GEMM_LDS * sizeof(double), st, M,
-                         k, b, (const double *)d_w);
-      if (int rc = check_launch("trsm_inner")) return rc;
+      const double *W = winv + ((int64_t)k * s + b) * PB * PB;
+      hipLaunchKernelGGL(k_trsm64, dim3(nbelow), dim3(256), 0, st, M, k, b, W);
+      if (int rc = check_launch("trsm64")) return rc;
     }
     if (b + 1 < s) {
       const int ncb = s - (b + 1);
-      hipLaunchKernelGGL(k_panel_update, dim3(nbelow * ncb), dim3(256), GEMM_LDS * sizeof(double),
-                         st, M, k, b, nrb);
-      if (int rc = check_launch("panel_update")) return rc;
+      hipLaunchKernelGGL(k_panel_update64, dim3(nbelow * ncb), dim3(256), 0, st, M, k, b, nrb);
+      if (int rc = check_launch("panel_update64")) return rc;
     }
   }
   return 0;
@@ -339,22 +442,13 @@ static int trailing(const TileMap &M, int64_t N, int k, int jlo, int jhi, hipStr
   return check_launch("update_trailing");
 }
 
-// Kernels with more than the default dynamic LDS opt in once per process.
+// The trailing-update kernel uses exactly 64 KB of dynamic LDS; opt in once.
 static int lds_optin() {
   static int done = 0;
   if (done) return 0;
-  hipError_t e = hipFuncSetAttribute((const void *)k_potrf_inner,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)POTRF_LDS);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_update_trailing,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(GEMM_LDS * sizeof(double)));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_panel_update, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(GEMM_LDS * sizeof(double)));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_trsm_inner, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(GEMM_LDS * sizeof(double)));
+  hipError_t e = hipFuncSetAttribute((const void *)k_update_trailing,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(GEMM_LDS * sizeof(double)));
   if (e != hipSuccess) {
     set_error("hipFuncSetAttribute (dynamic LDS) failed: %s", hipGetErrorString(e));
     return MVG_ERR_LAUNCH;
@@ -367,10 +461,9 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   if (int rc = lds_optin()) return rc;
   const TileMap M = A->map();
   const int T = M.T;
-  double *d_w = nullptr;
-  if (hipMallocAsync((void **)&d_w, sizeof(double) * IB * IB * 2, st) != hipSuccess) {
-    set_error("hipMallocAsync failed for the panel workspace");
-    return MVG_ERR_ALLOC;
+  if (!A->d_winv) {
+    set_error("dense_potrf: matrix has no inverse-block store");
+    return MVG_ERR_STATE;
   }
   hipStream_t side = side_stream();
   hipEvent_t evP, evR, ev0;
@@ -378,11 +471,10 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventCreateWithFlags(&evR, hipEventDisableTiming);
   hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
   int rc = 0;
-  double *w_side = d_w + IB * IB;  // panel workspace used on the side stream
   const PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
   hipEventRecord(ev0, st);
   hipStreamWaitEvent(side, ev0, 0);
-  rc = panel_factor(M, 0, w_side, d_info, pt, side);
+  rc = panel_factor(M, 0, A->d_winv, d_info, pt, side);
   hipEventRecord(evP, side);
   for (int k = 0; k < T && !rc; ++k) {
     hipStreamWaitEvent(st, evP, 0);
@@ -391,14 +483,13 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
     if (rc) break;
     if (k + 1 < T) {
       rc = trailing(M, A->N, k, k + 1, k + 1, side);
-      if (!rc) rc = panel_factor(M, k + 1, w_side, d_info, pt, side);
+      if (!rc) rc = panel_factor(M, k + 1, A->d_winv, d_info, pt, side);
       hipEventRecord(evP, side);
       hipStreamWaitEvent(side, evR, 0);
     }
   }
   hipEventRecord(evP, side);
   hipStreamWaitEvent(st, evP, 0);
-  hipFreeAsync(d_w, st);
   hipEventDestroy(evP);
   hipEventDestroy(evR);
   hipEventDestroy(ev0);
@@ -407,106 +498,126 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
 
 // ------------------------------------------------------- triangular solves
 //
-// Vectors are padded to Np = T nb.  nrhs right-hand sides are stored column
-// after column with leading dimension Np; blockIdx.z selects the column.
+// Vectors are padded to Np = T nb; nrhs right-hand sides are stored column
+// after column with leading dimension ldv, blockIdx.z selects the column.
+// The diagonal tiles are solved with the 64 x 64 inverses kept by the
+// factorisation, so each step is a pair of small matrix-vector products.
 
-// Solve L_kk y = v_k in place (one workgroup, 64-wide blocks: wave 0 solves
-// the 64 x 64 triangle with lane shuffles, all waves update the rows below).
-__global__ __launch_bounds__(256) void k_trsv_diag_fwd(TileMap M, int k, double *__restrict__ V,
-                                                      int64_t ldv) {
+// v_k <- L_kk^-1 v_k: for inner blocks b = 0..s-1: y_b = W_b v_b, then the
+// rows of the tile below block b lose L[rows, b] y_b.  One workgroup.
+__global__ __launch_bounds__(256) void k_trsv_tile_fwd(TileMap M, int k,
+                                                       const double *__restrict__ winv,
+                                                       double *__restrict__ V, int64_t ldv) {
   __shared__ double v[1024];
-  const int nb = M.nb, tid = threadIdx.x;
+  __shared__ double part[4][PB];
+  const int nb = M.nb, tid = threadIdx.x, s = nb / PB;
+  const int row = tid & 63, wave = tid >> 6;
   double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
   const double *Lk = tile_ptr(M, k, k);
   for (int r = tid; r < nb; r += 256) v[r] = vk[r];
   __syncthreads();
-  for (int b0 = 0; b0 < nb; b0 += 64) {
-    if (tid < 64) {
-      double vi = v[b0 + tid];
-      for (int c = 0; c < 64; ++c) {
-        const double lcc = Lk[(int64_t)(b0 + c) * nb + b0 + c];
-        double yc = __shfl(vi, c) / lcc;
-        if (tid == c) vi = yc;
-        if (tid > c) vi -= Lk[(int64_t)(b0 + c) * nb + b0 + tid] * yc;
-      }
-      v[b0 + tid] = vi;
-    }
+  for (int b = 0; b < s; ++b) {
+    const double *W = winv + ((int64_t)k * s + b) * PB * PB;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int c = wave * 16; c < wave * 16 + 16; ++c) acc += W[c * PB + row] * v[b * PB + c];
+    part[wave][row] = acc;
     __syncthreads();
-    for (int r = b0 + 64 + tid; r < nb; r += 256) {
-      double s = 0.0;
-      for (int c = 0; c < 64; ++c) s += Lk[(int64_t)(b0 + c) * nb + r] * v[b0 + c];
-      v[r] -= s;
+    if (tid < PB) v[b * PB + tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+    __syncthreads();
+    for (int r = (b + 1) * PB + tid; r < nb; r += 256) {
+      double t = 0.0;
+      const double *col = Lk + (int64_t)(b * PB) * nb + r;
+#pragma unroll 8
+      for (int c = 0; c < PB; ++c) t += col[(int64_t)c * nb] * v[b * PB + c];
+      v[r] -= t;
     }
     __syncthreads();
   }
   for (int r = tid; r < nb; r += 256) vk[r] = v[r];
 }
 
-// v_i -= L_ik y_k for tiles i in (k, T): one thread per row, 256 rows per block.
+// v_i -= L_ik y_k for tiles i in (k, T): 64 rows per workgroup, the four waves
+// take a quarter of the columns each and are added in a fixed order.
 __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__restrict__ V,
                                                  int64_t ldv) {
   __shared__ double y[1024];
-  const int nb = M.nb, tid = threadIdx.x;
+  __shared__ double part[4][64];
+  const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *Vc = V + (int64_t)blockIdx.z * ldv;
-  const int chunks = (nb + 255) / 256;
+  const int chunks = nb / 64;
   const int i = k + 1 + blockIdx.x / chunks;
-  const int r = (blockIdx.x % chunks) * 256 + tid;
+  const int r = (blockIdx.x % chunks) * 64 + lane;
   for (int c = tid; c < nb; c += 256) y[c] = Vc[(int64_t)k * nb + c];
   __syncthreads();
-  if (r >= nb) return;
-  const double *L = tile_ptr(M, i, k);
-  double s = 0.0;
-  for (int c = 0; c < nb; ++c) s += L[(int64_t)c * nb + r] * y[c];
-  Vc[(int64_t)i * nb + r] -= s;
+  const double *L = tile_ptr(M, i, k) + r;
+  const int q = nb / 4;
+  double s0 = 0.0, s1 = 0.0;
+  for (int c = wave * q; c < wave * q + q; c += 2) {
+    s0 += L[(int64_t)c * nb] * y[c];
+    s1 += L[(int64_t)(c + 1) * nb] * y[c + 1];
+  }
+  part[wave][lane] = s0 + s1;
+  __syncthreads();
+  if (tid < 64)
+    Vc[(int64_t)i * nb + r] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
 }
 
-// Solve L_kk^T w = v_k in place.
-__global__ __launch_bounds__(256) void k_trsv_diag_bwd(TileMap M, int k, double *__restrict__ V,
-                                                      int64_t ldv) {
+// v_k <- L_kk^-T v_k: inner blocks from the bottom: v_b -= L[rows below b, b]^T
+// y_below, then y_b = W_b^T v_b.
+__global__ __launch_bounds__(256) void k_trsv_tile_bwd(TileMap M, int k,
+                                                       const double *__restrict__ winv,
+                                                       double *__restrict__ V, int64_t ldv) {
   __shared__ double v[1024];
-  const int nb = M.nb, tid = threadIdx.x;
+  __shared__ double part[4][PB];
+  const int nb = M.nb, tid = threadIdx.x, s = nb / PB;
+  const int lane = tid & 63, wave = tid >> 6;
   double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
   const double *Lk = tile_ptr(M, k, k);
   for (int r = tid; r < nb; r += 256) v[r] = vk[r];
   __syncthreads();
-  for (int b0 = nb - 64; b0 >= 0; b0 -= 64) {
-    if (tid < 64) {
-      double vi = v[b0 + tid];
-      for (int c = 63; c >= 0; --c) {
-        const double lcc = Lk[(int64_t)(b0 + c) * nb + b0 + c];
-        double wc = __shfl(vi, c) / lcc;
-        if (tid == c) vi = wc;
-        if (tid < c) vi -= Lk[(int64_t)(b0 + tid) * nb + b0 + c] * wc;  // L[c][tid]
-      }
-      v[b0 + tid] = vi;
+  for (int b = s - 1; b >= 0; --b) {
+    // v_b[c] -= sum_{r >= (b+1)64} L[r][b64 + c] v[r]: one wave per column
+    for (int c = wave; c < PB; c += 4) {
+      const double *col = Lk + (int64_t)(b * PB + c) * nb;
+      double t = 0.0;
+      for (int r = (b + 1) * PB + lane; r < nb; r += 64) t += col[r] * v[r];
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      if (lane == 0) part[0][c] = t;
     }
     __syncthreads();
-    // rows r < b0: v_r -= sum_{c in block} L[c][r] w_c  (L column r, rows b0..b0+63)
-    for (int r = tid; r < b0; r += 256) {
-      double s = 0.0;
-      const double *col = Lk + (int64_t)r * nb + b0;
-      for (int c = 0; c < 64; ++c) s += col[c] * v[b0 + c];
-      v[r] -= s;
+    if (tid < PB) v[b * PB + tid] -= part[0][tid];
+    __syncthreads();
+    // y_b = W_b^T v_b: y[c] = sum_r W[r][c] v[r] (column c of W is contiguous)
+    const double *W = winv + ((int64_t)k * s + b) * PB * PB;
+    {
+      const int c = lane;
+      double acc = 0.0;
+#pragma unroll 4
+      for (int r = wave * 16; r < wave * 16 + 16; ++r) acc += W[c * PB + r] * v[b * PB + r];
+      part[wave][c] = acc;
     }
+    __syncthreads();
+    if (tid < PB) v[b * PB + tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
     __syncthreads();
   }
   for (int r = tid; r < nb; r += 256) vk[r] = v[r];
 }
 
-// v_j -= L_kj^T w_k for tiles j in [0, k): one wave per column, lanes over rows.
+// v_j -= L_kj^T w_k for tiles j in [0, k): 64 columns per workgroup, one wave
+// per column at a time, lanes over rows.
 __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__restrict__ V,
                                                  int64_t ldv) {
   __shared__ double w[1024];
   const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *Vc = V + (int64_t)blockIdx.z * ldv;
-  const int cpb = 64;  // columns per block
-  const int cb = nb / cpb;
+  const int cb = nb / 64;
   const int j = blockIdx.x / cb;
-  const int c0 = (blockIdx.x % cb) * cpb;
+  const int c0 = (blockIdx.x % cb) * 64;
   for (int r = tid; r < nb; r += 256) w[r] = Vc[(int64_t)k * nb + r];
   __syncthreads();
   const double *L = tile_ptr(M, k, j);
-  for (int c = c0 + wave; c < c0 + cpb; c += 4) {
+  for (int c = c0 + wave; c < c0 + 64; c += 4) {
     const double *col = L + (int64_t)c * nb;
     double s = 0.0;
     for (int r = lane; r < nb; r += 64) s += col[r] * w[r];
@@ -515,17 +626,22 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__re
   }
 }
 
-int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) {
-  const TileMap M = A->map();
-  const int nb = M.nb;
-  if (nb > 1024 || nb % 64) {
-    set_error("triangular solve needs nb <= 1024 and nb %% 64 == 0");
+static int solve_args_ok(const mvg_mat *A) {
+  if (A->nb > 1024 || A->nb % PB || !A->d_winv) {
+    set_error("triangular solve needs nb <= 1024, nb %% 64 == 0 and a factored matrix");
     return MVG_ERR_STATE;
   }
-  const int chunks = (nb + 255) / 256;
+  return 0;
+}
+
+int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) {
+  if (int rc = solve_args_ok(A)) return rc;
+  const TileMap M = A->map();
+  const int chunks = M.nb / 64;
   for (int k = 0; k < M.T; ++k) {
-    hipLaunchKernelGGL(k_trsv_diag_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M, k, d_V, A->Np);
-    if (int rc = check_launch("trsv_diag_fwd")) return rc;
+    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M, k,
+                       (const double *)A->d_winv, d_V, A->Np);
+    if (int rc = check_launch("trsv_tile_fwd")) return rc;
     if (k + 1 < M.T) {
       hipLaunchKernelGGL(k_gemv_fwd, dim3((M.T - k - 1) * chunks, 1, nrhs), dim3(256), 0, st, M, k,
                          d_V, A->Np);
@@ -540,15 +656,13 @@ int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st) {
 }
 
 int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
+  if (int rc = solve_args_ok(A)) return rc;
   const TileMap M = A->map();
   const int nb = M.nb;
-  if (nb > 1024 || nb % 64) {
-    set_error("triangular solve needs nb <= 1024 and nb %% 64 == 0");
-    return MVG_ERR_STATE;
-  }
   for (int k = M.T - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_trsv_diag_bwd, dim3(1), dim3(256), 0, st, M, k, d_v, A->Np);
-    if (int rc = check_launch("trsv_diag_bwd")) return rc;
+    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(1), dim3(256), 0, st, M, k, (const double *)A->d_winv,
+                       d_v, A->Np);
+    if (int rc = check_launch("trsv_tile_bwd")) return rc;
     if (k > 0) {
       hipLaunchKernelGGL(k_gemv_bwd, dim3(k * (nb / 64)), dim3(256), 0, st, M, k, d_v, A->Np);
       if (int rc = check_launch("gemv_bwd")) return rc;
