@@ -59,7 +59,8 @@ enum {
 
 typedef struct {
     int precision;      /* MVG_FP64 / MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_TLR        */
-    int nb;             /* tile size; dense and mixed: multiple of 128 (0 = 512);     */
+    int nb;             /* tile size; dense and mixed: 128, 256, 512, 768 or 1024    */
+                        /* (0 = 512);                                                  */
                         /* TLR: even, >= 64 (0 = 1200)                                 */
     int band_tiles;     /* mixed: tiles with |I - J| < band_tiles stay FP64 (0 = 2)   */
     double tlr_acc;     /* TLR: absolute singular-value threshold (0 = 1e-7)          */

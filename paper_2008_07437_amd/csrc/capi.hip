@@ -169,7 +169,7 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   if (d.precision == MVG_TLR) {
     if (d.nb < 64 || d.nb % 2) return -2;
   } else {
-    if (d.nb < IB || d.nb % IB || d.nb > 1024) return -2;
+    if (d.nb != 128 && d.nb != 256 && d.nb != 512 && d.nb != 768 && d.nb != 1024) return -2;
   }
   if (d.band_tiles <= 0) d.band_tiles = 2;
   if (d.tlr_acc <= 0.0) d.tlr_acc = 1e-7;
@@ -257,7 +257,7 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   ok = ok && hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
   ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
   ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_winv, sizeof(double) * (size_t)A->Np * 64) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_winv, sizeof(double) * (size_t)A->Np * A->nb) == hipSuccess;
   if (!ok) {
     hipGetLastError();
     set_error("device allocation of %.3f GB for a %lld-location matrix failed",
@@ -325,7 +325,8 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
   const int T = (int)((N + d.nb - 1) / d.nb);
   const int64_t Np = (int64_t)T * d.nb;
   size_t b = layout_bytes(n_loc, d);
-  b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 64 * Np);
+  // matrix + inverse diagonal tiles + panel workspace + vectors
+  b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * Np * d.nb);
   b += (sizeof(int64_t) + sizeof(int)) * (size_t)T * (T + 1) / 2;
   return b;
 }

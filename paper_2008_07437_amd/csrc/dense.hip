@@ -12,6 +12,7 @@
 // the inverse, and the rest of the panel gets a rank-128 update.  Every
 // GEMM-shaped step runs on v_mfma_f64_16x16x4_f64.
 #include <algorithm>
+#include <cstdlib>
 
 #include "mvgeo_internal.h"
 
@@ -44,132 +45,208 @@ __device__ __forceinline__ double *tile_ptr(TileMap M, int I, int J) {
   return reinterpret_cast<double *>(M.base + M.off[tidx(I, J, M.T)]);
 }
 
-// --------------------------------------------------------- 128x128 GEMM block
+// ------------------------------------------------- trailing update (GEMM)
 //
-// C (128x128) = or -= A (128xK) * B (128xK)^T, all column-major.  C may alias
-// A (in-place TRSM): every global read of A completes before the epilogue
-// writes C, so neither pointer is declared restrict.  256 threads,
-// 4 waves in a 2x2 grid, each wave 64x64 = 4x4 MFMA 16x16 tiles.  K is staged
-// through LDS 16 at a time, double buffered.  The MFMA takes the B fragment as
-// its first operand so that each lane's accumulator holds 16 consecutive rows
-// of one column: lane l, element e <-> C[l%16][l/16 + 4e] of the 16x16 tile.
-constexpr int KB = 16;
-constexpr int GEMM_LDS = 2 * 2 * IB * KB;  // doubles
+// A_ij -= L_ik L_jk^T over all tiles of the trailing matrix, in 128 x 128
+// output blocks.  Each workgroup (256 threads, 4 waves in a 2 x 2 grid, each
+// wave 64 x 64 = 4 x 4 MFMA 16x16 tiles) is persistent: it walks a contiguous
+// chunk of output blocks, and the chunks of the workgroups on one XCD are
+// adjacent, so neighbouring blocks (which share panel strips) meet in that
+// XCD's L2.  K is streamed through LDS in slices of TKB columns with TS-stage
+// pipelining by direct global->LDS loads (global_load_lds_dwordx4): no VGPR
+// staging, one barrier per slice, and the slices of the next block are in
+// flight while the current block's C update is written.  The MFMA takes the
+// B fragment as its first operand so that each lane's accumulator holds 16
+// consecutive rows of one column: lane l, element e <-> C[l%16][l/16 + 4e].
+constexpr int KB = 16;   // K slice of the small panel GEMM
+constexpr int TKB = 8;   // K slice of the trailing GEMM
+constexpr int TS = 4;    // pipeline stages of the trailing GEMM
+constexpr int TD = TKB * 2 / 4;  // direct loads per wave per stage (1 KB each)
 
-template <bool SUB>
-__device__ __forceinline__ void gemm_block(double *C, int ldc, const double *A, int lda,
-                                           const double *__restrict__ B, int ldb, int K,
-                                           double *__restrict__ smem) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
-  // LDS: buffer b holds the A slice at smem + b*2*IB*KB and the B slice after it
+#define MVG_LDS(p) ((__attribute__((address_space(3))) void *)(p))
 
-  dbl4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+// s_waitcnt vmcnt(n) leaving lgkmcnt / expcnt unconstrained (GFX9 encoding).
+__device__ __forceinline__ void wait_vmcnt_8() { __builtin_amdgcn_s_waitcnt(0x0F78); }
+__device__ __forceinline__ void wait_vmcnt_0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+static_assert((TS - 2) * TD == 8, "wait_vmcnt_8 encodes the steady-state count");
 
-  // global -> register staging: thread loads column kk = tid/16, rows (tid%16)*8 .. +8
-  const int kk = tid >> 4, r8 = (tid & 15) * 8;
-  const double *ga = A + (int64_t)kk * lda + r8;
-  const double *gb = B + (int64_t)kk * ldb + r8;
-  double *la = smem + kk * IB + r8;
-  double *lb = smem + IB * KB + kk * IB + r8;
-  const int64_t stepa = (int64_t)KB * lda, stepb = (int64_t)KB * ldb;
-  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define MVG_GLOAD(pa, pb)                                               \
-  do {                                                                  \
-    const double2 *qa_ = reinterpret_cast<const double2 *>(pa);         \
-    const double2 *qb_ = reinterpret_cast<const double2 *>(pb);         \
-    ra0 = qa_[0]; ra1 = qa_[1]; ra2 = qa_[2]; ra3 = qa_[3];             \
-    rb0 = qb_[0]; rb1 = qb_[1]; rb2 = qb_[2]; rb3 = qb_[3];             \
-  } while (0)
-#define MVG_SSTORE(off)                                                 \
-  do {                                                                  \
-    double2 *sa_ = reinterpret_cast<double2 *>(la + (off));             \
-    double2 *sb_ = reinterpret_cast<double2 *>(lb + (off));             \
-    sa_[0] = ra0; sa_[1] = ra1; sa_[2] = ra2; sa_[3] = ra3;             \
-    sb_[0] = rb0; sb_[1] = rb1; sb_[2] = rb2; sb_[3] = rb3;             \
-  } while (0)
+struct TrailBlock {
+  const double *A, *B;
+  double *C;
+  int nk;  // K slices of this block
+};
 
-  const int nk = K / KB;
-  MVG_GLOAD(ga, gb);
-  MVG_SSTORE(0);
-  __syncthreads();
-  const int l16 = lane & 15, lk = lane >> 4;
-  for (int kb = 0; kb < nk; ++kb) {
-    const int buf = kb & 1;
-    const bool more = kb + 1 < nk;
-    if (more) MVG_GLOAD(ga + (kb + 1) * stepa, gb + (kb + 1) * stepb);
-    const double *a = smem + buf * 2 * IB * KB + wr * 64 + l16;
-    const double *b = smem + buf * 2 * IB * KB + IB * KB + wc * 64 + l16;
-#pragma unroll
-    for (int ks = 0; ks < KB; ks += 4) {
-      double af[4], bf[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        af[t] = a[(ks + lk) * IB + t * 16];
-        bf[t] = b[(ks + lk) * IB + t * 16];
-      }
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 4; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[tj], af[ti], acc[ti][tj], 0, 0, 0);
-    }
-    if (more) MVG_SSTORE((buf ^ 1) * 2 * IB * KB);
-    __syncthreads();
-  }
-#undef MVG_GLOAD
-#undef MVG_SSTORE
-  // epilogue
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = wr * 64 + ti * 16 + l16;
-        const int col = wc * 64 + tj * 16 + lk + 4 * e;
-        double *p = C + (int64_t)col * ldc + row;
-        if (SUB) *p -= acc[ti][tj][e];
-        else *p = acc[ti][tj][e];
-      }
-}
+enum { TRAIL_UPDATE = 0, TRAIL_TRSM = 1 };
 
-// XCD-aware remap: blocks are dealt round-robin to the 8 XCDs; give each XCD
-// a contiguous range of logical blocks so neighbouring tiles share its L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nwg_padded) {
-  const int64_t per = nwg_padded >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-// Trailing update of step k for tile columns j in [jlo, jhi], rows i in [j, T):
-// A_ij -= L_ik L_jk^T (GEMM; SYRK on the diagonal tile, lower sub-blocks only).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update_trailing(TileMap M, int k, int jlo, int jhi,
-                                                         int64_t nwg, int64_t nwg_pad) {
-  extern __shared__ double smem[];
-  const int64_t lid = xcd_remap(blockIdx.x, nwg_pad);
-  if (lid >= nwg) return;
-  const int s = M.nb / IB, ss = s * s;
-  int64_t t = lid / ss;
+// Logical block lid of the trailing update of step k over columns j >= jlo:
+// tile (i, j) and 128 x 128 sub-block (sr, sc); false for the strict upper
+// sub-blocks of a diagonal tile (SYRK computes the lower part only).
+// Panel TRSM (mode TRAIL_TRSM): tile (k+1+lid/ss, k), output sub-block (sr, sc)
+// = P[sr] W_k[sc]^T with P the copy of the panel; W_k is lower triangular, so
+// only the first (sc+1)*128 columns of K contribute.
+template <int MODE>
+__device__ __forceinline__ bool trail_decode(const TileMap &M, int k, int jlo, int64_t lid,
+                                             const double *P, const double *W, TrailBlock &t) {
+  const int s = M.nb / IB, ss = s * s, nb = M.nb;
+  int64_t q = lid / ss;
   const int sub = (int)(lid % ss);
+  const int sr = sub % s, sc = sub / s;
+  if (MODE == TRAIL_TRSM) {
+    const int i = k + 1 + (int)q;
+    t.C = tile_ptr(M, i, k) + (int64_t)sc * IB * nb + sr * IB;
+    t.A = P + q * (int64_t)nb * nb + sr * IB;
+    t.B = W + sc * IB;
+    t.nk = (sc + 1) * (IB / TKB);
+    return true;
+  }
   int j = jlo;
-  while (t >= M.T - j) {
-    t -= M.T - j;
+  while (q >= M.T - j) {
+    q -= M.T - j;
     ++j;
   }
-  const int i = j + (int)t;
-  const int sr = sub % s, sc = sub / s;
-  if (i == j && sr < sc) return;
-  const int nb = M.nb;
-  double *C = tile_ptr(M, i, j) + (int64_t)sc * IB * nb + sr * IB;
-  const double *A = tile_ptr(M, i, k) + sr * IB;
-  const double *B = tile_ptr(M, j, k) + sc * IB;
-  gemm_block<true>(C, nb, A, nb, B, nb, nb, smem);
-  (void)jhi;
+  const int i = j + (int)q;
+  if (i == j && sr < sc) return false;
+  t.C = tile_ptr(M, i, j) + (int64_t)sc * IB * nb + sr * IB;
+  t.A = tile_ptr(M, i, k) + sr * IB;
+  t.B = tile_ptr(M, j, k) + sc * IB;
+  t.nk = nb / TKB;
+  return true;
+}
+
+// First valid block in [lid, lid1), or lid1.
+template <int MODE>
+__device__ __forceinline__ int64_t trail_next(const TileMap &M, int k, int jlo, int64_t lid,
+                                              int64_t lid1, const double *P, const double *W,
+                                              TrailBlock &t) {
+  while (lid < lid1 && !trail_decode<MODE>(M, k, jlo, lid, P, W, t)) ++lid;
+  return lid;
+}
+
+template <int NB, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update_trailing(
+    TileMap M, int k, int jlo, int64_t lid0, int64_t nwg, int64_t chunk, const double *__restrict__ P,
+    const double *__restrict__ W) {
+  __shared__ double sA0[TKB * IB], sA1[TKB * IB], sA2[TKB * IB], sA3[TKB * IB];
+  __shared__ double sB0[TKB * IB], sB1[TKB * IB], sB2[TKB * IB], sB3[TKB * IB];
+#define MVG_STA(u) ((u) == 0 ? sA0 : (u) == 1 ? sA1 : (u) == 2 ? sA2 : sA3)
+#define MVG_STB(u) ((u) == 0 ? sB0 : (u) == 1 ? sB1 : (u) == 2 ? sB2 : sB3)
+  static_assert((NB / TKB) % TS == 0 && (IB / TKB) % TS == 0, "slices per block must divide by TS");
+  const int G = gridDim.x;  // multiple of 8
+  const int b = blockIdx.x;
+  const int64_t bp = (int64_t)(b & 7) * (G >> 3) + (b >> 3);  // XCD-contiguous chunk order
+  const int64_t lid1 = min(nwg, lid0 + (bp + 1) * chunk);
+  TrailBlock cur, nxt;
+  int64_t lc = trail_next<MODE>(M, k, jlo, lid0 + bp * chunk, lid1, P, W, cur);
+  if (lc >= lid1) return;
+  int64_t ln = trail_next<MODE>(M, k, jlo, lc + 1, lid1, P, W, nxt);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave & 1, wc = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // A slice of TKB = 8 columns (1 KB each) and the B slice: wave w loads
+  // columns w and w + 4 of both, one column per direct load; lane l moves
+  // rows 2l, 2l+1.
+  const int loff = 2 * lane;
+#define MVG_ISSUE(pa, pb, kb, st)                                                                 \
+  do {                                                                                            \
+    const double *a_ = (pa) + (int64_t)((kb) * TKB + wave) * NB;                                  \
+    const double *b_ = (pb) + (int64_t)((kb) * TKB + wave) * NB;                                  \
+    __builtin_amdgcn_global_load_lds((const void *)(a_ + loff), MVG_LDS(MVG_STA(st) + wave * IB), \
+                                     16, 0, 0);                                                   \
+    __builtin_amdgcn_global_load_lds((const void *)(a_ + 4 * NB + loff),                         \
+                                     MVG_LDS(MVG_STA(st) + (wave + 4) * IB), 16, 0, 0);          \
+    __builtin_amdgcn_global_load_lds((const void *)(b_ + loff), MVG_LDS(MVG_STB(st) + wave * IB), \
+                                     16, 0, 0);                                                   \
+    __builtin_amdgcn_global_load_lds((const void *)(b_ + 4 * NB + loff),                         \
+                                     MVG_LDS(MVG_STB(st) + (wave + 4) * IB), 16, 0, 0);          \
+  } while (0)
+  static_assert(TD == 4, "MVG_ISSUE issues four direct loads per wave");
+#pragma unroll
+  for (int p = 0; p < TS - 1; ++p) MVG_ISSUE(cur.A, cur.B, p, p);
+  dbl4 acc[4][4];
+  // MFMA(A fragment, B fragment): lane l, element e of tile (ti, tj) holds
+  // C[wr*64 + ti*16 + 4e + l/16][wc*64 + tj*16 + l%16]; the four elements of
+  // a lane sit 4 rows apart in one column, so only one address per tj is live.
+  const int64_t coff = (int64_t)(wc * 64 + l16) * NB + wr * 64 + lk;
+  for (;;) {
+    // the accumulators start from C, the products are subtracted (negated A
+    // fragments) and the block ends with plain stores
+    // one opaque base per column group keeps every other offset an immediate
+    // (the empty asm stops the compiler from re-deriving 64 separate addresses)
+    typedef __attribute__((address_space(1))) double gdouble;  // global, not flat
+    gdouble *cb[4];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      cb[tj] = (gdouble *)(cur.C + coff + (int64_t)tj * 16 * NB);
+      asm volatile("" : "+v"(cb[tj]));
+    }
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[ti][tj][e] = (MODE == TRAIL_UPDATE) ? (double)cb[tj][ti * 16 + 4 * e] : 0.0;
+    const bool have_next = ln < lid1;
+    const int nk = cur.nk;
+    for (int kb0 = 0; kb0 < nk; kb0 += TS) {
+#pragma unroll
+      for (int u = 0; u < TS; ++u) {
+        const int kb = kb0 + u;
+        // TS-1 slices in flight; the oldest (kb) is complete when <= (TS-2) TD remain
+        // the barrier is pinned: no LDS read of this stage and no direct load
+        // into the stage being refilled may be scheduled across it
+        wait_vmcnt_8();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        asm volatile("" ::: "memory");
+        // refill the stage computed in the previous step: next slice of this
+        // block, else the first slices of the next block, else (past the end
+        // of the chunk) the last slice again, in bounds and never read
+        const int p = kb + TS - 1;
+        const bool in_cur = p < nk;
+        const bool use_next = !in_cur && have_next;
+        const double *pa = use_next ? nxt.A : cur.A;
+        const double *pb = use_next ? nxt.B : cur.B;
+        const int pk = in_cur ? p : (use_next ? p - nk : nk - 1);
+        MVG_ISSUE(pa, pb, pk, (u + TS - 1) % TS);
+        const double *a = MVG_STA(u) + wr * 64 + l16;
+        const double *bb = MVG_STB(u) + wc * 64 + l16;
+#pragma unroll
+        for (int ks = 0; ks < TKB; ks += 4) {
+          double af[4], bf[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            af[t] = (MODE == TRAIL_UPDATE) ? -a[(ks + lk) * IB + t * 16] : a[(ks + lk) * IB + t * 16];
+            bf[t] = bb[(ks + lk) * IB + t * 16];
+          }
+#pragma unroll
+          for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj)
+              acc[ti][tj] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(af[ti], bf[tj], acc[ti][tj], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cb[tj][ti * 16 + 4 * e] = acc[ti][tj][e];
+    if (!have_next) break;
+    cur = nxt;
+    lc = ln;
+    ln = trail_next<MODE>(M, k, jlo, lc + 1, lid1, P, W, nxt);
+  }
+  // no direct LDS load may outlive the workgroup
+  wait_vmcnt_0();
+#undef MVG_ISSUE
+#undef MVG_STA
+#undef MVG_STB
 }
 
 // ------------------------------------------------------------ panel kernels
@@ -344,28 +421,29 @@ __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double
       for (int jj = 0; jj < 4; ++jj) x[jq][jj] = xr[jj];
     }
   }
-  double *W = winv + (int64_t)(g0 / PB) * PB * PB;
+  // inverse block (b, b) of W_k = L_kk^-1 (nb x nb, column-major, ld nb)
+  double *W = winv + (int64_t)k * nb * nb + (int64_t)b * PB * nb + b * PB;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int r = ty + 16 * i, c = tx + 16 * jj;
       if (r >= c) G[(int64_t)c * nb + r] = a[i][jj];
-      W[c * PB + r] = (r >= c) ? x[i][jj] : 0.0;
+      W[(int64_t)c * nb + r] = (r >= c) ? x[i][jj] : 0.0;
     }
 }
 
 // Panel TRSM for inner block b: 64-row blocks R in (b, nrb) of panel k:
 // P[R, b] <- P[R, b] W_b^T, in place (each workgroup owns its 64 x 64 block).
 __global__ __launch_bounds__(256) void k_trsm64(TileMap M, int k, int b,
-                                                const double *__restrict__ W) {
+                                                const double *__restrict__ W, int ldw) {
   __shared__ double smem[SMALL_LDS];
   const int s = M.nb / PB;
   const int R = b + 1 + blockIdx.x;
   const int nb = M.nb;
   const int i = k + R / s, rl = R % s;
   double *C = tile_ptr(M, i, k) + (int64_t)b * PB * nb + rl * PB;
-  gemm_block64<false>(C, nb, C, nb, W, PB, PB, smem);
+  gemm_block64<false>(C, nb, C, nb, W, ldw, PB, smem);
 }
 
 // Panel update after inner block b: inner column blocks cb in (b, s), row
@@ -385,113 +463,326 @@ __global__ __launch_bounds__(256) void k_panel_update64(TileMap M, int k, int b,
                      D + (int64_t)b * PB * nb + cb * PB, nb, PB, smem);
 }
 
+// Off-diagonal 64-blocks of W_k = L_kk^-1 at block distance d = i - j:
+// W_ij = -W_ii sum_{m=j..i-1} L_im W_mj (the blocks at smaller distances are
+// already in place).  One workgroup per j; 64 x 64 MFMA products through LDS.
+__global__ __launch_bounds__(256) void k_trtri_step(TileMap M, int k, int d,
+                                                    double *__restrict__ winv) {
+  __shared__ double sa[PB * PB];  // A operand, [kk][r]
+  __shared__ double sb[PB * PB];  // B operand, [kk][c]
+  const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+  const int j = blockIdx.x, i = j + d;
+  const double *L = tile_ptr(M, k, k);
+  double *W = winv + (int64_t)k * nb * nb;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b2 = 0; b2 < 2; ++b2) acc[a][b2] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // stage A[r][kk] (column-major block at base, ld nb) into sa[kk][r]; B^T block
+  // Bt[kk][c] = X[kk][c] of a column-major block X into sb[kk][c]
+  auto mma = [&]() {
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < PB; ks += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        af[t] = sa[(ks + lk) * PB + wr * 32 + t * 16 + l16];
+        bf[t] = sb[(ks + lk) * PB + wc * 32 + t * 16 + l16];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ti], bf[tj], acc[ti][tj], 0, 0, 0);
+    }
+    __syncthreads();
+  };
+  for (int m = j; m < i; ++m) {
+    const double *Lim = L + (int64_t)(m * PB) * nb + i * PB;  // rows i-block, cols m-block
+    const double *Wmj = W + (int64_t)(j * PB) * nb + m * PB;  // rows m-block, cols j-block
+    for (int e = tid; e < PB * PB; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      sa[c * PB + r] = Lim[(int64_t)c * nb + r];  // sa[kk = c][r]
+      sb[r * PB + c] = Wmj[(int64_t)c * nb + r];  // sb[kk = r][c] = Wmj[r][c]
+    }
+    mma();
+  }
+  // T = acc (64 x 64): lane l, element e of tile (ti, tj) is
+  // T[wr*32 + ti*16 + 4e + l/16][wc*32 + tj*16 + l%16]; now W_ij = -W_ii T
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + ti * 16 + 4 * e + lk, c = wc * 32 + tj * 16 + l16;
+        sb[r * PB + c] = acc[ti][tj][e];
+        acc[ti][tj][e] = 0.0;
+      }
+  const double *Wii = W + (int64_t)(i * PB) * nb + i * PB;
+  for (int e = tid; e < PB * PB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    sa[c * PB + r] = Wii[(int64_t)c * nb + r];
+  }
+  mma();
+  double *Wij = W + (int64_t)(j * PB) * nb + i * PB;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr * 32 + ti * 16 + 4 * e + lk, c = wc * 32 + tj * 16 + l16;
+        Wij[(int64_t)c * nb + r] = -acc[ti][tj][e];
+      }
+}
+
+// Zero the strict upper 64-blocks of W_k (the factorisation never writes them).
+__global__ void k_zero_upper_blocks(int nb, int k, double *__restrict__ winv) {
+  const int s = nb / PB;
+  double *W = winv + (int64_t)k * nb * nb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)nb * nb;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % nb), c = (int)(e / nb);
+    if (r / PB < c / PB) W[e] = 0.0;
+  }
+  (void)s;
+}
+
+// P <- the tiles (i, k), i in (k, T) (source of the out-of-place panel TRSM).
+__global__ void k_copy_panel(TileMap M, int k, double *__restrict__ P) {
+  const int64_t per = (int64_t)M.nb * M.nb / 2;  // double2 per tile
+  const int64_t n = (int64_t)(M.T - k - 1) * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / per, o = e % per;
+    const double2 *src = reinterpret_cast<const double2 *>(tile_ptr(M, k + 1 + (int)t, k));
+    reinterpret_cast<double2 *>(P)[e] = src[o];
+  }
+}
+
+// SYRK of one diagonal tile, A_jj -= L_jk L_jk^T (lower 64-blocks), with the
+// small-footprint 64 x 64 block GEMM so that it runs next to the persistent
+// trailing update instead of waiting for it to drain.
+__global__ __launch_bounds__(256) void k_syrk64(TileMap M, int k, int j) {
+  __shared__ double smem[SMALL_LDS];
+  const int s = M.nb / PB;
+  int bi = 0, t = blockIdx.x;  // lower-triangular block (bi, bj), bi >= bj
+  while (t > bi) {
+    t -= bi + 1;
+    ++bi;
+  }
+  const int bj = t;
+  const int nb = M.nb;
+  double *C = tile_ptr(M, j, j) + (int64_t)bj * PB * nb + bi * PB;
+  const double *L = tile_ptr(M, j, k);
+  gemm_block64<true>(C, nb, L + bi * PB, nb, L + bj * PB, nb, nb, smem);
+  (void)s;
+}
+
 struct PivotTol {
   double t0, t1;
   int64_t N;
 };
 
-static int panel_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
-                        hipStream_t st) {
+// Factor the diagonal tile (k, k) in place and fill W_k = L_kk^-1: 64-wide
+// inner blocks (register Cholesky + inverse of the block, in-tile TRSM and
+// update), then the off-diagonal blocks of W_k by block distance.
+static int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
+                       hipStream_t st) {
   const int s = M.nb / PB;
-  const int nrb = (M.T - k) * s;  // 64-row blocks of panel k
+  hipLaunchKernelGGL(k_zero_upper_blocks, dim3(64), dim3(256), 0, st, M.nb, k, winv);
+  if (int rc = check_launch("zero_upper_blocks")) return rc;
   for (int b = 0; b < s; ++b) {
     hipLaunchKernelGGL(k_potrf64, dim3(1), dim3(256), 0, st, M, k, b, winv, d_info, pt.t0, pt.t1,
                        pt.N);
     if (int rc = check_launch("potrf64")) return rc;
-    const int nbelow = nrb - (b + 1);
+    const int nbelow = s - (b + 1);
     if (nbelow > 0) {
-      const double *W = winv + ((int64_t)k * s + b) * PB * PB;
-      hipLaunchKernelGGL(k_trsm64, dim3(nbelow), dim3(256), 0, st, M, k, b, W);
+      const double *W = winv + (int64_t)k * M.nb * M.nb + (int64_t)b * PB * M.nb + b * PB;
+      hipLaunchKernelGGL(k_trsm64, dim3(nbelow), dim3(256), 0, st, M, k, b, W, M.nb);
       if (int rc = check_launch("trsm64")) return rc;
-    }
-    if (b + 1 < s) {
-      const int ncb = s - (b + 1);
-      hipLaunchKernelGGL(k_panel_update64, dim3(nbelow * ncb), dim3(256), 0, st, M, k, b, nrb);
+      hipLaunchKernelGGL(k_panel_update64, dim3(nbelow * nbelow), dim3(256), 0, st, M, k, b, s);
       if (int rc = check_launch("panel_update64")) return rc;
     }
+  }
+  for (int d = 1; d < s; ++d) {
+    hipLaunchKernelGGL(k_trtri_step, dim3(s - d), dim3(256), 0, st, M, k, d, winv);
+    if (int rc = check_launch("trtri_step")) return rc;
   }
   return 0;
 }
 
-// Useful flops of a trailing-update launch (rows past N are padding).
-static double trailing_flops(int64_t N, int nb, int T, int k, int jlo, int jhi) {
+// Useful flops of a trailing-update launch over tile columns [jlo, jhi]
+// (rows past N are padding).
+static double trailing_flops(int64_t N, int nb, int T, int k, int jlo, int jhi, bool skip_first) {
   auto len = [&](int t) { return (double)std::min<int64_t>(nb, N - (int64_t)t * nb); };
   const double K = len(k);
   double f = 0.0;
   for (int j = jlo; j <= jhi; ++j) {
     const double cj = len(j);
-    f += cj * (cj + 1.0) * K;  // SYRK on the diagonal tile
+    if (!(skip_first && j == jlo)) f += cj * (cj + 1.0) * K;  // SYRK on the diagonal tile
     for (int i = j + 1; i < T; ++i) f += 2.0 * len(i) * cj * K;
   }
   return f;
 }
 
-static int trailing(const TileMap &M, int64_t N, int k, int jlo, int jhi, hipStream_t st) {
-  if (jlo > jhi || jlo >= M.T) return 0;
-  const int s = M.nb / IB;
-  int64_t ntile = 0;
-  for (int j = jlo; j <= jhi; ++j) ntile += M.T - j;
-  const int64_t nwg = ntile * s * s;
-  const int64_t pad = (nwg + 7) / 8 * 8;
-  // bytes: C read + written, the two panel operands read once per output tile
-  const double bytes = 8.0 * (double)ntile * M.nb * M.nb * 4.0;
-  int h = prof_begin(MVG_PROF_TRAILING, st, trailing_flops(N, M.nb, M.T, k, jlo, jhi), bytes);
-  hipLaunchKernelGGL(k_update_trailing, dim3((unsigned)pad), dim3(256), GEMM_LDS * sizeof(double),
-                     st, M, k, jlo, jhi, nwg, pad);
-  prof_end(h, st);
+// Persistent grid of the GEMM kernels: two workgroups per CU, minus a few
+// slots left free so that the look-ahead stream's small kernels find a CU
+// (persistent workgroups never retire mid-launch).  MVG_GEMM_RESERVE
+// overrides the number of reserved slots (tuning).
+constexpr int GEMM_CUS = 256;
+static int gemm_reserve() {
+  static int r = -1;
+  if (r < 0) {
+    const char *e = getenv("MVG_GEMM_RESERVE");
+    r = e ? atoi(e) : 32;
+    if (r < 0 || r > 2 * GEMM_CUS - 8) r = 32;
+  }
+  return r;
+}
+// 1: persistent workgroups walking chunks of blocks; 0 (default, measured
+// faster with the look-ahead stream): one block per workgroup, so that
+// workgroups retire continuously and the look-ahead kernels find room
+// (MVG_GEMM_PERSIST, tuning).
+static int gemm_persist() {
+  static int r = -1;
+  if (r < 0) {
+    const char *e = getenv("MVG_GEMM_PERSIST");
+    r = e ? (atoi(e) != 0) : 0;
+  }
+  return r;
+}
+// 1: the next diagonal tile is factored on a second stream while the
+// trailing update runs; 0: one stream (MVG_LOOKAHEAD, tuning).
+static int lookahead() {
+  static int r = -1;
+  if (r < 0) {
+    const char *e = getenv("MVG_LOOKAHEAD");
+    r = e ? (atoi(e) != 0) : 1;
+  }
+  return r;
+}
+
+template <int MODE>
+static int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t nwg,
+                        const double *P, const double *W, hipStream_t st) {
+  const int64_t work = nwg - lid0;
+  if (work <= 0) return 0;
+  int64_t G = gemm_persist() ? std::min<int64_t>(work, 2 * GEMM_CUS - gemm_reserve()) : work;
+  G = (G + 7) / 8 * 8;
+  const int64_t chunk = (work + G - 1) / G;
+  switch (M.nb) {
+#define MVG_CASE(NBV)                                                                          \
+  case NBV:                                                                                    \
+    hipLaunchKernelGGL((k_update_trailing<NBV, MODE>), dim3((unsigned)G), dim3(256), 0, st, M, \
+                       k, jlo, lid0, nwg, chunk, P, W);                                        \
+    break;
+    MVG_CASE(128) MVG_CASE(256) MVG_CASE(512) MVG_CASE(768) MVG_CASE(1024)
+#undef MVG_CASE
+    default:
+      set_error("tile size %d is not one of 128, 256, 512, 768, 1024", M.nb);
+      return MVG_ERR_STATE;
+  }
   return check_launch("update_trailing");
 }
 
-// The trailing-update kernel uses exactly 64 KB of dynamic LDS; opt in once.
-static int lds_optin() {
-  static int done = 0;
-  if (done) return 0;
-  hipError_t e = hipFuncSetAttribute((const void *)k_update_trailing,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)(GEMM_LDS * sizeof(double)));
-  if (e != hipSuccess) {
-    set_error("hipFuncSetAttribute (dynamic LDS) failed: %s", hipGetErrorString(e));
-    return MVG_ERR_LAUNCH;
-  }
-  done = 1;
-  return 0;
+// Trailing update of step k: A_ij -= L_ik L_jk^T for k < j <= i, optionally
+// without the diagonal tile (k+1, k+1) (first = 0: that tile is left to the
+// look-ahead stream), or only that tile (only_first).
+static int trailing(const TileMap &M, int64_t N, int k, bool skip_first, bool only_first,
+                    hipStream_t st) {
+  const int jlo = k + 1;
+  if (jlo >= M.T) return 0;
+  const int s = M.nb / IB;
+  const int64_t ss = (int64_t)s * s;
+  const int64_t ntile = only_first ? 1 : (int64_t)(M.T - jlo) * (M.T - jlo + 1) / 2;
+  const int64_t nwg = ntile * ss;
+  const int64_t lid0 = skip_first ? ss : 0;
+  if (lid0 >= nwg) return 0;
+  const double flops = only_first ? (double)std::min<int64_t>(M.nb, N - (int64_t)jlo * M.nb) *
+                                        ((double)std::min<int64_t>(M.nb, N - (int64_t)jlo * M.nb) + 1) *
+                                        (double)std::min<int64_t>(M.nb, N - (int64_t)k * M.nb)
+                                  : trailing_flops(N, M.nb, M.T, k, jlo, M.T - 1, skip_first);
+  const double bytes = 8.0 * (double)(ntile - (skip_first ? 1 : 0)) * M.nb * M.nb * 4.0;
+  int h = prof_begin(MVG_PROF_TRAILING, st, flops, bytes);
+  int rc = launch_trail<TRAIL_UPDATE>(M, k, jlo, lid0, nwg, nullptr, nullptr, st);
+  prof_end(h, st);
+  return rc;
 }
 
+// Panel TRSM of step k: L_ik = A_ik W_k^T for i in (k, T), out of place from
+// a copy of the panel.
+static int panel_trsm(const TileMap &M, int k, const double *winv, double *P, hipStream_t st) {
+  const int nbelow = M.T - k - 1;
+  if (nbelow <= 0) return 0;
+  hipLaunchKernelGGL(k_copy_panel, dim3(1024), dim3(256), 0, st, M, k, P);
+  if (int rc = check_launch("copy_panel")) return rc;
+  const int s = M.nb / IB;
+  const int64_t nwg = (int64_t)nbelow * s * s;
+  return launch_trail<TRAIL_TRSM>(M, k, 0, 0, nwg, P, winv + (int64_t)k * M.nb * M.nb, st);
+}
+
+// Right-looking tiled Cholesky with one tile of look-ahead.  Caller stream:
+// panel TRSM of column k (GEMM against W_k), then the trailing update of
+// step k except the diagonal tile (k+1, k+1).  Look-ahead stream: as soon as
+// the panel of column k is solved, the SYRK of tile (k+1, k+1) and its
+// factorisation with W_{k+1} (one tile of work, small footprint), so the
+// next panel TRSM never waits for the trailing update.
 int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
-  if (int rc = lds_optin()) return rc;
   const TileMap M = A->map();
   const int T = M.T;
   if (!A->d_winv) {
-    set_error("dense_potrf: matrix has no inverse-block store");
+    set_error("dense_potrf: matrix has no inverse-tile store");
     return MVG_ERR_STATE;
   }
-  hipStream_t side = side_stream();
-  hipEvent_t evP, evR, ev0;
-  hipEventCreateWithFlags(&evP, hipEventDisableTiming);
-  hipEventCreateWithFlags(&evR, hipEventDisableTiming);
+  double *P = nullptr;
+  const size_t pbytes = sizeof(double) * (size_t)std::max(1, T - 1) * M.nb * M.nb;
+  if (hipMallocAsync((void **)&P, pbytes, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("dense_potrf: panel workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  hipStream_t side = lookahead() ? side_stream() : st;
+  hipEvent_t evD, evS, ev0;
+  hipEventCreateWithFlags(&evD, hipEventDisableTiming);
+  hipEventCreateWithFlags(&evS, hipEventDisableTiming);
   hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
-  int rc = 0;
   const PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
+  int rc = 0;
   hipEventRecord(ev0, st);
   hipStreamWaitEvent(side, ev0, 0);
-  rc = panel_factor(M, 0, A->d_winv, d_info, pt, side);
-  hipEventRecord(evP, side);
+  rc = diag_factor(M, 0, A->d_winv, d_info, pt, side);
+  hipEventRecord(evD, side);
   for (int k = 0; k < T && !rc; ++k) {
-    hipStreamWaitEvent(st, evP, 0);
-    if (k + 2 < T) rc = trailing(M, A->N, k, k + 2, T - 1, st);
-    hipEventRecord(evR, st);
+    hipStreamWaitEvent(st, evD, 0);           // W_k ready
+    rc = panel_trsm(M, k, A->d_winv, P, st);  // L_ik, i > k
+    hipEventRecord(evS, st);
     if (rc) break;
     if (k + 1 < T) {
-      rc = trailing(M, A->N, k, k + 1, k + 1, side);
-      if (!rc) rc = panel_factor(M, k + 1, A->d_winv, d_info, pt, side);
-      hipEventRecord(evP, side);
-      hipStreamWaitEvent(side, evR, 0);
+      hipStreamWaitEvent(side, evS, 0);
+      {  // SYRK of tile (k+1, k+1) by step k
+        const int sb = M.nb / PB;
+        const double nj = (double)std::min<int64_t>(M.nb, A->N - (int64_t)(k + 1) * M.nb);
+        const double nk = (double)std::min<int64_t>(M.nb, A->N - (int64_t)k * M.nb);
+        int h = prof_begin(MVG_PROF_TRAILING, side, nj * (nj + 1.0) * nk, 0.0);
+        hipLaunchKernelGGL(k_syrk64, dim3(sb * (sb + 1) / 2), dim3(256), 0, side, M, k, k + 1);
+        prof_end(h, side);
+        rc = check_launch("syrk64");
+      }
+      if (!rc) rc = diag_factor(M, k + 1, A->d_winv, d_info, pt, side);
+      hipEventRecord(evD, side);
+      if (!rc) rc = trailing(M, A->N, k, true, false, st);  // the rest of step k
     }
   }
-  hipEventRecord(evP, side);
-  hipStreamWaitEvent(st, evP, 0);
-  hipEventDestroy(evP);
-  hipEventDestroy(evR);
+  hipEventRecord(evD, side);
+  hipStreamWaitEvent(st, evD, 0);
+  hipFreeAsync(P, st);
+  hipEventDestroy(evD);
+  hipEventDestroy(evS);
   hipEventDestroy(ev0);
   return rc;
 }
@@ -500,41 +791,31 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
 //
 // Vectors are padded to Np = T nb; nrhs right-hand sides are stored column
 // after column with leading dimension ldv, blockIdx.z selects the column.
-// The diagonal tiles are solved with the 64 x 64 inverses kept by the
-// factorisation, so each step is a pair of small matrix-vector products.
+// The diagonal tiles are solved with the inverses W_k kept by the
+// factorisation: each step is a dense triangular matrix-vector product.
 
-// v_k <- L_kk^-1 v_k: for inner blocks b = 0..s-1: y_b = W_b v_b, then the
-// rows of the tile below block b lose L[rows, b] y_b.  One workgroup.
-__global__ __launch_bounds__(256) void k_trsv_tile_fwd(TileMap M, int k,
-                                                       const double *__restrict__ winv,
+// v_k <- W_k v_k (one workgroup; W_k lower triangular, column-major).
+__global__ __launch_bounds__(256) void k_trsv_tile_fwd(int nb, int k, const double *__restrict__ winv,
                                                        double *__restrict__ V, int64_t ldv) {
   __shared__ double v[1024];
-  __shared__ double part[4][PB];
-  const int nb = M.nb, tid = threadIdx.x, s = nb / PB;
-  const int row = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
-  const double *Lk = tile_ptr(M, k, k);
+  const double *W = winv + (int64_t)k * nb * nb;
   for (int r = tid; r < nb; r += 256) v[r] = vk[r];
   __syncthreads();
-  for (int b = 0; b < s; ++b) {
-    const double *W = winv + ((int64_t)k * s + b) * PB * PB;
+  // rows r0..r0+255 per pass; the 4 waves split the columns c <= r
+  double out[4];
+  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
+    const int r = pass * 256 + tid;
     double acc = 0.0;
-#pragma unroll 4
-    for (int c = wave * 16; c < wave * 16 + 16; ++c) acc += W[c * PB + row] * v[b * PB + c];
-    part[wave][row] = acc;
-    __syncthreads();
-    if (tid < PB) v[b * PB + tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-    __syncthreads();
-    for (int r = (b + 1) * PB + tid; r < nb; r += 256) {
-      double t = 0.0;
-      const double *col = Lk + (int64_t)(b * PB) * nb + r;
-#pragma unroll 8
-      for (int c = 0; c < PB; ++c) t += col[(int64_t)c * nb] * v[b * PB + c];
-      v[r] -= t;
-    }
-    __syncthreads();
+    if (r < nb)
+      for (int c = 0; c <= r; ++c) acc += W[(int64_t)c * nb + r] * v[c];
+    out[pass] = acc;
   }
-  for (int r = tid; r < nb; r += 256) vk[r] = v[r];
+  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
+    const int r = pass * 256 + tid;
+    if (r < nb) vk[r] = out[pass];
+  }
 }
 
 // v_i -= L_ik y_k for tiles i in (k, T): 64 rows per workgroup, the four waves
@@ -563,45 +844,26 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__re
     Vc[(int64_t)i * nb + r] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
 }
 
-// v_k <- L_kk^-T v_k: inner blocks from the bottom: v_b -= L[rows below b, b]^T
-// y_below, then y_b = W_b^T v_b.
-__global__ __launch_bounds__(256) void k_trsv_tile_bwd(TileMap M, int k,
-                                                       const double *__restrict__ winv,
+// v_k <- W_k^T v_k: output c = sum_{r >= c} W[r][c] v[r] (column c of W_k is
+// contiguous); one workgroup.
+__global__ __launch_bounds__(256) void k_trsv_tile_bwd(int nb, int k, const double *__restrict__ winv,
                                                        double *__restrict__ V, int64_t ldv) {
   __shared__ double v[1024];
-  __shared__ double part[4][PB];
-  const int nb = M.nb, tid = threadIdx.x, s = nb / PB;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
-  const double *Lk = tile_ptr(M, k, k);
+  const double *W = winv + (int64_t)k * nb * nb;
   for (int r = tid; r < nb; r += 256) v[r] = vk[r];
   __syncthreads();
-  for (int b = s - 1; b >= 0; --b) {
-    // v_b[c] -= sum_{r >= (b+1)64} L[r][b64 + c] v[r]: one wave per column
-    for (int c = wave; c < PB; c += 4) {
-      const double *col = Lk + (int64_t)(b * PB + c) * nb;
-      double t = 0.0;
-      for (int r = (b + 1) * PB + lane; r < nb; r += 64) t += col[r] * v[r];
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-      if (lane == 0) part[0][c] = t;
-    }
-    __syncthreads();
-    if (tid < PB) v[b * PB + tid] -= part[0][tid];
-    __syncthreads();
-    // y_b = W_b^T v_b: y[c] = sum_r W[r][c] v[r] (column c of W is contiguous)
-    const double *W = winv + ((int64_t)k * s + b) * PB * PB;
-    {
-      const int c = lane;
-      double acc = 0.0;
-#pragma unroll 4
-      for (int r = wave * 16; r < wave * 16 + 16; ++r) acc += W[c * PB + r] * v[b * PB + r];
-      part[wave][c] = acc;
-    }
-    __syncthreads();
-    if (tid < PB) v[b * PB + tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-    __syncthreads();
+  __shared__ double out[1024];
+  for (int c = wave; c < nb; c += 4) {
+    const double *col = W + (int64_t)c * nb;
+    double t = 0.0;
+    for (int r = c + lane; r < nb; r += 64) t += col[r] * v[r];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) out[c] = t;
   }
-  for (int r = tid; r < nb; r += 256) vk[r] = v[r];
+  __syncthreads();
+  for (int r = tid; r < nb; r += 256) vk[r] = out[r];
 }
 
 // v_j -= L_kj^T w_k for tiles j in [0, k): 64 columns per workgroup, one wave
@@ -639,7 +901,7 @@ int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) 
   const TileMap M = A->map();
   const int chunks = M.nb / 64;
   for (int k = 0; k < M.T; ++k) {
-    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M, k,
+    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M.nb, k,
                        (const double *)A->d_winv, d_V, A->Np);
     if (int rc = check_launch("trsv_tile_fwd")) return rc;
     if (k + 1 < M.T) {
@@ -660,7 +922,7 @@ int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
   const TileMap M = A->map();
   const int nb = M.nb;
   for (int k = M.T - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(1), dim3(256), 0, st, M, k, (const double *)A->d_winv,
+    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(1), dim3(256), 0, st, nb, k, (const double *)A->d_winv,
                        d_v, A->Np);
     if (int rc = check_launch("trsv_tile_bwd")) return rc;
     if (k > 0) {

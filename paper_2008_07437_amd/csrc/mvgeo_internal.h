@@ -79,7 +79,7 @@ struct mvg_mat {
   int *h_kind = nullptr;
   double *d_x = nullptr, *d_y = nullptr;  // library copies of the locations
   double *d_qtab = nullptr;               // quadrature table of theta
-  double *d_winv = nullptr;               // 64 x 64 inverses of the diagonal blocks of L
+  double *d_winv = nullptr;               // W_k = L_kk^-1 per diagonal tile (nb x nb)
   mvg_theta theta{};
   mvg::MaternArgs margs{};
   // TLR storage (precision == MVG_TLR)
