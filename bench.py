@@ -23,6 +23,28 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+def measured_traffic(kernel: str, workload_tag: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/*_hbm_traffic.md), or None when no summary exists for
+    this workload or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md")):
+        for line in open(path):
+            if not line.startswith("traffic_json:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if rec.get("kernel") != kernel or rec.get("workload") != workload_tag:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+                return None
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(n_full, sample_n, theta, seed):
     """Oracle (as is) on the leading sample_n locations of the same workload,
     scaled to evals/s at n_full by the O(n^3) cost of the factorisation."""
@@ -57,6 +79,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=2400)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -70,6 +94,15 @@ def main():
     import synthetic
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * (1 << 30))
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
+        return
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     n = args.n
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
@@ -144,7 +177,8 @@ def main():
         "roofline": {"kernel": "k_update_trailing", "bound": "mfma",
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
-                     "traffic": None,
+                     "traffic": measured_traffic("k_update_trailing<%d, 0>" % args.nb,
+                                                 "cfg1_n%d_nb%d" % (n, args.nb)),
                      "launches": tr["launches"],
                      "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
                      "flops_per_launch": tr["flops"] / max(1, tr["launches"])},
