@@ -113,7 +113,17 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * index; a failing theta gets h_loglik = -inf).  n_theta > 1 evaluates all
  * theta in one batched launch sequence (bitwise equal to n_theta separate
  * calls).  keep (nullable, n_theta == 1 only) receives a resident factor for
- * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*. */
+ * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*.
+ *
+ * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16; not in the paper): Sigma is
+ * generated once in FP64 and kept for the refinement; the factor has FP64
+ * tiles within band_tiles of the diagonal (all diagonal factorisations FP64)
+ * and FP32 tiles elsewhere, updated on FP32 (or BF16-operand) MFMA.  The solve
+ * x = Sigma^-1 Z is refined in FP64 (r = Z - Sigma x with the FP64 Sigma,
+ * correction from the mixed factor) until ||r|| <= ir_tol ||Z||, ir_max_iter
+ * sweeps, or stagnation; h_quad = Z^T x.  h_logdet is that of the mixed factor
+ * (not refined).  Memory: the FP64 lower tiles plus the mixed copy.
+ * Requires band_tiles >= 2. */
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o,
            double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
@@ -175,12 +185,20 @@ void mvg_factor_destroy(mvg_factor *F);
  * records of one kind: MVG_PROF_TRAILING (the trailing-update GEMM/SYRK
  * kernel, the FLOP sink of the factorisation), MVG_PROF_GEN (covariance
  * generation), MVG_PROF_POTRF (whole factorisation), MVG_PROF_SOLVE (solve and
- * reductions), MVG_PROF_COKRIGE.  *flops and *bytes are algorithmic counts
- * (useful work, no padding).  Synchronises the device. */
+ * reductions), MVG_PROF_COKRIGE, MVG_PROF_LOWP (the FP32/BF16 off-band
+ * update of the mixed-precision factorisation), MVG_PROF_IR (iterative
+ * refinement of the mixed-precision solve).  *flops and *bytes are
+ * algorithmic counts (useful work, no padding).  Synchronises the device. */
 enum { MVG_PROF_TRAILING = 0, MVG_PROF_GEN = 1, MVG_PROF_POTRF = 2, MVG_PROF_SOLVE = 3,
-       MVG_PROF_COKRIGE = 4, MVG_PROF_NKINDS = 5 };
+       MVG_PROF_COKRIGE = 4, MVG_PROF_LOWP = 5, MVG_PROF_IR = 6, MVG_PROF_NKINDS = 7 };
 int mvg_prof_enable(int on);
 int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, double *bytes);
+
+/* Iterative refinement of the last mixed-precision loglik call on the
+ * calling thread, theta index i: *iters = correction sweeps applied,
+ * *relres = final ||Z - Sigma x|| / ||Z||, *converged = 1 if ir_tol was met.
+ * Returns 0, or -1 if there is no such record. */
+int mvg_ir_stats(int i, int *iters, double *relres, int *converged);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *mvg_last_error(void);

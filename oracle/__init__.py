@@ -22,6 +22,10 @@ Each function states the passage of the paper it follows:
   factorisation error.
 * ``round_to`` -- emulation of FP32 / BF16 round-to-nearest-even, used to size
   the mixed-precision error.
+* ``mixed_cholesky_emulated`` -- not in the paper: the mixed-precision tiled
+  factorisation (FP64 band, FP32 / BF16 off the band) emulated in FP64 with
+  rounding at the operand points, to predict the size of its error (not its
+  bits).  Parity unpinned beyond the reductions its tests check.
 """
 from __future__ import annotations
 
@@ -305,3 +309,63 @@ def round_to(a, fmt: str) -> np.ndarray:
         u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
         return u.astype(np.uint32).view(np.float32).astype(np.float64)
     raise ValueError(fmt)
+
+
+def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
+    """Not in the paper.  Right-looking tiled Cholesky of S (padded with an
+    identity block to a multiple of nb) where tiles (I, J) with I - J >= band
+    are stored in FP32 and updated with operands rounded to ``fmt`` ("fp32" or
+    "bf16"), everything else in FP64:
+
+    * off-band tiles start as S rounded to FP32;
+    * diagonal tiles: FP64 Cholesky; W_k = L_kk^-1 (FP64);
+    * panel tiles within the band: L_ik = A_ik W_k^T in FP64; off the band:
+      round32(A_ik round32(W_k)^T);
+    * trailing tiles within the band: A_ij -= L_ik L_jk^T in FP64 (the FP32
+      panel values upcast exactly); off the band:
+      A_ij = round32(A_ij - op(L_ik) op(L_jk)^T), op = round to fmt.
+
+    Products are formed in FP64 and rounded once, so the result predicts the
+    size of the mixed-precision error of an FP32-accumulating implementation,
+    not its bits.  Returns (L padded, info) with info the 1-based index of the
+    first non-positive pivot (0 if none)."""
+    S = _f64(S)
+    N = S.shape[0]
+    T = (N + nb - 1) // nb
+    Np = T * nb
+    A = np.eye(Np)
+    A[:N, :N] = S
+    A = np.tril(A)
+
+    def blk(I, J):
+        return slice(I * nb, (I + 1) * nb), slice(J * nb, (J + 1) * nb)
+
+    def op(a):
+        return round_to(a, "fp32") if fmt == "fp32" else round_to(round_to(a, "fp32"), "bf16")
+
+    if fmt not in ("fp32", "bf16"):
+        raise ValueError(fmt)
+    for J in range(T):
+        for I in range(J + band, T):
+            A[blk(I, J)] = round_to(A[blk(I, J)], "fp32")
+    for k in range(T):
+        d = A[blk(k, k)]
+        d = np.tril(d) + np.tril(d, -1).T
+        Lkk, info = potrf(d)
+        if info:
+            return A, k * nb + info
+        A[blk(k, k)] = Lkk
+        W = np.linalg.solve(Lkk, np.eye(nb))
+        for i in range(k + 1, T):
+            if i - k < band:
+                A[blk(i, k)] = A[blk(i, k)] @ W.T
+            else:
+                A[blk(i, k)] = round_to(A[blk(i, k)] @ round_to(W, "fp32").T, "fp32")
+        for j in range(k + 1, T):
+            for i in range(j, T):
+                Li, Lj = A[blk(i, k)], A[blk(j, k)]
+                if i - j < band:
+                    A[blk(i, j)] = A[blk(i, j)] - Li @ Lj.T
+                else:
+                    A[blk(i, j)] = round_to(A[blk(i, j)] - op(Li) @ op(Lj).T, "fp32")
+    return np.tril(A), 0

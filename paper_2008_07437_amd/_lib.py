@@ -83,6 +83,7 @@ def _load():
         "mvg_last_error": (ctypes.c_char_p, []),
         "mvg_prof_enable": (c_int, [c_int]),
         "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
+        "mvg_ir_stats": (c_int, [c_int, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -289,7 +290,7 @@ def cokrige_predict(factor: Factor, x0, y0, with_mse=False, stream=None):
     return (zhat, mse) if with_mse else zhat
 
 
-PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4}
+PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4, "lowp": 5, "ir": 6}
 
 
 def mvg_prof_enable(on: bool = True):
@@ -307,3 +308,11 @@ def mvg_prof_read(kind: str) -> dict:
 def mvg_footprint(n_loc: int, opts=None) -> int:
     o = _opts(opts)
     return int(_load().mvg_footprint(int(n_loc), ctypes.byref(o)))
+
+
+def mvg_ir_stats(i: int = 0) -> dict:
+    """Iterative refinement of the last mixed-precision loglik on this thread, theta i."""
+    it, rel, conv = c_int(), c_double(), c_int()
+    _check("mvg_ir_stats", _load().mvg_ir_stats(int(i), ctypes.byref(it), ctypes.byref(rel),
+                                                 ctypes.byref(conv)))
+    return {"iters": it.value, "relres": rel.value, "converged": bool(conv.value)}

@@ -1,5 +1,6 @@
 // C ABI entry points (declared in include/mvgeo.h): argument checking, the
 // library-owned matrices and factors, and the orchestration of the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -172,6 +173,8 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
     if (d.nb != 128 && d.nb != 256 && d.nb != 512 && d.nb != 768 && d.nb != 1024) return -2;
   }
   if (d.band_tiles <= 0) d.band_tiles = 2;
+  if ((d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16) && d.band_tiles < 2)
+    return -3;
   if (d.tlr_acc <= 0.0) d.tlr_acc = 1e-7;
   if (d.tlr_max_rank <= 0) d.tlr_max_rank = 300;
   if (d.ir_max_iter <= 0) d.ir_max_iter = 20;
@@ -328,6 +331,14 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
   // matrix + inverse diagonal tiles + panel workspace + vectors
   b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * Np * d.nb);
   b += (sizeof(int64_t) + sizeof(int)) * (size_t)T * (T + 1) / 2;
+  if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16) {
+    mvg_opts f = d;
+    f.precision = MVG_FP64;
+    b += layout_bytes(n_loc, f);  // FP64 Sigma kept for the refinement
+    b += sizeof(double) * (size_t)T * (T + 1) * d.nb;  // symmetric-product partials
+    b += sizeof(double) * (size_t)4 * Np;              // refinement vectors
+    b += (size_t)(T > 1 ? T - 1 : 1) * d.nb * d.nb * (4 + (d.precision == MVG_MIXED_BF16 ? 2 : 0));
+  }
   return b;
 }
 
@@ -368,7 +379,8 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
     return MVG_ERR_ALLOC;
   }
   int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
-  if (!rc) rc = dense_potrf(A, d_info, st);
+  const bool mixed = A->precision == MVG_MIXED_FP32 || A->precision == MVG_MIXED_BF16;
+  if (!rc) rc = mixed ? mixed_potrf(A, d_info, st) : dense_potrf(A, d_info, st);
   int64_t info = 0;
   hipMemcpyAsync(&info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st);
   hipFreeAsync(d_info, st);
@@ -400,6 +412,208 @@ static int eval_one(mvg_mat *A, const double *d_z, double *d_yv, double *d_part,
   return rc;
 }
 
+struct IrStat {
+  int iters, converged;
+  double relres;
+};
+static thread_local std::vector<IrStat> g_ir;
+
+int mvg_ir_stats(int i, int *iters, double *relres, int *converged) {
+  if (i < 0 || i >= (int)g_ir.size()) return -1;
+  if (iters) *iters = g_ir[i].iters;
+  if (relres) *relres = g_ir[i].relres;
+  if (converged) *converged = g_ir[i].converged;
+  return 0;
+}
+
+// Workspace of one mixed-precision evaluation (device, one allocation).
+struct MixedWs {
+  double *zp, *x, *sx, *r, *yv, *part, *sym, *scal;  // scal: 8 doubles
+};
+
+// Mixed-precision evaluation: Sigma in FP64 (S) converted into the mixed
+// matrix A, mixed factorisation, log|Sigma| from the mixed factor, then x =
+// Sigma^-1 Z refined in FP64 against S, q = Z^T x.  out2 = {logdet, q}
+// (device), info (device), stat (host).
+static int eval_mixed(mvg_mat *S, mvg_mat *A, const double *d_z, const mvg_opts &o,
+                      const MixedWs &w, double *d_out2, int64_t *d_info, IrStat *stat,
+                      hipStream_t st) {
+  const double Nd = (double)A->N;
+  const int64_t Np = A->Np;
+  int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
+  if (!rc) rc = launch_mat_convert(S, A, st);
+  int hp = prof_begin(MVG_PROF_POTRF, st, Nd * Nd * Nd / 3.0 + Nd * Nd / 2.0, 0.0);
+  if (!rc) rc = mixed_potrf(A, d_info, st);
+  prof_end(hp, st);
+  A->factored = 1;
+  if (rc) return rc;
+  int64_t info = 0;
+  hipMemcpyAsync(&info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return MVG_ERR_LAUNCH;
+  stat->iters = 0;
+  stat->converged = 0;
+  stat->relres = NAN;
+  if (info != INT64_MAX) return 0;  // not positive definite in mixed arithmetic
+  int hs = prof_begin(MVG_PROF_SOLVE, st, Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
+  hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)((Np + 255) / 256)), dim3(256), 0, st, d_z, A->N,
+                     w.zp, Np);
+  rc = check_launch("copy_pad");
+  if (!rc) rc = hipMemcpyAsync(w.yv, w.zp, sizeof(double) * Np, hipMemcpyDeviceToDevice, st)
+                    ? MVG_ERR_LAUNCH : 0;
+  if (!rc) rc = trsv_forward(A, w.yv, st);
+  if (!rc) rc = logdet_quad(A, w.yv, w.part, d_out2, st);  // {logdet, y^T y}
+  if (!rc) rc = hipMemcpyAsync(w.x, w.yv, sizeof(double) * Np, hipMemcpyDeviceToDevice, st)
+                    ? MVG_ERR_LAUNCH : 0;
+  if (!rc) rc = trsv_backward(A, w.x, st);
+  if (!rc) rc = launch_dot(w.zp, w.zp, Np, w.part, w.scal, st);  // ||Z||^2
+  prof_end(hs, st);
+  double zn2 = 0.0;
+  if (!rc) {
+    hipMemcpyAsync(&zn2, w.scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) rc = MVG_ERR_LAUNCH;
+  }
+  const double zn = std::sqrt(zn2);
+  double prev = INFINITY;
+  for (int it = 0; !rc; ++it) {
+    int hi = prof_begin(MVG_PROF_IR, st, 2.0 * Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
+    rc = launch_symv(S, w.x, w.sx, w.sym, st);
+    if (!rc) rc = launch_axpy_norm(w.zp, w.sx, w.r, Np, w.part, w.scal + 1, st);
+    prof_end(hi, st);
+    double rn2 = 0.0;
+    if (!rc) {
+      hipMemcpyAsync(&rn2, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+      if (hipStreamSynchronize(st) != hipSuccess) rc = MVG_ERR_LAUNCH;
+    }
+    if (rc) break;
+    const double rel = zn > 0.0 ? std::sqrt(rn2) / zn : 0.0;
+    stat->relres = rel;
+    if (rel <= o.ir_tol) {
+      stat->converged = 1;
+      break;
+    }
+    if (it >= o.ir_max_iter || !(rel < 0.9 * prev)) break;  // budget spent or stagnating
+    prev = rel;
+    int hc = prof_begin(MVG_PROF_IR, st, 2.0 * Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
+    rc = trsv_forward(A, w.r, st);
+    if (!rc) rc = trsv_backward(A, w.r, st);
+    if (!rc) rc = launch_axpy(w.x, w.r, Np, st);
+    prof_end(hc, st);
+    stat->iters = it + 1;
+  }
+  if (!rc) rc = launch_dot(w.zp, w.x, Np, w.part, d_out2 + 1, st);  // q = Z^T x
+  return rc;
+}
+
+static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                        const mvg_theta *th, int n_theta, const mvg_opts &d, double *h_loglik,
+                        double *h_logdet, double *h_quad, int64_t *h_status, mvg_factor **keep,
+                        hipStream_t st) {
+  mvg_opts d64 = d;
+  d64.precision = MVG_FP64;
+  mvg_mat *S = nullptr, *A = nullptr;
+  int rc = mat_create(n_loc, d64, &th[0], d_x, d_y, st, &S);
+  if (rc) return rc;
+  rc = mat_create(n_loc, d, &th[0], d_x, d_y, st, &A);
+  if (rc) {
+    mat_free(S);
+    return rc;
+  }
+  const int64_t Np = A->Np;
+  const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
+  const int nred = std::max(reduce_chunks(Np), (int)((A->N + 4095) / 4096));
+  // zp x sx r yv (Np each) | part (2 nred) | sym (2 nt nb) | scal 8 | out2 | info
+  const size_t ws_n = 5 * (size_t)Np + 2 * nred + 2 * (size_t)nt * A->nb + 8 + 2 * n_theta + n_theta;
+  double *ws = nullptr;
+  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+    hipGetLastError();
+    mat_free(S);
+    mat_free(A);
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  MixedWs w;
+  w.zp = ws;
+  w.x = ws + Np;
+  w.sx = ws + 2 * Np;
+  w.r = ws + 3 * Np;
+  w.yv = ws + 4 * Np;
+  w.part = ws + 5 * Np;
+  w.sym = w.part + 2 * nred;
+  w.scal = w.sym + 2 * nt * A->nb;
+  double *d_out2 = w.scal + 8;
+  int64_t *d_info = reinterpret_cast<int64_t *>(d_out2 + 2 * n_theta);
+  g_ir.assign(n_theta, IrStat{0, 0, NAN});
+  for (int i = 0; i < n_theta && !rc; ++i) {
+    if (i > 0) {
+      S->theta = A->theta = th[i];
+      matern_setup(&th[i], &S->margs);
+      A->margs = S->margs;
+    }
+    int hg = prof_begin(MVG_PROF_GEN, st, 0.0, 8.0 * (double)S->N * (S->N + 1) / 2);
+    rc = mat_generate(S, st);
+    prof_end(hg, st);
+    if (!rc) rc = launch_quad_table(A->margs, A->d_qtab, st);  // for cokriging on A
+    if (!rc) rc = eval_mixed(S, A, d_z, d, w, d_out2 + 2 * i, d_info + i, &g_ir[i], st);
+  }
+  std::vector<double> out2(2 * n_theta);
+  std::vector<int64_t> info(n_theta);
+  hipMemcpyAsync(out2.data(), d_out2, sizeof(double) * 2 * n_theta, hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(info.data(), d_info, sizeof(int64_t) * n_theta, hipMemcpyDeviceToHost, st);
+  mvg_factor *F = nullptr;
+  if (!rc && keep) {
+    F = new mvg_factor();
+    F->A = A;
+    if (hipMalloc((void **)&F->d_w, sizeof(double) * Np * 2) != hipSuccess) {
+      hipGetLastError();
+      rc = MVG_ERR_ALLOC;
+      set_error("factor allocation failed");
+    } else {
+      F->d_y = F->d_w + Np;
+      hipMemcpyAsync(F->d_y, w.yv, sizeof(double) * Np, hipMemcpyDeviceToDevice, st);
+      hipMemcpyAsync(F->d_w, w.x, sizeof(double) * Np, hipMemcpyDeviceToDevice, st);
+    }
+  }
+  hipFreeAsync(ws, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    set_error("stream synchronisation failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = MVG_ERR_LAUNCH;
+  }
+  mat_free(S);
+  if (rc) {
+    if (F) {
+      hipFree(F->d_w);
+      delete F;
+    }
+    mat_free(A);
+    return rc;
+  }
+  const double two_pi_term = (double)n_loc * std::log(2.0 * M_PI);
+  for (int i = 0; i < n_theta; ++i) {
+    const int64_t inf = info[i] == INT64_MAX ? 0 : info[i];
+    if (h_status) h_status[i] = inf;
+    if (inf) {
+      h_loglik[i] = -INFINITY;
+      if (h_logdet) h_logdet[i] = NAN;
+      if (h_quad) h_quad[i] = NAN;
+    } else {
+      h_loglik[i] = -two_pi_term - 0.5 * out2[2 * i] - 0.5 * out2[2 * i + 1];
+      if (h_logdet) h_logdet[i] = out2[2 * i];
+      if (h_quad) h_quad[i] = out2[2 * i + 1];
+    }
+  }
+  if (F && info[0] == INT64_MAX) {
+    *keep = F;
+  } else {
+    if (F) {
+      hipFree(F->d_w);
+      delete F;
+    }
+    if (keep) *keep = nullptr;
+    mat_free(A);
+  }
+  return 0;
+}
+
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o, double *h_loglik,
            double *h_logdet, double *h_quad, int64_t *h_status, mvg_factor **keep,
@@ -418,11 +632,14 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
     MaternArgs tmp;
     if (matern_setup(&th[i], &tmp)) return -5;
   }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16)
+    return loglik_mixed(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
+                        h_status, keep, st);
   if (d.precision != MVG_FP64) {
     set_error("loglik: precision %d not available in this build", d.precision);
     return -7;
   }
-  hipStream_t st = (hipStream_t)hip_stream;
   mvg_mat *A = nullptr;
   int rc = mat_create(n_loc, d, &th[0], d_x, d_y, st, &A);
   if (rc) return rc;
@@ -571,7 +788,7 @@ int morton_order(const double *d_x, const double *d_y, int64_t n_loc, int64_t *d
 }
 
 int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_stream) {
-  if (!L || !L->factored || L->precision == MVG_TLR) return -1;
+  if (!L || !L->factored || L->precision != MVG_FP64) return -1;
   if (!d_eps) return -2;
   if (!d_z || d_z == d_eps) return -3;
   return launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream);

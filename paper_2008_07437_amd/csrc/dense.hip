@@ -44,6 +44,12 @@ int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st) {
 __device__ __forceinline__ double *tile_ptr(TileMap M, int I, int J) {
   return reinterpret_cast<double *>(M.base + M.off[tidx(I, J, M.T)]);
 }
+__device__ __forceinline__ float *tile_ptr_f32(TileMap M, int I, int J) {
+  return reinterpret_cast<float *>(M.base + M.off[tidx(I, J, M.T)]);
+}
+__device__ __forceinline__ bool tile_is_f32(TileMap M, int I, int J) {
+  return M.kind && M.kind[tidx(I, J, M.T)] == TK_F32;
+}
 
 // ------------------------------------------------- trailing update (GEMM)
 //
@@ -76,7 +82,6 @@ struct TrailBlock {
   int nk;  // K slices of this block
 };
 
-enum { TRAIL_UPDATE = 0, TRAIL_TRSM = 1 };
 
 // Logical block lid of the trailing update of step k over columns j >= jlo:
 // tile (i, j) and 128 x 128 sub-block (sr, sc); false for the strict upper
@@ -97,6 +102,23 @@ __device__ __forceinline__ bool trail_decode(const TileMap &M, int k, int jlo, i
     t.A = P + q * (int64_t)nb * nb + sr * IB;
     t.B = W + sc * IB;
     t.nk = (sc + 1) * (IB / TKB);
+    return true;
+  }
+  if (MODE == TRAIL_BAND) {
+    // band targets (mixed precision): tiles (i, j), j > k, j <= i < j + band,
+    // band passed as jlo; operands from P = the panel of step k upcast to FP64
+    const int band = jlo;
+    int j = k + 1;
+    while (q >= min(band, M.T - j)) {
+      q -= min(band, M.T - j);
+      ++j;
+    }
+    const int i = j + (int)q;
+    if (i == j && sr < sc) return false;
+    t.C = tile_ptr(M, i, j) + (int64_t)sc * IB * nb + sr * IB;
+    t.A = P + (int64_t)(i - k - 1) * nb * nb + sr * IB;
+    t.B = P + (int64_t)(j - k - 1) * nb * nb + sc * IB;
+    t.nk = nb / TKB;
     return true;
   }
   int j = jlo;
@@ -186,7 +208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          acc[ti][tj][e] = (MODE == TRAIL_UPDATE) ? (double)cb[tj][ti * 16 + 4 * e] : 0.0;
+          acc[ti][tj][e] = (MODE != TRAIL_TRSM) ? (double)cb[tj][ti * 16 + 4 * e] : 0.0;
     const bool have_next = ln < lid1;
     const int nk = cur.nk;
     for (int kb0 = 0; kb0 < nk; kb0 += TS) {
@@ -219,7 +241,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           double af[4], bf[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            af[t] = (MODE == TRAIL_UPDATE) ? -a[(ks + lk) * IB + t * 16] : a[(ks + lk) * IB + t * 16];
+            af[t] = (MODE != TRAIL_TRSM) ? -a[(ks + lk) * IB + t * 16] : a[(ks + lk) * IB + t * 16];
             bf[t] = bb[(ks + lk) * IB + t * 16];
           }
 #pragma unroll
@@ -583,16 +605,23 @@ __global__ __launch_bounds__(256) void k_syrk64(TileMap M, int k, int j) {
   (void)s;
 }
 
-struct PivotTol {
-  double t0, t1;
-  int64_t N;
-};
+// SYRK of the next diagonal tile (k+1, k+1) by step k on stream st.
+int launch_syrk_next(const mvg_mat *A, int k, hipStream_t st) {
+  const TileMap M = A->map();
+  const int sb = M.nb / PB;
+  const double nj = (double)std::min<int64_t>(M.nb, A->N - (int64_t)(k + 1) * M.nb);
+  const double nk = (double)std::min<int64_t>(M.nb, A->N - (int64_t)k * M.nb);
+  int h = prof_begin(MVG_PROF_TRAILING, st, nj * (nj + 1.0) * nk, 0.0);
+  hipLaunchKernelGGL(k_syrk64, dim3(sb * (sb + 1) / 2), dim3(256), 0, st, M, k, k + 1);
+  prof_end(h, st);
+  return check_launch("syrk64");
+}
 
 // Factor the diagonal tile (k, k) in place and fill W_k = L_kk^-1: 64-wide
 // inner blocks (register Cholesky + inverse of the block, in-tile TRSM and
 // update), then the off-diagonal blocks of W_k by block distance.
-static int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
-                       hipStream_t st) {
+int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
+                hipStream_t st) {
   const int s = M.nb / PB;
   hipLaunchKernelGGL(k_zero_upper_blocks, dim3(64), dim3(256), 0, st, M.nb, k, winv);
   if (int rc = check_launch("zero_upper_blocks")) return rc;
@@ -668,8 +697,8 @@ static int lookahead() {
 }
 
 template <int MODE>
-static int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t nwg,
-                        const double *P, const double *W, hipStream_t st) {
+int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t nwg, const double *P,
+                 const double *W, hipStream_t st) {
   const int64_t work = nwg - lid0;
   if (work <= 0) return 0;
   int64_t G = gemm_persist() ? std::min<int64_t>(work, 2 * GEMM_CUS - gemm_reserve()) : work;
@@ -689,6 +718,13 @@ static int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t 
   }
   return check_launch("update_trailing");
 }
+
+template int launch_trail<TRAIL_UPDATE>(const TileMap &, int, int, int64_t, int64_t, const double *,
+                                        const double *, hipStream_t);
+template int launch_trail<TRAIL_TRSM>(const TileMap &, int, int, int64_t, int64_t, const double *,
+                                      const double *, hipStream_t);
+template int launch_trail<TRAIL_BAND>(const TileMap &, int, int, int64_t, int64_t, const double *,
+                                      const double *, hipStream_t);
 
 // Trailing update of step k: A_ij -= L_ik L_jk^T for k < j <= i, optionally
 // without the diagonal tile (k+1, k+1) (first = 0: that tile is left to the
@@ -764,15 +800,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
     if (rc) break;
     if (k + 1 < T) {
       hipStreamWaitEvent(side, evS, 0);
-      {  // SYRK of tile (k+1, k+1) by step k
-        const int sb = M.nb / PB;
-        const double nj = (double)std::min<int64_t>(M.nb, A->N - (int64_t)(k + 1) * M.nb);
-        const double nk = (double)std::min<int64_t>(M.nb, A->N - (int64_t)k * M.nb);
-        int h = prof_begin(MVG_PROF_TRAILING, side, nj * (nj + 1.0) * nk, 0.0);
-        hipLaunchKernelGGL(k_syrk64, dim3(sb * (sb + 1) / 2), dim3(256), 0, side, M, k, k + 1);
-        prof_end(h, side);
-        rc = check_launch("syrk64");
-      }
+      rc = launch_syrk_next(A, k, side);  // SYRK of tile (k+1, k+1) by step k
       if (!rc) rc = diag_factor(M, k + 1, A->d_winv, d_info, pt, side);
       hipEventRecord(evD, side);
       if (!rc) rc = trailing(M, A->N, k, true, false, st);  // the rest of step k
@@ -831,12 +859,20 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__re
   const int r = (blockIdx.x % chunks) * 64 + lane;
   for (int c = tid; c < nb; c += 256) y[c] = Vc[(int64_t)k * nb + c];
   __syncthreads();
-  const double *L = tile_ptr(M, i, k) + r;
   const int q = nb / 4;
   double s0 = 0.0, s1 = 0.0;
-  for (int c = wave * q; c < wave * q + q; c += 2) {
-    s0 += L[(int64_t)c * nb] * y[c];
-    s1 += L[(int64_t)(c + 1) * nb] * y[c + 1];
+  if (tile_is_f32(M, i, k)) {  // mixed precision: off-band tiles in FP32
+    const float *L = tile_ptr_f32(M, i, k) + r;
+    for (int c = wave * q; c < wave * q + q; c += 2) {
+      s0 += (double)L[(int64_t)c * nb] * y[c];
+      s1 += (double)L[(int64_t)(c + 1) * nb] * y[c + 1];
+    }
+  } else {
+    const double *L = tile_ptr(M, i, k) + r;
+    for (int c = wave * q; c < wave * q + q; c += 2) {
+      s0 += L[(int64_t)c * nb] * y[c];
+      s1 += L[(int64_t)(c + 1) * nb] * y[c + 1];
+    }
   }
   part[wave][lane] = s0 + s1;
   __syncthreads();
@@ -878,11 +914,16 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__re
   const int c0 = (blockIdx.x % cb) * 64;
   for (int r = tid; r < nb; r += 256) w[r] = Vc[(int64_t)k * nb + r];
   __syncthreads();
-  const double *L = tile_ptr(M, k, j);
+  const bool f32 = tile_is_f32(M, k, j);
   for (int c = c0 + wave; c < c0 + 64; c += 4) {
-    const double *col = L + (int64_t)c * nb;
     double s = 0.0;
-    for (int r = lane; r < nb; r += 64) s += col[r] * w[r];
+    if (f32) {
+      const float *col = tile_ptr_f32(M, k, j) + (int64_t)c * nb;
+      for (int r = lane; r < nb; r += 64) s += (double)col[r] * w[r];
+    } else {
+      const double *col = tile_ptr(M, k, j) + (int64_t)c * nb;
+      for (int r = lane; r < nb; r += 64) s += col[r] * w[r];
+    }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) Vc[(int64_t)j * nb + c] -= s;
   }

@@ -120,7 +120,29 @@ int launch_cokrige_c0(const MaternArgs &P, const double *d_qtab, const double *d
                       const double *d_y0, int64_t m, double *d_c0, hipStream_t st);
 
 // dense FP64 Cholesky pieces
+struct PivotTol {
+  double t0, t1;
+  int64_t N;
+};
+enum { TRAIL_UPDATE = 0, TRAIL_TRSM = 1, TRAIL_BAND = 2 };
+template <int MODE>
+int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t nwg, const double *P,
+                 const double *W, hipStream_t st);
+int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const PivotTol &pt,
+                hipStream_t st);
+int launch_syrk_next(const mvg_mat *A, int k, hipStream_t st);
 int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st);
+int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st);
+int launch_symv(const mvg_mat *A, const double *d_x, double *d_y, double *d_part, hipStream_t st);
+// r = z - sx and out = ||r||^2; d_part holds reduce_chunks(n) doubles
+int launch_axpy_norm(const double *d_z, const double *d_sx, double *d_r, int64_t n, double *d_part,
+                     double *d_out, hipStream_t st);
+int launch_dot(const double *d_a, const double *d_b, int64_t n, double *d_part, double *d_out,
+               hipStream_t st);
+int launch_axpy(double *d_x, const double *d_d, int64_t n, hipStream_t st);  // x += d
+int reduce_chunks(int64_t n);
+// FP64 matrix -> mixed-layout matrix of the same shape
+int launch_mat_convert(const mvg_mat *S, mvg_mat *D, hipStream_t st);
 int launch_fill_i64(int64_t *d, int64_t v, int64_t n, hipStream_t st);
 int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st);
 int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st);     // v <- L^-1 v

@@ -339,3 +339,44 @@ def test_round_to_formats(orc):
     assert abs(b[3] - 3.140625) < 1e-12
     f = orc.round_to(v, "fp32")
     assert f[3] == float(np.float32(3.14159265358979))
+
+
+# ------------------------------------------- mixed-precision emulation (not in the paper)
+
+def _small_cov(orc, n, a, seed=2):
+    th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
+    x, y = synthetic.jittered_grid(n, seed)
+    p = orc.morton_order(x, y)
+    return orc.cov_dense(x[p], y[p], th)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_mixed_emulation_full_band_is_exact_cholesky(orc, fmt):
+    """A band covering every tile leaves no low-precision tile: LAPACK's factor."""
+    S = _small_cov(orc, 90, 0.1)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 10, fmt)
+    assert info == 0
+    Np = L.shape[0]
+    ref = np.eye(Np)
+    ref[:180, :180] = scipy.linalg.cholesky(S, lower=True)
+    np.testing.assert_allclose(L, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("fmt,bound", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_mixed_emulation_rounds_off_band_and_stays_close(orc, fmt, bound):
+    """Off-band factor tiles are FP32 values; the factor reproduces S within
+    the precision's rounding scale; band tiles carry no FP32 rounding."""
+    S = _small_cov(orc, 90, 0.03)
+    nb = 32
+    L, info = orc.mixed_cholesky_emulated(S, nb, 2, fmt)
+    assert info == 0
+    T = L.shape[0] // nb
+    for J in range(T):
+        for I in range(J + 2, T):
+            t = L[I * nb:(I + 1) * nb, J * nb:(J + 1) * nb]
+            assert np.array_equal(orc.round_to(t, "fp32"), t)
+    R = (L @ L.T)[:180, :180]
+    assert np.max(np.abs(R - S)) <= bound
+    assert np.max(np.abs(R - S)) > 0.0
+    ld = 2 * np.sum(np.log(np.diag(L)[:180]))
+    assert abs(ld - np.linalg.slogdet(S)[1]) <= 50 * bound * 180
