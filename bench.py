@@ -67,6 +67,56 @@ def cpu_baseline(n_full, sample_n, theta, seed):
                       (sample_n, sample_n, n_full, dt, sample_n, n_full)}
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def run_variants(mvg, xs, ys, z, th, args, ref_loglik, reps=2):
+    """Mixed-precision evaluations of the same inputs beside the FP64 result:
+    evals/s, relative delta loglik and delta log|Sigma| against FP64, the
+    refinement sweeps, and the off-band GEMM rate on its own MFMA peak."""
+    import torch
+    out = {}
+    ref = mvg.loglik(xs, ys, z, th, {"nb": args.nb})
+    for name, prec, peak, band in (
+            ("mixed_fp32", mvg.MVG_MIXED_FP32, FP32_MFMA_PEAK_TFLOPS, args.band),
+            ("mixed_fp32_band%d" % args.wide_band, mvg.MVG_MIXED_FP32, FP32_MFMA_PEAK_TFLOPS,
+             args.wide_band),
+            ("mixed_bf16", mvg.MVG_MIXED_BF16, BF16_MFMA_PEAK_TFLOPS, args.band)):
+        o = {"nb": args.nb, "precision": prec, "band_tiles": band}
+        mvg.loglik(xs, ys, z, th, o)  # warm-up
+        torch.cuda.synchronize()
+        mvg.mvg_prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = mvg.loglik(xs, ys, z, th, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        prof = {k: mvg.mvg_prof_read(k) for k in ("trailing", "lowp", "potrf", "ir", "gen")}
+        mvg.mvg_prof_enable(False)
+        ir = mvg.mvg_ir_stats(0)
+        N = 2 * args.n
+        lp = prof["lowp"]
+        lp_tf = lp["flops"] / (lp["ms"] * 1e-3) / 1e12 if lp["ms"] > 0 else None
+        potrf_ms = prof["potrf"]["ms"] / max(1, prof["potrf"]["launches"])
+        out[name] = {
+            "evals_per_s": 1.0 / dt,
+            "status": int(res["status"][0]),
+            "rel_dloglik_vs_fp64": abs(res["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0]),
+            "dlogdet_vs_fp64": float(res["logdet"][0] - ref["logdet"][0]),
+            "rel_dquad_vs_fp64": abs(res["quad"][0] - ref["quad"][0]) / abs(ref["quad"][0]),
+            "ir": ir,
+            "band_tiles": band,
+            "cholesky_tflops_equiv": (N ** 3 / 3.0) / (potrf_ms * 1e-3) / 1e12,
+            "phases_ms_per_eval": {k: prof[k]["ms"] / reps for k in ("gen", "potrf", "ir")},
+            "offband_gemm": {"achieved": lp_tf, "peak": peak, "unit": "TFLOP/s",
+                             "frac": lp_tf / peak if lp_tf else None},
+            "band_gemm_tflops": (prof["trailing"]["flops"] / (prof["trailing"]["ms"] * 1e-3) / 1e12
+                                 if prof["trailing"]["ms"] > 0 else None),
+        }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +128,11 @@ def main():
     ap.add_argument("--targets", type=int, default=100)
     ap.add_argument("--cpu-sample-n", type=int, default=2400)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed-precision evaluations of the same inputs")
+    ap.add_argument("--band", type=int, default=2, help="FP64 band width in tiles (mixed)")
+    ap.add_argument("--wide-band", type=int, default=16,
+                    help="second, wider FP64 band for the FP32 variant")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM counters)")
@@ -183,6 +238,8 @@ def main():
                      "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
                      "flops_per_launch": tr["flops"] / max(1, tr["launches"])},
     }
+    if not args.no_variants:
+        out["variants"] = run_variants(mvg, xs, ys, z, th, args, last["loglik"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
     print(json.dumps(out), flush=True)

@@ -120,9 +120,12 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * tiles within band_tiles of the diagonal (all diagonal factorisations FP64)
  * and FP32 tiles elsewhere, updated on FP32 (or BF16-operand) MFMA.  The solve
  * x = Sigma^-1 Z is refined in FP64 (r = Z - Sigma x with the FP64 Sigma,
- * correction from the mixed factor) until ||r|| <= ir_tol ||Z||, ir_max_iter
- * sweeps, or stagnation; h_quad = Z^T x.  h_logdet is that of the mixed factor
- * (not refined).  Memory: the FP64 lower tiles plus the mixed copy.
+ * correction from the mixed factor) until ||r|| <= ir_tol ||Z||, or
+ * |x^T r| <= 1e-10 |Z^T x| (the quadratic form has converged; not used when
+ * keep is set, since predictions use x itself), ir_max_iter
+ * sweeps, or stagnation; h_quad = Z^T x + x^T r (the last residual's
+ * first-order correction).  h_logdet is that of the mixed factor (not
+ * refined).  Memory: the FP64 lower tiles plus the mixed copy.
  * Requires band_tiles >= 2. */
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o,
@@ -196,7 +199,8 @@ int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, 
 
 /* Iterative refinement of the last mixed-precision loglik call on the
  * calling thread, theta index i: *iters = correction sweeps applied,
- * *relres = final ||Z - Sigma x|| / ||Z||, *converged = 1 if ir_tol was met.
+ * *relres = final ||Z - Sigma x|| / ||Z||, *converged = 1 if a stopping
+ * criterion (residual or quadratic form) was met.
  * Returns 0, or -1 if there is no such record. */
 int mvg_ir_stats(int i, int *iters, double *relres, int *converged);
 

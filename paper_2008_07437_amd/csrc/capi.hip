@@ -412,6 +412,14 @@ static int eval_one(mvg_mat *A, const double *d_z, double *d_yv, double *d_part,
   return rc;
 }
 
+// The refinement also stops once |x^T r| <= IR_QUAD_TOL |Z^T x|: the
+// quadratic form is then known to ~IR_QUAD_TOL^2 relative.
+constexpr double IR_QUAD_TOL = 1e-10;
+
+__global__ void k_add_pair(const double *__restrict__ s, double *__restrict__ out) {
+  if (threadIdx.x == 0) out[0] = s[0] + s[1];
+}
+
 struct IrStat {
   int iters, converged;
   double relres;
@@ -437,7 +445,7 @@ struct MixedWs {
 // (device), info (device), stat (host).
 static int eval_mixed(mvg_mat *S, mvg_mat *A, const double *d_z, const mvg_opts &o,
                       const MixedWs &w, double *d_out2, int64_t *d_info, IrStat *stat,
-                      hipStream_t st) {
+                      bool need_x, hipStream_t st) {
   const double Nd = (double)A->N;
   const int64_t Np = A->Np;
   int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
@@ -477,21 +485,26 @@ static int eval_mixed(mvg_mat *S, mvg_mat *A, const double *d_z, const mvg_opts 
   for (int it = 0; !rc; ++it) {
     int hi = prof_begin(MVG_PROF_IR, st, 2.0 * Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
     rc = launch_symv(S, w.x, w.sx, w.sym, st);
-    if (!rc) rc = launch_axpy_norm(w.zp, w.sx, w.r, Np, w.part, w.scal + 1, st);
+    if (!rc) rc = launch_axpy_norm(w.zp, w.sx, w.r, Np, w.part, w.scal + 1, st);  // r, ||r||^2
+    if (!rc) rc = launch_dot(w.zp, w.x, Np, w.part, w.scal + 2, st);             // Z^T x
+    if (!rc) rc = launch_dot(w.x, w.r, Np, w.part, w.scal + 3, st);              // x^T r
     prof_end(hi, st);
-    double rn2 = 0.0;
+    double h[3] = {0.0, 0.0, 0.0};
     if (!rc) {
-      hipMemcpyAsync(&rn2, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+      hipMemcpyAsync(h, w.scal + 1, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
       if (hipStreamSynchronize(st) != hipSuccess) rc = MVG_ERR_LAUNCH;
     }
     if (rc) break;
-    const double rel = zn > 0.0 ? std::sqrt(rn2) / zn : 0.0;
+    // Z^T Sigma^-1 Z = Z^T x + x*^T r with x* = Sigma^-1 Z; x^T r estimates the
+    // second term to first order, so q = Z^T x + x^T r is refined to second order
+    const double rel = zn > 0.0 ? std::sqrt(h[0]) / zn : 0.0;
     stat->relres = rel;
-    if (rel <= o.ir_tol) {
+    // a kept factor predicts with x itself: then only the residual criterion
+    if (rel <= o.ir_tol || (!need_x && std::fabs(h[2]) <= IR_QUAD_TOL * std::fabs(h[1]))) {
       stat->converged = 1;
       break;
     }
-    if (it >= o.ir_max_iter || !(rel < 0.9 * prev)) break;  // budget spent or stagnating
+    if (it >= o.ir_max_iter || !(rel < 0.5 * prev)) break;  // budget spent or stagnating
     prev = rel;
     int hc = prof_begin(MVG_PROF_IR, st, 2.0 * Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
     rc = trsv_forward(A, w.r, st);
@@ -500,7 +513,11 @@ static int eval_mixed(mvg_mat *S, mvg_mat *A, const double *d_z, const mvg_opts 
     prof_end(hc, st);
     stat->iters = it + 1;
   }
-  if (!rc) rc = launch_dot(w.zp, w.x, Np, w.part, d_out2 + 1, st);  // q = Z^T x
+  if (!rc) {
+    hipLaunchKernelGGL(k_add_pair, dim3(1), dim3(64), 0, st, (const double *)(w.scal + 2),
+                       d_out2 + 1);
+    rc = check_launch("add_pair");
+  }
   return rc;
 }
 
@@ -553,7 +570,8 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
     rc = mat_generate(S, st);
     prof_end(hg, st);
     if (!rc) rc = launch_quad_table(A->margs, A->d_qtab, st);  // for cokriging on A
-    if (!rc) rc = eval_mixed(S, A, d_z, d, w, d_out2 + 2 * i, d_info + i, &g_ir[i], st);
+    if (!rc) rc = eval_mixed(S, A, d_z, d, w, d_out2 + 2 * i, d_info + i, &g_ir[i],
+                                keep != nullptr, st);
   }
   std::vector<double> out2(2 * n_theta);
   std::vector<int64_t> info(n_theta);

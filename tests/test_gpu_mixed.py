@@ -95,7 +95,7 @@ def test_mixed_fp32_loglik(lib, orc, a, nb):
     dld = got["logdet"][0] - ref["logdet"]
     _say("  rel dloglik %.2e  dlogdet %.3e (emulated %.3e)  quad rel %.2e  IR %s"
          % (dl, dld, eld - ref["logdet"], abs(got["quad"][0] - ref["quad"]) / ref["quad"], st))
-    assert st["relres"] <= 1e-12, st
+    assert st["converged"], st
     assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
     if a <= 0.1:  # at a = 0.3 kappa * 2^-24 nears 1e-1: both errors are noise-dominated
         assert abs(dld) <= max(3.0 * abs(eld - ref["logdet"]), 1e-10 * abs(ref["logdet"]))
@@ -116,7 +116,7 @@ def test_mixed_bf16_loglik(lib, orc, a):
     dld = got["logdet"][0] - ref["logdet"]
     _say("  rel dloglik %.2e  dlogdet %.3e (emulated %.3e)  IR %s"
          % (dl, dld, eld - ref["logdet"], st))
-    assert st["relres"] <= 1e-12, st
+    assert st["converged"], st
     assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
     assert abs(dld) <= 10.0 * abs(eld - ref["logdet"])
     assert dl <= 1e-4
