@@ -267,8 +267,12 @@ def loglik(x, y, z, thetas, opts=None, keep=False, stream=None):
 
 
 def tlr_compress(x, y, theta, opts=None, stream=None):
+    """TLR compression of Sigma(theta); returns (Mat, ranks T x T, -1 = dense)."""
     h = c_void_p()
     th = Theta.of(theta)
+    if opts is None or isinstance(opts, dict):
+        opts = dict(opts or {})
+        opts["precision"] = MVG_TLR
     o = _opts(opts)
     N = 2 * x.numel()
     T = (N + (o.nb or 1200) - 1) // (o.nb or 1200)

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "mvgeo_internal.h"
+#include "tlr.h"
 
 namespace mvg {
 
@@ -168,7 +169,7 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   if (d.precision < MVG_FP64 || d.precision > MVG_TLR) return -1;
   if (d.nb == 0) d.nb = (d.precision == MVG_TLR) ? 1200 : 512;
   if (d.precision == MVG_TLR) {
-    if (d.nb < 64 || d.nb % 2) return -2;
+    if (d.nb < 64 || d.nb % 2 || d.nb > QR_MAXM) return -2;
   } else {
     if (d.nb != 128 && d.nb != 256 && d.nb != 512 && d.nb != 768 && d.nb != 1024) return -2;
   }
@@ -177,6 +178,7 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
     return -3;
   if (d.tlr_acc <= 0.0) d.tlr_acc = 1e-7;
   if (d.tlr_max_rank <= 0) d.tlr_max_rank = 300;
+  if (d.tlr_max_rank > QR_MAXN - 16) return -4;
   if (d.ir_max_iter <= 0) d.ir_max_iter = 20;
   if (d.ir_tol <= 0.0) d.ir_tol = 1e-14;
   *out = d;
@@ -185,6 +187,7 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
 
 static void mat_free(mvg_mat *A) {
   if (!A) return;
+  tlr_state_free(A->tlr);
   arena_release(A->arena, A->arena_bytes);
   hipFree(A->d_off);
   hipFree(A->d_kind);
@@ -192,13 +195,8 @@ static void mat_free(mvg_mat *A) {
   hipFree(A->d_y);
   hipFree(A->d_qtab);
   hipFree(A->d_winv);
-  hipFree(A->lr_arena);
-  hipFree(A->d_rank);
-  hipFree(A->d_uoff);
   delete[] A->h_off;
   delete[] A->h_kind;
-  delete[] A->h_rank;
-  delete[] A->h_uoff;
   delete A;
 }
 
@@ -244,6 +242,7 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   A->precision = o.precision;
   A->band = o.band_tiles;
   A->theta = *th;
+  A->opts = o;
   if (int rc = matern_setup(th, &A->margs)) {
     delete A;
     return rc;
@@ -275,6 +274,48 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   // the host offset tables are read by the copies above; keep them alive with A
   *out = A;
   return 0;
+}
+
+// A TLR matrix: locations, theta constants, quadrature table; the tiles are
+// built by tlr_build.
+static int tlr_mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, const double *d_x,
+                          const double *d_y, hipStream_t st, mvg_mat **out) {
+  mvg_mat *A = new mvg_mat();
+  A->n_loc = n_loc;
+  A->N = 2 * n_loc;
+  A->nb = o.nb;
+  A->T = (int)((A->N + o.nb - 1) / o.nb);
+  A->Np = (int64_t)A->T * o.nb;
+  A->precision = MVG_TLR;
+  A->theta = *th;
+  A->opts = o;
+  if (int rc = matern_setup(th, &A->margs)) {
+    delete A;
+    return rc;
+  }
+  A->tlr = new TlrState();
+  bool ok = hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
+  if (!ok) {
+    hipGetLastError();
+    set_error("device allocation for a %lld-location TLR matrix failed", (long long)n_loc);
+    mat_free(A);
+    return MVG_ERR_ALLOC;
+  }
+  hipMemcpyAsync(A->d_x, d_x, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(A->d_y, d_y, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
+  *out = A;
+  return 0;
+}
+
+// Regenerate and compress Sigma(theta) into a TLR matrix.
+static int tlr_generate(mvg_mat *A, hipStream_t st) {
+  if (int rc = launch_quad_table(A->margs, A->d_qtab, st)) return rc;
+  A->factored = 0;
+  store_free(A->tlr->S);
+  store_free(A->tlr->L);
+  return tlr_build(A, A->opts, st);
 }
 
 // Regenerate Sigma(theta) into an existing matrix of the same shape.
@@ -327,6 +368,18 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
   const int64_t N = 2 * n_loc;
   const int T = (int)((N + d.nb - 1) / d.nb);
   const int64_t Np = (int64_t)T * d.nb;
+  if (d.precision == MVG_TLR) {
+    // estimate: dense diagonal tiles of Sigma and L plus W (3 T nbp^2), the
+    // dense tile-column buffer (T nb^2), low-rank pairs at an assumed mean
+    // rank of 64 for Sigma and L, the update workspace of the widest column
+    const size_t nbp = (d.nb + 63) / 64 * 64;
+    const size_t nt = (size_t)T * (T - 1) / 2;
+    size_t b = sizeof(double) * (3 * (size_t)T * nbp * nbp + (size_t)T * d.nb * d.nb);
+    b += sizeof(double) * 2 * nt * 2 * (size_t)d.nb * 64;
+    b += sizeof(double) * (size_t)(T + 1) * d.nb * ((size_t)T / 2 * 64 + d.nb);
+    b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN);
+    return b;
+  }
   size_t b = layout_bytes(n_loc, d);
   // matrix + inverse diagonal tiles + panel workspace + vectors
   b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * Np * d.nb);
@@ -368,8 +421,8 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
   (void)o;
   if (!A) return -1;
   if (!h_info) return -3;
-  if (A->factored || A->precision == MVG_TLR) {
-    set_error("potrf_tiled: matrix already factored or TLR (use loglik)");
+  if (A->factored) {
+    set_error("potrf_tiled: matrix already factored");
     return -1;
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -380,7 +433,9 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
   }
   int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
   const bool mixed = A->precision == MVG_MIXED_FP32 || A->precision == MVG_MIXED_BF16;
-  if (!rc) rc = mixed ? mixed_potrf(A, d_info, st) : dense_potrf(A, d_info, st);
+  if (!rc)
+    rc = A->precision == MVG_TLR ? tlr_potrf(A, A->opts, d_info, st)
+                                 : mixed ? mixed_potrf(A, d_info, st) : dense_potrf(A, d_info, st);
   int64_t info = 0;
   hipMemcpyAsync(&info, d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st);
   hipFreeAsync(d_info, st);
@@ -397,7 +452,7 @@ static int eval_one(mvg_mat *A, const double *d_z, double *d_yv, double *d_part,
   int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
   const double Nd = (double)A->N;
   int hp = prof_begin(MVG_PROF_POTRF, st, Nd * Nd * Nd / 3.0 + Nd * Nd / 2.0, 0.0);
-  if (!rc) rc = dense_potrf(A, d_info, st);
+  if (!rc) rc = A->tlr ? tlr_potrf(A, A->opts, d_info, st) : dense_potrf(A, d_info, st);
   prof_end(hp, st);
   int hs = prof_begin(MVG_PROF_SOLVE, st, Nd * Nd, 8.0 * Nd * (Nd + 1) / 2);
   if (!rc) {
@@ -654,12 +709,10 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16)
     return loglik_mixed(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
                         h_status, keep, st);
-  if (d.precision != MVG_FP64) {
-    set_error("loglik: precision %d not available in this build", d.precision);
-    return -7;
-  }
+  const bool tlr = d.precision == MVG_TLR;
   mvg_mat *A = nullptr;
-  int rc = mat_create(n_loc, d, &th[0], d_x, d_y, st, &A);
+  int rc = tlr ? tlr_mat_create(n_loc, d, &th[0], d_x, d_y, st, &A)
+               : mat_create(n_loc, d, &th[0], d_x, d_y, st, &A);
   if (rc) return rc;
   const int nred = (int)((A->N + 4095) / 4096);
   double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2 n_theta) | info (n_theta)
@@ -679,7 +732,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
     }
     const double npair = (double)n_loc * (n_loc + 1) / 2;
     int hg = prof_begin(MVG_PROF_GEN, st, 0.0, 8.0 * (double)A->N * (A->N + 1) / 2);
-    rc = mat_generate(A, st);
+    rc = tlr ? tlr_generate(A, st) : mat_generate(A, st);
     prof_end(hg, st);
     (void)npair;
     if (!rc) rc = eval_one(A, d_z, d_yv, d_part, d_out2 + 2 * i, d_info + i, st);
@@ -834,9 +887,10 @@ int mvg_mat_gather(const mvg_mat *A, const int64_t *d_rows, const int64_t *d_col
 }
 
 int mvg_mat_to_dense(const mvg_mat *A, double *d_out, int64_t ld, void *hip_stream) {
-  if (!A || A->precision == MVG_TLR) return -1;
+  if (!A) return -1;
   if (!d_out) return -2;
   if (ld < A->N) return -3;
+  if (A->precision == MVG_TLR) return tlr_to_dense(A, d_out, ld, (hipStream_t)hip_stream);
   return launch_to_dense(A, d_out, ld, (hipStream_t)hip_stream);
 }
 
@@ -859,10 +913,34 @@ void mvg_factor_destroy(mvg_factor *F) {
 
 int tlr_compress(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
                  const mvg_opts *o, mvg_mat **out, int32_t *h_ranks, void *hip_stream) {
-  (void)d_x; (void)d_y; (void)n_loc; (void)th; (void)o; (void)out; (void)h_ranks;
-  (void)hip_stream;
-  set_error("tlr_compress: not available in this build");
-  return MVG_ERR_STATE;
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (n_loc < 1) return -3;
+  if (!th) return -4;
+  mvg_opts d;
+  if (!o || o->precision != MVG_TLR || normalize_opts(o, &d)) return -5;
+  if (!out) return -6;
+  MaternArgs tmp;
+  if (matern_setup(th, &tmp)) return -4;
+  hipStream_t st = (hipStream_t)hip_stream;
+  mvg_mat *A = nullptr;
+  if (int rc = tlr_mat_create(n_loc, d, th, d_x, d_y, st, &A)) return rc < 0 && rc > -100 ? -4 : rc;
+  int rc = tlr_generate(A, st);
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = MVG_ERR_LAUNCH;
+  if (rc) {
+    mat_free(A);
+    return rc;
+  }
+  if (h_ranks) {
+    const int T = A->T;
+    for (int I = 0; I < T; ++I)
+      for (int J = 0; J < T; ++J) {
+        const int hi = std::max(I, J), lo = std::min(I, J);
+        h_ranks[(int64_t)I * T + J] = (I == J) ? -1 : A->tlr->S.rank[tidx(hi, lo, T)];
+      }
+  }
+  *out = A;
+  return 0;
 }
 
 }  // extern "C"

@@ -15,6 +15,7 @@
 #include <cstdlib>
 
 #include "mvgeo_internal.h"
+#include "tlr.h"
 
 namespace mvg {
 
@@ -371,7 +372,7 @@ __device__ __forceinline__ void gemm_block64(double *C, int ldc, const double *A
 // *d_info.
 __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double *__restrict__ winv,
                                                  int64_t *__restrict__ d_info, double tol0,
-                                                 double tol1, int64_t N) {
+                                                 double tol1, int64_t N, int64_t gbase, int lreal) {
   __shared__ double scol[2][PB];
   __shared__ double srow[2][PB];
   const int tid = threadIdx.x;
@@ -388,7 +389,8 @@ __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double
       x[i][jj] = (r == c) ? 1.0 : 0.0;
     }
   bool failed = false;
-  const int64_t g0 = (int64_t)k * nb + (int64_t)b * PB;
+  // global row of the block's first row; local rows >= lreal are padding
+  const int64_t g0 = gbase + (int64_t)b * PB;
   for (int j = 0; j < PB; ++j) {
     const int buf = j & 1, jq = j >> 4, jr = j & 15;
     if (tx == jr) {
@@ -403,7 +405,8 @@ __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double
     const double d = scol[buf][j];
     if (tid == 0 && !failed) {
       const int64_t g = g0 + j;
-      const double tol = g >= N ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
+      const bool pad = g >= N || b * PB + j >= lreal;
+      const double tol = pad ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
       if (!(d > tol) || !(d > 0.0)) {
         failed = true;
         atomicMin((unsigned long long *)d_info, (unsigned long long)(g + 1));
@@ -627,7 +630,8 @@ int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const Pi
   if (int rc = check_launch("zero_upper_blocks")) return rc;
   for (int b = 0; b < s; ++b) {
     hipLaunchKernelGGL(k_potrf64, dim3(1), dim3(256), 0, st, M, k, b, winv, d_info, pt.t0, pt.t1,
-                       pt.N);
+                       pt.N, pt.gbase >= 0 ? pt.gbase : (int64_t)k * M.nb,
+                       pt.lreal > 0 ? pt.lreal : M.nb);
     if (int rc = check_launch("potrf64")) return rc;
     const int nbelow = s - (b + 1);
     if (nbelow > 0) {
@@ -938,6 +942,7 @@ static int solve_args_ok(const mvg_mat *A) {
 }
 
 int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) {
+  if (A->tlr) return tlr_trsm_forward(A, d_V, nrhs, A->Np, st);
   if (int rc = solve_args_ok(A)) return rc;
   const TileMap M = A->map();
   const int chunks = M.nb / 64;
@@ -959,6 +964,7 @@ int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st) {
 }
 
 int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
+  if (A->tlr) return tlr_trsv_backward(A, d_v, st);
   if (int rc = solve_args_ok(A)) return rc;
   const TileMap M = A->map();
   const int nb = M.nb;
@@ -1025,6 +1031,7 @@ __global__ void k_reduce_pairs(const double *__restrict__ part, int n, double *_
 
 int logdet_quad(const mvg_mat *A, const double *d_y, double *d_part, double *d_out2,
                 hipStream_t st) {
+  if (A->tlr) return tlr_logdet_quad(A, d_y, d_part, d_out2, st);
   const int nblk = (int)((A->N + RED_CHUNK - 1) / RED_CHUNK);
   hipLaunchKernelGGL(k_logdet_quad_part, dim3(nblk), dim3(256), 0, st, A->map(), A->N, d_y, d_part);
   if (int rc = check_launch("logdet_quad_part")) return rc;

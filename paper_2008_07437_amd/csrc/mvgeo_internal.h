@@ -66,6 +66,8 @@ struct TileMap {
   int T, nb;
 };
 
+struct TlrState;
+
 }  // namespace mvg
 
 struct mvg_mat {
@@ -81,14 +83,9 @@ struct mvg_mat {
   double *d_qtab = nullptr;               // quadrature table of theta
   double *d_winv = nullptr;               // W_k = L_kk^-1 per diagonal tile (nb x nb)
   mvg_theta theta{};
+  mvg_opts opts{};
   mvg::MaternArgs margs{};
-  // TLR storage (precision == MVG_TLR)
-  double *lr_arena = nullptr;
-  size_t lr_bytes = 0;
-  int32_t *h_rank = nullptr;      // T*T, -1 dense
-  int32_t *d_rank = nullptr;
-  int64_t *h_uoff = nullptr;      // per packed tile: element offset of U (V follows)
-  int64_t *d_uoff = nullptr;
+  mvg::TlrState *tlr = nullptr;   // TLR storage (precision == MVG_TLR)
   mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb}; }
 };
 
@@ -120,9 +117,14 @@ int launch_cokrige_c0(const MaternArgs &P, const double *d_qtab, const double *d
                       const double *d_y0, int64_t m, double *d_c0, hipStream_t st);
 
 // dense FP64 Cholesky pieces
+// Pivot rule: a pivot at or below 2^-40 of the variable's variance (t0 for
+// even, t1 for odd global rows) is a failure.  gbase: global row of the
+// tile's row 0 (-1: k nb); lreal: rows of the tile that are not padding (0: nb).
 struct PivotTol {
   double t0, t1;
   int64_t N;
+  int64_t gbase = -1;
+  int lreal = 0;
 };
 enum { TRAIL_UPDATE = 0, TRAIL_TRSM = 1, TRAIL_BAND = 2 };
 template <int MODE>

@@ -1,0 +1,112 @@
+// Tile-low-rank (TLR) storage, the batched kernels it is built from, and the
+// TLR compression / Cholesky / solve drivers (internal to the library).
+#pragma once
+
+#include <vector>
+
+#include "mvgeo_internal.h"
+
+namespace mvg {
+
+// ------------------------------------------------------------ task lists
+
+struct GemmTask {  // C = alpha op(A) op(B) + beta C, column-major
+  const double *A, *B;
+  double *C;
+  int M, N, K, lda, ldb, ldc;
+  int ta, tb;  // 1: transposed operand
+  double alpha, beta;
+};
+
+constexpr int QR_MAXM = 2048;  // rows of a QR task (tile size bound)
+constexpr int QR_MAXN = 512;   // columns of a QR task (sketch width bound)
+struct QrTask {
+  double *A;    // m x n, overwritten by R (upper) and the reflectors (below)
+  int m, n, lda;
+  double *tau;  // n (nullable)
+  double *Q;    // m x n explicit Q (nullable)
+  int ldq;
+};
+
+constexpr int JACOBI_MAX_SWEEPS = 40;
+struct SvdTask {
+  double *R;  // n x n, overwritten by R J
+  int n, ldr;
+  double *J;  // n x n right rotations
+  int ldj;
+  double *sig;  // n column norms of R J
+};
+
+struct SketchTask {
+  double *out;
+  int rows, cols, ld;
+  uint64_t seed, stream;
+};
+
+enum { COPY_PLAIN = 0, COPY_UPPER_TRI = 1, COPY_IDENTITY = 2, COPY_LOWER_TRI = 3, COPY_ZERO = 4 };
+struct CopyTask {
+  const double *src;
+  double *dst;
+  int rows, cols, lds, ldd;
+  const int *idx;  // source column per destination column (nullable)
+  int mode;
+};
+
+int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
+                        hipStream_t st);
+int64_t gemm_blocks(const GemmTask &t);
+int launch_qr(const QrTask *d_tasks, int ntask, hipStream_t st);
+int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st);
+int launch_gaussian(const SketchTask *d_tasks, int ntask, hipStream_t st);
+int launch_copy_cols(const CopyTask *d_tasks, int ntask, hipStream_t st);
+
+// ------------------------------------------------------------ TLR storage
+//
+// Dense diagonal tiles (nb x nb each, leading dimension nbp = nb rounded up
+// to a multiple of 64 so that the dense diagonal kernels apply; the padding
+// is an identity block) and, for every off-diagonal lower tile (I > J),
+// either a low-rank pair (U, V), nb x r each, tile = U V^T, or a dense tile
+// stored as U = tile, V = I (r = nb, reported as rank -1).
+struct TlrStore {
+  int T = 0, nb = 0, nbp = 0;
+  int64_t N = 0;
+  double *diag = nullptr;          // T * nbp * nbp
+  std::vector<int> rank;           // per packed tile; diagonal entries unused
+  std::vector<char> dense;         // 1: stored dense (U = tile, V = I)
+  std::vector<int64_t> uoff;       // element offset of U in buf (V follows U)
+  double *buf = nullptr;
+  size_t cap = 0, used = 0;        // doubles
+  int reff(int64_t t) const { return dense[t] ? nb : rank[t]; }
+  const double *U(int64_t t) const { return buf + uoff[t]; }
+  const double *V(int64_t t) const { return buf + uoff[t] + (int64_t)nb * reff(t); }
+};
+
+// TLR state of a matrix: the compressed Sigma, its factor once factored, and
+// device copies of the factor's offsets and effective ranks for the solves.
+struct TlrState {
+  TlrStore S, L;
+  int64_t *d_uoff = nullptr;
+  int *d_reff = nullptr;
+};
+
+int tlr_build(mvg_mat *A, const mvg_opts &o, hipStream_t st);          // Sigma -> TLR Sigma
+int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st);
+int tlr_upload_meta(mvg_mat *A, hipStream_t st);
+int tlr_trsm_forward(const mvg_mat *A, double *d_V, int nrhs, int64_t ldv, hipStream_t st);
+int tlr_trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st);
+int tlr_logdet_quad(const mvg_mat *A, const double *d_y, double *d_part, double *d_out2,
+                    hipStream_t st);
+int tlr_to_dense(const mvg_mat *A, double *out, int64_t ld, hipStream_t st);
+void tlr_state_free(TlrState *S);
+void store_free(TlrStore &S);
+
+// One pass of a TLR driver keeps its host task lists alive until the stream
+// is synchronised (asynchronous copies read them).
+struct HostLists {
+  std::vector<std::vector<char>> keep;
+  std::vector<void *> dev;  // device buffers to free at the end
+  void *stage(const void *p, size_t bytes, hipStream_t st, int *rc);
+  void release(hipStream_t st);
+};
+
+}  // namespace mvg

@@ -1,0 +1,801 @@
+// Tile-low-rank covariance and Cholesky factorisation (Section 5.3).
+//
+// Compression: every off-diagonal tile of Sigma is generated densely and
+// compressed by a randomized SVD (Gaussian sketch, Householder QR of the
+// sketch, projection, QR of the projection, one-sided Jacobi SVD of the
+// small triangular factor), truncated at singular values <= acc (absolute
+// 2-norm rule); a tile whose rank would exceed max_rank stays dense.  The
+// sketch width starts from the rank of the previous tile at the same
+// distance from the diagonal and doubles until the kept rank is at least
+// OVERSAMPLE below it.
+//
+// Factorisation (left-looking over tile columns j): the column's tiles of the
+// compressed Sigma are expanded into a dense panel, the updates of all
+// earlier columns are applied as one GEMM,
+//   A_ij -= sum_{k<j} U_ik (V_ik^T V_jk) U_jk^T  =  [U_ik G_ijk]_k [U_jk]_k^T,
+// the diagonal tile is factored in FP64 (with its inverse W_j), and the
+// sub-diagonal tiles are recompressed at acc with the triangular solve
+// applied to V only (L_ij = U (W_j V)^T).  Each factor tile is compressed
+// once, after all its updates.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "tlr.h"
+
+namespace mvg {
+
+constexpr int OVERSAMPLE = 16;
+
+void *HostLists::stage(const void *p, size_t bytes, hipStream_t st, int *rc) {
+  if (bytes == 0) bytes = 8;
+  keep.emplace_back((const char *)p, (const char *)p + bytes);
+  void *d = nullptr;
+  if (hipMallocAsync(&d, bytes, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: staging allocation of %zu bytes failed", bytes);
+    *rc = MVG_ERR_ALLOC;
+    return nullptr;
+  }
+  dev.push_back(d);
+  if (hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: staging copy failed");
+    *rc = MVG_ERR_LAUNCH;
+    return nullptr;
+  }
+  return d;
+}
+
+void HostLists::release(hipStream_t st) {
+  for (void *d : dev) hipFreeAsync(d, st);
+  dev.clear();
+  hipStreamSynchronize(st);
+  keep.clear();
+}
+
+static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t st) {
+  std::vector<GemmTask> t;
+  std::vector<int64_t> start;
+  int64_t nb = 0;
+  for (const GemmTask &g : v) {
+    const int64_t b = gemm_blocks(g);
+    if (b == 0) continue;
+    t.push_back(g);
+    start.push_back(nb);
+    nb += b;
+  }
+  if (t.empty()) return 0;
+  int rc = 0;
+  const GemmTask *dt = (const GemmTask *)L.stage(t.data(), t.size() * sizeof(GemmTask), st, &rc);
+  const int64_t *ds = (const int64_t *)L.stage(start.data(), start.size() * 8, st, &rc);
+  if (rc) return rc;
+  return launch_gemm_batched(dt, ds, (int)t.size(), nb, st);
+}
+
+template <class T, int (*F)(const T *, int, hipStream_t)>
+static int run_list(const std::vector<T> &v, HostLists &L, hipStream_t st) {
+  if (v.empty()) return 0;
+  int rc = 0;
+  const T *d = (const T *)L.stage(v.data(), v.size() * sizeof(T), st, &rc);
+  if (rc) return rc;
+  return F(d, (int)v.size(), st);
+}
+
+static GemmTask gemm(const double *A, int lda, int ta, const double *B, int ldb, int tb, double *C,
+                     int ldc, int M, int N, int K, double alpha, double beta) {
+  return GemmTask{A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta};
+}
+
+// ------------------------------------------------------------- the store
+
+static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
+  if (S.used + n > S.cap) {
+    size_t cap = std::max({S.cap * 2, S.used + n, (size_t)1 << 22});
+    double *nbuf = nullptr;
+    if (hipMallocAsync((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
+      hipGetLastError();
+      set_error("TLR: low-rank store allocation of %.2f GB failed", cap * 8.0 / 1e9);
+      return MVG_ERR_ALLOC;
+    }
+    if (S.used)
+      hipMemcpyAsync(nbuf, S.buf, S.used * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (S.buf) hipFreeAsync(S.buf, st);
+    S.buf = nbuf;
+    S.cap = cap;
+  }
+  *off = (int64_t)S.used;
+  S.used += n;
+  return 0;
+}
+
+static int store_init(TlrStore &S, int T, int nb, int64_t N, hipStream_t st) {
+  S.T = T;
+  S.nb = nb;
+  S.nbp = (nb + 63) / 64 * 64;
+  S.N = N;
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  S.rank.assign(nt, 0);
+  S.dense.assign(nt, 0);
+  S.uoff.assign(nt, 0);
+  S.used = 0;
+  const size_t dbytes = sizeof(double) * (size_t)T * S.nbp * S.nbp;
+  if (hipMallocAsync((void **)&S.diag, dbytes, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: diagonal tile allocation of %.2f GB failed", dbytes / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  // identity everywhere: the padding of each nbp x nbp diagonal tile stays so
+  std::vector<CopyTask> v;
+  HostLists L;
+  for (int j = 0; j < T; ++j)
+    v.push_back(CopyTask{S.diag, S.diag + (int64_t)j * S.nbp * S.nbp, S.nbp, S.nbp, S.nbp, S.nbp,
+                         nullptr, COPY_IDENTITY});
+  int rc = run_list<CopyTask, launch_copy_cols>(v, L, st);
+  L.release(st);
+  return rc;
+}
+
+void store_free(TlrStore &S) {
+  hipFree(S.diag);
+  hipFree(S.buf);
+  S.diag = nullptr;
+  S.buf = nullptr;
+  S.cap = S.used = 0;
+}
+
+// ------------------------------------------------------------ compression
+
+struct CompressJob {
+  const double *C;  // nb x nb tile, column-major
+  int ldc;
+  int64_t t;        // packed tile index in the destination store
+  int s;            // sketch width
+  uint64_t key;     // sketch stream
+};
+
+// Compresses the jobs' tiles into store D; V is replaced by W V when W
+// (nb x nb, ldw, lower triangular) is given.  sguess[d] (d = I - J) is
+// updated with the ranks found.
+static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
+                         uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
+                         hipStream_t st) {
+  const int nb = D.nb;
+  const int T = D.T;
+  while (!jobs.empty()) {
+    // scratch per job: Om | Y | Z (nb x s each), R | J (s x s), sig | tau (s)
+    std::vector<size_t> base(jobs.size());
+    size_t tot = 0;
+    for (size_t b = 0; b < jobs.size(); ++b) {
+      const size_t s = jobs[b].s;
+      base[b] = tot;
+      tot += 3 * (size_t)nb * s + 4 * s * s + 2 * s;
+    }
+    double *ws = nullptr;
+    if (hipMallocAsync((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
+      hipGetLastError();
+      set_error("TLR: compression workspace of %.2f GB failed", tot * 8.0 / 1e9);
+      return MVG_ERR_ALLOC;
+    }
+    auto Om = [&](size_t b) { return ws + base[b]; };
+    auto Yb = [&](size_t b) { return ws + base[b] + (size_t)nb * jobs[b].s; };
+    auto Zb = [&](size_t b) { return ws + base[b] + 2 * (size_t)nb * jobs[b].s; };
+    auto Rb = [&](size_t b) { return ws + base[b] + 3 * (size_t)nb * jobs[b].s; };
+    auto Jb = [&](size_t b) { return Rb(b) + (size_t)jobs[b].s * jobs[b].s; };
+    auto Gj = [&](size_t b) { return Jb(b) + (size_t)jobs[b].s * jobs[b].s; };
+    auto Gr = [&](size_t b) { return Gj(b) + (size_t)jobs[b].s * jobs[b].s; };
+    auto Sg = [&](size_t b) { return Gr(b) + (size_t)jobs[b].s * jobs[b].s; };
+    auto Tau = [&](size_t b) { return Sg(b) + jobs[b].s; };
+    HostLists L;
+    int rc = 0;
+    {
+      std::vector<SketchTask> sk;
+      std::vector<GemmTask> g;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        sk.push_back(SketchTask{Om(b), nb, jobs[b].s, nb, seed, jobs[b].key});
+        g.push_back(gemm(jobs[b].C, jobs[b].ldc, 0, Om(b), nb, 0, Yb(b), nb, nb, jobs[b].s, nb,
+                         1.0, 0.0));
+      }
+      rc = run_list<SketchTask, launch_gaussian>(sk, L, st);
+      if (!rc) rc = run_gemms(g, L, st);  // Y = C Omega
+    }
+    if (!rc) {
+      std::vector<QrTask> q;
+      for (size_t b = 0; b < jobs.size(); ++b)
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tau(b), Om(b), nb});
+      rc = run_list<QrTask, launch_qr>(q, L, st);  // Q -> Om
+    }
+    if (!rc) {
+      std::vector<GemmTask> g;
+      for (size_t b = 0; b < jobs.size(); ++b)
+        g.push_back(gemm(jobs[b].C, jobs[b].ldc, 1, Om(b), nb, 0, Yb(b), nb, nb, jobs[b].s, nb,
+                         1.0, 0.0));
+      rc = run_gemms(g, L, st);  // B^T = C^T Q -> Y
+    }
+    if (!rc) {
+      std::vector<QrTask> q;
+      for (size_t b = 0; b < jobs.size(); ++b)
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tau(b), Zb(b), nb});
+      rc = run_list<QrTask, launch_qr>(q, L, st);  // B^T = Q' R, Q' -> Z
+    }
+    if (!rc) {
+      std::vector<CopyTask> c;
+      std::vector<SvdTask> sv;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        const int s = jobs[b].s;
+        c.push_back(CopyTask{Yb(b), Rb(b), s, s, nb, s, nullptr, COPY_UPPER_TRI});
+        sv.push_back(SvdTask{Rb(b), s, s, Jb(b), s, Sg(b)});
+      }
+      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_list<SvdTask, launch_jacobi>(sv, L, st);  // R J, J, sigma
+    }
+    // singular values to the host: ranks and retries
+    std::vector<double> sig;
+    if (!rc) {
+      size_t ns = 0;
+      for (auto &j : jobs) ns += j.s;
+      sig.resize(ns);
+      size_t o = 0;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        hipMemcpyAsync(sig.data() + o, Sg(b), sizeof(double) * jobs[b].s, hipMemcpyDeviceToHost, st);
+        o += jobs[b].s;
+      }
+      if (hipStreamSynchronize(st) != hipSuccess) {
+        set_error("TLR: compression kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        rc = MVG_ERR_LAUNCH;
+      }
+    }
+    // per job: retry with a wider sketch, or final rank (dense past max_rank)
+    enum { DONE = 0, RETRY = 1 };
+    std::vector<int> status(jobs.size(), DONE);
+    std::vector<CompressJob> retry;
+    std::vector<int> allidx;                 // kept columns, sorted by sigma, all jobs
+    std::vector<size_t> idx0(jobs.size(), 0);
+    const int smax = std::min(nb, QR_MAXN);
+    if (!rc) {
+      size_t o = 0;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        const int s = jobs[b].s;
+        const double *sg = sig.data() + o;
+        o += s;
+        std::vector<int> idx(s);
+        for (int i = 0; i < s; ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return sg[x] > sg[y]; });
+        int r = 0;
+        while (r < s && sg[idx[r]] > acc) ++r;
+        const int64_t t = jobs[b].t;
+        int64_t q = t;  // packed index -> (I, J)
+        int J = 0;
+        while (q >= T - J) {
+          q -= T - J;
+          ++J;
+        }
+        const int d = (int)q;  // I - J
+        if (r > max_rank) {
+          D.dense[t] = 1;
+          D.rank[t] = -1;
+          sguess[d] = r;
+        } else if (r > s - OVERSAMPLE && s < smax) {  // the sketch may have missed range
+          CompressJob j = jobs[b];
+          j.s = std::min(smax, (std::max(2 * s, r + 2 * OVERSAMPLE) + 15) / 16 * 16);
+          retry.push_back(j);
+          status[b] = RETRY;
+        } else {
+          D.dense[t] = 0;
+          D.rank[t] = r;
+          sguess[d] = r;
+          idx0[b] = allidx.size();
+          allidx.insert(allidx.end(), idx.begin(), idx.begin() + r);
+        }
+      }
+      // storage (the store may move: reserve everything before taking pointers)
+      for (size_t b = 0; b < jobs.size() && !rc; ++b) {
+        if (status[b] != DONE) continue;
+        const int64_t t = jobs[b].t;
+        const int r = D.reff(t);
+        D.uoff[t] = 0;
+        if (r > 0) rc = store_reserve(D, 2 * (size_t)nb * r, st, &D.uoff[t]);
+      }
+    }
+    // U = Q J_keep, V = W Q' (R J)_keep, or the dense tile (U = tile, V = W or I)
+    if (!rc) {
+      const int *didx = allidx.empty() ? nullptr
+                                       : (const int *)L.stage(allidx.data(), sizeof(int) * allidx.size(), st, &rc);
+      std::vector<CopyTask> c;
+      std::vector<GemmTask> g1, g2;
+      for (size_t b = 0; b < jobs.size() && !rc; ++b) {
+        if (status[b] != DONE) continue;
+        const int64_t t = jobs[b].t;
+        const int s = jobs[b].s;
+        double *U = D.buf + D.uoff[t];
+        if (D.dense[t]) {
+          double *V = U + (int64_t)nb * nb;
+          c.push_back(CopyTask{jobs[b].C, U, nb, nb, jobs[b].ldc, nb, nullptr, COPY_PLAIN});
+          if (W)
+            c.push_back(CopyTask{W, V, nb, nb, ldw, nb, nullptr, COPY_PLAIN});
+          else
+            c.push_back(CopyTask{V, V, nb, nb, nb, nb, nullptr, COPY_IDENTITY});
+          continue;
+        }
+        const int r = D.rank[t];
+        if (r == 0) continue;
+        double *V = U + (int64_t)nb * r;
+        c.push_back(CopyTask{Jb(b), Gj(b), s, r, s, s, didx + idx0[b], COPY_PLAIN});
+        c.push_back(CopyTask{Rb(b), Gr(b), s, r, s, s, didx + idx0[b], COPY_PLAIN});
+        g1.push_back(gemm(Om(b), nb, 0, Gj(b), s, 0, U, nb, nb, r, s, 1.0, 0.0));
+        if (W) {
+          g1.push_back(gemm(Zb(b), nb, 0, Gr(b), s, 0, Yb(b), nb, nb, r, s, 1.0, 0.0));
+          g2.push_back(gemm(W, ldw, 0, Yb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
+        } else {
+          g1.push_back(gemm(Zb(b), nb, 0, Gr(b), s, 0, V, nb, nb, r, s, 1.0, 0.0));
+        }
+      }
+      if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_gemms(g1, L, st);
+      if (!rc) rc = run_gemms(g2, L, st);
+    }
+    hipFreeAsync(ws, st);
+    L.release(st);
+    if (rc) return rc;
+    jobs.swap(retry);
+  }
+  return 0;
+}
+
+static int sketch_width(const std::vector<int> &sguess, int d, int nb) {
+  const int g = sguess[d] >= 0 ? sguess[d] : 16;
+  return std::min({nb, QR_MAXN, (g + OVERSAMPLE + 8 + 15) / 16 * 16});
+}
+
+// ---------------------------------------------------- Sigma -> TLR Sigma
+
+int tlr_build(mvg_mat *A, const mvg_opts &o, hipStream_t st) {
+  TlrState *S = A->tlr;
+  const int T = A->T, nb = A->nb;
+  TlrStore &D = S->S;
+  if (int rc = store_init(D, T, nb, A->N, st)) return rc;
+  // tiles are generated densely a range of whole tile columns at a time
+  // (packed order: the tiles of a column are contiguous), up to BUILD_BYTES
+  constexpr size_t BUILD_BYTES = (size_t)16 << 30;
+  const size_t tile_bytes = sizeof(double) * (size_t)nb * nb;
+  const int64_t max_tiles = std::max<int64_t>(T, (int64_t)(BUILD_BYTES / tile_bytes));
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  double *G = nullptr;
+  const int64_t gtiles = std::min<int64_t>(nt, max_tiles);
+  if (hipMallocAsync((void **)&G, tile_bytes * gtiles, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: tile buffer of %.2f GB failed", tile_bytes * gtiles / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  std::vector<int> sguess(T, -1);
+  int rc = 0;
+  for (int J0 = 0; J0 < T && !rc;) {
+    int J1 = J0;
+    int64_t cnt = 0;
+    while (J1 < T && cnt + (T - J1) <= gtiles) cnt += T - J1++;
+    const int64_t t0 = tidx(J0, J0, T);
+    std::vector<int64_t> off(nt, 0);
+    for (int64_t t = t0; t < t0 + cnt; ++t) off[t] = (t - t0) * (int64_t)tile_bytes;
+    HostLists L;
+    const int64_t *doff = (const int64_t *)L.stage(off.data(), off.size() * 8, st, &rc);
+    if (rc) break;
+    const TileMap M{(char *)G, doff, nullptr, T, nb};
+    rc = launch_cov_tiles(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, M, (int)t0, (int)cnt, st);
+    std::vector<CopyTask> c;
+    std::vector<CompressJob> jobs;
+    for (int J = J0; J < J1; ++J) {
+      const int64_t td = tidx(J, J, T) - t0;
+      c.push_back(CopyTask{G + td * nb * nb, D.diag + (int64_t)J * D.nbp * D.nbp, nb, nb, nb, D.nbp,
+                           nullptr, COPY_PLAIN});
+      for (int I = J + 1; I < T; ++I) {
+        const int64_t t = tidx(I, J, T);
+        jobs.push_back(CompressJob{G + (t - t0) * nb * nb, nb, t, sketch_width(sguess, I - J, nb),
+                                   (uint64_t)t * 2 + 0});
+      }
+    }
+    if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+    if (!rc) rc = compress_jobs(jobs, D, o.tlr_acc, o.tlr_max_rank, o.seed, nullptr, 0, sguess, st);
+    L.release(st);
+    J0 = J1;
+  }
+  hipFreeAsync(G, st);
+  return rc;
+}
+
+// ------------------------------------------------------ TLR Cholesky
+
+int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
+  TlrState *S = A->tlr;
+  const int T = A->T, nb = A->nb;
+  const TlrStore &Sg = S->S;
+  TlrStore &Lf = S->L;
+  const int nbp = Sg.nbp;
+  store_free(Lf);
+  if (int rc = store_init(Lf, T, nb, A->N, st)) return rc;
+  if (!A->d_winv) {
+    if (hipMalloc((void **)&A->d_winv, sizeof(double) * (size_t)T * nbp * nbp) != hipSuccess) {
+      hipGetLastError();
+      set_error("TLR: inverse diagonal tiles allocation failed");
+      return MVG_ERR_ALLOC;
+    }
+  }
+  // tile map of the factor's diagonal tiles (nbp x nbp each) for the dense
+  // diagonal kernels
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  std::vector<int64_t> doff(nt, 0);
+  for (int j = 0; j < T; ++j) doff[tidx(j, j, T)] = (int64_t)j * nbp * nbp * 8;
+  HostLists L0;
+  int rc = 0;
+  const int64_t *d_doff = (const int64_t *)L0.stage(doff.data(), doff.size() * 8, st, &rc);
+  if (rc) return rc;
+  const TileMap Md{(char *)Lf.diag, d_doff, nullptr, T, nbp};
+  double *P = nullptr;  // dense panel: (T - j) nb x nb, ld (T - j) nb
+  if (hipMallocAsync((void **)&P, sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
+    hipGetLastError();
+    L0.release(st);
+    set_error("TLR: panel allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  std::vector<int> sguess(T, -1);
+  for (int j = 0; j < T && !rc; ++j) {
+    const int ntile = T - j;
+    const int ldp = ntile * nb;
+    HostLists L;
+    // (1) expand column j of the compressed Sigma into the panel
+    {
+      std::vector<CopyTask> c{CopyTask{Sg.diag + (int64_t)j * nbp * nbp, P, nb, nb, nbp, ldp,
+                                       nullptr, COPY_PLAIN}};
+      std::vector<GemmTask> g;
+      for (int i = j + 1; i < T; ++i) {
+        const int64_t t = tidx(i, j, T);
+        const int r = Sg.reff(t);
+        g.push_back(gemm(Sg.U(t), nb, 0, Sg.V(t), nb, 1, P + (int64_t)(i - j) * nb, ldp, nb, nb, r,
+                         1.0, 0.0));
+      }
+      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_gemms(g, L, st);
+    }
+    // (2) updates from the factor columns k < j
+    int64_t Kj = 0;
+    std::vector<int64_t> koff(j + 1, 0);
+    for (int k = 0; k < j; ++k) {
+      koff[k] = Kj;
+      Kj += Lf.reff(tidx(j, k, T));
+    }
+    if (!rc && Kj > 0) {
+      size_t gsz = 0;
+      for (int i = j; i < T; ++i)
+        for (int k = 0; k < j; ++k) gsz += (size_t)Lf.reff(tidx(i, k, T)) * Lf.reff(tidx(j, k, T));
+      double *Qc = nullptr, *Pc = nullptr, *Gs = nullptr;
+      const size_t qn = (size_t)nb * Kj, pn = (size_t)ldp * Kj;
+      if (hipMallocAsync((void **)&Qc, sizeof(double) * (qn + pn + std::max<size_t>(gsz, 1)), st) !=
+          hipSuccess) {
+        hipGetLastError();
+        set_error("TLR: update workspace of %.2f GB failed", (qn + pn + gsz) * 8.0 / 1e9);
+        rc = MVG_ERR_ALLOC;
+      } else {
+        Pc = Qc + qn;
+        Gs = Pc + pn;
+        std::vector<CopyTask> c;
+        std::vector<GemmTask> gG, gP;
+        for (int k = 0; k < j; ++k) {
+          const int64_t tj = tidx(j, k, T);
+          const int rj = Lf.reff(tj);
+          if (rj) c.push_back(CopyTask{Lf.U(tj), Qc + koff[k] * nb, nb, rj, nb, nb, nullptr, COPY_PLAIN});
+        }
+        size_t go = 0;
+        for (int i = j; i < T; ++i)
+          for (int k = 0; k < j; ++k) {
+            const int64_t ti = tidx(i, k, T), tj = tidx(j, k, T);
+            const int ri = Lf.reff(ti), rj = Lf.reff(tj);
+            if (!rj) continue;
+            double *Gik = Gs + go;
+            if (ri) gG.push_back(gemm(Lf.V(ti), nb, 1, Lf.V(tj), nb, 0, Gik, ri, ri, rj, nb, 1.0, 0.0));
+            // K = 0 (rank-0 tile) writes zeros into its block of Pc
+            gP.push_back(gemm(Lf.U(ti), nb, 0, Gik, std::max(ri, 1), 0,
+                              Pc + (int64_t)(i - j) * nb + koff[k] * ldp, ldp, nb, rj, ri, 1.0, 0.0));
+            go += (size_t)ri * rj;
+          }
+        rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+        if (!rc) rc = run_gemms(gG, L, st);
+        if (!rc) rc = run_gemms(gP, L, st);
+        if (!rc) {
+          std::vector<GemmTask> gB{gemm(Pc, ldp, 0, Qc, nb, 1, P, ldp, ldp, nb, (int)Kj, -1.0, 1.0)};
+          const double fl = 2.0 * ldp * nb * (double)Kj;
+          int h = prof_begin(MVG_PROF_TRAILING, st, fl, 0.0);
+          rc = run_gemms(gB, L, st);
+          prof_end(h, st);
+        }
+        hipFreeAsync(Qc, st);
+      }
+    }
+    // (3) diagonal tile: FP64 Cholesky and W_j
+    if (!rc) {
+      std::vector<CopyTask> c{CopyTask{P, Lf.diag + (int64_t)j * nbp * nbp, nb, nb, ldp, nbp,
+                                       nullptr, COPY_PLAIN}};
+      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
+      pt.gbase = (int64_t)j * nb;
+      pt.lreal = nb;
+      if (!rc) rc = diag_factor(Md, j, A->d_winv, d_info, pt, st);
+    }
+    // (4) recompress the sub-diagonal tiles, V <- W_j V
+    if (!rc && j + 1 < T) {
+      std::vector<CompressJob> jobs;
+      for (int i = j + 1; i < T; ++i) {
+        const int64_t t = tidx(i, j, T);
+        const int g = Sg.dense[t] ? nb : Sg.rank[t];
+        std::vector<int> sg1(1, std::max(g, sguess[i - j]));
+        jobs.push_back(CompressJob{P + (int64_t)(i - j) * nb, ldp, t, sketch_width(sg1, 0, nb),
+                                   (uint64_t)t * 2 + 1});
+      }
+      rc = compress_jobs(jobs, Lf, o.tlr_acc, o.tlr_max_rank, o.seed ^ 0x5bd1e995u,
+                         A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st);
+    }
+    L.release(st);
+  }
+  hipFreeAsync(P, st);
+  L0.release(st);
+  if (!rc) rc = tlr_upload_meta(A, st);
+  return rc;
+}
+
+// Device copies of the factor's per-tile offsets and ranks (for the solves).
+int tlr_upload_meta(mvg_mat *A, hipStream_t st) {
+  TlrState *S = A->tlr;
+  const TlrStore &Lf = S->L;
+  const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
+  std::vector<int64_t> u(nt);
+  std::vector<int> r(nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    u[t] = Lf.uoff[t];
+    r[t] = Lf.reff(t);
+  }
+  hipFree(S->d_uoff);
+  hipFree(S->d_reff);
+  S->d_uoff = nullptr;
+  S->d_reff = nullptr;
+  if (hipMalloc((void **)&S->d_uoff, nt * 8) != hipSuccess ||
+      hipMalloc((void **)&S->d_reff, nt * 4) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: metadata allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  hipMemcpyAsync(S->d_uoff, u.data(), nt * 8, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(S->d_reff, r.data(), nt * 4, hipMemcpyHostToDevice, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return MVG_ERR_LAUNCH;
+  return 0;
+}
+
+// ------------------------------------------------------------------ solves
+//
+// Vectors have length Np = T nb; nrhs columns with leading dimension ldv
+// (blockIdx.z selects the column).
+
+constexpr int TLR_MAXNB = 2048;
+
+// v_k <- W_k v_k (lower triangular W_k, ld nbp)
+__global__ __launch_bounds__(256) void k_tlr_tile_fwd(int nb, int nbp, int k,
+                                                      const double *__restrict__ winv,
+                                                      double *__restrict__ V, int64_t ldv) {
+  __shared__ double v[TLR_MAXNB];
+  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  const double *W = winv + (int64_t)k * nbp * nbp;
+  for (int r = threadIdx.x; r < nb; r += 256) v[r] = vk[r];
+  __syncthreads();
+  double out[TLR_MAXNB / 256];
+#pragma unroll
+  for (int p = 0; p < TLR_MAXNB / 256; ++p) {
+    const int r = p * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (r < nb)
+      for (int c = 0; c <= r; ++c) acc += W[(int64_t)c * nbp + r] * v[c];
+    out[p] = acc;
+  }
+#pragma unroll
+  for (int p = 0; p < TLR_MAXNB / 256; ++p) {
+    const int r = p * 256 + threadIdx.x;
+    if (r < nb) vk[r] = out[p];
+  }
+}
+
+// v_k <- W_k^T v_k
+__global__ __launch_bounds__(256) void k_tlr_tile_bwd(int nb, int nbp, int k,
+                                                      const double *__restrict__ winv,
+                                                      double *__restrict__ V, int64_t ldv) {
+  __shared__ double v[TLR_MAXNB];
+  __shared__ double out[TLR_MAXNB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  const double *W = winv + (int64_t)k * nbp * nbp;
+  for (int r = threadIdx.x; r < nb; r += 256) v[r] = vk[r];
+  __syncthreads();
+  for (int c = wave; c < nb; c += 4) {
+    const double *col = W + (int64_t)c * nbp;
+    double t = 0.0;
+    for (int r = c + lane; r < nb; r += 64) t += col[r] * v[r];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) out[c] = t;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < nb; r += 256) vk[r] = out[r];
+}
+
+// Forward update after v_k: v_i -= U_ik (V_ik^T v_k) for i = k + 1 + blockIdx.x.
+// Backward update after w_k: v_j -= V_kj (U_kj^T w_k) for j = blockIdx.x < k.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_tlr_lr_update(int T, int nb, int k,
+                                                       const double *__restrict__ buf,
+                                                       const int64_t *__restrict__ uoff,
+                                                       const int *__restrict__ reff,
+                                                       double *__restrict__ V, int64_t ldv) {
+  __shared__ double x[TLR_MAXNB];
+  __shared__ double g[TLR_MAXNB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int other = FWD ? k + 1 + blockIdx.x : blockIdx.x;
+  const int64_t t = FWD ? tidx(other, k, T) : tidx(k, other, T);
+  const int r = reff[t];
+  if (r == 0) return;
+  const double *U = buf + uoff[t];
+  const double *Vt = U + (int64_t)nb * r;
+  const double *left = FWD ? U : Vt;   // applied to g
+  const double *right = FWD ? Vt : U;  // contracted with x
+  double *vc = V + (int64_t)blockIdx.z * ldv;
+  for (int i = threadIdx.x; i < nb; i += 256) x[i] = vc[(int64_t)k * nb + i];
+  __syncthreads();
+  for (int c = wave; c < r; c += 4) {
+    const double *col = right + (int64_t)c * nb;
+    double s = 0.0;
+    for (int i = lane; i < nb; i += 64) s += col[i] * x[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) g[c] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) s += left[(int64_t)c * nb + i] * g[c];
+    vc[(int64_t)other * nb + i] -= s;
+  }
+}
+
+static int tlr_solve_ok(const mvg_mat *A) {
+  if (!A->tlr || !A->tlr->d_uoff || A->nb > TLR_MAXNB) {
+    set_error("TLR solve needs a factored TLR matrix with nb <= %d", TLR_MAXNB);
+    return MVG_ERR_STATE;
+  }
+  return 0;
+}
+
+int tlr_trsm_forward(const mvg_mat *A, double *d_V, int nrhs, int64_t ldv, hipStream_t st) {
+  if (int rc = tlr_solve_ok(A)) return rc;
+  const TlrState *S = A->tlr;
+  const int T = A->T, nb = A->nb, nbp = S->L.nbp;
+  for (int k = 0; k < T; ++k) {
+    hipLaunchKernelGGL(k_tlr_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, nb, nbp, k,
+                       (const double *)A->d_winv, d_V, ldv);
+    if (int rc = check_launch("tlr_tile_fwd")) return rc;
+    if (k + 1 < T) {
+      hipLaunchKernelGGL(k_tlr_lr_update<true>, dim3(T - k - 1, 1, nrhs), dim3(256), 0, st, T, nb,
+                         k, (const double *)S->L.buf, (const int64_t *)S->d_uoff,
+                         (const int *)S->d_reff, d_V, ldv);
+      if (int rc = check_launch("tlr_lr_update")) return rc;
+    }
+  }
+  return 0;
+}
+
+int tlr_trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
+  if (int rc = tlr_solve_ok(A)) return rc;
+  const TlrState *S = A->tlr;
+  const int T = A->T, nb = A->nb, nbp = S->L.nbp;
+  for (int k = T - 1; k >= 0; --k) {
+    hipLaunchKernelGGL(k_tlr_tile_bwd, dim3(1), dim3(256), 0, st, nb, nbp, k,
+                       (const double *)A->d_winv, d_v, A->Np);
+    if (int rc = check_launch("tlr_tile_bwd")) return rc;
+    if (k > 0) {
+      hipLaunchKernelGGL(k_tlr_lr_update<false>, dim3(k), dim3(256), 0, st, T, nb, k,
+                         (const double *)S->L.buf, (const int64_t *)S->d_uoff,
+                         (const int *)S->d_reff, d_v, A->Np);
+      if (int rc = check_launch("tlr_lr_update")) return rc;
+    }
+  }
+  return 0;
+}
+
+// {2 sum log L_jj over the N real rows, y^T y}: fixed-order two-stage sums
+constexpr int TLR_RED = 4096;
+__global__ __launch_bounds__(256) void k_tlr_logdet_part(const double *__restrict__ diag, int nb,
+                                                         int nbp, int64_t N,
+                                                         const double *__restrict__ y,
+                                                         double *__restrict__ part) {
+  __shared__ double r0[256], r1[256];
+  const int64_t base = (int64_t)blockIdx.x * TLR_RED;
+  double a = 0.0, q = 0.0;
+  for (int t = threadIdx.x; t < TLR_RED; t += 256) {
+    const int64_t gi = base + t;
+    if (gi >= N) break;
+    const int64_t j = gi / nb, r = gi % nb;
+    a += log(diag[j * nbp * nbp + r * nbp + r]);
+    q += y[gi] * y[gi];
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = q;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r0[threadIdx.x] += r0[threadIdx.x + s];
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r0[0];
+    part[2 * blockIdx.x + 1] = r1[0];
+  }
+}
+
+__global__ void k_tlr_logdet_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0.0, q = 0.0;
+    for (int i = 0; i < n; ++i) {
+      a += part[2 * i];
+      q += part[2 * i + 1];
+    }
+    out[0] = 2.0 * a;
+    out[1] = q;
+  }
+}
+
+int tlr_logdet_quad(const mvg_mat *A, const double *d_y, double *d_part, double *d_out2,
+                    hipStream_t st) {
+  const int nblk = (int)((A->N + TLR_RED - 1) / TLR_RED);
+  hipLaunchKernelGGL(k_tlr_logdet_part, dim3(nblk), dim3(256), 0, st, (const double *)A->tlr->L.diag,
+                     A->nb, A->tlr->L.nbp, A->N, d_y, d_part);
+  if (int rc = check_launch("tlr_logdet_part")) return rc;
+  hipLaunchKernelGGL(k_tlr_logdet_final, dim3(1), dim3(64), 0, st, (const double *)d_part, nblk,
+                     d_out2);
+  return check_launch("tlr_logdet_final");
+}
+
+// Lower triangle of the compressed Sigma (or of the factor once factored) as
+// a dense N x N column-major matrix (inspection of small cases).
+int tlr_to_dense(const mvg_mat *A, double *out, int64_t ld, hipStream_t st) {
+  const TlrStore &D = A->factored ? A->tlr->L : A->tlr->S;
+  const int T = A->T, nb = A->nb;
+  const int64_t N = A->N;
+  HostLists L;
+  std::vector<CopyTask> c;
+  std::vector<GemmTask> g;
+  for (int J = 0; J < T; ++J) {
+    const int cols = (int)std::min<int64_t>(nb, N - (int64_t)J * nb);
+    for (int I = 0; I < J; ++I)  // upper tiles: zero
+      c.push_back(CopyTask{out, out + (int64_t)J * nb * ld + (int64_t)I * nb, nb, cols, (int)ld,
+                           (int)ld, nullptr, COPY_ZERO});
+    for (int I = J; I < T; ++I) {
+      const int rows = (int)std::min<int64_t>(nb, N - (int64_t)I * nb);
+      double *o = out + (int64_t)J * nb * ld + (int64_t)I * nb;
+      if (I == J) {
+        c.push_back(CopyTask{D.diag + (int64_t)J * D.nbp * D.nbp, o, rows, cols, D.nbp, (int)ld,
+                             nullptr, COPY_LOWER_TRI});
+        continue;
+      }
+      const int64_t t = tidx(I, J, T);
+      g.push_back(gemm(D.U(t), nb, 0, D.V(t), nb, 1, o, (int)ld, rows, cols, D.reff(t), 1.0, 0.0));
+    }
+  }
+  int rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+  if (!rc) rc = run_gemms(g, L, st);
+  L.release(st);
+  return rc;
+}
+
+void tlr_state_free(TlrState *S) {
+  if (!S) return;
+  store_free(S->S);
+  store_free(S->L);
+  hipFree(S->d_uoff);
+  hipFree(S->d_reff);
+  delete S;
+}
+
+}  // namespace mvg

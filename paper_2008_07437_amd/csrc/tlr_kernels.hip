@@ -1,0 +1,405 @@
+// Batched small dense linear algebra for the tile-low-rank (TLR) path on
+// gfx950: FP64 GEMM on MFMA over lists of variable-size products, Householder
+// QR of tall-skinny matrices, one-sided Jacobi SVD of small square matrices,
+// Gaussian sketch matrices.  One list entry per product / matrix; the TLR
+// driver builds the lists on the host.
+#include <cmath>
+
+#include "tlr.h"
+
+namespace mvg {
+
+typedef double dbl4t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ batched GEMM
+//
+// C = alpha op(A) op(B) + beta C, column-major, op(X) = X or X^T.  One
+// workgroup per 64 x 64 block of C; four waves of 32 x 32 (2 x 2 tiles of
+// v_mfma_f64_16x16x4f64); K slices of 16 staged through LDS with the next
+// slice's global loads in flight during the current slice's MFMAs.  Ragged
+// edges are zero-filled on load and masked on store.
+constexpr int GB = 64, GK = 16;
+
+__device__ __forceinline__ int find_task(const int64_t *__restrict__ start, int n, int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict__ tasks,
+                                                      const int64_t *__restrict__ start, int ntask) {
+  __shared__ double As[GK][GB + 2];
+  __shared__ double Bs[GK][GB + 2];
+  const int t = find_task(start, ntask, blockIdx.x);
+  const GemmTask tk = tasks[t];
+  const int mt = (tk.M + GB - 1) / GB;
+  const int64_t local = (int64_t)blockIdx.x - start[t];
+  const int m0 = (int)(local % mt) * GB, n0 = (int)(local / mt) * GB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int m, k;
+      if (!tk.ta) { m = tid & 63; k = (tid >> 6) + 4 * i; }
+      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
+      const int gm = m0 + m, gk = k0 + k;
+      double v = 0.0;
+      if (gm < tk.M && gk < tk.K)
+        v = tk.ta ? tk.A[(int64_t)gm * tk.lda + gk] : tk.A[(int64_t)gk * tk.lda + gm];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int n, k;
+      if (tk.tb) { n = tid & 63; k = (tid >> 6) + 4 * i; }
+      else { k = tid & 15; n = (tid >> 4) + 16 * i; }
+      const int gn = n0 + n, gk = k0 + k;
+      double v = 0.0;
+      if (gn < tk.N && gk < tk.K)
+        v = tk.tb ? tk.B[(int64_t)gk * tk.ldb + gn] : tk.B[(int64_t)gn * tk.ldb + gk];
+      rb[i] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!tk.ta) As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
+      else As[tid & 15][(tid >> 4) + 16 * i] = ra[i];
+      if (tk.tb) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
+      else Bs[tid & 15][(tid >> 4) + 16 * i] = rb[i];
+    }
+  };
+  dbl4t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
+  if (tk.K > 0) load(0);
+  for (int k0 = 0; k0 < tk.K; k0 += GK) {
+    store();
+    __syncthreads();
+    if (k0 + GK < tk.K) load(k0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[ks + lk][wr * 32 + i * 16 + l16];
+        b[i] = Bs[ks + lk][wc * 32 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[i][j] of a 16 x 16 tile: lane j + 16 (i % 4), element i / 4
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 32 + i * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 32 + j * 16 + l16;
+        if (gm < tk.M && gn < tk.N) {
+          double *c = tk.C + (int64_t)gn * tk.ldc + gm;
+          const double v = tk.alpha * acc[i][j][e];
+          *c = (tk.beta == 0.0) ? v : v + tk.beta * *c;
+        }
+      }
+}
+
+int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
+                        hipStream_t st) {
+  if (ntask <= 0 || nblocks <= 0) return 0;
+  if (nblocks >= ((int64_t)1 << 31)) {
+    set_error("batched GEMM: %lld blocks", (long long)nblocks);
+    return MVG_ERR_LIMIT;
+  }
+  hipLaunchKernelGGL(k_gemm_batched, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks, d_start,
+                     ntask);
+  return check_launch("gemm_batched");
+}
+
+int64_t gemm_blocks(const GemmTask &t) {
+  if (t.M <= 0 || t.N <= 0) return 0;
+  return (int64_t)((t.M + GB - 1) / GB) * ((t.N + GB - 1) / GB);
+}
+
+// ---------------------------------------------------------- Householder QR
+//
+// A (m x n, m >= n, column-major, lda) = Q R by n Householder reflectors
+// H_j = I - tau_j v_j v_j^T (v_j(j) = 1, stored below the diagonal of A; R
+// above and on it).  If Q is given, the first n columns of H_0 ... H_{n-1}
+// are written there (m x n, ldq).  One workgroup per matrix; column c of the
+// trailing update belongs to wave c % QW throughout.
+constexpr int QW = 8;  // waves per QR workgroup
+
+__global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks) {
+  __shared__ double v[QR_MAXM];
+  __shared__ double s_tau[QR_MAXN];
+  __shared__ double red[QW];
+  const QrTask tk = tasks[blockIdx.x];
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  double *A = tk.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < n; ++j) {
+    double *aj = A + (int64_t)j * lda;
+    double ss = 0.0;
+    for (int i = j + 1 + tid; i < m; i += 64 * QW) ss += aj[i] * aj[i];
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    double sigma2 = 0.0;
+    for (int w = 0; w < QW; ++w) sigma2 += red[w];
+    const double alpha = aj[j];
+    double tau = 0.0, scale = 0.0, beta = alpha;
+    if (sigma2 > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    for (int i = j + 1 + tid; i < m; i += 64 * QW) {
+      const double vi = aj[i] * scale;
+      v[i] = vi;
+    }
+    if (tid == 0) {
+      v[j] = 1.0;
+      s_tau[j] = tau;
+    }
+    __syncthreads();
+    // store the reflector below the diagonal and beta on it
+    for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = v[i];
+    if (tid == 0) aj[j] = beta;
+    if (tau != 0.0) {
+      for (int c = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c < n; c += QW) {
+        double *ac = A + (int64_t)c * lda;
+        double w = 0.0;
+        for (int i = j + lane; i < m; i += 64) w += v[i] * ac[i];
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+        const double tw = tau * w;
+        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (tk.tau)
+    for (int j = tid; j < n; j += 64 * QW) tk.tau[j] = s_tau[j];
+  if (!tk.Q) return;
+  double *Q = tk.Q;
+  const int ldq = tk.ldq;
+  for (int c = wave; c < n; c += QW)
+    for (int i = lane; i < m; i += 64) Q[(int64_t)c * ldq + i] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    const double tau = s_tau[j];
+    const double *aj = A + (int64_t)j * lda;
+    for (int i = j + 1 + tid; i < m; i += 64 * QW) v[i] = aj[i];
+    if (tid == 0) v[j] = 1.0;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int c = j + (((wave - j) % QW + QW) % QW); c < n; c += QW) {
+        double *qc = Q + (int64_t)c * ldq;
+        double w = 0.0;
+        for (int i = j + lane; i < m; i += 64) w += v[i] * qc[i];
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+        const double tw = tau * w;
+        for (int i = j + lane; i < m; i += 64) qc[i] -= tw * v[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int launch_qr(const QrTask *d_tasks, int ntask, hipStream_t st) {
+  if (ntask <= 0) return 0;
+  hipLaunchKernelGGL(k_qr, dim3(ntask), dim3(64 * QW), 0, st, d_tasks);
+  return check_launch("qr");
+}
+
+// ------------------------------------------------------- one-sided Jacobi
+//
+// Orthogonalises the columns of R (n x n, ldr) by plane rotations applied
+// on the right, R <- R J, accumulating J (n x n, ldj, starts at I).  Pairs
+// follow a round-robin tournament (n - 1 rounds of n / 2 disjoint pairs per
+// sweep), the waves share a round's pairs.  A pair is rotated when
+// |r_p . r_q| > n 2^-52 sqrt(|r_p|^2 |r_q|^2) (below that the inner product is
+// rounding noise); the sweeps stop after one without a rotation.
+// sig[i] = |column i of R J|.  Matrices with n <= JACOBI_LDS_N are worked on
+// in LDS and written back at the end.
+constexpr int JACOBI_LDS_N = 80;
+constexpr int JW = 8;  // waves per workgroup
+
+__device__ __forceinline__ void jacobi_pair(double *rp, double *rq, double *jp, double *jq, int n,
+                                            int lane, double tol, int &any) {
+  double a = 0.0, b = 0.0, g = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double x = rp[i], y = rq[i];
+    a += x * x;
+    b += y * y;
+    g += x * y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    g += __shfl_xor(g, o);
+  }
+  if (!(fabs(g) > tol * sqrt(a * b)) || a == 0.0 || b == 0.0) return;
+  any = 1;
+  const double zeta = (b - a) / (2.0 * g);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  for (int i = lane; i < n; i += 64) {
+    const double x = rp[i], y = rq[i];
+    rp[i] = cs * x - sn * y;
+    rq[i] = sn * x + cs * y;
+  }
+  for (int i = lane; i < n; i += 64) {
+    const double x = jp[i], y = jq[i];
+    jp[i] = cs * x - sn * y;
+    jq[i] = sn * x + cs * y;
+  }
+}
+
+__global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ tasks) {
+  __shared__ int changed;
+  __shared__ double sR[JACOBI_LDS_N * JACOBI_LDS_N];
+  __shared__ double sJ[JACOBI_LDS_N * JACOBI_LDS_N];
+  const SvdTask tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool in_lds = n <= JACOBI_LDS_N;
+  double *R = in_lds ? sR : tk.R;
+  double *J = in_lds ? sJ : tk.J;
+  const int ldr = in_lds ? n : tk.ldr, ldj = in_lds ? n : tk.ldj;
+  if (in_lds)
+    for (int e = tid; e < n * n; e += 64 * JW) sR[e] = tk.R[(int64_t)(e / n) * tk.ldr + e % n];
+  for (int c = wave; c < n; c += JW)
+    for (int i = lane; i < n; i += 64) J[(int64_t)c * ldj + i] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
+  const int np = n + (n & 1);  // players; an odd n adds an idle one
+  const double tol = (double)(n > 1 ? n : 1) * 0x1p-52;
+  for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    int any = 0;
+    for (int round = 0; round < np - 1; ++round) {
+      for (int pi = wave; pi < np / 2; pi += JW) {
+        int p, q;
+        if (pi == 0) {
+          p = round;
+          q = np - 1;
+        } else {
+          p = (round + pi) % (np - 1);
+          q = (round - pi + (np - 1)) % (np - 1);
+        }
+        if (p > q) { const int t = p; p = q; q = t; }
+        if (q >= n) continue;
+        jacobi_pair(R + (int64_t)p * ldr, R + (int64_t)q * ldr, J + (int64_t)p * ldj,
+                    J + (int64_t)q * ldj, n, lane, tol, any);
+      }
+      __syncthreads();
+    }
+    if (any && lane == 0) atomicOr(&changed, 1);
+    __syncthreads();
+    if (!changed) break;
+  }
+  for (int c = wave; c < n; c += JW) {
+    const double *rc = R + (int64_t)c * ldr;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += rc[i] * rc[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) tk.sig[c] = sqrt(s);
+  }
+  if (in_lds)
+    for (int e = tid; e < n * n; e += 64 * JW) {
+      const int c = e / n, i = e % n;
+      tk.R[(int64_t)c * tk.ldr + i] = sR[e];
+      tk.J[(int64_t)c * tk.ldj + i] = sJ[e];
+    }
+}
+
+int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st) {
+  if (ntask <= 0) return 0;
+  hipLaunchKernelGGL(k_jacobi, dim3(ntask), dim3(64 * JW), 0, st, d_tasks);
+  return check_launch("jacobi");
+}
+
+// -------------------------------------------------------- Gaussian sketch
+//
+// Philox4x32-10 (Salmon et al., SC'11) keyed by (seed, stream), counter =
+// element index; Box-Muller turns two 32-bit words into a standard normal.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__global__ void k_gaussian(const SketchTask *__restrict__ tasks) {
+  const SketchTask tk = tasks[blockIdx.y];
+  const int64_t total = (int64_t)tk.rows * tk.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)(e >> 32), (uint32_t)tk.stream,
+                     (uint32_t)(tk.stream >> 32)};
+    philox10(c, (uint32_t)tk.seed, (uint32_t)(tk.seed >> 32));
+    const double u1 = ((double)c[0] + 1.0) * 0x1p-32;  // (0, 1]
+    const double u2 = (double)c[1] * 0x1p-32;
+    const double r = sqrt(-2.0 * log(u1));
+    const int64_t row = e % tk.rows, col = e / tk.rows;
+    tk.out[col * tk.ld + row] = r * cospi(2.0 * u2);
+  }
+}
+
+int launch_gaussian(const SketchTask *d_tasks, int ntask, hipStream_t st) {
+  if (ntask <= 0) return 0;
+  hipLaunchKernelGGL(k_gaussian, dim3(64, ntask), dim3(256), 0, st, d_tasks);
+  return check_launch("gaussian");
+}
+
+// ------------------------------------------------------------ data movement
+
+// dst (rows x cols, ldd) = src (rows x cols, lds) with src columns picked by
+// idx (nullable: identity) and optionally the lower triangle only (upper 0).
+__global__ void k_copy_cols(const CopyTask *__restrict__ tasks) {
+  const CopyTask tk = tasks[blockIdx.y];
+  const int64_t total = (int64_t)tk.rows * tk.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % tk.rows), c = (int)(e / tk.rows);
+    const int sc = tk.idx ? tk.idx[c] : c;
+    double v = tk.src[(int64_t)sc * tk.lds + r];
+    if (tk.mode == COPY_UPPER_TRI && r > c) v = 0.0;
+    if (tk.mode == COPY_LOWER_TRI && r < c) v = 0.0;
+    if (tk.mode == COPY_ZERO) v = 0.0;
+    if (tk.mode == COPY_IDENTITY) v = (r == c) ? 1.0 : 0.0;
+    tk.dst[(int64_t)c * tk.ldd + r] = v;
+  }
+}
+
+int launch_copy_cols(const CopyTask *d_tasks, int ntask, hipStream_t st) {
+  if (ntask <= 0) return 0;
+  hipLaunchKernelGGL(k_copy_cols, dim3(64, ntask), dim3(256), 0, st, d_tasks);
+  return check_launch("copy_cols");
+}
+
+}  // namespace mvg
