@@ -111,8 +111,8 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * d_z: 2*n_loc FP64 in Representation I.  Host outputs (n_theta each):
  * h_loglik, h_logdet, h_quad (nullable), h_status (nullable: 0 or the pivot
  * index; a failing theta gets h_loglik = -inf).  n_theta > 1 evaluates all
- * theta in one batched launch sequence (bitwise equal to n_theta separate
- * calls).  keep (nullable, n_theta == 1 only) receives a resident factor for
+ * theta on the same arena (large problems) or in one persistent launch
+ * (2 n_loc <= MVG_SMALL_MAX_ROWS, FP64, see loglik_many).  keep (nullable, n_theta == 1 only) receives a resident factor for
  * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*.
  *
  * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16; not in the paper): Sigma is
@@ -131,6 +131,29 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
            const mvg_theta *th, int n_theta, const mvg_opts *o,
            double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
            mvg_factor **keep, void *hip_stream);
+
+/* One task of loglik_many: a dataset (device pointers, caller-owned) and a
+ * theta. */
+typedef struct {
+    const double *x, *y, *z;  /* n_loc locations, 2 n_loc values (Representation I) */
+    int64_t n_loc;
+    mvg_theta theta;
+} mvg_task;
+
+/* Largest 2 n_loc of a loglik_many task. */
+#define MVG_SMALL_MAX_ROWS 1024
+
+/* Eq. (1) for many small problems (2 n_loc <= MVG_SMALL_MAX_ROWS each,
+ * datasets and theta may all differ) in one persistent launch: a fixed grid
+ * of workgroups takes tasks from a device queue, one workgroup per task
+ * (generation, FP64 Cholesky, solve, log-determinant).  A task's result does
+ * not depend on the other tasks of the batch (bitwise).  loglik with
+ * n_theta > 1, FP64 and 2 n_loc <= MVG_SMALL_MAX_ROWS (and no keep) takes
+ * this path.  Outputs as for loglik (host, n_tasks each; h_logdet, h_quad,
+ * h_status nullable).  Returns 0, -1..-3 for bad arguments, -(100 + i) for
+ * task i with an invalid theta or size, MVG_ERR_*. */
+int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *h_logdet,
+                double *h_quad, int64_t *h_status, void *hip_stream);
 
 /* TLR compression (Section 5.3) of the off-diagonal tiles of Sigma(theta) by
  * randomized SVD with absolute truncation s_i > tlr_acc; tiles needing a rank
@@ -181,6 +204,53 @@ const double *mvg_factor_w(const mvg_factor *F);
 
 void mvg_mat_destroy(mvg_mat *A);
 void mvg_factor_destroy(mvg_factor *F);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A request server over registered datasets (not in the paper): likelihood
+ * and cokriging requests of uneven size are admitted by HBM footprint
+ * (mvg_footprint) against a byte budget and run concurrently on n_workers
+ * streams; small FP64 likelihoods waiting together are evaluated in one
+ * persistent launch (loglik_many); factors stay resident in an LRU cache
+ * keyed by (dataset, theta) and serve later cokriging requests (a miss
+ * factors first).  Results (mvg_result) carry the server-clock arrival,
+ * start and end times.  Datasets and cokriging buffers are caller-owned
+ * device memory that must outlive the requests using them.  Calls are
+ * thread-safe. */
+enum { MVG_REQ_LOGLIK = 0, MVG_REQ_COKRIGE = 1 };
+
+typedef struct {
+    int64_t id;
+    int kind;            /* MVG_REQ_* */
+    int status;          /* 0, the pivot index, or an MVG_ERR_* / argument code */
+    int64_t n_loc;
+    double loglik, logdet, quad;   /* likelihood requests and cokriging misses */
+    double t_arrive, t_start, t_end;  /* seconds on the server clock */
+    int batch;           /* requests evaluated in the same launch */
+    int cache_hit;       /* cokriging: 1 if the factor was resident */
+    int precision;
+} mvg_result;
+
+typedef struct mvg_server mvg_server;
+
+/* NULL on bad arguments (budget 0, n_workers outside 1..32). */
+mvg_server *mvg_server_create(size_t hbm_budget, int n_workers, const mvg_opts *o);
+/* Returns the dataset id (>= 0) or -1..-3. */
+int mvg_server_add_dataset(mvg_server *S, const double *d_x, const double *d_y,
+                           const double *d_z, int64_t n_loc);
+/* Queues a request; t_arrive < 0 means now.  cokriging: m targets d_x0,
+ * d_y0, predictions into d_zhat (2m).  Returns the request id or -1..-4. */
+int64_t mvg_server_submit(mvg_server *S, int kind, int dataset, const mvg_theta *th,
+                          const double *d_x0, const double *d_y0, int64_t m, double *d_zhat,
+                          double t_arrive);
+/* Moves up to max finished results into out, waiting up to wait_ms for the
+ * first one; returns their number. */
+int mvg_server_poll(mvg_server *S, mvg_result *out, int max, int wait_ms);
+double mvg_server_clock(const mvg_server *S);
+int mvg_server_stats(mvg_server *S, int64_t *hits, int64_t *misses, int64_t *batches,
+                     size_t *cached_bytes);
+/* Finishes the queued requests, then frees the server and its cache. */
+void mvg_server_destroy(mvg_server *S);
 
 /* Diagnostics: timing of kernel launches with HIP events recorded on the
  * stream each launch is enqueued on.  mvg_prof_enable(1) clears the records

@@ -10,6 +10,6 @@ the built library or a GPU every call raises.
 from ._lib import (  # noqa: F401
     MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR,
     Opts, Theta, Mat, Factor, MvgError,
-    library_path, morton_order, cov_generate, potrf_tiled, loglik, tlr_compress,
+    library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many, tlr_compress,
     cokrige_predict, mvg_footprint, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
 )

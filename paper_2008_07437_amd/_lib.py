@@ -84,6 +84,7 @@ def _load():
         "mvg_prof_enable": (c_int, [c_int]),
         "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
         "mvg_ir_stats": (c_int, [c_int, P, P, P]),
+        "loglik_many": (c_int, [P, c_int, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -264,6 +265,32 @@ def loglik(x, y, z, thetas, opts=None, keep=False, stream=None):
     if keep:
         return res, (Factor(fh.value) if fh.value else None)
     return res
+
+
+class Task(ctypes.Structure):
+    _fields_ = [("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("n_loc", c_int64),
+                ("theta", Theta)]
+
+
+SMALL_MAX_ROWS = 1024
+
+
+def loglik_many(tasks, stream=None):
+    """Eq. (1) for many small problems in one persistent launch.  tasks: list
+    of (x, y, z, theta) with device float64 tensors (2 n <= 1024).  Returns a
+    dict of numpy arrays as loglik does."""
+    k = len(tasks)
+    arr = (Task * k)()
+    for i, (x, y, z, th) in enumerate(tasks):
+        arr[i] = Task(_dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"), x.numel(),
+                      Theta.of(th))
+    ll, ld, q = np.zeros(k), np.zeros(k), np.zeros(k)
+    st = np.zeros(k, dtype=np.int64)
+    _check("loglik_many", _load().loglik_many(arr, k, ll.ctypes.data_as(c_void_p),
+                                              ld.ctypes.data_as(c_void_p),
+                                              q.ctypes.data_as(c_void_p),
+                                              st.ctypes.data_as(c_void_p), _stream(stream)))
+    return {"loglik": ll, "logdet": ld, "quad": q, "status": st}
 
 
 def tlr_compress(x, y, theta, opts=None, stream=None):

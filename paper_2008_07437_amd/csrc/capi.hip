@@ -687,6 +687,76 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
   return 0;
 }
 
+static int run_small(const std::vector<SmallTask> &tasks, int64_t nmax, double *h_loglik,
+                     double *h_logdet, double *h_quad, int64_t *h_status, hipStream_t st) {
+  const int nt = (int)tasks.size();
+  const int G = small_batch_workgroups(nt);
+  const size_t wsd = small_workspace_doubles(nmax) * (size_t)G;
+  char *buf = nullptr;
+  const size_t tb = sizeof(SmallTask) * nt, ob = sizeof(double) * 4 * nt;
+  const size_t bytes = tb + ob + sizeof(double) * wsd + 256;
+  if (hipMallocAsync((void **)&buf, bytes, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("batched likelihood workspace of %.2f GB failed", bytes / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  SmallTask *d_tasks = (SmallTask *)buf;
+  double *d_out = (double *)(buf + (tb + 255) / 256 * 256);
+  int *d_counter = (int *)(d_out + 4 * nt);
+  double *d_ws = (double *)((char *)d_counter + 256);
+  hipMemcpyAsync(d_tasks, tasks.data(), tb, hipMemcpyHostToDevice, st);
+  int hp = prof_begin(MVG_PROF_POTRF, st, 0.0, 0.0);
+  int rc = launch_small_loglik(d_tasks, nt, nmax, d_counter, d_ws, d_out, st);
+  prof_end(hp, st);
+  std::vector<double> out(4 * nt);
+  if (!rc) hipMemcpyAsync(out.data(), d_out, ob, hipMemcpyDeviceToHost, st);
+  hipFreeAsync(buf, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    set_error("batched likelihood failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = MVG_ERR_LAUNCH;
+  }
+  if (rc) return rc;
+  for (int i = 0; i < nt; ++i) {
+    h_loglik[i] = out[4 * i];
+    if (h_logdet) h_logdet[i] = out[4 * i + 1];
+    if (h_quad) h_quad[i] = out[4 * i + 2];
+    if (h_status) h_status[i] = (int64_t)out[4 * i + 3];
+  }
+  return 0;
+}
+
+static SmallTask small_task(const double *x, const double *y, const double *z, int64_t n,
+                            const mvg_theta &th) {
+  SmallTask t{};
+  t.x = x;
+  t.y = y;
+  t.z = z;
+  t.n = n;
+  matern_setup(&th, &t.P);
+  t.t0 = 0x1p-40 * th.sigma11_sq;
+  t.t1 = 0x1p-40 * th.sigma22_sq;
+  return t;
+}
+
+int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *h_logdet,
+                double *h_quad, int64_t *h_status, void *hip_stream) {
+  if (!h_tasks) return -1;
+  if (n_tasks < 1) return -2;
+  if (!h_loglik) return -3;
+  std::vector<SmallTask> tasks;
+  int64_t nmax = 1;
+  for (int i = 0; i < n_tasks; ++i) {
+    const mvg_task &t = h_tasks[i];
+    MaternArgs tmp;
+    if (!t.x || !t.y || !t.z || t.n_loc < 1 || 2 * t.n_loc > SMALL_MAX ||
+        matern_setup(&t.theta, &tmp))
+      return -(100 + i);
+    tasks.push_back(small_task(t.x, t.y, t.z, t.n_loc, t.theta));
+    nmax = std::max(nmax, t.n_loc);
+  }
+  return run_small(tasks, nmax, h_loglik, h_logdet, h_quad, h_status, (hipStream_t)hip_stream);
+}
+
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o, double *h_loglik,
            double *h_logdet, double *h_quad, int64_t *h_status, mvg_factor **keep,
@@ -706,6 +776,11 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
     if (matern_setup(&th[i], &tmp)) return -5;
   }
   hipStream_t st = (hipStream_t)hip_stream;
+  if (d.precision == MVG_FP64 && n_theta > 1 && 2 * n_loc <= SMALL_MAX && !keep) {
+    std::vector<SmallTask> tasks;
+    for (int i = 0; i < n_theta; ++i) tasks.push_back(small_task(d_x, d_y, d_z, n_loc, th[i]));
+    return run_small(tasks, n_loc, h_loglik, h_logdet, h_quad, h_status, st);
+  }
   if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16)
     return loglik_mixed(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
                         h_status, keep, st);

@@ -12,7 +12,7 @@
 // table held in LDS.  Half-integer orders 1/2, 3/2, 5/2 use their closed forms.
 #include <cmath>
 
-#include "mvgeo_internal.h"
+#include "matern_dev.h"
 
 namespace mvg {
 
@@ -45,23 +45,7 @@ int matern_setup(const mvg_theta *th, MaternArgs *P) {
 
 __global__ void k_quad_table(MaternArgs P, double *__restrict__ q) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= QN) return;
-  int j = -1;
-  for (int l = 0; l < QLEV; ++l)
-    if (k >= qlev_off(l) && k < qlev_off(l) + qlev_cnt(l)) j = l;
-  double cm1 = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  if (j >= 0) {
-    const double t = (double)(k - qlev_off(j)) * qlev_h(j);
-    const double s = sinh(0.5 * t);
-    cm1 = 2.0 * s * s;  // cosh t - 1 without cancellation
-    c0 = cosh(P.nu[0] * t);
-    c1 = cosh(P.nu[1] * t);
-    c2 = cosh(P.nu[2] * t);
-  }
-  q[k] = cm1;
-  q[QN + k] = c0;
-  q[2 * QN + k] = c1;
-  q[3 * QN + k] = c2;
+  if (k < QN) quad_entry(k, P, q);
 }
 
 int launch_quad_table(const MaternArgs &P, double *d_qtab, hipStream_t st) {
@@ -69,62 +53,6 @@ int launch_quad_table(const MaternArgs &P, double *d_qtab, hipStream_t st) {
   return check_launch("quad_table");
 }
 
-// Normalised Matern M(x; nu_o) for the three orders, x > 0.  sq: LDS table.
-__device__ __forceinline__ void matern3(double x, const MaternArgs &P,
-                                        const double *__restrict__ sq, double M[3]) {
-  if (x > qlev_xmax(QLEV - 1)) {
-    M[0] = M[1] = M[2] = 0.0;
-    return;
-  }
-  const double ex = exp(-x);
-  double s0 = 0.5, s1 = 0.5, s2 = 0.5, logh = 0.0;
-  if (P.any_quad) {
-    const int j = x <= qlev_xmax(0) ? 0 : x <= qlev_xmax(1) ? 1 : x <= qlev_xmax(2) ? 2
-                : x <= qlev_xmax(3) ? 3 : 4;
-    const int off = qlev_off(j), cnt = qlev_cnt(j);
-    logh = log(qlev_h(j));
-    for (int k = 1; k < cnt; ++k) {
-      const double e = exp(-x * sq[off + k]);
-      const double t0 = e * sq[QN + off + k];
-      const double t1 = e * sq[2 * QN + off + k];
-      const double t2 = e * sq[3 * QN + off + k];
-      s0 += t0;
-      s1 += t1;
-      s2 += t2;
-      if (t0 <= 1e-17 * s0 && t1 <= 1e-17 * s1 && t2 <= 1e-17 * s2) break;
-    }
-  }
-  const double lx = log(x);
-  const double s[3] = {s0, s1, s2};
-#pragma unroll
-  for (int o = 0; o < 3; ++o) {
-    switch (P.closed[o]) {
-      case 1: M[o] = ex; break;
-      case 2: M[o] = (1.0 + x) * ex; break;
-      case 3: M[o] = (1.0 + x + x * x * (1.0 / 3.0)) * ex; break;
-      default: M[o] = exp(P.nu[o] * lx - x + P.lnorm[o] + logh) * s[o]; break;
-    }
-  }
-}
-
-// 2x2 block C(||s_l - s_r||) of Representation I: c[0]=C11, c[1]=C22, c[2]=C12.
-__device__ __forceinline__ void cross_cov_block(double xl, double yl, double xr, double yr,
-                                                const MaternArgs &P, const double *sq,
-                                                double c[3]) {
-  const double dx = xl - xr, dy = yl - yr;
-  const double h = sqrt(dx * dx + dy * dy);
-  if (h == 0.0) {
-    c[0] = P.coef[0];
-    c[1] = P.coef[1];
-    c[2] = P.coef[2];
-    return;
-  }
-  double M[3];
-  matern3(h / P.a, P, sq, M);
-  c[0] = P.coef[0] * M[0];
-  c[1] = P.coef[1] * M[1];
-  c[2] = P.coef[2] * M[2];
-}
 
 __device__ __forceinline__ void load_qtab(const double *__restrict__ q, double *sq) {
   for (int i = threadIdx.x; i < 4 * QN; i += blockDim.x) sq[i] = q[i];

@@ -162,6 +162,19 @@ int morton_sort(const double *d_x, const double *d_y, int64_t n, int64_t *d_perm
                 double *d_ys, hipStream_t st);
 int launch_trmv(const mvg_mat *L, const double *d_eps, double *d_z, hipStream_t st);
 
+// many small likelihoods in one persistent launch (one workgroup per task)
+constexpr int SMALL_MAX = 1024;  // 2n bound of a task
+struct SmallTask {
+  const double *x, *y, *z;  // device, n locations, 2n values
+  int64_t n;
+  MaternArgs P;
+  double t0, t1;            // pivot tolerances (2^-40 sigma_ii^2)
+};
+int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *d_counter,
+                        double *d_ws, double *d_out, hipStream_t st);  // out: 4 per task
+size_t small_workspace_doubles(int64_t nmax);
+int small_batch_workgroups(int ntask);
+
 // permanent second stream for look-ahead (default priority)
 hipStream_t side_stream();
 

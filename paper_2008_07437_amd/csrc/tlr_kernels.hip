@@ -142,6 +142,33 @@ int64_t gemm_blocks(const GemmTask &t) {
 // are written there (m x n, ldq).  One workgroup per matrix; column c of the
 // trailing update belongs to wave c % QW throughout.
 constexpr int QW = 8;  // waves per QR workgroup
+constexpr int QE = QR_MAXM / 64;  // column elements per lane
+
+// col[j:m] <- (I - tau v v^T) col[j:m] by one wave: the lane's elements are
+// loaded together into registers (independent loads in flight), then the
+// inner product, the wave reduction and the update.
+__device__ __forceinline__ void reflect_col(double *col, const double *v, int j, int m, double tau,
+                                            int lane) {
+  double x[QE];
+#pragma unroll
+  for (int e = 0; e < QE; ++e) {
+    const int i = j + lane + 64 * e;
+    x[e] = i < m ? col[i] : 0.0;
+  }
+  double w = 0.0;
+#pragma unroll
+  for (int e = 0; e < QE; ++e) {
+    const int i = j + lane + 64 * e;
+    if (i < m) w += v[i] * x[e];
+  }
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+  const double tw = tau * w;
+#pragma unroll
+  for (int e = 0; e < QE; ++e) {
+    const int i = j + lane + 64 * e;
+    if (i < m) col[i] = x[e] - tw * v[i];
+  }
+}
 
 __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks) {
   __shared__ double v[QR_MAXM];
@@ -181,14 +208,8 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
     for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = v[i];
     if (tid == 0) aj[j] = beta;
     if (tau != 0.0) {
-      for (int c = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c < n; c += QW) {
-        double *ac = A + (int64_t)c * lda;
-        double w = 0.0;
-        for (int i = j + lane; i < m; i += 64) w += v[i] * ac[i];
-        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-        const double tw = tau * w;
-        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * v[i];
-      }
+      for (int c = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c < n; c += QW)
+        reflect_col(A + (int64_t)c * lda, v, j, m, tau, lane);
     }
     __syncthreads();
   }
@@ -207,14 +228,8 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
     if (tid == 0) v[j] = 1.0;
     __syncthreads();
     if (tau != 0.0) {
-      for (int c = j + (((wave - j) % QW + QW) % QW); c < n; c += QW) {
-        double *qc = Q + (int64_t)c * ldq;
-        double w = 0.0;
-        for (int i = j + lane; i < m; i += 64) w += v[i] * qc[i];
-        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-        const double tw = tau * w;
-        for (int i = j + lane; i < m; i += 64) qc[i] -= tw * v[i];
-      }
+      for (int c = j + (((wave - j) % QW + QW) % QW); c < n; c += QW)
+        reflect_col(Q + (int64_t)c * ldq, v, j, m, tau, lane);
     }
     __syncthreads();
   }
@@ -236,17 +251,45 @@ int launch_qr(const QrTask *d_tasks, int ntask, hipStream_t st) {
 // rounding noise); the sweeps stop after one without a rotation.
 // sig[i] = |column i of R J|.  Matrices with n <= JACOBI_LDS_N are worked on
 // in LDS and written back at the end.
-constexpr int JACOBI_LDS_N = 80;
+constexpr int JACOBI_LDS_N = 128;
 constexpr int JW = 8;  // waves per workgroup
 
+template <int E>  // n <= 64 E
+__device__ __forceinline__ void rotate_cols(double *p, double *q, int n, int lane, double cs,
+                                            double sn) {
+  double xp[E], xq[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    xp[e] = i < n ? p[i] : 0.0;
+    xq[e] = i < n ? q[i] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    if (i < n) {
+      p[i] = cs * xp[e] - sn * xq[e];
+      q[i] = sn * xp[e] + cs * xq[e];
+    }
+  }
+}
+
+template <int E>
 __device__ __forceinline__ void jacobi_pair(double *rp, double *rq, double *jp, double *jq, int n,
                                             int lane, double tol, int &any) {
+  double xp[E], xq[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    xp[e] = i < n ? rp[i] : 0.0;
+    xq[e] = i < n ? rq[i] : 0.0;
+  }
   double a = 0.0, b = 0.0, g = 0.0;
-  for (int i = lane; i < n; i += 64) {
-    const double x = rp[i], y = rq[i];
-    a += x * x;
-    b += y * y;
-    g += x * y;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    a += xp[e] * xp[e];
+    b += xq[e] * xq[e];
+    g += xp[e] * xq[e];
   }
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_xor(a, o);
@@ -258,38 +301,24 @@ __device__ __forceinline__ void jacobi_pair(double *rp, double *rq, double *jp, 
   const double zeta = (b - a) / (2.0 * g);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-  for (int i = lane; i < n; i += 64) {
-    const double x = rp[i], y = rq[i];
-    rp[i] = cs * x - sn * y;
-    rq[i] = sn * x + cs * y;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane + 64 * e;
+    if (i < n) {
+      rp[i] = cs * xp[e] - sn * xq[e];
+      rq[i] = sn * xp[e] + cs * xq[e];
+    }
   }
-  for (int i = lane; i < n; i += 64) {
-    const double x = jp[i], y = jq[i];
-    jp[i] = cs * x - sn * y;
-    jq[i] = sn * x + cs * y;
-  }
+  rotate_cols<E>(jp, jq, n, lane, cs, sn);
 }
 
-__global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ tasks) {
-  __shared__ int changed;
-  __shared__ double sR[JACOBI_LDS_N * JACOBI_LDS_N];
-  __shared__ double sJ[JACOBI_LDS_N * JACOBI_LDS_N];
-  const SvdTask tk = tasks[blockIdx.x];
-  const int n = tk.n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool in_lds = n <= JACOBI_LDS_N;
-  double *R = in_lds ? sR : tk.R;
-  double *J = in_lds ? sJ : tk.J;
-  const int ldr = in_lds ? n : tk.ldr, ldj = in_lds ? n : tk.ldj;
-  if (in_lds)
-    for (int e = tid; e < n * n; e += 64 * JW) sR[e] = tk.R[(int64_t)(e / n) * tk.ldr + e % n];
-  for (int c = wave; c < n; c += JW)
-    for (int i = lane; i < n; i += 64) J[(int64_t)c * ldj + i] = (i == c) ? 1.0 : 0.0;
-  __syncthreads();
+template <int E>
+__device__ void jacobi_sweeps(double *R, int ldr, double *J, int ldj, int n, int tid, int lane,
+                              int wave, int *changed) {
   const int np = n + (n & 1);  // players; an odd n adds an idle one
   const double tol = (double)(n > 1 ? n : 1) * 0x1p-52;
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) changed = 0;
+    if (tid == 0) *changed = 0;
     __syncthreads();
     int any = 0;
     for (int round = 0; round < np - 1; ++round) {
@@ -304,14 +333,42 @@ __global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ 
         }
         if (p > q) { const int t = p; p = q; q = t; }
         if (q >= n) continue;
-        jacobi_pair(R + (int64_t)p * ldr, R + (int64_t)q * ldr, J + (int64_t)p * ldj,
-                    J + (int64_t)q * ldj, n, lane, tol, any);
+        jacobi_pair<E>(R + (int64_t)p * ldr, R + (int64_t)q * ldr, J + (int64_t)p * ldj,
+                       J + (int64_t)q * ldj, n, lane, tol, any);
       }
       __syncthreads();
     }
-    if (any && lane == 0) atomicOr(&changed, 1);
+    if (any && lane == 0) atomicOr(changed, 1);
     __syncthreads();
-    if (!changed) break;
+    if (!*changed) break;
+  }
+}
+
+__global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ tasks) {
+  __shared__ int changed;
+  __shared__ double sR[JACOBI_LDS_N * JACOBI_LDS_N];
+  const SvdTask tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool in_lds = n <= JACOBI_LDS_N;
+  double *R = in_lds ? sR : tk.R;
+  const int ldr = in_lds ? n : tk.ldr;
+  double *J = tk.J;
+  const int ldj = tk.ldj;
+  if (in_lds)
+    for (int e = tid; e < n * n; e += 64 * JW) sR[e] = tk.R[(int64_t)(e / n) * tk.ldr + e % n];
+  for (int c = wave; c < n; c += JW)
+    for (int i = lane; i < n; i += 64) J[(int64_t)c * ldj + i] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
+  switch ((n + 63) / 64) {
+    case 1: jacobi_sweeps<1>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 2: jacobi_sweeps<2>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 3: jacobi_sweeps<3>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 4: jacobi_sweeps<4>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 5: jacobi_sweeps<5>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 6: jacobi_sweeps<6>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    case 7: jacobi_sweeps<7>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
+    default: jacobi_sweeps<8>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
   }
   for (int c = wave; c < n; c += JW) {
     const double *rc = R + (int64_t)c * ldr;
@@ -320,12 +377,10 @@ __global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ 
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) tk.sig[c] = sqrt(s);
   }
-  if (in_lds)
-    for (int e = tid; e < n * n; e += 64 * JW) {
-      const int c = e / n, i = e % n;
-      tk.R[(int64_t)c * tk.ldr + i] = sR[e];
-      tk.J[(int64_t)c * tk.ldj + i] = sJ[e];
-    }
+  if (in_lds) {
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 64 * JW) tk.R[(int64_t)(e / n) * tk.ldr + e % n] = sR[e];
+  }
 }
 
 int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st) {
