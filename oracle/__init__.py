@@ -258,11 +258,13 @@ def morton_order(x, y) -> np.ndarray:
 
 # -------------------------------------------------------------- approximations
 
-def tlr_truncate_tiles(S: np.ndarray, nb: int, acc: float, max_rank: int):
+def tlr_truncate_tiles(S: np.ndarray, nb: int, acc: float, max_rank: int, rule: str = "2norm"):
     """Section 5.3 TLR compression by per-tile SVD: every off-diagonal tile of
     the (padded) matrix keeps the singular triplets with s_i > acc (absolute
-    2-norm rule); a tile whose rank would exceed max_rank stays dense.
-    Returns (S_tilde, ranks) with ranks[I, J] (-1 for dense tiles)."""
+    2-norm rule), or, with rule="frobenius", the fewest leading triplets whose
+    discarded tail has Frobenius norm <= acc; a tile whose rank would exceed
+    max_rank stays dense.  Returns (S_tilde, ranks) with ranks[I, J] (-1 for
+    dense tiles)."""
     N = S.shape[0]
     T = (N + nb - 1) // nb
     St = np.array(S, copy=True)
@@ -272,7 +274,11 @@ def tlr_truncate_tiles(S: np.ndarray, nb: int, acc: float, max_rank: int):
             r0, r1 = I * nb, min(N, (I + 1) * nb)
             c0, c1 = J * nb, min(N, (J + 1) * nb)
             U, s, Vt = np.linalg.svd(S[r0:r1, c0:c1], full_matrices=False)
-            k = int(np.sum(s > acc))
+            if rule == "2norm":
+                k = int(np.sum(s > acc))
+            else:
+                tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]  # tail[i] = ||s[i:]||
+                k = int(np.sum(tail > acc))
             if k > max_rank:
                 continue
             ranks[I, J] = k

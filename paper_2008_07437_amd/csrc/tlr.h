@@ -24,8 +24,11 @@ struct QrTask {
   double *A;    // m x n, overwritten by R (upper) and the reflectors (below)
   int m, n, lda;
   double *tau;  // n (nullable)
-  double *Q;    // m x n explicit Q (nullable)
+  double *Q;    // m x n (or m x rank) explicit Q (nullable)
   int ldq;
+  int *piv;     // nullable: column pivoting, column order out (n)
+  double tol;   // pivoting: stop when the remaining Frobenius norm <= tol
+  int *rank;    // pivoting: reflectors applied (out)
 };
 
 constexpr int JACOBI_MAX_SWEEPS = 40;

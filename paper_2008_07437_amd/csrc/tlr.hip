@@ -1,10 +1,10 @@
 // Tile-low-rank covariance and Cholesky factorisation (Section 5.3).
 //
 // Compression: every off-diagonal tile of Sigma is generated densely and
-// compressed by a randomized SVD (Gaussian sketch, Householder QR of the
-// sketch, projection, QR of the projection, one-sided Jacobi SVD of the
-// small triangular factor), truncated at singular values <= acc (absolute
-// 2-norm rule); a tile whose rank would exceed max_rank stays dense.  The
+// compressed by a randomized range finder (Gaussian sketch, Householder QR
+// of the sketch, projection) followed by a column-pivoted QR of the
+// projection stopped when the Frobenius norm of the rest is <= acc; a tile
+// whose rank would exceed max_rank stays dense.  The
 // sketch width starts from the rank of the previous tile at the same
 // distance from the diagonal and doubles until the kept rank is at least
 // OVERSAMPLE below it.
@@ -157,19 +157,28 @@ struct CompressJob {
 // Compresses the jobs' tiles into store D; V is replaced by W V when W
 // (nb x nb, ldw, lower triangular) is given.  sguess[d] (d = I - J) is
 // updated with the ranks found.
+//
+// Per tile C (nb x nb): Y = C Omega (Gaussian, nb x s); Y = Q R (Householder);
+// B^T = C^T Q; B^T P = Q' R' by column-pivoted Householder QR stopped at the
+// first k with ||R'_22||_F <= acc.  Then C ~= Q B ~= (Q P R'_k^T) Q'_k^T, i.e.
+// U = (Q P) R'_k^T and V = Q'_k, with ||C - U V^T||_2 <= ||C - Q B||_2 + acc
+// (the Frobenius-norm tail rule; it keeps at least the ranks of the 2-norm
+// rule s_i > acc).  A rank above s - OVERSAMPLE (the sketch may have missed
+// part of the range) is retried with a wider sketch.
 static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
                          uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
                          hipStream_t st) {
   const int nb = D.nb;
   const int T = D.T;
+  const int smax = std::min(nb, QR_MAXN);
   while (!jobs.empty()) {
-    // scratch per job: Om | Y | Z (nb x s each), R | J (s x s), sig | tau (s)
+    // scratch per job: Om | Y | Z | Qp (nb x s each), R (s x s), piv (s) + rank
     std::vector<size_t> base(jobs.size());
     size_t tot = 0;
     for (size_t b = 0; b < jobs.size(); ++b) {
       const size_t s = jobs[b].s;
       base[b] = tot;
-      tot += 3 * (size_t)nb * s + 4 * s * s + 2 * s;
+      tot += 4 * (size_t)nb * s + s * s + s + 2;
     }
     double *ws = nullptr;
     if (hipMallocAsync((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
@@ -180,12 +189,10 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     auto Om = [&](size_t b) { return ws + base[b]; };
     auto Yb = [&](size_t b) { return ws + base[b] + (size_t)nb * jobs[b].s; };
     auto Zb = [&](size_t b) { return ws + base[b] + 2 * (size_t)nb * jobs[b].s; };
-    auto Rb = [&](size_t b) { return ws + base[b] + 3 * (size_t)nb * jobs[b].s; };
-    auto Jb = [&](size_t b) { return Rb(b) + (size_t)jobs[b].s * jobs[b].s; };
-    auto Gj = [&](size_t b) { return Jb(b) + (size_t)jobs[b].s * jobs[b].s; };
-    auto Gr = [&](size_t b) { return Gj(b) + (size_t)jobs[b].s * jobs[b].s; };
-    auto Sg = [&](size_t b) { return Gr(b) + (size_t)jobs[b].s * jobs[b].s; };
-    auto Tau = [&](size_t b) { return Sg(b) + jobs[b].s; };
+    auto Qp = [&](size_t b) { return ws + base[b] + 3 * (size_t)nb * jobs[b].s; };
+    auto Rb = [&](size_t b) { return ws + base[b] + 4 * (size_t)nb * jobs[b].s; };
+    auto Pv = [&](size_t b) { return (int *)(Rb(b) + (size_t)jobs[b].s * jobs[b].s); };
+    auto Rk = [&](size_t b) { return (int *)(Rb(b) + (size_t)jobs[b].s * jobs[b].s + jobs[b].s); };
     HostLists L;
     int rc = 0;
     {
@@ -202,7 +209,7 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     if (!rc) {
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b)
-        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tau(b), Om(b), nb});
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, nullptr, Om(b), nb, nullptr, 0.0, nullptr});
       rc = run_list<QrTask, launch_qr>(q, L, st);  // Q -> Om
     }
     if (!rc) {
@@ -215,67 +222,38 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     if (!rc) {
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b)
-        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tau(b), Zb(b), nb});
-      rc = run_list<QrTask, launch_qr>(q, L, st);  // B^T = Q' R, Q' -> Z
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, nullptr, Zb(b), nb, Pv(b), acc, Rk(b)});
+      rc = run_list<QrTask, launch_qr>(q, L, st);  // B^T P = Q' R', Q'_k -> Z
     }
+    // ranks to the host
+    std::vector<int> ranks(jobs.size(), 0);
     if (!rc) {
-      std::vector<CopyTask> c;
-      std::vector<SvdTask> sv;
-      for (size_t b = 0; b < jobs.size(); ++b) {
-        const int s = jobs[b].s;
-        c.push_back(CopyTask{Yb(b), Rb(b), s, s, nb, s, nullptr, COPY_UPPER_TRI});
-        sv.push_back(SvdTask{Rb(b), s, s, Jb(b), s, Sg(b)});
-      }
-      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
-      if (!rc) rc = run_list<SvdTask, launch_jacobi>(sv, L, st);  // R J, J, sigma
-    }
-    // singular values to the host: ranks and retries
-    std::vector<double> sig;
-    if (!rc) {
-      size_t ns = 0;
-      for (auto &j : jobs) ns += j.s;
-      sig.resize(ns);
-      size_t o = 0;
-      for (size_t b = 0; b < jobs.size(); ++b) {
-        hipMemcpyAsync(sig.data() + o, Sg(b), sizeof(double) * jobs[b].s, hipMemcpyDeviceToHost, st);
-        o += jobs[b].s;
-      }
+      for (size_t b = 0; b < jobs.size(); ++b)
+        hipMemcpyAsync(&ranks[b], Rk(b), sizeof(int), hipMemcpyDeviceToHost, st);
       if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("TLR: compression kernels failed: %s", hipGetErrorString(hipGetLastError()));
         rc = MVG_ERR_LAUNCH;
       }
     }
-    // per job: retry with a wider sketch, or final rank (dense past max_rank)
     enum { DONE = 0, RETRY = 1 };
     std::vector<int> status(jobs.size(), DONE);
     std::vector<CompressJob> retry;
-    std::vector<int> allidx;                 // kept columns, sorted by sigma, all jobs
-    std::vector<size_t> idx0(jobs.size(), 0);
-    const int smax = std::min(nb, QR_MAXN);
     if (!rc) {
-      size_t o = 0;
       for (size_t b = 0; b < jobs.size(); ++b) {
-        const int s = jobs[b].s;
-        const double *sg = sig.data() + o;
-        o += s;
-        std::vector<int> idx(s);
-        for (int i = 0; i < s; ++i) idx[i] = i;
-        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return sg[x] > sg[y]; });
-        int r = 0;
-        while (r < s && sg[idx[r]] > acc) ++r;
+        const int s = jobs[b].s, r = ranks[b];
         const int64_t t = jobs[b].t;
-        int64_t q = t;  // packed index -> (I, J)
+        int64_t q = t;  // packed index -> distance I - J
         int J = 0;
         while (q >= T - J) {
           q -= T - J;
           ++J;
         }
-        const int d = (int)q;  // I - J
+        const int d = (int)q;
         if (r > max_rank) {
           D.dense[t] = 1;
           D.rank[t] = -1;
           sguess[d] = r;
-        } else if (r > s - OVERSAMPLE && s < smax) {  // the sketch may have missed range
+        } else if (r > s - OVERSAMPLE && s < smax) {
           CompressJob j = jobs[b];
           j.s = std::min(smax, (std::max(2 * s, r + 2 * OVERSAMPLE) + 15) / 16 * 16);
           retry.push_back(j);
@@ -284,8 +262,6 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
           D.dense[t] = 0;
           D.rank[t] = r;
           sguess[d] = r;
-          idx0[b] = allidx.size();
-          allidx.insert(allidx.end(), idx.begin(), idx.begin() + r);
         }
       }
       // storage (the store may move: reserve everything before taking pointers)
@@ -297,13 +273,11 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
         if (r > 0) rc = store_reserve(D, 2 * (size_t)nb * r, st, &D.uoff[t]);
       }
     }
-    // U = Q J_keep, V = W Q' (R J)_keep, or the dense tile (U = tile, V = W or I)
+    // U = (Q P) R'_k^T, V = W Q'_k (or the dense tile: U = tile, V = W or I)
     if (!rc) {
-      const int *didx = allidx.empty() ? nullptr
-                                       : (const int *)L.stage(allidx.data(), sizeof(int) * allidx.size(), st, &rc);
       std::vector<CopyTask> c;
-      std::vector<GemmTask> g1, g2;
-      for (size_t b = 0; b < jobs.size() && !rc; ++b) {
+      std::vector<GemmTask> g;
+      for (size_t b = 0; b < jobs.size(); ++b) {
         if (status[b] != DONE) continue;
         const int64_t t = jobs[b].t;
         const int s = jobs[b].s;
@@ -320,19 +294,16 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
         const int r = D.rank[t];
         if (r == 0) continue;
         double *V = U + (int64_t)nb * r;
-        c.push_back(CopyTask{Jb(b), Gj(b), s, r, s, s, didx + idx0[b], COPY_PLAIN});
-        c.push_back(CopyTask{Rb(b), Gr(b), s, r, s, s, didx + idx0[b], COPY_PLAIN});
-        g1.push_back(gemm(Om(b), nb, 0, Gj(b), s, 0, U, nb, nb, r, s, 1.0, 0.0));
-        if (W) {
-          g1.push_back(gemm(Zb(b), nb, 0, Gr(b), s, 0, Yb(b), nb, nb, r, s, 1.0, 0.0));
-          g2.push_back(gemm(W, ldw, 0, Yb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
-        } else {
-          g1.push_back(gemm(Zb(b), nb, 0, Gr(b), s, 0, V, nb, nb, r, s, 1.0, 0.0));
-        }
+        c.push_back(CopyTask{Om(b), Qp(b), nb, s, nb, nb, Pv(b), COPY_PLAIN});      // Q P
+        c.push_back(CopyTask{Yb(b), Rb(b), r, s, nb, s, nullptr, COPY_UPPER_TRI});  // R'_k
+        g.push_back(gemm(Qp(b), nb, 0, Rb(b), s, 1, U, nb, nb, r, s, 1.0, 0.0));
+        if (W)
+          g.push_back(gemm(W, ldw, 0, Zb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
+        else
+          c.push_back(CopyTask{Zb(b), V, nb, r, nb, nb, nullptr, COPY_PLAIN});
       }
-      if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
-      if (!rc) rc = run_gemms(g1, L, st);
-      if (!rc) rc = run_gemms(g2, L, st);
+      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_gemms(g, L, st);
     }
     hipFreeAsync(ws, st);
     L.release(st);

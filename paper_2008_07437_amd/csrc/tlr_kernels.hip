@@ -146,9 +146,10 @@ constexpr int QE = QR_MAXM / 64;  // column elements per lane
 
 // col[j:m] <- (I - tau v v^T) col[j:m] by one wave: the lane's elements are
 // loaded together into registers (independent loads in flight), then the
-// inner product, the wave reduction and the update.
+// inner product, the wave reduction and the update.  With nrm, the squared
+// norm of the updated rows j+1..m-1 is written there (lane 0).
 __device__ __forceinline__ void reflect_col(double *col, const double *v, int j, int m, double tau,
-                                            int lane) {
+                                            int lane, double *nrm) {
   double x[QE];
 #pragma unroll
   for (int e = 0; e < QE; ++e) {
@@ -163,22 +164,104 @@ __device__ __forceinline__ void reflect_col(double *col, const double *v, int j,
   }
   for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
   const double tw = tau * w;
+  double ss = 0.0;
 #pragma unroll
   for (int e = 0; e < QE; ++e) {
     const int i = j + lane + 64 * e;
-    if (i < m) col[i] = x[e] - tw * v[i];
+    if (i < m) {
+      const double y = x[e] - tw * v[i];
+      col[i] = y;
+      if (i > j) ss += y * y;
+    }
+  }
+  if (nrm) {
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    if (lane == 0) *nrm = ss;
   }
 }
 
+// With tk.piv: column pivoting (largest remaining column norm first, ties to
+// the lower index) and early stop once the Frobenius norm of the remaining
+// block is <= tk.tol; *tk.rank receives the number of reflectors k, tk.piv
+// the column order, and only the first k columns of Q are formed.
 __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks) {
   __shared__ double v[QR_MAXM];
   __shared__ double s_tau[QR_MAXN];
+  __shared__ double s_nrm[QR_MAXN];
+  __shared__ int s_piv[QR_MAXN];
   __shared__ double red[QW];
+  __shared__ int s_arg;
+  __shared__ double s_tail;
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, n = tk.n, lda = tk.lda;
   double *A = tk.A;
+  const bool pivot = tk.piv != nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (pivot) {
+    for (int c = wave; c < n; c += QW) {
+      const double *ac = A + (int64_t)c * lda;
+      double ss = 0.0;
+      for (int i = lane; i < m; i += 64) ss += ac[i] * ac[i];
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      if (lane == 0) {
+        s_nrm[c] = ss;
+        s_piv[c] = c;
+      }
+    }
+    __syncthreads();
+  }
+  int kmax = n;
   for (int j = 0; j < n; ++j) {
+    if (pivot) {
+      if (wave == 0) {
+        double best = -1.0, tail = 0.0;
+        int bi = n;
+        for (int c = j + lane; c < n; c += 64) {
+          const double t = s_nrm[c];
+          tail += t;
+          if (t > best) {
+            best = t;
+            bi = c;
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          tail += __shfl_xor(tail, o);
+          const double ob = __shfl_xor(best, o);
+          const int oi = __shfl_xor(bi, o);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (lane == 0) {
+          s_arg = bi;
+          s_tail = tail;
+        }
+      }
+      __syncthreads();
+      if (s_tail <= tk.tol * tk.tol) {  // uniform
+        kmax = j;
+        break;
+      }
+      const int p = s_arg;
+      if (p != j) {
+        double *aj = A + (int64_t)j * lda, *ap = A + (int64_t)p * lda;
+        for (int i = tid; i < m; i += 64 * QW) {
+          const double t = aj[i];
+          aj[i] = ap[i];
+          ap[i] = t;
+        }
+        if (tid == 0) {
+          const double tn = s_nrm[j];
+          s_nrm[j] = s_nrm[p];
+          s_nrm[p] = tn;
+          const int ti = s_piv[j];
+          s_piv[j] = s_piv[p];
+          s_piv[p] = ti;
+        }
+      }
+      __syncthreads();
+    }
     double *aj = A + (int64_t)j * lda;
     double ss = 0.0;
     for (int i = j + 1 + tid; i < m; i += 64 * QW) ss += aj[i] * aj[i];
@@ -207,29 +290,33 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
     // store the reflector below the diagonal and beta on it
     for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = v[i];
     if (tid == 0) aj[j] = beta;
-    if (tau != 0.0) {
+    if (tau != 0.0 || pivot) {
       for (int c = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c < n; c += QW)
-        reflect_col(A + (int64_t)c * lda, v, j, m, tau, lane);
+        reflect_col(A + (int64_t)c * lda, v, j, m, tau, lane, pivot ? &s_nrm[c] : nullptr);
     }
     __syncthreads();
   }
   if (tk.tau)
-    for (int j = tid; j < n; j += 64 * QW) tk.tau[j] = s_tau[j];
+    for (int j = tid; j < kmax; j += 64 * QW) tk.tau[j] = s_tau[j];
+  if (pivot) {
+    for (int c = tid; c < n; c += 64 * QW) tk.piv[c] = s_piv[c];
+    if (tid == 0) *tk.rank = kmax;
+  }
   if (!tk.Q) return;
   double *Q = tk.Q;
   const int ldq = tk.ldq;
-  for (int c = wave; c < n; c += QW)
+  for (int c = wave; c < kmax; c += QW)
     for (int i = lane; i < m; i += 64) Q[(int64_t)c * ldq + i] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
+  for (int j = kmax - 1; j >= 0; --j) {
     const double tau = s_tau[j];
     const double *aj = A + (int64_t)j * lda;
     for (int i = j + 1 + tid; i < m; i += 64 * QW) v[i] = aj[i];
     if (tid == 0) v[j] = 1.0;
     __syncthreads();
     if (tau != 0.0) {
-      for (int c = j + (((wave - j) % QW + QW) % QW); c < n; c += QW)
-        reflect_col(Q + (int64_t)c * ldq, v, j, m, tau, lane);
+      for (int c = j + (((wave - j) % QW + QW) % QW); c < kmax; c += QW)
+        reflect_col(Q + (int64_t)c * ldq, v, j, m, tau, lane, nullptr);
     }
     __syncthreads();
   }

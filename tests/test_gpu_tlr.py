@@ -1,9 +1,10 @@
 """GPU checks of the tile-low-rank path (Section 5.3) against the FP64 oracle.
 
 Compression is checked tile by tile against the oracle's truncated SVD of the
-same tiles (ranks within a few: the randomized sketch and the exact SVD see
-the same singular values but may split near-threshold ones differently) and
-by the 2-norm of each tile's error (<= a small multiple of acc).  The
+same tiles under the same Frobenius tail rule (the GPU's column-pivoted QR is
+not the optimal truncation, so its rank may exceed the SVD's by a few; the
+sketch sees the same singular values) and by the 2-norm of each tile's error
+(<= a small multiple of acc).  The
 log-likelihood is checked against the exact oracle value (relative 1e-6 at
 acc <= 1e-7, the target for the TLR form) and against the oracle's likelihood
 of its own truncated matrix (the compression-only error)."""
@@ -54,13 +55,14 @@ def test_tlr_compress_tiles(lib, orc, acc):
     _say("tlr_compress n=%d nb=%d acc=%g" % (n, nb, acc))
     A, ranks = lib.tlr_compress(_dev(x), _dev(y), TH, {"nb": nb, "tlr_acc": acc})
     S = orc.cov_dense(x, y, TH)
-    _, oranks = orc.tlr_truncate_tiles(S, nb, acc, 300)
+    _, oranks = orc.tlr_truncate_tiles(S, nb, acc, 300, rule="frobenius")
     St = A.to_dense().cpu().numpy()
     T = ranks.shape[0]
     worst = 0.0
     for I in range(T):
         for J in range(I):
-            assert abs(int(ranks[I, J]) - int(oranks[I, J])) <= 3, (I, J, ranks[I, J], oranks[I, J])
+            o = int(oranks[I, J])
+            assert o - 1 <= int(ranks[I, J]) <= o + max(4, o // 8), (I, J, ranks[I, J], o)
             assert ranks[I, J] == ranks[J, I]
             d = St[I * nb:(I + 1) * nb, J * nb:(J + 1) * nb] - S[I * nb:(I + 1) * nb, J * nb:(J + 1) * nb]
             worst = max(worst, np.linalg.norm(d, 2))

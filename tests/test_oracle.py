@@ -380,3 +380,20 @@ def test_mixed_emulation_rounds_off_band_and_stays_close(orc, fmt, bound):
     assert np.max(np.abs(R - S)) > 0.0
     ld = 2 * np.sum(np.log(np.diag(L)[:180]))
     assert abs(ld - np.linalg.slogdet(S)[1]) <= 50 * bound * 180
+
+
+def test_tlr_frobenius_rule_keeps_more_and_bounds_tail(orc):
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y = synthetic.jittered_grid(150, 4)
+    p = orc.morton_order(x, y)
+    S = orc.cov_dense(x[p], y[p], th)
+    for acc in (1e-5, 1e-8):
+        S2, r2 = orc.tlr_truncate_tiles(S, 60, acc, 60)
+        Sf, rf = orc.tlr_truncate_tiles(S, 60, acc, 60, rule="frobenius")
+        low = np.tril_indices(r2.shape[0], -1)
+        assert np.all(rf[low] >= r2[low])
+        for I in range(r2.shape[0]):
+            for J in range(I):
+                blk = (slice(I * 60, (I + 1) * 60), slice(J * 60, (J + 1) * 60))
+                assert np.linalg.norm(Sf[blk] - S[blk]) <= acc * (1 + 1e-9)
+                assert np.linalg.norm(S2[blk] - S[blk], 2) <= acc * (1 + 1e-9)
