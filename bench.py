@@ -13,6 +13,8 @@ the stream each launch runs on, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -117,6 +119,180 @@ def run_variants(mvg, xs, ys, z, th, args, ref_loglik, reps=2):
     return out
 
 
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def run_tlr(args, mvg, dev, synthetic, torch):
+    """TLR likelihood on the N = 100,000 workload (200,000 x 200,000, tile
+    1200), beside one dense FP64 evaluation of the same inputs."""
+    n, nb = args.n, 1200
+    th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    z = dev(synthetic.normal_eps(2 * n, args.seed))
+    ref = None
+    dense = {}
+    if not args.no_dense_ref:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref = mvg.loglik(xs, ys, z, th, {"nb": 512})
+        torch.cuda.synchronize()
+        dense = {"evals_per_s": 1.0 / (time.perf_counter() - t0), "loglik": float(ref["loglik"][0])}
+    accs = [float(a) for a in args.accs.split(",")]
+    res = {}
+    for acc in accs:
+        o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300}
+        mvg.mvg_prof_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            r = mvg.loglik(xs, ys, z, th, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(1, args.steps)
+        pr = {k: mvg.mvg_prof_read(k) for k in ("gen", "potrf", "solve", "trailing")}
+        mvg.mvg_prof_enable(False)
+        rec = {"evals_per_s": 1.0 / dt, "s_per_eval": dt, "status": int(r["status"][0]),
+               "loglik": float(r["loglik"][0]),
+               "phases_ms_per_eval": {"compress": pr["gen"]["ms"] / max(1, args.steps),
+                                      "factor": pr["potrf"]["ms"] / max(1, args.steps),
+                                      "solve": pr["solve"]["ms"] / max(1, args.steps)},
+               "update_gemm_tflops": (pr["trailing"]["flops"] / (pr["trailing"]["ms"] * 1e-3) / 1e12
+                                      if pr["trailing"]["ms"] > 0 else None)}
+        if ref is not None:
+            rec["rel_dloglik_vs_fp64"] = abs(r["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0])
+        res["acc%g" % acc] = rec
+    _, ranks = mvg.tlr_compress(xs, ys, th, {"nb": nb, "tlr_acc": accs[0], "tlr_max_rank": 300})
+    T = ranks.shape[0]
+    low = ranks[np.tril_indices(T, -1)]
+    head = res["acc%g" % accs[0]]
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          head["evals_per_s"], "evals/s", max(1, args.steps), 0, 1e3 * head["s_per_eval"], "f64",
+          {"workload": "TLR bivariate Matern loglik, N=%d locations (%dx%d), tile %d, acc %s, "
+                       "max rank 300, theta=(1,1,%g,0.5,1,0.5)" % (n, 2 * n, 2 * n, nb, args.accs,
+                                                                   args.a),
+           "n_loc": n, "nb": nb, "precision": "tlr"},
+          tlr=res, dense_fp64=dense,
+          ranks={"acc": accs[0], "median_offset1": int(np.median(np.diag(ranks, -1))),
+                 "median_all": int(np.median(low[low >= 0])) if (low >= 0).any() else None,
+                 "dense_tiles": int((low < 0).sum()), "tiles": int(low.size)})
+
+
+def run_batched(args, mvg, dev, synthetic, torch):
+    """Many theta on the N = 400 workload (800 x 800) in one persistent launch."""
+    n = 400
+    th0 = synthetic.THETA_CFG0
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    z = dev(synthetic.normal_eps(2 * n, args.seed))
+    ths = synthetic.jittered_thetas(args.batch, args.seed + 1)
+    mvg.loglik(xs, ys, z, ths[:8], {"nb": 128})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = mvg.loglik(xs, ys, z, ths, {"nb": 128})
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the same evaluations one call at a time (tiled path), on a subset
+    k = min(32, args.batch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for t in ths[:k]:
+        mvg.loglik(xs, ys, z, t, {"nb": 128})
+    torch.cuda.synchronize()
+    single = k / (time.perf_counter() - t1)
+    simplex = synthetic.nelder_mead_simplex(th0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mvg.loglik(xs, ys, z, simplex, {"nb": 128})
+    torch.cuda.synchronize()
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          args.batch / dt, "evals/s", args.steps, 1, 1e3 * dt, "f64",
+          {"workload": "batched FP64 loglik, %d theta (+-20%% around (1,1,0.1,0.5,1,0.5)) on "
+                       "N=%d locations (%dx%d), one persistent launch" % (args.batch, n, 2 * n, 2 * n),
+           "n_loc": n, "batch": args.batch, "precision": "fp64"},
+          single_call_evals_per_s=single, speedup_vs_single_calls=(args.batch / dt) / single,
+          simplex7_ms=1e3 * (time.perf_counter() - t2), failed=int((r["status"] != 0).sum()))
+
+
+def serve_stream(args, mvg, dev, synthetic, torch, rate, nreq):
+    """One Poisson stream through a fresh server; returns its summary."""
+    import threading
+    reqs, sizes = synthetic.serving_stream(nreq, args.seed, rate_hz=rate)
+    data = []
+    for d, n in enumerate(sizes):
+        x, y = synthetic.jittered_grid(int(n), args.seed + 100 + d)
+        _, xs, ys = mvg.morton_order(dev(x), dev(y), sorted_xy=True)
+        data.append((xs, ys, dev(synthetic.normal_eps(2 * int(n), args.seed + 100 + d))))
+    x0r, y0r = synthetic.uniform_targets(100, args.seed)
+    x0, y0 = dev(x0r), dev(y0r)
+    S = mvg.Server(int(args.budget_gb * (1 << 30)), args.workers, {"nb": 512})
+    ids = [S.add_dataset(*t) for t in data]
+    torch.cuda.synchronize()
+    last = None
+    plan = []
+    for q in reqs:   # a cokriging request refers to the latest likelihood's (dataset, theta)
+        if q.kind == "cokrige" and last is not None:
+            plan.append((mvg.REQ_COKRIGE, last[0], last[1], q.arrival_s))
+        else:
+            plan.append((mvg.REQ_LOGLIK, q.dataset, q.theta, q.arrival_s))
+            last = (q.dataset, q.theta)
+    zh = [torch.empty(200, dtype=torch.float64, device="cuda") for _ in plan]
+    t_base = S.clock()
+
+    def feeder():
+        for i, (kind, d, th, ta) in enumerate(plan):
+            wait = t_base + ta - S.clock()
+            if wait > 0:
+                time.sleep(wait)
+            if kind == mvg.REQ_COKRIGE:
+                S.submit(kind, ids[d], th, x0, y0, zh[i], t_arrive=t_base + ta)
+            else:
+                S.submit(kind, ids[d], th, t_arrive=t_base + ta)
+
+    th_feed = threading.Thread(target=feeder)
+    th_feed.start()
+    done = []
+    while len(done) < len(plan):
+        done += S.poll(256, 200)
+    th_feed.join()
+    stats = S.stats()
+    S.close()
+    lat = np.array([r.t_end - r.t_arrive for r in done])
+    span = max(r.t_end for r in done) - t_base
+    ok = [r for r in done if r.status == 0]
+    return {"achieved_rate": len(ok) / span, "offered_rate": len(plan) / (plan[-1][3] or 1.0),
+            "requests": len(plan), "makespan_s": span,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "rejected": int(sum(1 for r in done if r.status < 0)),
+            "failed": int(sum(1 for r in done if r.status > 0)), "cache": stats,
+            "mean_batch": float(np.mean([r.batch for r in done])), "datasets": len(sizes)}
+
+
+def run_serving(args, mvg, dev, synthetic, torch):
+    """The 50 req/s stream (above the FP64 capacity: the queue grows) and a
+    stream below capacity (bounded latency), same request mix."""
+    hot = serve_stream(args, mvg, dev, synthetic, torch, args.rate, args.requests)
+    calm = serve_stream(args, mvg, dev, synthetic, torch, args.sustain_rate, args.requests)
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          hot["achieved_rate"], "requests/s", hot["requests"], 0,
+          1e3 * hot["makespan_s"] / hot["requests"], "f64",
+          {"workload": "serving: %d requests, Poisson %.0f req/s, %d datasets n~U[1000,20000], "
+                       "10%% cokriging (100 targets) on the latest likelihood's factor, theta +-20%%"
+                       % (hot["requests"], args.rate, hot["datasets"]),
+           "requests": hot["requests"], "rate_hz": args.rate, "workers": args.workers,
+           "budget_gb": args.budget_gb, "precision": "fp64"},
+          offered_rate=hot["offered_rate"], p50_latency_s=hot["p50_latency_s"],
+          p99_latency_s=hot["p99_latency_s"], rejected=hot["rejected"], failed=hot["failed"],
+          cache=hot["cache"], mean_batch=hot["mean_batch"],
+          below_capacity={"rate_hz": args.sustain_rate, **calm})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +310,17 @@ def main():
     ap.add_argument("--wide-band", type=int, default=16,
                     help="second, wider FP64 band for the FP32 variant")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving"],
+                    help="dense: N=25,600 FP64 (+ mixed variants); tlr: N=100,000 TLR; batched: "
+                         "many theta at N=400 in one launch; serving: request stream")
+    ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
+    ap.add_argument("--no-dense-ref", action="store_true")
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--sustain-rate", type=float, default=6.0)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -158,9 +345,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
         return
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
+    if args.workload == "tlr":
+        if args.n == 25600:
+            args.n = 100000
+        return run_tlr(args, mvg, dev, synthetic, torch)
+    if args.workload == "batched":
+        return run_batched(args, mvg, dev, synthetic, torch)
+    if args.workload == "serving":
+        return run_serving(args, mvg, dev, synthetic, torch)
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     n = args.n
-    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
     # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)

@@ -85,6 +85,13 @@ def _load():
         "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
         "mvg_ir_stats": (c_int, [c_int, P, P, P]),
         "loglik_many": (c_int, [P, c_int, P, P, P, P, P]),
+        "mvg_server_create": (P, [ctypes.c_size_t, c_int, P]),
+        "mvg_server_add_dataset": (c_int, [P, P, P, P, c_int64]),
+        "mvg_server_submit": (c_int64, [P, c_int, c_int, P, P, P, c_int64, P, c_double]),
+        "mvg_server_poll": (c_int, [P, P, c_int, c_int]),
+        "mvg_server_clock": (c_double, [P]),
+        "mvg_server_stats": (c_int, [P, P, P, P, P]),
+        "mvg_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -347,3 +354,74 @@ def mvg_ir_stats(i: int = 0) -> dict:
     _check("mvg_ir_stats", _load().mvg_ir_stats(int(i), ctypes.byref(it), ctypes.byref(rel),
                                                  ctypes.byref(conv)))
     return {"iters": it.value, "relres": rel.value, "converged": bool(conv.value)}
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", c_int64), ("kind", c_int), ("status", c_int), ("n_loc", c_int64),
+                ("loglik", c_double), ("logdet", c_double), ("quad", c_double),
+                ("t_arrive", c_double), ("t_start", c_double), ("t_end", c_double),
+                ("batch", c_int), ("cache_hit", c_int), ("precision", c_int)]
+
+
+REQ_LOGLIK, REQ_COKRIGE = 0, 1
+
+
+class Server:
+    """Request server of the library (footprint admission, concurrent
+    workers, continuous batching of small likelihoods, resident factors).
+    Datasets and cokriging buffers must stay alive while requests use them;
+    this wrapper keeps references to them."""
+
+    def __init__(self, hbm_budget_bytes: int, n_workers: int = 4, opts=None):
+        self._o = _opts(opts)
+        h = _load().mvg_server_create(int(hbm_budget_bytes), int(n_workers), ctypes.byref(self._o))
+        if not h:
+            raise MvgError("mvg_server_create", -1, "bad arguments")
+        self._h = c_void_p(h)
+        self._keep = []
+
+    def add_dataset(self, x, y, z) -> int:
+        r = _load().mvg_server_add_dataset(self._h, _dev_f64(x, "x"), _dev_f64(y, "y"),
+                                           _dev_f64(z, "z"), x.numel())
+        if r < 0:
+            raise MvgError("mvg_server_add_dataset", r, "")
+        self._keep.append((x, y, z))
+        return r
+
+    def submit(self, kind, dataset, theta, x0=None, y0=None, zhat=None, t_arrive=-1.0) -> int:
+        th = Theta.of(theta)
+        m = 0 if x0 is None else x0.numel()
+        args = (None, None, None) if x0 is None else (_dev_f64(x0, "x0"), _dev_f64(y0, "y0"),
+                                                      c_void_p(zhat.data_ptr()))
+        if x0 is not None:
+            self._keep.append((x0, y0, zhat))
+        r = _load().mvg_server_submit(self._h, int(kind), int(dataset), ctypes.byref(th), args[0],
+                                      args[1], m, args[2], float(t_arrive))
+        if r < 0:
+            raise MvgError("mvg_server_submit", int(r), "")
+        return int(r)
+
+    def poll(self, max_results=256, wait_ms=100):
+        buf = (Result * max_results)()
+        k = _load().mvg_server_poll(self._h, buf, max_results, int(wait_ms))
+        return [buf[i] for i in range(k)]
+
+    def clock(self) -> float:
+        return _load().mvg_server_clock(self._h)
+
+    def stats(self) -> dict:
+        h, m, b, c = c_int64(), c_int64(), c_int64(), ctypes.c_size_t()
+        _load().mvg_server_stats(self._h, ctypes.byref(h), ctypes.byref(m), ctypes.byref(b),
+                                 ctypes.byref(c))
+        return {"hits": h.value, "misses": m.value, "batches": b.value, "cached_bytes": c.value}
+
+    def close(self):
+        if self._h:
+            _load().mvg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,7 +12,8 @@
 //
 // Resident factors.  A likelihood request keeps its factor (and Sigma^-1 Z)
 // in an LRU cache keyed by (dataset, theta); a cokriging request on a cached
-// key predicts from it directly, otherwise it factors first (a miss).  Cached
+// key predicts from it directly; one whose key is being factored by a running
+// likelihood request waits for it; otherwise it factors first (a miss).  Cached
 // factors count against the budget and are evicted oldest first when an
 // admission needs the room.
 #include <hip/hip_runtime.h>
@@ -89,6 +90,7 @@ struct mvg_server {
   };
   std::list<Key> lru;
   std::map<Key, Entry> cache;
+  std::map<Key, int> inflight;  // likelihoods running whose factor will be cached
   int64_t next_id = 0, misses = 0, hits = 0, batches = 0;
   bool stop = false;
   std::mutex mu;
@@ -153,6 +155,10 @@ void mvg_server::worker() {
             continue;
           }
           if (i > 0 && waiting[0].bypassed >= MAX_BYPASS) break;
+          // a cokriging request whose factor is being computed waits for it
+          if (r.kind == MVG_REQ_COKRIGE && inflight.count(key_of(r.dataset, r.theta)) &&
+              !cache.count(key_of(r.dataset, r.theta)))
+            continue;
           if (reserved + r.bytes + cached <= budget || make_room(r.bytes)) {
             pick = i;
             break;
@@ -164,6 +170,7 @@ void mvg_server::worker() {
           waiting.erase(waiting.begin() + pick);
           reserved += r.bytes;
           batch.push_back(r);
+          if (r.kind == MVG_REQ_LOGLIK) ++inflight[key_of(r.dataset, r.theta)];
           const bool small = r.kind == MVG_REQ_LOGLIK && opts.precision == MVG_FP64 &&
                              2 * datasets[r.dataset].n <= mvg::SMALL_MAX;
           if (small) {  // continuous batching of the small likelihoods waiting now
@@ -173,6 +180,7 @@ void mvg_server::worker() {
                   reserved + cached + q.bytes <= budget) {
                 reserved += q.bytes;
                 batch.push_back(q);
+                ++inflight[key_of(q.dataset, q.theta)];
                 waiting.erase(waiting.begin() + i);
               } else {
                 ++i;
@@ -268,6 +276,10 @@ void mvg_server::worker() {
     std::lock_guard<std::mutex> lk(mu);
     for (size_t i = 0; i < batch.size(); ++i) {
       reserved -= batch[i].bytes;
+      if (batch[i].kind == MVG_REQ_LOGLIK) {
+        auto it = inflight.find(key_of(batch[i].dataset, batch[i].theta));
+        if (it != inflight.end() && --it->second == 0) inflight.erase(it);
+      }
       out[i].t_end = t_end;
       done.push_back(out[i]);
     }
