@@ -170,8 +170,10 @@ def test_invalid_theta_is_rejected(lib):
 
 
 def test_batched_equals_single_bitwise(lib, orc):
+    """Above the small-problem size a batch of theta runs the tiled path theta
+    after theta on one arena: bitwise equal to single calls."""
     th0 = THETA0
-    x, y, z = _data(orc, 400, 2, th0)
+    x, y, z = _data(orc, 600, 2, th0)
     simplex = synthetic.nelder_mead_simplex(th0)
     b = lib.loglik(_dev(x), _dev(y), _dev(z), simplex, {"nb": 256})
     for i, t in enumerate(simplex):
@@ -179,6 +181,17 @@ def test_batched_equals_single_bitwise(lib, orc):
         assert s["loglik"][0] == b["loglik"][i]
         ref = orc.loglik(x, y, z, t)
         assert abs(b["loglik"][i] - ref["loglik"]) <= 1e-9 * abs(ref["loglik"])
+
+
+def test_small_batch_agrees_with_single_calls(lib, orc):
+    """2n <= 1024: the batch takes the one-launch path (its own summation
+    order), single calls the tiled path; they agree to rounding."""
+    x, y, z = _data(orc, 400, 2, THETA0)
+    simplex = synthetic.nelder_mead_simplex(THETA0)
+    b = lib.loglik(_dev(x), _dev(y), _dev(z), simplex, {"nb": 256})
+    for i, t in enumerate(simplex):
+        s = lib.loglik(_dev(x), _dev(y), _dev(z), t, {"nb": 256})
+        assert abs(s["loglik"][0] - b["loglik"][i]) <= 1e-12 * abs(s["loglik"][0])
 
 
 def test_morton_order_bit_exact(lib, orc):
