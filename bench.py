@@ -298,7 +298,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=25600)
+    ap.add_argument("--n", type=int, default=None,
+                    help="locations (default 25,600; 100,000 for --workload tlr)")
     ap.add_argument("--a", type=float, default=0.1)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--targets", type=int, default=100)
@@ -347,9 +348,9 @@ def main():
         return
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
     if args.workload == "tlr":
-        if args.n == 25600:
-            args.n = 100000
+        args.n = args.n or 100000
         return run_tlr(args, mvg, dev, synthetic, torch)
+    args.n = args.n or 25600
     if args.workload == "batched":
         return run_batched(args, mvg, dev, synthetic, torch)
     if args.workload == "serving":

@@ -58,7 +58,9 @@ struct CopyTask {
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
                         hipStream_t st);
 int64_t gemm_blocks(const GemmTask &t);
-int launch_qr(const QrTask *d_tasks, int ntask, hipStream_t st);
+int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);  // mmax: largest m
+// unpivoted QR in panels (compact WY); tk.tau must hold (n + 8) x 8 doubles (T factors)
+int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);
 int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st);
 int launch_gaussian(const SketchTask *d_tasks, int ntask, hipStream_t st);
 int launch_copy_cols(const CopyTask *d_tasks, int ntask, hipStream_t st);

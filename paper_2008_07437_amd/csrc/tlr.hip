@@ -82,6 +82,16 @@ static int run_list(const std::vector<T> &v, HostLists &L, hipStream_t st) {
   return F(d, (int)v.size(), st);
 }
 
+static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostLists &L,
+                  hipStream_t st) {
+  if (v.empty()) return 0;
+  int rc = 0;
+  const QrTask *d = (const QrTask *)L.stage(v.data(), v.size() * sizeof(QrTask), st, &rc);
+  if (rc) return rc;
+  return blocked ? launch_qr_blocked(d, (int)v.size(), mmax, st)
+                 : launch_qr(d, (int)v.size(), mmax, st);
+}
+
 static GemmTask gemm(const double *A, int lda, int ta, const double *B, int ldb, int tb, double *C,
                      int ldc, int M, int N, int K, double alpha, double beta) {
   return GemmTask{A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta};
@@ -158,12 +168,14 @@ struct CompressJob {
 // (nb x nb, ldw, lower triangular) is given.  sguess[d] (d = I - J) is
 // updated with the ranks found.
 //
-// Per tile C (nb x nb): Y = C Omega (Gaussian, nb x s); Y = Q R (Householder);
-// B^T = C^T Q; B^T P = Q' R' by column-pivoted Householder QR stopped at the
-// first k with ||R'_22||_F <= acc.  Then C ~= Q B ~= (Q P R'_k^T) Q'_k^T, i.e.
-// U = (Q P) R'_k^T and V = Q'_k, with ||C - U V^T||_2 <= ||C - Q B||_2 + acc
-// (the Frobenius-norm tail rule; it keeps at least the ranks of the 2-norm
-// rule s_i > acc).  A rank above s - OVERSAMPLE (the sketch may have missed
+// Per tile C (nb x nb): Y = C Omega (Gaussian, nb x s); Y = Q R (blocked
+// Householder); B^T = C^T Q = Q'' R'' (blocked Householder); R'' P = Q3 R3 by
+// column-pivoted Householder QR of the small s x s factor, stopped at the
+// first k with ||R3_22||_F <= acc.  Then B^T P ~= (Q'' Q3_k) R3_k and
+// C ~= Q B ~= (Q P R3_k^T) (Q'' Q3_k)^T, i.e. U = (Q P) R3_k^T and
+// V = Q'' Q3_k, with ||C - U V^T||_2 <= ||C - Q B||_2 + acc (the
+// Frobenius-norm tail rule; it keeps at least the ranks of the 2-norm rule
+// s_i > acc).  A rank above s - OVERSAMPLE (the sketch may have missed
 // part of the range) is retried with a wider sketch.
 static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
                          uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
@@ -172,13 +184,15 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
   const int T = D.T;
   const int smax = std::min(nb, QR_MAXN);
   while (!jobs.empty()) {
-    // scratch per job: Om | Y | Z | Qp (nb x s each), R (s x s), piv (s) + rank
+    // scratch per job: Om | Y | Z | Qp (nb x s each), R | Q3 (s x s), T (8 (s + 8)), piv (s) + rank
     std::vector<size_t> base(jobs.size());
     size_t tot = 0;
+    int smx = 1;
     for (size_t b = 0; b < jobs.size(); ++b) {
       const size_t s = jobs[b].s;
       base[b] = tot;
-      tot += 4 * (size_t)nb * s + s * s + s + 2;
+      tot += 4 * (size_t)nb * s + 2 * s * s + 8 * (s + 8) + s + 2;
+      smx = std::max(smx, jobs[b].s);
     }
     double *ws = nullptr;
     if (hipMallocAsync((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
@@ -191,8 +205,11 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     auto Zb = [&](size_t b) { return ws + base[b] + 2 * (size_t)nb * jobs[b].s; };
     auto Qp = [&](size_t b) { return ws + base[b] + 3 * (size_t)nb * jobs[b].s; };
     auto Rb = [&](size_t b) { return ws + base[b] + 4 * (size_t)nb * jobs[b].s; };
-    auto Pv = [&](size_t b) { return (int *)(Rb(b) + (size_t)jobs[b].s * jobs[b].s); };
-    auto Rk = [&](size_t b) { return (int *)(Rb(b) + (size_t)jobs[b].s * jobs[b].s + jobs[b].s); };
+    auto Q3 = [&](size_t b) { return Rb(b) + (size_t)jobs[b].s * jobs[b].s; };
+    auto Tb = [&](size_t b) { return Q3(b) + (size_t)jobs[b].s * jobs[b].s; };
+    // T factors of the blocked QR: one 8 x 8 block per panel of 8 columns
+    auto Pv = [&](size_t b) { return (int *)(Tb(b) + 8 * ((size_t)jobs[b].s + 8)); };
+    auto Rk = [&](size_t b) { return (int *)(Tb(b) + 8 * ((size_t)jobs[b].s + 8) + jobs[b].s); };
     HostLists L;
     int rc = 0;
     {
@@ -209,8 +226,8 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     if (!rc) {
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b)
-        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, nullptr, Om(b), nb, nullptr, 0.0, nullptr});
-      rc = run_list<QrTask, launch_qr>(q, L, st);  // Q -> Om
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tb(b), Om(b), nb, nullptr, 0.0, nullptr});
+      rc = run_qr(q, nb, true, L, st);  // Q -> Om
     }
     if (!rc) {
       std::vector<GemmTask> g;
@@ -222,8 +239,19 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     if (!rc) {
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b)
-        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, nullptr, Zb(b), nb, Pv(b), acc, Rk(b)});
-      rc = run_list<QrTask, launch_qr>(q, L, st);  // B^T P = Q' R', Q'_k -> Z
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tb(b), Zb(b), nb, nullptr, 0.0, nullptr});
+      rc = run_qr(q, nb, true, L, st);  // B^T = Q'' R'', Q'' -> Z
+    }
+    if (!rc) {
+      std::vector<CopyTask> c;
+      std::vector<QrTask> q;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        const int s = jobs[b].s;
+        c.push_back(CopyTask{Yb(b), Rb(b), s, s, nb, s, nullptr, COPY_UPPER_TRI});
+        q.push_back(QrTask{Rb(b), s, s, s, nullptr, Q3(b), s, Pv(b), acc, Rk(b)});
+      }
+      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_qr(q, smx, false, L, st);  // R'' P = Q3 R3, stopped at ||R3_22||_F <= acc
     }
     // ranks to the host
     std::vector<int> ranks(jobs.size(), 0);
@@ -276,7 +304,7 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     // U = (Q P) R'_k^T, V = W Q'_k (or the dense tile: U = tile, V = W or I)
     if (!rc) {
       std::vector<CopyTask> c;
-      std::vector<GemmTask> g;
+      std::vector<GemmTask> g, g2;
       for (size_t b = 0; b < jobs.size(); ++b) {
         if (status[b] != DONE) continue;
         const int64_t t = jobs[b].t;
@@ -294,16 +322,16 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
         const int r = D.rank[t];
         if (r == 0) continue;
         double *V = U + (int64_t)nb * r;
-        c.push_back(CopyTask{Om(b), Qp(b), nb, s, nb, nb, Pv(b), COPY_PLAIN});      // Q P
-        c.push_back(CopyTask{Yb(b), Rb(b), r, s, nb, s, nullptr, COPY_UPPER_TRI});  // R'_k
+        c.push_back(CopyTask{Om(b), Qp(b), nb, s, nb, nb, Pv(b), COPY_PLAIN});     // Q P
+        c.push_back(CopyTask{Rb(b), Rb(b), r, s, s, s, nullptr, COPY_UPPER_TRI});  // R3_k
         g.push_back(gemm(Qp(b), nb, 0, Rb(b), s, 1, U, nb, nb, r, s, 1.0, 0.0));
-        if (W)
-          g.push_back(gemm(W, ldw, 0, Zb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
-        else
-          c.push_back(CopyTask{Zb(b), V, nb, r, nb, nb, nullptr, COPY_PLAIN});
+        // Q'_k = Q'' Q3_k, then V = W Q'_k
+        g.push_back(gemm(Zb(b), nb, 0, Q3(b), s, 0, W ? Yb(b) : V, nb, nb, r, s, 1.0, 0.0));
+        if (W) g2.push_back(gemm(W, ldw, 0, Yb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
       }
       rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
       if (!rc) rc = run_gemms(g, L, st);
+      if (!rc) rc = run_gemms(g2, L, st);
     }
     hipFreeAsync(ws, st);
     L.release(st);

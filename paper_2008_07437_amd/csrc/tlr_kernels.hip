@@ -142,41 +142,69 @@ int64_t gemm_blocks(const GemmTask &t) {
 // are written there (m x n, ldq).  One workgroup per matrix; column c of the
 // trailing update belongs to wave c % QW throughout.
 constexpr int QW = 8;  // waves per QR workgroup
-constexpr int QE = QR_MAXM / 64;  // column elements per lane
 
-// col[j:m] <- (I - tau v v^T) col[j:m] by one wave: the lane's elements are
-// loaded together into registers (independent loads in flight), then the
-// inner product, the wave reduction and the update.  With nrm, the squared
-// norm of the updated rows j+1..m-1 is written there (lane 0).
-__device__ __forceinline__ void reflect_col(double *col, const double *v, int j, int m, double tau,
-                                            int lane, double *nrm) {
-  double x[QE];
+// Columns c0, c0 + QW, ..., c0 + (NC-1) QW (those < n) of A, rows j..m-1, are
+// replaced by (I - tau v v^T) times themselves by one wave: all their
+// elements are loaded first (independent loads in flight), then the inner
+// products, the wave reductions and the updates.  With nrm, the squared norm
+// of each updated column's rows j+1..m-1 goes to nrm[c] (lane 0).  m <= 64 QE.
+template <int QE, int NC>
+__device__ __forceinline__ void reflect_cols(double *A, int lda, int c0, int n, const double *v,
+                                             int j, int m, double tau, int lane, double *nrm) {
+  // pass 1: inner products (all loads of the NC columns issued together)
+  double w[NC];
+  {
+    double x[NC][QE];
 #pragma unroll
-  for (int e = 0; e < QE; ++e) {
-    const int i = j + lane + 64 * e;
-    x[e] = i < m ? col[i] : 0.0;
+    for (int k = 0; k < NC; ++k) {
+      const int c = c0 + k * QW;
+#pragma unroll
+      for (int e = 0; e < QE; ++e) {
+        const int i = j + lane + 64 * e;
+        x[k][e] = (c < n && i < m) ? A[(int64_t)c * lda + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      w[k] = 0.0;
+#pragma unroll
+      for (int e = 0; e < QE; ++e) {
+        const int i = j + lane + 64 * e;
+        if (i < m) w[k] += v[i] * x[k][e];
+      }
+    }
   }
-  double w = 0.0;
+  for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-  for (int e = 0; e < QE; ++e) {
-    const int i = j + lane + 64 * e;
-    if (i < m) w += v[i] * x[e];
-  }
-  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-  const double tw = tau * w;
-  double ss = 0.0;
+    for (int k = 0; k < NC; ++k) w[k] += __shfl_xor(w[k], o);
+  // pass 2: update (the columns are re-read from the cache)
+  double ss[NC];
 #pragma unroll
-  for (int e = 0; e < QE; ++e) {
-    const int i = j + lane + 64 * e;
-    if (i < m) {
-      const double y = x[e] - tw * v[i];
-      col[i] = y;
-      if (i > j) ss += y * y;
+  for (int k = 0; k < NC; ++k) {
+    const int c = c0 + k * QW;
+    const double tw = tau * w[k];
+    ss[k] = 0.0;
+    if (c < n) {
+      double *col = A + (int64_t)c * lda;
+#pragma unroll
+      for (int e = 0; e < QE; ++e) {
+        const int i = j + lane + 64 * e;
+        if (i < m) {
+          const double y = col[i] - tw * v[i];
+          col[i] = y;
+          if (i > j) ss[k] += y * y;
+        }
+      }
     }
   }
   if (nrm) {
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-    if (lane == 0) *nrm = ss;
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < NC; ++k) ss[k] += __shfl_xor(ss[k], o);
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+        if (c0 + k * QW < n) nrm[c0 + k * QW] = ss[k];
   }
 }
 
@@ -184,6 +212,7 @@ __device__ __forceinline__ void reflect_col(double *col, const double *v, int j,
 // the lower index) and early stop once the Frobenius norm of the remaining
 // block is <= tk.tol; *tk.rank receives the number of reflectors k, tk.piv
 // the column order, and only the first k columns of Q are formed.
+template <int QE, int NC>
 __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks) {
   __shared__ double v[QR_MAXM];
   __shared__ double s_tau[QR_MAXN];
@@ -196,7 +225,8 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
   const int m = tk.m, n = tk.n, lda = tk.lda;
   double *A = tk.A;
   const bool pivot = tk.piv != nullptr;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (pivot) {
     for (int c = wave; c < n; c += QW) {
       const double *ac = A + (int64_t)c * lda;
@@ -291,8 +321,8 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
     for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = v[i];
     if (tid == 0) aj[j] = beta;
     if (tau != 0.0 || pivot) {
-      for (int c = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c < n; c += QW)
-        reflect_col(A + (int64_t)c * lda, v, j, m, tau, lane, pivot ? &s_nrm[c] : nullptr);
+      for (int c0 = j + 1 + (((wave - (j + 1)) % QW + QW) % QW); c0 < n; c0 += QW * NC)
+        reflect_cols<QE, NC>(A, lda, c0, n, v, j, m, tau, lane, pivot ? s_nrm : nullptr);
     }
     __syncthreads();
   }
@@ -315,16 +345,239 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
     if (tid == 0) v[j] = 1.0;
     __syncthreads();
     if (tau != 0.0) {
-      for (int c = j + (((wave - j) % QW + QW) % QW); c < kmax; c += QW)
-        reflect_col(Q + (int64_t)c * ldq, v, j, m, tau, lane, nullptr);
+      for (int c0 = j + (((wave - j) % QW + QW) % QW); c0 < kmax; c0 += QW * NC)
+        reflect_cols<QE, NC>(Q, ldq, c0, kmax, v, j, m, tau, lane, nullptr);
     }
     __syncthreads();
   }
 }
 
-int launch_qr(const QrTask *d_tasks, int ntask, hipStream_t st) {
+// ----------------------------------------------------- blocked Householder
+//
+// A = Q R without pivoting, reflectors grouped in panels of QB columns
+// (compact WY form H_p = I - V T V^T, Schreiber and Van Loan): a panel is
+// factored column by column, then the rest of A is updated once per panel,
+// A_c <- A_c - V T^T (V^T A_c), and Q = H_1 ... H_P [I; 0] is formed panel by
+// panel from the last.  One workgroup per matrix; V of the current panel
+// lives in LDS; the T factors go to tk.tau ((n + QB) x QB doubles, required).
+constexpr int QB = 8;
+
+template <int QE, int NC>
+__device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, int p0, int m,
+                                            int bw, const double (*V)[QB], const double (*T)[QB],
+                                            bool trans, int lane) {
+  // columns c0, c0 + QW, ... (< n): rows p0..m-1 <- (I - V op(T) V^T) rows
+  double y[NC][QB];
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+#pragma unroll
+    for (int q = 0; q < QB; ++q) y[k][q] = 0.0;
+  {
+    double x[NC][QE];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int c = c0 + k * QW;
+#pragma unroll
+      for (int e = 0; e < QE; ++e) {
+        const int r = lane + 64 * e, i = p0 + r;
+        x[k][e] = (c < n && i < m) ? A[(int64_t)c * lda + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < QE; ++e) {
+      const int r = lane + 64 * e;
+      if (p0 + r < m)
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const double vq = V[r][q];
+#pragma unroll
+          for (int k = 0; k < NC; ++k) y[k][q] += vq * x[k][e];
+        }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int q = 0; q < QB; ++q) y[k][q] += __shfl_xor(y[k][q], o);
+  // y <- op(T) y  (T upper triangular; T^T for the factorisation)
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double t[QB];
+#pragma unroll
+    for (int a = 0; a < QB; ++a) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        const double tab = trans ? T[b][a] : T[a][b];
+        if (a < bw && b < bw) sacc += tab * y[k][b];
+      }
+      t[a] = sacc;
+    }
+#pragma unroll
+    for (int a = 0; a < QB; ++a) y[k][a] = t[a];
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = c0 + k * QW;
+    if (c >= n) continue;
+    double *col = A + (int64_t)c * lda;
+#pragma unroll
+    for (int e = 0; e < QE; ++e) {
+      const int r = lane + 64 * e, i = p0 + r;
+      if (i < m) {
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) d += V[r][q] * y[k][q];
+        col[i] -= d;
+      }
+    }
+  }
+}
+
+template <int QE, int NC>
+__global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict__ tasks) {
+  __shared__ double V[QR_MAXM][QB];
+  __shared__ double T[QB][QB];
+  __shared__ double G[QB][QB];
+  __shared__ double s_tau[QB];
+  __shared__ double red[QW];
+  const QrTask tk = tasks[blockIdx.x];
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  double *A = tk.A;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double *Tg = tk.tau;  // n x QB: T of panel p at rows p .. p + QB - 1
+  for (int p0 = 0; p0 < n; p0 += QB) {
+    const int bw = min(QB, n - p0);
+    for (int e = tid; e < (m - p0) * QB; e += 64 * QW) V[e / QB][e % QB] = 0.0;
+    __syncthreads();
+    // panel: reflectors of columns p0 .. p0 + bw - 1
+    for (int jj = 0; jj < bw; ++jj) {
+      const int j = p0 + jj;
+      double *aj = A + (int64_t)j * lda;
+      double ss = 0.0;
+      for (int i = j + 1 + tid; i < m; i += 64 * QW) ss += aj[i] * aj[i];
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      if (lane == 0) red[wave] = ss;
+      __syncthreads();
+      double sigma2 = 0.0;
+      for (int w = 0; w < QW; ++w) sigma2 += red[w];
+      const double alpha = aj[j];
+      double tau = 0.0, scale = 0.0, beta = alpha;
+      if (sigma2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int i = j + 1 + tid; i < m; i += 64 * QW) V[i - p0][jj] = aj[i] * scale;
+      if (tid == 0) {
+        V[j - p0][jj] = 1.0;
+        s_tau[jj] = tau;
+      }
+      __syncthreads();
+      for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = V[i - p0][jj];
+      if (tid == 0) aj[j] = beta;
+      // the remaining panel columns, one per wave
+      const int c = j + 1 + wave;
+      if (tau != 0.0 && c < p0 + bw) {
+        double *ac = A + (int64_t)c * lda;
+        double w = 0.0;
+        for (int i = j + lane; i < m; i += 64) w += V[i - p0][jj] * ac[i];
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+        const double tw = tau * w;
+        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * V[i - p0][jj];
+      }
+      __syncthreads();
+    }
+    // T of the panel: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j)
+    for (int q = wave; q < QB * QB; q += QW) {
+      const int a = q / QB, b = q % QB;
+      double d = 0.0;
+      if (a < b && b < bw)
+        for (int r = lane; r < m - p0; r += 64) d += V[r][a] * V[r][b];
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+      if (lane == 0) G[a][b] = d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int a = 0; a < QB; ++a)
+        for (int b = 0; b < QB; ++b) T[a][b] = 0.0;
+      for (int b = 0; b < bw; ++b) {
+        T[b][b] = s_tau[b];
+        for (int a = 0; a < b; ++a) {
+          double sacc = 0.0;
+          for (int c = a; c < b; ++c) sacc += T[a][c] * G[c][b];
+          T[a][b] = -s_tau[b] * sacc;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < QB * QB; e += 64 * QW) Tg[(int64_t)(p0 + e / QB) * QB + e % QB] = T[e / QB][e % QB];
+    // rest of A: A_c <- (I - V T^T V^T) A_c
+    for (int c0 = p0 + bw + wave; c0 < n; c0 += QW * NC)
+      apply_block<QE, NC>(A, lda, c0, n, p0, m, bw, V, T, true, lane);
+    __syncthreads();
+  }
+  if (!tk.Q) return;
+  double *Q = tk.Q;
+  const int ldq = tk.ldq;
+  for (int c = wave; c < n; c += QW)
+    for (int i = lane; i < m; i += 64) Q[(int64_t)c * ldq + i] = (i == c) ? 1.0 : 0.0;
+  for (int p0 = ((n - 1) / QB) * QB; p0 >= 0; p0 -= QB) {
+    const int bw = min(QB, n - p0);
+    __syncthreads();
+    for (int e = tid; e < (m - p0) * QB; e += 64 * QW) {
+      const int r = e / QB, q = e % QB, i = p0 + r;
+      double val = 0.0;
+      if (q < bw) val = (r == q) ? 1.0 : (r > q ? A[(int64_t)(p0 + q) * lda + i] : 0.0);
+      V[r][q] = val;
+    }
+    for (int e = tid; e < QB * QB; e += 64 * QW) T[e / QB][e % QB] = Tg[(int64_t)(p0 + e / QB) * QB + e % QB];
+    __syncthreads();
+    for (int c0 = p0 + wave; c0 < n; c0 += QW * NC)
+      apply_block<QE, NC>(Q, ldq, c0, n, p0, m, bw, V, T, false, lane);
+  }
+}
+
+int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st) {
   if (ntask <= 0) return 0;
-  hipLaunchKernelGGL(k_qr, dim3(ntask), dim3(64 * QW), 0, st, d_tasks);
+  if (mmax > QR_MAXM) {
+    set_error("QR: %d rows above %d", mmax, QR_MAXM);
+    return MVG_ERR_LIMIT;
+  }
+  const dim3 g(ntask), b(64 * QW);
+  if (mmax <= 64 * 4)
+    hipLaunchKernelGGL((k_qr_blocked<4, 2>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 8)
+    hipLaunchKernelGGL((k_qr_blocked<8, 1>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 16)
+    hipLaunchKernelGGL((k_qr_blocked<16, 1>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 20)
+    hipLaunchKernelGGL((k_qr_blocked<20, 1>), g, b, 0, st, d_tasks);
+  else
+    hipLaunchKernelGGL((k_qr_blocked<32, 1>), g, b, 0, st, d_tasks);
+  return check_launch("qr_blocked");
+}
+
+int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st) {
+  if (ntask <= 0) return 0;
+  if (mmax > QR_MAXM) {
+    set_error("QR: %d rows above %d", mmax, QR_MAXM);
+    return MVG_ERR_LIMIT;
+  }
+  const dim3 g(ntask), b(64 * QW);
+  if (mmax <= 64 * 4)
+    hipLaunchKernelGGL((k_qr<4, 8>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 8)
+    hipLaunchKernelGGL((k_qr<8, 6>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 16)
+    hipLaunchKernelGGL((k_qr<16, 3>), g, b, 0, st, d_tasks);
+  else if (mmax <= 64 * 20)
+    hipLaunchKernelGGL((k_qr<20, 2>), g, b, 0, st, d_tasks);
+  else
+    hipLaunchKernelGGL((k_qr<32, 1>), g, b, 0, st, d_tasks);
   return check_launch("qr");
 }
 
