@@ -255,15 +255,17 @@ void mvg_server_destroy(mvg_server *S);
 /* Diagnostics: timing of kernel launches with HIP events recorded on the
  * stream each launch is enqueued on.  mvg_prof_enable(1) clears the records
  * and starts recording, mvg_prof_enable(0) stops.  mvg_prof_read sums the
- * records of one kind: MVG_PROF_TRAILING (the trailing-update GEMM/SYRK
- * kernel, the FLOP sink of the factorisation), MVG_PROF_GEN (covariance
+ * records of one kind: MVG_PROF_TRAILING (the trailing-update GEMM kernel,
+ * the FLOP sink of the factorisation; in the TLR factorisation its update
+ * GEMM), MVG_PROF_SYRK (the look-ahead SYRK of the next diagonal tile), MVG_PROF_GEN (covariance
  * generation), MVG_PROF_POTRF (whole factorisation), MVG_PROF_SOLVE (solve and
  * reductions), MVG_PROF_COKRIGE, MVG_PROF_LOWP (the FP32/BF16 off-band
  * update of the mixed-precision factorisation), MVG_PROF_IR (iterative
  * refinement of the mixed-precision solve).  *flops and *bytes are
  * algorithmic counts (useful work, no padding).  Synchronises the device. */
 enum { MVG_PROF_TRAILING = 0, MVG_PROF_GEN = 1, MVG_PROF_POTRF = 2, MVG_PROF_SOLVE = 3,
-       MVG_PROF_COKRIGE = 4, MVG_PROF_LOWP = 5, MVG_PROF_IR = 6, MVG_PROF_NKINDS = 7 };
+       MVG_PROF_COKRIGE = 4, MVG_PROF_LOWP = 5, MVG_PROF_IR = 6, MVG_PROF_SYRK = 7,
+       MVG_PROF_NKINDS = 8 };
 int mvg_prof_enable(int on);
 int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, double *bytes);
 

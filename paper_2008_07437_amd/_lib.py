@@ -328,7 +328,8 @@ def cokrige_predict(factor: Factor, x0, y0, with_mse=False, stream=None):
     return (zhat, mse) if with_mse else zhat
 
 
-PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4, "lowp": 5, "ir": 6}
+PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4, "lowp": 5, "ir": 6,
+              "syrk": 7}
 
 
 def mvg_prof_enable(on: bool = True):

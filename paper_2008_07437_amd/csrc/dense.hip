@@ -614,7 +614,7 @@ int launch_syrk_next(const mvg_mat *A, int k, hipStream_t st) {
   const int sb = M.nb / PB;
   const double nj = (double)std::min<int64_t>(M.nb, A->N - (int64_t)(k + 1) * M.nb);
   const double nk = (double)std::min<int64_t>(M.nb, A->N - (int64_t)k * M.nb);
-  int h = prof_begin(MVG_PROF_TRAILING, st, nj * (nj + 1.0) * nk, 0.0);
+  int h = prof_begin(MVG_PROF_SYRK, st, nj * (nj + 1.0) * nk, 0.0);
   hipLaunchKernelGGL(k_syrk64, dim3(sb * (sb + 1) / 2), dim3(256), 0, st, M, k, k + 1);
   prof_end(h, st);
   return check_launch("syrk64");
