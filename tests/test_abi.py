@@ -46,3 +46,44 @@ def test_product_path_fails_without_gpu_or_library(monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises((ImportError, RuntimeError)):
         L._load()
+
+
+def _lib_cpu():
+    lib = ctypes.CDLL(SO)
+    lib.mvg_footprint.restype = ctypes.c_size_t
+    lib.mvg_footprint.argtypes = [ctypes.c_int64, ctypes.c_void_p]
+    return lib
+
+
+def _opts(**kw):
+    import paper_2008_07437_amd._lib as L
+    return L.Opts.make(**kw)
+
+
+@pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
+def test_footprint_host_logic():
+    """mvg_footprint is host arithmetic (no device call): it grows with n,
+    mixed precision adds the FP64 copy kept for the refinement, the TLR
+    estimate stays far below dense at large n, and invalid options give 0."""
+    lib = _lib_cpu()
+    fp = lambda n, **kw: lib.mvg_footprint(n, ctypes.byref(_opts(**kw)))  # noqa: E731
+    dense = [fp(n, nb=512) for n in (1000, 5000, 25600)]
+    assert dense[0] < dense[1] < dense[2]
+    # 51,200^2 lower tiles: 100*101/2 tiles of 2 MiB, about 10.6 GB
+    assert 10.5e9 < dense[2] < 11.5e9
+    assert fp(25600, nb=512, precision=1) > dense[2]
+    assert fp(100000, nb=1200, precision=3) < 0.5 * fp(100000, nb=512)
+    assert fp(1000, nb=100) == 0                      # not a supported dense tile size
+    assert fp(1000, nb=128, precision=1, band_tiles=1) == 0
+    assert fp(1000, nb=1200, precision=3, tlr_max_rank=600) == 0
+    assert fp(0, nb=512) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
+def test_server_rejects_bad_arguments_without_a_device():
+    lib = ctypes.CDLL(SO)
+    lib.mvg_server_create.restype = ctypes.c_void_p
+    lib.mvg_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    assert lib.mvg_server_create(0, 2, None) is None
+    assert lib.mvg_server_create(1 << 30, 0, None) is None
+    assert lib.mvg_server_create(1 << 30, 64, None) is None
