@@ -219,6 +219,42 @@ def run_batched(args, mvg, dev, synthetic, torch):
           simplex7_ms=1e3 * (time.perf_counter() - t2), failed=int((r["status"] != 0).sum()))
 
 
+def run_mloe(args, mvg, dev, synthetic, torch):
+    """Prediction efficiency (Section 5.4, Algorithm 1) of an approximate
+    model's theta_a against the true theta on the N = 25,600 workload with
+    100 targets: two covariance generations, two FP64 Cholesky
+    factorisations, the multi-right-hand-side solves and the traces."""
+    n, m = args.n, args.targets
+    th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
+    tha = (0.97, 1.04, 1.08 * args.a, 0.52, 0.96, 0.47)
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    x0r, y0r = synthetic.uniform_targets(m, args.seed)
+    x0, y0 = dev(x0r), dev(y0r)
+    o = {"nb": args.nb}
+    for _ in range(args.warmup):
+        mvg.mloe_mmom(xs, ys, th, tha, x0, y0, o)
+    torch.cuda.synchronize()
+    mvg.mvg_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = mvg.mloe_mmom(xs, ys, th, tha, x0, y0, o)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    mvg.mvg_prof_enable(False)
+    gen, fac, sol = (mvg.mvg_prof_read(k) for k in ("gen", "potrf", "solve"))
+    per = lambda p: p["ms"] / args.steps   # noqa: E731
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          1.0 / dt, "MLOE/MMOM evals/s", args.steps, args.warmup, 1e3 * dt, "f64",
+          {"workload": "multivariate MLOE/MMOM, N=%d locations (%dx%d), %d targets, nb %d, "
+                       "theta_a = theta perturbed by 3-8%%" % (n, 2 * n, 2 * n, m, args.nb),
+           "n_loc": n, "targets": m, "precision": "fp64"},
+          mloe=r["mloe"], mmom=r["mmom"], status=r["status"],
+          gen_ms=per(gen), fact_ms=per(fac), comp_ms=per(sol),
+          fact_tflops=fac["flops"] / (fac["ms"] * 1e9) if fac["ms"] else None,
+          comp_tflops=sol["flops"] / (sol["ms"] * 1e9) if sol["ms"] else None)
+
+
 def serve_stream(args, mvg, dev, synthetic, torch, rate, nreq):
     """One Poisson stream through a fresh server; returns its summary."""
     import threading
@@ -311,9 +347,10 @@ def main():
     ap.add_argument("--wide-band", type=int, default=16,
                     help="second, wider FP64 band for the FP32 variant")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe"],
                     help="dense: N=25,600 FP64 (+ mixed variants); tlr: N=100,000 TLR; batched: "
-                         "many theta at N=400 in one launch; serving: request stream")
+                         "many theta at N=400 in one launch; serving: request stream; mloe: "
+                         "MLOE/MMOM at N=25,600 with 100 targets")
     ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
     ap.add_argument("--no-dense-ref", action="store_true")
     ap.add_argument("--batch", type=int, default=1024)
@@ -355,6 +392,8 @@ def main():
         return run_batched(args, mvg, dev, synthetic, torch)
     if args.workload == "serving":
         return run_serving(args, mvg, dev, synthetic, torch)
+    if args.workload == "mloe":
+        return run_mloe(args, mvg, dev, synthetic, torch)
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     n = args.n
     # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)

@@ -132,6 +132,25 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
            double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
            mvg_factor **keep, void *hip_stream);
 
+/* Multivariate prediction-efficiency criteria (Section 5.4, Eq. (5)-(8),
+ * Algorithm 1): for m targets s0, with c0_t, c0_a the Eq. (3)-(4) cross
+ * covariances under the true theta and an approximate model's estimate
+ * theta_a,
+ *   E_t     = tr{C(0; theta) - c0_t^T Sigma(theta)^-1 c0_t},
+ *   E_a     = tr{C(0; theta_a) - c0_a^T Sigma(theta_a)^-1 c0_a},
+ *   E_{t,a} = tr{C(0; theta) - 2 c0_t^T Sigma(theta_a)^-1 c0_a
+ *              + c0_a^T Sigma(theta_a)^-1 Sigma(theta) Sigma(theta_a)^-1 c0_a},
+ *   LOE = E_{t,a} / E_t - 1,  MOM = E_a / E_{t,a} - 1,
+ * *h_mloe / *h_mmom = their means over the targets; d_loe, d_mom (nullable,
+ * device, m each) receive the per-target values.  Two dense FP64 tiled
+ * factorisations (o: FP64 only, nb as for cov_generate); m <= 65535.
+ * Returns 0, -1..-10, 1 or 2 if Sigma(theta) or Sigma(theta_a) is not
+ * positive definite, MVG_ERR_*. */
+int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
+              const mvg_theta *th_a, const double *d_x0, const double *d_y0, int64_t m,
+              const mvg_opts *o, double *h_mloe, double *h_mmom, double *d_loe, double *d_mom,
+              void *hip_stream);
+
 /* One task of loglik_many: a dataset (device pointers, caller-owned) and a
  * theta. */
 typedef struct {

@@ -22,6 +22,8 @@ Each function states the passage of the paper it follows:
   factorisation error.
 * ``round_to`` -- emulation of FP32 / BF16 round-to-nearest-even, used to size
   the mixed-precision error.
+* ``cross_cov_targets`` / ``mloe_mmom`` -- the multivariate prediction
+  efficiency criteria of Section 5.4 (Eq. (5)-(8), Algorithm 1).
 * ``mixed_cholesky_emulated`` -- not in the paper: the mixed-precision tiled
   factorisation (FP64 band, FP32 / BF16 off the band) emulated in FP64 with
   rounding at the operand points, to predict the size of its error (not its
@@ -375,3 +377,56 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
                 else:
                     A[blk(i, j)] = round_to(A[blk(i, j)] - op(Li) @ op(Lj).T, "fp32")
     return np.tril(A), 0
+
+
+def cross_cov_targets(x, y, x0, y0, theta) -> np.ndarray:
+    """c0 of Eq. (3)-(4) for every target: a 2n x 2m matrix whose columns
+    2l + j hold C_ij(||s_r - s0_l||) at rows 2r + i (Representation I)."""
+    xa, ya, x0a, y0a = _f64(x), _f64(y), _f64(x0), _f64(y0)
+    h = np.sqrt((xa[:, None] - x0a[None, :]) ** 2 + (ya[:, None] - y0a[None, :]) ** 2)
+    t = _theta(theta)
+    nu12 = 0.5 * (t[3] + t[4])
+    c11 = t[0] * matern(h / t[2], t[3])
+    c22 = t[1] * matern(h / t[2], t[4])
+    c12 = rho12(theta) * np.sqrt(t[0]) * np.sqrt(t[1]) * matern(h / t[2], nu12)
+    n, m = h.shape
+    c0 = np.empty((2 * n, 2 * m))
+    c0[0::2, 0::2] = c11
+    c0[1::2, 0::2] = c12
+    c0[0::2, 1::2] = c12
+    c0[1::2, 1::2] = c22
+    return c0
+
+
+def mloe_mmom(x, y, theta, theta_a, x0, y0) -> dict:
+    """Section 5.4: per target s0, E_t (Eq. 5 with the true theta), E_a (Eq. 5
+    with the approximate model's theta_a) and E_{t,a} (Eq. 6), then
+    LOE = E_{t,a}/E_t - 1 and MOM = E_a/E_{t,a} - 1 and their means (Eq. 7-8),
+    following Algorithm 1 with the oracle's own Cholesky factors and
+    triangular solves."""
+    S, Sa = cov_dense(x, y, theta), cov_dense(x, y, theta_a)
+    L, info = potrf(S)
+    La, info_a = potrf(Sa)
+    if info or info_a:
+        raise ValueError("covariance not positive definite")
+    c0t = cross_cov_targets(x, y, x0, y0, theta)
+    c0a = cross_cov_targets(x, y, x0, y0, theta_a)
+    t, ta = _theta(theta), _theta(theta_a)
+    tr_t, tr_a = t[0] + t[1], ta[0] + ta[1]
+    m = c0t.shape[1] // 2
+    loe, mom = np.empty(m), np.empty(m)
+    for l in range(m):
+        et = tr_t
+        ea = tr_a
+        eta = tr_t
+        for j in (2 * l, 2 * l + 1):
+            ut = trsv_lower(L, c0t[:, j])                    # L^-1 c0_t
+            ua = trsv_lower(La, c0a[:, j])                   # L_a^-1 c0_a
+            wa = trsv_lower(La, ua, trans=True)              # Sigma_a^-1 c0_a
+            et -= float(np.dot(ut, ut))
+            ea -= float(np.dot(ua, ua))
+            lw = L.T @ wa                                    # L^T w_a
+            eta += -2.0 * float(np.dot(c0t[:, j], wa)) + float(np.dot(lw, lw))
+        loe[l] = eta / et - 1.0
+        mom[l] = ea / eta - 1.0
+    return {"mloe": float(np.mean(loe)), "mmom": float(np.mean(mom)), "loe": loe, "mom": mom}

@@ -72,6 +72,7 @@ def _load():
         "loglik": (c_int, [P, P, P, c_int64, P, c_int, P, P, P, P, P, P, P]),
         "tlr_compress": (c_int, [P, P, c_int64, P, P, P, P, P]),
         "cokrige_predict": (c_int, [P, P, P, c_int64, P, P, P]),
+        "mloe_mmom": (c_int, [P, P, c_int64, P, P, P, P, c_int64, P, P, P, P, P, P]),
         "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
         "mvg_mat_shape": (c_int, [P, P, P, P, P, P]),
         "mvg_mat_gather": (c_int, [P, P, P, c_int64, P, P]),
@@ -326,6 +327,26 @@ def cokrige_predict(factor: Factor, x0, y0, with_mse=False, stream=None):
         c_void_p(mse.data_ptr()) if with_mse else None, _stream(stream)))
     zhat = zhat.view(m, 2)
     return (zhat, mse) if with_mse else zhat
+
+
+def mloe_mmom(x, y, theta, theta_a, x0, y0, opts=None, stream=None):
+    """Section 5.4 (Eq. 5-8, Algorithm 1): prediction efficiency of the model
+    theta_a when theta is true, at the m targets (x0, y0).  Returns
+    {'mloe', 'mmom', 'loe', 'mom', 'status'}; status 1 / 2 means Sigma(theta) /
+    Sigma(theta_a) is not positive definite (means are NaN then)."""
+    m = x0.numel()
+    th, tha = Theta.of(theta), Theta.of(theta_a)
+    loe = torch.empty(m, dtype=torch.float64, device=x0.device)
+    mom = torch.empty(m, dtype=torch.float64, device=x0.device)
+    a, b = c_double(), c_double()
+    o = _opts(opts)
+    rc = _load().mloe_mmom(_dev_f64(x, "x"), _dev_f64(y, "y"), x.numel(), ctypes.byref(th),
+                           ctypes.byref(tha), _dev_f64(x0, "x0"), _dev_f64(y0, "y0"), m,
+                           ctypes.byref(o), ctypes.byref(a), ctypes.byref(b),
+                           c_void_p(loe.data_ptr()), c_void_p(mom.data_ptr()), _stream(stream))
+    if rc not in (0, 1, 2):
+        _check("mloe_mmom", rc)
+    return {"mloe": a.value, "mmom": b.value, "loe": loe, "mom": mom, "status": rc}
 
 
 PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4, "lowp": 5, "ir": 6,

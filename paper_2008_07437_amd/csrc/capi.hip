@@ -873,6 +873,127 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   return 0;
 }
 
+__global__ void k_loe_mom(const double *__restrict__ sT, const double *__restrict__ sA,
+                          const double *__restrict__ dT, const double *__restrict__ sQ, int64_t m,
+                          double trt, double tra, double *__restrict__ loe,
+                          double *__restrict__ mom) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= m) return;
+  const double et = trt - (sT[2 * l] + sT[2 * l + 1]);
+  const double ea = tra - (sA[2 * l] + sA[2 * l + 1]);
+  const double eta = trt - 2.0 * (dT[2 * l] + dT[2 * l + 1]) + (sQ[2 * l] + sQ[2 * l + 1]);
+  loe[l] = eta / et - 1.0;
+  mom[l] = ea / eta - 1.0;
+}
+
+// Section 5.4, Eq. (5)-(8), Algorithm 1 on two dense FP64 factors.
+int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
+              const mvg_theta *th_a, const double *d_x0, const double *d_y0, int64_t m,
+              const mvg_opts *o, double *h_mloe, double *h_mmom, double *d_loe, double *d_mom,
+              void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (n_loc < 1) return -3;
+  if (!th) return -4;
+  if (!th_a) return -5;
+  if (!d_x0) return -6;
+  if (!d_y0) return -7;
+  if (m < 1 || m > 65535) return -8;
+  mvg_opts d;
+  if (normalize_opts(o, &d) || d.precision != MVG_FP64) return -9;
+  if (!h_mloe || !h_mmom) return -10;
+  MaternArgs tmp;
+  if (matern_setup(th, &tmp)) return -4;
+  if (matern_setup(th_a, &tmp)) return -5;
+  hipStream_t st = (hipStream_t)hip_stream;
+  mvg_mat *A = nullptr, *Aa = nullptr;
+  int rc = mat_create(n_loc, d, th, d_x, d_y, st, &A);
+  if (!rc) rc = mat_create(n_loc, d, th_a, d_x, d_y, st, &Aa);
+  if (rc) {
+    mat_free(A);
+    return rc;
+  }
+  const int64_t Np = A->Np, k2 = 2 * m;
+  double *ws = nullptr;  // C0t | X1 | X2 | X3 (Np x 2m) | sT sA dT sQ (2m) | loe mom (m) | info 2
+  const size_t wn = 4 * (size_t)Np * k2 + 4 * k2 + 2 * m + 2;
+  if (hipMallocAsync((void **)&ws, sizeof(double) * wn, st) != hipSuccess) {
+    hipGetLastError();
+    mat_free(A);
+    mat_free(Aa);
+    set_error("MLOE/MMOM workspace of %.2f GB failed", wn * 8.0 / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  double *C0t = ws, *X1 = C0t + Np * k2, *X2 = X1 + Np * k2, *X3 = X2 + Np * k2;
+  double *sT = X3 + Np * k2, *sA = sT + k2, *dT = sA + k2, *sQ = dT + k2;
+  double *loe = sQ + k2, *mom = loe + m;
+  int64_t *info = reinterpret_cast<int64_t *>(mom + m);
+  // Sigma(theta) = L L^T, Sigma(theta_a) = L_a L_a^T
+  int hg = prof_begin(MVG_PROF_GEN, st, 0.0, 8.0 * (double)A->N * (A->N + 1));
+  rc = mat_generate(A, st);
+  if (!rc) rc = mat_generate(Aa, st);
+  prof_end(hg, st);
+  if (!rc) rc = launch_fill_i64(info, INT64_MAX, 2, st);
+  const double Nd = (double)A->N;
+  int hp = prof_begin(MVG_PROF_POTRF, st, 2.0 * (Nd * Nd * Nd / 3.0 + Nd * Nd / 2.0), 0.0);
+  if (!rc) rc = dense_potrf(A, info, st);
+  if (!rc) rc = dense_potrf(Aa, info + 1, st);
+  prof_end(hp, st);
+  // forward solves (3), backward solve, L^T product: N^2 k2 flops each
+  int hs = prof_begin(MVG_PROF_SOLVE, st, 5.0 * Nd * Nd * (double)k2, 0.0);
+  // E_t: ||L^-1 c0_t||^2 per column
+  if (!rc) rc = launch_cokrige_c0(A->margs, A->d_qtab, A->d_x, A->d_y, n_loc, Np, d_x0, d_y0, m,
+                                  C0t, st);
+  if (!rc && hipMemcpyAsync(X1, C0t, sizeof(double) * Np * k2, hipMemcpyDeviceToDevice, st))
+    rc = MVG_ERR_LAUNCH;
+  if (!rc) rc = trsm_forward_multi(A, X1, (int)k2, st);
+  if (!rc) rc = launch_sum_sq_cols(X1, Np, (int)k2, sT, st);
+  // E_a: ||L_a^-1 c0_a||^2; w_a = Sigma_a^-1 c0_a
+  if (!rc) rc = launch_cokrige_c0(Aa->margs, Aa->d_qtab, Aa->d_x, Aa->d_y, n_loc, Np, d_x0, d_y0,
+                                  m, X2, st);
+  if (!rc) rc = trsm_forward_multi(Aa, X2, (int)k2, st);
+  if (!rc) rc = launch_sum_sq_cols(X2, Np, (int)k2, sA, st);
+  if (!rc) rc = trsm_backward_multi(Aa, X2, (int)k2, st);
+  // E_{t,a}: c0_t . w_a and ||L^T w_a||^2
+  if (!rc) rc = launch_dot_cols(C0t, X2, Np, (int)k2, dT, st);
+  if (!rc) rc = launch_trmm_t(A, X2, X3, (int)k2, st);
+  if (!rc) rc = launch_sum_sq_cols(X3, Np, (int)k2, sQ, st);
+  prof_end(hs, st);
+  if (!rc) {
+    hipLaunchKernelGGL(k_loe_mom, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       (const double *)sT, (const double *)sA, (const double *)dT,
+                       (const double *)sQ, m, th->sigma11_sq + th->sigma22_sq,
+                       th_a->sigma11_sq + th_a->sigma22_sq, d_loe ? d_loe : loe,
+                       d_mom ? d_mom : mom);
+    rc = check_launch("loe_mom");
+  }
+  std::vector<double> hl(m), hm(m);
+  int64_t hinfo[2] = {0, 0};
+  if (!rc) {
+    hipMemcpyAsync(hl.data(), d_loe ? d_loe : loe, sizeof(double) * m, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(hm.data(), d_mom ? d_mom : mom, sizeof(double) * m, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st);
+  }
+  hipFreeAsync(ws, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = MVG_ERR_LAUNCH;
+  mat_free(A);
+  mat_free(Aa);
+  if (rc) return rc;
+  if (hinfo[0] != INT64_MAX || hinfo[1] != INT64_MAX) {
+    set_error("MLOE/MMOM: a covariance matrix is not positive definite (pivot %lld / %lld)",
+              (long long)(hinfo[0] == INT64_MAX ? 0 : hinfo[0]),
+              (long long)(hinfo[1] == INT64_MAX ? 0 : hinfo[1]));
+    return hinfo[0] != INT64_MAX ? 1 : 2;
+  }
+  double a = 0.0, b = 0.0;
+  for (int64_t l = 0; l < m; ++l) {
+    a += hl[l];
+    b += hm[l];
+  }
+  *h_mloe = a / (double)m;
+  *h_mmom = b / (double)m;
+  return 0;
+}
+
 int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0, int64_t m,
                     double *d_zhat, double *d_mse, void *hip_stream) {
   if (!F || !F->A || !F->d_w) return -1;

@@ -1,5 +1,4 @@
-// Dense FP64 tiled Cholesky factorisation, triangular solves and reductions
-// on gfx950 (Section 5.1-5.2: the tile Cholesky as POTRF / TRSM / SYRK /
+// Dense FP64 tiled Cholesky factorisation and reductions on gfx950 (Section 5.1-5.2: the tile Cholesky as POTRF / TRSM / SYRK /
 // GEMM tasks; log|Sigma| = 2 sum log L_jj and Z^T Sigma^-1 Z = ||L^-1 Z||^2).
 //
 // Storage: lower tiles of nb x nb, column-major inside a tile (ld = nb).
@@ -15,6 +14,7 @@
 #include <cstdlib>
 
 #include "mvgeo_internal.h"
+#include "tile_dev.h"
 #include "tlr.h"
 
 namespace mvg {
@@ -40,16 +40,6 @@ int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st) {
   if (n <= 0) return 0;
   hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, v, n);
   return check_launch("fill_f64");
-}
-
-__device__ __forceinline__ double *tile_ptr(TileMap M, int I, int J) {
-  return reinterpret_cast<double *>(M.base + M.off[tidx(I, J, M.T)]);
-}
-__device__ __forceinline__ float *tile_ptr_f32(TileMap M, int I, int J) {
-  return reinterpret_cast<float *>(M.base + M.off[tidx(I, J, M.T)]);
-}
-__device__ __forceinline__ bool tile_is_f32(TileMap M, int I, int J) {
-  return M.kind && M.kind[tidx(I, J, M.T)] == TK_F32;
 }
 
 // ------------------------------------------------- trailing update (GEMM)
@@ -817,167 +807,6 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventDestroy(evS);
   hipEventDestroy(ev0);
   return rc;
-}
-
-// ------------------------------------------------------- triangular solves
-//
-// Vectors are padded to Np = T nb; nrhs right-hand sides are stored column
-// after column with leading dimension ldv, blockIdx.z selects the column.
-// The diagonal tiles are solved with the inverses W_k kept by the
-// factorisation: each step is a dense triangular matrix-vector product.
-
-// v_k <- W_k v_k (one workgroup; W_k lower triangular, column-major).
-__global__ __launch_bounds__(256) void k_trsv_tile_fwd(int nb, int k, const double *__restrict__ winv,
-                                                       double *__restrict__ V, int64_t ldv) {
-  __shared__ double v[1024];
-  const int tid = threadIdx.x;
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
-  const double *W = winv + (int64_t)k * nb * nb;
-  for (int r = tid; r < nb; r += 256) v[r] = vk[r];
-  __syncthreads();
-  // rows r0..r0+255 per pass; the 4 waves split the columns c <= r
-  double out[4];
-  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
-    const int r = pass * 256 + tid;
-    double acc = 0.0;
-    if (r < nb)
-      for (int c = 0; c <= r; ++c) acc += W[(int64_t)c * nb + r] * v[c];
-    out[pass] = acc;
-  }
-  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
-    const int r = pass * 256 + tid;
-    if (r < nb) vk[r] = out[pass];
-  }
-}
-
-// v_i -= L_ik y_k for tiles i in (k, T): 64 rows per workgroup, the four waves
-// take a quarter of the columns each and are added in a fixed order.
-__global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__restrict__ V,
-                                                 int64_t ldv) {
-  __shared__ double y[1024];
-  __shared__ double part[4][64];
-  const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double *Vc = V + (int64_t)blockIdx.z * ldv;
-  const int chunks = nb / 64;
-  const int i = k + 1 + blockIdx.x / chunks;
-  const int r = (blockIdx.x % chunks) * 64 + lane;
-  for (int c = tid; c < nb; c += 256) y[c] = Vc[(int64_t)k * nb + c];
-  __syncthreads();
-  const int q = nb / 4;
-  double s0 = 0.0, s1 = 0.0;
-  if (tile_is_f32(M, i, k)) {  // mixed precision: off-band tiles in FP32
-    const float *L = tile_ptr_f32(M, i, k) + r;
-    for (int c = wave * q; c < wave * q + q; c += 2) {
-      s0 += (double)L[(int64_t)c * nb] * y[c];
-      s1 += (double)L[(int64_t)(c + 1) * nb] * y[c + 1];
-    }
-  } else {
-    const double *L = tile_ptr(M, i, k) + r;
-    for (int c = wave * q; c < wave * q + q; c += 2) {
-      s0 += L[(int64_t)c * nb] * y[c];
-      s1 += L[(int64_t)(c + 1) * nb] * y[c + 1];
-    }
-  }
-  part[wave][lane] = s0 + s1;
-  __syncthreads();
-  if (tid < 64)
-    Vc[(int64_t)i * nb + r] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-}
-
-// v_k <- W_k^T v_k: output c = sum_{r >= c} W[r][c] v[r] (column c of W_k is
-// contiguous); one workgroup.
-__global__ __launch_bounds__(256) void k_trsv_tile_bwd(int nb, int k, const double *__restrict__ winv,
-                                                       double *__restrict__ V, int64_t ldv) {
-  __shared__ double v[1024];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
-  const double *W = winv + (int64_t)k * nb * nb;
-  for (int r = tid; r < nb; r += 256) v[r] = vk[r];
-  __syncthreads();
-  __shared__ double out[1024];
-  for (int c = wave; c < nb; c += 4) {
-    const double *col = W + (int64_t)c * nb;
-    double t = 0.0;
-    for (int r = c + lane; r < nb; r += 64) t += col[r] * v[r];
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0) out[c] = t;
-  }
-  __syncthreads();
-  for (int r = tid; r < nb; r += 256) vk[r] = out[r];
-}
-
-// v_j -= L_kj^T w_k for tiles j in [0, k): 64 columns per workgroup, one wave
-// per column at a time, lanes over rows.
-__global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__restrict__ V,
-                                                 int64_t ldv) {
-  __shared__ double w[1024];
-  const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double *Vc = V + (int64_t)blockIdx.z * ldv;
-  const int cb = nb / 64;
-  const int j = blockIdx.x / cb;
-  const int c0 = (blockIdx.x % cb) * 64;
-  for (int r = tid; r < nb; r += 256) w[r] = Vc[(int64_t)k * nb + r];
-  __syncthreads();
-  const bool f32 = tile_is_f32(M, k, j);
-  for (int c = c0 + wave; c < c0 + 64; c += 4) {
-    double s = 0.0;
-    if (f32) {
-      const float *col = tile_ptr_f32(M, k, j) + (int64_t)c * nb;
-      for (int r = lane; r < nb; r += 64) s += (double)col[r] * w[r];
-    } else {
-      const double *col = tile_ptr(M, k, j) + (int64_t)c * nb;
-      for (int r = lane; r < nb; r += 64) s += col[r] * w[r];
-    }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) Vc[(int64_t)j * nb + c] -= s;
-  }
-}
-
-static int solve_args_ok(const mvg_mat *A) {
-  if (A->nb > 1024 || A->nb % PB || !A->d_winv) {
-    set_error("triangular solve needs nb <= 1024, nb %% 64 == 0 and a factored matrix");
-    return MVG_ERR_STATE;
-  }
-  return 0;
-}
-
-int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) {
-  if (A->tlr) return tlr_trsm_forward(A, d_V, nrhs, A->Np, st);
-  if (int rc = solve_args_ok(A)) return rc;
-  const TileMap M = A->map();
-  const int chunks = M.nb / 64;
-  for (int k = 0; k < M.T; ++k) {
-    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M.nb, k,
-                       (const double *)A->d_winv, d_V, A->Np);
-    if (int rc = check_launch("trsv_tile_fwd")) return rc;
-    if (k + 1 < M.T) {
-      hipLaunchKernelGGL(k_gemv_fwd, dim3((M.T - k - 1) * chunks, 1, nrhs), dim3(256), 0, st, M, k,
-                         d_V, A->Np);
-      if (int rc = check_launch("gemv_fwd")) return rc;
-    }
-  }
-  return 0;
-}
-
-int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st) {
-  return trsm_forward_multi(A, d_v, 1, st);
-}
-
-int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
-  if (A->tlr) return tlr_trsv_backward(A, d_v, st);
-  if (int rc = solve_args_ok(A)) return rc;
-  const TileMap M = A->map();
-  const int nb = M.nb;
-  for (int k = M.T - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(1), dim3(256), 0, st, nb, k, (const double *)A->d_winv,
-                       d_v, A->Np);
-    if (int rc = check_launch("trsv_tile_bwd")) return rc;
-    if (k > 0) {
-      hipLaunchKernelGGL(k_gemv_bwd, dim3(k * (nb / 64)), dim3(256), 0, st, M, k, d_v, A->Np);
-      if (int rc = check_launch("gemv_bwd")) return rc;
-    }
-  }
-  return 0;
 }
 
 // ----------------------------------------------------------- reductions

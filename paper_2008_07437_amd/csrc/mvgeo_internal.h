@@ -149,6 +149,10 @@ int launch_fill_i64(int64_t *d, int64_t v, int64_t n, hipStream_t st);
 int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st);
 int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st);     // v <- L^-1 v
 int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st);    // v <- L^-T v
+int trsm_backward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st);  // V <- L^-T V
+int launch_trmm_t(const mvg_mat *A, const double *d_X, double *d_Y, int nrhs, hipStream_t st);  // Y = L^T X
+int launch_dot_cols(const double *d_A, const double *d_B, int64_t Np, int ncols, double *d_out,
+                    hipStream_t st);
 int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st);  // V <- L^-1 V (col-major, ld Np)
 int logdet_quad(const mvg_mat *A, const double *d_y, double *d_part, double *d_out2,
                 hipStream_t st);  // d_out2 = {2 sum log L_jj, y^T y}

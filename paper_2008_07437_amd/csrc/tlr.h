@@ -16,6 +16,7 @@ struct GemmTask {  // C = alpha op(A) op(B) + beta C, column-major
   int M, N, K, lda, ldb, ldc;
   int ta, tb;  // 1: transposed operand
   double alpha, beta;
+  int tri;     // 1: A as stored is lower triangular (entries above its diagonal read as 0)
 };
 
 constexpr int QR_MAXM = 2048;  // rows of a QR task (tile size bound)

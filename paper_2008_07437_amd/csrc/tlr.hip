@@ -667,6 +667,12 @@ static int tlr_solve_ok(const mvg_mat *A) {
 
 int tlr_trsm_forward(const mvg_mat *A, double *d_V, int nrhs, int64_t ldv, hipStream_t st) {
   if (int rc = tlr_solve_ok(A)) return rc;
+  if (nrhs > 65535) {  // right-hand sides go in gridDim.z
+    for (int c = 0; c < nrhs; c += 65535)
+      if (int rc = tlr_trsm_forward(A, d_V + (int64_t)c * ldv, std::min(65535, nrhs - c), ldv, st))
+        return rc;
+    return 0;
+  }
   const TlrState *S = A->tlr;
   const int T = A->T, nb = A->nb, nbp = S->L.nbp;
   for (int k = 0; k < T; ++k) {

@@ -49,7 +49,9 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict
       else { k = tid & 15; m = (tid >> 4) + 16 * i; }
       const int gm = m0 + m, gk = k0 + k;
       double v = 0.0;
-      if (gm < tk.M && gk < tk.K)
+      // stored element (row, col) = (gm, gk), or (gk, gm) when transposed
+      const bool zero_tri = tk.tri && (tk.ta ? gm > gk : gk > gm);
+      if (gm < tk.M && gk < tk.K && !zero_tri)
         v = tk.ta ? tk.A[(int64_t)gm * tk.lda + gk] : tk.A[(int64_t)gk * tk.lda + gm];
       ra[i] = v;
     }
@@ -361,12 +363,13 @@ __global__ __launch_bounds__(64 * QW) void k_qr(const QrTask *__restrict__ tasks
 // panel from the last.  One workgroup per matrix; V of the current panel
 // lives in LDS; the T factors go to tk.tau ((n + QB) x QB doubles, required).
 constexpr int QB = 8;
+constexpr int BWV = 8;  // waves per blocked-QR workgroup
 
 template <int QE, int NC>
 __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, int p0, int m,
                                             int bw, const double (*V)[QB], const double (*T)[QB],
                                             bool trans, int lane) {
-  // columns c0, c0 + QW, ... (< n): rows p0..m-1 <- (I - V op(T) V^T) rows
+  // columns c0, c0 + BWV, ... (< n): rows p0..m-1 <- (I - V op(T) V^T) rows
   double y[NC][QB];
 #pragma unroll
   for (int k = 0; k < NC; ++k)
@@ -376,7 +379,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
     double x[NC][QE];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int c = c0 + k * QW;
+      const int c = c0 + k * BWV;
 #pragma unroll
       for (int e = 0; e < QE; ++e) {
         const int r = lane + 64 * e, i = p0 + r;
@@ -393,6 +396,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
 #pragma unroll
           for (int k = 0; k < NC; ++k) y[k][q] += vq * x[k][e];
         }
+      __builtin_amdgcn_sched_barrier(0);  // keep the LDS reads of V row by row
     }
   }
   for (int o = 32; o > 0; o >>= 1)
@@ -419,7 +423,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    const int c = c0 + k * QW;
+    const int c = c0 + k * BWV;
     if (c >= n) continue;
     double *col = A + (int64_t)c * lda;
 #pragma unroll
@@ -431,17 +435,18 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
         for (int q = 0; q < QB; ++q) d += V[r][q] * y[k][q];
         col[i] -= d;
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
 template <int QE, int NC>
-__global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict__ tasks) {
+__global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restrict__ tasks) {
   __shared__ double V[QR_MAXM][QB];
   __shared__ double T[QB][QB];
   __shared__ double G[QB][QB];
   __shared__ double s_tau[QB];
-  __shared__ double red[QW];
+  __shared__ double red[BWV];
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, n = tk.n, lda = tk.lda;
   double *A = tk.A;
@@ -450,19 +455,19 @@ __global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict
   double *Tg = tk.tau;  // n x QB: T of panel p at rows p .. p + QB - 1
   for (int p0 = 0; p0 < n; p0 += QB) {
     const int bw = min(QB, n - p0);
-    for (int e = tid; e < (m - p0) * QB; e += 64 * QW) V[e / QB][e % QB] = 0.0;
+    for (int e = tid; e < (m - p0) * QB; e += 64 * BWV) V[e / QB][e % QB] = 0.0;
     __syncthreads();
     // panel: reflectors of columns p0 .. p0 + bw - 1
     for (int jj = 0; jj < bw; ++jj) {
       const int j = p0 + jj;
       double *aj = A + (int64_t)j * lda;
       double ss = 0.0;
-      for (int i = j + 1 + tid; i < m; i += 64 * QW) ss += aj[i] * aj[i];
+      for (int i = j + 1 + tid; i < m; i += 64 * BWV) ss += aj[i] * aj[i];
       for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
       if (lane == 0) red[wave] = ss;
       __syncthreads();
       double sigma2 = 0.0;
-      for (int w = 0; w < QW; ++w) sigma2 += red[w];
+      for (int w = 0; w < BWV; ++w) sigma2 += red[w];
       const double alpha = aj[j];
       double tau = 0.0, scale = 0.0, beta = alpha;
       if (sigma2 > 0.0) {
@@ -471,13 +476,13 @@ __global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      for (int i = j + 1 + tid; i < m; i += 64 * QW) V[i - p0][jj] = aj[i] * scale;
+      for (int i = j + 1 + tid; i < m; i += 64 * BWV) V[i - p0][jj] = aj[i] * scale;
       if (tid == 0) {
         V[j - p0][jj] = 1.0;
         s_tau[jj] = tau;
       }
       __syncthreads();
-      for (int i = j + 1 + tid; i < m; i += 64 * QW) aj[i] = V[i - p0][jj];
+      for (int i = j + 1 + tid; i < m; i += 64 * BWV) aj[i] = V[i - p0][jj];
       if (tid == 0) aj[j] = beta;
       // the remaining panel columns, one per wave
       const int c = j + 1 + wave;
@@ -492,7 +497,7 @@ __global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict
       __syncthreads();
     }
     // T of the panel: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j)
-    for (int q = wave; q < QB * QB; q += QW) {
+    for (int q = wave; q < QB * QB; q += BWV) {
       const int a = q / QB, b = q % QB;
       double d = 0.0;
       if (a < b && b < bw)
@@ -514,29 +519,29 @@ __global__ __launch_bounds__(64 * QW) void k_qr_blocked(const QrTask *__restrict
       }
     }
     __syncthreads();
-    for (int e = tid; e < QB * QB; e += 64 * QW) Tg[(int64_t)(p0 + e / QB) * QB + e % QB] = T[e / QB][e % QB];
+    for (int e = tid; e < QB * QB; e += 64 * BWV) Tg[(int64_t)(p0 + e / QB) * QB + e % QB] = T[e / QB][e % QB];
     // rest of A: A_c <- (I - V T^T V^T) A_c
-    for (int c0 = p0 + bw + wave; c0 < n; c0 += QW * NC)
+    for (int c0 = p0 + bw + wave; c0 < n; c0 += BWV * NC)
       apply_block<QE, NC>(A, lda, c0, n, p0, m, bw, V, T, true, lane);
     __syncthreads();
   }
   if (!tk.Q) return;
   double *Q = tk.Q;
   const int ldq = tk.ldq;
-  for (int c = wave; c < n; c += QW)
+  for (int c = wave; c < n; c += BWV)
     for (int i = lane; i < m; i += 64) Q[(int64_t)c * ldq + i] = (i == c) ? 1.0 : 0.0;
   for (int p0 = ((n - 1) / QB) * QB; p0 >= 0; p0 -= QB) {
     const int bw = min(QB, n - p0);
     __syncthreads();
-    for (int e = tid; e < (m - p0) * QB; e += 64 * QW) {
+    for (int e = tid; e < (m - p0) * QB; e += 64 * BWV) {
       const int r = e / QB, q = e % QB, i = p0 + r;
       double val = 0.0;
       if (q < bw) val = (r == q) ? 1.0 : (r > q ? A[(int64_t)(p0 + q) * lda + i] : 0.0);
       V[r][q] = val;
     }
-    for (int e = tid; e < QB * QB; e += 64 * QW) T[e / QB][e % QB] = Tg[(int64_t)(p0 + e / QB) * QB + e % QB];
+    for (int e = tid; e < QB * QB; e += 64 * BWV) T[e / QB][e % QB] = Tg[(int64_t)(p0 + e / QB) * QB + e % QB];
     __syncthreads();
-    for (int c0 = p0 + wave; c0 < n; c0 += QW * NC)
+    for (int c0 = p0 + wave; c0 < n; c0 += BWV * NC)
       apply_block<QE, NC>(Q, ldq, c0, n, p0, m, bw, V, T, false, lane);
   }
 }
@@ -547,7 +552,7 @@ int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st
     set_error("QR: %d rows above %d", mmax, QR_MAXM);
     return MVG_ERR_LIMIT;
   }
-  const dim3 g(ntask), b(64 * QW);
+  const dim3 g(ntask), b(64 * BWV);
   if (mmax <= 64 * 4)
     hipLaunchKernelGGL((k_qr_blocked<4, 2>), g, b, 0, st, d_tasks);
   else if (mmax <= 64 * 8)

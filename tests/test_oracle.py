@@ -397,3 +397,58 @@ def test_tlr_frobenius_rule_keeps_more_and_bounds_tail(orc):
                 blk = (slice(I * 60, (I + 1) * 60), slice(J * 60, (J + 1) * 60))
                 assert np.linalg.norm(Sf[blk] - S[blk]) <= acc * (1 + 1e-9)
                 assert np.linalg.norm(S2[blk] - S[blk], 2) <= acc * (1 + 1e-9)
+
+
+# ----------------------------------------------- MLOE / MMOM (Section 5.4)
+
+def _mloe_data(orc, n=80, m=6, seed=12):
+    x, y = synthetic.jittered_grid(n, seed)
+    p = orc.morton_order(x, y)
+    x0, y0 = synthetic.uniform_targets(m, seed)
+    return x[p], y[p], x0, y0
+
+
+def test_mloe_mmom_zero_at_true_theta(orc):
+    """theta_a = theta: E_{t,a} = E_t = E_a, so every LOE and MOM is 0."""
+    x, y, x0, y0 = _mloe_data(orc)
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    r = orc.mloe_mmom(x, y, th, th, x0, y0)
+    assert np.max(np.abs(r["loe"])) <= 1e-10 and np.max(np.abs(r["mom"])) <= 1e-10
+
+
+def test_mloe_true_predictor_is_optimal_and_brute_force(orc):
+    """LOE >= 0 (the true-parameter cokriging predictor minimises the MSE
+    under the true model); E_t equals the oracle's Eq. (5) MSE; E_{t,a} equals
+    a direct evaluation with numpy inverses."""
+    x, y, x0, y0 = _mloe_data(orc)
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    tha = (1.1, 0.9, 0.13, 0.6, 0.9, 0.45)
+    r = orc.mloe_mmom(x, y, th, tha, x0, y0)
+    assert np.all(r["loe"] >= -1e-12)
+    assert np.any(r["loe"] > 1e-6)
+    z = synthetic.normal_eps(2 * len(x), 1)
+    _, mse = orc.cokrige(x, y, z, th, x0, y0, with_mse=True)
+    S, Sa = orc.cov_dense(x, y, th), orc.cov_dense(x, y, tha)
+    Si, Sai = np.linalg.inv(S), np.linalg.inv(Sa)
+    c0t = orc.cross_cov_targets(x, y, x0, y0, th)
+    c0a = orc.cross_cov_targets(x, y, x0, y0, tha)
+    for l in range(len(x0)):
+        ct, ca = c0t[:, 2 * l:2 * l + 2], c0a[:, 2 * l:2 * l + 2]
+        et = 2.0 - np.trace(ct.T @ Si @ ct)
+        assert abs(et - mse[l]) <= 1e-9 * abs(et)
+        eta = 2.0 - 2 * np.trace(ct.T @ Sai @ ca) + np.trace(ca.T @ Sai @ S @ Sai @ ca)
+        ea = 2.0 - np.trace(ca.T @ Sai @ ca)
+        assert abs(r["loe"][l] - (eta / et - 1)) <= 1e-8
+        assert abs(r["mom"][l] - (ea / eta - 1)) <= 1e-8
+
+
+def test_cross_cov_targets_matches_entries(orc):
+    x, y, x0, y0 = _mloe_data(orc, n=20, m=3)
+    th = (1.3, 0.7, 0.2, 0.8, 1.7, -0.4)
+    c0 = orc.cross_cov_targets(x, y, x0, y0, th)
+    for r in (0, 7, 19):
+        for l in range(3):
+            h = float(np.hypot(x[r] - x0[l], y[r] - y0[l]))
+            for i in range(2):
+                for j in range(2):
+                    assert abs(c0[2 * r + i, 2 * l + j] - orc.cross_cov(th, i, j, h)) <= 1e-14
