@@ -116,6 +116,28 @@ def run_variants(mvg, xs, ys, z, th, args, ref_loglik, reps=2):
             "band_gemm_tflops": (prof["trailing"]["flops"] / (prof["trailing"]["ms"] * 1e-3) / 1e12
                                  if prof["trailing"]["ms"] > 0 else None),
         }
+    # Diagonal Super Tile (tiles far from the diagonal annihilated), at the
+    # workload's range and at weak dependence (a = 0.03) on the same data
+    th_weak = (th[0], th[1], 0.03) + tuple(th[3:])
+    ref_weak = mvg.loglik(xs, ys, z, th_weak, {"nb": args.nb})
+    for tag, t, r in (("", th, ref), ("_a0.03", th_weak, ref_weak)):
+        for name, keep in (("dst_40_60", 0.4), ("dst_70_30", 0.7)):
+            w = mvg.mvg_dst_band(args.n, args.nb, keep)
+            o = {"nb": args.nb, "precision": mvg.MVG_DST, "band_tiles": w}
+            mvg.loglik(xs, ys, z, t, o)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                res = mvg.loglik(xs, ys, z, t, o)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            ok = int(res["status"][0]) == 0
+            out[name + tag] = {
+                "evals_per_s": 1.0 / dt, "status": int(res["status"][0]), "band_tiles": w,
+                "a": t[2],
+                "rel_dloglik_vs_fp64": (abs(res["loglik"][0] - r["loglik"][0]) /
+                                        abs(r["loglik"][0]) if ok else None),
+            }
     return out
 
 

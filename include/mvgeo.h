@@ -54,7 +54,9 @@ enum {
     MVG_FP64 = 0,        /* exact dense FP64 (Section 5.2)                          */
     MVG_MIXED_FP32 = 1,  /* FP64 band tiles, FP32 off-band tiles, FP64 refinement   */
     MVG_MIXED_BF16 = 2,  /* FP64 band, off-band GEMMs on BF16 operands, FP32 accum. */
-    MVG_TLR = 3          /* tile low-rank, FP64 (Section 5.3)                       */
+    MVG_TLR = 3,         /* tile low-rank, FP64 (Section 5.3)                       */
+    MVG_DST = 4          /* Diagonal Super Tile (Section 4.4, Experiment 2 of 6.4): */
+                         /* exact FP64 with the tiles |I - J| >= band_tiles set to 0 */
 };
 
 typedef struct {
@@ -62,7 +64,9 @@ typedef struct {
     int nb;             /* tile size; dense and mixed: 128, 256, 512, 768 or 1024    */
                         /* (0 = 512);                                                  */
                         /* TLR: even, >= 64 (0 = 1200)                                 */
-    int band_tiles;     /* mixed: tiles with |I - J| < band_tiles stay FP64 (0 = 2)   */
+    int band_tiles;     /* mixed: tiles with |I - J| < band_tiles stay FP64 (0 = 2);  */
+                        /* DST: tiles with |I - J| < band_tiles are kept, the others */
+                        /* are annihilated (0 = 2; see mvg_dst_band)                   */
     double tlr_acc;     /* TLR: absolute singular-value threshold (0 = 1e-7)          */
     int tlr_max_rank;   /* TLR: larger ranks keep the tile dense (0 = 300)            */
     uint64_t seed;      /* TLR: seed of the randomized-SVD sketch                      */
@@ -70,7 +74,16 @@ typedef struct {
     double ir_tol;      /* mixed: stop when ||r|| <= ir_tol ||Z|| (0 = 1e-14)          */
 } mvg_opts;
 
-/* Library-owned device matrix: the lower tiles of Sigma (dense, mixed or TLR).
+/* DST band for a kept fraction of tiles (Experiment 2 of Section 6.4: "DST
+ * 40/60" keeps 40 % of the tiles, those nearest the diagonal): with
+ * T = ceil(2 n_loc / nb) tiles per side, the smallest w in [1, T] such that
+ * the T x T tiles with |I - J| < w, T + (w - 1)(2T - w) of them, number at
+ * least keep_fraction * T * T (compared in FP64).  Host only, no device
+ * work.  Returns w, or -1 for n_loc < 1, nb < 1 or keep_fraction outside
+ * (0, 1]. */
+int mvg_dst_band(int64_t n_loc, int nb, double keep_fraction);
+
+/* Library-owned device matrix: the lower tiles of Sigma (dense, mixed, TLR or DST).
  * Freed only by mvg_mat_destroy. */
 typedef struct mvg_mat mvg_mat;
 
@@ -95,15 +108,19 @@ int morton_order(const double *d_x, const double *d_y, int64_t n_loc,
  * column-major inside a tile, lower tiles only; 2n is padded up to a multiple
  * of nb with an identity block (log-determinant and quadratic form
  * unchanged).  Mixed precision stores off-band tiles in FP32.  TLR returns
- * dense tiles (compress with tlr_compress).  Returns 0, -1..-7, MVG_ERR_*. */
+ * dense tiles (compress with tlr_compress).  DST stores the kept tiles only;
+ * every annihilated tile reads as one shared zero tile.  Returns 0, -1..-7,
+ * MVG_ERR_*. */
 int cov_generate(const double *d_x, const double *d_y, int64_t n_loc,
                  const mvg_theta *th, const mvg_opts *o, mvg_mat **out,
                  void *hip_stream);
 
 /* In-place tiled Cholesky Sigma = L L^T of a matrix from cov_generate
  * (POTRF / TRSM / SYRK / GEMM tile tasks, Section 5.1).  *h_info receives 0
- * or the 1-based index of the first non-positive pivot.  Returns 0 (also when
- * *h_info > 0), -1..-3, MVG_ERR_*. */
+ * or the 1-based index of the first non-positive pivot.  DST: the factor of
+ * the band matrix keeps the band (L_ij = 0 for i - j >= band_tiles), so only
+ * tiles within it are updated.  Returns 0 (also when *h_info > 0), -1..-3,
+ * MVG_ERR_*. */
 int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream);
 
 /* Eq. (1) for n_theta parameter vectors on one dataset:
@@ -126,7 +143,11 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * sweeps, or stagnation; h_quad = Z^T x + x^T r (the last residual's
  * first-order correction).  h_logdet is that of the mixed factor (not
  * refined).  Memory: the FP64 lower tiles plus the mixed copy.
- * Requires band_tiles >= 2. */
+ * Requires band_tiles >= 2.
+ *
+ * DST (MVG_DST): Eq. (1) of the Diagonal Super Tile matrix (Section 4.4),
+ * Sigma with the tiles |I - J| >= band_tiles set to zero, in FP64; the
+ * truncated matrix need not be positive definite (then h_status > 0). */
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o,
            double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,

@@ -24,6 +24,9 @@ Each function states the passage of the paper it follows:
   the mixed-precision error.
 * ``cross_cov_targets`` / ``mloe_mmom`` -- the multivariate prediction
   efficiency criteria of Section 5.4 (Eq. (5)-(8), Algorithm 1).
+* ``dst_band`` / ``dst_mask`` -- the Diagonal Super Tile approximation
+  (Section 4.4; "DST 40/60" and "DST 70/30" of Experiment 2, Section 6.4.1):
+  the tiles far from the diagonal set to zero.
 * ``mixed_cholesky_emulated`` -- not in the paper: the mixed-precision tiled
   factorisation (FP64 band, FP32 / BF16 off the band) emulated in FP64 with
   rounding at the operand points, to predict the size of its error (not its
@@ -430,3 +433,30 @@ def mloe_mmom(x, y, theta, theta_a, x0, y0) -> dict:
         loe[l] = eta / et - 1.0
         mom[l] = ea / eta - 1.0
     return {"mloe": float(np.mean(loe)), "mmom": float(np.mean(mom)), "loe": loe, "mom": mom}
+
+
+def dst_band(T: int, keep: float) -> int:
+    """Section 6.4.1, Experiment 2: "DST 40/60" keeps the 40 % of the tiles
+    nearest the diagonal.  Reading: of the T x T tiles, those with
+    |I - J| < w are kept, w the smallest band whose tile count reaches
+    keep * T * T (counted tile by tile)."""
+    need = keep * T * T
+    kept = 0
+    for w in range(1, T + 1):
+        d = w - 1                      # tile diagonal |I - J| = d joins the band
+        kept += T if d == 0 else 2 * (T - d)
+        if kept >= need:
+            return w
+    return T
+
+
+def dst_mask(S: np.ndarray, nb: int, band: int) -> np.ndarray:
+    """Section 4.4: the DST matrix, entries of the nb x nb tiles (I, J) with
+    |I - J| >= band annihilated."""
+    out = np.array(S, dtype=np.float64, copy=True)
+    N = out.shape[0]
+    for r in range(N):
+        for c in range(N):
+            if abs(r // nb - c // nb) >= band:
+                out[r, c] = 0.0
+    return out

@@ -10,7 +10,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libmvgeo.so")
 
-MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR = 0, 1, 2, 3
+MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR, MVG_DST = 0, 1, 2, 3, 4
 
 c_double, c_int, c_int64, c_void_p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
 
@@ -74,6 +74,7 @@ def _load():
         "cokrige_predict": (c_int, [P, P, P, c_int64, P, P, P]),
         "mloe_mmom": (c_int, [P, P, c_int64, P, P, P, P, c_int64, P, P, P, P, P, P]),
         "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
+        "mvg_dst_band": (c_int, [c_int64, c_int, c_double]),
         "mvg_mat_shape": (c_int, [P, P, P, P, P, P]),
         "mvg_mat_gather": (c_int, [P, P, P, c_int64, P, P]),
         "mvg_mat_to_dense": (c_int, [P, P, c_int64, P]),
@@ -363,6 +364,14 @@ def mvg_prof_read(kind: str) -> dict:
                                                  ctypes.byref(ms), ctypes.byref(fl),
                                                  ctypes.byref(by)))
     return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+def mvg_dst_band(n_loc: int, nb: int, keep_fraction: float) -> int:
+    """Kept tile diagonals of a DST matrix that keeps keep_fraction of the tiles."""
+    w = int(_load().mvg_dst_band(int(n_loc), int(nb), float(keep_fraction)))
+    if w < 1:
+        raise ValueError("mvg_dst_band: bad arguments")
+    return w
 
 
 def mvg_footprint(n_loc: int, opts=None) -> int:

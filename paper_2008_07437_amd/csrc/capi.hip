@@ -166,7 +166,7 @@ using namespace mvg;
 static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   mvg_opts d{};
   if (o) d = *o;
-  if (d.precision < MVG_FP64 || d.precision > MVG_TLR) return -1;
+  if (d.precision < MVG_FP64 || d.precision > MVG_DST) return -1;
   if (d.nb == 0) d.nb = (d.precision == MVG_TLR) ? 1200 : 512;
   if (d.precision == MVG_TLR) {
     if (d.nb < 64 || d.nb % 2 || d.nb > QR_MAXM) return -2;
@@ -200,20 +200,35 @@ static void mat_free(mvg_mat *A) {
   delete A;
 }
 
-// Tile layout: band tiles (|I - J| < band) FP64, the rest FP64 or FP32 by precision.
+// Tile layout: band tiles (|I - J| < band) FP64; the rest FP32 (mixed), FP64,
+// or (DST) all mapped to one shared zero tile stored after the others.
+// zero_off receives that tile's offset (-1: none).
 static int tile_layout(int T, int nb, int precision, int band, int64_t *off, int *kind,
-                       size_t *total) {
+                       size_t *total, int64_t *zero_off) {
   size_t pos = 0;
+  bool any_zero = false;
   for (int J = 0; J < T; ++J)
     for (int I = J; I < T; ++I) {
       const int64_t t = tidx(I, J, T);
-      const bool lowp = (precision == MVG_MIXED_FP32 || precision == MVG_MIXED_BF16) &&
-                        (I - J) >= band;
+      const bool far = (I - J) >= band;
+      const bool lowp = (precision == MVG_MIXED_FP32 || precision == MVG_MIXED_BF16) && far;
+      if (precision == MVG_DST && far) {
+        kind[t] = TK_ZERO;
+        any_zero = true;
+        continue;
+      }
       kind[t] = lowp ? TK_F32 : TK_F64;
       off[t] = (int64_t)pos;
       pos += (size_t)nb * nb * (lowp ? 4 : 8);
       pos = (pos + 255) / 256 * 256;
     }
+  *zero_off = -1;
+  if (any_zero) {
+    *zero_off = (int64_t)pos;
+    for (int64_t t = 0; t < (int64_t)T * (T + 1) / 2; ++t)
+      if (kind[t] == TK_ZERO) off[t] = (int64_t)pos;
+    pos += ((size_t)nb * nb * 8 + 255) / 256 * 256;
+  }
   *total = pos;
   return 0;
 }
@@ -222,12 +237,18 @@ static size_t layout_bytes(int64_t n_loc, const mvg_opts &o) {
   const int64_t N = 2 * n_loc;
   const int T = (int)((N + o.nb - 1) / o.nb);
   size_t total = 0;
+  bool any_zero = false;
   for (int J = 0; J < T; ++J)
     for (int I = J; I < T; ++I) {
-      const bool lowp = (o.precision == MVG_MIXED_FP32 || o.precision == MVG_MIXED_BF16) &&
-                        (I - J) >= o.band_tiles;
+      const bool far = (I - J) >= o.band_tiles;
+      const bool lowp = (o.precision == MVG_MIXED_FP32 || o.precision == MVG_MIXED_BF16) && far;
+      if (o.precision == MVG_DST && far) {
+        any_zero = true;
+        continue;
+      }
       total += ((size_t)o.nb * o.nb * (lowp ? 4 : 8) + 255) / 256 * 256;
     }
+  if (any_zero) total += ((size_t)o.nb * o.nb * 8 + 255) / 256 * 256;
   return total;
 }
 
@@ -250,8 +271,9 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
   A->h_off = new int64_t[nt];
   A->h_kind = new int[nt];
+  int64_t zero_off = -1;
   tile_layout(A->T, A->nb, A->precision == MVG_TLR ? MVG_FP64 : A->precision, A->band, A->h_off,
-              A->h_kind, &A->arena_bytes);
+              A->h_kind, &A->arena_bytes, &zero_off);
   A->arena = (char *)arena_acquire(A->arena_bytes);
   bool ok = A->arena != nullptr;
   ok = ok && hipMalloc(&A->d_off, sizeof(int64_t) * nt) == hipSuccess;
@@ -272,6 +294,13 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   hipMemcpyAsync(A->d_x, d_x, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
   hipMemcpyAsync(A->d_y, d_y, sizeof(double) * n_loc, hipMemcpyDeviceToDevice, st);
   // the host offset tables are read by the copies above; keep them alive with A
+  if (zero_off >= 0) {  // the shared tile of the annihilated DST tiles
+    if (int rc = launch_fill_f64(reinterpret_cast<double *>(A->arena + zero_off), 0.0,
+                                 (int64_t)A->nb * A->nb, st)) {
+      mat_free(A);
+      return rc;
+    }
+  }
   *out = A;
   return 0;
 }
@@ -393,6 +422,15 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
     b += (size_t)(T > 1 ? T - 1 : 1) * d.nb * d.nb * (4 + (d.precision == MVG_MIXED_BF16 ? 2 : 0));
   }
   return b;
+}
+
+int mvg_dst_band(int64_t n_loc, int nb, double keep_fraction) {
+  if (n_loc < 1 || nb < 1 || !(keep_fraction > 0.0) || keep_fraction > 1.0) return -1;
+  const int64_t T = (2 * n_loc + nb - 1) / nb;
+  const double need = keep_fraction * (double)T * (double)T;
+  for (int64_t w = 1; w < T; ++w)
+    if ((double)(T + (w - 1) * (2 * T - w)) >= need) return (int)w;
+  return (int)T;
 }
 
 int cov_generate(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,

@@ -113,8 +113,8 @@ __device__ __forceinline__ bool trail_decode(const TileMap &M, int k, int jlo, i
     return true;
   }
   int j = jlo;
-  while (q >= M.T - j) {
-    q -= M.T - j;
+  while (q >= M.iend - j) {
+    q -= M.iend - j;
     ++j;
   }
   const int i = j + (int)q;
@@ -570,7 +570,7 @@ __global__ void k_zero_upper_blocks(int nb, int k, double *__restrict__ winv) {
 // P <- the tiles (i, k), i in (k, T) (source of the out-of-place panel TRSM).
 __global__ void k_copy_panel(TileMap M, int k, double *__restrict__ P) {
   const int64_t per = (int64_t)M.nb * M.nb / 2;  // double2 per tile
-  const int64_t n = (int64_t)(M.T - k - 1) * per;
+  const int64_t n = (int64_t)(M.iend - k - 1) * per;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = e / per, o = e % per;
@@ -639,8 +639,8 @@ int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const Pi
   return 0;
 }
 
-// Useful flops of a trailing-update launch over tile columns [jlo, jhi]
-// (rows past N are padding).
+// Useful flops of a trailing-update launch over tile columns [jlo, jhi] and
+// tile rows below T (rows past N are padding).
 static double trailing_flops(int64_t N, int nb, int T, int k, int jlo, int jhi, bool skip_first) {
   auto len = [&](int t) { return (double)std::min<int64_t>(nb, N - (int64_t)t * nb); };
   const double K = len(k);
@@ -720,23 +720,25 @@ template int launch_trail<TRAIL_TRSM>(const TileMap &, int, int, int64_t, int64_
 template int launch_trail<TRAIL_BAND>(const TileMap &, int, int, int64_t, int64_t, const double *,
                                       const double *, hipStream_t);
 
-// Trailing update of step k: A_ij -= L_ik L_jk^T for k < j <= i, optionally
-// without the diagonal tile (k+1, k+1) (first = 0: that tile is left to the
-// look-ahead stream), or only that tile (only_first).
+// Trailing update of step k: A_ij -= L_ik L_jk^T for k < j <= i < M.iend,
+// optionally without the diagonal tile (k+1, k+1) (first = 0: that tile is
+// left to the look-ahead stream), or only that tile (only_first).  With a
+// DST band of w tiles L_ik = 0 for i >= k + w, so M.iend = min(T, k + w)
+// skips only zero products.
 static int trailing(const TileMap &M, int64_t N, int k, bool skip_first, bool only_first,
                     hipStream_t st) {
   const int jlo = k + 1;
-  if (jlo >= M.T) return 0;
+  if (jlo >= M.iend) return 0;
   const int s = M.nb / IB;
   const int64_t ss = (int64_t)s * s;
-  const int64_t ntile = only_first ? 1 : (int64_t)(M.T - jlo) * (M.T - jlo + 1) / 2;
+  const int64_t ntile = only_first ? 1 : (int64_t)(M.iend - jlo) * (M.iend - jlo + 1) / 2;
   const int64_t nwg = ntile * ss;
   const int64_t lid0 = skip_first ? ss : 0;
   if (lid0 >= nwg) return 0;
   const double flops = only_first ? (double)std::min<int64_t>(M.nb, N - (int64_t)jlo * M.nb) *
                                         ((double)std::min<int64_t>(M.nb, N - (int64_t)jlo * M.nb) + 1) *
                                         (double)std::min<int64_t>(M.nb, N - (int64_t)k * M.nb)
-                                  : trailing_flops(N, M.nb, M.T, k, jlo, M.T - 1, skip_first);
+                                  : trailing_flops(N, M.nb, M.iend, k, jlo, M.iend - 1, skip_first);
   const double bytes = 8.0 * (double)(ntile - (skip_first ? 1 : 0)) * M.nb * M.nb * 4.0;
   int h = prof_begin(MVG_PROF_TRAILING, st, flops, bytes);
   int rc = launch_trail<TRAIL_UPDATE>(M, k, jlo, lid0, nwg, nullptr, nullptr, st);
@@ -744,10 +746,10 @@ static int trailing(const TileMap &M, int64_t N, int k, bool skip_first, bool on
   return rc;
 }
 
-// Panel TRSM of step k: L_ik = A_ik W_k^T for i in (k, T), out of place from
-// a copy of the panel.
+// Panel TRSM of step k: L_ik = A_ik W_k^T for i in (k, M.iend), out of place
+// from a copy of the panel.
 static int panel_trsm(const TileMap &M, int k, const double *winv, double *P, hipStream_t st) {
-  const int nbelow = M.T - k - 1;
+  const int nbelow = M.iend - k - 1;
   if (nbelow <= 0) return 0;
   hipLaunchKernelGGL(k_copy_panel, dim3(1024), dim3(256), 0, st, M, k, P);
   if (int rc = check_launch("copy_panel")) return rc;
@@ -763,8 +765,16 @@ static int panel_trsm(const TileMap &M, int k, const double *winv, double *P, hi
 // factorisation with W_{k+1} (one tile of work, small footprint), so the
 // next panel TRSM never waits for the trailing update.
 int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
-  const TileMap M = A->map();
-  const int T = M.T;
+  const TileMap M0 = A->map();
+  const int T = M0.T;
+  // DST: tile rows at or beyond k + band of column k stay zero
+  const int dst_band = A->precision == MVG_DST ? A->band : T;
+  auto step_map = [&](int k) {
+    TileMap m = M0;
+    m.iend = std::min(T, k + dst_band);
+    return m;
+  };
+  const TileMap &M = M0;
   if (!A->d_winv) {
     set_error("dense_potrf: matrix has no inverse-tile store");
     return MVG_ERR_STATE;
@@ -789,7 +799,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventRecord(evD, side);
   for (int k = 0; k < T && !rc; ++k) {
     hipStreamWaitEvent(st, evD, 0);           // W_k ready
-    rc = panel_trsm(M, k, A->d_winv, P, st);  // L_ik, i > k
+    rc = panel_trsm(step_map(k), k, A->d_winv, P, st);  // L_ik, i > k
     hipEventRecord(evS, st);
     if (rc) break;
     if (k + 1 < T) {
@@ -797,7 +807,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
       rc = launch_syrk_next(A, k, side);  // SYRK of tile (k+1, k+1) by step k
       if (!rc) rc = diag_factor(M, k + 1, A->d_winv, d_info, pt, side);
       hipEventRecord(evD, side);
-      if (!rc) rc = trailing(M, A->N, k, true, false, st);  // the rest of step k
+      if (!rc) rc = trailing(step_map(k), A->N, k, true, false, st);  // the rest of step k
     }
   }
   hipEventRecord(evD, side);

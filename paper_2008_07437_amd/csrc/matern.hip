@@ -67,10 +67,11 @@ __global__ __launch_bounds__(256) void k_cov_tiles(MaternArgs P, const double *_
                                                    const double *__restrict__ ys, int64_t n_loc,
                                                    TileMap M, int tile_first, int spt) {
   __shared__ double sq[4 * QN];
-  load_qtab(qtab, sq);
   const int nsub = spt * spt;
   const int64_t tile = tile_first + blockIdx.x / nsub;
   const int sub = blockIdx.x % nsub;
+  if (M.kind && M.kind[tile] == TK_ZERO) return;  // annihilated DST tile (whole workgroup)
+  load_qtab(qtab, sq);
   int J = 0;
   int64_t t = tile;
   while (t >= M.T - J) {

@@ -56,7 +56,9 @@ __host__ __device__ inline int64_t tidx(int I, int J, int T) {
   return (int64_t)J * T - ((int64_t)J * (J - 1)) / 2 + (I - J);
 }
 
-enum TileKind : int { TK_F64 = 0, TK_F32 = 1 };
+// TK_ZERO: an annihilated DST tile; every such tile maps to one shared,
+// zero-filled FP64 tile that nothing writes.
+enum TileKind : int { TK_F64 = 0, TK_F32 = 1, TK_ZERO = 2 };
 
 // Tile storage: base + off[tidx] bytes, column-major inside the tile, ld = nb.
 struct TileMap {
@@ -64,6 +66,7 @@ struct TileMap {
   const int64_t *off;  // device array, T(T+1)/2 byte offsets
   const int *kind;     // device array, TileKind per tile (nullptr: all F64)
   int T, nb;
+  int iend;            // trailing updates touch tile rows < iend (T, or the DST band end)
 };
 
 struct TlrState;
@@ -86,7 +89,7 @@ struct mvg_mat {
   mvg_opts opts{};
   mvg::MaternArgs margs{};
   mvg::TlrState *tlr = nullptr;   // TLR storage (precision == MVG_TLR)
-  mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb}; }
+  mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb, T}; }
 };
 
 struct mvg_factor {

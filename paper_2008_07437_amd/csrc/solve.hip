@@ -148,7 +148,8 @@ constexpr int GEMM_RHS_MIN = 4;
 enum { TS_FORWARD = 0, TS_BACKWARD = 1, TS_TRMM_T = 2 };
 
 static bool gemm_solve_ok(const mvg_mat *A, int nrhs) {
-  return A->precision == MVG_FP64 && !A->tlr && A->h_off && nrhs >= GEMM_RHS_MIN;
+  return (A->precision == MVG_FP64 || A->precision == MVG_DST) && !A->tlr && A->h_off &&
+         nrhs >= GEMM_RHS_MIN;
 }
 
 static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int mode,
@@ -159,6 +160,7 @@ static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int
     return (const double *)(A->arena + A->h_off[tidx(I, J, T)]);
   };
   auto W = [&](int k) { return (const double *)A->d_winv + (int64_t)k * nb * nb; };
+  auto zero = [&](int I, int J) { return A->h_kind && A->h_kind[tidx(I, J, T)] == TK_ZERO; };
   auto task = [&](const double *a, int ta, int tri, const double *b, double *c, double alpha,
                   double beta) {
     return GemmTask{a, b, c, nb, nrhs, nb, nb, ld, ld, ta, 0, alpha, beta, tri};
@@ -186,7 +188,8 @@ static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int
       if (k + 1 < T) {
         f = tasks.size();
         for (int i = k + 1; i < T; ++i)
-          tasks.push_back(task(L(i, k), 0, 0, Y + k * tstride, X + i * tstride, -1.0, 1.0));
+          if (!zero(i, k))
+            tasks.push_back(task(L(i, k), 0, 0, Y + k * tstride, X + i * tstride, -1.0, 1.0));
         close(f);
       }
     }
@@ -198,7 +201,8 @@ static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int
       if (k > 0) {
         f = tasks.size();
         for (int j = 0; j < k; ++j)
-          tasks.push_back(task(L(k, j), 1, 0, Y + k * tstride, X + j * tstride, -1.0, 1.0));
+          if (!zero(k, j))
+            tasks.push_back(task(L(k, j), 1, 0, Y + k * tstride, X + j * tstride, -1.0, 1.0));
         close(f);
       }
     }
@@ -206,8 +210,9 @@ static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int
     for (int d = 0; d < T; ++d) {
       const size_t f = tasks.size();
       for (int J = 0; J + d < T; ++J)
-        tasks.push_back(task(L(J + d, J), 1, d == 0, X + (J + d) * tstride, Y + J * tstride, 1.0,
-                             d == 0 ? 0.0 : 1.0));
+        if (d == 0 || !zero(J + d, J))
+          tasks.push_back(task(L(J + d, J), 1, d == 0, X + (J + d) * tstride, Y + J * tstride,
+                               1.0, d == 0 ? 0.0 : 1.0));
       close(f);
     }
   }

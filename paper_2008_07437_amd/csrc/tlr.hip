@@ -378,7 +378,7 @@ int tlr_build(mvg_mat *A, const mvg_opts &o, hipStream_t st) {
     HostLists L;
     const int64_t *doff = (const int64_t *)L.stage(off.data(), off.size() * 8, st, &rc);
     if (rc) break;
-    const TileMap M{(char *)G, doff, nullptr, T, nb};
+    const TileMap M{(char *)G, doff, nullptr, T, nb, T};
     rc = launch_cov_tiles(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, M, (int)t0, (int)cnt, st);
     std::vector<CopyTask> c;
     std::vector<CompressJob> jobs;
@@ -427,7 +427,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   int rc = 0;
   const int64_t *d_doff = (const int64_t *)L0.stage(doff.data(), doff.size() * 8, st, &rc);
   if (rc) return rc;
-  const TileMap Md{(char *)Lf.diag, d_doff, nullptr, T, nbp};
+  const TileMap Md{(char *)Lf.diag, d_doff, nullptr, T, nbp, T};
   double *P = nullptr;  // dense panel: (T - j) nb x nb, ld (T - j) nb
   if (hipMallocAsync((void **)&P, sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
     hipGetLastError();

@@ -80,6 +80,28 @@ def test_footprint_host_logic():
 
 
 @pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
+def test_dst_band_matches_oracle_and_footprint_shrinks(orc):
+    """mvg_dst_band (host arithmetic) equals the oracle's tile-by-tile count
+    for every size, tile and fraction tried (bit-exact integer); a DST
+    matrix stores only its kept tiles plus one zero tile."""
+    lib = _lib_cpu()
+    lib.mvg_dst_band.restype = ctypes.c_int
+    lib.mvg_dst_band.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_double]
+    for n in (1, 64, 100, 1000, 1337, 25600):
+        for nb in (128, 256, 512):
+            T = (2 * n + nb - 1) // nb
+            for keep in (0.05, 0.3, 0.4, 0.5, 0.7, 0.999, 1.0):
+                assert lib.mvg_dst_band(n, nb, keep) == orc.dst_band(T, keep), (n, nb, keep)
+    assert lib.mvg_dst_band(1000, 128, 0.0) == -1 and lib.mvg_dst_band(1000, 128, 1.5) == -1
+    assert lib.mvg_dst_band(0, 128, 0.4) == -1
+    fp = lambda n, **kw: lib.mvg_footprint(n, ctypes.byref(_opts(**kw)))  # noqa: E731
+    w = lib.mvg_dst_band(25600, 512, 0.4)
+    dst, dense = fp(25600, nb=512, precision=4, band_tiles=w), fp(25600, nb=512)
+    assert dst < 0.75 * dense
+    assert fp(25600, nb=512, precision=4, band_tiles=100) == dense
+
+
+@pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
 def test_server_rejects_bad_arguments_without_a_device():
     lib = ctypes.CDLL(SO)
     lib.mvg_server_create.restype = ctypes.c_void_p

@@ -452,3 +452,46 @@ def test_cross_cov_targets_matches_entries(orc):
             for i in range(2):
                 for j in range(2):
                     assert abs(c0[2 * r + i, 2 * l + j] - orc.cross_cov(th, i, j, h)) <= 1e-14
+
+
+# ----------------------------------------------- DST (Section 4.4, 6.4.1)
+
+def test_dst_band_counts(orc):
+    """The kept tile count reaches the fraction at w and not at w - 1; a
+    fraction of 1 keeps every tile; one tile per side keeps it."""
+    for T in (1, 2, 7, 20, 43):
+        for keep in (0.05, 0.4, 0.7, 1.0):
+            w = orc.dst_band(T, keep)
+            cnt = lambda v: sum(1 for I in range(T) for J in range(T)  # noqa: E731
+                                if abs(I - J) < v)      # brute-force tile count
+            assert cnt(w) >= keep * T * T
+            assert w == 1 or cnt(w - 1) < keep * T * T
+    assert orc.dst_band(20, 1.0) == 20 and orc.dst_band(1, 0.4) == 1
+    # DST 40/60 and 70/30 at 100 tiles per side: w ~ T (1 - sqrt(1 - keep))
+    assert abs(orc.dst_band(100, 0.4) - 100 * (1 - np.sqrt(0.6))) <= 2
+    assert abs(orc.dst_band(100, 0.7) - 100 * (1 - np.sqrt(0.3))) <= 2
+
+
+def test_dst_full_band_is_exact_and_band_one_splits(orc):
+    """band >= T leaves Sigma unchanged (the exact likelihood); band = 1 makes
+    Sigma block diagonal, so the likelihood is the sum of the diagonal
+    blocks' likelihoods, each checked with scipy's multivariate normal."""
+    from scipy.stats import multivariate_normal
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y = synthetic.jittered_grid(90, 3)
+    p = orc.morton_order(x, y)
+    x, y = x[p], y[p]
+    z = orc.simulate_z(x, y, th, synthetic.normal_eps(180, 3))
+    S = orc.cov_dense(x, y, th)
+    nb = 40
+    T = (180 + nb - 1) // nb
+    full = orc.loglik_from_matrix(orc.dst_mask(S, nb, T), z)
+    ex = orc.loglik(x, y, z, th)["loglik"]
+    assert abs(full["loglik"] - ex) <= 1e-12 * abs(ex)
+    diag = orc.loglik_from_matrix(orc.dst_mask(S, nb, 1), z)
+    ref = sum(multivariate_normal(mean=np.zeros(len(z[a:a + nb])),
+                                  cov=S[a:a + nb, a:a + nb]).logpdf(z[a:a + nb])
+              for a in range(0, 180, nb))
+    assert abs(diag["loglik"] - ref) <= 1e-9 * abs(ref)
+    M = orc.dst_mask(S, nb, 2)
+    assert np.all(M[:nb, 2 * nb:] == 0) and np.array_equal(M[:2 * nb, :2 * nb], S[:2 * nb, :2 * nb])
