@@ -277,6 +277,50 @@ def run_mloe(args, mvg, dev, synthetic, torch):
           comp_tflops=sol["flops"] / (sol["ms"] * 1e9) if sol["ms"] else None)
 
 
+def run_trivariate(args, mvg, dev, synthetic, torch):
+    """The p = 3 model (the trivariate application's form, Section 6.4.2) at
+    the dense workload's matrix order: n = 17,066 locations, 51,198 x 51,198,
+    Eq. (1) and the profile likelihood of Section 5.2 (three univariate
+    17,066 x 17,066 factorisations, then Eq. (1))."""
+    n = args.n
+    th = {"sigma_sq": [1.0, 1.0, 1.0], "a": args.a, "nu": [0.5, 1.0, 1.5],
+          "beta": [[1.0, 0.5, -0.3], [0.5, 1.0, -0.2], [-0.3, -0.2, 1.0]]}
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    o = {"nb": args.nb}
+    A = mvg.cov_generate_p(xs, ys, th, o)       # Z = L eps at the true theta (setup)
+    if mvg.potrf_tiled(A):
+        raise SystemExit("trivariate Sigma(theta) not positive definite")
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(3 * n, args.seed)))
+    del A
+    for _ in range(args.warmup):
+        mvg.loglik_p(xs, ys, z, th, o)
+    torch.cuda.synchronize()
+    mvg.mvg_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = mvg.loglik_p(xs, ys, z, th, o)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    prof = {k: mvg.mvg_prof_read(k) for k in ("gen", "potrf")}
+    mvg.mvg_prof_enable(False)
+    N = 3 * n
+    potrf_ms = prof["potrf"]["ms"] / max(1, prof["potrf"]["launches"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof_ll = mvg.profile_loglik_p(xs, ys, z, th, o)
+    torch.cuda.synchronize()
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          1.0 / dt, "evals/s", args.steps, args.warmup, 1e3 * dt, "f64",
+          {"workload": "trivariate parsimonious Matern loglik, N=%d locations (%dx%d), nb %d"
+                       % (n, N, N, args.nb), "n_loc": n, "p": 3, "precision": "fp64"},
+          loglik=float(r["loglik"][0]), status=int(r["status"][0]),
+          cholesky_tflops=(N ** 3 / 3.0) / (potrf_ms * 1e-3) / 1e12,
+          gen_ms=prof["gen"]["ms"] / max(1, prof["gen"]["launches"]),
+          profile_loglik={"seconds": time.perf_counter() - t1, "loglik": prof_ll["loglik"],
+                          "sigma_sq": [float(v) for v in prof_ll["sigma_sq"]]})
+
+
 def serve_stream(args, mvg, dev, synthetic, torch, rate, nreq):
     """One Poisson stream through a fresh server; returns its summary."""
     import threading
@@ -369,10 +413,10 @@ def main():
     ap.add_argument("--wide-band", type=int, default=16,
                     help="second, wider FP64 band for the FP32 variant")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe", "trivariate"],
                     help="dense: N=25,600 FP64 (+ mixed variants); tlr: N=100,000 TLR; batched: "
                          "many theta at N=400 in one launch; serving: request stream; mloe: "
-                         "MLOE/MMOM at N=25,600 with 100 targets")
+                         "MLOE/MMOM at N=25,600 with 100 targets; trivariate: p = 3 at N=17,066")
     ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
     ap.add_argument("--no-dense-ref", action="store_true")
     ap.add_argument("--batch", type=int, default=1024)
@@ -416,6 +460,9 @@ def main():
         return run_serving(args, mvg, dev, synthetic, torch)
     if args.workload == "mloe":
         return run_mloe(args, mvg, dev, synthetic, torch)
+    if args.workload == "trivariate":
+        args.n = 17066 if args.n == 25600 else args.n
+        return run_trivariate(args, mvg, dev, synthetic, torch)
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     n = args.n
     # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)

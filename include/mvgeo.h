@@ -172,6 +172,59 @@ int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_the
               const mvg_opts *o, double *h_mloe, double *h_mmom, double *d_loe, double *d_mom,
               void *hip_stream);
 
+/* ------------------------------------------------------------ p variables
+ *
+ * The parsimonious multivariate Matern of Section 4.2 for p = 1..MVG_PMAX
+ * variables (the trivariate model of the application in Section 6.4.2 is
+ * p = 3): Eq. (2) for i, j = 1..p with nu_ij = (nu_ii + nu_jj) / 2 and
+ * rho_ij = beta_ij sqrt(nu_ii nu_jj) / nu_ij (d = 2, rho_ii = 1), in
+ * Representation I: Sigma[p l + i, p r + j] = C_ij(||s_l - s_r||), Z
+ * interleaved (Z_1(s_1), .., Z_p(s_1), Z_1(s_2), ..). */
+#define MVG_PMAX 4
+
+/* theta of the p-variate model.  Admissible values: 1 <= p <= MVG_PMAX,
+ * sigma_sq[i] > 0, a > 0, 0 < nu[i] <= 5, beta (row-major p x p, entries
+ * i, j < p only) symmetric with unit diagonal and positive definite (checked
+ * by a Cholesky factorisation on the host). */
+typedef struct {
+    int p;
+    double sigma_sq[MVG_PMAX];
+    double a;
+    double nu[MVG_PMAX];
+    double beta[MVG_PMAX * MVG_PMAX];
+} mvg_theta_p;
+
+/* Eq. (1) for the p-variate model:
+ *   l(theta) = -(p n_loc / 2) log(2 pi) - 1/2 log|Sigma| - 1/2 Z^T Sigma^-1 Z,
+ * d_z: p * n_loc FP64 (interleaved as above).  Precision MVG_FP64 or MVG_DST
+ * (p = 2 also takes every precision of loglik, through loglik itself, with
+ * identical results).  Outputs as for loglik.  Returns 0, -1..-8 for bad
+ * arguments (-5: an invalid theta; -7: bad or unsupported options for this
+ * p), MVG_ERR_*. */
+int loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+             const mvg_theta_p *th, int n_theta, const mvg_opts *o, double *h_loglik,
+             double *h_logdet, double *h_quad, int64_t *h_status, void *hip_stream);
+
+/* Generate Sigma(theta) of the p-variate model into a new library-owned
+ * matrix (as cov_generate; precision MVG_FP64 or MVG_DST; p = 2 takes
+ * cov_generate's path).  Returns 0, -1..-7, MVG_ERR_*. */
+int cov_generate_p(const double *d_x, const double *d_y, int64_t n_loc,
+                   const mvg_theta_p *th, const mvg_opts *o, mvg_mat **out,
+                   void *hip_stream);
+
+/* Profile likelihood of Section 5.2: the marginal variances are replaced by
+ *   sigma_ii^2 = n^-1 Z_i^T R_ii^-1 Z_i,
+ * R_ii the n x n correlation matrix of variable i alone (nu_ii, a, unit
+ * variance; one univariate factorisation each), then Eq. (1) is evaluated at
+ * theta with those variances (th->sigma_sq is not read).  h_sigma_sq
+ * receives the p estimates; the other outputs as for loglik_p (one theta).
+ * A failing univariate factorisation gives *h_status = -(1 + i) for
+ * variable i.  Returns 0, -1..-9, MVG_ERR_*. */
+int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                     const mvg_theta_p *th, const mvg_opts *o, double *h_sigma_sq,
+                     double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
+                     void *hip_stream);
+
 /* One task of loglik_many: a dataset (device pointers, caller-owned) and a
  * theta. */
 typedef struct {
@@ -220,6 +273,9 @@ int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_strea
 /* HBM bytes the library allocates for one likelihood evaluation of n_loc
  * locations with these options (matrix + workspaces), for admission control. */
 size_t mvg_footprint(int64_t n_loc, const mvg_opts *o);
+
+/* Number of variables p of a matrix (its order is p n_loc), or -1. */
+int mvg_mat_nvar(const mvg_mat *A);
 
 /* Shape of a matrix: n_loc, tile size, tile count per side, precision,
  * factored flag.  Any output pointer may be NULL. */

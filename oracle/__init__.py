@@ -24,6 +24,10 @@ Each function states the passage of the paper it follows:
   the mixed-precision error.
 * ``cross_cov_targets`` / ``mloe_mmom`` -- the multivariate prediction
   efficiency criteria of Section 5.4 (Eq. (5)-(8), Algorithm 1).
+* ``theta_p_check`` / ``rho_p`` / ``cov_dense_p`` / ``loglik_p`` /
+  ``profile_loglik_p`` -- the parsimonious multivariate Matern for p
+  variables (Section 4.2, Eq. (1)-(2)) and the profile likelihood of
+  Section 5.2.
 * ``dst_band`` / ``dst_mask`` -- the Diagonal Super Tile approximation
   (Section 4.4; "DST 40/60" and "DST 70/30" of Experiment 2, Section 6.4.1):
   the tiles far from the diagonal set to zero.
@@ -459,4 +463,93 @@ def dst_mask(S: np.ndarray, nb: int, band: int) -> np.ndarray:
         for c in range(N):
             if abs(r // nb - c // nb) >= band:
                 out[r, c] = 0.0
+    return out
+
+
+# ------------------------------------------------------------ p variables
+
+def _theta_p(th):
+    sig = np.asarray(th["sigma_sq"], dtype=np.float64).ravel()
+    p = sig.size
+    nu = np.asarray(th["nu"], dtype=np.float64).ravel()
+    beta = np.asarray(th["beta"], dtype=np.float64).reshape(p, p)
+    return p, sig, float(th["a"]), nu, beta
+
+
+def theta_p_check(th) -> int:
+    """Section 4.2: sigma_ii^2 > 0, a > 0, nu_ii > 0 (<= 5 as for p = 2) and
+    (beta_ij) a symmetric positive definite correlation matrix.  0 or a
+    negative code (-1 p, -2 variances, -3 range, -4 smoothness, -5 beta)."""
+    p, sig, a, nu, beta = _theta_p(th)
+    if not 1 <= p <= 4 or nu.size != p:
+        return -1
+    if not np.all(sig > 0):
+        return -2
+    if not a > 0:
+        return -3
+    if not np.all((nu > 0) & (nu <= 5)):
+        return -4
+    if not np.array_equal(beta, beta.T) or not np.all(np.diag(beta) == 1.0):
+        return -5
+    if np.min(np.linalg.eigvalsh(beta)) <= 0:
+        return -5
+    return 0
+
+
+def rho_p(th) -> np.ndarray:
+    """Colocated correlations rho_ij of Section 4.2 for d = 2, from the Gamma
+    function itself (the third factor read without the square root, as for
+    p = 2); rho_ii = 1."""
+    p, sig, a, nu, beta = _theta_p(th)
+    r = np.empty((p, p))
+    for i in range(p):
+        for j in range(p):
+            nij = 0.5 * (nu[i] + nu[j])
+            r[i, j] = (beta[i, j] * np.sqrt(gamma(nu[i] + 1.0) / gamma(nu[i]))
+                       * np.sqrt(gamma(nu[j] + 1.0) / gamma(nu[j])) * gamma(nij) / gamma(nij + 1.0))
+    return r
+
+
+def cov_dense_p(x, y, th) -> np.ndarray:
+    """Sigma of the p-variate model in Representation I (Section 5.2):
+    entry (p l + i, p r + j) = rho_ij sigma_i sigma_j M(||s_l - s_r|| / a; nu_ij)."""
+    if theta_p_check(th):
+        raise ValueError("invalid theta_p")
+    p, sig, a, nu, beta = _theta_p(th)
+    xa, ya = _f64(x), _f64(y)
+    n = xa.size
+    h = np.sqrt((xa[:, None] - xa[None, :]) ** 2 + (ya[:, None] - ya[None, :]) ** 2)
+    rho = rho_p(th)
+    S = np.empty((p * n, p * n))
+    for i in range(p):
+        for j in range(p):
+            M = matern(h.ravel() / a, 0.5 * (nu[i] + nu[j])).reshape(n, n)
+            S[i::p, j::p] = rho[i, j] * np.sqrt(sig[i]) * np.sqrt(sig[j]) * M
+    return S
+
+
+def loglik_p(x, y, z, th) -> dict:
+    """Eq. (1) for p variables (-(p n / 2) log 2 pi - log|Sigma| / 2 - q / 2)."""
+    return loglik_from_matrix(cov_dense_p(x, y, th), z)
+
+
+def profile_loglik_p(x, y, z, th) -> dict:
+    """Section 5.2: sigma_ii^2 = n^-1 Z_i^T R_ii^-1 Z_i with R_ii the
+    correlation matrix of variable i alone (unit variance, nu_ii, a), then
+    Eq. (1) at theta with those variances."""
+    p, sig, a, nu, beta = _theta_p(th)
+    za = _f64(z)
+    n = za.size // p
+    s_hat = np.empty(p)
+    for i in range(p):
+        R = cov_dense_p(x, y, {"sigma_sq": [1.0], "a": a, "nu": [nu[i]], "beta": [[1.0]]})
+        L, info = potrf(R)
+        if info:
+            raise ValueError("R_%d%d not positive definite" % (i + 1, i + 1))
+        u = trsv_lower(L, za[i::p])
+        s_hat[i] = float(np.dot(u, u)) / n
+    full = dict(th)
+    full["sigma_sq"] = list(s_hat)
+    out = loglik_p(x, y, z, full)
+    out["sigma_sq"] = s_hat
     return out

@@ -34,6 +34,35 @@ class Theta(ctypes.Structure):
         return cls(*t)
 
 
+PMAX = 4
+
+
+class ThetaP(ctypes.Structure):
+    """theta of the p-variate model: {'sigma_sq': [p], 'a': a, 'nu': [p],
+    'beta': p x p} (beta symmetric, unit diagonal, positive definite)."""
+    _fields_ = [("p", c_int), ("sigma_sq", c_double * PMAX), ("a", c_double),
+                ("nu", c_double * PMAX), ("beta", c_double * (PMAX * PMAX))]
+
+    @classmethod
+    def of(cls, t) -> "ThetaP":
+        if isinstance(t, cls):
+            return t
+        s = [float(v) for v in t["sigma_sq"]]
+        p = len(s)
+        if not 1 <= p <= PMAX or len(t["nu"]) != p:
+            raise ValueError("theta_p: 1 <= p <= %d variables, one nu per variable" % PMAX)
+        b = np.asarray(t["beta"], dtype=np.float64).reshape(p, p)
+        out = cls()
+        out.p = p
+        out.a = float(t["a"])
+        for i in range(p):
+            out.sigma_sq[i] = s[i]
+            out.nu[i] = float(t["nu"][i])
+            for j in range(p):
+                out.beta[i * PMAX + j] = float(b[i, j])
+        return out
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("nb", c_int), ("band_tiles", c_int),
                 ("tlr_acc", c_double), ("tlr_max_rank", c_int), ("seed", ctypes.c_uint64),
@@ -73,9 +102,13 @@ def _load():
         "tlr_compress": (c_int, [P, P, c_int64, P, P, P, P, P]),
         "cokrige_predict": (c_int, [P, P, P, c_int64, P, P, P]),
         "mloe_mmom": (c_int, [P, P, c_int64, P, P, P, P, c_int64, P, P, P, P, P, P]),
+        "loglik_p": (c_int, [P, P, P, c_int64, P, c_int, P, P, P, P, P, P]),
+        "cov_generate_p": (c_int, [P, P, c_int64, P, P, P, P]),
+        "profile_loglik_p": (c_int, [P, P, P, c_int64, P, P, P, P, P, P, P, P]),
         "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
         "mvg_dst_band": (c_int, [c_int64, c_int, c_double]),
         "mvg_mat_shape": (c_int, [P, P, P, P, P, P]),
+        "mvg_mat_nvar": (c_int, [P]),
         "mvg_mat_gather": (c_int, [P, P, P, c_int64, P, P]),
         "mvg_mat_to_dense": (c_int, [P, P, c_int64, P]),
         "mvg_factor_mat": (P, [P]),
@@ -158,8 +191,8 @@ class Mat:
         return out
 
     def to_dense(self, stream=None) -> torch.Tensor:
-        """Lower triangle as a dense (2n, 2n) tensor (strict upper part 0)."""
-        N = 2 * self.shape()["n_loc"]
+        """Lower triangle as a dense (p n, p n) tensor (strict upper part 0)."""
+        N = _load().mvg_mat_nvar(self._h) * self.shape()["n_loc"]
         buf = torch.empty((N, N), dtype=torch.float64, device="cuda")  # column-major view
         _check("mvg_mat_to_dense", _load().mvg_mat_to_dense(self._h, c_void_p(buf.data_ptr()), N,
                                                            _stream(stream)))
@@ -241,6 +274,49 @@ def cov_generate(x, y, theta, opts=None, stream=None) -> Mat:
                                                ctypes.byref(th), ctypes.byref(o), ctypes.byref(h),
                                                _stream(stream)))
     return Mat(h)
+
+
+def cov_generate_p(x, y, theta_p, opts=None, stream=None) -> Mat:
+    """Sigma of the p-variate model (Representation I, p x p blocks)."""
+    h = c_void_p()
+    th = ThetaP.of(theta_p)
+    o = _opts(opts)
+    _check("cov_generate_p", _load().cov_generate_p(_dev_f64(x, "x"), _dev_f64(y, "y"), x.numel(),
+                                                   ctypes.byref(th), ctypes.byref(o),
+                                                   ctypes.byref(h), _stream(stream)))
+    return Mat(h)
+
+
+def loglik_p(x, y, z, thetas_p, opts=None, stream=None) -> dict:
+    """Eq. (1) for the p-variate model; thetas_p: one theta dict or a list."""
+    ths = [thetas_p] if isinstance(thetas_p, (dict, ThetaP)) else list(thetas_p)
+    k = len(ths)
+    arr = (ThetaP * k)(*[ThetaP.of(t) for t in ths])
+    ll, ld, q = np.zeros(k), np.zeros(k), np.zeros(k)
+    st = np.zeros(k, dtype=np.int64)
+    o = _opts(opts)
+    _check("loglik_p", _load().loglik_p(_dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"),
+                                        x.numel(), arr, k, ctypes.byref(o),
+                                        ll.ctypes.data_as(c_void_p), ld.ctypes.data_as(c_void_p),
+                                        q.ctypes.data_as(c_void_p), st.ctypes.data_as(c_void_p),
+                                        _stream(stream)))
+    return {"loglik": ll, "logdet": ld, "quad": q, "status": st}
+
+
+def profile_loglik_p(x, y, z, theta_p, opts=None, stream=None) -> dict:
+    """Section 5.2 profile likelihood: sigma_ii^2 = Z_i^T R_ii^-1 Z_i / n, then
+    Eq. (1) at those variances (theta_p's own variances are not read)."""
+    th = ThetaP.of(theta_p)
+    s2 = np.zeros(th.p)
+    ll, ld, q = c_double(), c_double(), c_double()
+    st = c_int64()
+    o = _opts(opts)
+    _check("profile_loglik_p", _load().profile_loglik_p(
+        _dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"), x.numel(), ctypes.byref(th),
+        ctypes.byref(o), s2.ctypes.data_as(c_void_p), ctypes.byref(ll), ctypes.byref(ld),
+        ctypes.byref(q), ctypes.byref(st), _stream(stream)))
+    return {"sigma_sq": s2, "loglik": ll.value, "logdet": ld.value, "quad": q.value,
+            "status": st.value}
 
 
 def potrf_tiled(mat: Mat, opts=None, stream=None) -> int:

@@ -10,7 +10,8 @@ SOURCES = ["capi.hip", "matern.hip", "dense.hip", "solve.hip", "mixed.hip", "mor
            "tlr_kernels.hip", "batched.hip", "serve.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-Wno-unused-value"]
+         "-Wno-unused-result", "-Wno-unused-value",
+         "-Wl,-z,defs"]  # an unresolved symbol fails the link, not the first load
 
 
 def build(verbose: bool = False) -> str:

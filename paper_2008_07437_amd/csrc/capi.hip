@@ -185,6 +185,19 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   return 0;
 }
 
+PivotTol mvg::pivot_tol(const mvg_mat *A) {
+  PivotTol t{};
+  t.p = A->p;
+  if (A->p == 2) {
+    t.tol[0] = 0x1p-40 * A->theta.sigma11_sq;
+    t.tol[1] = 0x1p-40 * A->theta.sigma22_sq;
+  } else {
+    for (int i = 0; i < A->p; ++i) t.tol[i] = 0x1p-40 * A->theta_p.sigma_sq[i];
+  }
+  t.N = A->N;
+  return t;
+}
+
 static void mat_free(mvg_mat *A) {
   if (!A) return;
   tlr_state_free(A->tlr);
@@ -252,22 +265,55 @@ static size_t layout_bytes(int64_t n_loc, const mvg_opts &o) {
   return total;
 }
 
+// Tile storage for p variables (N = p n_loc); the caller sets theta.
+static int mat_alloc(int64_t n_loc, int p, const mvg_opts &o, const double *d_x, const double *d_y,
+                     hipStream_t st, mvg_mat **out);
+
 static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, const double *d_x,
                       const double *d_y, hipStream_t st, mvg_mat **out) {
+  MaternArgs margs;
+  if (int rc = matern_setup(th, &margs)) return rc;
+  mvg_mat *A = nullptr;
+  if (int rc = mat_alloc(n_loc, 2, o, d_x, d_y, st, &A)) return rc;
+  A->theta = *th;
+  A->margs = margs;
+  *out = A;
+  return 0;
+}
+
+// p-variate matrix; p = 2 keeps the bivariate kernels (theta converted).
+static mvg_theta theta_from_p(const mvg_theta_p &t) {
+  return mvg_theta{t.sigma_sq[0], t.sigma_sq[1], t.a, t.nu[0], t.nu[1], t.beta[1]};
+}
+
+static int mat_create_p(int64_t n_loc, const mvg_opts &o, const mvg_theta_p *th,
+                        const double *d_x, const double *d_y, hipStream_t st, mvg_mat **out) {
+  MaternArgsP mp;
+  if (int rc = matern_setup_p(th, &mp)) return rc;
+  if (th->p == 2) {
+    const mvg_theta t2 = theta_from_p(*th);
+    return mat_create(n_loc, o, &t2, d_x, d_y, st, out);
+  }
+  mvg_mat *A = nullptr;
+  if (int rc = mat_alloc(n_loc, th->p, o, d_x, d_y, st, &A)) return rc;
+  A->theta_p = *th;
+  A->margs_p = mp;
+  *out = A;
+  return 0;
+}
+
+static int mat_alloc(int64_t n_loc, int p, const mvg_opts &o, const double *d_x, const double *d_y,
+                     hipStream_t st, mvg_mat **out) {
   mvg_mat *A = new mvg_mat();
   A->n_loc = n_loc;
-  A->N = 2 * n_loc;
+  A->p = p;
+  A->N = (int64_t)p * n_loc;
   A->nb = o.nb;
   A->T = (int)((A->N + o.nb - 1) / o.nb);
   A->Np = (int64_t)A->T * o.nb;
   A->precision = o.precision;
   A->band = o.band_tiles;
-  A->theta = *th;
   A->opts = o;
-  if (int rc = matern_setup(th, &A->margs)) {
-    delete A;
-    return rc;
-  }
   const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
   A->h_off = new int64_t[nt];
   A->h_kind = new int[nt];
@@ -280,7 +326,7 @@ static int mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th, con
   ok = ok && hipMalloc(&A->d_kind, sizeof(int) * nt) == hipSuccess;
   ok = ok && hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
   ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
+  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * (1 + PORD) * QN) == hipSuccess;
   ok = ok && hipMalloc(&A->d_winv, sizeof(double) * (size_t)A->Np * A->nb) == hipSuccess;
   if (!ok) {
     hipGetLastError();
@@ -349,9 +395,13 @@ static int tlr_generate(mvg_mat *A, hipStream_t st) {
 
 // Regenerate Sigma(theta) into an existing matrix of the same shape.
 static int mat_generate(mvg_mat *A, hipStream_t st) {
+  A->factored = 0;
+  if (A->p != 2) {
+    if (int rc = launch_quad_table_p(A->margs_p, A->d_qtab, st)) return rc;
+    return launch_cov_tiles_p(A->margs_p, A->d_qtab, A->d_x, A->d_y, A->n_loc, A->map(), st);
+  }
   if (int rc = launch_quad_table(A->margs, A->d_qtab, st)) return rc;
   const int64_t nt = (int64_t)A->T * (A->T + 1) / 2;
-  A->factored = 0;
   return launch_cov_tiles(A->margs, A->d_qtab, A->d_x, A->d_y, A->n_loc, A->map(), 0, (int)nt, st);
 }
 
@@ -911,6 +961,196 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   return 0;
 }
 
+// ------------------------------------------------------------ p variables
+
+static bool p_precision_ok(const mvg_opts &d) {
+  return d.precision == MVG_FP64 || d.precision == MVG_DST;
+}
+
+int cov_generate_p(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta_p *th,
+                   const mvg_opts *o, mvg_mat **out, void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (n_loc < 1) return -3;
+  if (!th) return -4;
+  mvg_opts d;
+  if (normalize_opts(o, &d)) return -5;
+  if (!out) return -6;
+  MaternArgsP tmp;
+  if (matern_setup_p(th, &tmp)) return -4;
+  if (th->p == 2) {
+    const mvg_theta t2 = theta_from_p(*th);
+    return cov_generate(d_x, d_y, n_loc, &t2, o, out, hip_stream);
+  }
+  if (!p_precision_ok(d)) return -5;
+  hipStream_t st = (hipStream_t)hip_stream;
+  mvg_mat *A = nullptr;
+  if (int rc = mat_create_p(n_loc, d, th, d_x, d_y, st, &A)) return rc < 0 && rc > -100 ? -4 : rc;
+  if (int rc = mat_generate(A, st)) {
+    mat_free(A);
+    return rc;
+  }
+  *out = A;
+  return 0;
+}
+
+// Eq. (1) for p != 2 variables, n_theta thetas on one matrix (FP64 / DST).
+static int loglik_p_run(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                        const mvg_theta_p *th, int n_theta, const mvg_opts &d, double *h_loglik,
+                        double *h_logdet, double *h_quad, int64_t *h_status, hipStream_t st) {
+  mvg_mat *A = nullptr;
+  int rc = mat_create_p(n_loc, d, &th[0], d_x, d_y, st, &A);
+  if (rc) return rc;
+  const int nred = (int)((A->N + 4095) / 4096);
+  double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2 n_theta) | info (n_theta)
+  const size_t ws_n = (size_t)A->Np + 2 * nred + 2 * n_theta + n_theta;
+  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+    hipGetLastError();
+    mat_free(A);
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  double *d_yv = ws, *d_part = ws + A->Np, *d_out2 = d_part + 2 * nred;
+  int64_t *d_info = reinterpret_cast<int64_t *>(d_out2 + 2 * n_theta);
+  for (int i = 0; i < n_theta && !rc; ++i) {
+    if (i > 0) {
+      A->theta_p = th[i];
+      matern_setup_p(&th[i], &A->margs_p);
+    }
+    int hg = prof_begin(MVG_PROF_GEN, st, 0.0, 8.0 * (double)A->N * (A->N + 1) / 2);
+    rc = mat_generate(A, st);
+    prof_end(hg, st);
+    if (!rc) rc = eval_one(A, d_z, d_yv, d_part, d_out2 + 2 * i, d_info + i, st);
+  }
+  std::vector<double> out2(2 * n_theta);
+  std::vector<int64_t> info(n_theta);
+  hipMemcpyAsync(out2.data(), d_out2, sizeof(double) * 2 * n_theta, hipMemcpyDeviceToHost, st);
+  hipMemcpyAsync(info.data(), d_info, sizeof(int64_t) * n_theta, hipMemcpyDeviceToHost, st);
+  hipFreeAsync(ws, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    set_error("stream synchronisation failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = MVG_ERR_LAUNCH;
+  }
+  const double two_pi_term = 0.5 * (double)A->N * std::log(2.0 * M_PI);
+  mat_free(A);
+  if (rc) return rc;
+  for (int i = 0; i < n_theta; ++i) {
+    const int64_t inf = info[i] == INT64_MAX ? 0 : info[i];
+    if (h_status) h_status[i] = inf;
+    if (inf) {
+      h_loglik[i] = -INFINITY;
+      if (h_logdet) h_logdet[i] = NAN;
+      if (h_quad) h_quad[i] = NAN;
+    } else {
+      h_loglik[i] = -two_pi_term - 0.5 * out2[2 * i] - 0.5 * out2[2 * i + 1];
+      if (h_logdet) h_logdet[i] = out2[2 * i];
+      if (h_quad) h_quad[i] = out2[2 * i + 1];
+    }
+  }
+  return 0;
+}
+
+int loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+             const mvg_theta_p *th, int n_theta, const mvg_opts *o, double *h_loglik,
+             double *h_logdet, double *h_quad, int64_t *h_status, void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (!d_z) return -3;
+  if (n_loc < 1) return -4;
+  if (!th || n_theta < 1) return -5;
+  mvg_opts d;
+  if (normalize_opts(o, &d)) return -7;
+  if (!h_loglik) return -8;
+  const int p = th[0].p;
+  for (int i = 0; i < n_theta; ++i) {
+    MaternArgsP tmp;
+    if (th[i].p != p || matern_setup_p(&th[i], &tmp)) return -5;
+  }
+  if (p == 2) {
+    std::vector<mvg_theta> t2;
+    for (int i = 0; i < n_theta; ++i) t2.push_back(theta_from_p(th[i]));
+    return loglik(d_x, d_y, d_z, n_loc, t2.data(), n_theta, o, h_loglik, h_logdet, h_quad,
+                  h_status, nullptr, hip_stream);
+  }
+  if (!p_precision_ok(d)) {
+    set_error("p = %d variables: precision must be FP64 or DST", p);
+    return -7;
+  }
+  return loglik_p_run(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad, h_status,
+                      (hipStream_t)hip_stream);
+}
+
+__global__ void k_stride_copy(const double *__restrict__ z, int p, int i, int64_t n,
+                              double *__restrict__ out) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < n) out[l] = z[(int64_t)p * l + i];
+}
+
+int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                     const mvg_theta_p *th, const mvg_opts *o, double *h_sigma_sq,
+                     double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
+                     void *hip_stream) {
+  if (!d_x) return -1;
+  if (!d_y) return -2;
+  if (!d_z) return -3;
+  if (n_loc < 1) return -4;
+  if (!th) return -5;
+  mvg_theta_p t = *th;
+  MaternArgsP tmp;
+  if (t.p < 1 || t.p > PMAX) return -5;
+  for (int i = 0; i < t.p; ++i) t.sigma_sq[i] = 1.0;  // not read: only the shape is checked
+  if (matern_setup_p(&t, &tmp)) return -5;
+  mvg_opts d;
+  if (normalize_opts(o, &d)) return -6;
+  if (!h_sigma_sq) return -7;
+  if (!h_loglik) return -8;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int p = t.p;
+  // marginal variances: Z_i^T R_ii^-1 Z_i / n with R_ii univariate, unit variance (FP64)
+  double *zi = nullptr;
+  if (hipMallocAsync((void **)&zi, sizeof(double) * n_loc, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  mvg_opts d1 = d;
+  d1.precision = MVG_FP64;
+  int rc = 0;
+  for (int i = 0; i < p && !rc; ++i) {
+    hipLaunchKernelGGL(k_stride_copy, dim3((unsigned)((n_loc + 255) / 256)), dim3(256), 0, st, d_z,
+                       p, i, n_loc, zi);
+    rc = check_launch("stride_copy");
+    mvg_theta_p u{};
+    u.p = 1;
+    u.sigma_sq[0] = 1.0;
+    u.a = t.a;
+    u.nu[0] = t.nu[i];
+    u.beta[0] = 1.0;
+    double ll = 0.0, q = 0.0;
+    int64_t status = 0;
+    if (!rc) rc = loglik_p_run(d_x, d_y, zi, n_loc, &u, 1, d1, &ll, nullptr, &q, &status, st);
+    if (!rc && status) {
+      hipFreeAsync(zi, st);
+      hipStreamSynchronize(st);
+      *h_loglik = -INFINITY;
+      if (h_logdet) *h_logdet = NAN;
+      if (h_quad) *h_quad = NAN;
+      if (h_status) *h_status = -(1 + i);
+      for (int k = 0; k < p; ++k) h_sigma_sq[k] = NAN;
+      return 0;
+    }
+    t.sigma_sq[i] = q / (double)n_loc;
+  }
+  hipFreeAsync(zi, st);
+  if (rc) {
+    hipStreamSynchronize(st);
+    return rc;
+  }
+  for (int i = 0; i < p; ++i) h_sigma_sq[i] = t.sigma_sq[i];
+  // Eq. (1) at the profiled variances
+  return loglik_p(d_x, d_y, d_z, n_loc, &t, 1, o, h_loglik, h_logdet, h_quad, h_status, hip_stream);
+}
+
 __global__ void k_loe_mom(const double *__restrict__ sT, const double *__restrict__ sA,
                           const double *__restrict__ dT, const double *__restrict__ sQ, int64_t m,
                           double trt, double tra, double *__restrict__ loe,
@@ -1098,6 +1338,8 @@ int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_strea
   if (!d_z || d_z == d_eps) return -3;
   return launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream);
 }
+
+int mvg_mat_nvar(const mvg_mat *A) { return A ? A->p : -1; }
 
 int mvg_mat_shape(const mvg_mat *A, int64_t *n_loc, int *nb, int *ntiles, int *precision,
                   int *factored) {

@@ -361,8 +361,9 @@ __device__ __forceinline__ void gemm_block64(double *C, int ldc, const double *A
 // rounding noise must not decide; the first such global row (1-based) goes to
 // *d_info.
 __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double *__restrict__ winv,
-                                                 int64_t *__restrict__ d_info, double tol0,
-                                                 double tol1, int64_t N, int64_t gbase, int lreal) {
+                                                 int64_t *__restrict__ d_info, PivotTol pt) {
+  const int64_t N = pt.N, gbase = pt.gbase;
+  const int lreal = pt.lreal;
   __shared__ double scol[2][PB];
   __shared__ double srow[2][PB];
   const int tid = threadIdx.x;
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double
     if (tid == 0 && !failed) {
       const int64_t g = g0 + j;
       const bool pad = g >= N || b * PB + j >= lreal;
-      const double tol = pad ? 0x1p-40 : ((g & 1) ? tol1 : tol0);
+      const double tol = pad ? 0x1p-40 : pt.tol[g % pt.p];
       if (!(d > tol) || !(d > 0.0)) {
         failed = true;
         atomicMin((unsigned long long *)d_info, (unsigned long long)(g + 1));
@@ -618,10 +619,11 @@ int diag_factor(const TileMap &M, int k, double *winv, int64_t *d_info, const Pi
   const int s = M.nb / PB;
   hipLaunchKernelGGL(k_zero_upper_blocks, dim3(64), dim3(256), 0, st, M.nb, k, winv);
   if (int rc = check_launch("zero_upper_blocks")) return rc;
+  PivotTol q = pt;
+  q.gbase = pt.gbase >= 0 ? pt.gbase : (int64_t)k * M.nb;
+  q.lreal = pt.lreal > 0 ? pt.lreal : M.nb;
   for (int b = 0; b < s; ++b) {
-    hipLaunchKernelGGL(k_potrf64, dim3(1), dim3(256), 0, st, M, k, b, winv, d_info, pt.t0, pt.t1,
-                       pt.N, pt.gbase >= 0 ? pt.gbase : (int64_t)k * M.nb,
-                       pt.lreal > 0 ? pt.lreal : M.nb);
+    hipLaunchKernelGGL(k_potrf64, dim3(1), dim3(256), 0, st, M, k, b, winv, d_info, q);
     if (int rc = check_launch("potrf64")) return rc;
     const int nbelow = s - (b + 1);
     if (nbelow > 0) {
@@ -791,7 +793,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventCreateWithFlags(&evD, hipEventDisableTiming);
   hipEventCreateWithFlags(&evS, hipEventDisableTiming);
   hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
-  const PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
+  const PivotTol pt = pivot_tol(A);
   int rc = 0;
   hipEventRecord(ev0, st);
   hipStreamWaitEvent(side, ev0, 0);

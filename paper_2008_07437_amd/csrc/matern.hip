@@ -10,6 +10,7 @@
 // exponential per node serves the three orders nu11, nu22, nu12, and the
 // node-dependent factors cosh(nu t_k), cosh(t_k) - 1 come from a per-theta
 // table held in LDS.  Half-integer orders 1/2, 3/2, 5/2 use their closed forms.
+#include <algorithm>
 #include <cmath>
 
 #include "matern_dev.h"
@@ -130,6 +131,176 @@ int launch_cov_tiles(const MaternArgs &P, const double *d_qtab, const double *d_
     if (rc) return rc;
   }
   (void)nwg;
+  return 0;
+}
+
+// ------------------------------------------------------------ p variables
+
+int matern_setup_p(const mvg_theta_p *th, MaternArgsP *P) {
+  if (!th) return -1;
+  const int p = th->p;
+  if (p < 1 || p > PMAX) return -1;
+  for (int i = 0; i < p; ++i)
+    if (!(th->sigma_sq[i] > 0.0) || !std::isfinite(th->sigma_sq[i])) return -2;
+  if (!(th->a > 0.0) || !std::isfinite(th->a)) return -3;
+  for (int i = 0; i < p; ++i)
+    if (!(th->nu[i] > 0.0) || !(th->nu[i] <= 5.0)) return -4;
+  // beta: symmetric, unit diagonal, positive definite (Cholesky)
+  double c[PMAX][PMAX];
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      const double b = th->beta[i * PMAX + j];
+      if (!std::isfinite(b) || b != th->beta[j * PMAX + i]) return -5;
+      if (i == j && b != 1.0) return -5;
+      c[i][j] = b;
+    }
+  for (int j = 0; j < p; ++j) {
+    double d = c[j][j];
+    for (int k = 0; k < j; ++k) d -= c[j][k] * c[j][k];
+    if (!(d > 0.0)) return -5;
+    const double l = std::sqrt(d);
+    c[j][j] = l;
+    for (int i = j + 1; i < p; ++i) {
+      double v = c[i][j];
+      for (int k = 0; k < j; ++k) v -= c[i][k] * c[j][k];
+      c[i][j] = v / l;
+    }
+  }
+  P->p = p;
+  P->no = p * (p + 1) / 2;
+  P->a = th->a;
+  P->any_quad = 0;
+  for (int i = 0; i < p; ++i)
+    for (int j = i; j < p; ++j) {
+      const int o = pord(i, j, p);
+      const double nu = 0.5 * (th->nu[i] + th->nu[j]);
+      // colocated correlation for d = 2: Gamma(nu + 1) / Gamma(nu) = nu
+      const double rho = i == j ? 1.0 : th->beta[i * PMAX + j] * std::sqrt(th->nu[i] * th->nu[j]) / nu;
+      P->nu[o] = nu;
+      P->coef[o] = rho * std::sqrt(th->sigma_sq[i]) * std::sqrt(th->sigma_sq[j]);
+      P->lnorm[o] = -((nu - 1.0) * std::log(2.0) + std::lgamma(nu));
+      P->closed[o] = nu == 0.5 ? 1 : nu == 1.5 ? 2 : nu == 2.5 ? 3 : 0;
+      if (!P->closed[o]) P->any_quad = 1;
+    }
+  return 0;
+}
+
+__global__ void k_quad_table_p(MaternArgsP P, double *__restrict__ q) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < QN) quad_entry_p(k, P, q);
+}
+
+int launch_quad_table_p(const MaternArgsP &P, double *d_qtab, hipStream_t st) {
+  hipLaunchKernelGGL(k_quad_table_p, dim3((QN + 255) / 256), dim3(256), 0, st, P, d_qtab);
+  return check_launch("quad_table_p");
+}
+
+// One workgroup: up to 32 x 32 location pairs (l, r) whose P x P blocks meet
+// lower tile (I, J); a thread takes one l and four r, evaluates all orders of
+// a pair at once and writes the entries (P l + i, P r + j) that lie in the
+// tile.  Every tile entry belongs to exactly one pair, so each is written
+// once.  Rows / columns at or beyond N = P n are the identity padding.
+template <int P>
+__global__ __launch_bounds__(256) void k_cov_tiles_p(MaternArgsP A, const double *__restrict__ qtab,
+                                                     const double *__restrict__ xs,
+                                                     const double *__restrict__ ys, int64_t n_loc,
+                                                     TileMap M, int64_t tile_first, int spt) {
+  constexpr int NO = P * (P + 1) / 2;
+  __shared__ double sq[(1 + NO) * QN];
+  const int nsub = spt * spt;
+  const int64_t tile = tile_first + blockIdx.x / nsub;
+  const int sub = blockIdx.x % nsub;
+  const int kind = M.kind ? M.kind[tile] : TK_F64;
+  if (kind == TK_ZERO) return;  // annihilated DST tile (whole workgroup)
+  for (int i = threadIdx.x; i < (1 + NO) * QN; i += blockDim.x) sq[i] = qtab[i];
+  __syncthreads();
+  int J = 0;
+  int64_t t = tile;
+  while (t >= M.T - J) {
+    t -= M.T - J;
+    ++J;
+  }
+  const int I = J + (int)t;
+  const int nb = M.nb;
+  const int64_t N = (int64_t)P * n_loc;
+  const int64_t g0 = (int64_t)I * nb, c0 = (int64_t)J * nb;  // first row / column of the tile
+  const int64_t lr0 = g0 / P, lr1 = (g0 + nb - 1) / P;       // row locations meeting the tile
+  const int64_t lc0 = c0 / P, lc1 = (c0 + nb - 1) / P;
+  const int64_t l = lr0 + (sub % spt) * 32 + (threadIdx.x & 31);
+  if (l > lr1) return;
+  const bool lreal = l < n_loc;
+  const double xl = lreal ? xs[l] : 0.0, yl = lreal ? ys[l] : 0.0;
+  char *tb = M.base + M.off[tile];
+  const int64_t rbase = lc0 + (sub / spt) * 32 + (threadIdx.x >> 5) * 4;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = rbase + q;
+    if (r > lc1) break;
+    const bool real = lreal && r < n_loc;
+    double Mv[NO];
+    bool zero_h = false;
+    if (real) {
+      const double dx = xl - xs[r], dy = yl - ys[r];
+      const double h = sqrt(dx * dx + dy * dy);
+      zero_h = h == 0.0;
+      if (!zero_h) matern_p<NO>(h / A.a, A, sq, Mv);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int64_t g = (int64_t)P * l + i;
+      if (g < g0 || g >= g0 + nb) continue;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int64_t c = (int64_t)P * r + j;
+        if (c < c0 || c >= c0 + nb) continue;
+        double v;
+        if (g >= N || c >= N) {
+          v = g == c ? 1.0 : 0.0;
+        } else {
+          const int o = i <= j ? pord(i, j, P) : pord(j, i, P);
+          v = zero_h ? A.coef[o] : A.coef[o] * Mv[o];
+        }
+        const int64_t e = (c - c0) * nb + (g - g0);
+        if (kind == TK_F64)
+          reinterpret_cast<double *>(tb)[e] = v;
+        else
+          reinterpret_cast<float *>(tb)[e] = (float)v;
+      }
+    }
+  }
+}
+
+int launch_cov_tiles_p(const MaternArgsP &P, const double *d_qtab, const double *d_x,
+                       const double *d_y, int64_t n_loc, TileMap M, hipStream_t st) {
+  const int64_t nt = (int64_t)M.T * (M.T + 1) / 2;
+  const int p = P.p;
+  const int spt = (int)(((M.nb - 1) / p + 2 + 31) / 32);  // location rows per tile <= (nb-1)/p + 2
+  const int64_t per = ((int64_t)1 << 30) / (spt * spt);
+  for (int64_t t0 = 0; t0 < nt; t0 += per) {
+    const int64_t cnt = std::min<int64_t>(per, nt - t0);
+    const dim3 grid((unsigned)(cnt * spt * spt));
+    switch (p) {
+      case 1:
+        hipLaunchKernelGGL(k_cov_tiles_p<1>, grid, dim3(256), 0, st, P, d_qtab, d_x, d_y, n_loc, M,
+                           t0, spt);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_cov_tiles_p<2>, grid, dim3(256), 0, st, P, d_qtab, d_x, d_y, n_loc, M,
+                           t0, spt);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_cov_tiles_p<3>, grid, dim3(256), 0, st, P, d_qtab, d_x, d_y, n_loc, M,
+                           t0, spt);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_cov_tiles_p<4>, grid, dim3(256), 0, st, P, d_qtab, d_x, d_y, n_loc, M,
+                           t0, spt);
+        break;
+      default:
+        set_error("p = %d variables is not supported", p);
+        return MVG_ERR_STATE;
+    }
+    if (int rc = check_launch("cov_tiles_p")) return rc;
+  }
   return 0;
 }
 

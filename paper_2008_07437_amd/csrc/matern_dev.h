@@ -90,4 +90,65 @@ __device__ __forceinline__ void cross_cov_block(double xl, double yl, double xr,
   c[2] = P.coef[2] * M[2];
 }
 
+// ------------------------------------------------------------ p variables
+
+// Table entry k of the p-variate table ((1 + no) x QN).
+__device__ __forceinline__ void quad_entry_p(int k, const MaternArgsP &P, double *__restrict__ q) {
+  int j = -1;
+  for (int l = 0; l < QLEV; ++l)
+    if (k >= qlev_off(l) && k < qlev_off(l) + qlev_cnt(l)) j = l;
+  double t = 0.0, cm1 = 0.0;
+  if (j >= 0) {
+    t = (double)(k - qlev_off(j)) * qlev_h(j);
+    const double s = sinh(0.5 * t);
+    cm1 = 2.0 * s * s;
+  }
+  q[k] = cm1;
+  for (int o = 0; o < P.no; ++o) q[(1 + o) * QN + k] = j >= 0 ? cosh(P.nu[o] * t) : 0.0;
+}
+
+// Normalised Matern M(x; nu_o) for all NO orders of the p-variate model,
+// x > 0 (one exponential per node for every order).
+template <int NO>
+__device__ __forceinline__ void matern_p(double x, const MaternArgsP &P,
+                                         const double *__restrict__ sq, double M[NO]) {
+  if (x > qlev_xmax(QLEV - 1)) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o) M[o] = 0.0;
+    return;
+  }
+  const double ex = exp(-x);
+  double s[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) s[o] = 0.5;
+  double logh = 0.0;
+  if (P.any_quad) {
+    const int j = x <= qlev_xmax(0) ? 0 : x <= qlev_xmax(1) ? 1 : x <= qlev_xmax(2) ? 2
+                : x <= qlev_xmax(3) ? 3 : 4;
+    const int off = qlev_off(j), cnt = qlev_cnt(j);
+    logh = log(qlev_h(j));
+    for (int k = 1; k < cnt; ++k) {
+      const double e = exp(-x * sq[off + k]);
+      bool small = true;
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        const double tt = e * sq[(1 + o) * QN + off + k];
+        s[o] += tt;
+        small = small && tt <= 1e-17 * s[o];
+      }
+      if (small) break;
+    }
+  }
+  const double lx = log(x);
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    switch (P.closed[o]) {
+      case 1: M[o] = ex; break;
+      case 2: M[o] = (1.0 + x) * ex; break;
+      case 3: M[o] = (1.0 + x + x * x * (1.0 / 3.0)) * ex; break;
+      default: M[o] = exp(P.nu[o] * lx - x + P.lnorm[o] + logh) * s[o]; break;
+    }
+  }
+}
+
 }  // namespace mvg

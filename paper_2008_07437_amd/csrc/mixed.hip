@@ -443,7 +443,7 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   hipEventCreateWithFlags(&evD, hipEventDisableTiming);
   hipEventCreateWithFlags(&evS, hipEventDisableTiming);
   hipEventCreateWithFlags(&ev0, hipEventDisableTiming);
-  const PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
+  const PivotTol pt = pivot_tol(A);
   int rc = 0;
   hipEventRecord(ev0, st);
   hipStreamWaitEvent(side, ev0, 0);

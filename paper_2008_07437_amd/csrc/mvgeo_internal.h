@@ -49,6 +49,26 @@ struct MaternArgs {
 // Validates theta and fills the constants; returns 0 or -(index of the bad entry).
 int matern_setup(const mvg_theta *th, MaternArgs *out);
 
+// The p-variate model: orders o(i, j), i <= j, packed row by row
+// (o = i p - i (i - 1) / 2 + j - i); the quadrature table holds
+// cosh t_k - 1 and then cosh(nu_o t_k) for every order ((1 + no) x QN).
+constexpr int PMAX = MVG_PMAX;
+constexpr int PORD = PMAX * (PMAX + 1) / 2;
+__host__ __device__ constexpr int pord(int i, int j, int p) {
+  return i * p - i * (i - 1) / 2 + (j - i);
+}
+struct MaternArgsP {
+  int p, no;
+  double a;
+  double coef[PORD];   // rho_ij sigma_i sigma_j
+  double nu[PORD];
+  double lnorm[PORD];  // -log(2^(nu-1) Gamma(nu))
+  int closed[PORD];    // as MaternArgs::closed
+  int any_quad;
+};
+int matern_setup_p(const mvg_theta_p *th, MaternArgsP *out);
+int launch_quad_table_p(const MaternArgsP &P, double *d_qtab, hipStream_t st);
+
 // ------------------------------------------------------------------- tiles
 
 // Packed lower tile index, tiles of a column contiguous.
@@ -88,6 +108,9 @@ struct mvg_mat {
   mvg_theta theta{};
   mvg_opts opts{};
   mvg::MaternArgs margs{};
+  int p = 2;                      // variables; p != 2 uses theta_p / margs_p
+  mvg_theta_p theta_p{};
+  mvg::MaternArgsP margs_p{};
   mvg::TlrState *tlr = nullptr;   // TLR storage (precision == MVG_TLR)
   mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb, T}; }
 };
@@ -111,6 +134,9 @@ int launch_quad_table(const MaternArgs &P, double *d_qtab, hipStream_t st);
 int launch_cov_tiles(const MaternArgs &P, const double *d_qtab, const double *d_x,
                      const double *d_y, int64_t n_loc, TileMap M, int tile_first, int tile_count,
                      hipStream_t st);
+// p-variate Sigma (p != 2 or on request) over all tiles of M
+int launch_cov_tiles_p(const MaternArgsP &P, const double *d_qtab, const double *d_x,
+                       const double *d_y, int64_t n_loc, TileMap M, hipStream_t st);
 // c0^T w and optionally ||L^-1 c0||^2 pieces for cokriging
 int launch_cokrige_dot(const MaternArgs &P, const double *d_qtab, const double *d_x,
                        const double *d_y, int64_t n_loc, const double *d_x0, const double *d_y0,
@@ -120,15 +146,17 @@ int launch_cokrige_c0(const MaternArgs &P, const double *d_qtab, const double *d
                       const double *d_y0, int64_t m, double *d_c0, hipStream_t st);
 
 // dense FP64 Cholesky pieces
-// Pivot rule: a pivot at or below 2^-40 of the variable's variance (t0 for
-// even, t1 for odd global rows) is a failure.  gbase: global row of the
-// tile's row 0 (-1: k nb); lreal: rows of the tile that are not padding (0: nb).
+// Pivot rule: a pivot at or below 2^-40 of the variable's variance (tol[g % p]
+// for global row g) is a failure.  gbase: global row of the tile's row 0
+// (-1: k nb); lreal: rows of the tile that are not padding (0: nb).
 struct PivotTol {
-  double t0, t1;
+  double tol[PMAX];
+  int p;
   int64_t N;
   int64_t gbase = -1;
   int lreal = 0;
 };
+PivotTol pivot_tol(const mvg_mat *A);
 enum { TRAIL_UPDATE = 0, TRAIL_TRSM = 1, TRAIL_BAND = 2 };
 template <int MODE>
 int launch_trail(const TileMap &M, int k, int jlo, int64_t lid0, int64_t nwg, const double *P,

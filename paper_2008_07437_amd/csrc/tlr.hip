@@ -513,7 +513,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
       std::vector<CopyTask> c{CopyTask{P, Lf.diag + (int64_t)j * nbp * nbp, nb, nb, ldp, nbp,
                                        nullptr, COPY_PLAIN}};
       rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
-      PivotTol pt{0x1p-40 * A->theta.sigma11_sq, 0x1p-40 * A->theta.sigma22_sq, A->N};
+      PivotTol pt = pivot_tol(A);
       pt.gbase = (int64_t)j * nb;
       pt.lreal = nb;
       if (!rc) rc = diag_factor(Md, j, A->d_winv, d_info, pt, st);

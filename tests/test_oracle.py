@@ -495,3 +495,90 @@ def test_dst_full_band_is_exact_and_band_one_splits(orc):
     assert abs(diag["loglik"] - ref) <= 1e-9 * abs(ref)
     M = orc.dst_mask(S, nb, 2)
     assert np.all(M[:nb, 2 * nb:] == 0) and np.array_equal(M[:2 * nb, :2 * nb], S[:2 * nb, :2 * nb])
+
+
+# ----------------------------------------------- p variables (Section 4.2, 5.2)
+
+def _sites_p(orc, n, seed):
+    x, y = synthetic.jittered_grid(n, seed)
+    p = orc.morton_order(x, y)
+    return x[p], y[p]
+
+
+TH3 = {"sigma_sq": [1.0, 1.5, 0.7], "a": 0.1, "nu": [0.5, 1.0, 1.7],
+       "beta": [[1.0, 0.5, -0.3], [0.5, 1.0, -0.2], [-0.3, -0.2, 1.0]]}
+
+
+def test_cov_p_two_variables_equals_bivariate(orc):
+    """The p-variate assembly (numpy, rho from the Gamma function) at p = 2
+    equals the bivariate C oracle entry by entry."""
+    x, y = _sites_p(orc, 60, 2)
+    th = (1.3, 0.7, 0.2, 0.8, 1.7, -0.4)
+    thp = {"sigma_sq": [1.3, 0.7], "a": 0.2, "nu": [0.8, 1.7], "beta": [[1, -0.4], [-0.4, 1]]}
+    A, B = orc.cov_dense_p(x, y, thp), orc.cov_dense(x, y, th)
+    assert np.max(np.abs(A - B)) <= 1e-14 * np.max(np.abs(B))
+    assert abs(orc.rho_p(thp)[0, 1] - orc.rho12(th)) <= 1e-15
+
+
+def test_loglik_p_independent_blocks(orc):
+    """beta = I: the variables are independent, so Eq. (1) is the sum of the
+    univariate Gaussian log-densities (scipy); beta with a zero third row:
+    the bivariate oracle for (Z1, Z2) plus the univariate density of Z3."""
+    from scipy.stats import multivariate_normal
+    x, y = _sites_p(orc, 50, 4)
+    n = 50
+    z = synthetic.normal_eps(3 * n, 4)
+    th = dict(TH3, beta=np.eye(3).tolist())
+    h = np.sqrt((x[:, None] - x[None, :]) ** 2 + (y[:, None] - y[None, :]) ** 2)
+    ref = 0.0
+    for i in range(3):
+        C = th["sigma_sq"][i] * orc.matern(h.ravel() / th["a"], th["nu"][i]).reshape(n, n)
+        ref += multivariate_normal(mean=np.zeros(n), cov=C).logpdf(z[i::3])
+    got = orc.loglik_p(x, y, z, th)["loglik"]
+    assert abs(got - ref) <= 1e-9 * abs(ref)
+    b = [[1.0, 0.6, 0.0], [0.6, 1.0, 0.0], [0.0, 0.0, 1.0]]
+    th2 = dict(TH3, beta=b)
+    z12 = np.empty(2 * n)
+    z12[0::2], z12[1::2] = z[0::3], z[1::3]
+    biv = orc.loglik(x, y, z12, (1.0, 1.5, 0.1, 0.5, 1.0, 0.6))["loglik"]
+    C3 = 0.7 * orc.matern(h.ravel() / 0.1, 1.7).reshape(n, n)
+    ref2 = biv + multivariate_normal(mean=np.zeros(n), cov=C3).logpdf(z[2::3])
+    got2 = orc.loglik_p(x, y, z, th2)["loglik"]
+    assert abs(got2 - ref2) <= 1e-9 * abs(ref2)
+
+
+def test_theta_p_check(orc):
+    assert orc.theta_p_check(TH3) == 0
+    bad = dict(TH3, beta=[[1, 0.9, 0.9], [0.9, 1, -0.9], [0.9, -0.9, 1]])   # not positive definite
+    assert orc.theta_p_check(bad) == -5
+    asym = dict(TH3, beta=[[1, 0.5, 0.1], [0.4, 1, 0.1], [0.1, 0.1, 1]])
+    assert orc.theta_p_check(asym) == -5
+    assert orc.theta_p_check(dict(TH3, a=-1.0)) == -3
+    assert orc.theta_p_check(dict(TH3, nu=[0.5, 6.0, 1.0])) == -4
+
+
+def test_profile_loglik(orc):
+    """p = 1: the profiled variance maximises Eq. (1) in sigma^2, so the
+    profile likelihood equals the closed form -n/2 log 2 pi - n/2 log(q/n) -
+    log|R|/2 - n/2; p = 3: each sigma_ii^2 against numpy's inverse."""
+    x, y = _sites_p(orc, 70, 6)
+    n = 70
+    z1 = 1.7 * synthetic.normal_eps(n, 6)
+    th1 = {"sigma_sq": [5.0], "a": 0.1, "nu": [1.2], "beta": [[1.0]]}
+    r = orc.profile_loglik_p(x, y, z1, th1)
+    R = orc.cov_dense_p(x, y, dict(th1, sigma_sq=[1.0]))
+    q = float(z1 @ np.linalg.solve(R, z1))
+    ld = float(np.linalg.slogdet(R)[1])
+    closed = -n / 2 * np.log(2 * np.pi) - n / 2 * np.log(q / n) - ld / 2 - n / 2
+    assert abs(r["sigma_sq"][0] - q / n) <= 1e-10 * q / n
+    assert abs(r["loglik"] - closed) <= 1e-9 * abs(closed)
+    for f in (0.97, 1.03):
+        other = orc.loglik_p(x, y, z1, dict(th1, sigma_sq=[f * q / n]))["loglik"]
+        assert other < r["loglik"]
+    z3 = synthetic.normal_eps(3 * n, 7)
+    r3 = orc.profile_loglik_p(x, y, z3, TH3)
+    for i in range(3):
+        Ri = orc.cov_dense_p(x, y, {"sigma_sq": [1.0], "a": 0.1, "nu": [TH3["nu"][i]],
+                                    "beta": [[1.0]]})
+        zi = z3[i::3]
+        assert abs(r3["sigma_sq"][i] - zi @ np.linalg.solve(Ri, zi) / n) <= 1e-9
