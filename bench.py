@@ -321,6 +321,39 @@ def run_trivariate(args, mvg, dev, synthetic, torch):
                           "sigma_sq": [float(v) for v in prof_ll["sigma_sq"]]})
 
 
+def run_mle(args, mvg, dev, synthetic, torch):
+    """Maximum likelihood at the shape of the synthetic estimation study
+    (Section 6.4.1, Experiment 2: 22,464 sampled locations, a = 0.09, nu11 =
+    0.5, nu22 = 1): Nelder-Mead from a perturbed start, a bounded number of
+    exact FP64 evaluations (one fit needs a few hundred)."""
+    n = args.n
+    th = (1.0, 1.0, 0.09, 0.5, 1.0, 0.5)
+    start = (1.2, 0.8, 0.12, 0.6, 0.9, 0.3)
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    A = mvg.cov_generate(xs, ys, th, {"nb": args.nb})
+    if mvg.potrf_tiled(A):
+        raise SystemExit("Sigma(theta) not positive definite")
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    del A
+    o = {"nb": args.nb}
+    l_true = float(mvg.loglik(xs, ys, z, th, o)["loglik"][0])
+    l_start = float(mvg.loglik(xs, ys, z, start, o)["loglik"][0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit = mvg.mle_fit(xs, ys, z, start, o, max_evals=args.max_evals)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+          fit["evals"] / dt, "evals/s", fit["evals"], 0, 1e3 * dt / fit["evals"], "f64",
+          {"workload": "Nelder-Mead MLE, N=%d locations (%dx%d), nb %d, FP64, %d evaluations"
+                       % (n, 2 * n, 2 * n, args.nb, args.max_evals), "n_loc": n,
+           "precision": "fp64"},
+          fit_seconds=dt, theta_start=start, theta_true=th, theta_hat=fit["theta"],
+          loglik_start=l_start, loglik_true=l_true, loglik_hat=fit["loglik"],
+          converged=fit["converged"], iterations=fit["iters"])
+
+
 def serve_stream(args, mvg, dev, synthetic, torch, rate, nreq):
     """One Poisson stream through a fresh server; returns its summary."""
     import threading
@@ -413,13 +446,14 @@ def main():
     ap.add_argument("--wide-band", type=int, default=16,
                     help="second, wider FP64 band for the FP32 variant")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe", "trivariate"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe", "trivariate", "mle"],
                     help="dense: N=25,600 FP64 (+ mixed variants); tlr: N=100,000 TLR; batched: "
                          "many theta at N=400 in one launch; serving: request stream; mloe: "
-                         "MLOE/MMOM at N=25,600 with 100 targets; trivariate: p = 3 at N=17,066")
+                         "MLOE/MMOM at N=25,600 with 100 targets; trivariate: p = 3 at N=17,066; mle: Nelder-Mead at N=22,464")
     ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
     ap.add_argument("--no-dense-ref", action="store_true")
     ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--max-evals", type=int, default=40, help="MLE: likelihood evaluations")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--sustain-rate", type=float, default=6.0)
@@ -460,6 +494,9 @@ def main():
         return run_serving(args, mvg, dev, synthetic, torch)
     if args.workload == "mloe":
         return run_mloe(args, mvg, dev, synthetic, torch)
+    if args.workload == "mle":
+        args.n = 22464 if args.n == 25600 else args.n
+        return run_mle(args, mvg, dev, synthetic, torch)
     if args.workload == "trivariate":
         args.n = 17066 if args.n == 25600 else args.n
         return run_trivariate(args, mvg, dev, synthetic, torch)

@@ -225,6 +225,49 @@ int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, in
                      double *h_loglik, double *h_logdet, double *h_quad, int64_t *h_status,
                      void *hip_stream);
 
+/* ------------------------------------------------------- maximum likelihood
+ *
+ * The optimiser around Eq. (1) (Section 5.1 uses NLopt for this step without
+ * naming a method): derivative-free Nelder-Mead simplex search (Nelder and
+ * Mead 1965; reflection 1, expansion 2, contraction 1/2, shrink 1/2).  The
+ * objective is called in batches: the starting simplex (dim + 1 points) and
+ * every shrink (dim points) in one call, single points otherwise. */
+
+/* Host objective for mvg_nelder_mead: f[i] = objective at row i of V
+ * (m x dim, row-major); returns 0, or a non-zero code that stops the search
+ * and is returned.  NaN values count as +infinity. */
+typedef int (*mvg_batch_objective)(int m, const double *V, double *f, void *ctx);
+
+/* Minimise f from x0 (starting simplex x0 and x0 + step e_i).  Stops when
+ * max f - min f <= ftol over the simplex and every vertex is within xtol of
+ * the best in every coordinate (*converged = 1), or after max_evals
+ * evaluations (checked between steps, so a step may finish past it).  Host
+ * only: no device work.  Returns 0, -1..-9 for bad arguments (dim in 1..64,
+ * max_evals >= dim + 1), or the objective's code. */
+int mvg_nelder_mead(int dim, const double *x0, double step, mvg_batch_objective f, void *ctx,
+                    int max_evals, double ftol, double xtol, double *x_best, double *f_best,
+                    int *n_evals, int *n_iters, int *converged);
+
+typedef struct {
+    int max_evals;  /* likelihood evaluations (0 = 1000)                        */
+    double ftol;    /* simplex spread of -loglik (0 = 1e-6)                      */
+    double xtol;    /* simplex size in the search coordinates (0 = 1e-5)        */
+    double step;    /* starting simplex step in the search coordinates (0 = 0.1) */
+} mvg_mle_opts;
+
+/* Maximum-likelihood estimate of the bivariate theta from th0 by
+ * mvg_nelder_mead on -loglik (any precision of loglik), searched in
+ * unconstrained coordinates: log sigma11^2, log sigma22^2, log a,
+ * logit(nu_ii / 5) (so 0 < nu_ii < 5), atanh beta.  A theta whose matrix
+ * is not positive definite counts as -infinity.  th_hat, h_loglik: the best
+ * point found; h_evals, h_iters, h_converged (nullable).  Returns 0, -1..-8
+ * for bad arguments (-5: th0 invalid or nu_ii = 5), or loglik's error
+ * codes. */
+int mle_fit(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+            const mvg_theta *th0, const mvg_opts *o, const mvg_mle_opts *mo,
+            mvg_theta *th_hat, double *h_loglik, int *h_evals, int *h_iters,
+            int *h_converged, void *hip_stream);
+
 /* One task of loglik_many: a dataset (device pointers, caller-owned) and a
  * theta. */
 typedef struct {

@@ -103,6 +103,7 @@ def _load():
         "cokrige_predict": (c_int, [P, P, P, c_int64, P, P, P]),
         "mloe_mmom": (c_int, [P, P, c_int64, P, P, P, P, c_int64, P, P, P, P, P, P]),
         "loglik_p": (c_int, [P, P, P, c_int64, P, c_int, P, P, P, P, P, P]),
+        "mle_fit": (c_int, [P, P, P, c_int64, P, P, P, P, P, P, P, P, P]),
         "cov_generate_p": (c_int, [P, P, c_int64, P, P, P, P]),
         "profile_loglik_p": (c_int, [P, P, P, c_int64, P, P, P, P, P, P, P, P]),
         "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
@@ -317,6 +318,29 @@ def profile_loglik_p(x, y, z, theta_p, opts=None, stream=None) -> dict:
         ctypes.byref(q), ctypes.byref(st), _stream(stream)))
     return {"sigma_sq": s2, "loglik": ll.value, "logdet": ld.value, "quad": q.value,
             "status": st.value}
+
+
+class MleOpts(ctypes.Structure):
+    _fields_ = [("max_evals", c_int), ("ftol", c_double), ("xtol", c_double), ("step", c_double)]
+
+
+def mle_fit(x, y, z, theta0, opts=None, max_evals=0, ftol=0.0, xtol=0.0, step=0.0, stream=None):
+    """Nelder-Mead maximum-likelihood estimate of theta from theta0 (host
+    driver in the library; every evaluation is the GPU likelihood)."""
+    th0 = Theta.of(theta0)
+    mo = MleOpts(int(max_evals), float(ftol), float(xtol), float(step))
+    out = Theta()
+    ll = c_double()
+    ev, it, conv = c_int(), c_int(), c_int()
+    o = _opts(opts)
+    _check("mle_fit", _load().mle_fit(_dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"),
+                                      x.numel(), ctypes.byref(th0), ctypes.byref(o),
+                                      ctypes.byref(mo), ctypes.byref(out), ctypes.byref(ll),
+                                      ctypes.byref(ev), ctypes.byref(it), ctypes.byref(conv),
+                                      _stream(stream)))
+    th = (out.sigma11_sq, out.sigma22_sq, out.a, out.nu11, out.nu22, out.beta)
+    return {"theta": th, "loglik": ll.value, "evals": ev.value, "iters": it.value,
+            "converged": bool(conv.value)}
 
 
 def potrf_tiled(mat: Mat, opts=None, stream=None) -> int:

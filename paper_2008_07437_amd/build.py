@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libmvgeo.so")
 SOURCES = ["capi.hip", "matern.hip", "dense.hip", "solve.hip", "mixed.hip", "morton.hip", "tlr.hip",
-           "tlr_kernels.hip", "batched.hip", "serve.cpp"]
+           "tlr_kernels.hip", "batched.hip", "serve.cpp", "mle.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-value",

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -15,7 +16,8 @@ def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = set()
-    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", src, re.M):
+    for m in re.finditer(r"^\s*(?!typedef)(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(",
+                         src, re.M):
         name = m.group(1)
         if name not in ("if", "while", "for", "sizeof", "defined"):
             names.add(name)
@@ -109,3 +111,61 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert lib.mvg_server_create(0, 2, None) is None
     assert lib.mvg_server_create(1 << 30, 0, None) is None
     assert lib.mvg_server_create(1 << 30, 64, None) is None
+
+
+@pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
+def test_nelder_mead_host_optimiser():
+    """mvg_nelder_mead (host only) on objectives with known minima: a
+    weighted quadratic (minimum at c), Rosenbrock's valley (minimum at
+    (1, 1)); the first call evaluates the whole starting simplex in one batch,
+    later calls one point (or dim points for a shrink); an objective error stops the
+    search and is returned."""
+    lib = ctypes.CDLL(SO)
+    CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+    lib.mvg_nelder_mead.restype = ctypes.c_int
+    lib.mvg_nelder_mead.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_double, CB,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    sizes = []
+
+    def run(fun, x0, step, max_evals, ftol, xtol):
+        dim = len(x0)
+
+        def cb(m, V, f, ctx):
+            sizes.append(m)
+            for i in range(m):
+                f[i] = fun(np.array([V[i * dim + j] for j in range(dim)]))
+            return 0
+        cbf = CB(cb)
+        xb = np.zeros(dim)
+        fb = ctypes.c_double()
+        ev, it, cv = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        x0a = np.asarray(x0, dtype=np.float64)
+        rc = lib.mvg_nelder_mead(dim, x0a.ctypes.data, step, cbf, None, max_evals, ftol, xtol,
+                                 xb.ctypes.data, ctypes.byref(fb), ctypes.byref(ev),
+                                 ctypes.byref(it), ctypes.byref(cv))
+        return rc, xb, fb.value, ev.value, bool(cv.value)
+
+    c = np.array([0.3, -1.2, 2.0, 0.7])
+    w = np.array([1.0, 3.0, 0.5, 2.0])
+    rc, xb, fb, ev, cv = run(lambda v: float(np.sum(w * (v - c) ** 2)), [0, 0, 0, 0], 0.5, 4000,
+                             1e-14, 1e-8)
+    assert rc == 0 and cv and np.max(np.abs(xb - c)) <= 1e-6 and fb <= 1e-12
+    assert sizes[0] == 5 and set(sizes[1:]) <= {1, 4}   # starting simplex in one batch
+    sizes.clear()
+    rosen = lambda v: float(100.0 * (v[1] - v[0] ** 2) ** 2 + (1.0 - v[0]) ** 2)  # noqa: E731
+    rc, xb, fb, ev, cv = run(rosen, [-1.2, 1.0], 0.1, 5000, 1e-14, 1e-9)
+    assert rc == 0 and cv and np.max(np.abs(xb - 1.0)) <= 1e-5
+    assert lib.mvg_nelder_mead(0, None, 0.1, CB(lambda *a: 0), None, 10, 0, 0, None, None, None,
+                               None, None) == -1
+
+    def failing(m, V, f, ctx):
+        return 7
+    fb_ = CB(failing)
+    xb = np.zeros(2)
+    out = [ctypes.c_double(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()]
+    x0 = np.zeros(2)
+    assert lib.mvg_nelder_mead(2, x0.ctypes.data, 0.1, fb_, None, 100, 0.0, 0.0, xb.ctypes.data,
+                               *[ctypes.byref(o) for o in out]) == 7
