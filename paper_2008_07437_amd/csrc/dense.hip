@@ -52,20 +52,24 @@ int launch_fill_f64(double *d, double v, int64_t n, hipStream_t st) {
 // XCD's L2.  K is streamed through LDS in slices of TKB columns with TS-stage
 // pipelining by direct global->LDS loads (global_load_lds_dwordx4): no VGPR
 // staging, one barrier per slice, and the slices of the next block are in
-// flight while the current block's C update is written.  The MFMA takes the
-// B fragment as its first operand so that each lane's accumulator holds 16
-// consecutive rows of one column: lane l, element e <-> C[l%16][l/16 + 4e].
+// flight while the current block's C update is written.  Lane l, element e
+// of an accumulator tile holds C[4e + l/16][l%16] of that 16 x 16 tile.
 constexpr int KB = 16;   // K slice of the small panel GEMM
-constexpr int TKB = 8;   // K slice of the trailing GEMM
-constexpr int TS = 4;    // pipeline stages of the trailing GEMM
+constexpr int TKB = 16;  // K slice of the trailing GEMM
+constexpr int TS = 2;    // pipeline stages of the trailing GEMM (64 KB LDS per workgroup)
 constexpr int TD = TKB * 2 / 4;  // direct loads per wave per stage (1 KB each)
 
 #define MVG_LDS(p) ((__attribute__((address_space(3))) void *)(p))
 
-// s_waitcnt vmcnt(n) leaving lgkmcnt / expcnt unconstrained (GFX9 encoding).
-__device__ __forceinline__ void wait_vmcnt_8() { __builtin_amdgcn_s_waitcnt(0x0F78); }
-__device__ __forceinline__ void wait_vmcnt_0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-static_assert((TS - 2) * TD == 8, "wait_vmcnt_8 encodes the steady-state count");
+// s_waitcnt vmcnt(N) leaving lgkmcnt / expcnt unconstrained (GFX9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit count");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 0xF) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void wait_vmcnt_0() { wait_vmcnt<0>(); }
+static_assert(TKB % 4 == 0 && TS >= 2, "four columns per wave and slice step, two stages");
 
 struct TrailBlock {
   const double *A, *B;
@@ -139,10 +143,10 @@ template <int NB, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update_trailing(
     TileMap M, int k, int jlo, int64_t lid0, int64_t nwg, int64_t chunk, const double *__restrict__ P,
     const double *__restrict__ W) {
-  __shared__ double sA0[TKB * IB], sA1[TKB * IB], sA2[TKB * IB], sA3[TKB * IB];
-  __shared__ double sB0[TKB * IB], sB1[TKB * IB], sB2[TKB * IB], sB3[TKB * IB];
-#define MVG_STA(u) ((u) == 0 ? sA0 : (u) == 1 ? sA1 : (u) == 2 ? sA2 : sA3)
-#define MVG_STB(u) ((u) == 0 ? sB0 : (u) == 1 ? sB1 : (u) == 2 ? sB2 : sB3)
+  __shared__ double sA[TS][TKB * IB];
+  __shared__ double sB[TS][TKB * IB];
+#define MVG_STA(u) (sA[(u)])
+#define MVG_STB(u) (sB[(u)])
   static_assert((NB / TKB) % TS == 0 && (IB / TKB) % TS == 0, "slices per block must divide by TS");
   const int G = gridDim.x;  // multiple of 8
   const int b = blockIdx.x;
@@ -156,24 +160,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave & 1, wc = wave >> 1;
   const int l16 = lane & 15, lk = lane >> 4;
-  // A slice of TKB = 8 columns (1 KB each) and the B slice: wave w loads
-  // columns w and w + 4 of both, one column per direct load; lane l moves
-  // rows 2l, 2l+1.
+  // A slice of TKB columns (1 KB each) and the B slice: wave w loads columns
+  // w, w + 4, ... of both, one column per direct load; lane l moves rows 2l,
+  // 2l+1.
   const int loff = 2 * lane;
 #define MVG_ISSUE(pa, pb, kb, st)                                                                 \
   do {                                                                                            \
     const double *a_ = (pa) + (int64_t)((kb) * TKB + wave) * NB;                                  \
     const double *b_ = (pb) + (int64_t)((kb) * TKB + wave) * NB;                                  \
-    __builtin_amdgcn_global_load_lds((const void *)(a_ + loff), MVG_LDS(MVG_STA(st) + wave * IB), \
-                                     16, 0, 0);                                                   \
-    __builtin_amdgcn_global_load_lds((const void *)(a_ + 4 * NB + loff),                         \
-                                     MVG_LDS(MVG_STA(st) + (wave + 4) * IB), 16, 0, 0);          \
-    __builtin_amdgcn_global_load_lds((const void *)(b_ + loff), MVG_LDS(MVG_STB(st) + wave * IB), \
-                                     16, 0, 0);                                                   \
-    __builtin_amdgcn_global_load_lds((const void *)(b_ + 4 * NB + loff),                         \
-                                     MVG_LDS(MVG_STB(st) + (wave + 4) * IB), 16, 0, 0);          \
+    _Pragma("unroll") for (int c_ = 0; c_ < TKB / 4; ++c_) {                                      \
+      __builtin_amdgcn_global_load_lds((const void *)(a_ + 4 * c_ * NB + loff),                  \
+                                       MVG_LDS(MVG_STA(st) + (wave + 4 * c_) * IB), 16, 0, 0);   \
+      __builtin_amdgcn_global_load_lds((const void *)(b_ + 4 * c_ * NB + loff),                  \
+                                       MVG_LDS(MVG_STB(st) + (wave + 4 * c_) * IB), 16, 0, 0);   \
+    }                                                                                             \
   } while (0)
-  static_assert(TD == 4, "MVG_ISSUE issues four direct loads per wave");
+  static_assert(TD == 2 * (TKB / 4), "MVG_ISSUE issues TD direct loads per wave");
 #pragma unroll
   for (int p = 0; p < TS - 1; ++p) MVG_ISSUE(cur.A, cur.B, p, p);
   dbl4 acc[4][4];
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // TS-1 slices in flight; the oldest (kb) is complete when <= (TS-2) TD remain
         // the barrier is pinned: no LDS read of this stage and no direct load
         // into the stage being refilled may be scheduled across it
-        wait_vmcnt_8();
+        wait_vmcnt<(TS - 2) * TD>();
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
