@@ -62,7 +62,7 @@ enum {
 typedef struct {
     int precision;      /* MVG_FP64 / MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_TLR        */
     int nb;             /* tile size; dense and mixed: 128, 256, 512, 768 or 1024    */
-                        /* (0 = 512);                                                  */
+                        /* (0 = 512; MVG_NB_AUTO: autotuned, see mvg_autotune_nb);     */
                         /* TLR: even, >= 64 (0 = 1200)                                 */
     int band_tiles;     /* mixed: tiles with |I - J| < band_tiles stay FP64 (0 = 2);  */
                         /* DST: tiles with |I - J| < band_tiles are kept, the others */
@@ -171,6 +171,25 @@ int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_the
               const mvg_theta *th_a, const double *d_x0, const double *d_y0, int64_t m,
               const mvg_opts *o, double *h_mloe, double *h_mmom, double *d_loe, double *d_mom,
               void *hip_stream);
+
+/* ------------------------------------------------------------ autotuning
+ *
+ * Tile size picked by measurement: for each candidate nb, one untimed
+ * warm-up and one timed likelihood evaluation of this very problem (theta,
+ * data, precision); the fastest candidate wins.  The choice is cached in the
+ * process per (n_loc, precision, band_tiles); a cached key returns at once
+ * (return value 1, h_seconds untouched).  cand: n_cand tile sizes from
+ * {128, 256, 512, 768, 1024} (NULL: 256, 512, 768, 1024).  h_seconds
+ * (nullable): the time of each candidate (INFINITY if it failed to run).
+ * Precision FP64, DST or mixed.  Returns 0 (tuned), 1 (cached), -1..-9 for
+ * bad arguments, MVG_ERR_*.
+ *
+ * loglik with opts.nb = MVG_NB_AUTO uses the cached choice for its key,
+ * tuning first (with its first theta) when the key is new. */
+#define MVG_NB_AUTO (-1)
+int mvg_autotune_nb(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                    const mvg_theta *th, const mvg_opts *o, const int *cand, int n_cand,
+                    int *best_nb, double *h_seconds, void *hip_stream);
 
 /* ------------------------------------------------------------ p variables
  *

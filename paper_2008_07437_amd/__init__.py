@@ -12,6 +12,6 @@ from ._lib import (  # noqa: F401
     Opts, Theta, ThetaP, Mat, Factor, MvgError, cov_generate_p, loglik_p, profile_loglik_p,
     mle_fit, MleOpts,
     library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many, tlr_compress,
-    cokrige_predict, mloe_mmom, mvg_footprint, mvg_dst_band, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
+    cokrige_predict, mloe_mmom, mvg_footprint, mvg_dst_band, mvg_autotune_nb, MVG_NB_AUTO, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
     Server, Result, REQ_LOGLIK, REQ_COKRIGE,
 )

@@ -108,6 +108,7 @@ def _load():
         "profile_loglik_p": (c_int, [P, P, P, c_int64, P, P, P, P, P, P, P, P]),
         "mvg_footprint": (ctypes.c_size_t, [c_int64, P]),
         "mvg_dst_band": (c_int, [c_int64, c_int, c_double]),
+        "mvg_autotune_nb": (c_int, [P, P, P, c_int64, P, P, P, c_int, P, P, P]),
         "mvg_mat_shape": (c_int, [P, P, P, P, P, P]),
         "mvg_mat_nvar": (c_int, [P]),
         "mvg_mat_gather": (c_int, [P, P, P, c_int64, P, P]),
@@ -464,6 +465,29 @@ def mvg_prof_read(kind: str) -> dict:
                                                  ctypes.byref(ms), ctypes.byref(fl),
                                                  ctypes.byref(by)))
     return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+MVG_NB_AUTO = -1
+
+
+def mvg_autotune_nb(x, y, z, theta, opts=None, candidates=None, stream=None):
+    """Tile size by measurement (one timed evaluation per candidate, cached
+    per (n_loc, precision, band)).  Returns (nb, {candidate: seconds} or
+    None when the choice came from the cache)."""
+    th = Theta.of(theta)
+    o = _opts(opts)
+    cand = None if candidates is None else (c_int * len(candidates))(*candidates)
+    k = 4 if candidates is None else len(candidates)
+    secs = np.full(k, np.nan)
+    best = c_int()
+    rc = _load().mvg_autotune_nb(_dev_f64(x, "x"), _dev_f64(y, "y"), _dev_f64(z, "z"), x.numel(),
+                                 ctypes.byref(th), ctypes.byref(o), cand,
+                                 0 if candidates is None else len(candidates), ctypes.byref(best),
+                                 secs.ctypes.data_as(c_void_p), _stream(stream))
+    if rc < 0:
+        _check("mvg_autotune_nb", rc)
+    cands = list(candidates) if candidates is not None else [256, 512, 768, 1024]
+    return best.value, (None if rc == 1 else dict(zip(cands, secs.tolist())))
 
 
 def mvg_dst_band(n_loc: int, nb: int, keep_fraction: float) -> int:

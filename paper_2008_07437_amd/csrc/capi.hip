@@ -1,10 +1,13 @@
 // C ABI entry points (declared in include/mvgeo.h): argument checking, the
 // library-owned matrices and factors, and the orchestration of the kernels.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "mvgeo_internal.h"
@@ -845,6 +848,79 @@ int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *
   return run_small(tasks, nmax, h_loglik, h_logdet, h_quad, h_status, (hipStream_t)hip_stream);
 }
 
+// ------------------------------------------------------------ autotuning
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int64_t, int, int>, int> g_tune;  // (n_loc, precision, band) -> nb
+
+static bool tunable(int precision) {
+  return precision == MVG_FP64 || precision == MVG_DST || precision == MVG_MIXED_FP32 ||
+         precision == MVG_MIXED_BF16;
+}
+
+int mvg_autotune_nb(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
+                    const mvg_theta *th, const mvg_opts *o, const int *cand, int n_cand,
+                    int *best_nb, double *h_seconds, void *hip_stream) {
+  if (!d_x || !d_y || !d_z) return -1;
+  if (n_loc < 1) return -4;
+  MaternArgs tmp;
+  if (!th || matern_setup(th, &tmp)) return -5;
+  mvg_opts base{};
+  if (o) base = *o;
+  base.nb = 0;
+  mvg_opts d;
+  if (normalize_opts(&base, &d) || !tunable(d.precision)) return -6;
+  static const int dflt[4] = {256, 512, 768, 1024};
+  if (!cand) {
+    cand = dflt;
+    n_cand = 4;
+  }
+  if (n_cand < 1 || n_cand > 16) return -8;
+  for (int i = 0; i < n_cand; ++i)
+    if (cand[i] != 128 && cand[i] != 256 && cand[i] != 512 && cand[i] != 768 && cand[i] != 1024)
+      return -7;
+  if (!best_nb) return -9;
+  const auto key = std::make_tuple(n_loc, d.precision, d.band_tiles);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *best_nb = it->second;
+      return 1;
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  double best_t = INFINITY;
+  int best = 0;
+  for (int i = 0; i < n_cand; ++i) {
+    mvg_opts c = d;
+    c.nb = cand[i];
+    double ll = 0.0, t = INFINITY;
+    int rc = loglik(d_x, d_y, d_z, n_loc, th, 1, &c, &ll, nullptr, nullptr, nullptr, nullptr, st);
+    if (!rc) {
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = loglik(d_x, d_y, d_z, n_loc, th, 1, &c, &ll, nullptr, nullptr, nullptr, nullptr, st);
+      if (!rc) t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc && rc != MVG_ERR_ALLOC) return rc;  // a tile too large for memory is just skipped
+    if (h_seconds) h_seconds[i] = t;
+    if (t < best_t) {
+      best_t = t;
+      best = cand[i];
+    }
+  }
+  if (!best) {
+    set_error("autotune: no candidate tile size ran");
+    return MVG_ERR_ALLOC;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  *best_nb = best;
+  return 0;
+}
+
 int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
            const mvg_theta *th, int n_theta, const mvg_opts *o, double *h_loglik,
            double *h_logdet, double *h_quad, int64_t *h_status, mvg_factor **keep,
@@ -855,6 +931,15 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   if (n_loc < 1) return -4;
   if (!th) return -5;
   if (n_theta < 1) return -6;
+  if (o && o->nb == MVG_NB_AUTO) {  // resolve the tile size, then evaluate as usual
+    if (!tunable(o->precision)) return -7;
+    mvg_opts c = *o;
+    int rc = mvg_autotune_nb(d_x, d_y, d_z, n_loc, &th[0], o, nullptr, 0, &c.nb, nullptr,
+                             hip_stream);
+    if (rc < 0) return rc;
+    return loglik(d_x, d_y, d_z, n_loc, th, n_theta, &c, h_loglik, h_logdet, h_quad, h_status,
+                  keep, hip_stream);
+  }
   mvg_opts d;
   if (normalize_opts(o, &d)) return -7;
   if (!h_loglik) return -8;
