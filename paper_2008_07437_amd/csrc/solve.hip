@@ -19,34 +19,40 @@ constexpr int VB = 64;  // rows per workgroup chunk of the per-column kernels
 // The diagonal tiles are solved with the inverses W_k kept by the
 // factorisation: each step is a dense triangular matrix-vector product.
 
-// v_k <- W_k v_k (one workgroup; W_k lower triangular, column-major).
+// y_k = W_k x_k (W_k lower triangular, column-major): 64 output rows per
+// workgroup (nb / 64 workgroups per right-hand side), the four waves take a
+// quarter of the columns c <= r each and are added in a fixed order.  Reads
+// x from X, writes y to Y (out of place: other workgroups still read x).
 __global__ __launch_bounds__(256) void k_trsv_tile_fwd(int nb, int k, const double *__restrict__ winv,
-                                                       double *__restrict__ V, int64_t ldv) {
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ Y, int64_t ldv) {
   __shared__ double v[1024];
-  const int tid = threadIdx.x;
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  __shared__ double part[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * 64, r = r0 + lane;
+  const double *xk = X + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
   const double *W = winv + (int64_t)k * nb * nb;
-  for (int r = tid; r < nb; r += 256) v[r] = vk[r];
+  const int cend = r0 + 64;  // columns c < cend can meet rows r0..r0+63
+  for (int c = tid; c < cend; c += 256) v[c] = xk[c];
   __syncthreads();
-  // rows r0..r0+255 per pass; the 4 waves split the columns c <= r
-  double out[4];
-  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
-    const int r = pass * 256 + tid;
-    double acc = 0.0;
-    if (r < nb)
-      for (int c = 0; c <= r; ++c) acc += W[(int64_t)c * nb + r] * v[c];
-    out[pass] = acc;
+  const int q = cend / 4;    // a multiple of 16
+  double s0 = 0.0, s1 = 0.0;
+  for (int c = wave * q; c < wave * q + q; c += 2) {
+    if (c <= r) s0 += W[(int64_t)c * nb + r] * v[c];
+    if (c + 1 <= r) s1 += W[(int64_t)(c + 1) * nb + r] * v[c + 1];
   }
-  for (int pass = 0; pass < (nb + 255) / 256; ++pass) {
-    const int r = pass * 256 + tid;
-    if (r < nb) vk[r] = out[pass];
-  }
+  part[wave][lane] = s0 + s1;
+  __syncthreads();
+  if (tid < 64)
+    Y[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + r0 + tid] =
+        (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
 }
 
-// v_i -= L_ik y_k for tiles i in (k, T): 64 rows per workgroup, the four waves
-// take a quarter of the columns each and are added in a fixed order.
+// v_i -= L_ik y_k for tiles i in (k, T), y_k read from Y: 64 rows per
+// workgroup, the four waves take a quarter of the columns each and are added
+// in a fixed order.
 __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__restrict__ V,
-                                                 int64_t ldv) {
+                                                 const double *__restrict__ Y, int64_t ldv) {
   __shared__ double y[1024];
   __shared__ double part[4][64];
   const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__re
   const int chunks = nb / 64;
   const int i = k + 1 + blockIdx.x / chunks;
   const int r = (blockIdx.x % chunks) * 64 + lane;
-  for (int c = tid; c < nb; c += 256) y[c] = Vc[(int64_t)k * nb + c];
+  for (int c = tid; c < nb; c += 256) y[c] = Y[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + c];
   __syncthreads();
   const int q = nb / 4;
   double s0 = 0.0, s1 = 0.0;
@@ -77,39 +83,39 @@ __global__ __launch_bounds__(256) void k_gemv_fwd(TileMap M, int k, double *__re
     Vc[(int64_t)i * nb + r] -= (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
 }
 
-// v_k <- W_k^T v_k: output c = sum_{r >= c} W[r][c] v[r] (column c of W_k is
-// contiguous); one workgroup.
+// y_k = W_k^T x_k: output c = sum_{r >= c} W[r][c] x[r] (column c of W_k is
+// contiguous); 64 outputs per workgroup (nb / 64 workgroups per right-hand
+// side), one wave per output at a time, lanes over rows.  Out of place.
 __global__ __launch_bounds__(256) void k_trsv_tile_bwd(int nb, int k, const double *__restrict__ winv,
-                                                       double *__restrict__ V, int64_t ldv) {
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ Y, int64_t ldv) {
   __shared__ double v[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  const int c0 = blockIdx.x * 64;
+  const double *xk = X + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
   const double *W = winv + (int64_t)k * nb * nb;
-  for (int r = tid; r < nb; r += 256) v[r] = vk[r];
+  for (int r = c0 + tid; r < nb; r += 256) v[r] = xk[r];
   __syncthreads();
-  __shared__ double out[1024];
-  for (int c = wave; c < nb; c += 4) {
+  for (int c = c0 + wave; c < c0 + 64; c += 4) {
     const double *col = W + (int64_t)c * nb;
     double t = 0.0;
     for (int r = c + lane; r < nb; r += 64) t += col[r] * v[r];
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0) out[c] = t;
+    if (lane == 0) Y[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + c] = t;
   }
-  __syncthreads();
-  for (int r = tid; r < nb; r += 256) vk[r] = out[r];
 }
 
-// v_j -= L_kj^T w_k for tiles j in [0, k): 64 columns per workgroup, one wave
-// per column at a time, lanes over rows.
+// v_j -= L_kj^T w_k for tiles j in [0, k), w_k read from Y: 64 columns per
+// workgroup, one wave per column at a time, lanes over rows.
 __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__restrict__ V,
-                                                 int64_t ldv) {
+                                                 const double *__restrict__ Y, int64_t ldv) {
   __shared__ double w[1024];
   const int nb = M.nb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double *Vc = V + (int64_t)blockIdx.z * ldv;
   const int cb = nb / 64;
   const int j = blockIdx.x / cb;
   const int c0 = (blockIdx.x % cb) * 64;
-  for (int r = tid; r < nb; r += 256) w[r] = Vc[(int64_t)k * nb + r];
+  for (int r = tid; r < nb; r += 256) w[r] = Y[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + r];
   __syncthreads();
   const bool f32 = tile_is_f32(M, k, j);
   for (int c = c0 + wave; c < c0 + 64; c += 4) {
@@ -124,6 +130,25 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__re
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) Vc[(int64_t)j * nb + c] -= s;
   }
+}
+
+// Scratch of the per-column solves: the solved tiles (Np x nrhs).
+static int solve_scratch(const mvg_mat *A, int nrhs, double **Y, hipStream_t st) {
+  if (hipMallocAsync((void **)Y, sizeof(double) * A->Np * nrhs, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("solve workspace of %.3f GB failed", A->Np * nrhs * 8.0 / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  return 0;
+}
+
+// Copy the solution back into V and release the scratch.
+static int solve_finish(const mvg_mat *A, double *V, double *Y, int nrhs, int rc, hipStream_t st) {
+  if (!rc && hipMemcpyAsync(V, Y, sizeof(double) * A->Np * nrhs, hipMemcpyDeviceToDevice, st) !=
+                 hipSuccess)
+    rc = MVG_ERR_LAUNCH;
+  hipFreeAsync(Y, st);
+  return rc;
 }
 
 static int solve_args_ok(const mvg_mat *A) {
@@ -256,19 +281,24 @@ int trsm_forward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st) 
         return rc;
     return 0;
   }
+  // solved tiles go to Y (the tile solve is out of place), the updates to V;
+  // Y is copied back at the end
+  double *Y = nullptr;
+  if (int rc = solve_scratch(A, nrhs, &Y, st)) return rc;
   const TileMap M = A->map();
   const int chunks = M.nb / 64;
-  for (int k = 0; k < M.T; ++k) {
-    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, M.nb, k,
-                       (const double *)A->d_winv, d_V, A->Np);
-    if (int rc = check_launch("trsv_tile_fwd")) return rc;
-    if (k + 1 < M.T) {
+  int rc = 0;
+  for (int k = 0; k < M.T && !rc; ++k) {
+    hipLaunchKernelGGL(k_trsv_tile_fwd, dim3(chunks, 1, nrhs), dim3(256), 0, st, M.nb, k,
+                       (const double *)A->d_winv, (const double *)d_V, Y, A->Np);
+    rc = check_launch("trsv_tile_fwd");
+    if (!rc && k + 1 < M.T) {
       hipLaunchKernelGGL(k_gemv_fwd, dim3((M.T - k - 1) * chunks, 1, nrhs), dim3(256), 0, st, M, k,
-                         d_V, A->Np);
-      if (int rc = check_launch("gemv_fwd")) return rc;
+                         d_V, (const double *)Y, A->Np);
+      rc = check_launch("gemv_fwd");
     }
   }
-  return 0;
+  return solve_finish(A, d_V, Y, nrhs, rc, st);
 }
 
 int trsv_forward(const mvg_mat *A, double *d_v, hipStream_t st) {
@@ -290,19 +320,22 @@ int trsm_backward_multi(const mvg_mat *A, double *d_V, int nrhs, hipStream_t st)
         return rc;
     return 0;
   }
+  double *Y = nullptr;
+  if (int rc = solve_scratch(A, nrhs, &Y, st)) return rc;
   const TileMap M = A->map();
   const int nb = M.nb;
-  for (int k = M.T - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(1, 1, nrhs), dim3(256), 0, st, nb, k,
-                       (const double *)A->d_winv, d_V, A->Np);
-    if (int rc = check_launch("trsv_tile_bwd")) return rc;
-    if (k > 0) {
+  int rc = 0;
+  for (int k = M.T - 1; k >= 0 && !rc; --k) {
+    hipLaunchKernelGGL(k_trsv_tile_bwd, dim3(nb / 64, 1, nrhs), dim3(256), 0, st, nb, k,
+                       (const double *)A->d_winv, (const double *)d_V, Y, A->Np);
+    rc = check_launch("trsv_tile_bwd");
+    if (!rc && k > 0) {
       hipLaunchKernelGGL(k_gemv_bwd, dim3(k * (nb / 64), 1, nrhs), dim3(256), 0, st, M, k, d_V,
-                         A->Np);
-      if (int rc = check_launch("gemv_bwd")) return rc;
+                         (const double *)Y, A->Np);
+      rc = check_launch("gemv_bwd");
     }
   }
-  return 0;
+  return solve_finish(A, d_V, Y, nrhs, rc, st);
 }
 
 int trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
