@@ -18,6 +18,7 @@ namespace mvg {
 
 constexpr int SB = 32;             // column block
 constexpr int SW = 8;              // waves per workgroup
+constexpr int TU = 2;              // trailing tiles per wave in flight together
 constexpr int STHREADS = 64 * SW;
 
 typedef double dbl4s __attribute__((ext_vector_type(4)));
@@ -54,18 +55,24 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
       s_quad = 0.0;
     }
     __syncthreads();
-    // Sigma: 2 x 2 blocks of location pairs l >= r
-    for (int r = 0; r < n; ++r) {
-      const double xr = tk.x[r], yr = tk.y[r];
-      for (int l = r + tid; l < n; l += STHREADS) {
-        double c[3];
-        cross_cov_block(tk.x[l], tk.y[l], xr, yr, tk.P, sq, c);
-        double *a = A + (int64_t)(2 * r) * N + 2 * l;
-        a[0] = c[0];
-        a[1] = c[2];
-        a[N] = c[2];
-        a[N + 1] = c[1];
-      }
+    // Sigma: 2 x 2 blocks of the n (n + 1) / 2 location pairs l >= r, pair
+    // p = r (2n - r + 1) / 2 + (l - r), spread evenly over the threads
+    const int npair = n * (n + 1) / 2;
+    for (int pq = tid; pq < npair; pq += STHREADS) {
+      // r = the column whose pairs contain pq (exact integer fix-up after the root)
+      const double nn = 2.0 * n + 1.0;
+      int r = (int)((nn - sqrt(nn * nn - 8.0 * (double)pq)) * 0.5);
+      r = max(0, min(r, n - 1));
+      while (r > 0 && r * (2 * n - r + 1) / 2 > pq) --r;
+      while (r + 1 < n && (r + 1) * (2 * n - r) / 2 <= pq) ++r;
+      const int l = r + (pq - r * (2 * n - r + 1) / 2);
+      double c[3];
+      cross_cov_block(tk.x[l], tk.y[l], tk.x[r], tk.y[r], tk.P, sq, c);
+      double *a = A + (int64_t)(2 * r) * N + 2 * l;
+      a[0] = c[0];
+      a[1] = c[2];
+      a[N] = c[2];
+      a[N + 1] = c[1];
     }
     __syncthreads();
     for (int k0 = 0; k0 < N; k0 += SB) {
@@ -163,35 +170,51 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
         zv[i] -= zi;
       }
       // (c) trailing update A_ij -= L_i L_j^T for k0 + kb <= j <= i, 16 x 16
-      //     tiles on MFMA (lane j + 16 (i % 4), element i / 4 of a tile)
+      //     tiles on MFMA (lane j + 16 (i % 4), element i / 4 of a tile); a
+      //     wave takes TU tiles at a time so that their loads are in flight
+      //     together (the workspace is in global memory: latency-bound)
       const int m = (N - r0 + 15) / 16;
       const int ntile = m * (m + 1) / 2;
-      for (int t = wave; t < ntile; t += SW) {
-        int I = 0, rem = t;  // tile (I, J), J <= I, row-major over the lower triangle
-        while (rem > I) {
-          rem -= I + 1;
-          ++I;
-        }
-        const int J = rem;
-        const int rowA = r0 + I * 16 + l16, rowB = r0 + J * 16 + l16;
-        dbl4s acc;
+      for (int t0 = wave; t0 < ntile; t0 += SW * TU) {
+        int I[TU], J[TU];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gi = r0 + I * 16 + 4 * e + lk, gj = r0 + J * 16 + l16;
-          acc[e] = (gi < N && gj < N) ? A[(int64_t)gj * N + gi] : 0.0;
+        for (int u = 0; u < TU; ++u) {  // tile (I, J), J <= I, row-major over the lower triangle
+          const int t = t0 + u * SW;
+          int ii = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+          while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;  // exact after rounding
+          while (ii * (ii + 1) / 2 > t) --ii;
+          I[u] = t < ntile ? ii : m;  // past the end: a row of tiles beyond N (all masked)
+          J[u] = t < ntile ? t - ii * (ii + 1) / 2 : 0;
+        }
+        dbl4s acc[TU];
+        double av[TU][SB / 4], bv[TU][SB / 4];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) {
+          const int rowA = r0 + I[u] * 16 + l16, rowB = r0 + J[u] * 16 + l16;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int gi = r0 + I[u] * 16 + 4 * e + lk, gj = r0 + J[u] * 16 + l16;
+            acc[u][e] = (gi < N && gj < N) ? A[(int64_t)gj * N + gi] : 0.0;
+          }
+#pragma unroll
+          for (int kk = 0; kk < SB / 4; ++kk) {
+            const int q = 4 * kk + lk;
+            av[u][kk] = (rowA < N && q < kb) ? -A[(int64_t)(k0 + q) * N + rowA] : 0.0;
+            bv[u][kk] = (rowB < N && q < kb) ? A[(int64_t)(k0 + q) * N + rowB] : 0.0;
+          }
         }
 #pragma unroll
-        for (int ks = 0; ks < SB; ks += 4) {
-          const int q = ks + lk;
-          const double av = (rowA < N && q < kb) ? -A[(int64_t)(k0 + q) * N + rowA] : 0.0;
-          const double bv = (rowB < N && q < kb) ? A[(int64_t)(k0 + q) * N + rowB] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
+        for (int u = 0; u < TU; ++u)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gi = r0 + I * 16 + 4 * e + lk, gj = r0 + J * 16 + l16;
-          if (gi < N && gj < N) A[(int64_t)gj * N + gi] = acc[e];
-        }
+          for (int kk = 0; kk < SB / 4; ++kk)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][kk], bv[u][kk], acc[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < TU; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int gi = r0 + I[u] * 16 + 4 * e + lk, gj = r0 + J[u] * 16 + l16;
+            if (gi < N && gj < N) A[(int64_t)gj * N + gi] = acc[u][e];
+          }
       }
       __syncthreads();
     }

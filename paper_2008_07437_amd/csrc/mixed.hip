@@ -143,7 +143,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("" ::: "memory");
       const int p = kb + LS - 1;
+      __builtin_amdgcn_s_setprio(1);  // get the refill in flight first (as in the FP64 update)
       LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
+      __builtin_amdgcn_s_setprio(0);
       const float *a = LP_STA(u) + wr * 64 + l16;
       const float *bb = LP_STB(u) + wc * 64 + l16;
       flt4 part[4][4];
@@ -248,7 +250,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("" ::: "memory");
       const int p = kb + LS - 1;
+      __builtin_amdgcn_s_setprio(1);  // get the refill in flight first (as in the FP64 update)
       LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
+      __builtin_amdgcn_s_setprio(0);
       bf16x8 af[4], bf[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
