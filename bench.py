@@ -162,7 +162,7 @@ def run_tlr(args, mvg, dev, synthetic, torch):
     if not args.no_dense_ref:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ref = mvg.loglik(xs, ys, z, th, {"nb": 512})
+        ref = mvg.loglik(xs, ys, z, th, {"nb": 1024})
         torch.cuda.synchronize()
         dense = {"evals_per_s": 1.0 / (time.perf_counter() - t0), "loglik": float(ref["loglik"][0])}
     accs = [float(a) for a in args.accs.split(",")]
@@ -438,7 +438,7 @@ def main():
     ap.add_argument("--a", type=float, default=0.1)
     ap.add_argument("--nb", type=int, default=0,
                     help="tile size (0: dense workload autotunes among 256/512/768/1024; "
-                         "the others use 512)")
+                         "mloe / trivariate / mle use 1024)")
     ap.add_argument("--targets", type=int, default=100)
     ap.add_argument("--cpu-sample-n", type=int, default=2400)
     ap.add_argument("--no-cpu", action="store_true")
@@ -487,7 +487,7 @@ def main():
         return
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
     tune_nb = args.workload == "dense" and args.nb == 0
-    args.nb = args.nb or 512
+    args.nb = args.nb or 1024   # the size the autotuner picks at n = 25,600
     if args.workload == "tlr":
         args.n = args.n or 100000
         return run_tlr(args, mvg, dev, synthetic, torch)
