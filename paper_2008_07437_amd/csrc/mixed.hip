@@ -143,11 +143,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("" ::: "memory");
       const int p = kb + LS - 1;
-      __builtin_amdgcn_s_setprio(1);  // get the refill in flight first (as in the FP64 update)
-      LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
-      __builtin_amdgcn_s_setprio(0);
+      // as in the FP64 update: the first k-step's fragments are read, then
+      // the refill issued, at raised priority
+      __builtin_amdgcn_s_setprio(1);
       const float *a = LP_STA(u) + wr * 64 + l16;
       const float *bb = LP_STB(u) + wc * 64 + l16;
+      float af0[4], bf0[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        af0[t] = (MODE == LP_UPDATE) ? -a[lk * LB + t * 16] : a[lk * LB + t * 16];
+        bf0[t] = bb[lk * LB + t * 16];
+      }
+      LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
+      __builtin_amdgcn_s_setprio(0);
       flt4 part[4][4];
 #pragma unroll
       for (int ti = 0; ti < 4; ++ti)
@@ -158,8 +166,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         float af[4], bf[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          af[t] = (MODE == LP_UPDATE) ? -a[(ks + lk) * LB + t * 16] : a[(ks + lk) * LB + t * 16];
-          bf[t] = bb[(ks + lk) * LB + t * 16];
+          af[t] = ks == 0 ? af0[t]
+                          : ((MODE == LP_UPDATE) ? -a[(ks + lk) * LB + t * 16]
+                                                 : a[(ks + lk) * LB + t * 16]);
+          bf[t] = ks == 0 ? bf0[t] : bb[(ks + lk) * LB + t * 16];
         }
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti)
@@ -250,9 +260,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("" ::: "memory");
       const int p = kb + LS - 1;
-      __builtin_amdgcn_s_setprio(1);  // get the refill in flight first (as in the FP64 update)
-      LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
-      __builtin_amdgcn_s_setprio(0);
+      // the fragments are read, then the refill issued, at raised priority
+      __builtin_amdgcn_s_setprio(1);
       bf16x8 af[4], bf[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -265,6 +274,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         af[t] = __builtin_bit_cast(bf16x8, va);
         bf[t] = __builtin_bit_cast(bf16x8, vb);
       }
+      LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
       for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
