@@ -367,7 +367,7 @@ constexpr int BWV = 8;  // waves per blocked-QR workgroup
 
 template <int QE, int NC>
 __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, int p0, int m,
-                                            int bw, const double (*V)[QB], const double (*T)[QB],
+                                            int bw, const double (*V)[QR_MAXM], const double (*T)[QB],
                                             bool trans, int lane) {
   // columns c0, c0 + BWV, ... (< n): rows p0..m-1 <- (I - V op(T) V^T) rows
   double y[NC][QB];
@@ -392,7 +392,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
       if (p0 + r < m)
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-          const double vq = V[r][q];
+          const double vq = V[q][r];
 #pragma unroll
           for (int k = 0; k < NC; ++k) y[k][q] += vq * x[k][e];
         }
@@ -432,7 +432,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
       if (i < m) {
         double d = 0.0;
 #pragma unroll
-        for (int q = 0; q < QB; ++q) d += V[r][q] * y[k][q];
+        for (int q = 0; q < QB; ++q) d += V[q][r] * y[k][q];
         col[i] -= d;
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -442,7 +442,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
 
 template <int QE, int NC>
 __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restrict__ tasks) {
-  __shared__ double V[QR_MAXM][QB];
+  __shared__ double V[QB][QR_MAXM];  // reflector q in V[q][.]: lane-contiguous reads
   __shared__ double T[QB][QB];
   __shared__ double G[QB][QB];
   __shared__ double s_tau[QB];
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restric
   double *Tg = tk.tau;  // n x QB: T of panel p at rows p .. p + QB - 1
   for (int p0 = 0; p0 < n; p0 += QB) {
     const int bw = min(QB, n - p0);
-    for (int e = tid; e < (m - p0) * QB; e += 64 * BWV) V[e / QB][e % QB] = 0.0;
+    for (int e = tid; e < (m - p0) * QB; e += 64 * BWV) V[e % QB][e / QB] = 0.0;
     __syncthreads();
     // panel: reflectors of columns p0 .. p0 + bw - 1
     for (int jj = 0; jj < bw; ++jj) {
@@ -476,23 +476,23 @@ __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restric
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      for (int i = j + 1 + tid; i < m; i += 64 * BWV) V[i - p0][jj] = aj[i] * scale;
+      for (int i = j + 1 + tid; i < m; i += 64 * BWV) V[jj][i - p0] = aj[i] * scale;
       if (tid == 0) {
-        V[j - p0][jj] = 1.0;
+        V[jj][j - p0] = 1.0;
         s_tau[jj] = tau;
       }
       __syncthreads();
-      for (int i = j + 1 + tid; i < m; i += 64 * BWV) aj[i] = V[i - p0][jj];
+      for (int i = j + 1 + tid; i < m; i += 64 * BWV) aj[i] = V[jj][i - p0];
       if (tid == 0) aj[j] = beta;
       // the remaining panel columns, one per wave
       const int c = j + 1 + wave;
       if (tau != 0.0 && c < p0 + bw) {
         double *ac = A + (int64_t)c * lda;
         double w = 0.0;
-        for (int i = j + lane; i < m; i += 64) w += V[i - p0][jj] * ac[i];
+        for (int i = j + lane; i < m; i += 64) w += V[jj][i - p0] * ac[i];
         for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
         const double tw = tau * w;
-        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * V[i - p0][jj];
+        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * V[jj][i - p0];
       }
       __syncthreads();
     }
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restric
       const int a = q / QB, b = q % QB;
       double d = 0.0;
       if (a < b && b < bw)
-        for (int r = lane; r < m - p0; r += 64) d += V[r][a] * V[r][b];
+        for (int r = lane; r < m - p0; r += 64) d += V[a][r] * V[b][r];
       for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
       if (lane == 0) G[a][b] = d;
     }
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restric
       const int r = e / QB, q = e % QB, i = p0 + r;
       double val = 0.0;
       if (q < bw) val = (r == q) ? 1.0 : (r > q ? A[(int64_t)(p0 + q) * lda + i] : 0.0);
-      V[r][q] = val;
+      V[q][r] = val;
     }
     for (int e = tid; e < QB * QB; e += 64 * BWV) T[e / QB][e % QB] = Tg[(int64_t)(p0 + e / QB) * QB + e % QB];
     __syncthreads();
