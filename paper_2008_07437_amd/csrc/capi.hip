@@ -154,6 +154,29 @@ __global__ void k_mse_final(const double *__restrict__ ss, int64_t m, double trc
   mse[t] = trc0 - (ss[2 * t] + ss[2 * t + 1]);
 }
 
+__global__ void k_add_pair(const double *__restrict__ s, double *__restrict__ out) {
+  if (threadIdx.x == 0) out[0] = s[0] + s[1];
+}
+
+__global__ void k_stride_copy(const double *__restrict__ z, int p, int i, int64_t n,
+                              double *__restrict__ out) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < n) out[l] = z[(int64_t)p * l + i];
+}
+
+__global__ void k_loe_mom(const double *__restrict__ sT, const double *__restrict__ sA,
+                          const double *__restrict__ dT, const double *__restrict__ sQ, int64_t m,
+                          double trt, double tra, double *__restrict__ loe,
+                          double *__restrict__ mom) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= m) return;
+  const double et = trt - (sT[2 * l] + sT[2 * l + 1]);
+  const double ea = tra - (sA[2 * l] + sA[2 * l + 1]);
+  const double eta = trt - 2.0 * (dT[2 * l] + dT[2 * l + 1]) + (sQ[2 * l] + sQ[2 * l + 1]);
+  loe[l] = eta / et - 1.0;
+  mom[l] = ea / eta - 1.0;
+}
+
 __global__ void k_copy_pad(const double *__restrict__ src, int64_t n, double *__restrict__ dst,
                            int64_t np) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,9 +585,6 @@ static int eval_one(mvg_mat *A, const double *d_z, double *d_yv, double *d_part,
 // quadratic form is then known to ~IR_QUAD_TOL^2 relative.
 constexpr double IR_QUAD_TOL = 1e-10;
 
-__global__ void k_add_pair(const double *__restrict__ s, double *__restrict__ out) {
-  if (threadIdx.x == 0) out[0] = s[0] + s[1];
-}
 
 struct IrStat {
   int iters, converged;
@@ -1165,11 +1185,6 @@ int loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_
                       (hipStream_t)hip_stream);
 }
 
-__global__ void k_stride_copy(const double *__restrict__ z, int p, int i, int64_t n,
-                              double *__restrict__ out) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < n) out[l] = z[(int64_t)p * l + i];
-}
 
 int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
                      const mvg_theta_p *th, const mvg_opts *o, double *h_sigma_sq,
@@ -1236,18 +1251,6 @@ int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, in
   return loglik_p(d_x, d_y, d_z, n_loc, &t, 1, o, h_loglik, h_logdet, h_quad, h_status, hip_stream);
 }
 
-__global__ void k_loe_mom(const double *__restrict__ sT, const double *__restrict__ sA,
-                          const double *__restrict__ dT, const double *__restrict__ sQ, int64_t m,
-                          double trt, double tra, double *__restrict__ loe,
-                          double *__restrict__ mom) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= m) return;
-  const double et = trt - (sT[2 * l] + sT[2 * l + 1]);
-  const double ea = tra - (sA[2 * l] + sA[2 * l + 1]);
-  const double eta = trt - 2.0 * (dT[2 * l] + dT[2 * l + 1]) + (sQ[2 * l] + sQ[2 * l + 1]);
-  loe[l] = eta / et - 1.0;
-  mom[l] = ea / eta - 1.0;
-}
 
 // Section 5.4, Eq. (5)-(8), Algorithm 1 on two dense FP64 factors.
 int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_theta *th,
