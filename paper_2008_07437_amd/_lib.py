@@ -217,6 +217,18 @@ class Factor:
     def handle(self):
         return self._h
 
+    def gather(self, rows, cols, stream=None) -> torch.Tensor:
+        """Entries (rows[t], cols[t]), rows >= cols, of the factor L."""
+        r = torch.as_tensor(np.asarray(rows, dtype=np.int64)).cuda()
+        c = torch.as_tensor(np.asarray(cols, dtype=np.int64)).cuda()
+        out = torch.empty(r.numel(), dtype=torch.float64, device="cuda")
+        mat = c_void_p(_load().mvg_factor_mat(self._h))
+        _check("mvg_mat_gather", _load().mvg_mat_gather(mat, c_void_p(r.data_ptr()),
+                                                       c_void_p(c.data_ptr()), r.numel(),
+                                                       c_void_p(out.data_ptr()), _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return out
+
     def w(self, n: int) -> torch.Tensor:
         """w = Sigma^-1 Z (first 2n entries), copied out."""
         ptr = _load().mvg_factor_w(self._h)

@@ -1,0 +1,156 @@
+"""GPU checks at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark times, on outputs the oracle can compute one by
+one or through properties that hold at any size:
+
+* dense FP64, n = 25,600 (51,200^2), nb 1024 (the tile size the autotuner
+  picks): sampled covariance entries against the oracle's entries; the
+  solution w = Sigma^-1 Z against the oracle's own rows of Sigma (the
+  residual (Sigma w - Z)_r at sampled rows r, relative to sum_c
+  |Sigma_rc w_c|: a backward-stable Cholesky leaves it at ~n u);
+  log|Sigma| against 2 sum log L_jj from the gathered diagonal; the
+  quadratic form against Z^T w; cokriging against c0^T w with the oracle's
+  c0;
+* mixed FP32, n = 50,000 (100,000^2): relative delta loglik against the FP64
+  path <= 1e-6 and the refined solution's residual against the oracle's rows;
+* TLR, n = 100,000 (200,000^2), tile 1200, acc 1e-7: relative delta loglik
+  against the FP64 path <= 1e-6;
+* batched, 1024 theta at n = 400: sampled tasks against the oracle.
+
+Z is seeded white noise (an input; no input or expected value comes from
+the GPU path)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_2008_07437_amd as m
+    m._lib._load()
+    return m
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+TH = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+
+
+def _sites(orc, n, seed=0):
+    x, y = synthetic.jittered_grid(n, seed)
+    p = orc.morton_order(x, y)
+    return x[p], y[p]
+
+
+def _residual_rows(orc, x, y, th, w, z, rows):
+    """max over rows r of |(Sigma w)_r - z_r| / sum_c |Sigma_rc w_c| with the
+    oracle's entries of Sigma (one row at a time)."""
+    N = 2 * x.size
+    worst = 0.0
+    cols = np.arange(N, dtype=np.int64)
+    for r in rows:
+        srow = orc.cov_entries(x, y, th, np.full(N, r, dtype=np.int64), cols)
+        num = abs(float(np.dot(srow, w)) - z[r])
+        den = float(np.sum(np.abs(srow * w)))
+        worst = max(worst, num / den)
+    return worst
+
+
+def test_dense_fullsize_sampled(lib, orc):
+    n, nb = 25600, 1024
+    N = 2 * n
+    rng = np.random.default_rng(11)
+    x, y = _sites(orc, n)
+    z = synthetic.normal_eps(N, 0)
+    _say("full-size dense: covariance entries n=%d nb=%d" % (n, nb))
+    A = lib.cov_generate(_dev(x), _dev(y), TH, {"nb": nb})
+    r = rng.integers(0, N, 4096)
+    c = rng.integers(0, N, 4096)
+    r, c = np.maximum(r, c), np.minimum(r, c)
+    got = A.gather(r, c).cpu().numpy()
+    ref = orc.cov_entries(x, y, TH, r, c)
+    assert np.max(np.abs(got - ref)) <= 1e-13
+    del A
+    _say("full-size dense: loglik with resident factor")
+    res, F = lib.loglik(_dev(x), _dev(y), _dev(z), TH, {"nb": nb}, keep=True)
+    assert res["status"][0] == 0
+    w = F.w(n).cpu().numpy()
+    d = F.gather(np.arange(N), np.arange(N)).cpu().numpy()
+    logdet = 2.0 * float(np.sum(np.log(d)))
+    _say("  logdet gpu %.10f from diag %.10f; quad %.10f vs z.w %.10f"
+         % (res["logdet"][0], logdet, res["quad"][0], float(z @ w)))
+    assert abs(res["logdet"][0] - logdet) <= 1e-12 * abs(logdet)
+    assert abs(res["quad"][0] - float(z @ w)) <= 1e-10 * abs(res["quad"][0])
+    _say("full-size dense: residual rows against the oracle's Sigma")
+    worst = _residual_rows(orc, x, y, TH, w, z, rng.integers(0, N, 24))
+    _say("  max relative residual %.2e" % worst)
+    assert worst <= 1e-10
+    _say("full-size dense: cokriging")
+    x0, y0 = synthetic.uniform_targets(8, 3)
+    zh = lib.cokrige_predict(F, _dev(x0), _dev(y0)).cpu().numpy()
+    c0 = orc.cross_cov_targets(x, y, x0, y0, TH)
+    ref = (c0.T @ w).reshape(-1, 2)
+    scale = (np.abs(c0).T @ np.abs(w)).reshape(-1, 2)
+    assert np.max(np.abs(zh - ref) / scale) <= 1e-11
+
+
+def test_mixed_fullsize(lib, orc):
+    n = 50000
+    N = 2 * n
+    x, y = _sites(orc, n, 1)
+    z = synthetic.normal_eps(N, 1)
+    _say("full-size mixed: FP64 reference n=%d" % n)
+    d64 = lib.loglik(_dev(x), _dev(y), _dev(z), TH, {"nb": 1024})
+    _say("full-size mixed: FP32 band 2")
+    res, F = lib.loglik(_dev(x), _dev(y), _dev(z), TH,
+                        {"nb": 1024, "precision": lib.MVG_MIXED_FP32}, keep=True)
+    dl = abs(res["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
+    _say("  rel dloglik %.2e  IR %s" % (dl, lib.mvg_ir_stats(0)))
+    assert res["status"][0] == 0 and dl <= 1e-6
+    w = F.w(n).cpu().numpy()
+    worst = _residual_rows(orc, x, y, TH, w, z, np.random.default_rng(5).integers(0, N, 8))
+    _say("  refined solution: max relative residual %.2e" % worst)
+    assert worst <= 1e-10
+
+
+def test_tlr_fullsize(lib, orc):
+    n = 100000
+    x, y = _sites(orc, n, 0)
+    z = synthetic.normal_eps(2 * n, 0)
+    _say("full-size TLR: FP64 reference n=%d (200,000^2)" % n)
+    d64 = lib.loglik(_dev(x), _dev(y), _dev(z), TH, {"nb": 1024})
+    _say("full-size TLR: acc 1e-7, tile 1200")
+    t = lib.loglik(_dev(x), _dev(y), _dev(z), TH,
+                   {"nb": 1200, "precision": lib.MVG_TLR, "tlr_acc": 1e-7, "tlr_max_rank": 300})
+    dl = abs(t["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
+    _say("  rel dloglik %.2e" % dl)
+    assert t["status"][0] == 0 and dl <= 1e-6
+
+
+def test_batched_fullsize_sampled(lib, orc):
+    n = 400
+    x, y = _sites(orc, n, 0)
+    z = synthetic.normal_eps(2 * n, 0)
+    ths = synthetic.jittered_thetas(1024, 1)
+    _say("full-size batched: 1024 theta at n=%d" % n)
+    got = lib.loglik(_dev(x), _dev(y), _dev(z), ths, {"nb": 128})
+    for i in np.random.default_rng(2).choice(1024, 10, replace=False):
+        ref = orc.loglik(x, y, z, ths[i])
+        if ref["info"]:
+            assert got["status"][i] == ref["info"]
+        else:
+            assert abs(got["loglik"][i] - ref["loglik"]) <= 1e-9 * abs(ref["loglik"])
