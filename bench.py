@@ -188,6 +188,18 @@ def run_tlr(args, mvg, dev, synthetic, torch):
         if ref is not None:
             rec["rel_dloglik_vs_fp64"] = abs(r["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0])
         res["acc%g" % acc] = rec
+    simplex = None
+    if not args.no_simplex:  # the 7 points of a Nelder-Mead step in one call
+        pts = synthetic.nelder_mead_simplex(th)
+        o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": accs[0], "tlr_max_rank": 300}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r7 = mvg.loglik(xs, ys, z, pts, o)
+        torch.cuda.synchronize()
+        dt7 = time.perf_counter() - t0
+        simplex = {"points": len(pts), "seconds": dt7, "evals_per_s": len(pts) / dt7,
+                   "vs_one_at_a_time": (len(pts) / dt7) / res["acc%g" % accs[0]]["evals_per_s"],
+                   "failed": int((r7["status"] != 0).sum())}
     _, ranks = mvg.tlr_compress(xs, ys, th, {"nb": nb, "tlr_acc": accs[0], "tlr_max_rank": 300})
     T = ranks.shape[0]
     low = ranks[np.tril_indices(T, -1)]
@@ -198,7 +210,7 @@ def run_tlr(args, mvg, dev, synthetic, torch):
                        "max rank 300, theta=(1,1,%g,0.5,1,0.5)" % (n, 2 * n, 2 * n, nb, args.accs,
                                                                    args.a),
            "n_loc": n, "nb": nb, "precision": "tlr"},
-          tlr=res, dense_fp64=dense,
+          tlr=res, dense_fp64=dense, simplex7=simplex,
           ranks={"acc": accs[0], "median_offset1": int(np.median(np.diag(ranks, -1))),
                  "median_all": int(np.median(low[low >= 0])) if (low >= 0).any() else None,
                  "dense_tiles": int((low < 0).sum()), "tiles": int(low.size)})
@@ -454,6 +466,8 @@ def main():
                          "MLOE/MMOM at N=25,600 with 100 targets; trivariate: p = 3 at N=17,066; mle: Nelder-Mead at N=22,464")
     ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
     ap.add_argument("--no-dense-ref", action="store_true")
+    ap.add_argument("--no-simplex", action="store_true",
+                    help="TLR: skip the 7-point simplex evaluated in one call")
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--max-evals", type=int, default=40, help="MLE: likelihood evaluations")
     ap.add_argument("--requests", type=int, default=200)

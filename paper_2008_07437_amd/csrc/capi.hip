@@ -1,12 +1,15 @@
 // C ABI entry points (declared in include/mvgeo.h): argument checking, the
 // library-owned matrices and factors, and the orchestration of the kernels.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -868,6 +871,65 @@ int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *
   return run_small(tasks, nmax, h_loglik, h_logdet, h_quad, h_status, (hipStream_t)hip_stream);
 }
 
+// Several theta as independent evaluations on concurrent streams (one host
+// thread and stream each, up to TLR_CONCURRENT at a time and as many as the
+// free device memory holds).  A TLR evaluation is bound by its column-by-
+// column critical path (one workgroup per tile QR), so several together fill
+// the device; each result is the one a single call gives.
+constexpr int TLR_CONCURRENT = 4;
+
+static int loglik_concurrent(const double *d_x, const double *d_y, const double *d_z,
+                             int64_t n_loc, const mvg_theta *th, int n_theta, const mvg_opts &d,
+                             double *h_loglik, double *h_logdet, double *h_quad,
+                             int64_t *h_status, hipStream_t st) {
+  if (hipStreamSynchronize(st) != hipSuccess) {  // the inputs are ready on the caller's stream
+    set_error("stream synchronisation failed");
+    return MVG_ERR_LAUNCH;
+  }
+  int dev = 0;
+  hipGetDevice(&dev);
+  size_t free_b = 0, total_b = 0;
+  hipMemGetInfo(&free_b, &total_b);
+  const size_t need = std::max<size_t>(1, mvg_footprint(n_loc, &d));
+  const int nw = (int)std::max<size_t>(
+      1, std::min<size_t>({(size_t)n_theta, (size_t)TLR_CONCURRENT, free_b / need}));
+  std::atomic<int> next{0};
+  std::vector<int> rcs(nw, 0);
+  std::vector<std::string> errs(nw);
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nw; ++w)
+    pool.emplace_back([&, w] {
+      hipSetDevice(dev);
+      hipStream_t s = nullptr;
+      if (hipStreamCreate(&s) != hipSuccess) {
+        rcs[w] = MVG_ERR_LAUNCH;
+        errs[w] = "stream creation failed";
+        return;
+      }
+      for (;;) {
+        const int i = next++;
+        if (i >= n_theta) break;
+        const int rc = loglik(d_x, d_y, d_z, n_loc, &th[i], 1, &d, &h_loglik[i],
+                              h_logdet ? &h_logdet[i] : nullptr, h_quad ? &h_quad[i] : nullptr,
+                              h_status ? &h_status[i] : nullptr, nullptr, s);
+        if (rc) {
+          rcs[w] = rc;
+          errs[w] = mvg_last_error();
+          break;
+        }
+      }
+      hipStreamSynchronize(s);
+      hipStreamDestroy(s);
+    });
+  for (auto &t : pool) t.join();
+  for (int w = 0; w < nw; ++w)
+    if (rcs[w]) {
+      set_error("%s", errs[w].c_str());
+      return rcs[w];
+    }
+  return 0;
+}
+
 // ------------------------------------------------------------ autotuning
 
 static std::mutex g_tune_mu;
@@ -977,6 +1039,9 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16)
     return loglik_mixed(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
                         h_status, keep, st);
+  if (d.precision == MVG_TLR && n_theta > 1 && !keep)
+    return loglik_concurrent(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
+                             h_status, st);
   const bool tlr = d.precision == MVG_TLR;
   mvg_mat *A = nullptr;
   int rc = tlr ? tlr_mat_create(n_loc, d, &th[0], d_x, d_y, st, &A)
