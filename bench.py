@@ -141,6 +141,11 @@ def run_variants(mvg, xs, ys, z, th, args, ref_loglik, reps=2):
     return out
 
 
+def _step(msg):
+    """Progress of a long workload (stderr; the JSON line stays alone on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -156,10 +161,17 @@ def run_tlr(args, mvg, dev, synthetic, torch):
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
-    z = dev(synthetic.normal_eps(2 * n, args.seed))
+    # Z = L eps at the true theta from the FP64 factor (setup; 160 GB resident)
+    _step("tlr: Z = L eps from the FP64 factor, n=%d" % n)
+    A = mvg.cov_generate(xs, ys, th, {"nb": 1024})
+    if mvg.potrf_tiled(A):
+        raise SystemExit("Sigma(theta) not positive definite")
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    del A
     ref = None
     dense = {}
     if not args.no_dense_ref:
+        _step("tlr: dense FP64 reference evaluation")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ref = mvg.loglik(xs, ys, z, th, {"nb": 1024})
@@ -169,6 +181,7 @@ def run_tlr(args, mvg, dev, synthetic, torch):
     res = {}
     for acc in accs:
         o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300}
+        _step("tlr: acc %g, %d evaluation(s)" % (acc, max(1, args.steps)))
         mvg.mvg_prof_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -191,6 +204,7 @@ def run_tlr(args, mvg, dev, synthetic, torch):
     simplex = None
     if not args.no_simplex:  # the 7 points of a Nelder-Mead step in one call
         pts = synthetic.nelder_mead_simplex(th)
+        _step("tlr: %d simplex points in one call" % len(pts))
         o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": accs[0], "tlr_max_rank": 300}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -479,8 +493,8 @@ def main():
                     help="only run a plain device copy of this many GiB (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the factorisation would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -523,6 +537,7 @@ def main():
     # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    _step("dense: Z = L eps, n=%d" % n)
     A = mvg.cov_generate(xs, ys, th, {"nb": args.nb})
     info = mvg.potrf_tiled(A)
     if info:
@@ -531,6 +546,7 @@ def main():
     del A
     tuned = None
     if tune_nb:  # the library's autotuner picks the tile size on this problem (setup)
+        _step("dense: autotuning the tile size")
         args.nb, tuned = mvg.mvg_autotune_nb(xs, ys, z, th, {}, [256, 512, 768, 1024])
     x0r, y0r = synthetic.uniform_targets(args.targets, args.seed)
     x0, y0 = dev(x0r), dev(y0r)
@@ -546,6 +562,7 @@ def main():
         last["zhat0"] = zhat[0].tolist()
         del F
 
+    _step("dense: nb %d, %d warm-up + %d timed steps" % (args.nb, args.warmup, args.steps))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -602,8 +619,10 @@ def main():
                      "flops_per_launch": tr["flops"] / max(1, tr["launches"])},
     }
     if not args.no_variants:
+        _step("dense: mixed-precision and DST variants")
         out["variants"] = run_variants(mvg, xs, ys, z, th, args, last["loglik"])
     if not args.no_cpu:
+        _step("dense: oracle timing on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
     print(json.dumps(out), flush=True)
 
