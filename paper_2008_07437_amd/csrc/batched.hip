@@ -18,10 +18,91 @@ namespace mvg {
 
 constexpr int SB = 32;             // column block
 constexpr int SW = 8;              // waves per workgroup
-constexpr int TU = 2;              // trailing tiles per wave in flight together
 constexpr int STHREADS = 64 * SW;
 
 typedef double dbl4s __attribute__((ext_vector_type(4)));
+
+// A[col * N + row] from a clamped address inside the task's N x N workspace.
+// Masked entries are loaded unconditionally and zeroed afterwards, behind a
+// scheduling barrier: a load under a branch, or a select scheduled next to
+// its load, waits for the value at once, and a wave's loads then go out one
+// at a time instead of all in flight together.
+// The offset is formed in 32 bits (the workspace of one task is below 4 GiB)
+// so that the load takes the uniform base in scalar registers.
+__device__ __forceinline__ double clamped_load(const double *A, int N, int col, int row) {
+  const unsigned off = ((unsigned)min(col, N - 1) * (unsigned)N + (unsigned)min(row, N - 1)) * 8u;
+  return *(const double *)((const char *)A + off);
+}
+
+__device__ __forceinline__ double load_at(const double *A, int N, int col, int row) {
+  return *(const double *)((const char *)A + ((unsigned)col * (unsigned)N + (unsigned)row) * 8u);
+}
+
+__device__ __forceinline__ void store_at(double *A, int N, int col, int row, double v) {
+  *(double *)((char *)A + ((unsigned)col * (unsigned)N + (unsigned)row) * 8u) = v;
+}
+
+// C -= L_I L_J^T on one 32 x 32 block of the trailing matrix (2 x 2 tiles of
+// 16 x 16 on MFMA: lane j + 16 (i % 4), element i / 4 of a tile): rows
+// iA.., columns jB.., the panel in columns k0 .. k0 + kb.  Every panel
+// fragment loaded serves two tiles, and all loads are issued before the
+// first wait.  MASK: the block reaches past row N - 1 or kb < SB (masked
+// entries are loaded from clamped addresses and zeroed; stores are guarded).
+template <bool MASK>
+__device__ __forceinline__ void trail_block(double *A, int N, int k0, int kb, int iA, int jB,
+                                            bool diag, int l16, int lk) {
+  dbl4s acc[2][2];
+  double av[2][SB / 4], bv[2][SB / 4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kk = 0; kk < SB / 4; ++kk) {
+      const int q = k0 + (MASK ? min(4 * kk + lk, kb - 1) : 4 * kk + lk);
+      av[h][kk] = MASK ? clamped_load(A, N, q, iA + 16 * h + l16) : load_at(A, N, q, iA + 16 * h + l16);
+      bv[h][kk] = MASK ? clamped_load(A, N, q, jB + 16 * h + l16) : load_at(A, N, q, jB + 16 * h + l16);
+    }
+#pragma unroll
+  for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+    for (int hj = 0; hj < 2; ++hj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int col = jB + 16 * hj + l16, row = iA + 16 * hi + 4 * e + lk;
+        acc[hi][hj][e] = MASK ? clamped_load(A, N, col, row) : load_at(A, N, col, row);
+      }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kk = 0; kk < SB / 4; ++kk) {
+      if (MASK) {
+        const bool okq = 4 * kk + lk < kb;
+        av[h][kk] = (iA + 16 * h + l16 < N && okq) ? -av[h][kk] : 0.0;
+        if (!(jB + 16 * h + l16 < N && okq)) bv[h][kk] = 0.0;
+      } else {
+        av[h][kk] = -av[h][kk];
+      }
+    }
+#pragma unroll
+  for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+    for (int hj = 0; hj < 2; ++hj) {
+      if (diag && hi < hj) continue;
+      if (MASK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (!(iA + 16 * hi + 4 * e + lk < N && jB + 16 * hj + l16 < N)) acc[hi][hj][e] = 0.0;
+      }
+#pragma unroll
+      for (int kk = 0; kk < SB / 4; ++kk)
+        acc[hi][hj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[hi][kk], bv[hj][kk], acc[hi][hj], 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = iA + 16 * hi + 4 * e + lk, gj = jB + 16 * hj + l16;
+        if (!MASK || (gi < N && gj < N)) store_at(A, N, gj, gi, acc[hi][hj][e]);
+      }
+    }
+}
 
 __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__restrict__ tasks,
                                                            int ntask, int *__restrict__ counter,
@@ -32,6 +113,8 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
   __shared__ double sD[SB][SB + 1];   // diagonal block -> L_kk
   __shared__ double sW[SB][SB + 1];   // W = L_kk^-1
   __shared__ double sy[SB];
+  __shared__ double slg[SB];          // log L_jj of the block
+  __shared__ double szk[SB];          // z of the block's rows
   __shared__ int s_task, s_fail;
   __shared__ double s_logdet, s_quad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -82,6 +165,7 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
         const int r = e % kb, c = e / kb;
         sD[r][c] = (r >= c) ? A[(int64_t)(k0 + c) * N + k0 + r] : 0.0;
       }
+      if (tid < kb) szk[tid] = zv[k0 + tid];  // final: earlier blocks have updated it
       __syncthreads();
       for (int c = 0; c < kb; ++c) {
         const double d = sD[c][c];
@@ -93,10 +177,7 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
         }
         const double ljj = sqrt(d);
         __syncthreads();
-        if (tid == 0) {
-          sD[c][c] = ljj;
-          s_logdet += log(ljj);
-        }
+        if (tid == 0) sD[c][c] = ljj;
         for (int r = c + 1 + tid; r < kb; r += STHREADS) sD[r][c] /= ljj;
         __syncthreads();
         for (int e = tid; e < kb * kb; e += STHREADS) {
@@ -107,22 +188,35 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
       }
       __syncthreads();
       if (s_fail) break;
-      // W = L_kk^-1 by columns (thread c), then y_k = W z_k; entries outside
-      // the kb x kb block are zero
-      for (int e = tid; e < SB * SB; e += STHREADS) sW[e % SB][e / SB] = 0.0;
-      __syncthreads();
-      if (tid < kb) {
+      // log L_jj off the column loop's critical path, summed in column order
+      if (tid < kb) slg[tid] = log(sD[tid][tid]);
+      // W = L_kk^-1, column c by thread c with the column in registers (the
+      // rows above c are zeros, so the sums over q < c add exact zeros), then
+      // y_k = W z_k; entries outside the kb x kb block are zero
+      if (tid < SB) {
         const int c = tid;
-        for (int r = c; r < kb; ++r) {
+        double w[SB];
+#pragma unroll
+        for (int r = 0; r < SB; ++r) {
           double s = (r == c) ? 1.0 : 0.0;
-          for (int q = c; q < r; ++q) s -= sD[r][q] * sW[q][c];
-          sW[r][c] = s / sD[r][r];
+#pragma unroll
+          for (int q = 0; q < r; ++q) s -= sD[r][q] * w[q];
+          w[r] = (r >= c && r < kb) ? s / sD[r][r] : 0.0;
         }
+#pragma unroll
+        for (int r = 0; r < SB; ++r) sW[r][c] = w[r];
       }
       __syncthreads();
+      if (tid == 0) {
+        double ld = s_logdet;
+        for (int c = 0; c < kb; ++c) ld += slg[c];
+        s_logdet = ld;
+      }
       if (tid < SB) {
         double s = 0.0;
-        for (int q = 0; q <= tid && q < kb; ++q) s += sW[tid][q] * zv[k0 + q];
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+          if (q <= tid && q < kb) s += sW[tid][q] * szk[q];
         sy[tid] = tid < kb ? s : 0.0;
       }
       __syncthreads();
@@ -144,10 +238,11 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
         const int row = r0 + t * 16 + l16;
         double av[SB / 4];
 #pragma unroll
-        for (int kk = 0; kk < SB / 4; ++kk) {
-          const int q = 4 * kk + lk;
-          av[kk] = (row < N && q < kb) ? A[(int64_t)(k0 + q) * N + row] : 0.0;
-        }
+        for (int kk = 0; kk < SB / 4; ++kk) av[kk] = clamped_load(A, N, k0 + 4 * kk + lk, row);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int kk = 0; kk < SB / 4; ++kk)
+          if (!(row < N && 4 * kk + lk < kb)) av[kk] = 0.0;
 #pragma unroll
         for (int half = 0; half < SB / 16; ++half) {
           dbl4s acc = dbl4s{0.0, 0.0, 0.0, 0.0};
@@ -165,56 +260,31 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
       }
       __syncthreads();
       for (int i = r0 + tid; i < N; i += STHREADS) {  // z_i -= L_i y_k
+        double v[SB];
+#pragma unroll
+        for (int c = 0; c < SB; ++c) v[c] = clamped_load(A, N, k0 + c, i);
+        __builtin_amdgcn_sched_barrier(0);
         double zi = 0.0;
-        for (int c = 0; c < kb; ++c) zi += A[(int64_t)(k0 + c) * N + i] * sy[c];
+#pragma unroll
+        for (int c = 0; c < SB; ++c)
+          if (c < kb) zi += v[c] * sy[c];
         zv[i] -= zi;
       }
-      // (c) trailing update A_ij -= L_i L_j^T for k0 + kb <= j <= i, 16 x 16
-      //     tiles on MFMA (lane j + 16 (i % 4), element i / 4 of a tile); a
-      //     wave takes TU tiles at a time so that their loads are in flight
-      //     together (the workspace is in global memory: latency-bound)
-      const int m = (N - r0 + 15) / 16;
-      const int ntile = m * (m + 1) / 2;
-      for (int t0 = wave; t0 < ntile; t0 += SW * TU) {
-        int I[TU], J[TU];
-#pragma unroll
-        for (int u = 0; u < TU; ++u) {  // tile (I, J), J <= I, row-major over the lower triangle
-          const int t = t0 + u * SW;
-          int ii = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-          while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;  // exact after rounding
-          while (ii * (ii + 1) / 2 > t) --ii;
-          I[u] = t < ntile ? ii : m;  // past the end: a row of tiles beyond N (all masked)
-          J[u] = t < ntile ? t - ii * (ii + 1) / 2 : 0;
-        }
-        dbl4s acc[TU];
-        double av[TU][SB / 4], bv[TU][SB / 4];
-#pragma unroll
-        for (int u = 0; u < TU; ++u) {
-          const int rowA = r0 + I[u] * 16 + l16, rowB = r0 + J[u] * 16 + l16;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int gi = r0 + I[u] * 16 + 4 * e + lk, gj = r0 + J[u] * 16 + l16;
-            acc[u][e] = (gi < N && gj < N) ? A[(int64_t)gj * N + gi] : 0.0;
-          }
-#pragma unroll
-          for (int kk = 0; kk < SB / 4; ++kk) {
-            const int q = 4 * kk + lk;
-            av[u][kk] = (rowA < N && q < kb) ? -A[(int64_t)(k0 + q) * N + rowA] : 0.0;
-            bv[u][kk] = (rowB < N && q < kb) ? A[(int64_t)(k0 + q) * N + rowB] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < TU; ++u)
-#pragma unroll
-          for (int kk = 0; kk < SB / 4; ++kk)
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][kk], bv[u][kk], acc[u], 0, 0, 0);
-#pragma unroll
-        for (int u = 0; u < TU; ++u)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int gi = r0 + I[u] * 16 + 4 * e + lk, gj = r0 + J[u] * 16 + l16;
-            if (gi < N && gj < N) A[(int64_t)gj * N + gi] = acc[u][e];
-          }
+      // (c) trailing update A_ij -= L_i L_j^T for k0 + kb <= j <= i, one
+      //     32 x 32 block per wave at a time
+      const int m2 = (N - r0 + 31) / 32;
+      const int nblk = m2 * (m2 + 1) / 2;
+      for (int t = wave; t < nblk; t += SW) {  // block (I2, J2), J2 <= I2, row-major
+        int I2 = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((I2 + 1) * (I2 + 2) / 2 <= t) ++I2;  // exact after rounding
+        while (I2 * (I2 + 1) / 2 > t) --I2;
+        const int J2 = t - I2 * (I2 + 1) / 2;
+        const int iA = r0 + 32 * I2, jB = r0 + 32 * J2;
+        const bool diag = I2 == J2;  // its upper-right tile lies above the diagonal
+        if (kb == SB && iA + 32 <= N && jB + 32 <= N)
+          trail_block<false>(A, N, k0, kb, iA, jB, diag, l16, lk);
+        else
+          trail_block<true>(A, N, k0, kb, iA, jB, diag, l16, lk);
       }
       __syncthreads();
     }
