@@ -368,9 +368,12 @@ def loglik(x, y, z, thetas, opts=None, keep=False, stream=None):
     """Eq. (1) for one theta (6 numbers) or a batch (k x 6).  Returns a dict of
     numpy arrays {'loglik', 'logdet', 'quad', 'status'} and, with keep=True
     (single theta), the resident Factor as a second value."""
-    th = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+    # mvg_theta is six consecutive doubles: a C-contiguous k x 6 array has its layout
+    th = np.ascontiguousarray(np.atleast_2d(np.asarray(thetas, dtype=np.float64)))
+    if th.ndim != 2 or th.shape[1] != 6:
+        raise ValueError("theta needs 6 entries")
     k = th.shape[0]
-    arr = (Theta * k)(*[Theta.of(t) for t in th])
+    arr = th.ctypes.data_as(c_void_p)
     ll = np.zeros(k)
     ld = np.zeros(k)
     q = np.zeros(k)
