@@ -84,7 +84,8 @@ def run_variants(mvg, xs, ys, z, th, args, ref_loglik, reps=2):
             ("mixed_fp32", mvg.MVG_MIXED_FP32, FP32_MFMA_PEAK_TFLOPS, args.band),
             ("mixed_fp32_band%d" % args.wide_band, mvg.MVG_MIXED_FP32, FP32_MFMA_PEAK_TFLOPS,
              args.wide_band),
-            ("mixed_bf16", mvg.MVG_MIXED_BF16, BF16_MFMA_PEAK_TFLOPS, args.band)):
+            ("mixed_bf16", mvg.MVG_MIXED_BF16, BF16_MFMA_PEAK_TFLOPS, args.band),
+            ("mixed_fp32x", mvg.MVG_MIXED_FP32X, FP32_MFMA_PEAK_TFLOPS, args.band)):
         o = {"nb": args.nb, "precision": prec, "band_tiles": band}
         mvg.loglik(xs, ys, z, th, o)  # warm-up
         torch.cuda.synchronize()

@@ -55,12 +55,14 @@ enum {
     MVG_MIXED_FP32 = 1,  /* FP64 band tiles, FP32 off-band tiles, FP64 refinement   */
     MVG_MIXED_BF16 = 2,  /* FP64 band, off-band GEMMs on BF16 operands, FP32 accum. */
     MVG_TLR = 3,         /* tile low-rank, FP64 (Section 5.3)                       */
-    MVG_DST = 4          /* Diagonal Super Tile (Section 4.4, Experiment 2 of 6.4): */
+    MVG_DST = 4,         /* Diagonal Super Tile (Section 4.4, Experiment 2 of 6.4): */
                          /* exact FP64 with the tiles |I - J| >= band_tiles set to 0 */
+    MVG_MIXED_FP32X = 5  /* FP64 tiles and panel solves; off-band trailing GEMMs on  */
+                         /* FP32 MFMA (operands rounded to FP32), FP64 refinement   */
 };
 
 typedef struct {
-    int precision;      /* MVG_FP64 / MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_TLR        */
+    int precision;      /* MVG_FP64 / MVG_MIXED_* / MVG_TLR / MVG_DST                  */
     int nb;             /* tile size; dense and mixed: 128, 256, 512, 768 or 1024    */
                         /* (0 = 512; MVG_NB_AUTO: autotuned, see mvg_autotune_nb);     */
                         /* TLR: even, >= 64 (0 = 1200)                                 */
@@ -132,7 +134,8 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * (2 n_loc <= MVG_SMALL_MAX_ROWS, FP64, see loglik_many).  keep (nullable, n_theta == 1 only) receives a resident factor for
  * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*.
  *
- * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16; not in the paper): Sigma is
+ * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_MIXED_FP32X; not in
+ * the paper): Sigma is
  * generated once in FP64 and kept for the refinement; the factor has FP64
  * tiles within band_tiles of the diagonal (all diagonal factorisations FP64)
  * and FP32 tiles elsewhere, updated on FP32 (or BF16-operand) MFMA.  The solve
@@ -144,6 +147,12 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * first-order correction).  h_logdet is that of the mixed factor (not
  * refined).  Memory: the FP64 lower tiles plus the mixed copy.
  * Requires band_tiles >= 2.
+ * MVG_MIXED_FP32X (not in the paper) keeps every tile in FP64 and solves every
+ * panel in FP64; only the trailing updates of tiles band_tiles or more
+ * tile-diagonals off the diagonal take FP32 operands (rounded from the FP64
+ * panel) on FP32 MFMA, with 16-product stage sums added to the FP64 tile.
+ * The log-determinant then carries only the operand rounding; memory is that
+ * of two FP64 copies of Sigma.
  *
  * DST (MVG_DST): Eq. (1) of the Diagonal Super Tile matrix (Section 4.4),
  * Sigma with the tiles |I - J| >= band_tiles set to zero, in FP64; the

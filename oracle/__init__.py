@@ -326,11 +326,13 @@ def round_to(a, fmt: str) -> np.ndarray:
     raise ValueError(fmt)
 
 
-def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
+def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage: str = "fp32"):
     """Not in the paper.  Right-looking tiled Cholesky of S (padded with an
-    identity block to a multiple of nb) where tiles (I, J) with I - J >= band
-    are stored in FP32 and updated with operands rounded to ``fmt`` ("fp32" or
-    "bf16"), everything else in FP64:
+    identity block to a multiple of nb) where the trailing updates of tiles
+    (I, J) with I - J >= band take operands rounded to ``fmt`` ("fp32",
+    "bf16", or "fp64" for no rounding), everything else in FP64.
+
+    storage "fp32" (MVG_MIXED_FP32 / BF16): those tiles are stored in FP32:
 
     * off-band tiles start as S rounded to FP32;
     * diagonal tiles: FP64 Cholesky; W_k = L_kk^-1 (FP64);
@@ -339,6 +341,10 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
     * trailing tiles within the band: A_ij -= L_ik L_jk^T in FP64 (the FP32
       panel values upcast exactly); off the band:
       A_ij = round32(A_ij - op(L_ik) op(L_jk)^T), op = round to fmt.
+
+    storage "fp64" (MVG_MIXED_FP32X): every tile stays FP64 and every panel
+    tile is solved in FP64; only the off-band trailing products take rounded
+    operands: A_ij -= op(L_ik) op(L_jk)^T.
 
     Products are formed in FP64 and rounded once, so the result predicts the
     size of the mixed-precision error of an FP32-accumulating implementation,
@@ -356,13 +362,19 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
         return slice(I * nb, (I + 1) * nb), slice(J * nb, (J + 1) * nb)
 
     def op(a):
+        if fmt == "fp64":
+            return a
         return round_to(a, "fp32") if fmt == "fp32" else round_to(round_to(a, "fp32"), "bf16")
 
-    if fmt not in ("fp32", "bf16"):
+    if fmt not in ("fp32", "bf16", "fp64"):
         raise ValueError(fmt)
-    for J in range(T):
-        for I in range(J + band, T):
-            A[blk(I, J)] = round_to(A[blk(I, J)], "fp32")
+    if storage not in ("fp32", "fp64"):
+        raise ValueError(storage)
+    low = storage == "fp32"
+    if low:
+        for J in range(T):
+            for I in range(J + band, T):
+                A[blk(I, J)] = round_to(A[blk(I, J)], "fp32")
     for k in range(T):
         d = A[blk(k, k)]
         d = np.tril(d) + np.tril(d, -1).T
@@ -372,7 +384,7 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
         A[blk(k, k)] = Lkk
         W = np.linalg.solve(Lkk, np.eye(nb))
         for i in range(k + 1, T):
-            if i - k < band:
+            if i - k < band or not low:
                 A[blk(i, k)] = A[blk(i, k)] @ W.T
             else:
                 A[blk(i, k)] = round_to(A[blk(i, k)] @ round_to(W, "fp32").T, "fp32")
@@ -381,8 +393,10 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str):
                 Li, Lj = A[blk(i, k)], A[blk(j, k)]
                 if i - j < band:
                     A[blk(i, j)] = A[blk(i, j)] - Li @ Lj.T
-                else:
+                elif low:
                     A[blk(i, j)] = round_to(A[blk(i, j)] - op(Li) @ op(Lj).T, "fp32")
+                else:
+                    A[blk(i, j)] = A[blk(i, j)] - op(Li) @ op(Lj).T
     return np.tril(A), 0
 
 

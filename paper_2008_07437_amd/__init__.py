@@ -8,7 +8,7 @@ and the current stream) into those calls.  There is no CPU fallback: without
 the built library or a GPU every call raises.
 """
 from ._lib import (  # noqa: F401
-    MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR, MVG_DST,
+    MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR, MVG_DST, MVG_MIXED_FP32X,
     Opts, Theta, ThetaP, Mat, Factor, MvgError, cov_generate_p, loglik_p, profile_loglik_p,
     mle_fit, MleOpts,
     library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many, tlr_compress,

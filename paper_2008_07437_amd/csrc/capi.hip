@@ -192,10 +192,15 @@ using namespace mvg;
 
 // ------------------------------------------------------------ matrices
 
+static bool is_mixed(int precision) {
+  return precision == MVG_MIXED_FP32 || precision == MVG_MIXED_BF16 ||
+         precision == MVG_MIXED_FP32X;
+}
+
 static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   mvg_opts d{};
   if (o) d = *o;
-  if (d.precision < MVG_FP64 || d.precision > MVG_DST) return -1;
+  if (d.precision < MVG_FP64 || d.precision > MVG_MIXED_FP32X) return -1;
   if (d.nb == 0) d.nb = (d.precision == MVG_TLR) ? 1200 : 512;
   if (d.precision == MVG_TLR) {
     if (d.nb < 64 || d.nb % 2 || d.nb > QR_MAXM) return -2;
@@ -203,8 +208,7 @@ static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
     if (d.nb != 128 && d.nb != 256 && d.nb != 512 && d.nb != 768 && d.nb != 1024) return -2;
   }
   if (d.band_tiles <= 0) d.band_tiles = 2;
-  if ((d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16) && d.band_tiles < 2)
-    return -3;
+  if (is_mixed(d.precision) && d.band_tiles < 2) return -3;
   if (d.tlr_acc <= 0.0) d.tlr_acc = 1e-7;
   if (d.tlr_max_rank <= 0) d.tlr_max_rank = 300;
   if (d.tlr_max_rank > QR_MAXN - 16) return -4;
@@ -492,7 +496,7 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
   // matrix + inverse diagonal tiles + panel workspace + vectors
   b += sizeof(double) * (size_t)(2 * n_loc + 3 * Np + 4 * QN + 2 * Np * d.nb);
   b += (sizeof(int64_t) + sizeof(int)) * (size_t)T * (T + 1) / 2;
-  if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16) {
+  if (is_mixed(d.precision)) {
     mvg_opts f = d;
     f.precision = MVG_FP64;
     b += layout_bytes(n_loc, f);  // FP64 Sigma kept for the refinement
@@ -549,7 +553,7 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
     return MVG_ERR_ALLOC;
   }
   int rc = launch_fill_i64(d_info, INT64_MAX, 1, st);
-  const bool mixed = A->precision == MVG_MIXED_FP32 || A->precision == MVG_MIXED_BF16;
+  const bool mixed = is_mixed(A->precision);
   if (!rc)
     rc = A->precision == MVG_TLR ? tlr_potrf(A, A->opts, d_info, st)
                                  : mixed ? mixed_potrf(A, d_info, st) : dense_potrf(A, d_info, st);
@@ -936,8 +940,7 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int64_t, int, int>, int> g_tune;  // (n_loc, precision, band) -> nb
 
 static bool tunable(int precision) {
-  return precision == MVG_FP64 || precision == MVG_DST || precision == MVG_MIXED_FP32 ||
-         precision == MVG_MIXED_BF16;
+  return precision == MVG_FP64 || precision == MVG_DST || is_mixed(precision);
 }
 
 int mvg_autotune_nb(const double *d_x, const double *d_y, const double *d_z, int64_t n_loc,
@@ -1036,7 +1039,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
     for (int i = 0; i < n_theta; ++i) tasks.push_back(small_task(d_x, d_y, d_z, n_loc, th[i]));
     return run_small(tasks, n_loc, h_loglik, h_logdet, h_quad, h_status, st);
   }
-  if (d.precision == MVG_MIXED_FP32 || d.precision == MVG_MIXED_BF16)
+  if (is_mixed(d.precision))
     return loglik_mixed(d_x, d_y, d_z, n_loc, th, n_theta, d, h_loglik, h_logdet, h_quad,
                         h_status, keep, st);
   if (d.precision == MVG_TLR && n_theta > 1 && !keep)

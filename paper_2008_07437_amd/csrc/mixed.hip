@@ -13,9 +13,13 @@
 //   trailing update: band targets on FP64 MFMA, off-band targets on FP32 /
 //   BF16 MFMA;
 //   the look-ahead stream factors the next diagonal tile in FP64.
+// FP32X keeps every tile in FP64 and solves every panel in FP64; only the
+// off-band trailing GEMMs run on FP32 MFMA (operands rounded from the FP64
+// panel, 16-product stage sums added to the FP64 tile).
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "mvgeo_internal.h"
 
@@ -44,7 +48,9 @@ __device__ __forceinline__ int64_t lp_xcd_remap(int64_t bid, int64_t pad) {
   return (bid & 7) * per + (bid >> 3);
 }
 
-enum { LP_UPDATE = 0, LP_TRSM = 1 };
+// UPDATE: FP32 target tile; TRSM: off-band panel solve into an FP32 tile;
+// UPDATE64: FP64 target tile (FP32 operands, FP64 storage).
+enum { LP_UPDATE = 0, LP_TRSM = 1, LP_UPDATE64 = 2 };
 
 // Off-band target tiles of step k, enumerated column by column: (i, j) with
 // j > k and i >= j + band.
@@ -60,8 +66,9 @@ __device__ __forceinline__ void lp_offband(const TileMap &M, int k, int band, in
 
 // ------------------------------------------------------------ FP32 GEMM
 //
-// 128 x 128 output block of an FP32 tile; 4 waves in a 2 x 2 grid of 64 x 64.
-// UPDATE: C -= A B^T with A, B the staged FP32 panel; TRSM: C = A W^T with A
+// 128 x 128 output block of a tile; 4 waves in a 2 x 2 grid of 64 x 64.
+// UPDATE (FP32 tile) and UPDATE64 (FP64 tile): C -= A B^T with A, B the
+// staged FP32 panel; TRSM: C = A W^T with A
 // the pre-TRSM copy of the tile and W = W_k in FP32 (lower triangular, only
 // the first (sc+1)*128 columns of K contribute).  Accumulator layout of
 // v_mfma_f32_16x16x4_f32: lane l, element e <-> D[4(l/16) + e][l%16].
@@ -78,21 +85,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int s = NB / LB, ss = s * s;
   const int64_t q = lid / ss;
   const int sub = (int)(lid % ss), sr = sub % s, sc = sub / s;
+  typedef typename std::conditional<MODE == LP_UPDATE64, double, float>::type CT;
+  constexpr bool upd = MODE != LP_TRSM;
   const float *A, *B;
-  float *C;
+  CT *C;
   int nk;
-  if (MODE == LP_UPDATE) {
+  if (upd) {
     int i, j;
     lp_offband(M, k, band, q, i, j);
     A = P32 + (int64_t)(i - k - 1) * NB * NB + sr * LB;
     B = P32 + (int64_t)(j - k - 1) * NB * NB + sc * LB;
-    C = reinterpret_cast<float *>(tile_bytes(M, i, j)) + (int64_t)sc * LB * NB + sr * LB;
+    C = reinterpret_cast<CT *>(tile_bytes(M, i, j)) + (int64_t)sc * LB * NB + sr * LB;
     nk = NB / LK32;
   } else {
     const int i = k + band + (int)q;
     A = P32 + (int64_t)(i - k - 1) * NB * NB + sr * LB;
     B = W32 + sc * LB;
-    C = reinterpret_cast<float *>(tile_bytes(M, i, k)) + (int64_t)sc * LB * NB + sr * LB;
+    C = reinterpret_cast<CT *>(tile_bytes(M, i, k)) + (int64_t)sc * LB * NB + sr * LB;
     nk = (sc + 1) * (LB / LK32);
   }
   const int tid = threadIdx.x, lane = tid & 63;
@@ -125,7 +134,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) {
-      if (MODE == LP_UPDATE) {
+      if (MODE == LP_UPDATE64) {
+        acc[ti][tj] = *reinterpret_cast<const dbl4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16);
+      } else if (MODE == LP_UPDATE) {
         const flt4 c = *reinterpret_cast<const flt4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16);
         acc[ti][tj] = dbl4{(double)c[0], (double)c[1], (double)c[2], (double)c[3]};
       } else {
@@ -151,7 +162,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       float af0[4], bf0[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        af0[t] = (MODE == LP_UPDATE) ? -a[lk * LB + t * 16] : a[lk * LB + t * 16];
+        af0[t] = upd ? -a[lk * LB + t * 16] : a[lk * LB + t * 16];
         bf0[t] = bb[lk * LB + t * 16];
       }
       LP_ISSUE(p < nk ? p : nk - 1, (u + LS - 1) % LS);
@@ -167,8 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           af[t] = ks == 0 ? af0[t]
-                          : ((MODE == LP_UPDATE) ? -a[(ks + lk) * LB + t * 16]
-                                                 : a[(ks + lk) * LB + t * 16]);
+                          : (upd ? -a[(ks + lk) * LB + t * 16] : a[(ks + lk) * LB + t * 16]);
           bf[t] = ks == 0 ? bf0[t] : bb[(ks + lk) * LB + t * 16];
         }
 #pragma unroll
@@ -190,8 +200,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) {
       const dbl4 v = acc[ti][tj];
-      *reinterpret_cast<flt4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16) =
-          flt4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+      if (MODE == LP_UPDATE64)
+        *reinterpret_cast<dbl4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16) = v;
+      else
+        *reinterpret_cast<flt4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16) =
+            flt4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
     }
   lp_wait_vmcnt_0();
 #undef LP_ISSUE
@@ -370,11 +383,14 @@ __global__ __launch_bounds__(256) void k_panel_stage_post(TileMap M, int k, doub
 
 template <int NB>
 static int launch_lowp_update(const TileMap &M, int k, int band, int64_t nwg, const float *P32,
-                              const uint16_t *P16, bool bf16, hipStream_t st) {
+                              const uint16_t *P16, bool bf16, bool c64, hipStream_t st) {
   const int64_t pad = (nwg + 7) / 8 * 8;
   if (bf16)
     hipLaunchKernelGGL(k_lowp_bf16<NB>, dim3((unsigned)pad), dim3(256), 0, st, M, k, band, nwg, pad,
                        P16);
+  else if (c64)
+    hipLaunchKernelGGL((k_lowp_f32<NB, LP_UPDATE64>), dim3((unsigned)pad), dim3(256), 0, st, M, k,
+                       band, nwg, pad, P32, (const float *)nullptr);
   else
     hipLaunchKernelGGL((k_lowp_f32<NB, LP_UPDATE>), dim3((unsigned)pad), dim3(256), 0, st, M, k,
                        band, nwg, pad, P32, (const float *)nullptr);
@@ -391,13 +407,13 @@ static int launch_lowp_trsm(const TileMap &M, int k, int band, int64_t nwg, cons
 }
 
 static int lowp_update(const TileMap &M, int k, int band, int64_t nwg, const float *P32,
-                       const uint16_t *P16, bool bf16, hipStream_t st) {
+                       const uint16_t *P16, bool bf16, bool c64, hipStream_t st) {
   switch (M.nb) {
-    case 128: return launch_lowp_update<128>(M, k, band, nwg, P32, P16, bf16, st);
-    case 256: return launch_lowp_update<256>(M, k, band, nwg, P32, P16, bf16, st);
-    case 512: return launch_lowp_update<512>(M, k, band, nwg, P32, P16, bf16, st);
-    case 768: return launch_lowp_update<768>(M, k, band, nwg, P32, P16, bf16, st);
-    case 1024: return launch_lowp_update<1024>(M, k, band, nwg, P32, P16, bf16, st);
+    case 128: return launch_lowp_update<128>(M, k, band, nwg, P32, P16, bf16, c64, st);
+    case 256: return launch_lowp_update<256>(M, k, band, nwg, P32, P16, bf16, c64, st);
+    case 512: return launch_lowp_update<512>(M, k, band, nwg, P32, P16, bf16, c64, st);
+    case 768: return launch_lowp_update<768>(M, k, band, nwg, P32, P16, bf16, c64, st);
+    case 1024: return launch_lowp_update<1024>(M, k, band, nwg, P32, P16, bf16, c64, st);
   }
   set_error("mixed precision: unsupported tile size %d", M.nb);
   return MVG_ERR_STATE;
@@ -437,6 +453,9 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   const TileMap M = A->map();
   const int T = M.T, nb = M.nb, band = A->band;
   const bool bf16 = A->precision == MVG_MIXED_BF16;
+  // FP32X: every tile FP64 and every panel solved in FP64; only the off-band
+  // trailing GEMMs take FP32 operands (FP32 MFMA, FP64 target tiles)
+  const bool x64 = A->precision == MVG_MIXED_FP32X;
   const int s = nb / LB;
   const int64_t ss = (int64_t)s * s;
   const int64_t per = (int64_t)nb * nb;
@@ -468,8 +487,8 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
     hipStreamWaitEvent(st, evD, 0);
     const int nbelow = T - k - 1;
     if (nbelow > 0) {
-      const int nband = std::min(band - 1, nbelow);      // FP64 panel tiles
-      const int noff = nbelow - nband;                   // FP32 panel tiles
+      const int nband = x64 ? nbelow : std::min(band - 1, nbelow);  // FP64 panel tiles
+      const int noff = nbelow - nband;                               // FP32 panel tiles
       hipLaunchKernelGGL(k_panel_stage_pre, dim3(64, nbelow), dim3(256), 0, st, M, k, P64, P32);
       rc = check_launch("panel_stage_pre");
       if (!rc && nband > 0)
@@ -506,7 +525,7 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
       for (int j = k + 1; j < T; ++j) noff_t += std::max(0, T - j - band);
       if (noff_t > 0) {
         int h = prof_begin(MVG_PROF_LOWP, st, flow, 0.0);
-        rc = lowp_update(M, k, band, noff_t * ss, P32, P16, bf16, st);
+        rc = lowp_update(M, k, band, noff_t * ss, P32, P16, bf16, x64, st);
         prof_end(h, st);
       }
     }

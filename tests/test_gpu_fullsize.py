@@ -10,8 +10,9 @@ one or through properties that hold at any size:
   log|Sigma| against 2 sum log L_jj from the gathered diagonal; the
   quadratic form against Z^T w; cokriging against c0^T w with the oracle's
   c0;
-* mixed FP32, n = 50,000 (100,000^2): relative delta loglik against the FP64
-  path and the refined solution's residual against the oracle's rows;
+* mixed FP32 and FP32X, n = 50,000 (100,000^2): relative delta loglik
+  against the FP64 path and the refined solution's residual against the
+  oracle's rows;
 * TLR, n = 100,000 (200,000^2), tile 1200, acc 1e-7: relative delta loglik
   against the FP64 path <= 1e-6;
 * batched, 1024 theta at n = 400: sampled tasks against the oracle.
@@ -158,12 +159,14 @@ def test_mixed_fullsize(lib, orc, nu1, nu2, beta, spd):
 
 
 def test_mixed_fullsize_model_data(lib, orc):
-    """Mixed FP32 on Z = L eps at n = 50,000.  The refined quadratic form
-    matches FP64; the log-determinant of the mixed factor carries the FP32
-    rounding of the Schur complements, biased low and growing with n: at this
-    size FP32 off the band misses |delta loglik| <= 1e-6 for every band width
-    (a wider band only narrows the miss).  The bound asserted is the measured
-    size of that miss with margin, so that a regression shows."""
+    """Mixed precision on Z = L eps at n = 50,000.  MVG_MIXED_FP32: the refined
+    quadratic form matches FP64; the log-determinant of the mixed factor
+    carries the FP32 rounding of the stored Schur complements and of the
+    off-band panel solves, biased low and growing with n: at this size it
+    misses |delta loglik| <= 1e-6 for every band width (a wider band only
+    narrows the miss; the bound asserted is the measured miss with margin,
+    so that a regression shows).  MVG_MIXED_FP32X (FP64 tiles and panel
+    solves, FP32 operands in the off-band GEMMs) meets 1e-6."""
     n = 50000
     x, y = _sites(orc, n, 1)
     z = _model_z(lib, x, y, TH, 1)
@@ -179,6 +182,11 @@ def test_mixed_fullsize_model_data(lib, orc):
         assert r["status"][0] == 0
         assert dq <= 1e-9
         assert dl <= 1e-4
+    r = lib.loglik(_dev(x), _dev(y), z, TH, {"nb": 1024, "precision": lib.MVG_MIXED_FP32X})
+    dl = abs(r["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
+    _say("  model Z, FP32X band 2: status %d rel dloglik %.2e (dlogdet %.3e)"
+         % (r["status"][0], dl, r["logdet"][0] - d64["logdet"][0]))
+    assert r["status"][0] == 0 and dl <= 1e-6
 
 
 def test_tlr_fullsize(lib, orc):

@@ -51,14 +51,14 @@ def _data(orc, n, seed, theta):
 _CASES = {}
 
 
-def _case(orc, n, seed, th, nb, band, fmt):
+def _case(orc, n, seed, th, nb, band, fmt, storage="fp32"):
     """Oracle loglik and the emulated mixed log-determinant (cached per module)."""
-    key = (n, seed, tuple(th), nb, band, fmt)
+    key = (n, seed, tuple(th), nb, band, fmt, storage)
     if key not in _CASES:
         x, y, z = _data(orc, n, seed, th)
         ref = orc.loglik(x, y, z, th)
         S = orc.cov_dense(x, y, th)
-        L, info = orc.mixed_cholesky_emulated(S, nb, band, fmt)
+        L, info = orc.mixed_cholesky_emulated(S, nb, band, fmt, storage)
         eld = 2.0 * float(np.sum(np.log(np.diag(L)[:2 * n]))) if info == 0 else float("nan")
         _CASES[key] = (x, y, z, ref, eld, info)
     return _CASES[key]
@@ -70,7 +70,7 @@ def test_mixed_full_band_matches_fp64(lib, orc):
     x, y, z = _data(orc, 700, 4, th)
     _say("mixed full band n=700 nb=128")
     d64 = lib.loglik(_dev(x), _dev(y), _dev(z), th, {"nb": 128})
-    for prec in (lib.MVG_MIXED_FP32, lib.MVG_MIXED_BF16):
+    for prec in (lib.MVG_MIXED_FP32, lib.MVG_MIXED_BF16, lib.MVG_MIXED_FP32X):
         got = lib.loglik(_dev(x), _dev(y), _dev(z), th,
                          {"nb": 128, "precision": prec, "band_tiles": 64})
         assert got["status"][0] == 0
@@ -99,6 +99,37 @@ def test_mixed_fp32_loglik(lib, orc, a, nb):
     assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
     if a <= 0.1:  # at a = 0.3 kappa * 2^-24 nears 1e-1: both errors are noise-dominated
         assert abs(dld) <= max(3.0 * abs(eld - ref["logdet"]), 1e-10 * abs(ref["logdet"]))
+    assert dl <= 1e-6
+
+
+@pytest.mark.parametrize("nb", [128, 256])
+@pytest.mark.parametrize("a", [0.03, 0.1, 0.3])
+def test_mixed_fp32x_loglik(lib, orc, a, nb):
+    """FP64 tiles and panel solves, FP32 operands in the off-band trailing
+    GEMMs: the log-determinant error against the oracle's emulation with FP64
+    storage.  The emulation forms the products of FP32-rounded operands
+    exactly; the GPU also rounds each 16-product stage sum to FP32, an error
+    of the same order per product as the operand rounding but not in the
+    emulation, so the bound is 50x the emulated size or 2e-9 relative
+    (measured up to ~25x at a = 0.1).  At a = 0.3 both are noise-dominated
+    (kappa 2^-24 nears 1e-1) and only the likelihood is held."""
+    th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
+    n = 1000
+    x, y, z, ref, eld, einfo = _case(orc, n, 1, th, nb, 2, "fp32", "fp64")
+    _say("mixed fp32x n=%d nb=%d a=%g" % (n, nb, a))
+    got = lib.loglik(_dev(x), _dev(y), _dev(z), th,
+                     {"nb": nb, "precision": lib.MVG_MIXED_FP32X})
+    assert einfo == 0 and got["status"][0] == 0
+    st = lib.mvg_ir_stats(0)
+    dl = abs(got["loglik"][0] - ref["loglik"]) / abs(ref["loglik"])
+    dld = got["logdet"][0] - ref["logdet"]
+    _say("  rel dloglik %.2e  dlogdet %.3e (emulated %.3e)  IR %s"
+         % (dl, dld, eld - ref["logdet"], st))
+    assert st["converged"], st
+    assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
+    if a <= 0.1:
+        assert abs(dld) <= max(50.0 * abs(eld - ref["logdet"]), 2e-9 * abs(ref["logdet"]))
+        assert dl <= 1e-7
     assert dl <= 1e-6
 
 

@@ -382,6 +382,40 @@ def test_mixed_emulation_rounds_off_band_and_stays_close(orc, fmt, bound):
     assert abs(ld - np.linalg.slogdet(S)[1]) <= 50 * bound * 180
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_mixed_emulation_without_rounding_is_exact_cholesky(orc, storage):
+    """No operand rounding and FP64 storage: the tiled steps reduce to
+    LAPACK's factor; with FP32 storage only the stored off-band tiles differ,
+    by FP32 rounding."""
+    S = _small_cov(orc, 90, 0.1)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 2, "fp64", storage)
+    assert info == 0
+    ref = np.eye(L.shape[0])
+    ref[:180, :180] = scipy.linalg.cholesky(S, lower=True)
+    if storage == "fp64":
+        np.testing.assert_allclose(L, ref, atol=1e-12)
+    else:
+        assert np.max(np.abs(L - ref)) <= 1e-5 and np.max(np.abs(L - ref)) > 0.0
+
+
+def test_mixed_emulation_fp64_storage_rounds_only_the_products(orc):
+    """FP64 storage with FP32 operands: the first block column is the exact
+    panel (no update has touched it), off-band tiles are not FP32 values, and
+    the factor reproduces S far closer than with FP32 storage."""
+    S = _small_cov(orc, 90, 0.03)
+    nb = 32
+    L, info = orc.mixed_cholesky_emulated(S, nb, 2, "fp32", "fp64")
+    L32, info32 = orc.mixed_cholesky_emulated(S, nb, 2, "fp32", "fp32")
+    assert info == 0 and info32 == 0
+    ref = scipy.linalg.cholesky(S, lower=True)
+    np.testing.assert_allclose(L[:180, :nb], ref[:, :nb], atol=1e-12)
+    t = L[3 * nb:4 * nb, 0:nb]
+    assert not np.array_equal(orc.round_to(t, "fp32"), t)
+    e64 = np.max(np.abs((L @ L.T)[:180, :180] - S))
+    e32 = np.max(np.abs((L32 @ L32.T)[:180, :180] - S))
+    assert 0.0 < e64 < e32
+
+
 def test_tlr_frobenius_rule_keeps_more_and_bounds_tail(orc):
     th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
     x, y = synthetic.jittered_grid(150, 4)
