@@ -79,6 +79,26 @@ def test_footprint_host_logic():
     assert fp(1000, nb=128, precision=1, band_tiles=1) == 0
     assert fp(1000, nb=1200, precision=3, tlr_max_rank=600) == 0
     assert fp(0, nb=512) == 0
+    # FP32X: every tile FP64 plus the FP64 Sigma: about twice the dense size,
+    # more than FP32 storage; a band below 2 is refused as for the other modes
+    fx = fp(25600, nb=512, precision=5)
+    assert fx > fp(25600, nb=512, precision=1) and 1.9 * dense[2] < fx < 2.3 * dense[2]
+    assert fp(1000, nb=128, precision=5, band_tiles=1) == 0
+    assert fp(1000, nb=128, precision=6) == 0         # no such precision
+
+
+def test_theta_batch_marshalling_rejects_bad_shapes():
+    """loglik hands a batch of theta to the library as one k x 6 FP64 array
+    (the layout of mvg_theta); other shapes are refused before any device
+    or library call."""
+    import ctypes as C
+    import paper_2008_07437_amd as mvg
+    assert C.sizeof(mvg.Theta) == 6 * 8
+    assert [f[0] for f in mvg.Theta._fields_] == ["sigma11_sq", "sigma22_sq", "a", "nu11",
+                                                  "nu22", "beta"]
+    for bad in ([(1.0, 1.0, 0.1)], [[1.0] * 7], np.ones((2, 3, 6))):
+        with pytest.raises(ValueError):
+            mvg.loglik(None, None, None, bad)
 
 
 @pytest.mark.skipif(not os.path.exists(SO), reason="library not built")
