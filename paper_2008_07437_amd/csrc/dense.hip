@@ -401,59 +401,70 @@ __global__ __launch_bounds__(256) void k_potrf64(TileMap M, int k, int b, double
   bool failed = false;
   // global row of the block's first row; local rows >= lreal are padding
   const int64_t g0 = gbase + (int64_t)b * PB;
-  for (int j = 0; j < PB; ++j) {
-    const int buf = j & 1, jq = j >> 4, jr = j & 15;
-    if (tx == jr) {
+  // pivot tolerance of row g is tol[g % p]: a counter started at g0 % p and
+  // wrapped at p (no division per column)
+  int m = (int)(g0 % pt.p);
+  // columns j = 16 jq + jr: jq is a compile-time index into the register
+  // blocks a[.][jq], x[jq][.] (no indirect register addressing)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) scol[buf][ty + 16 * i] = a[i][jq];
-    }
-    if (ty == jr) {
+  for (int jq = 0; jq < 4; ++jq) {
+#pragma unroll 1
+    for (int jr = 0; jr < 16; ++jr) {
+      const int j = 16 * jq + jr;
+      const int buf = j & 1;
+      if (tx == jr) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) srow[buf][tx + 16 * jj] = x[jq][jj];
-    }
-    __syncthreads();
-    const double d = scol[buf][j];
-    if (tid == 0 && !failed) {
-      const int64_t g = g0 + j;
-      const bool pad = g >= N || b * PB + j >= lreal;
-      const double tol = pad ? 0x1p-40 : pt.tol[g % pt.p];
-      if (!(d > tol) || !(d > 0.0)) {
-        failed = true;
-        atomicMin((unsigned long long *)d_info, (unsigned long long)(g + 1));
+        for (int i = 0; i < 4; ++i) scol[buf][ty + 16 * i] = a[i][jq];
       }
-    }
-    const double ljj = sqrt(d);
-    const double rinv = 1.0 / ljj;
-    double lr[4], lc[4], xr[4];
+      if (ty == jr) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ty + 16 * i;
-      lr[i] = (r > j) ? scol[buf][r] * rinv : 0.0;
-    }
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int c = tx + 16 * jj;
-      lc[jj] = (c > j) ? scol[buf][c] * rinv : 0.0;
-      xr[jj] = srow[buf][c] * rinv;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        a[i][jj] -= lr[i] * lc[jj];
-        x[i][jj] -= lr[i] * xr[jj];
+        for (int jj = 0; jj < 4; ++jj) srow[buf][tx + 16 * jj] = x[jq][jj];
       }
-    if (tx == jr) {
+      __syncthreads();
+      const double d = scol[buf][j];
+      if (tid == 0 && !failed) {
+        const int64_t g = g0 + j;
+        const bool pad = g >= N || b * PB + j >= lreal;
+        const double tol = pad ? 0x1p-40 : pt.tol[m];
+        if (!(d > tol) || !(d > 0.0)) {
+          failed = true;
+          atomicMin((unsigned long long *)d_info, (unsigned long long)(g + 1));
+        }
+      }
+      m = (m + 1 == pt.p) ? 0 : m + 1;
+      const double ljj = sqrt(d);
+      const double rinv = 1.0 / ljj;
+      double lr[4], lc[4], xr[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = ty + 16 * i;
-        if (r == j) a[i][jq] = ljj;
-        else if (r > j) a[i][jq] = lr[i];
+        lr[i] = (r > j) ? scol[buf][r] * rinv : 0.0;
       }
-    }
-    if (ty == jr) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) x[jq][jj] = xr[jj];
+      for (int jj = 0; jj < 4; ++jj) {
+        const int c = tx + 16 * jj;
+        lc[jj] = (c > j) ? scol[buf][c] * rinv : 0.0;
+        xr[jj] = srow[buf][c] * rinv;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          a[i][jj] -= lr[i] * lc[jj];
+          x[i][jj] -= lr[i] * xr[jj];
+        }
+      if (tx == jr) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = ty + 16 * i;
+          if (r == j) a[i][jq] = ljj;
+          else if (r > j) a[i][jq] = lr[i];
+        }
+      }
+      if (ty == jr) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) x[jq][jj] = xr[jj];
+      }
     }
   }
   // inverse block (b, b) of W_k = L_kk^-1 (nb x nb, column-major, ld nb)
