@@ -546,13 +546,24 @@ __global__ __launch_bounds__(256) void k_trtri_step(TileMap M, int k, int d,
     }
     __syncthreads();
   };
+  // staging: every load of a 64 x 64 block is issued before the LDS stores
+  // (a load-store loop would wait for each value in turn)
+  constexpr int SQ = PB * PB / 256;
   for (int m = j; m < i; ++m) {
     const double *Lim = L + (int64_t)(m * PB) * nb + i * PB;  // rows i-block, cols m-block
     const double *Wmj = W + (int64_t)(j * PB) * nb + m * PB;  // rows m-block, cols j-block
-    for (int e = tid; e < PB * PB; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      sa[c * PB + r] = Lim[(int64_t)c * nb + r];  // sa[kk = c][r]
-      sb[r * PB + c] = Wmj[(int64_t)c * nb + r];  // sb[kk = r][c] = Wmj[r][c]
+    double va[SQ], vb[SQ];
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int e = tid + 256 * q, r = e & 63, c = e >> 6;
+      va[q] = Lim[(int64_t)c * nb + r];
+      vb[q] = Wmj[(int64_t)c * nb + r];
+    }
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int e = tid + 256 * q, r = e & 63, c = e >> 6;
+      sa[c * PB + r] = va[q];  // sa[kk = c][r]
+      sb[r * PB + c] = vb[q];  // sb[kk = r][c] = Wmj[r][c]
     }
     mma();
   }
@@ -569,9 +580,18 @@ __global__ __launch_bounds__(256) void k_trtri_step(TileMap M, int k, int d,
         acc[ti][tj][e] = 0.0;
       }
   const double *Wii = W + (int64_t)(i * PB) * nb + i * PB;
-  for (int e = tid; e < PB * PB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    sa[c * PB + r] = Wii[(int64_t)c * nb + r];
+  {
+    double va[SQ];
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int e = tid + 256 * q;
+      va[q] = Wii[(int64_t)(e >> 6) * nb + (e & 63)];
+    }
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      const int e = tid + 256 * q;
+      sa[(e >> 6) * PB + (e & 63)] = va[q];
+    }
   }
   mma();
   double *Wij = W + (int64_t)(j * PB) * nb + i * PB;
