@@ -375,17 +375,24 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
   for (int k = 0; k < NC; ++k)
 #pragma unroll
     for (int q = 0; q < QB; ++q) y[k][q] = 0.0;
+  // the lane's rows of the columns, loaded from clamped indices (inside the
+  // m x n matrix) all at once and zeroed where masked after a scheduling
+  // barrier (a load under a branch waits for its value before the next);
+  // kept for the final update, which therefore reads A only here
+  double x[NC][QE];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = min(c0 + k * BWV, n - 1);
+#pragma unroll
+    for (int e = 0; e < QE; ++e) x[k][e] = A[(int64_t)c * lda + min(p0 + lane + 64 * e, m - 1)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+#pragma unroll
+    for (int e = 0; e < QE; ++e)
+      if (!(c0 + k * BWV < n && p0 + lane + 64 * e < m)) x[k][e] = 0.0;
   {
-    double x[NC][QE];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int c = c0 + k * BWV;
-#pragma unroll
-      for (int e = 0; e < QE; ++e) {
-        const int r = lane + 64 * e, i = p0 + r;
-        x[k][e] = (c < n && i < m) ? A[(int64_t)c * lda + i] : 0.0;
-      }
-    }
 #pragma unroll
     for (int e = 0; e < QE; ++e) {
       const int r = lane + 64 * e;
@@ -433,7 +440,7 @@ __device__ __forceinline__ void apply_block(double *A, int lda, int c0, int n, i
         double d = 0.0;
 #pragma unroll
         for (int q = 0; q < QB; ++q) d += V[q][r] * y[k][q];
-        col[i] -= d;
+        col[i] = x[k][e] - d;  // x holds col[i]: only this wave writes column c
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -488,11 +495,25 @@ __global__ __launch_bounds__(64 * BWV) void k_qr_blocked(const QrTask *__restric
       const int c = j + 1 + wave;
       if (tau != 0.0 && c < p0 + bw) {
         double *ac = A + (int64_t)c * lda;
+        // rows j + lane + 64 e (< m; 64 QE >= m): loaded at once from clamped
+        // rows, used in the same order as a row-by-row loop
+        double av[QE];
+#pragma unroll
+        for (int e = 0; e < QE; ++e) av[e] = ac[min(j + lane + 64 * e, m - 1)];
+        __builtin_amdgcn_sched_barrier(0);
         double w = 0.0;
-        for (int i = j + lane; i < m; i += 64) w += V[jj][i - p0] * ac[i];
+#pragma unroll
+        for (int e = 0; e < QE; ++e) {
+          const int i = j + lane + 64 * e;
+          if (i < m) w += V[jj][i - p0] * av[e];
+        }
         for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
         const double tw = tau * w;
-        for (int i = j + lane; i < m; i += 64) ac[i] -= tw * V[jj][i - p0];
+#pragma unroll
+        for (int e = 0; e < QE; ++e) {
+          const int i = j + lane + 64 * e;
+          if (i < m) ac[i] = av[e] - tw * V[jj][i - p0];  // only this wave writes column c
+        }
       }
       __syncthreads();
     }
