@@ -153,33 +153,38 @@ constexpr int QW = 8;  // waves per QR workgroup
 template <int QE, int NC>
 __device__ __forceinline__ void reflect_cols(double *A, int lda, int c0, int n, const double *v,
                                              int j, int m, double tau, int lane, double *nrm) {
-  // pass 1: inner products (all loads of the NC columns issued together)
+  // pass 1: inner products.  All loads of the NC columns are issued together
+  // from clamped indices (inside the m x n matrix) and zeroed where masked
+  // after a scheduling barrier (a load under a branch waits for its value
+  // before the next); the values serve pass 2 as well.
   double w[NC];
-  {
-    double x[NC][QE];
+  double x[NC][QE];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int c = c0 + k * QW;
+  for (int k = 0; k < NC; ++k) {
+    const int c = min(c0 + k * QW, n - 1);
 #pragma unroll
-      for (int e = 0; e < QE; ++e) {
-        const int i = j + lane + 64 * e;
-        x[k][e] = (c < n && i < m) ? A[(int64_t)c * lda + i] : 0.0;
-      }
-    }
+    for (int e = 0; e < QE; ++e) x[k][e] = A[(int64_t)c * lda + min(j + lane + 64 * e, m - 1)];
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      w[k] = 0.0;
+  for (int k = 0; k < NC; ++k)
 #pragma unroll
-      for (int e = 0; e < QE; ++e) {
-        const int i = j + lane + 64 * e;
-        if (i < m) w[k] += v[i] * x[k][e];
-      }
+    for (int e = 0; e < QE; ++e)
+      if (!(c0 + k * QW < n && j + lane + 64 * e < m)) x[k][e] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    w[k] = 0.0;
+#pragma unroll
+    for (int e = 0; e < QE; ++e) {
+      const int i = j + lane + 64 * e;
+      if (i < m) w[k] += v[i] * x[k][e];
     }
   }
   for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
     for (int k = 0; k < NC; ++k) w[k] += __shfl_xor(w[k], o);
-  // pass 2: update (the columns are re-read from the cache)
+  // pass 2: update from the values of pass 1 (only this wave writes the
+  // columns c0 + k QW)
   double ss[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -192,7 +197,7 @@ __device__ __forceinline__ void reflect_cols(double *A, int lda, int c0, int n, 
       for (int e = 0; e < QE; ++e) {
         const int i = j + lane + 64 * e;
         if (i < m) {
-          const double y = col[i] - tw * v[i];
+          const double y = x[k][e] - tw * v[i];
           col[i] = y;
           if (i > j) ss[k] += y * y;
         }
