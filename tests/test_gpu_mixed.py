@@ -153,20 +153,24 @@ def test_mixed_bf16_loglik(lib, orc, a):
     assert dl <= 1e-4
 
 
-def test_mixed_ragged_and_wide_band(lib, orc):
+@pytest.mark.parametrize("mode", ["fp32", "fp32x"])
+def test_mixed_ragged_and_wide_band(lib, orc, mode):
     """Ragged last tile; bands of 2 and 3 tiles; smoother second variable and
     negative beta.  The condition number is ~4e7, so kappa 2^-24 > 1: FP32
     storage alone moves the log-determinant by ~1e-2 (emulated) and the
-    error is dominated by the few smallest eigenvalues; held to 1e-5."""
+    error is dominated by the few smallest eigenvalues; held to 1e-5 (FP32X,
+    FP64 storage, is held to the same bound)."""
     th = (1.5, 0.8, 0.15, 0.8, 1.7, -0.6)
     x, y, z = _data(orc, 1337, 21, th)
     ref = orc.loglik(x, y, z, th)
     S = orc.cov_dense(x, y, th)
+    prec = lib.MVG_MIXED_FP32 if mode == "fp32" else lib.MVG_MIXED_FP32X
+    storage = "fp32" if mode == "fp32" else "fp64"
     for band in (2, 3):
-        L, info = orc.mixed_cholesky_emulated(S, 256, band, "fp32")
+        L, info = orc.mixed_cholesky_emulated(S, 256, band, "fp32", storage)
         eld = 2.0 * float(np.sum(np.log(np.diag(L)[:2 * 1337])))
         got = lib.loglik(_dev(x), _dev(y), _dev(z), th,
-                         {"nb": 256, "precision": lib.MVG_MIXED_FP32, "band_tiles": band})
+                         {"nb": 256, "precision": prec, "band_tiles": band})
         dl = abs(got["loglik"][0] - ref["loglik"]) / abs(ref["loglik"])
         dld = got["logdet"][0] - ref["logdet"]
         _say("  band %d rel dloglik %.2e dlogdet %.3e (emulated %.3e)"
