@@ -34,7 +34,10 @@ Each function states the passage of the paper it follows:
 * ``mixed_cholesky_emulated`` -- not in the paper: the mixed-precision tiled
   factorisation (FP64 band, FP32 / BF16 off the band) emulated in FP64 with
   rounding at the operand points, to predict the size of its error (not its
-  bits).  Parity unpinned beyond the reductions its tests check.
+  bits).  Pinned by the defining equations of its rounding points: band
+  blocks reproduce S to FP64 rounding, off-band blocks deviate at the
+  operand precision's scale, FP64-storage panel tiles solve their Schur
+  complement in FP64 (``tests/test_oracle.py``).
 """
 from __future__ import annotations
 
@@ -326,7 +329,8 @@ def round_to(a, fmt: str) -> np.ndarray:
     raise ValueError(fmt)
 
 
-def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage: str = "fp32"):
+def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage: str = "fp32",
+                            _plant: str = ""):
     """Not in the paper.  Right-looking tiled Cholesky of S (padded with an
     identity block to a multiple of nb) where the trailing updates of tiles
     (I, J) with I - J >= band take operands rounded to ``fmt`` ("fp32",
@@ -349,7 +353,12 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
     Products are formed in FP64 and rounded once, so the result predicts the
     size of the mixed-precision error of an FP32-accumulating implementation,
     not its bits.  Returns (L padded, info) with info the 1-based index of the
-    first non-positive pivot (0 if none)."""
+    first non-positive pivot (0 if none).
+
+    ``_plant`` exists only for the tests that check the pins of this function
+    can fail: "band_operands" rounds the operands of band-target updates too,
+    "w32" solves off-band panel tiles against round32(W_k) in FP64 storage.
+    Both are mistakes; the default "" is the definition above."""
     S = _f64(S)
     N = S.shape[0]
     T = (N + nb - 1) // nb
@@ -370,6 +379,8 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
         raise ValueError(fmt)
     if storage not in ("fp32", "fp64"):
         raise ValueError(storage)
+    if _plant not in ("", "band_operands", "w32"):
+        raise ValueError(_plant)
     low = storage == "fp32"
     if low:
         for J in range(T):
@@ -384,14 +395,18 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
         A[blk(k, k)] = Lkk
         W = np.linalg.solve(Lkk, np.eye(nb))
         for i in range(k + 1, T):
-            if i - k < band or not low:
+            if _plant == "w32" and not low and i - k >= band:
+                A[blk(i, k)] = A[blk(i, k)] @ round_to(W, "fp32").T
+            elif i - k < band or not low:
                 A[blk(i, k)] = A[blk(i, k)] @ W.T
             else:
                 A[blk(i, k)] = round_to(A[blk(i, k)] @ round_to(W, "fp32").T, "fp32")
         for j in range(k + 1, T):
             for i in range(j, T):
                 Li, Lj = A[blk(i, k)], A[blk(j, k)]
-                if i - j < band:
+                if i - j < band and _plant == "band_operands":
+                    A[blk(i, j)] = A[blk(i, j)] - op(Li) @ op(Lj).T
+                elif i - j < band:
                     A[blk(i, j)] = A[blk(i, j)] - Li @ Lj.T
                 elif low:
                     A[blk(i, j)] = round_to(A[blk(i, j)] - op(Li) @ op(Lj).T, "fp32")

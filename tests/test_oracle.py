@@ -416,6 +416,105 @@ def test_mixed_emulation_fp64_storage_rounds_only_the_products(orc):
     assert 0.0 < e64 < e32
 
 
+def _mixed_pin_violations(orc, S, L, nb, band, fmt, storage):
+    """Checks the emulated mixed factor against the defining equations of its
+    rounding points (not against its own loop):
+
+    * band blocks (I - J < band): S_IJ = sum_{k <= J} L_Ik L_Jk^T to FP64
+      rounding (updates into band tiles take the stored values exactly, the
+      diagonal tile and its panel solve are FP64): relative residual
+      <= 8 u kappa(L_JJ);
+    * off-band blocks: the same residual is at FP32 scale, neither FP64
+      rounding (a missing rounding) nor beyond 2e-2 (bf16) / 1e-6 (fp32);
+      with FP32 storage relative to the block, with FP64 storage relative to
+      the products of the updates it received (J >= 1), where the rounding
+      sits;
+    * FP64 storage: every off-band panel tile solves its Schur complement in
+      FP64, L_IJ L_JJ^T = S_IJ - sum_{k < J} op(L_Ik) op(L_Jk)^T with op the
+      operand rounding, to 8 u kappa(L_JJ).
+    Returns the list of violated pins (empty when all hold)."""
+    u = 2.0 ** -53
+    N = S.shape[0]
+    Np = L.shape[0]
+    T = Np // nb
+    Sp = np.eye(Np)
+    Sp[:N, :N] = S
+
+    def B(I, J):
+        return slice(I * nb, (I + 1) * nb), slice(J * nb, (J + 1) * nb)
+
+    def op(a):
+        f = orc.round_to(a, "fp32")
+        return f if fmt == "fp32" else orc.round_to(f, "bf16")
+
+    top = 1e-6 if fmt == "fp32" else 2e-2   # u = 2^-24 and 2^-8 per operand
+    bad = []
+    for J in range(T):
+        kap = np.linalg.cond(L[B(J, J)])
+        for I in range(J, T):
+            full = sum(L[B(I, k)] @ L[B(J, k)].T for k in range(J + 1))
+            ab = sum(np.abs(L[B(I, k)]) @ np.abs(L[B(J, k)]).T for k in range(J + 1))
+            scale = np.max(np.abs(Sp[B(I, J)])) + np.max(ab)
+            rel = np.max(np.abs(Sp[B(I, J)] - full)) / scale
+            if I - J < band:
+                if rel > 8 * u * kap:
+                    bad.append(("band", I, J, rel))
+            elif storage == "fp32":
+                if not (1e-11 < rel <= top):
+                    bad.append(("offband-scale", I, J, rel))
+            elif J >= 1:   # FP64 storage: the rounding sits in the products alone
+                prod = np.max(sum(np.abs(L[B(I, k)]) @ np.abs(L[B(J, k)]).T for k in range(J)))
+                relp = np.max(np.abs(Sp[B(I, J)] - full)) / prod
+                if not (1e-11 < relp <= top):
+                    bad.append(("offband-scale", I, J, relp))
+            if storage == "fp64" and I - J >= band:
+                schur = Sp[B(I, J)] - sum((op(L[B(I, k)]) @ op(L[B(J, k)]).T for k in range(J)),
+                                          np.zeros((nb, nb)))
+                r3 = np.max(np.abs(schur - L[B(I, J)] @ L[B(J, J)].T)) / scale
+                if r3 > 8 * u * kap:
+                    bad.append(("panel-fp64", I, J, r3))
+    return bad
+
+
+@pytest.mark.parametrize("a", [0.03, 0.1])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+def test_mixed_emulation_satisfies_its_rounding_definition(orc, a, storage, fmt):
+    """Mixed precision is not in the paper: its definition is the placement of
+    the rounding points (FP64 band and FP64 diagonal factors; off-band products
+    on rounded operands; FP32 storage of off-band tiles or FP64 storage with
+    FP64 panel solves).  The emulated factor satisfies each defining equation
+    at the precision that definition gives it."""
+    S = _small_cov(orc, 90, a)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 2, fmt, storage)
+    assert info == 0
+    assert _mixed_pin_violations(orc, S, L, 32, 2, fmt, storage) == []
+
+
+@pytest.mark.parametrize("plant,storage,kind", [("band_operands", "fp32", "band"),
+                                                ("band_operands", "fp64", "band"),
+                                                ("w32", "fp64", "panel-fp64")])
+def test_mixed_emulation_pins_catch_misplaced_rounding(orc, plant, storage, kind):
+    """A rounding placed where the definition has none (operands of a band
+    update rounded; W_k rounded to FP32 in an FP64-storage panel solve) breaks
+    the pins above."""
+    S = _small_cov(orc, 90, 0.1)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 2, "fp32", storage, _plant=plant)
+    assert info == 0
+    bad = _mixed_pin_violations(orc, S, L, 32, 2, "fp32", storage)
+    assert any(b[0] == kind for b in bad), bad
+
+
+def test_mixed_emulation_pins_catch_missing_offband_rounding(orc):
+    """No rounding at all off the band (FP64 operands, FP64 storage) leaves the
+    off-band residuals at FP64 scale: the FP32-scale pin fails."""
+    S = _small_cov(orc, 90, 0.1)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 2, "fp64", "fp64")
+    assert info == 0
+    bad = _mixed_pin_violations(orc, S, L, 32, 2, "fp32", "fp64")
+    assert any(b[0] == "offband-scale" for b in bad), bad
+
+
 def test_tlr_frobenius_rule_keeps_more_and_bounds_tail(orc):
     th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
     x, y = synthetic.jittered_grid(150, 4)
