@@ -93,7 +93,8 @@ def test_cov_generate_gather_matches_dense(lib, orc):
 
 
 @pytest.mark.parametrize("n,nb,a", [(400, 128, 0.1), (400, 256, 0.03), (400, 256, 0.3),
-                                    (555, 256, 0.1), (1000, 512, 0.1)])
+                                    (555, 256, 0.1), (1000, 512, 0.1),
+                                    (1600, 768, 0.1), (1600, 1024, 0.3), (1600, 1024, 0.03)])
 def test_potrf_factor_matches_oracle(lib, orc, n, nb, a):
     _say("potrf n=%d nb=%d a=%g" % (n, nb, a))
     th = (1.0, 1.0, a, 0.5, 1.0, 0.5)

@@ -86,6 +86,50 @@ def _residual_rows(orc, x, y, th, w, z, rows):
     return worst
 
 
+def _golden_dense():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense_n25600.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def _sha(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("a", [0.1, 0.3, 0.03])
+def test_dense_fullsize_against_oracle(lib, orc, a):
+    """Eq. (1) at n = 25,600 (51,200^2) against the oracle's own evaluation
+    of the same inputs (tests/golden/dense_n25600.json, written by
+    tests/golden/make_dense_n25600.py, which calls only the oracle): log|Sigma|
+    and Z^T Sigma^-1 Z each within 1e-9 relative, or 10x the FP64 noise floor
+    (the oracle against a LAPACK factor of the same Sigma) where that is
+    larger; at the tile sizes the autotuner offers above 512."""
+    g = _golden_dense()
+    case = g["cases"].get("a%g" % a) if g else None
+    if case is None:
+        pytest.skip("no oracle value stored for a = %g" % a)
+    n = g["n_loc"]
+    x, y = _sites(orc, n, g["seed"])
+    z = synthetic.normal_eps(2 * n, g["seed"])
+    assert (_sha(x), _sha(y), _sha(z)) == (g["sha256_x"], g["sha256_y"], g["sha256_z"])
+    th = tuple(case["theta"])
+    X, Y, Z = _dev(x), _dev(y), _dev(z)
+    for nb in (1024, 768):
+        _say("full-size dense vs oracle: a=%g nb=%d" % (a, nb))
+        got = lib.loglik(X, Y, Z, th, {"nb": nb})
+        assert got["status"][0] == 0
+        for key, fl in (("logdet", case["floor_logdet"]), ("quad", case["floor_quad"])):
+            tol = max(1e-9, 10.0 * fl)
+            rel = abs(got[key][0] - case[key]) / abs(case[key])
+            _say("  %s gpu %.16e oracle %.16e rel %.2e (floor %.2e, tol %.1e)"
+                 % (key, got[key][0], case[key], rel, fl, tol))
+            assert rel <= tol, key
+        rel = abs(got["loglik"][0] - case["loglik"]) / abs(case["loglik"])
+        assert rel <= max(1e-9, 10.0 * max(case["floor_logdet"], case["floor_quad"]))
+
+
 def test_dense_fullsize_sampled(lib, orc):
     n, nb = 25600, 1024
     N = 2 * n
