@@ -319,6 +319,29 @@ typedef struct {
 int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *h_logdet,
                 double *h_quad, int64_t *h_status, void *hip_stream);
 
+/* Scratch of loglik_many_noalloc: a fixed device array of this many bytes,
+ * held by every device the library runs on until the process ends. */
+#define MVG_NOALLOC_SCRATCH_BYTES (256ull << 20)
+/* Largest n_tasks of one loglik_many_noalloc call. */
+#define MVG_NOALLOC_MAX_TASKS 4096
+
+/* loglik_many without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same tasks, outputs and results
+ * (bitwise) as loglik_many; the task list, per-task outputs, queue counter
+ * and per-workgroup workspaces live in the library's fixed scratch array of
+ * MVG_NOALLOC_SCRATCH_BYTES on the current device instead of an allocation
+ * (when it holds fewer N x N workspaces than loglik_many would allocate,
+ * fewer workgroups take the same tasks).  The call stages through static
+ * host buffers and synchronises hip_stream before it returns.  Calls from
+ * one process are serialised; calls from several processes that overlap on
+ * one GPU would share its array and race (there is no cross-process lock).
+ * Returns as loglik_many, and MVG_ERR_LIMIT when n_tasks exceeds
+ * MVG_NOALLOC_MAX_TASKS or one workspace does not fit the scratch. */
+int loglik_many_noalloc(const mvg_task *h_tasks, int n_tasks, double *h_loglik,
+                        double *h_logdet, double *h_quad, int64_t *h_status,
+                        void *hip_stream);
+
 /* TLR compression (Section 5.3) of the off-diagonal tiles of Sigma(theta) by
  * randomized SVD with absolute truncation s_i > tlr_acc; tiles needing a rank
  * above tlr_max_rank stay dense.  h_ranks (nullable, T*T int32, row-major,

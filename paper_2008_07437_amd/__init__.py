@@ -11,7 +11,8 @@ from ._lib import (  # noqa: F401
     MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR, MVG_DST, MVG_MIXED_FP32X,
     Opts, Theta, ThetaP, Mat, Factor, MvgError, cov_generate_p, loglik_p, profile_loglik_p,
     mle_fit, MleOpts,
-    library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many, tlr_compress,
+    library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many,
+    loglik_many_noalloc, tlr_compress,
     cokrige_predict, mloe_mmom, mvg_footprint, mvg_dst_band, mvg_autotune_nb, MVG_NB_AUTO, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
     Server, Result, REQ_LOGLIK, REQ_COKRIGE,
 )

@@ -122,6 +122,7 @@ def _load():
         "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
         "mvg_ir_stats": (c_int, [c_int, P, P, P]),
         "loglik_many": (c_int, [P, c_int, P, P, P, P, P]),
+        "loglik_many_noalloc": (c_int, [P, c_int, P, P, P, P, P]),
         "mvg_server_create": (P, [ctypes.c_size_t, c_int, P]),
         "mvg_server_add_dataset": (c_int, [P, P, P, P, c_int64]),
         "mvg_server_submit": (c_int64, [P, c_int, c_int, P, P, P, c_int64, P, c_double]),
@@ -400,10 +401,22 @@ class Task(ctypes.Structure):
 SMALL_MAX_ROWS = 1024
 
 
-def loglik_many(tasks, stream=None):
+def loglik_many(tasks, stream=None, noalloc=False):
     """Eq. (1) for many small problems in one persistent launch.  tasks: list
     of (x, y, z, theta) with device float64 tensors (2 n <= 1024).  Returns a
-    dict of numpy arrays as loglik does."""
+    dict of numpy arrays as loglik does.  noalloc=True calls
+    loglik_many_noalloc (the library's fixed scratch array, no allocation)."""
+    if noalloc:
+        return loglik_many_noalloc(tasks, stream)
+    return _loglik_many("loglik_many", tasks, stream)
+
+
+def loglik_many_noalloc(tasks, stream=None):
+    """loglik_many without any device allocation (fixed scratch array)."""
+    return _loglik_many("loglik_many_noalloc", tasks, stream)
+
+
+def _loglik_many(name, tasks, stream):
     k = len(tasks)
     arr = (Task * k)()
     for i, (x, y, z, th) in enumerate(tasks):
@@ -411,10 +424,9 @@ def loglik_many(tasks, stream=None):
                       Theta.of(th))
     ll, ld, q = np.zeros(k), np.zeros(k), np.zeros(k)
     st = np.zeros(k, dtype=np.int64)
-    _check("loglik_many", _load().loglik_many(arr, k, ll.ctypes.data_as(c_void_p),
-                                              ld.ctypes.data_as(c_void_p),
-                                              q.ctypes.data_as(c_void_p),
-                                              st.ctypes.data_as(c_void_p), _stream(stream)))
+    _check(name, getattr(_load(), name)(arr, k, ll.ctypes.data_as(c_void_p),
+                                        ld.ctypes.data_as(c_void_p), q.ctypes.data_as(c_void_p),
+                                        st.ctypes.data_as(c_void_p), _stream(stream)))
     return {"loglik": ll, "logdet": ld, "quad": q, "status": st}
 
 

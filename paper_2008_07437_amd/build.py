@@ -1,23 +1,49 @@
-"""Build step for the gfx950 library: hipcc -> paper_2008_07437_amd/libmvgeo.so."""
+"""Build step for the gfx950 library: hipcc -> paper_2008_07437_amd/libmvgeo.so.
+
+Every source is compiled to an object in parallel (each file's kernels and
+device functions are self-contained, so no relocatable device code is
+needed), then the objects are linked into the shared library."""
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libmvgeo.so")
 SOURCES = ["capi.hip", "matern.hip", "dense.hip", "solve.hip", "mixed.hip", "morton.hip", "tlr.hip",
-           "tlr_kernels.hip", "batched.hip", "serve.cpp", "mle.cpp"]
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-Wno-unused-value",
-         "-Wl,-z,defs"]  # an unresolved symbol fails the link, not the first load
+           "tlr_kernels.hip", "batched.hip", "noalloc.hip", "serve.cpp", "mle.cpp"]
+CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-result", "-Wno-unused-value"]
+LDFLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC",
+           "-Wl,-z,defs"]  # an unresolved symbol fails the link, not the first load
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs,
-           "-o", SO + ".tmp"]
+def _obj(src: str) -> str:
+    return os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+
+
+def _compile(src: str, verbose: bool) -> None:
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = ["hipcc", *CFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c",
+           os.path.join(CSRC, src), "-o", _obj(src)]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = False, only=None) -> str:
+    """Compiles the sources (all of them, or those named in `only` when their
+    objects exist) and links libmvgeo.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    todo = [s for s in SOURCES if only is None or s in only or not os.path.exists(_obj(s))]
+    jobs = max(1, min(len(todo), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_compile, s, verbose) for s in todo]:
+            f.result()
+    cmd = ["hipcc", *LDFLAGS, *[_obj(s) for s in SOURCES], "-o", SO + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -26,4 +52,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, only=sys.argv[1:] or None))

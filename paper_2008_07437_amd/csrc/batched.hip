@@ -319,7 +319,7 @@ size_t small_workspace_doubles(int64_t nmax) {
 }
 
 int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *d_counter,
-                        double *d_ws, double *d_out, hipStream_t st) {
+                        double *d_ws, double *d_out, hipStream_t st, int max_wg) {
   if (ntask <= 0) return 0;
   if (2 * nmax > SMALL_MAX) {
     set_error("batched small likelihood: 2n = %lld above %d", (long long)(2 * nmax), SMALL_MAX);
@@ -327,7 +327,8 @@ int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *
   }
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, d_counter);
   if (int rc = check_launch("zero_int")) return rc;
-  const int G = small_batch_workgroups(ntask);
+  int G = small_batch_workgroups(ntask);
+  if (max_wg > 0 && G > max_wg) G = max_wg;  // the workspace holds max_wg task slots
   hipLaunchKernelGGL(k_small_loglik, dim3(G), dim3(STHREADS), 0, st, d_tasks, ntask, d_counter, d_ws,
                      (int64_t)small_workspace_doubles(nmax), d_out);
   return check_launch("small_loglik");

@@ -186,6 +186,19 @@ __global__ void k_copy_pad(const double *__restrict__ src, int64_t n, double *__
   if (i < np) dst[i] = i < n ? src[i] : 0.0;
 }
 
+SmallTask small_task(const double *x, const double *y, const double *z, int64_t n,
+                     const mvg_theta &th) {
+  SmallTask t{};
+  t.x = x;
+  t.y = y;
+  t.z = z;
+  t.n = n;
+  matern_setup(&th, &t.P);
+  t.t0 = 0x1p-40 * th.sigma11_sq;
+  t.t1 = 0x1p-40 * th.sigma22_sq;
+  return t;
+}
+
 }  // namespace mvg
 
 using namespace mvg;
@@ -843,18 +856,6 @@ static int run_small(const std::vector<SmallTask> &tasks, int64_t nmax, double *
   return 0;
 }
 
-static SmallTask small_task(const double *x, const double *y, const double *z, int64_t n,
-                            const mvg_theta &th) {
-  SmallTask t{};
-  t.x = x;
-  t.y = y;
-  t.z = z;
-  t.n = n;
-  matern_setup(&th, &t.P);
-  t.t0 = 0x1p-40 * th.sigma11_sq;
-  t.t1 = 0x1p-40 * th.sigma22_sq;
-  return t;
-}
 
 int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *h_logdet,
                 double *h_quad, int64_t *h_status, void *hip_stream) {

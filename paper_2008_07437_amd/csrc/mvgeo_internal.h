@@ -205,8 +205,13 @@ struct SmallTask {
   MaternArgs P;
   double t0, t1;            // pivot tolerances (2^-40 sigma_ii^2)
 };
+// out: 4 per task; d_ws holds one small_workspace_doubles(nmax) slot per
+// workgroup, min(small_batch_workgroups(ntask), max_wg if > 0) workgroups
 int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *d_counter,
-                        double *d_ws, double *d_out, hipStream_t st);  // out: 4 per task
+                        double *d_ws, double *d_out, hipStream_t st, int max_wg = 0);
+// a task of the batched kernel from a dataset and theta (theta validated by the caller)
+SmallTask small_task(const double *x, const double *y, const double *z, int64_t n,
+                     const mvg_theta &th);
 size_t small_workspace_doubles(int64_t nmax);
 int small_batch_workgroups(int ntask);
 
