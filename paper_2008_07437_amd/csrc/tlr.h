@@ -62,6 +62,13 @@ int64_t gemm_blocks(const GemmTask &t);
 int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);  // mmax: largest m
 // unpivoted QR in panels (compact WY); tk.tau must hold (n + 8) x 8 doubles (T factors)
 int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);
+// unpivoted QR in panels of 16 over several launches (panel factor, then a
+// multi-workgroup block-reflector update per panel; Q formed the same way);
+// tk.tau must hold (n + 16) x 16 doubles; usable when qr_panels_ok
+bool qr_panels_ok(int mmin, int mmax, int nmax);
+int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool with_q,
+                     hipStream_t st);
+constexpr int QR_TAU_WIDTH = 16;  // T factors: (n + 16) x 16 doubles per task
 int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st);
 int launch_gaussian(const SketchTask *d_tasks, int ntask, hipStream_t st);
 int launch_copy_cols(const CopyTask *d_tasks, int ntask, hipStream_t st);

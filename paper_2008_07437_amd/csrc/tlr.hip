@@ -82,14 +82,42 @@ static int run_list(const std::vector<T> &v, HostLists &L, hipStream_t st) {
   return F(d, (int)v.size(), st);
 }
 
+// Unpivoted QRs of a batch go to the several-launch panel form when every
+// matrix fits it and the widest has at least QR_PANELS_MIN_N columns (a
+// single workgroup per matrix is then the critical path); narrower batches
+// stay with the one-launch blocked kernel.  MVG_QR_PANELS=0 / 1 forces the
+// choice (experiments).
+constexpr int QR_PANELS_MIN_N = 64;
+
+static int qr_panels_mode() {
+  static const int mode = [] {
+    const char *e = getenv("MVG_QR_PANELS");
+    return e ? atoi(e) : -1;
+  }();
+  return mode;
+}
+
 static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostLists &L,
                   hipStream_t st) {
   if (v.empty()) return 0;
   int rc = 0;
   const QrTask *d = (const QrTask *)L.stage(v.data(), v.size() * sizeof(QrTask), st, &rc);
   if (rc) return rc;
-  return blocked ? launch_qr_blocked(d, (int)v.size(), mmax, st)
-                 : launch_qr(d, (int)v.size(), mmax, st);
+  if (blocked) {
+    int mmin = v[0].m, mx = 0, nmax = 0;
+    bool with_q = false;
+    for (const QrTask &t : v) {
+      mmin = std::min(mmin, t.m);
+      mx = std::max(mx, t.m);
+      nmax = std::max(nmax, t.n);
+      with_q = with_q || t.Q;
+    }
+    const int mode = qr_panels_mode();
+    const bool panels = qr_panels_ok(mmin, mx, nmax) && (mode == 1 || (mode != 0 && nmax >= QR_PANELS_MIN_N));
+    if (panels) return launch_qr_panels(d, (int)v.size(), mx, nmax, with_q, st);
+    return launch_qr_blocked(d, (int)v.size(), mmax, st);
+  }
+  return launch_qr(d, (int)v.size(), mmax, st);
 }
 
 static GemmTask gemm(const double *A, int lda, int ta, const double *B, int ldb, int tb, double *C,
@@ -184,14 +212,16 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
   const int T = D.T;
   const int smax = std::min(nb, QR_MAXN);
   while (!jobs.empty()) {
-    // scratch per job: Om | Y | Z | Qp (nb x s each), R | Q3 (s x s), T (8 (s + 8)), piv (s) + rank
+    // scratch per job: Om | Y | Z | Qp (nb x s each), R | Q3 (s x s),
+    // T factors (QR_TAU_WIDTH (s + QR_TAU_WIDTH)), piv (s) + rank
+    constexpr size_t TW = QR_TAU_WIDTH;
     std::vector<size_t> base(jobs.size());
     size_t tot = 0;
     int smx = 1;
     for (size_t b = 0; b < jobs.size(); ++b) {
       const size_t s = jobs[b].s;
       base[b] = tot;
-      tot += 4 * (size_t)nb * s + 2 * s * s + 8 * (s + 8) + s + 2;
+      tot += 4 * (size_t)nb * s + 2 * s * s + TW * (s + TW) + s + 2;
       smx = std::max(smx, jobs[b].s);
     }
     double *ws = nullptr;
@@ -207,9 +237,9 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     auto Rb = [&](size_t b) { return ws + base[b] + 4 * (size_t)nb * jobs[b].s; };
     auto Q3 = [&](size_t b) { return Rb(b) + (size_t)jobs[b].s * jobs[b].s; };
     auto Tb = [&](size_t b) { return Q3(b) + (size_t)jobs[b].s * jobs[b].s; };
-    // T factors of the blocked QR: one 8 x 8 block per panel of 8 columns
-    auto Pv = [&](size_t b) { return (int *)(Tb(b) + 8 * ((size_t)jobs[b].s + 8)); };
-    auto Rk = [&](size_t b) { return (int *)(Tb(b) + 8 * ((size_t)jobs[b].s + 8) + jobs[b].s); };
+    // T factors of the blocked QR (one block per panel of columns)
+    auto Pv = [&](size_t b) { return (int *)(Tb(b) + TW * ((size_t)jobs[b].s + TW)); };
+    auto Rk = [&](size_t b) { return (int *)(Tb(b) + TW * ((size_t)jobs[b].s + TW) + jobs[b].s); };
     HostLists L;
     int rc = 0;
     {

@@ -592,6 +592,333 @@ int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st
   return check_launch("qr_blocked");
 }
 
+// ------------------------------------------ blocked QR over several launches
+//
+// The same factorisation as k_qr_blocked (compact WY panels, Schreiber and
+// Van Loan), split so that one large matrix is not left to one workgroup:
+// per panel of PQB columns one launch factors the panel of every task (one
+// workgroup per task, the panel in registers) and one launch applies the
+// panel's block reflector to the rest of A (several workgroups per task,
+// PAP_CB columns each, on FP64 MFMA); Q = H_1 ... H_P [I; 0] is then formed
+// panel by panel from the last by the same apply kernel.  A panel step costs
+// two workgroup barriers and one wave-reduction of PQB values; the matrix
+// itself stays in L2 / HBM (an nb x s sketch is up to 6 MB).
+// Requirements (checked by the launcher): m % 4 == 0, n + PQB <= m <= PQ_MAXM.
+constexpr int PQB = 16;          // panel width
+constexpr int PQ_THREADS = 512;  // panel workgroup
+constexpr int PQ_MAXM = 1536;    // rows: 3 per panel thread
+constexpr int PAP_CB = 32;       // columns per apply workgroup
+constexpr int PAP_THREADS = 256; // apply workgroup (4 waves)
+
+// T factors in tk.tau: panel p0 at rows p0 .. p0 + PQB - 1 of a PQB-wide
+// row-major array ((n + PQB) x PQB doubles).
+template <int RPT>
+__global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restrict__ tasks, int p0) {
+  __shared__ double red_s[PQ_THREADS / 64];
+  __shared__ double red_d[PQ_THREADS / 64][PQB];
+  __shared__ double s_alpha;
+  __shared__ double sT[PQB][PQB];
+  const QrTask tk = tasks[blockIdx.x];
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  if (p0 >= n) return;  // uniform: this task has no panel here
+  const int pb = min(PQB, n - p0);
+  double *A = tk.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // rows p0 + tid + 512 e of the panel columns: loaded together from clamped
+  // addresses, zeroed outside the matrix after a scheduling barrier
+  double a[RPT][PQB];
+#pragma unroll
+  for (int e = 0; e < RPT; ++e) {
+    const int r = min(p0 + tid + PQ_THREADS * e, m - 1);
+#pragma unroll
+    for (int c = 0; c < PQB; ++c) a[e][c] = A[(int64_t)min(p0 + c, n - 1) * lda + r];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int e = 0; e < RPT; ++e)
+#pragma unroll
+    for (int c = 0; c < PQB; ++c)
+      if (p0 + tid + PQ_THREADS * e >= m || c >= pb) a[e][c] = 0.0;
+  for (int jj = 0; jj < pb; ++jj) {
+    const int j = p0 + jj;
+    // squared norm of column jj below row j, and its entry on row j
+    double ss = 0.0;
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+      const int r = p0 + tid + PQ_THREADS * e;
+      double x = 0.0;
+#pragma unroll
+      for (int c = 0; c < PQB; ++c)
+        if (c == jj) x = a[e][c];
+      if (r > j) ss += x * x;
+      if (r == j) s_alpha = x;
+    }
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    if (lane == 0) red_s[wave] = ss;
+    __syncthreads();
+    double sigma2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < PQ_THREADS / 64; ++w) sigma2 += red_s[w];
+    const double alpha = s_alpha;
+    double tau = 0.0, scale = 0.0, beta = alpha;
+    if (sigma2 > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // the reflector below row j (v_j = 1 implicit), beta on row j; then the
+    // inner products of v with every other panel column: d_c for c > jj
+    // (to update them), d_c = V[:, c]^T v for c < jj (for T)
+    double v[RPT];
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+      const int r = p0 + tid + PQ_THREADS * e;
+#pragma unroll
+      for (int c = 0; c < PQB; ++c)
+        if (c == jj) {
+          if (r > j) a[e][c] *= scale;
+          else if (r == j) a[e][c] = beta;
+          v[e] = r > j ? a[e][c] : (r == j ? 1.0 : 0.0);
+        }
+    }
+    double d[PQB];
+#pragma unroll
+    for (int c = 0; c < PQB; ++c) {
+      d[c] = 0.0;
+#pragma unroll
+      for (int e = 0; e < RPT; ++e) d[c] += a[e][c] * v[e];
+    }
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int c = 0; c < PQB; ++c) d[c] += __shfl_xor(d[c], o);
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < PQB; ++c) red_d[wave][c] = d[c];
+    __syncthreads();
+    {
+      // lane c < PQB sums the waves' partials of column c in a fixed order,
+      // then every lane takes the sums from those lanes (reading all of
+      // red_d per lane would hold 128 values in registers)
+      double part = 0.0;
+      if (lane < PQB)
+#pragma unroll
+        for (int w = 0; w < PQ_THREADS / 64; ++w) part += red_d[w][lane];
+#pragma unroll
+      for (int c = 0; c < PQB; ++c) d[c] = __shfl(part, c);
+    }
+    // rows >= j of the columns right of jj: a -= tau (v^T a) v
+#pragma unroll
+    for (int e = 0; e < RPT; ++e)
+#pragma unroll
+      for (int c = 0; c < PQB; ++c)
+        if (c > jj) a[e][c] -= tau * d[c] * v[e];
+    // column jj of T (thread c owns row c of T): T_jj = tau,
+    // T[c][jj] = -tau sum_{c <= l < jj} T[c][l] (V[:, l]^T v_jj)
+    if (tid < jj) {
+      double t = 0.0;
+      for (int l = tid; l < jj; ++l) {
+        double dl = 0.0;
+#pragma unroll
+        for (int c = 0; c < PQB; ++c)
+          if (c == l) dl = d[c];
+        t += sT[tid][l] * dl;
+      }
+      sT[tid][jj] = -tau * t;
+    } else if (tid == jj) {
+      sT[jj][jj] = tau;
+    }
+  }
+  // the panel back (R on and above the diagonal, reflectors below), and T
+#pragma unroll
+  for (int e = 0; e < RPT; ++e) {
+    const int r = p0 + tid + PQ_THREADS * e;
+    if (r < m)
+#pragma unroll
+      for (int c = 0; c < PQB; ++c)
+        if (c < pb) A[(int64_t)(p0 + c) * lda + r] = a[e][c];
+  }
+  if (tid < PQB) {
+    double *Tg = tk.tau + (int64_t)(p0 + tid) * PQB;
+    for (int b = 0; b < PQB; ++b) Tg[b] = (tid < pb && b < pb && b >= tid) ? sT[tid][b] : 0.0;
+  }
+}
+
+// X <- (I - V op(T) V^T) X on rows p0 .. m-1, for PAP_CB columns of X per
+// workgroup.  V: the panel's reflectors (columns p0 .. p0 + pb - 1 of tk.A,
+// unit on row p0 + q, zero above).  MODE 0 (factorisation): X = columns
+// p0 + pb + PAP_CB b of tk.A, op(T) = T^T.  MODE 1 (forming Q): X = columns
+// p0 + PAP_CB b of tk.Q, op(T) = T.
+// W = V^T X runs on v_mfma_f64_16x16x4f64 with the contraction over rows:
+// in K-step s lane l holds row r0 + 4 (l / 16) + s, so a lane's four rows
+// are consecutive (one 32-byte load per column); then W' = op(T) W in LDS;
+// then X -= V W' on the same MFMA with X tiles as accumulators.
+template <int MODE>
+__global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restrict__ tasks, int p0,
+                                                          int nblk) {
+  __shared__ double sW[PAP_THREADS / 64][PQB][PAP_CB + 1];
+  __shared__ double sN[PQB][PAP_CB + 1];  // -op(T) W
+  __shared__ double sT[PQB][PQB + 1];
+  const QrTask tk = tasks[blockIdx.x / nblk];
+  const int b = blockIdx.x % nblk;
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  if (p0 >= n) return;
+  if (MODE == 1 && !tk.Q) return;
+  const int pb = min(PQB, n - p0);
+  const int c0 = (MODE == 0 ? p0 + pb : p0) + PAP_CB * b;
+  if (c0 >= n) return;  // uniform per workgroup
+  double *X = MODE == 0 ? tk.A : tk.Q;
+  const int ldx = MODE == 0 ? lda : tk.ldq;
+  const int M = m - p0;  // rows of the block (a multiple of 4)
+  const double *V = tk.A + (int64_t)p0 * lda + p0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int qv = min(l16, pb - 1);                      // clamped reflector column
+  const int xc0 = min(c0 + l16, n - 1), xc1 = min(c0 + 16 + l16, n - 1);
+  const bool xok0 = c0 + l16 < n, xok1 = c0 + 16 + l16 < n;
+  const int nchunk = (M + 15) / 16;
+  // ---- W = V^T X
+  dbl4t acc[2] = {dbl4t{0.0, 0.0, 0.0, 0.0}, dbl4t{0.0, 0.0, 0.0, 0.0}};
+  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
+    const int rr = 16 * ch + 4 * lk;          // first of the lane's 4 rows
+    const int rl = min(rr, M - 4);            // in bounds (M >= 4, M % 4 == 0)
+    double vv[4], x0[4], x1[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      vv[s] = V[(int64_t)qv * lda + rl + s];
+      x0[s] = X[(int64_t)xc0 * ldx + p0 + rl + s];
+      x1[s] = X[(int64_t)xc1 * ldx + p0 + rl + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = rr + s;
+      const bool rok = r < M;
+      double vq = vv[s];
+      if (r < l16) vq = 0.0;            // above the unit diagonal of V
+      else if (r == l16) vq = 1.0;
+      if (!rok || l16 >= pb) vq = 0.0;
+      const double xa = (rok && xok0) ? x0[s] : 0.0;
+      const double xb = (rok && xok1) ? x1[s] : 0.0;
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xa, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xb, acc[1], 0, 0, 0);
+    }
+  }
+  // D[q][c] of a 16 x 16 tile: lane c + 16 (q % 4), element q / 4
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sW[wave][4 * e + lk][16 * h + l16] = acc[h][e];
+  if (tid < PQB * PQB) {
+    const int i = tid / PQB, k = tid % PQB;
+    sT[i][k] = tk.tau[(int64_t)(p0 + i) * PQB + k];
+  }
+  __syncthreads();
+  // the four waves' partial sums, in a fixed order
+  for (int o = tid; o < PQB * PAP_CB; o += PAP_THREADS) {
+    const int q = o / PAP_CB, c = o % PAP_CB;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PAP_THREADS / 64; ++w) t += sW[w][q][c];
+    sW[0][q][c] = t;
+  }
+  __syncthreads();
+  for (int o = tid; o < PQB * PAP_CB; o += PAP_THREADS) {
+    const int q = o / PAP_CB, c = o % PAP_CB;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < PQB; ++k) t += (MODE == 0 ? sT[k][q] : sT[q][k]) * sW[0][k][c];
+    sN[q][c] = -t;
+  }
+  __syncthreads();
+  // ---- X -= V W'  (accumulators start from the X tiles)
+  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
+    const int r0 = 16 * ch;
+    const int rv = min(r0 + l16, M - 1);      // V row of this lane (A operand)
+    double va[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) va[s] = V[(int64_t)min(4 * s + lk, pb - 1) * lda + rv];
+    dbl4t xt[2];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rx = min(r0 + 4 * e + lk, M - 1);
+      xt[0][e] = X[(int64_t)xc0 * ldx + p0 + rx];
+      xt[1][e] = X[(int64_t)xc1 * ldx + p0 + rx];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = 4 * s + lk, r = r0 + l16;
+      double vq = va[s];
+      if (r < q) vq = 0.0;
+      else if (r == q) vq = 1.0;
+      if (r >= M || q >= pb) vq = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        xt[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, sN[q][16 * h + l16], xt[h], 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rx = r0 + 4 * e + lk;
+      if (rx < M) {
+        if (xok0) X[(int64_t)xc0 * ldx + p0 + rx] = xt[0][e];
+        if (xok1) X[(int64_t)xc1 * ldx + p0 + rx] = xt[1][e];
+      }
+    }
+  }
+}
+
+__global__ void k_qr_qinit(const QrTask *__restrict__ tasks, int nblk) {
+  // Q = [I; 0]: one workgroup per (task, 64 columns)
+  const QrTask tk = tasks[blockIdx.x / nblk];
+  if (!tk.Q) return;
+  const int c0 = 64 * (blockIdx.x % nblk);
+  for (int c = c0; c < min(c0 + 64, tk.n); ++c)
+    for (int i = threadIdx.x; i < tk.m; i += blockDim.x)
+      tk.Q[(int64_t)c * tk.ldq + i] = (i == c) ? 1.0 : 0.0;
+}
+
+bool qr_panels_ok(int mmin, int mmax, int nmax) {
+  return mmax <= PQ_MAXM && (mmin % 4) == 0 && (mmax % 4) == 0 && nmax + PQB <= mmin;
+}
+
+int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool with_q,
+                     hipStream_t st) {
+  if (ntask <= 0 || nmax <= 0) return 0;
+  if (mmax > PQ_MAXM) {
+    set_error("QR: %d rows above %d", mmax, PQ_MAXM);
+    return MVG_ERR_LIMIT;
+  }
+  const int rpt = (mmax + PQ_THREADS - 1) / PQ_THREADS;
+  for (int p0 = 0; p0 < nmax; p0 += PQB) {
+    if (rpt == 1)
+      hipLaunchKernelGGL((k_qr_panel<1>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    else if (rpt == 2)
+      hipLaunchKernelGGL((k_qr_panel<2>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    else
+      hipLaunchKernelGGL((k_qr_panel<3>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    if (int rc = check_launch("qr_panel")) return rc;
+    const int rest = nmax - p0 - PQB;
+    if (rest > 0) {
+      const int nblk = (rest + PAP_CB - 1) / PAP_CB;
+      hipLaunchKernelGGL((k_qr_apply<0>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks,
+                         p0, nblk);
+      if (int rc = check_launch("qr_apply")) return rc;
+    }
+  }
+  if (!with_q) return 0;
+  const int qb = (nmax + 63) / 64;
+  hipLaunchKernelGGL(k_qr_qinit, dim3(ntask * qb), dim3(256), 0, st, d_tasks, qb);
+  if (int rc = check_launch("qr_qinit")) return rc;
+  for (int p0 = ((nmax - 1) / PQB) * PQB; p0 >= 0; p0 -= PQB) {
+    const int nblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
+    hipLaunchKernelGGL((k_qr_apply<1>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks, p0,
+                       nblk);
+    if (int rc = check_launch("qr_apply")) return rc;
+  }
+  return 0;
+}
+
 int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st) {
   if (ntask <= 0) return 0;
   if (mmax > QR_MAXM) {
