@@ -30,16 +30,10 @@ struct QrTask {
   int *piv;     // nullable: column pivoting, column order out (n)
   double tol;   // pivoting: stop when the remaining Frobenius norm <= tol
   int *rank;    // pivoting: reflectors applied (out)
+  double *work; // randomized pivoting (launch_qrcp_panels): m x QRS_ROWS Gaussian,
+                // then QRS_ROWS x n sample (nullable otherwise)
 };
 
-constexpr int JACOBI_MAX_SWEEPS = 40;
-struct SvdTask {
-  double *R;  // n x n, overwritten by R J
-  int n, ldr;
-  double *J;  // n x n right rotations
-  int ldj;
-  double *sig;  // n column norms of R J
-};
 
 struct SketchTask {
   double *out;
@@ -69,7 +63,15 @@ bool qr_panels_ok(int mmin, int mmax, int nmax);
 int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool with_q,
                      hipStream_t st);
 constexpr int QR_TAU_WIDTH = 16;  // T factors: (n + 16) x 16 doubles per task
-int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st);
+// Column-pivoted QR of tall matrices stopped at a Frobenius tail (the
+// k_qr pivoted form's contract: tk.piv, tk.rank, tk.tol, Q's first columns),
+// with pivots chosen per panel of 16 from a Gaussian sample of the trailing
+// matrix (randomized QRCP) and the factorisation done by the panel kernels.
+// tk.work: m x QRS_ROWS doubles holding a standard-normal matrix (filled by
+// the caller) followed by QRS_ROWS x n doubles of sample.
+constexpr int QRS_ROWS = 32;
+bool qrcp_panels_ok(int mmin, int mmax, int nmax);
+int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hipStream_t st);
 int launch_gaussian(const SketchTask *d_tasks, int ntask, hipStream_t st);
 int launch_copy_cols(const CopyTask *d_tasks, int ntask, hipStream_t st);
 

@@ -70,7 +70,12 @@ static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t s
   const GemmTask *dt = (const GemmTask *)L.stage(t.data(), t.size() * sizeof(GemmTask), st, &rc);
   const int64_t *ds = (const int64_t *)L.stage(start.data(), start.size() * 8, st, &rc);
   if (rc) return rc;
-  return launch_gemm_batched(dt, ds, (int)t.size(), nb, st);
+  double fl = 0.0;
+  for (const GemmTask &g : t) fl += 2.0 * g.M * (double)g.N * g.K;
+  const int h = prof_begin(MVG_PROF_TLRGEMM, st, fl, 0.0);  // after the task lists' copies
+  rc = launch_gemm_batched(dt, ds, (int)t.size(), nb, st);
+  prof_end(h, st);
+  return rc;
 }
 
 template <class T, int (*F)(const T *, int, hipStream_t)>
@@ -97,12 +102,28 @@ static int qr_panels_mode() {
   return mode;
 }
 
+// The randomized-pivot panel form of the truncating pivoted QR (on B^T)
+// replaces the blocked QR of B^T and the one-workgroup pivoted QR of R''
+// for batches whose widest sketch has at least QR_PANELS_MIN_N columns.
+// MVG_QRCP_PANELS=0 / 1 forces the choice (experiments).
+static bool use_qrcp_panels(int nb, int smax) {
+  static const int mode = [] {
+    const char *e = getenv("MVG_QRCP_PANELS");
+    return e ? atoi(e) : -1;
+  }();
+  if (mode == 0 || !qrcp_panels_ok(nb, nb, smax)) return false;
+  return mode == 1 || smax >= QR_PANELS_MIN_N;
+}
+
 static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostLists &L,
                   hipStream_t st) {
   if (v.empty()) return 0;
   int rc = 0;
   const QrTask *d = (const QrTask *)L.stage(v.data(), v.size() * sizeof(QrTask), st, &rc);
   if (rc) return rc;
+  double fl = 0.0;
+  for (const QrTask &t : v) fl += 4.0 * t.m * (double)t.n * t.n - 4.0 / 3.0 * t.n * (double)t.n * t.n;
+  const int h = prof_begin(MVG_PROF_QR, st, blocked ? fl : 0.0, 0.0);
   if (blocked) {
     int mmin = v[0].m, mx = 0, nmax = 0;
     bool with_q = false;
@@ -114,10 +135,13 @@ static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostList
     }
     const int mode = qr_panels_mode();
     const bool panels = qr_panels_ok(mmin, mx, nmax) && (mode == 1 || (mode != 0 && nmax >= QR_PANELS_MIN_N));
-    if (panels) return launch_qr_panels(d, (int)v.size(), mx, nmax, with_q, st);
-    return launch_qr_blocked(d, (int)v.size(), mmax, st);
+    rc = panels ? launch_qr_panels(d, (int)v.size(), mx, nmax, with_q, st)
+                : launch_qr_blocked(d, (int)v.size(), mmax, st);
+  } else {
+    rc = launch_qr(d, (int)v.size(), mmax, st);
   }
-  return launch_qr(d, (int)v.size(), mmax, st);
+  prof_end(h, st);
+  return rc;
 }
 
 static GemmTask gemm(const double *A, int lda, int ta, const double *B, int ldb, int tb, double *C,
@@ -197,14 +221,19 @@ struct CompressJob {
 // updated with the ranks found.
 //
 // Per tile C (nb x nb): Y = C Omega (Gaussian, nb x s); Y = Q R (blocked
-// Householder); B^T = C^T Q = Q'' R'' (blocked Householder); R'' P = Q3 R3 by
-// column-pivoted Householder QR of the small s x s factor, stopped at the
-// first k with ||R3_22||_F <= acc.  Then B^T P ~= (Q'' Q3_k) R3_k and
-// C ~= Q B ~= (Q P R3_k^T) (Q'' Q3_k)^T, i.e. U = (Q P) R3_k^T and
-// V = Q'' Q3_k, with ||C - U V^T||_2 <= ||C - Q B||_2 + acc (the
-// Frobenius-norm tail rule; it keeps at least the ranks of the 2-norm rule
-// s_i > acc).  A rank above s - OVERSAMPLE (the sketch may have missed
-// part of the range) is retried with a wider sketch.
+// Householder); then a column-pivoted QR of B^T = C^T Q, stopped at the first
+// k whose trailing block has ||R_22||_F <= acc, in one of two forms:
+//  * large batches (the widest sketch >= QR_PANELS_MIN_N columns, tall
+//    enough for the panel kernels): directly on B^T (nb x s) by the
+//    randomized-pivot panel QR, B^T P = Q4 R4, so U = (Q P) R4_k^T and
+//    V = Q4_k;
+//  * otherwise B^T = Q'' R'' (blocked Householder), then R'' P = Q3 R3 by
+//    the one-workgroup column-pivoted QR of the s x s factor, so
+//    U = (Q P) R3_k^T and V = Q'' Q3_k.
+// Either way ||C - U V^T||_2 <= ||C - Q B||_2 + acc (the Frobenius-norm
+// tail rule; it keeps at least the ranks of the 2-norm rule s_i > acc).  A
+// rank above s - OVERSAMPLE (the sketch may have missed part of the range)
+// is retried with a wider sketch.
 static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
                          uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
                          hipStream_t st) {
@@ -213,17 +242,23 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
   const int smax = std::min(nb, QR_MAXN);
   while (!jobs.empty()) {
     // scratch per job: Om | Y | Z | Qp (nb x s each), R | Q3 (s x s),
-    // T factors (QR_TAU_WIDTH (s + QR_TAU_WIDTH)), piv (s) + rank
+    // T factors (QR_TAU_WIDTH (s + QR_TAU_WIDTH)), piv (s), pivot-sample
+    // work (nb x QRS_ROWS + QRS_ROWS x s + s, randomized form only); then
+    // the ranks of all jobs (contiguous: one copy to the host)
     constexpr size_t TW = QR_TAU_WIDTH;
+    int smx = 1;
+    for (size_t b = 0; b < jobs.size(); ++b) smx = std::max(smx, jobs[b].s);
+    const bool rq = use_qrcp_panels(nb, smx);
     std::vector<size_t> base(jobs.size());
     size_t tot = 0;
-    int smx = 1;
     for (size_t b = 0; b < jobs.size(); ++b) {
       const size_t s = jobs[b].s;
       base[b] = tot;
-      tot += 4 * (size_t)nb * s + 2 * s * s + TW * (s + TW) + s + 2;
-      smx = std::max(smx, jobs[b].s);
+      tot += 4 * (size_t)nb * s + 2 * s * s + TW * (s + TW) + s + 1;
+      if (rq) tot += (size_t)QRS_ROWS * (nb + s) + s;
     }
+    const size_t rank_off = tot;
+    tot += (jobs.size() + 1) / 2;
     double *ws = nullptr;
     if (hipMallocAsync((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
       hipGetLastError();
@@ -239,7 +274,9 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     auto Tb = [&](size_t b) { return Q3(b) + (size_t)jobs[b].s * jobs[b].s; };
     // T factors of the blocked QR (one block per panel of columns)
     auto Pv = [&](size_t b) { return (int *)(Tb(b) + TW * ((size_t)jobs[b].s + TW)); };
-    auto Rk = [&](size_t b) { return (int *)(Tb(b) + TW * ((size_t)jobs[b].s + TW) + jobs[b].s); };
+    auto Wk = [&](size_t b) { return Tb(b) + TW * ((size_t)jobs[b].s + TW) + jobs[b].s + 1; };
+    int *d_ranks = (int *)(ws + rank_off);
+    auto Rk = [&](size_t b) { return d_ranks + b; };
     HostLists L;
     int rc = 0;
     {
@@ -266,13 +303,29 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
                          1.0, 0.0));
       rc = run_gemms(g, L, st);  // B^T = C^T Q -> Y
     }
-    if (!rc) {
+    if (!rc && rq) {
+      // B^T P = Q4 R4 (R4 in Y, Q4 -> Z), pivots from Gaussian samples
+      std::vector<SketchTask> sk;
+      std::vector<QrTask> q;
+      for (size_t b = 0; b < jobs.size(); ++b) {
+        sk.push_back(SketchTask{Wk(b), nb, QRS_ROWS, nb, seed, jobs[b].key | (1ull << 62)});
+        q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tb(b), Zb(b), nb, Pv(b), acc, Rk(b), Wk(b)});
+      }
+      rc = run_list<SketchTask, launch_gaussian>(sk, L, st);
+      if (!rc) {
+        const QrTask *d = (const QrTask *)L.stage(q.data(), q.size() * sizeof(QrTask), st, &rc);
+        const int h = prof_begin(MVG_PROF_QR, st, 0.0, 0.0);
+        if (!rc) rc = launch_qrcp_panels(d, (int)q.size(), nb, smx, st);
+        prof_end(h, st);
+      }
+    }
+    if (!rc && !rq) {
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b)
         q.push_back(QrTask{Yb(b), nb, jobs[b].s, nb, Tb(b), Zb(b), nb, nullptr, 0.0, nullptr});
       rc = run_qr(q, nb, true, L, st);  // B^T = Q'' R'', Q'' -> Z
     }
-    if (!rc) {
+    if (!rc && !rq) {
       std::vector<CopyTask> c;
       std::vector<QrTask> q;
       for (size_t b = 0; b < jobs.size(); ++b) {
@@ -286,8 +339,7 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     // ranks to the host
     std::vector<int> ranks(jobs.size(), 0);
     if (!rc) {
-      for (size_t b = 0; b < jobs.size(); ++b)
-        hipMemcpyAsync(&ranks[b], Rk(b), sizeof(int), hipMemcpyDeviceToHost, st);
+      hipMemcpyAsync(ranks.data(), d_ranks, sizeof(int) * jobs.size(), hipMemcpyDeviceToHost, st);
       if (hipStreamSynchronize(st) != hipSuccess) {
         set_error("TLR: compression kernels failed: %s", hipGetErrorString(hipGetLastError()));
         rc = MVG_ERR_LAUNCH;
@@ -352,7 +404,17 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
         const int r = D.rank[t];
         if (r == 0) continue;
         double *V = U + (int64_t)nb * r;
-        c.push_back(CopyTask{Om(b), Qp(b), nb, s, nb, nb, Pv(b), COPY_PLAIN});     // Q P
+        c.push_back(CopyTask{Om(b), Qp(b), nb, s, nb, nb, Pv(b), COPY_PLAIN});  // Q P
+        if (rq) {
+          c.push_back(CopyTask{Yb(b), Rb(b), r, s, nb, s, nullptr, COPY_UPPER_TRI});  // R4_k
+          g.push_back(gemm(Qp(b), nb, 0, Rb(b), s, 1, U, nb, nb, r, s, 1.0, 0.0));
+          // V = W Q4_k, or Q4_k
+          if (W)
+            g2.push_back(gemm(W, ldw, 0, Zb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
+          else
+            c.push_back(CopyTask{Zb(b), V, nb, r, nb, nb, nullptr, COPY_PLAIN});
+          continue;
+        }
         c.push_back(CopyTask{Rb(b), Rb(b), r, s, s, s, nullptr, COPY_UPPER_TRI});  // R3_k
         g.push_back(gemm(Qp(b), nb, 0, Rb(b), s, 1, U, nb, nb, r, s, 1.0, 0.0));
         // Q'_k = Q'' Q3_k, then V = W Q'_k

@@ -1,7 +1,8 @@
 // Batched small dense linear algebra for the tile-low-rank (TLR) path on
 // gfx950: FP64 GEMM on MFMA over lists of variable-size products, Householder
-// QR of tall-skinny matrices, one-sided Jacobi SVD of small square matrices,
-// Gaussian sketch matrices.  One list entry per product / matrix; the TLR
+// QR of tall-skinny matrices (one workgroup per matrix, or panels over
+// several launches; unpivoted, column-pivoted, or with randomized pivots and
+// a Frobenius-tail stop), Gaussian sketch matrices.  One list entry per product / matrix; the TLR
 // driver builds the lists on the host.
 #include <cmath>
 
@@ -621,6 +622,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, n = tk.n, lda = tk.lda;
   if (p0 >= n) return;  // uniform: this task has no panel here
+  if (tk.rank && *tk.rank <= p0) return;  // pivoted form: truncated before this panel
   const int pb = min(PQB, n - p0);
   double *A = tk.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -759,11 +761,13 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
   __shared__ double sW[PAP_THREADS / 64][PQB][PAP_CB + 1];
   __shared__ double sN[PQB][PAP_CB + 1];  // -op(T) W
   __shared__ double sT[PQB][PQB + 1];
+  __shared__ double sC[PAP_THREADS / 64][PAP_CB];
   const QrTask tk = tasks[blockIdx.x / nblk];
   const int b = blockIdx.x % nblk;
   const int m = tk.m, n = tk.n, lda = tk.lda;
   if (p0 >= n) return;
   if (MODE == 1 && !tk.Q) return;
+  if (tk.rank && *tk.rank <= p0) return;  // pivoted form: truncated before this panel
   const int pb = min(PQB, n - p0);
   const int c0 = (MODE == 0 ? p0 + pb : p0) + PAP_CB * b;
   if (c0 >= n) return;  // uniform per workgroup
@@ -831,7 +835,10 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
     sN[q][c] = -t;
   }
   __syncthreads();
-  // ---- X -= V W'  (accumulators start from the X tiles)
+  // ---- X -= V W'  (accumulators start from the X tiles); with tk.work
+  // (pivoted form, MODE 0) also the squared norms of the updated columns
+  // below the panel's rows (rows p0 + pb ..), for the truncation test
+  double css[2] = {0.0, 0.0};
   for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
     const int r0 = 16 * ch;
     const int rv = min(r0 + l16, M - 1);      // V row of this lane (A operand)
@@ -863,8 +870,272 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
       if (rx < M) {
         if (xok0) X[(int64_t)xc0 * ldx + p0 + rx] = xt[0][e];
         if (xok1) X[(int64_t)xc1 * ldx + p0 + rx] = xt[1][e];
+        if (rx >= pb) {
+          css[0] += xt[0][e] * xt[0][e];
+          css[1] += xt[1][e] * xt[1][e];
+        }
       }
     }
+  }
+  if (MODE == 0 && tk.work) {
+    // the four lanes of a column (l16 + 16 lk) in a fixed order, then the
+    // waves in a fixed order
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      css[h] += __shfl_xor(css[h], 16);
+      css[h] += __shfl_xor(css[h], 32);
+    }
+    if (lk == 0) {
+      sC[wave][l16] = css[0];
+      sC[wave][16 + l16] = css[1];
+    }
+    __syncthreads();
+    if (tid < PAP_CB && c0 + tid < n) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < PAP_THREADS / 64; ++w) t += sC[w][tid];
+      tk.work[(int64_t)QRS_ROWS * (m + n) + c0 + tid] = t;
+    }
+  }
+}
+
+// ------------------------------------------------ randomized pivoted QR
+//
+// Column-pivoted Householder QR stopped at the first k with a trailing
+// Frobenius norm <= tk.tol (the contract of k_qr's pivoted form), for tall
+// matrices, built from the panel kernels above.  Per panel of PQB columns:
+// a Gaussian sample G = Omega^T A_trail (QRS_ROWS rows) of the trailing
+// matrix; PQB pivots by column-pivoted QR of G (exact column norms of the
+// small sample at every step); the pivots' columns swapped into place (all
+// rows of A); the unpivoted panel factorisation and block-reflector update;
+// then the truncation test.  Randomized pivot selection from a sample with
+// oversampling: Martinsson, Quintana-Orti, Heavner and van de Geijn (2017);
+// Duersch and Gu (2017).  The truncation test is exact whatever the pivots:
+// after the panel, the tail after j reflectors (j inside the panel) is
+//   ||A_trail||_F^2 + sum_{j < i < p0 + PQB} ||R(i, i:n)||^2,
+// a sum of non-negative terms (orthogonal reflectors keep the norms of the
+// rows they act on), so no cancellation.
+// tk.work: Omega (m x QRS_ROWS, column-major, standard normal, filled by the
+// caller) | G (QRS_ROWS x n) | squared column norms of the trailing block (n).
+
+__global__ void k_qr_rinit(const QrTask *__restrict__ tasks) {
+  const QrTask tk = tasks[blockIdx.x];
+  for (int c = threadIdx.x; c < tk.n; c += blockDim.x) tk.piv[c] = c;
+  if (threadIdx.x == 0) *tk.rank = tk.n;
+}
+
+// G[:, c] = Omega(0 : m - q0, :)^T A(q0 : m, c) for columns c >= q0, PAP_CB
+// columns per workgroup (same MFMA layout as the first product of k_qr_apply).
+__global__ __launch_bounds__(PAP_THREADS) void k_qr_sample(const QrTask *__restrict__ tasks, int q0,
+                                                           int nblk) {
+  __shared__ double sW[PAP_THREADS / 64][QRS_ROWS][PAP_CB + 1];
+  const QrTask tk = tasks[blockIdx.x / nblk];
+  const int b = blockIdx.x % nblk;
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  if (q0 >= n || *tk.rank <= q0) return;
+  const int c0 = q0 + PAP_CB * b;
+  if (c0 >= n) return;
+  const int M = m - q0;
+  const double *Om = tk.work;  // Omega[r][q] at Om[q m + r]
+  double *G = tk.work + (int64_t)QRS_ROWS * m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int xc0 = min(c0 + l16, n - 1), xc1 = min(c0 + 16 + l16, n - 1);
+  const bool xok0 = c0 + l16 < n, xok1 = c0 + 16 + l16 < n;
+  const int nchunk = (M + 15) / 16;
+  dbl4t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
+  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
+    const int rr = 16 * ch + 4 * lk;
+    const int rl = min(rr, M - 4);
+    double o0[4], o1[4], x0[4], x1[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      o0[s] = Om[(int64_t)l16 * m + rl + s];
+      o1[s] = Om[(int64_t)(16 + l16) * m + rl + s];
+      x0[s] = tk.A[(int64_t)xc0 * lda + q0 + rl + s];
+      x1[s] = tk.A[(int64_t)xc1 * lda + q0 + rl + s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool rok = rr + s < M;
+      const double a0 = rok ? o0[s] : 0.0, a1 = rok ? o1[s] : 0.0;
+      const double xa = (rok && xok0) ? x0[s] : 0.0;
+      const double xb = (rok && xok1) ? x1[s] : 0.0;
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xa, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xb, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xa, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xb, acc[1][1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sW[wave][16 * i + 4 * e + lk][16 * j + l16] = acc[i][j][e];
+  __syncthreads();
+  for (int o = tid; o < QRS_ROWS * PAP_CB; o += PAP_THREADS) {
+    const int q = o % QRS_ROWS, c = o / QRS_ROWS;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < PAP_THREADS / 64; ++w) t += sW[w][q][c];
+    if (c0 + c < n) G[(int64_t)(c0 + c) * QRS_ROWS + q] = t;
+  }
+}
+
+// PQB pivots for the panel at p0 from the sample G(:, p0:n): column-pivoted
+// Householder QR of G (largest remaining column norm, ties to the lower
+// index; exact norms every step), then the same column swaps on A (all m
+// rows, in order) and on tk.piv.  One workgroup per task; G in LDS.
+__global__ __launch_bounds__(256) void k_qr_pick(const QrTask *__restrict__ tasks, int p0) {
+  __shared__ double sG[QRS_ROWS * QR_MAXN];
+  __shared__ double snrm[QR_MAXN];
+  __shared__ double sv[QRS_ROWS];
+  __shared__ int sswap[PQB];
+  __shared__ double s_tau;
+  const QrTask tk = tasks[blockIdx.x];
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  if (p0 >= n || *tk.rank <= p0) return;
+  const int nrem = n - p0, steps = min(PQB, nrem);
+  const double *G = tk.work + (int64_t)QRS_ROWS * m + (int64_t)p0 * QRS_ROWS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < QRS_ROWS * nrem; e += 256) sG[e] = G[e];
+  __syncthreads();
+  for (int t = 0; t < steps; ++t) {
+    for (int c = t + tid; c < nrem; c += 256) {
+      double ss = 0.0;
+      for (int i = t; i < QRS_ROWS; ++i) ss += sG[c * QRS_ROWS + i] * sG[c * QRS_ROWS + i];
+      snrm[c] = ss;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = nrem;
+      for (int c = t + lane; c < nrem; c += 64)
+        if (snrm[c] > best) {
+          best = snrm[c];
+          bi = c;
+        }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) sswap[t] = bi;
+    }
+    __syncthreads();
+    const int pcol = sswap[t];
+    if (pcol != t && tid < QRS_ROWS) {
+      const double a = sG[t * QRS_ROWS + tid];
+      sG[t * QRS_ROWS + tid] = sG[pcol * QRS_ROWS + tid];
+      sG[pcol * QRS_ROWS + tid] = a;
+    }
+    __syncthreads();
+    if (wave == 0) {  // reflector of column t, rows t .. QRS_ROWS - 1
+      const double x = lane < QRS_ROWS && lane >= t ? sG[t * QRS_ROWS + lane] : 0.0;
+      double ss = lane > t ? x * x : 0.0;
+      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+      const double alpha = __shfl(x, t);
+      double tau = 0.0, scale = 0.0;
+      if (ss > 0.0) {
+        const double nrm = sqrt(alpha * alpha + ss);
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (lane < QRS_ROWS) sv[lane] = lane > t ? x * scale : (lane == t ? 1.0 : 0.0);
+      if (lane == 0) s_tau = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    for (int c = t + 1 + tid; c < nrem; c += 256) {
+      double w = 0.0;
+      for (int i = t; i < QRS_ROWS; ++i) w += sv[i] * sG[c * QRS_ROWS + i];
+      for (int i = t; i < QRS_ROWS; ++i) sG[c * QRS_ROWS + i] -= tau * w * sv[i];
+    }
+    __syncthreads();
+  }
+  // the swaps on A and on the column order, in sequence
+  for (int t = 0; t < steps; ++t) {
+    const int pcol = sswap[t];
+    if (pcol != t) {
+      double *ca = tk.A + (int64_t)(p0 + t) * lda, *cb = tk.A + (int64_t)(p0 + pcol) * lda;
+      for (int r = tid; r < m; r += 256) {
+        const double a = ca[r];
+        ca[r] = cb[r];
+        cb[r] = a;
+      }
+      if (tid == 0) {
+        const int a = tk.piv[p0 + t];
+        tk.piv[p0 + t] = tk.piv[p0 + pcol];
+        tk.piv[p0 + pcol] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Truncation test after the panel at p0 (one workgroup per task): squared
+// norms r_i of the panel's rows of R (columns i .. n - 1) and of the
+// trailing block (from the column norms k_qr_apply left in tk.work), then
+// the first k (p0 <= k <= p0 + pb, k = 0 also tested on the first panel)
+// whose tail is <= tol; *tk.rank = k when found.  Fixed summation orders.
+__global__ __launch_bounds__(256) void k_qr_tail(const QrTask *__restrict__ tasks, int p0) {
+  __shared__ double red[256];
+  __shared__ double srow[PQB][17];
+  const QrTask tk = tasks[blockIdx.x];
+  const int m = tk.m, n = tk.n, lda = tk.lda;
+  if (p0 >= n || *tk.rank <= p0) return;
+  const int pb = min(PQB, n - p0), c1 = p0 + pb;
+  const int tid = threadIdx.x;
+  const double *cn = tk.work + (int64_t)QRS_ROWS * (m + n);
+  double t = 0.0;
+  for (int c = c1 + tid; c < n; c += 256) t += cn[c];
+  red[tid] = t;
+  // rows of R: thread (i, g) = (tid % 16, tid / 16) sums columns i + g, i + g + 16, ...
+  {
+    const int i = tid % PQB, g = tid / PQB;
+    double r = 0.0;
+    if (i < pb)
+      for (int c = p0 + i + g; c < n; c += 16) {
+        const double v = tk.A[(int64_t)c * lda + p0 + i];
+        r += v * v;
+      }
+    srow[i][g] = r;
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double ri[PQB];
+    for (int i = 0; i < PQB; ++i) {
+      double r = 0.0;
+      for (int g = 0; g < 16; ++g) r += srow[i][g];
+      ri[i] = r;
+    }
+    // tailsq[k - p0] = squared tail after k reflectors, k = p0 .. c1
+    double tailsq[PQB + 1];
+    double acc = red[0];
+    tailsq[pb] = acc;
+    for (int k = c1 - 1; k >= p0; --k) {
+      acc += ri[k - p0];
+      tailsq[k - p0] = acc;
+    }
+    const double tol2 = tk.tol * tk.tol;
+    int found = -1;
+    for (int k = (p0 == 0 ? p0 : p0 + 1); k <= c1 && found < 0; ++k)
+      if (tailsq[k - p0] <= tol2) found = k;
+    if (found >= 0) *tk.rank = found;
   }
 }
 
@@ -919,6 +1190,54 @@ int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool 
   return 0;
 }
 
+bool qrcp_panels_ok(int mmin, int mmax, int nmax) {
+  return qr_panels_ok(mmin, mmax, nmax) && nmax <= QR_MAXN;
+}
+
+int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hipStream_t st) {
+  if (ntask <= 0 || nmax <= 0) return 0;
+  if (mmax > PQ_MAXM || nmax > QR_MAXN) {
+    set_error("pivoted QR: %d x %d above %d x %d", mmax, nmax, PQ_MAXM, QR_MAXN);
+    return MVG_ERR_LIMIT;
+  }
+  const int rpt = (mmax + PQ_THREADS - 1) / PQ_THREADS;
+  hipLaunchKernelGGL(k_qr_rinit, dim3(ntask), dim3(256), 0, st, d_tasks);
+  if (int rc = check_launch("qr_rinit")) return rc;
+  for (int p0 = 0; p0 < nmax; p0 += PQB) {
+    const int sblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
+    hipLaunchKernelGGL(k_qr_sample, dim3(ntask * sblk), dim3(PAP_THREADS), 0, st, d_tasks, p0, sblk);
+    if (int rc = check_launch("qr_sample")) return rc;
+    hipLaunchKernelGGL(k_qr_pick, dim3(ntask), dim3(256), 0, st, d_tasks, p0);
+    if (int rc = check_launch("qr_pick")) return rc;
+    if (rpt == 1)
+      hipLaunchKernelGGL((k_qr_panel<1>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    else if (rpt == 2)
+      hipLaunchKernelGGL((k_qr_panel<2>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    else
+      hipLaunchKernelGGL((k_qr_panel<3>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    if (int rc = check_launch("qr_panel")) return rc;
+    const int rest = nmax - p0 - PQB;
+    if (rest > 0) {
+      const int nblk = (rest + PAP_CB - 1) / PAP_CB;
+      hipLaunchKernelGGL((k_qr_apply<0>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks,
+                         p0, nblk);
+      if (int rc = check_launch("qr_apply")) return rc;
+    }
+    hipLaunchKernelGGL(k_qr_tail, dim3(ntask), dim3(256), 0, st, d_tasks, p0);
+    if (int rc = check_launch("qr_tail")) return rc;
+  }
+  const int qb = (nmax + 63) / 64;
+  hipLaunchKernelGGL(k_qr_qinit, dim3(ntask * qb), dim3(256), 0, st, d_tasks, qb);
+  if (int rc = check_launch("qr_qinit")) return rc;
+  for (int p0 = ((nmax - 1) / PQB) * PQB; p0 >= 0; p0 -= PQB) {
+    const int nblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
+    hipLaunchKernelGGL((k_qr_apply<1>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks, p0,
+                       nblk);
+    if (int rc = check_launch("qr_apply")) return rc;
+  }
+  return 0;
+}
+
 int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st) {
   if (ntask <= 0) return 0;
   if (mmax > QR_MAXM) {
@@ -939,153 +1258,6 @@ int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st) {
   return check_launch("qr");
 }
 
-// ------------------------------------------------------- one-sided Jacobi
-//
-// Orthogonalises the columns of R (n x n, ldr) by plane rotations applied
-// on the right, R <- R J, accumulating J (n x n, ldj, starts at I).  Pairs
-// follow a round-robin tournament (n - 1 rounds of n / 2 disjoint pairs per
-// sweep), the waves share a round's pairs.  A pair is rotated when
-// |r_p . r_q| > n 2^-52 sqrt(|r_p|^2 |r_q|^2) (below that the inner product is
-// rounding noise); the sweeps stop after one without a rotation.
-// sig[i] = |column i of R J|.  Matrices with n <= JACOBI_LDS_N are worked on
-// in LDS and written back at the end.
-constexpr int JACOBI_LDS_N = 128;
-constexpr int JW = 8;  // waves per workgroup
-
-template <int E>  // n <= 64 E
-__device__ __forceinline__ void rotate_cols(double *p, double *q, int n, int lane, double cs,
-                                            double sn) {
-  double xp[E], xq[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = lane + 64 * e;
-    xp[e] = i < n ? p[i] : 0.0;
-    xq[e] = i < n ? q[i] : 0.0;
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = lane + 64 * e;
-    if (i < n) {
-      p[i] = cs * xp[e] - sn * xq[e];
-      q[i] = sn * xp[e] + cs * xq[e];
-    }
-  }
-}
-
-template <int E>
-__device__ __forceinline__ void jacobi_pair(double *rp, double *rq, double *jp, double *jq, int n,
-                                            int lane, double tol, int &any) {
-  double xp[E], xq[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = lane + 64 * e;
-    xp[e] = i < n ? rp[i] : 0.0;
-    xq[e] = i < n ? rq[i] : 0.0;
-  }
-  double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    a += xp[e] * xp[e];
-    b += xq[e] * xq[e];
-    g += xp[e] * xq[e];
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o);
-    b += __shfl_xor(b, o);
-    g += __shfl_xor(g, o);
-  }
-  if (!(fabs(g) > tol * sqrt(a * b)) || a == 0.0 || b == 0.0) return;
-  any = 1;
-  const double zeta = (b - a) / (2.0 * g);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = lane + 64 * e;
-    if (i < n) {
-      rp[i] = cs * xp[e] - sn * xq[e];
-      rq[i] = sn * xp[e] + cs * xq[e];
-    }
-  }
-  rotate_cols<E>(jp, jq, n, lane, cs, sn);
-}
-
-template <int E>
-__device__ void jacobi_sweeps(double *R, int ldr, double *J, int ldj, int n, int tid, int lane,
-                              int wave, int *changed) {
-  const int np = n + (n & 1);  // players; an odd n adds an idle one
-  const double tol = (double)(n > 1 ? n : 1) * 0x1p-52;
-  for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS; ++sweep) {
-    if (tid == 0) *changed = 0;
-    __syncthreads();
-    int any = 0;
-    for (int round = 0; round < np - 1; ++round) {
-      for (int pi = wave; pi < np / 2; pi += JW) {
-        int p, q;
-        if (pi == 0) {
-          p = round;
-          q = np - 1;
-        } else {
-          p = (round + pi) % (np - 1);
-          q = (round - pi + (np - 1)) % (np - 1);
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        if (q >= n) continue;
-        jacobi_pair<E>(R + (int64_t)p * ldr, R + (int64_t)q * ldr, J + (int64_t)p * ldj,
-                       J + (int64_t)q * ldj, n, lane, tol, any);
-      }
-      __syncthreads();
-    }
-    if (any && lane == 0) atomicOr(changed, 1);
-    __syncthreads();
-    if (!*changed) break;
-  }
-}
-
-__global__ __launch_bounds__(64 * JW) void k_jacobi(const SvdTask *__restrict__ tasks) {
-  __shared__ int changed;
-  __shared__ double sR[JACOBI_LDS_N * JACOBI_LDS_N];
-  const SvdTask tk = tasks[blockIdx.x];
-  const int n = tk.n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool in_lds = n <= JACOBI_LDS_N;
-  double *R = in_lds ? sR : tk.R;
-  const int ldr = in_lds ? n : tk.ldr;
-  double *J = tk.J;
-  const int ldj = tk.ldj;
-  if (in_lds)
-    for (int e = tid; e < n * n; e += 64 * JW) sR[e] = tk.R[(int64_t)(e / n) * tk.ldr + e % n];
-  for (int c = wave; c < n; c += JW)
-    for (int i = lane; i < n; i += 64) J[(int64_t)c * ldj + i] = (i == c) ? 1.0 : 0.0;
-  __syncthreads();
-  switch ((n + 63) / 64) {
-    case 1: jacobi_sweeps<1>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 2: jacobi_sweeps<2>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 3: jacobi_sweeps<3>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 4: jacobi_sweeps<4>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 5: jacobi_sweeps<5>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 6: jacobi_sweeps<6>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    case 7: jacobi_sweeps<7>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-    default: jacobi_sweeps<8>(R, ldr, J, ldj, n, tid, lane, wave, &changed); break;
-  }
-  for (int c = wave; c < n; c += JW) {
-    const double *rc = R + (int64_t)c * ldr;
-    double s = 0.0;
-    for (int i = lane; i < n; i += 64) s += rc[i] * rc[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) tk.sig[c] = sqrt(s);
-  }
-  if (in_lds) {
-    __syncthreads();
-    for (int e = tid; e < n * n; e += 64 * JW) tk.R[(int64_t)(e / n) * tk.ldr + e % n] = sR[e];
-  }
-}
-
-int launch_jacobi(const SvdTask *d_tasks, int ntask, hipStream_t st) {
-  if (ntask <= 0) return 0;
-  hipLaunchKernelGGL(k_jacobi, dim3(ntask), dim3(64 * JW), 0, st, d_tasks);
-  return check_launch("jacobi");
-}
 
 // -------------------------------------------------------- Gaussian sketch
 //
