@@ -364,6 +364,15 @@ int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0,
  * Returns 0, -1..-3, MVG_ERR_*. */
 int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_stream);
 
+/* Eq. (1) from a factored FP64 matrix (potrf_tiled): log|Sigma| = 2 sum
+ * log L_jj and Z^T Sigma^-1 Z = ||L^-1 Z||^2 with the same kernels as
+ * loglik, for a Z (device, p n_loc values) given after the factorisation
+ * (for instance Z = L eps from mvg_trmv on the same factor).  h_logdet and
+ * h_quad nullable.  Returns 0, -1 (not a factored FP64 matrix), -2, -3,
+ * MVG_ERR_*. */
+int mvg_mat_loglik(const mvg_mat *L, const double *d_z, double *h_loglik, double *h_logdet,
+                   double *h_quad, void *hip_stream);
+
 /* HBM bytes the library allocates for one likelihood evaluation of n_loc
  * locations with these options (matrix + workspaces), for admission control. */
 size_t mvg_footprint(int64_t n_loc, const mvg_opts *o);
@@ -451,11 +460,16 @@ void mvg_server_destroy(mvg_server *S);
  * generation), MVG_PROF_POTRF (whole factorisation), MVG_PROF_SOLVE (solve and
  * reductions), MVG_PROF_COKRIGE, MVG_PROF_LOWP (the FP32/BF16 off-band
  * update of the mixed-precision factorisation), MVG_PROF_IR (iterative
- * refinement of the mixed-precision solve).  *flops and *bytes are
- * algorithmic counts (useful work, no padding).  Synchronises the device. */
+ * refinement of the mixed-precision solve), MVG_PROF_TLRGEMM (every
+ * batched-GEMM launch of the TLR compression and factorisation, flops
+ * 2 M N K summed over its products), MVG_PROF_QR (the Householder QR launch
+ * groups of the TLR compression: the sketch QR, and the truncating pivoted
+ * QR; flops 4 m n^2 - 4 n^3 / 3 per unpivoted QR with its Q).  *flops and
+ * *bytes are algorithmic counts (useful work, no padding).  Synchronises the
+ * device. */
 enum { MVG_PROF_TRAILING = 0, MVG_PROF_GEN = 1, MVG_PROF_POTRF = 2, MVG_PROF_SOLVE = 3,
        MVG_PROF_COKRIGE = 4, MVG_PROF_LOWP = 5, MVG_PROF_IR = 6, MVG_PROF_SYRK = 7,
-       MVG_PROF_NKINDS = 8 };
+       MVG_PROF_TLRGEMM = 8, MVG_PROF_QR = 9, MVG_PROF_NKINDS = 10 };
 int mvg_prof_enable(int on);
 int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, double *bytes);
 

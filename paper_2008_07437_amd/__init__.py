@@ -13,6 +13,6 @@ from ._lib import (  # noqa: F401
     mle_fit, MleOpts,
     library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many,
     loglik_many_noalloc, tlr_compress,
-    cokrige_predict, mloe_mmom, mvg_footprint, mvg_dst_band, mvg_autotune_nb, MVG_NB_AUTO, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
+    cokrige_predict, mloe_mmom, mvg_footprint, mvg_mat_loglik, mvg_dst_band, mvg_autotune_nb, MVG_NB_AUTO, mvg_trmv, mvg_prof_enable, mvg_prof_read, mvg_ir_stats,
     Server, Result, REQ_LOGLIK, REQ_COKRIGE,
 )

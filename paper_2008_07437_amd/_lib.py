@@ -122,6 +122,7 @@ def _load():
         "mvg_prof_read": (c_int, [c_int, P, P, P, P]),
         "mvg_ir_stats": (c_int, [c_int, P, P, P]),
         "loglik_many": (c_int, [P, c_int, P, P, P, P, P]),
+        "mvg_mat_loglik": (c_int, [P, P, P, P, P, P]),
         "loglik_many_noalloc": (c_int, [P, c_int, P, P, P, P, P]),
         "mvg_server_create": (P, [ctypes.c_size_t, c_int, P]),
         "mvg_server_add_dataset": (c_int, [P, P, P, P, c_int64]),
@@ -279,6 +280,15 @@ def mvg_trmv(mat: "Mat", eps: torch.Tensor, stream=None) -> torch.Tensor:
     _check("mvg_trmv", _load().mvg_trmv(mat.handle, _dev_f64(eps, "eps"), c_void_p(z.data_ptr()),
                                        _stream(stream)))
     return z
+
+
+def mvg_mat_loglik(mat: "Mat", z: torch.Tensor, stream=None) -> dict:
+    """Eq. (1) from a factored FP64 matrix and Z (after the factorisation)."""
+    ll, ld, q = c_double(), c_double(), c_double()
+    _check("mvg_mat_loglik", _load().mvg_mat_loglik(mat.handle, _dev_f64(z, "z"), ctypes.byref(ll),
+                                                   ctypes.byref(ld), ctypes.byref(q),
+                                                   _stream(stream)))
+    return {"loglik": ll.value, "logdet": ld.value, "quad": q.value}
 
 
 def cov_generate(x, y, theta, opts=None, stream=None) -> Mat:
@@ -479,7 +489,7 @@ def mloe_mmom(x, y, theta, theta_a, x0, y0, opts=None, stream=None):
 
 
 PROF_KINDS = {"trailing": 0, "gen": 1, "potrf": 2, "solve": 3, "cokrige": 4, "lowp": 5, "ir": 6,
-              "syrk": 7}
+              "syrk": 7, "tlr_gemm": 8, "qr": 9}
 
 
 def mvg_prof_enable(on: bool = True):

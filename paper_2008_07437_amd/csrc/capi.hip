@@ -1496,6 +1496,41 @@ int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_strea
   return launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream);
 }
 
+int mvg_mat_loglik(const mvg_mat *L, const double *d_z, double *h_loglik, double *h_logdet,
+                   double *h_quad, void *hip_stream) {
+  if (!L || !L->factored || L->precision != MVG_FP64) return -1;
+  if (!d_z) return -2;
+  if (!h_loglik) return -3;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nred = (int)((L->N + 4095) / 4096);
+  double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2)
+  if (hipMallocAsync((void **)&ws, sizeof(double) * ((size_t)L->Np + 2 * nred + 2), st) !=
+      hipSuccess) {
+    hipGetLastError();
+    set_error("workspace allocation failed");
+    return MVG_ERR_ALLOC;
+  }
+  double *d_y = ws, *d_part = ws + L->Np, *d_out2 = d_part + 2 * nred;
+  hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)((L->Np + 255) / 256)), dim3(256), 0, st, d_z,
+                     L->N, d_y, L->Np);
+  int rc = check_launch("copy_pad");
+  if (!rc) rc = trsv_forward(L, d_y, st);
+  if (!rc) rc = logdet_quad(L, d_y, d_part, d_out2, st);
+  double out2[2] = {0.0, 0.0};
+  if (!rc) hipMemcpyAsync(out2, d_out2, sizeof(out2), hipMemcpyDeviceToHost, st);
+  hipFreeAsync(ws, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) {
+    set_error("stream synchronisation failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = MVG_ERR_LAUNCH;
+  }
+  if (rc) return rc;
+  *h_loglik = -(double)L->n_loc * (L->p / 2.0) * std::log(2.0 * M_PI) - 0.5 * out2[0] -
+              0.5 * out2[1];
+  if (h_logdet) *h_logdet = out2[0];
+  if (h_quad) *h_quad = out2[1];
+  return 0;
+}
+
 int mvg_mat_nvar(const mvg_mat *A) { return A ? A->p : -1; }
 
 int mvg_mat_shape(const mvg_mat *A, int64_t *n_loc, int *nb, int *ntiles, int *precision,

@@ -222,3 +222,21 @@ def test_cokrige_matches_oracle(lib, orc, nb):
     idx = np.array([0, 123, n - 1])
     zo = lib.cokrige_predict(F, _dev(x[idx]), _dev(y[idx])).cpu().numpy()
     np.testing.assert_allclose(zo, z.reshape(n, 2)[idx], rtol=1e-7, atol=1e-7)
+
+
+def test_mat_loglik_from_factor(lib, orc):
+    """Eq. (1) from an existing FP64 factor (mvg_mat_loglik): the same value
+    as loglik on the same inputs (same kernels, bitwise) and the oracle's
+    within 1e-9; Z drawn as L eps from that factor, as the benchmark does."""
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    x, y, _ = _data(orc, 700, 5, th, simulate=False)
+    X, Y = _dev(x), _dev(y)
+    A = lib.cov_generate(X, Y, th, {"nb": 256})
+    assert lib.potrf_tiled(A) == 0
+    z = lib.mvg_trmv(A, _dev(synthetic.normal_eps(1400, 5)))
+    got = lib.mvg_mat_loglik(A, z)
+    ref = lib.loglik(X, Y, z, th, {"nb": 256})
+    for key in ("loglik", "logdet", "quad"):
+        assert got[key] == ref[key][0], key
+    o = orc.loglik(x, y, z.cpu().numpy(), th)
+    assert abs(got["loglik"] - o["loglik"]) <= 1e-9 * abs(o["loglik"])
