@@ -476,7 +476,10 @@ int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, 
 /* Iterative refinement of the last mixed-precision loglik call on the
  * calling thread, theta index i: *iters = correction sweeps applied,
  * *relres = final ||Z - Sigma x|| / ||Z||, *converged = 1 if a stopping
- * criterion (residual or quadratic form) was met.
+ * criterion (residual or quadratic form) was met, -1 if the refinement
+ * stopped without meeting one (sweep budget or stagnation): loglik then
+ * evaluated that theta again in FP64 and returned the FP64 values (and, with
+ * keep, the FP64 factor).
  * Returns 0, or -1 if there is no such record. */
 int mvg_ir_stats(int i, int *iters, double *relres, int *converged);
 

@@ -545,7 +545,8 @@ def mvg_ir_stats(i: int = 0) -> dict:
     it, rel, conv = c_int(), c_double(), c_int()
     _check("mvg_ir_stats", _load().mvg_ir_stats(int(i), ctypes.byref(it), ctypes.byref(rel),
                                                  ctypes.byref(conv)))
-    return {"iters": it.value, "relres": rel.value, "converged": bool(conv.value)}
+    return {"iters": it.value, "relres": rel.value, "converged": conv.value == 1,
+            "fp64_fallback": conv.value == -1}
 
 
 class Result(ctypes.Structure):

@@ -36,16 +36,78 @@ int check_launch(const char *what) {
   return 0;
 }
 
+// The look-ahead stream of the calling thread (default priority), destroyed
+// when the thread exits.
+namespace {
+struct ThreadStream {
+  hipStream_t s = nullptr;
+  int dev = -1;
+  ~ThreadStream() {
+    if (s) hipStreamDestroy(s);
+  }
+};
+thread_local ThreadStream g_side;
+}  // namespace
+
 hipStream_t side_stream() {
-  static thread_local hipStream_t s = nullptr;
-  static thread_local int dev = -1;
   int cur = 0;
   hipGetDevice(&cur);
-  if (!s || dev != cur) {
-    hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
-    dev = cur;
+  if (!g_side.s || g_side.dev != cur) {
+    if (g_side.s) hipStreamDestroy(g_side.s);
+    hipStreamCreateWithFlags(&g_side.s, hipStreamNonBlocking);  // default priority
+    g_side.dev = cur;
   }
-  return s;
+  return g_side.s;
+}
+
+// Device memory of the library that outlives a call (tile arenas, per-matrix
+// buffers, factors) is allocated stream-ordered on a per-device release
+// stream, which is then synchronised (it is idle: the allocation is usable on
+// any stream at once), and freed stream-ordered on that stream once idle.
+// hipFree would wait for the whole device, i.e. for every other stream's
+// work, which serialises concurrent requests.
+static hipStream_t release_stream() {
+  static std::mutex mu;
+  static hipStream_t s[64] = {};
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!s[dev]) hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking);  // default priority
+  return s[dev];
+}
+
+void *dev_alloc(size_t bytes) {
+  void *p = nullptr;
+  hipStream_t r = release_stream();
+  if (hipMallocAsync(&p, bytes ? bytes : 8, r) != hipSuccess || hipStreamSynchronize(r) != hipSuccess) {
+    hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+// p idle (no work that uses it is pending)
+void dev_free(void *p) {
+  if (p) hipFreeAsync(p, release_stream());
+}
+
+// Records that the library's work on A so far is on stream st (for the
+// entry points that return before it completes), so that destroying A waits
+// for that work only.
+static int mark_done(const mvg_mat *A, hipStream_t st) {
+  if (!A->done && hipEventCreateWithFlags(&A->done, hipEventDisableTiming) != hipSuccess) {
+    A->done = nullptr;
+    hipGetLastError();
+    set_error("event creation failed");
+    return MVG_ERR_LAUNCH;
+  }
+  if (hipEventRecord(A->done, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("event record failed");
+    return MVG_ERR_LAUNCH;
+  }
+  return 0;
 }
 
 // ------------------------------------------------------------ profiling
@@ -59,13 +121,24 @@ static std::mutex g_prof_mu;
 static std::vector<ProfRec> g_prof;
 static bool g_prof_on = false;
 
+// Events are created once and reused across recording sessions (creating two
+// per record would cost more host time than the launches being timed).
+static std::vector<hipEvent_t> g_prof_events;
+
 int prof_begin(int kind, hipStream_t st, double flops, double bytes) {
   if (!g_prof_on) return -1;
-  ProfRec r{kind, nullptr, nullptr, flops, bytes};
-  hipEventCreate(&r.a);
-  hipEventCreate(&r.b);
-  hipEventRecord(r.a, st);
   std::lock_guard<std::mutex> lk(g_prof_mu);
+  const size_t need = 2 * (g_prof.size() + 1);
+  while (g_prof_events.size() < need) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      hipGetLastError();
+      return -1;
+    }
+    g_prof_events.push_back(e);
+  }
+  ProfRec r{kind, g_prof_events[need - 2], g_prof_events[need - 1], flops, bytes};
+  hipEventRecord(r.a, st);
   g_prof.push_back(r);
   return (int)g_prof.size() - 1;
 }
@@ -78,11 +151,7 @@ void prof_end(int h, hipStream_t st) {
 
 static void prof_clear() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  for (auto &r : g_prof) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
-  }
-  g_prof.clear();
+  g_prof.clear();  // the events stay for the next session
 }
 
 // ------------------------------------------------------------ arena pool
@@ -110,17 +179,16 @@ static void *arena_acquire(size_t bytes) {
         return p;
       }
   }
-  void *p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  void *p = dev_alloc(bytes);
+  if (!p) {
     // free the pool and retry once
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    for (auto &e : g_pool) hipFree(e.p);
-    g_pool.clear();
-    hipGetLastError();
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      hipGetLastError();
-      return nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_pool_mu);
+      for (auto &e : g_pool) dev_free(e.p);
+      g_pool.clear();
     }
+    hipStreamSynchronize(release_stream());  // the frees have returned their memory
+    p = dev_alloc(bytes);
   }
   return p;
 }
@@ -131,7 +199,7 @@ static void arena_release(void *p, size_t bytes) {
   hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_pool_mu);
   if (g_pool.size() >= POOL_MAX) {
-    hipFree(g_pool.front().p);
+    dev_free(g_pool.front().p);
     g_pool.erase(g_pool.begin());
   }
   g_pool.push_back({p, bytes, dev});
@@ -248,12 +316,13 @@ static void mat_free(mvg_mat *A) {
   if (!A) return;
   tlr_state_free(A->tlr);
   arena_release(A->arena, A->arena_bytes);
-  hipFree(A->d_off);
-  hipFree(A->d_kind);
-  hipFree(A->d_x);
-  hipFree(A->d_y);
-  hipFree(A->d_qtab);
-  hipFree(A->d_winv);
+  dev_free(A->d_off);
+  dev_free(A->d_kind);
+  dev_free(A->d_x);
+  dev_free(A->d_y);
+  dev_free(A->d_qtab);
+  dev_free(A->d_winv);
+  if (A->done) hipEventDestroy(A->done);
   delete[] A->h_off;
   delete[] A->h_kind;
   delete A;
@@ -368,12 +437,12 @@ static int mat_alloc(int64_t n_loc, int p, const mvg_opts &o, const double *d_x,
               A->h_kind, &A->arena_bytes, &zero_off);
   A->arena = (char *)arena_acquire(A->arena_bytes);
   bool ok = A->arena != nullptr;
-  ok = ok && hipMalloc(&A->d_off, sizeof(int64_t) * nt) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_kind, sizeof(int) * nt) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * (1 + PORD) * QN) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_winv, sizeof(double) * (size_t)A->Np * A->nb) == hipSuccess;
+  ok = ok && (A->d_off = (int64_t *)dev_alloc(sizeof(int64_t) * nt)) != nullptr;
+  ok = ok && (A->d_kind = (int *)dev_alloc(sizeof(int) * nt)) != nullptr;
+  ok = ok && (A->d_x = (double *)dev_alloc(sizeof(double) * n_loc)) != nullptr;
+  ok = ok && (A->d_y = (double *)dev_alloc(sizeof(double) * n_loc)) != nullptr;
+  ok = ok && (A->d_qtab = (double *)dev_alloc(sizeof(double) * (1 + PORD) * QN)) != nullptr;
+  ok = ok && (A->d_winv = (double *)dev_alloc(sizeof(double) * (size_t)A->Np * A->nb)) != nullptr;
   if (!ok) {
     hipGetLastError();
     set_error("device allocation of %.3f GB for a %lld-location matrix failed",
@@ -415,9 +484,9 @@ static int tlr_mat_create(int64_t n_loc, const mvg_opts &o, const mvg_theta *th,
     return rc;
   }
   A->tlr = new TlrState();
-  bool ok = hipMalloc(&A->d_x, sizeof(double) * n_loc) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_y, sizeof(double) * n_loc) == hipSuccess;
-  ok = ok && hipMalloc(&A->d_qtab, sizeof(double) * 4 * QN) == hipSuccess;
+  bool ok = (A->d_x = (double *)dev_alloc(sizeof(double) * n_loc)) != nullptr;
+  ok = ok && (A->d_y = (double *)dev_alloc(sizeof(double) * n_loc)) != nullptr;
+  ok = ok && (A->d_qtab = (double *)dev_alloc(sizeof(double) * 4 * QN)) != nullptr;
   if (!ok) {
     hipGetLastError();
     set_error("device allocation for a %lld-location TLR matrix failed", (long long)n_loc);
@@ -544,6 +613,11 @@ int cov_generate(const double *d_x, const double *d_y, int64_t n_loc, const mvg_
   mvg_mat *A = nullptr;
   if (int rc = mat_create(n_loc, d, th, d_x, d_y, st, &A)) return rc < 0 && rc > -100 ? -4 : rc;
   if (int rc = mat_generate(A, st)) {
+    mat_free(A);
+    return rc;
+  }
+  if (int rc = mark_done(A, st)) {
+    hipStreamSynchronize(st);
     mat_free(A);
     return rc;
   }
@@ -767,7 +841,7 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
   if (!rc && keep) {
     F = new mvg_factor();
     F->A = A;
-    if (hipMalloc((void **)&F->d_w, sizeof(double) * Np * 2) != hipSuccess) {
+    if (!(F->d_w = (double *)dev_alloc(sizeof(double) * Np * 2))) {
       hipGetLastError();
       rc = MVG_ERR_ALLOC;
       set_error("factor allocation failed");
@@ -785,7 +859,7 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
   mat_free(S);
   if (rc) {
     if (F) {
-      hipFree(F->d_w);
+      dev_free(F->d_w);
       delete F;
     }
     mat_free(A);
@@ -805,17 +879,41 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
       if (h_quad) h_quad[i] = out2[2 * i + 1];
     }
   }
-  if (F && info[0] == INT64_MAX) {
-    *keep = F;
-  } else {
-    if (F) {
-      hipFree(F->d_w);
-      delete F;
+  // a refinement that stopped without meeting a criterion (sweep budget or
+  // stagnation) leaves x = Sigma^-1 Z, and so the quadratic form and a kept
+  // factor's w, unconverged: that theta is evaluated again in FP64 (marked
+  // converged = -1 in mvg_ir_stats)
+  bool redo0 = false;
+  for (int i = 0; i < n_theta && !rc; ++i) {
+    if (info[i] != INT64_MAX || g_ir[i].converged) continue;
+    if (i == 0 && F) {
+      redo0 = true;
+      continue;
     }
-    if (keep) *keep = nullptr;
-    mat_free(A);
+    int64_t s1 = 0;
+    rc = loglik(d_x, d_y, d_z, n_loc, &th[i], 1, &d64, &h_loglik[i], h_logdet ? &h_logdet[i] : nullptr,
+                h_quad ? &h_quad[i] : nullptr, &s1, nullptr, st);
+    if (h_status) h_status[i] = s1;
+    g_ir[i].converged = -1;
   }
-  return 0;
+  if (F && info[0] == INT64_MAX && !redo0 && !rc) {
+    *keep = F;
+    return 0;
+  }
+  if (F) {
+    dev_free(F->d_w);
+    delete F;
+  }
+  if (keep) *keep = nullptr;
+  mat_free(A);
+  if (!rc && redo0) {  // n_theta == 1 with a kept factor: the FP64 factor instead
+    int64_t s1 = 0;
+    rc = loglik(d_x, d_y, d_z, n_loc, &th[0], 1, &d64, &h_loglik[0], h_logdet, h_quad, &s1, keep,
+                st);
+    if (h_status) h_status[0] = s1;
+    g_ir[0].converged = -1;
+  }
+  return rc;
 }
 
 static int run_small(const std::vector<SmallTask> &tasks, int64_t nmax, double *h_loglik,
@@ -879,9 +977,10 @@ int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *
 // Several theta as independent evaluations on concurrent streams (one host
 // thread and stream each, up to TLR_CONCURRENT at a time and as many as the
 // free device memory holds).  A TLR evaluation is bound by its column-by-
-// column critical path (one workgroup per tile QR), so several together fill
-// the device; each result is the one a single call gives.
-constexpr int TLR_CONCURRENT = 4;
+// column critical path (the compressions of a tile column, then a host
+// synchronisation for their ranks), so several together fill the device;
+// each result is the one a single call gives.
+constexpr int TLR_CONCURRENT = 8;
 
 static int loglik_concurrent(const double *d_x, const double *d_y, const double *d_z,
                              int64_t n_loc, const mvg_theta *th, int n_theta, const mvg_opts &d,
@@ -1082,7 +1181,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   if (!rc && keep) {
     F = new mvg_factor();
     F->A = A;
-    if (hipMalloc((void **)&F->d_w, sizeof(double) * A->Np * 2) != hipSuccess) {
+    if (!(F->d_w = (double *)dev_alloc(sizeof(double) * A->Np * 2))) {
       hipGetLastError();
       rc = MVG_ERR_ALLOC;
       set_error("factor allocation failed");
@@ -1100,7 +1199,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   }
   if (rc) {
     if (F) {
-      hipFree(F->d_w);
+      dev_free(F->d_w);
       delete F;
     }
     mat_free(A);
@@ -1122,7 +1221,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   }
   if (F) {
     if (info[0] != INT64_MAX) {  // a failed factor cannot predict
-      hipFree(F->d_w);
+      dev_free(F->d_w);
       delete F;
       mat_free(A);
       *keep = nullptr;
@@ -1161,6 +1260,11 @@ int cov_generate_p(const double *d_x, const double *d_y, int64_t n_loc, const mv
   mvg_mat *A = nullptr;
   if (int rc = mat_create_p(n_loc, d, th, d_x, d_y, st, &A)) return rc < 0 && rc > -100 ? -4 : rc;
   if (int rc = mat_generate(A, st)) {
+    mat_free(A);
+    return rc;
+  }
+  if (int rc = mark_done(A, st)) {
+    hipStreamSynchronize(st);
     mat_free(A);
     return rc;
   }
@@ -1493,7 +1597,8 @@ int mvg_trmv(const mvg_mat *L, const double *d_eps, double *d_z, void *hip_strea
   if (!L || !L->factored || L->precision != MVG_FP64) return -1;
   if (!d_eps) return -2;
   if (!d_z || d_z == d_eps) return -3;
-  return launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream);
+  if (int rc = launch_trmv(L, d_eps, d_z, (hipStream_t)hip_stream)) return rc;
+  return mark_done(L, (hipStream_t)hip_stream);
 }
 
 int mvg_mat_loglik(const mvg_mat *L, const double *d_z, double *h_loglik, double *h_logdet,
@@ -1551,15 +1656,19 @@ int mvg_mat_gather(const mvg_mat *A, const int64_t *d_rows, const int64_t *d_col
   if (!d_cols) return -3;
   if (m < 0) return -4;
   if (!d_out) return -5;
-  return launch_gather(A, d_rows, d_cols, m, d_out, (hipStream_t)hip_stream);
+  if (int rc = launch_gather(A, d_rows, d_cols, m, d_out, (hipStream_t)hip_stream)) return rc;
+  return mark_done(A, (hipStream_t)hip_stream);
 }
 
 int mvg_mat_to_dense(const mvg_mat *A, double *d_out, int64_t ld, void *hip_stream) {
   if (!A) return -1;
   if (!d_out) return -2;
   if (ld < A->N) return -3;
-  if (A->precision == MVG_TLR) return tlr_to_dense(A, d_out, ld, (hipStream_t)hip_stream);
-  return launch_to_dense(A, d_out, ld, (hipStream_t)hip_stream);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int rc = A->precision == MVG_TLR ? tlr_to_dense(A, d_out, ld, st)
+                                         : launch_to_dense(A, d_out, ld, st);
+  if (rc) return rc;
+  return mark_done(A, st);
 }
 
 const mvg_mat *mvg_factor_mat(const mvg_factor *F) { return F ? F->A : nullptr; }
@@ -1567,14 +1676,14 @@ const double *mvg_factor_w(const mvg_factor *F) { return F ? F->d_w : nullptr; }
 
 void mvg_mat_destroy(mvg_mat *A) {
   if (!A) return;
-  hipDeviceSynchronize();
+  if (A->done) hipEventSynchronize(A->done);  // the library's asynchronous work on A
   mat_free(A);
 }
 
 void mvg_factor_destroy(mvg_factor *F) {
   if (!F) return;
-  hipDeviceSynchronize();
-  hipFree(F->d_w);
+  if (F->A && F->A->done) hipEventSynchronize(F->A->done);
+  dev_free(F->d_w);
   mat_free(F->A);
   delete F;
 }

@@ -112,6 +112,7 @@ struct mvg_mat {
   mvg_theta_p theta_p{};
   mvg::MaternArgsP margs_p{};
   mvg::TlrState *tlr = nullptr;   // TLR storage (precision == MVG_TLR)
+  mutable hipEvent_t done = nullptr;  // after the library's last asynchronous work on it
   mvg::TileMap map() const { return mvg::TileMap{arena, d_off, d_kind, T, nb, T}; }
 };
 
@@ -215,8 +216,16 @@ SmallTask small_task(const double *x, const double *y, const double *z, int64_t 
 size_t small_workspace_doubles(int64_t nmax);
 int small_batch_workgroups(int ntask);
 
-// permanent second stream for look-ahead (default priority)
+// second stream of the calling thread for look-ahead (default priority)
 hipStream_t side_stream();
+
+// Library memory that outlives a call: stream-ordered allocation that is
+// usable on any stream when it returns (nullptr on failure), and a
+// stream-ordered free of idle memory (no device-wide wait, unlike hipFree).
+// Memory from hipMallocAsync on any stream may also be released with
+// dev_free once idle.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
 
 // event timing of launches (diagnostics); handles < 0 mean "not recording"
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);

@@ -115,10 +115,13 @@ int tlr_to_dense(const mvg_mat *A, double *out, int64_t ld, hipStream_t st);
 void tlr_state_free(TlrState *S);
 void store_free(TlrStore &S);
 
-// One pass of a TLR driver keeps its host task lists alive until the stream
-// is synchronised (asynchronous copies read them).
+// One pass of a TLR driver stages its host task lists to the device.  The
+// lists are copied into pinned host memory (a per-thread pool of
+// hipHostMalloc blocks), so the copies are asynchronous and the host can
+// build the next lists while the device works (a copy from pageable memory
+// would wait for the stream); release() synchronises the stream, frees the
+// device copies and returns the pinned memory to the pool.
 struct HostLists {
-  std::vector<std::vector<char>> keep;
   std::vector<void *> dev;  // device buffers to free at the end
   void *stage(const void *p, size_t bytes, hipStream_t st, int *rc);
   void release(hipStream_t st);

@@ -27,9 +27,51 @@ namespace mvg {
 
 constexpr int OVERSAMPLE = 16;
 
+// Pinned host blocks for staged task lists, per thread.  A thread drives one
+// stream at a time (every entry point synchronises its stream before it
+// returns), so once HostLists::release has synchronised that stream every
+// copy out of the pool has completed and the pool is rewound, also while
+// other HostLists of the thread keep their device copies.
+namespace {
+struct PinnedPool {
+  std::vector<std::pair<char *, size_t>> blocks;
+  size_t bi = 0, off = 0;
+  ~PinnedPool() {
+    for (auto &b : blocks) hipHostFree(b.first);
+  }
+  void *get(size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    while (bi < blocks.size() && off + bytes > blocks[bi].second) {
+      ++bi;
+      off = 0;
+    }
+    if (bi == blocks.size()) {
+      const size_t sz = std::max(bytes, (size_t)8 << 20);
+      char *p = nullptr;
+      if (hipHostMalloc((void **)&p, sz, hipHostMallocDefault) != hipSuccess) {
+        hipGetLastError();
+        return nullptr;
+      }
+      blocks.emplace_back(p, sz);
+      off = 0;
+    }
+    void *r = blocks[bi].first + off;
+    off += bytes;
+    return r;
+  }
+};
+thread_local PinnedPool g_pinned;
+}  // namespace
+
 void *HostLists::stage(const void *p, size_t bytes, hipStream_t st, int *rc) {
   if (bytes == 0) bytes = 8;
-  keep.emplace_back((const char *)p, (const char *)p + bytes);
+  void *h = g_pinned.get(bytes);
+  if (!h) {
+    set_error("TLR: pinned staging buffer of %zu bytes failed", bytes);
+    *rc = MVG_ERR_ALLOC;
+    return nullptr;
+  }
+  memcpy(h, p, bytes);
   void *d = nullptr;
   if (hipMallocAsync(&d, bytes, st) != hipSuccess) {
     hipGetLastError();
@@ -38,7 +80,7 @@ void *HostLists::stage(const void *p, size_t bytes, hipStream_t st, int *rc) {
     return nullptr;
   }
   dev.push_back(d);
-  if (hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+  if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
     hipGetLastError();
     set_error("TLR: staging copy failed");
     *rc = MVG_ERR_LAUNCH;
@@ -51,7 +93,8 @@ void HostLists::release(hipStream_t st) {
   for (void *d : dev) hipFreeAsync(d, st);
   dev.clear();
   hipStreamSynchronize(st);
-  keep.clear();
+  g_pinned.bi = 0;  // every staged copy of this thread has completed
+  g_pinned.off = 0;
 }
 
 static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t st) {
@@ -199,8 +242,8 @@ static int store_init(TlrStore &S, int T, int nb, int64_t N, hipStream_t st) {
 }
 
 void store_free(TlrStore &S) {
-  hipFree(S.diag);
-  hipFree(S.buf);
+  dev_free(S.diag);
+  dev_free(S.buf);
   S.diag = nullptr;
   S.buf = nullptr;
   S.cap = S.used = 0;
@@ -504,8 +547,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   store_free(Lf);
   if (int rc = store_init(Lf, T, nb, A->N, st)) return rc;
   if (!A->d_winv) {
-    if (hipMalloc((void **)&A->d_winv, sizeof(double) * (size_t)T * nbp * nbp) != hipSuccess) {
-      hipGetLastError();
+    if (!(A->d_winv = (double *)dev_alloc(sizeof(double) * (size_t)T * nbp * nbp))) {
       set_error("TLR: inverse diagonal tiles allocation failed");
       return MVG_ERR_ALLOC;
     }
@@ -642,13 +684,11 @@ int tlr_upload_meta(mvg_mat *A, hipStream_t st) {
     u[t] = Lf.uoff[t];
     r[t] = Lf.reff(t);
   }
-  hipFree(S->d_uoff);
-  hipFree(S->d_reff);
-  S->d_uoff = nullptr;
-  S->d_reff = nullptr;
-  if (hipMalloc((void **)&S->d_uoff, nt * 8) != hipSuccess ||
-      hipMalloc((void **)&S->d_reff, nt * 4) != hipSuccess) {
-    hipGetLastError();
+  dev_free(S->d_uoff);  // idle: the caller's stream has completed the earlier solves
+  dev_free(S->d_reff);
+  S->d_uoff = (int64_t *)dev_alloc(nt * 8);
+  S->d_reff = (int *)dev_alloc(nt * 4);
+  if (!S->d_uoff || !S->d_reff) {
     set_error("TLR: metadata allocation failed");
     return MVG_ERR_ALLOC;
   }
@@ -890,8 +930,8 @@ void tlr_state_free(TlrState *S) {
   if (!S) return;
   store_free(S->S);
   store_free(S->L);
-  hipFree(S->d_uoff);
-  hipFree(S->d_reff);
+  dev_free(S->d_uoff);
+  dev_free(S->d_reff);
   delete S;
 }
 

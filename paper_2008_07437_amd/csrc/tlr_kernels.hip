@@ -991,10 +991,15 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_sample(const QrTask *__restr
 // PQB pivots for the panel at p0 from the sample G(:, p0:n): column-pivoted
 // Householder QR of G (largest remaining column norm, ties to the lower
 // index; exact norms every step), then the same column swaps on A (all m
-// rows, in order) and on tk.piv.  One workgroup per task; G in LDS.
-__global__ __launch_bounds__(256) void k_qr_pick(const QrTask *__restrict__ tasks, int p0) {
-  __shared__ double sG[QRS_ROWS * QR_MAXN];
-  __shared__ double snrm[QR_MAXN];
+// rows, in order) and on tk.piv.  One workgroup per task; each thread keeps
+// the sample columns c = tid + 256 k in registers (QRS_ROWS values each).
+constexpr int PICK_THREADS = 256;
+constexpr int PICK_COLS = QR_MAXN / PICK_THREADS;  // columns per thread
+
+__global__ __launch_bounds__(PICK_THREADS) void k_qr_pick(const QrTask *__restrict__ tasks, int p0) {
+  __shared__ double s_best[PICK_THREADS / 64];
+  __shared__ int s_bidx[PICK_THREADS / 64];
+  __shared__ double scol[2][QRS_ROWS];  // the two columns of a swap
   __shared__ double sv[QRS_ROWS];
   __shared__ int sswap[PQB];
   __shared__ double s_tau;
@@ -1004,46 +1009,89 @@ __global__ __launch_bounds__(256) void k_qr_pick(const QrTask *__restrict__ task
   const int nrem = n - p0, steps = min(PQB, nrem);
   const double *G = tk.work + (int64_t)QRS_ROWS * m + (int64_t)p0 * QRS_ROWS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < QRS_ROWS * nrem; e += 256) sG[e] = G[e];
-  __syncthreads();
+  double g[PICK_COLS][QRS_ROWS];
+#pragma unroll
+  for (int k = 0; k < PICK_COLS; ++k) {
+    const int c = min(tid + PICK_THREADS * k, nrem - 1);
+#pragma unroll
+    for (int i = 0; i < QRS_ROWS; ++i) g[k][i] = G[(int64_t)c * QRS_ROWS + i];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < PICK_COLS; ++k)
+    if (tid + PICK_THREADS * k >= nrem)
+#pragma unroll
+      for (int i = 0; i < QRS_ROWS; ++i) g[k][i] = 0.0;
   for (int t = 0; t < steps; ++t) {
-    for (int c = t + tid; c < nrem; c += 256) {
+    // the thread's largest remaining norm (rows t ..), ties to the lower column
+    double best = -1.0;
+    int bi = nrem;
+#pragma unroll
+    for (int k = 0; k < PICK_COLS; ++k) {
+      const int c = tid + PICK_THREADS * k;
       double ss = 0.0;
-      for (int i = t; i < QRS_ROWS; ++i) ss += sG[c * QRS_ROWS + i] * sG[c * QRS_ROWS + i];
-      snrm[c] = ss;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = nrem;
-      for (int c = t + lane; c < nrem; c += 64)
-        if (snrm[c] > best) {
-          best = snrm[c];
-          bi = c;
-        }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
+#pragma unroll
+      for (int i = 0; i < QRS_ROWS; ++i)
+        if (i >= t) ss += g[k][i] * g[k][i];
+      if (c >= t && c < nrem && ss > best) {
+        best = ss;
+        bi = c;
       }
-      if (lane == 0) sswap[t] = bi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_best[wave] = best;
+      s_bidx[wave] = bi;
     }
     __syncthreads();
-    const int pcol = sswap[t];
-    if (pcol != t && tid < QRS_ROWS) {
-      const double a = sG[t * QRS_ROWS + tid];
-      sG[t * QRS_ROWS + tid] = sG[pcol * QRS_ROWS + tid];
-      sG[pcol * QRS_ROWS + tid] = a;
+    int pcol = s_bidx[0];
+    double pb = s_best[0];
+#pragma unroll
+    for (int w = 1; w < PICK_THREADS / 64; ++w)
+      if (s_best[w] > pb || (s_best[w] == pb && s_bidx[w] < pcol)) {
+        pb = s_best[w];
+        pcol = s_bidx[w];
+      }
+    if (tid == 0) sswap[t] = pcol;
+    // swap columns t and pcol through LDS (t < PQB: thread t, slot 0)
+    if (pcol != t) {
+#pragma unroll
+      for (int k = 0; k < PICK_COLS; ++k) {
+        const int c = tid + PICK_THREADS * k;
+        if (c == pcol)
+#pragma unroll
+          for (int i = 0; i < QRS_ROWS; ++i) scol[0][i] = g[k][i];
+        if (c == t)
+#pragma unroll
+          for (int i = 0; i < QRS_ROWS; ++i) scol[1][i] = g[k][i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PICK_COLS; ++k) {
+        const int c = tid + PICK_THREADS * k;
+        if (c == pcol)
+#pragma unroll
+          for (int i = 0; i < QRS_ROWS; ++i) g[k][i] = scol[1][i];
+        if (c == t)
+#pragma unroll
+          for (int i = 0; i < QRS_ROWS; ++i) g[k][i] = scol[0][i];
+      }
     }
-    __syncthreads();
-    if (wave == 0) {  // reflector of column t, rows t .. QRS_ROWS - 1
-      const double x = lane < QRS_ROWS && lane >= t ? sG[t * QRS_ROWS + lane] : 0.0;
-      double ss = lane > t ? x * x : 0.0;
-      for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-      const double alpha = __shfl(x, t);
+    // reflector of column t (rows t ..), by its owner: thread t, slot 0
+    if (tid == t) {
+      double ss = 0.0, alpha = 0.0;
+#pragma unroll
+      for (int i = 0; i < QRS_ROWS; ++i) {
+        if (i > t) ss += g[0][i] * g[0][i];
+        if (i == t) alpha = g[0][i];
+      }
       double tau = 0.0, scale = 0.0;
       if (ss > 0.0) {
         const double nrm = sqrt(alpha * alpha + ss);
@@ -1051,24 +1099,34 @@ __global__ __launch_bounds__(256) void k_qr_pick(const QrTask *__restrict__ task
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      if (lane < QRS_ROWS) sv[lane] = lane > t ? x * scale : (lane == t ? 1.0 : 0.0);
-      if (lane == 0) s_tau = tau;
+#pragma unroll
+      for (int i = 0; i < QRS_ROWS; ++i) sv[i] = i > t ? g[0][i] * scale : (i == t ? 1.0 : 0.0);
+      s_tau = tau;
     }
     __syncthreads();
     const double tau = s_tau;
-    for (int c = t + 1 + tid; c < nrem; c += 256) {
-      double w = 0.0;
-      for (int i = t; i < QRS_ROWS; ++i) w += sv[i] * sG[c * QRS_ROWS + i];
-      for (int i = t; i < QRS_ROWS; ++i) sG[c * QRS_ROWS + i] -= tau * w * sv[i];
+    double v[QRS_ROWS];
+#pragma unroll
+    for (int i = 0; i < QRS_ROWS; ++i) v[i] = sv[i];
+#pragma unroll
+    for (int k = 0; k < PICK_COLS; ++k) {
+      const int c = tid + PICK_THREADS * k;
+      if (c > t && c < nrem) {
+        double w = 0.0;
+#pragma unroll
+        for (int i = 0; i < QRS_ROWS; ++i) w += v[i] * g[k][i];
+#pragma unroll
+        for (int i = 0; i < QRS_ROWS; ++i) g[k][i] -= tau * w * v[i];
+      }
     }
-    __syncthreads();
+    __syncthreads();  // s_best, scol, sv and s_tau are rewritten next step
   }
   // the swaps on A and on the column order, in sequence
   for (int t = 0; t < steps; ++t) {
     const int pcol = sswap[t];
     if (pcol != t) {
       double *ca = tk.A + (int64_t)(p0 + t) * lda, *cb = tk.A + (int64_t)(p0 + pcol) * lda;
-      for (int r = tid; r < m; r += 256) {
+      for (int r = tid; r < m; r += PICK_THREADS) {
         const double a = ca[r];
         ca[r] = cb[r];
         cb[r] = a;
@@ -1207,7 +1265,7 @@ int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hip
     const int sblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
     hipLaunchKernelGGL(k_qr_sample, dim3(ntask * sblk), dim3(PAP_THREADS), 0, st, d_tasks, p0, sblk);
     if (int rc = check_launch("qr_sample")) return rc;
-    hipLaunchKernelGGL(k_qr_pick, dim3(ntask), dim3(256), 0, st, d_tasks, p0);
+    hipLaunchKernelGGL(k_qr_pick, dim3(ntask), dim3(PICK_THREADS), 0, st, d_tasks, p0);
     if (int rc = check_launch("qr_pick")) return rc;
     if (rpt == 1)
       hipLaunchKernelGGL((k_qr_panel<1>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);

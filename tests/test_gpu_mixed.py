@@ -135,6 +135,12 @@ def test_mixed_fp32x_loglik(lib, orc, a, nb):
 
 @pytest.mark.parametrize("a", [0.03, 0.1])
 def test_mixed_bf16_loglik(lib, orc, a):
+    """BF16 operands (FP32 storage) at n = 1000: the refined quadratic form
+    matches the oracle and the log-determinant is within 10x the oracle's
+    emulation of the same rounding points, but BF16 rounding (u = 2^-8) of
+    the off-band operands misses the 1e-6 target on the likelihood: the
+    regression bound 1e-4 is asserted, then the miss is reported as an
+    expected failure."""
     th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
     n, nb = 1000, 128
     x, y, z, ref, eld, einfo = _case(orc, n, 1, th, nb, 2, "bf16")
@@ -151,6 +157,8 @@ def test_mixed_bf16_loglik(lib, orc, a):
     assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
     assert abs(dld) <= 10.0 * abs(eld - ref["logdet"])
     assert dl <= 1e-4
+    if dl > 1e-6:
+        pytest.xfail("BF16 operands miss |delta loglik| <= 1e-6: %.2e" % dl)
 
 
 @pytest.mark.parametrize("mode", ["fp32", "fp32x"])
@@ -236,3 +244,33 @@ def test_mixed_factor_matches_emulation(lib, orc, prec, fmt, atol):
     _say("  %s factor max |gpu - emulated| %.2e" % (fmt, err))
     assert err <= atol
     assert np.max(np.abs(Lg[:, :128] - Le[:, :128])[:256]) <= 1e-12
+
+
+def test_mixed_unconverged_refinement_falls_back_to_fp64(lib, orc):
+    """A refinement that stops without meeting a criterion (here a budget of
+    one sweep and an unreachable tolerance) must not return its unconverged
+    quadratic form, nor a factor whose w is unconverged: loglik evaluates
+    that theta in FP64 instead (the FP64 values bitwise, and the FP64 factor
+    with keep), and mvg_ir_stats reports it."""
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    n, nb = 600, 128
+    x, y, z = _data(orc, n, 1, th)
+    X, Y, Z = _dev(x), _dev(y), _dev(z)
+    f64 = lib.loglik(X, Y, Z, th, {"nb": nb})
+    # BF16 operands: one sweep cannot reach the quadratic-form criterion either
+    o = {"nb": nb, "precision": lib.MVG_MIXED_BF16, "ir_max_iter": 1, "ir_tol": 1e-300}
+    got = lib.loglik(X, Y, Z, [th, th], o)
+    st = [lib.mvg_ir_stats(i) for i in range(2)]
+    assert all(s["fp64_fallback"] for s in st), st
+    for key in ("loglik", "logdet", "quad"):
+        assert got[key][0] == f64[key][0] and got[key][1] == f64[key][0], key
+    # with keep only the residual criterion applies
+    o = {"nb": nb, "precision": lib.MVG_MIXED_FP32, "ir_max_iter": 1, "ir_tol": 1e-300}
+    res, F = lib.loglik(X, Y, Z, th, o, keep=True)
+    assert lib.mvg_ir_stats(0)["fp64_fallback"]
+    assert res["loglik"][0] == f64["loglik"][0]
+    x0, y0 = synthetic.uniform_targets(7, 4)
+    _, F64 = lib.loglik(X, Y, Z, th, {"nb": nb}, keep=True)
+    a = lib.cokrige_predict(F, _dev(x0), _dev(y0)).cpu().numpy()
+    b = lib.cokrige_predict(F64, _dev(x0), _dev(y0)).cpu().numpy()
+    assert np.array_equal(a, b)

@@ -72,6 +72,13 @@ def test_mix_equals_alone_and_oracle(lib, orc):
     _say("  server stats", stats, "batch sizes", sorted({r.batch for r in res.values()}))
     assert max(r.batch for r in res.values()) > 1      # small requests were batched
     assert stats["hits"] >= 2                          # cokriging reused resident factors
+    # continuous batching, not a queue: admitted requests run at the same time
+    # (their [t_start, t_end] intervals on the server clock overlap)
+    iv = sorted((r.t_start, r.t_end) for r in res.values())
+    overlaps = sum(1 for i in range(len(iv)) for j in range(i + 1, len(iv))
+                   if iv[j][0] < iv[i][1] and iv[i][0] < iv[j][1])
+    _say("  overlapping request pairs: %d of %d requests" % (overlaps, len(iv)))
+    assert overlaps >= 1
     cache = {}
     for rid, kind, d, t, zh in reqs:
         r = res[rid]
