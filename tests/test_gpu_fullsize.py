@@ -202,35 +202,53 @@ def test_mixed_fullsize(lib, orc, nu1, nu2, beta, spd):
     assert worst <= 1e-10
 
 
-def test_mixed_fullsize_model_data(lib, orc):
-    """Mixed precision on Z = L eps at n = 50,000.  MVG_MIXED_FP32: the refined
-    quadratic form matches FP64; the log-determinant of the mixed factor
-    carries the FP32 rounding of the stored Schur complements and of the
-    off-band panel solves, biased low and growing with n: at this size it
-    misses |delta loglik| <= 1e-6 for every band width (a wider band only
-    narrows the miss; the bound asserted is the measured miss with margin,
-    so that a regression shows).  MVG_MIXED_FP32X (FP64 tiles and panel
-    solves, FP32 operands in the off-band GEMMs) meets 1e-6."""
-    n = 50000
-    x, y = _sites(orc, n, 1)
-    z = _model_z(lib, x, y, TH, 1)
-    d64 = lib.loglik(_dev(x), _dev(y), z, TH, {"nb": 1024})
-    assert d64["status"][0] == 0
-    for band in (2, 8):
-        r = lib.loglik(_dev(x), _dev(y), z, TH,
-                       {"nb": 1024, "precision": lib.MVG_MIXED_FP32, "band_tiles": band})
-        dl = abs(r["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
-        dq = abs(r["quad"][0] - d64["quad"][0]) / abs(d64["quad"][0])
-        _say("  model Z, FP32 band %d: status %d rel dloglik %.2e (dlogdet %.3e, rel dquad %.2e)"
-             % (band, r["status"][0], dl, r["logdet"][0] - d64["logdet"][0], dq))
-        assert r["status"][0] == 0
-        assert dq <= 1e-9
-        assert dl <= 1e-4
+_model = {}
+
+
+def _model_fp64(lib, orc):
+    """Z = L eps at n = 50,000 for the workload's theta and the FP64 result."""
+    if not _model:
+        n = 50000
+        x, y = _sites(orc, n, 1)
+        z = _model_z(lib, x, y, TH, 1)
+        d64 = lib.loglik(_dev(x), _dev(y), z, TH, {"nb": 1024})
+        assert d64["status"][0] == 0
+        _model.update(x=x, y=y, z=z, d64=d64)
+    return _model["x"], _model["y"], _model["z"], _model["d64"]
+
+
+def test_mixed_fp32x_fullsize_model_data(lib, orc):
+    """MVG_MIXED_FP32X (FP64 tiles and panel solves, FP32 operands in the
+    off-band GEMMs) on Z = L eps at n = 50,000 meets |delta loglik| <= 1e-6."""
+    x, y, z, d64 = _model_fp64(lib, orc)
     r = lib.loglik(_dev(x), _dev(y), z, TH, {"nb": 1024, "precision": lib.MVG_MIXED_FP32X})
     dl = abs(r["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
     _say("  model Z, FP32X band 2: status %d rel dloglik %.2e (dlogdet %.3e)"
          % (r["status"][0], dl, r["logdet"][0] - d64["logdet"][0]))
     assert r["status"][0] == 0 and dl <= 1e-6
+
+
+@pytest.mark.parametrize("band", [2, 8])
+def test_mixed_fp32_fullsize_model_data_expected_miss(lib, orc, band):
+    """MVG_MIXED_FP32 on Z = L eps at n = 50,000: the refined quadratic form
+    matches FP64 (1e-9), but the log-determinant of the mixed factor carries
+    the FP32 rounding of the stored Schur complements and of the off-band
+    panel solves, biased low and growing with n.  At this size it misses
+    |delta loglik| <= 1e-6 for every band width (measured 1.1e-5 at band 2,
+    5.0e-6 at band 8): the regression bound 1e-4 is asserted, then the cell
+    is reported as an expected failure of the 1e-6 target."""
+    x, y, z, d64 = _model_fp64(lib, orc)
+    r = lib.loglik(_dev(x), _dev(y), z, TH,
+                   {"nb": 1024, "precision": lib.MVG_MIXED_FP32, "band_tiles": band})
+    dl = abs(r["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
+    dq = abs(r["quad"][0] - d64["quad"][0]) / abs(d64["quad"][0])
+    _say("  model Z, FP32 band %d: status %d rel dloglik %.2e (dlogdet %.3e, rel dquad %.2e)"
+         % (band, r["status"][0], dl, r["logdet"][0] - d64["logdet"][0], dq))
+    assert r["status"][0] == 0
+    assert dq <= 1e-9
+    assert dl <= 1e-4
+    if dl > 1e-6:
+        pytest.xfail("FP32 storage misses |delta loglik| <= 1e-6 at n = 50,000: %.2e" % dl)
 
 
 def test_tlr_fullsize(lib, orc):
