@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the bivariate Matern log-likelihood hot path on one MI355X.
 
-One step = one likelihood evaluation l(theta) of the dense FP64 workload
-(N = 25,600 Morton-ordered jittered-grid locations, 51,200 x 51,200
-covariance: tile generation, tiled Cholesky, log-determinant, triangular
-solve) plus cokriging of 100 held-out locations on the resident factor.
-Inputs are synthetic and resident in HBM before the timed region.
-
-Prints one JSON line: evals/s, the Cholesky TFLOP/s, the roofline of the
-dominant kernel (trailing-update GEMM/SYRK on FP64 MFMA) from HIP events on
-the stream each launch runs on, and the CPU oracle timed on a bounded sample.
+Default line (the largest single-GPU workload): one step = one tile-low-rank
+likelihood evaluation l(theta) at N = 100,000 Morton-ordered jittered-grid
+locations (200,000 x 200,000 covariance, tile 1200, accuracy 1e-7, maximum
+rank 300): tile generation, compression, TLR Cholesky, log-determinant and
+solve.  Inputs (locations, Z = L eps drawn with the dense FP64 factor in the
+set-up) are resident in HBM before the timed region.  The same line carries
+the dense FP64 evaluation of the same inputs and the relative delta loglik,
+the ranks and the compressed-to-dense memory ratio, the roofline of the
+dominant kernel (HIP events on the stream each launch runs on), the dense
+FP64 workload (N = 25,600, tile size autotuned, cokriging of 100 targets) and
+the mixed-precision workload (N = 50,000, FP32 / FP32X against FP64) as
+nested records, and the CPU oracle timed on a bounded sample.  Other
+workloads: --workload dense | tlr | mixed | batched | serving | mloe |
+trivariate | mle.
 """
 import argparse
 import json
@@ -48,8 +53,12 @@ def measured_traffic(kernel: str, workload_tag: str):
 
 
 def cpu_baseline(n_full, sample_n, theta, seed):
-    """Oracle (as is) on the leading sample_n locations of the same workload,
-    scaled to evals/s at n_full by the O(n^3) cost of the factorisation."""
+    """The oracle (as is: plain C, OpenMP, FP64 Crout Cholesky) on the leading
+    sample_n locations of the same workload, timed on this host, scaled to
+    evals/s at n_full by the (2n)^3 / 3 cost of the factorisation that
+    dominates it.  The full-size oracle evaluation at n = 25,600 stored with
+    the golden values (timed once on the build host) is reported beside it
+    to show how well the cubic scaling holds there."""
     import numpy as np
 
     import oracle
@@ -62,11 +71,23 @@ def cpu_baseline(n_full, sample_n, theta, seed):
     oracle.loglik(x, y, z, theta)
     dt = time.perf_counter() - t0
     scale = (sample_n / n_full) ** 3
-    return {"value": scale / dt, "unit": "evals/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "one oracle loglik at N=%d (first %d Morton-ordered locations of the "
-                      "N=%d workload) took %.2f s; scaled by (%d/%d)^3" %
-                      (sample_n, sample_n, n_full, dt, sample_n, n_full)}
+    out = {"value": scale / dt, "unit": "evals/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": "one oracle loglik at N=%d (the first %d Morton-ordered locations of the "
+                     "N=%d workload) took %.2f s on %d host threads; scaled by (%d/%d)^3"
+                     % (sample_n, sample_n, n_full, dt, oracle.num_threads(), sample_n, n_full)}
+    gpath = os.path.join(ROOT, "tests", "golden", "dense_n25600.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        for key, case in sorted(g.get("cases", {}).items()):
+            out["full_size_reference"] = {
+                "n_loc": g["n_loc"], "seconds": case["oracle_seconds"],
+                "threads": case["oracle_threads"], "host": g["host"]["cpu"],
+                "extrapolated_from_this_sample_s": dt * (g["n_loc"] / sample_n) ** 3,
+                "note": "one full oracle evaluation at n = %d (%s) on the build host" %
+                        (g["n_loc"], key)}
+            break
+    return out
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -147,88 +168,289 @@ def _step(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def _plain(o):
+    """numpy scalars and arrays as JSON values."""
+    if isinstance(o, np.generic):
+        return o.item()
+    if isinstance(o, np.ndarray):
+        return o.tolist()
+    raise TypeError(type(o).__name__)
+
+
 def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
     out.update(extra)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_plain), flush=True)
 
 
-def run_tlr(args, mvg, dev, synthetic, torch):
-    """TLR likelihood on the N = 100,000 workload (200,000 x 200,000, tile
-    1200), beside one dense FP64 evaluation of the same inputs."""
-    n, nb = args.n, 1200
+def _prof(mvg, kinds):
+    return {k: mvg.mvg_prof_read(k) for k in kinds}
+
+
+def tlr_memory(ranks, nb, N):
+    """Compressed storage of the TLR Sigma (dense diagonal tiles, U and V per
+    off-diagonal tile, dense fall-back tiles nb^2) against the dense matrix."""
+    T = ranks.shape[0]
+    low = ranks[np.tril_indices(T, -1)]
+    comp = T * nb * nb + sum(nb * nb if k < 0 else 2 * nb * int(k) for k in low)
+    return {"compressed_gb": 8.0 * comp / 1e9, "dense_full_gb": 8.0 * N * N / 1e9,
+            "dense_lower_tiles_gb": 8.0 * T * (T + 1) / 2 * nb * nb / 1e9,
+            "ratio_full_over_tlr": float(N) * N / comp,
+            "ratio_lower_tiles_over_tlr": T * (T + 1) / 2 * nb * nb / comp}
+
+
+def tlr_record(args, mvg, dev, synthetic, torch, n, acc, steps, warmup, simplex=False):
+    """TLR likelihood on the N = n workload (2n x 2n, tile 1200, maximum rank
+    300): warm-up and timed evaluations, beside the dense FP64 evaluation of
+    the same inputs (the set-up factor: generation + Cholesky timed, then the
+    solve and log-determinant on that factor)."""
+    nb = 1200
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
-    # Z = L eps at the true theta from the FP64 factor (setup; 160 GB resident)
-    _step("tlr: Z = L eps from the FP64 factor, n=%d" % n)
+    # Z = L eps at the true theta from the FP64 factor (set-up; 160 GB resident),
+    # and the dense FP64 likelihood of the same inputs from that factor
+    _step("tlr: dense FP64 factor, Z = L eps, n=%d" % n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     A = mvg.cov_generate(xs, ys, th, {"nb": 1024})
     if mvg.potrf_tiled(A):
         raise SystemExit("Sigma(theta) not positive definite")
+    torch.cuda.synchronize()
+    t_fact = time.perf_counter() - t0
     z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ref = mvg.mvg_mat_loglik(A, z)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
     del A
-    ref = None
-    dense = {}
-    if not args.no_dense_ref:
-        _step("tlr: dense FP64 reference evaluation")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ref = mvg.loglik(xs, ys, z, th, {"nb": 1024})
-        torch.cuda.synchronize()
-        dense = {"evals_per_s": 1.0 / (time.perf_counter() - t0), "loglik": float(ref["loglik"][0])}
-    accs = [float(a) for a in args.accs.split(",")]
-    res = {}
-    for acc in accs:
-        o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300}
-        _step("tlr: acc %g, %d evaluation(s)" % (acc, max(1, args.steps)))
-        mvg.mvg_prof_enable(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(max(1, args.steps)):
-            r = mvg.loglik(xs, ys, z, th, o)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / max(1, args.steps)
-        pr = {k: mvg.mvg_prof_read(k) for k in ("gen", "potrf", "solve", "trailing")}
-        mvg.mvg_prof_enable(False)
-        rec = {"evals_per_s": 1.0 / dt, "s_per_eval": dt, "status": int(r["status"][0]),
-               "loglik": float(r["loglik"][0]),
-               "phases_ms_per_eval": {"compress": pr["gen"]["ms"] / max(1, args.steps),
-                                      "factor": pr["potrf"]["ms"] / max(1, args.steps),
-                                      "solve": pr["solve"]["ms"] / max(1, args.steps)},
-               "update_gemm_tflops": (pr["trailing"]["flops"] / (pr["trailing"]["ms"] * 1e-3) / 1e12
-                                      if pr["trailing"]["ms"] > 0 else None)}
-        if ref is not None:
-            rec["rel_dloglik_vs_fp64"] = abs(r["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0])
-        res["acc%g" % acc] = rec
-    simplex = None
-    if not args.no_simplex:  # the 7 points of a Nelder-Mead step in one call
+    dense = {"seconds": t_fact + t_solve, "evals_per_s": 1.0 / (t_fact + t_solve), "nb": 1024,
+             "loglik": ref["loglik"], "logdet": ref["logdet"], "quad": ref["quad"],
+             "cholesky_tflops": (2.0 * n) ** 3 / 3.0 / t_fact / 1e12}
+    o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300}
+    _step("tlr: acc %g, %d warm-up + %d timed evaluations" % (acc, warmup, steps))
+    for _ in range(warmup):
+        mvg.loglik(xs, ys, z, th, o)
+    torch.cuda.synchronize()
+    mvg.mvg_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = mvg.loglik(xs, ys, z, th, o)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pr = _prof(mvg, ("gen", "potrf", "solve", "trailing", "tlr_gemm", "qr"))
+    mvg.mvg_prof_enable(False)
+    per = lambda k: pr[k]["ms"] / steps   # noqa: E731
+    rec = {"evals_per_s": 1.0 / dt, "s_per_eval": dt, "status": int(r["status"][0]),
+           "loglik": float(r["loglik"][0]), "logdet": float(r["logdet"][0]),
+           "quad": float(r["quad"][0]),
+           "rel_dloglik_vs_fp64": abs(r["loglik"][0] - ref["loglik"]) / abs(ref["loglik"]),
+           "rel_dlogdet_vs_fp64": abs(r["logdet"][0] - ref["logdet"]) / abs(ref["logdet"]),
+           "rel_dquad_vs_fp64": abs(r["quad"][0] - ref["quad"]) / abs(ref["quad"]),
+           "speedup_vs_dense_fp64": dense["seconds"] / dt,
+           "phases_ms_per_eval": {"compress": per("gen"), "factor": per("potrf"),
+                                  "solve": per("solve"), "update_gemm": per("trailing"),
+                                  "all_batched_gemm": per("tlr_gemm"), "qr": per("qr")},
+           "update_gemm_tflops": (pr["trailing"]["flops"] / (pr["trailing"]["ms"] * 1e-3) / 1e12
+                                  if pr["trailing"]["ms"] > 0 else None)}
+    # dominant kernel: the batched GEMM (one launch per run, algorithmic 2MNK)
+    # against the QR launch groups
+    g, q = pr["tlr_gemm"], pr["qr"]
+    ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
+    roof = {"kernel": "k_gemm_batched", "bound": "mfma", "achieved": ach,
+            "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP64_MFMA_PEAK_TFLOPS if ach else None,
+            "traffic": measured_traffic("k_gemm_batched", "tlr_n%d_nb%d" % (n, nb)),
+            "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
+            "flops_per_launch": g["flops"] / max(1, g["launches"]),
+            "share_of_eval": g["ms"] / steps / (1e3 * dt),
+            "qr_groups_share_of_eval": q["ms"] / steps / (1e3 * dt)}
+    _, ranks = mvg.tlr_compress(xs, ys, th, {"nb": nb, "tlr_acc": acc, "tlr_max_rank": 300})
+    T = ranks.shape[0]
+    low = ranks[np.tril_indices(T, -1)]
+    rk = {"acc": acc, "median_offset1": int(np.median(np.diag(ranks, -1))),
+          "median_all": int(np.median(low[low >= 0])) if (low >= 0).any() else None,
+          "max": int(low.max()), "dense_tiles": int((low < 0).sum()), "tiles": int(low.size)}
+    out = {"n_loc": n, "nb": nb, "acc": acc, "tlr": rec, "dense_fp64": dense, "ranks": rk,
+           "memory": tlr_memory(ranks, nb, 2 * n), "roofline": roof}
+    if simplex:  # the 7 points of a Nelder-Mead step in one call
         pts = synthetic.nelder_mead_simplex(th)
         _step("tlr: %d simplex points in one call" % len(pts))
-        o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": accs[0], "tlr_max_rank": 300}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r7 = mvg.loglik(xs, ys, z, pts, o)
         torch.cuda.synchronize()
         dt7 = time.perf_counter() - t0
-        simplex = {"points": len(pts), "seconds": dt7, "evals_per_s": len(pts) / dt7,
-                   "vs_one_at_a_time": (len(pts) / dt7) / res["acc%g" % accs[0]]["evals_per_s"],
-                   "failed": int((r7["status"] != 0).sum())}
-    _, ranks = mvg.tlr_compress(xs, ys, th, {"nb": nb, "tlr_acc": accs[0], "tlr_max_rank": 300})
-    T = ranks.shape[0]
-    low = ranks[np.tril_indices(T, -1)]
-    head = res["acc%g" % accs[0]]
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
-          head["evals_per_s"], "evals/s", max(1, args.steps), 0, 1e3 * head["s_per_eval"], "f64",
-          {"workload": "TLR bivariate Matern loglik, N=%d locations (%dx%d), tile %d, acc %s, "
-                       "max rank 300, theta=(1,1,%g,0.5,1,0.5)" % (n, 2 * n, 2 * n, nb, args.accs,
-                                                                   args.a),
-           "n_loc": n, "nb": nb, "precision": "tlr"},
-          tlr=res, dense_fp64=dense, simplex7=simplex,
-          ranks={"acc": accs[0], "median_offset1": int(np.median(np.diag(ranks, -1))),
-                 "median_all": int(np.median(low[low >= 0])) if (low >= 0).any() else None,
-                 "dense_tiles": int((low < 0).sum()), "tiles": int(low.size)})
+        out["simplex7"] = {"points": len(pts), "seconds": dt7, "evals_per_s": len(pts) / dt7,
+                           "vs_one_at_a_time": (len(pts) / dt7) * dt,
+                           "failed": int((r7["status"] != 0).sum())}
+    return out
+
+
+METRIC = "loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency"
+
+
+def run_tlr(args, mvg, dev, synthetic, torch):
+    """TLR alone (any n / accuracy), with the simplex in one call."""
+    acc = float(args.accs.split(",")[0])
+    rec = tlr_record(args, mvg, dev, synthetic, torch, args.n, acc, max(1, args.steps),
+                     args.warmup, simplex=not args.no_simplex)
+    _line(METRIC, rec["tlr"]["evals_per_s"], "evals/s", max(1, args.steps), args.warmup,
+          1e3 * rec["tlr"]["s_per_eval"], "f64",
+          {"workload": "TLR bivariate Matern loglik, N=%d locations (%dx%d), tile 1200, acc %g, "
+                       "max rank 300, theta=(1,1,%g,0.5,1,0.5)" % (args.n, 2 * args.n, 2 * args.n,
+                                                                   acc, args.a),
+           "n_loc": args.n, "nb": 1200, "precision": "tlr"},
+          roofline=rec["roofline"], **{k: v for k, v in rec.items() if k != "roofline"})
+
+
+def dense_record(args, mvg, dev, synthetic, torch, n, steps, warmup, tune_set):
+    """Dense FP64 likelihood + cokriging of args.targets locations on the
+    N = n workload; tile size by the library's autotuner over tune_set."""
+    th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    _step("dense: Z = L eps, n=%d" % n)
+    A = mvg.cov_generate(xs, ys, th, {"nb": 1024})
+    info = mvg.potrf_tiled(A)
+    if info:
+        raise SystemExit("Sigma(theta) not positive definite at pivot %d" % info)
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    del A
+    tuned = None
+    nb = args.nb
+    if not nb:  # the library's autotuner picks the tile size on this problem (set-up)
+        _step("dense: autotuning the tile size over %s" % (tune_set,))
+        nb, tuned = mvg.mvg_autotune_nb(xs, ys, z, th, {}, list(tune_set))
+    x0r, y0r = synthetic.uniform_targets(args.targets, args.seed)
+    x0, y0 = dev(x0r), dev(y0r)
+    opts = {"nb": nb}
+    last = {}
+
+    def step():
+        res, F = mvg.loglik(xs, ys, z, th, opts, keep=True)
+        mvg.cokrige_predict(F, x0, y0)
+        last["loglik"] = float(res["loglik"][0])
+        del F
+
+    _step("dense: nb %d, %d warm-up + %d timed steps" % (nb, warmup, steps))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    mvg.mvg_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = _prof(mvg, ("trailing", "gen", "potrf", "solve", "cokrige"))
+    mvg.mvg_prof_enable(False)
+    N = 2 * n
+    potrf_ms = prof["potrf"]["ms"] / max(1, prof["potrf"]["launches"])
+    tr = prof["trailing"]
+    achieved = tr["flops"] / (tr["ms"] * 1e-3) / 1e12 if tr["ms"] > 0 else None
+    return {"workload": "dense FP64 bivariate Matern loglik + cokriging, N=%d locations (%dx%d), "
+                        "theta=(1,1,%g,0.5,1,0.5), nb=%d, %d targets"
+                        % (n, N, N, args.a, nb, args.targets),
+            "n_loc": n, "nb": nb, "steps": steps, "warmup": warmup,
+            "evals_per_s": steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "cholesky_tflops": N ** 3 / 3.0 / (potrf_ms * 1e-3) / 1e12,
+            "phases_ms_per_step": {k: prof[k]["ms"] / max(1, steps)
+                                   for k in ("gen", "potrf", "solve", "cokrige")},
+            "loglik": last["loglik"],
+            "autotune_seconds_per_eval": ({str(k): v for k, v in tuned.items()} if tuned else None),
+            "roofline": {"kernel": "k_update_trailing", "bound": "mfma", "achieved": achieved,
+                         "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
+                         "traffic": measured_traffic("k_update_trailing<%d, 0>" % nb,
+                                                     "cfg1_n%d_nb%d" % (n, nb)),
+                         "launches": tr["launches"],
+                         "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
+                         "flops_per_launch": tr["flops"] / max(1, tr["launches"])}}, (xs, ys, z, th)
+
+
+def mixed_record(args, mvg, dev, synthetic, torch, n, nu, beta, reps=1):
+    """Mixed precision on the N = n workload (theta = (1, 1, 0.1, nu11, nu22,
+    beta), Z = L eps): FP64 (set-up factor, then timed evaluations), FP32X and
+    FP32 storage with a 2-tile FP64 band; evals/s, relative delta loglik and
+    delta log|Sigma| against FP64 on the same inputs."""
+    th = (1.0, 1.0, 0.1, nu[0], nu[1], beta)
+    nb = 1024
+    xr, yr = synthetic.jittered_grid(n, args.seed)
+    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+    _step("mixed: Z = L eps, n=%d, nu=%s, beta=%g" % (n, nu, beta))
+    A = mvg.cov_generate(xs, ys, th, {"nb": nb})
+    if mvg.potrf_tiled(A):
+        raise SystemExit("Sigma(theta) not positive definite")
+    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+    del A
+    out = {"n_loc": n, "theta": th, "nb": nb, "band_tiles": 2}
+    ref = None
+    for name, prec in (("fp64", mvg.MVG_FP64), ("fp32x", mvg.MVG_MIXED_FP32X),
+                       ("fp32", mvg.MVG_MIXED_FP32)):
+        o = {"nb": nb, "precision": prec, "band_tiles": 2}
+        mvg.loglik(xs, ys, z, th, o)   # warm-up (arena sizes)
+        torch.cuda.synchronize()
+        mvg.mvg_prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = mvg.loglik(xs, ys, z, th, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        pr = _prof(mvg, ("potrf", "lowp", "trailing"))
+        mvg.mvg_prof_enable(False)
+        rec = {"evals_per_s": 1.0 / dt, "status": int(r["status"][0]),
+               "loglik": float(r["loglik"][0])}
+        if prec == mvg.MVG_FP64:
+            ref = r
+        elif int(r["status"][0]) == 0:
+            rec["rel_dloglik_vs_fp64"] = abs(r["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0])
+            rec["dlogdet_vs_fp64"] = float(r["logdet"][0] - ref["logdet"][0])
+            rec["rel_dquad_vs_fp64"] = abs(r["quad"][0] - ref["quad"][0]) / abs(ref["quad"][0])
+            rec["meets_1e-6"] = bool(rec["rel_dloglik_vs_fp64"] <= 1e-6)
+            rec["speedup_vs_fp64"] = out["fp64"]["evals_per_s"] and rec["evals_per_s"] / out["fp64"]["evals_per_s"]
+            lp = pr["lowp"]
+            if lp["ms"] > 0:
+                ach = lp["flops"] / (lp["ms"] * 1e-3) / 1e12
+                rec["offband_gemm"] = {"achieved": ach, "peak": FP32_MFMA_PEAK_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": ach / FP32_MFMA_PEAK_TFLOPS}
+        out[name] = rec
+    return out
+
+
+def run_headline(args, mvg, dev, synthetic, torch):
+    """The default line: TLR at N = 100,000 (the largest single-GPU workload)
+    with the dense FP64 workload (N = 25,600) and the mixed-precision workload
+    (N = 50,000) as nested records, and the CPU oracle."""
+    n = args.n or 100000
+    acc = float(args.accs.split(",")[0])
+    rec = tlr_record(args, mvg, dev, synthetic, torch, n, acc, args.steps, args.warmup,
+                     simplex=args.simplex)
+    cfg1 = cfg2 = None
+    if not args.no_nested:
+        cfg1, _ = dense_record(args, mvg, dev, synthetic, torch, 25600, args.nested_steps, 1,
+                               (256, 512, 768))
+        cfg2 = mixed_record(args, mvg, dev, synthetic, torch, 50000, (0.5, 1.0), 0.5)
+    cpu = None
+    if not args.no_cpu:
+        _step("oracle timing on the host (bounded sample)")
+        cpu = cpu_baseline(n, args.cpu_sample_n, (1.0, 1.0, args.a, 0.5, 1.0, 0.5), args.seed)
+    t = rec["tlr"]
+    _line(METRIC, t["evals_per_s"], "evals/s", args.steps, args.warmup, 1e3 * t["s_per_eval"],
+          "f64",
+          {"workload": "TLR bivariate parsimonious Matern loglik (generation, compression, TLR "
+                       "Cholesky, log-determinant, solve), N=%d locations (%dx%d), tile 1200, "
+                       "acc %g, max rank 300, theta=(1,1,%g,0.5,1,0.5), Z = L eps"
+                       % (n, 2 * n, 2 * n, acc, args.a),
+           "n_loc": n, "nb": 1200, "precision": "tlr", "parallelism": "single GPU"},
+          roofline=rec["roofline"], cpu_baseline=cpu,
+          tlr=t, dense_fp64=rec["dense_fp64"], ranks=rec["ranks"], memory=rec["memory"],
+          simplex7=rec.get("simplex7"), dense_n25600=cfg1, mixed_n50000=cfg2)
 
 
 def run_batched(args, mvg, dev, synthetic, torch):
@@ -265,7 +487,7 @@ def run_batched(args, mvg, dev, synthetic, torch):
     t2 = time.perf_counter()
     mvg.loglik(xs, ys, z, simplex, {"nb": 128})
     torch.cuda.synchronize()
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+    _line(METRIC,
           args.batch / dt, "evals/s", args.steps, warm, 1e3 * dt, "f64",
           {"workload": "batched FP64 loglik, %d theta (+-20%% around (1,1,0.1,0.5,1,0.5)) on "
                        "N=%d locations (%dx%d), one persistent launch" % (args.batch, n, 2 * n, 2 * n),
@@ -299,7 +521,7 @@ def run_mloe(args, mvg, dev, synthetic, torch):
     mvg.mvg_prof_enable(False)
     gen, fac, sol = (mvg.mvg_prof_read(k) for k in ("gen", "potrf", "solve"))
     per = lambda p: p["ms"] / args.steps   # noqa: E731
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+    _line(METRIC,
           1.0 / dt, "MLOE/MMOM evals/s", args.steps, args.warmup, 1e3 * dt, "f64",
           {"workload": "multivariate MLOE/MMOM, N=%d locations (%dx%d), %d targets, nb %d, "
                        "theta_a = theta perturbed by 3-8%%" % (n, 2 * n, 2 * n, m, args.nb),
@@ -343,7 +565,7 @@ def run_trivariate(args, mvg, dev, synthetic, torch):
     t1 = time.perf_counter()
     prof_ll = mvg.profile_loglik_p(xs, ys, z, th, o)
     torch.cuda.synchronize()
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+    _line(METRIC,
           1.0 / dt, "evals/s", args.steps, args.warmup, 1e3 * dt, "f64",
           {"workload": "trivariate parsimonious Matern loglik, N=%d locations (%dx%d), nb %d"
                        % (n, N, N, args.nb), "n_loc": n, "p": 3, "precision": "fp64"},
@@ -356,35 +578,76 @@ def run_trivariate(args, mvg, dev, synthetic, torch):
 
 def run_mle(args, mvg, dev, synthetic, torch):
     """Maximum likelihood at the shape of the synthetic estimation study
-    (Section 6.4.1, Experiment 2: 22,464 sampled locations, a = 0.09, nu11 =
-    0.5, nu22 = 1): Nelder-Mead from a perturbed start, a bounded number of
-    exact FP64 evaluations (one fit needs a few hundred)."""
-    n = args.n
-    th = (1.0, 1.0, 0.09, 0.5, 1.0, 0.5)
-    start = (1.2, 0.8, 0.12, 0.6, 0.9, 0.3)
-    xr, yr = synthetic.jittered_grid(n, args.seed)
-    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
-    A = mvg.cov_generate(xs, ys, th, {"nb": args.nb})
-    if mvg.potrf_tiled(A):
-        raise SystemExit("Sigma(theta) not positive definite")
-    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
-    del A
-    o = {"nb": args.nb}
-    l_true = float(mvg.loglik(xs, ys, z, th, o)["loglik"][0])
-    l_start = float(mvg.loglik(xs, ys, z, start, o)["loglik"][0])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fit = mvg.mle_fit(xs, ys, z, start, o, max_evals=args.max_evals)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
-          fit["evals"] / dt, "evals/s", fit["evals"], 0, 1e3 * dt / fit["evals"], "f64",
-          {"workload": "Nelder-Mead MLE, N=%d locations (%dx%d), nb %d, FP64, %d evaluations"
-                       % (n, 2 * n, 2 * n, args.nb, args.max_evals), "n_loc": n,
-           "precision": "fp64"},
-          fit_seconds=dt, theta_start=start, theta_true=th, theta_hat=fit["theta"],
-          loglik_start=l_start, loglik_true=l_true, loglik_hat=fit["loglik"],
-          converged=fit["converged"], iterations=fit["iters"])
+    (Section 6.4.1, Experiment 2): 22,464 + 2,500 jittered-grid locations,
+    Z = L eps simulated jointly at theta = (1, 1, a, 0.5, 1, 0.5) for each a in
+    --mle-as (0.03, 0.09, 0.2); theta estimated from the 22,464 by the
+    library's Nelder-Mead driver (exact FP64 likelihoods) from a perturbed
+    start, run in chunks of --mle-chunk evaluations restarted from the best
+    point (a restarted Nelder-Mead; each chunk reports its progress) until a
+    chunk converges or --max-evals is spent; the 2,500 held-out locations are
+    then predicted by cokriging with theta-hat and with the true theta."""
+    n_fit, n_hold = 22464, 2500
+    n = n_fit + n_hold
+    nb = args.nb
+    recs = []
+    for a in [float(v) for v in args.mle_as.split(",")]:
+        th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
+        start = (1.2, 0.8, 1.3 * a, 0.6, 0.9, 0.3)
+        xr, yr = synthetic.jittered_grid(n, args.seed)
+        _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
+        _step("mle a=%g: Z = L eps on %d locations" % (a, n))
+        A = mvg.cov_generate(xs, ys, th, {"nb": nb})
+        if mvg.potrf_tiled(A):
+            raise SystemExit("Sigma(theta) not positive definite")
+        z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+        del A
+        hold = np.sort(synthetic.rng(args.seed, 6).permutation(n)[:n_hold])
+        fit_idx = np.setdiff1d(np.arange(n), hold)
+        hi = torch.as_tensor(hold).cuda()
+        fi = torch.as_tensor(fit_idx).cuda()
+        zz = z.view(n, 2)
+        xf, yf = xs[fi].contiguous(), ys[fi].contiguous()
+        zf = zz[fi].reshape(-1).contiguous()
+        x0, y0 = xs[hi].contiguous(), ys[hi].contiguous()
+        z0 = zz[hi].cpu().numpy()
+        o = {"nb": nb}
+        l_true = float(mvg.loglik(xf, yf, zf, th, o)["loglik"][0])
+        cur = start
+        evals = 0
+        best = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while evals < args.max_evals:
+            fit = mvg.mle_fit(xf, yf, zf, cur, o, max_evals=min(args.mle_chunk,
+                                                                args.max_evals - evals))
+            evals += fit["evals"]
+            best = fit
+            cur = fit["theta"]
+            _step("mle a=%g: %d evaluations, loglik %.3f (true theta %.3f), theta %s%s"
+                  % (a, evals, fit["loglik"], l_true, np.round(cur, 4).tolist(),
+                     ", converged" if fit["converged"] else ""))
+            if fit["converged"]:
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mspe = {}
+        for tag, t in (("theta_hat", best["theta"]), ("theta_true", th)):
+            _, F = mvg.loglik(xf, yf, zf, t, o, keep=True)
+            zh = mvg.cokrige_predict(F, x0, y0).cpu().numpy().reshape(n_hold, 2)
+            del F
+            mspe[tag] = [float(np.mean((zh[:, j] - z0[:, j]) ** 2)) for j in range(2)]
+        recs.append({"a": a, "theta_true": th, "theta_start": start, "theta_hat": best["theta"],
+                     "loglik_hat": best["loglik"], "loglik_true": l_true,
+                     "converged": best["converged"], "evals": evals, "seconds": dt,
+                     "evals_per_s": evals / dt, "mspe": mspe})
+    tot_e = sum(r["evals"] for r in recs)
+    tot_t = sum(r["seconds"] for r in recs)
+    _line(METRIC, tot_e / tot_t, "evals/s", tot_e, 0, 1e3 * tot_t / tot_e, "f64",
+          {"workload": "Nelder-Mead MLE at the shape of Experiment 2: fit on %d of %d locations "
+                       "(%dx%d), cokriging of the %d held out, nb %d, FP64, a in %s"
+                       % (n_fit, n, 2 * n_fit, 2 * n_fit, n_hold, nb, args.mle_as),
+           "n_loc": n_fit, "held_out": n_hold, "precision": "fp64"},
+          fits=recs)
 
 
 def serve_stream(args, mvg, dev, synthetic, torch, rate, nreq):
@@ -447,7 +710,7 @@ def run_serving(args, mvg, dev, synthetic, torch):
     stream below capacity (bounded latency), same request mix."""
     hot = serve_stream(args, mvg, dev, synthetic, torch, args.rate, args.requests)
     calm = serve_stream(args, mvg, dev, synthetic, torch, args.sustain_rate, args.requests)
-    _line("loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
+    _line(METRIC,
           hot["achieved_rate"], "requests/s", hot["requests"], 0,
           1e3 * hot["makespan_s"] / hot["requests"], "f64",
           {"workload": "serving: %d requests, Poisson %.0f req/s, %d datasets n~U[1000,20000], "
@@ -461,36 +724,88 @@ def run_serving(args, mvg, dev, synthetic, torch):
           below_capacity={"rate_hz": args.sustain_rate, **calm})
 
 
+def run_dense(args, mvg, dev, synthetic, torch):
+    """The dense FP64 workload alone (N = 25,600), with the mixed-precision
+    and DST variants of the same inputs."""
+    n = args.n or 25600
+    tune = (256, 512, 768, 1024) if args.tune_1024 else (256, 512, 768)
+    rec, (xs, ys, z, th) = dense_record(args, mvg, dev, synthetic, torch, n, args.steps,
+                                        args.warmup, tune)
+    args.nb = rec["nb"]
+    args.n = n
+    extra = {}
+    if not args.no_variants:
+        _step("dense: mixed-precision and DST variants")
+        extra["variants"] = run_variants(mvg, xs, ys, z, th, args, rec["loglik"])
+    if not args.no_cpu:
+        _step("dense: oracle timing on the host (bounded sample)")
+        extra["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
+    roof = rec.pop("roofline")
+    _line(METRIC, rec["evals_per_s"], "evals/s", args.steps, args.warmup, rec["ms_per_step"],
+          "f64", {"workload": rec.pop("workload"), "n_loc": n, "matrix": 2 * n, "nb": rec["nb"],
+                  "precision": "fp64", "parallelism": "single GPU"},
+          roofline=roof, **rec, **extra)
+
+
+def run_mixed(args, mvg, dev, synthetic, torch):
+    """Mixed precision on the N = 50,000 workload for one (nu11, nu22, beta)."""
+    n = args.n or 50000
+    nu = tuple(float(v) for v in args.nu.split(","))
+    rec = mixed_record(args, mvg, dev, synthetic, torch, n, nu, args.beta, reps=max(1, args.steps))
+    best = max((rec[k] for k in ("fp32x", "fp32") if rec[k].get("meets_1e-6")),
+               key=lambda r: r["evals_per_s"], default=rec["fp64"])
+    _line(METRIC, best["evals_per_s"], "evals/s", max(1, args.steps), 1,
+          1e3 / best["evals_per_s"], "f64/f32",
+          {"workload": "mixed-precision bivariate Matern loglik, N=%d locations (%dx%d), nb 1024, "
+                       "FP64 band of 2 tiles, nu=%s, beta=%g" % (n, 2 * n, 2 * n, nu, args.beta),
+           "n_loc": n, "precision": "mixed"}, **rec)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None,
-                    help="locations (default 25,600; 100,000 for --workload tlr)")
+                    help="locations (default: 100,000 for the headline and tlr, 25,600 for dense, "
+                         "50,000 for mixed)")
     ap.add_argument("--a", type=float, default=0.1)
     ap.add_argument("--nb", type=int, default=0,
-                    help="tile size (0: dense workload autotunes among 256/512/768/1024; "
-                         "mloe / trivariate / mle use 1024)")
+                    help="dense tile size (0: autotuned among 256/512/768; mloe / trivariate / "
+                         "mle use 1024)")
+    ap.add_argument("--tune-1024", action="store_true", help="dense: also try tile size 1024")
     ap.add_argument("--targets", type=int, default=100)
-    ap.add_argument("--cpu-sample-n", type=int, default=2400)
+    ap.add_argument("--cpu-sample-n", type=int, default=6000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-nested", action="store_true",
+                    help="headline: skip the nested dense (N=25,600) and mixed (N=50,000) records")
+    ap.add_argument("--nested-steps", type=int, default=3)
+    ap.add_argument("--simplex", action="store_true",
+                    help="headline: also the 7-point simplex in one call")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the mixed-precision evaluations of the same inputs")
+                    help="dense: skip the mixed-precision evaluations of the same inputs")
     ap.add_argument("--band", type=int, default=2, help="FP64 band width in tiles (mixed)")
     ap.add_argument("--wide-band", type=int, default=16,
                     help="second, wider FP64 band for the FP32 variant")
+    ap.add_argument("--nu", default="0.5,1.0", help="mixed: nu11,nu22")
+    ap.add_argument("--beta", type=float, default=0.5, help="mixed: beta")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tlr", "batched", "serving", "mloe", "trivariate", "mle"],
-                    help="dense: N=25,600 FP64 (+ mixed variants); tlr: N=100,000 TLR; batched: "
-                         "many theta at N=400 in one launch; serving: request stream; mloe: "
-                         "MLOE/MMOM at N=25,600 with 100 targets; trivariate: p = 3 at N=17,066; mle: Nelder-Mead at N=22,464")
-    ap.add_argument("--accs", default="1e-7", help="TLR accuracies (first one is the value)")
-    ap.add_argument("--no-dense-ref", action="store_true")
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "dense", "tlr", "mixed", "batched", "serving", "mloe",
+                             "trivariate", "mle"],
+                    help="headline: TLR at N=100,000 with nested dense / mixed records; dense: "
+                         "N=25,600 FP64 (+ mixed variants); tlr: TLR alone (+ simplex); mixed: "
+                         "N=50,000 FP32X / FP32 vs FP64; batched: many theta at N=400 in one "
+                         "launch; serving: request stream; mloe: MLOE/MMOM at N=25,600; "
+                         "trivariate: p = 3 at N=17,066; mle: Nelder-Mead at N=22,464")
+    ap.add_argument("--accs", default="1e-7", help="TLR accuracy")
     ap.add_argument("--no-simplex", action="store_true",
-                    help="TLR: skip the 7-point simplex evaluated in one call")
+                    help="tlr: skip the 7-point simplex evaluated in one call")
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--max-evals", type=int, default=40, help="MLE: likelihood evaluations")
+    ap.add_argument("--max-evals", type=int, default=1500, help="MLE: evaluation budget per fit")
+    ap.add_argument("--mle-chunk", type=int, default=100,
+                    help="MLE: evaluations per restarted Nelder-Mead chunk")
+    ap.add_argument("--mle-as", default="0.03,0.09,0.2", help="MLE: ranges a to fit")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--sustain-rate", type=float, default=6.0)
@@ -504,7 +819,6 @@ def main():
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2008_07437_amd as mvg
@@ -521,12 +835,17 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
         return
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa
-    tune_nb = args.workload == "dense" and args.nb == 0
-    args.nb = args.nb or 1024   # the size the autotuner picks at n = 25,600
+    if args.workload == "headline":
+        return run_headline(args, mvg, dev, synthetic, torch)
     if args.workload == "tlr":
         args.n = args.n or 100000
         return run_tlr(args, mvg, dev, synthetic, torch)
+    if args.workload == "dense":
+        return run_dense(args, mvg, dev, synthetic, torch)
+    if args.workload == "mixed":
+        return run_mixed(args, mvg, dev, synthetic, torch)
     args.n = args.n or 25600
+    args.nb = args.nb or 1024
     if args.workload == "batched":
         return run_batched(args, mvg, dev, synthetic, torch)
     if args.workload == "serving":
@@ -534,104 +853,10 @@ def main():
     if args.workload == "mloe":
         return run_mloe(args, mvg, dev, synthetic, torch)
     if args.workload == "mle":
-        args.n = 22464 if args.n == 25600 else args.n
         return run_mle(args, mvg, dev, synthetic, torch)
     if args.workload == "trivariate":
         args.n = 17066 if args.n == 25600 else args.n
         return run_trivariate(args, mvg, dev, synthetic, torch)
-    th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
-    n = args.n
-    # --- data: Morton-ordered locations, Z = L eps at the true theta (setup)
-    xr, yr = synthetic.jittered_grid(n, args.seed)
-    _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
-    _step("dense: Z = L eps, n=%d" % n)
-    A = mvg.cov_generate(xs, ys, th, {"nb": args.nb})
-    info = mvg.potrf_tiled(A)
-    if info:
-        raise SystemExit("Sigma(theta) not positive definite at pivot %d" % info)
-    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
-    del A
-    tuned = None
-    if tune_nb:  # the library's autotuner picks the tile size on this problem (setup)
-        _step("dense: autotuning the tile size")
-        args.nb, tuned = mvg.mvg_autotune_nb(xs, ys, z, th, {}, [256, 512, 768, 1024])
-    x0r, y0r = synthetic.uniform_targets(args.targets, args.seed)
-    x0, y0 = dev(x0r), dev(y0r)
-    opts = {"nb": args.nb}
-    torch.cuda.synchronize()
-
-    last = {}
-
-    def step():
-        res, F = mvg.loglik(xs, ys, z, th, opts, keep=True)
-        zhat = mvg.cokrige_predict(F, x0, y0)
-        last["loglik"] = float(res["loglik"][0])
-        last["zhat0"] = zhat[0].tolist()
-        del F
-
-    _step("dense: nb %d, %d warm-up + %d timed steps" % (args.nb, args.warmup, args.steps))
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    mvg.mvg_prof_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = {k: mvg.mvg_prof_read(k) for k in ("trailing", "gen", "potrf", "solve", "cokrige")}
-    mvg.mvg_prof_enable(False)
-    wall = t1 - t0
-    ms_per_step = 1e3 * wall / args.steps
-    N = 2 * n
-    chol_flops = N ** 3 / 3.0
-    potrf_ms = prof["potrf"]["ms"] / max(1, prof["potrf"]["launches"])
-    tr = prof["trailing"]
-    achieved = tr["flops"] / (tr["ms"] * 1e-3) / 1e12 if tr["ms"] > 0 else None
-    out = {
-        "metric": "loglik evals/s + Cholesky TFLOP/s (FP64 vs mixed/TLR at |dl|<=1e-6); p99 latency",
-        "value": args.steps / wall,
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "dense FP64 bivariate Matern loglik + cokriging, N=%d locations "
-                               "(%dx%d covariance), theta=(1,1,%g,0.5,1,0.5), nb=%d, %d targets"
-                               % (n, N, N, args.a, args.nb, args.targets),
-                   "n_loc": n, "matrix": N, "nb": args.nb, "precision": "fp64",
-                   "parallelism": "single GPU"},
-        "cholesky_tflops": chol_flops / (potrf_ms * 1e-3) / 1e12,
-        "phases_ms_per_step": {k: prof[k]["ms"] / max(1, args.steps)
-                               for k in ("gen", "potrf", "solve", "cokrige")},
-        "loglik": last["loglik"],
-        "autotune_seconds_per_eval": ({str(k): v for k, v in tuned.items()} if tuned else None),
-        "roofline": {"kernel": "k_update_trailing", "bound": "mfma",
-                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
-                     "traffic": measured_traffic("k_update_trailing<%d, 0>" % args.nb,
-                                                 "cfg1_n%d_nb%d" % (n, args.nb)),
-                     "launches": tr["launches"],
-                     "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
-                     "flops_per_launch": tr["flops"] / max(1, tr["launches"])},
-    }
-    if not args.no_variants:
-        _step("dense: mixed-precision and DST variants")
-        out["variants"] = run_variants(mvg, xs, ys, z, th, args, last["loglik"])
-    if not args.no_cpu:
-        _step("dense: oracle timing on the host (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
