@@ -66,6 +66,8 @@ hipStream_t side_stream() {
 // any stream at once), and freed stream-ordered on that stream once idle.
 // hipFree would wait for the whole device, i.e. for every other stream's
 // work, which serialises concurrent requests.
+constexpr uint64_t POOL_KEEP = (uint64_t)48 << 30;
+
 static hipStream_t release_stream() {
   static std::mutex mu;
   static hipStream_t s[64] = {};
@@ -73,14 +75,39 @@ static hipStream_t release_stream() {
   hipGetDevice(&dev);
   if (dev < 0 || dev >= 64) dev = 0;
   std::lock_guard<std::mutex> lk(mu);
-  if (!s[dev]) hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking);  // default priority
+  if (!s[dev]) {
+    hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking);  // default priority
+    // keep up to POOL_KEEP bytes of freed stream-ordered memory mapped in the
+    // device's default pool: the per-evaluation workspaces and TLR stores
+    // (GBs) are then reused instead of mapped anew (~0.1 s per GB-sized
+    // allocation otherwise); dev_alloc trims the pool before giving up
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+      uint64_t keep = POOL_KEEP;
+      hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    hipGetLastError();
+  }
   return s[dev];
 }
 
 void *dev_alloc(size_t bytes) {
   void *p = nullptr;
   hipStream_t r = release_stream();
-  if (hipMallocAsync(&p, bytes ? bytes : 8, r) != hipSuccess || hipStreamSynchronize(r) != hipSuccess) {
+  if (hipMallocAsync(&p, bytes ? bytes : 8, r) != hipSuccess) {
+    hipGetLastError();
+    // memory kept by the pool after frees: return it and try once more
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipMemPool_t pool = nullptr;
+    hipStreamSynchronize(r);
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) hipMemPoolTrimTo(pool, 0);
+    if (hipMallocAsync(&p, bytes ? bytes : 8, r) != hipSuccess) {
+      hipGetLastError();
+      return nullptr;
+    }
+  }
+  if (hipStreamSynchronize(r) != hipSuccess) {
     hipGetLastError();
     return nullptr;
   }

@@ -214,6 +214,22 @@ static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
   return 0;
 }
 
+// Capacity of at least cap doubles (contents kept).
+static int store_grow(TlrStore &S, size_t cap, hipStream_t st) {
+  if (cap <= S.cap) return 0;
+  double *nbuf = nullptr;
+  if (hipMallocAsync((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: low-rank store allocation of %.2f GB failed", cap * 8.0 / 1e9);
+    return MVG_ERR_ALLOC;
+  }
+  if (S.used) hipMemcpyAsync(nbuf, S.buf, S.used * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (S.buf) hipFreeAsync(S.buf, st);
+  S.buf = nbuf;
+  S.cap = cap;
+  return 0;
+}
+
 static int store_init(TlrStore &S, int T, int nb, int64_t N, hipStream_t st) {
   S.T = T;
   S.nb = nb;
@@ -570,6 +586,15 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
     return MVG_ERR_ALLOC;
   }
   std::vector<int> sguess(T, -1);
+  // the factor's store sized up front from the compressed Sigma's (the factor's
+  // ranks are close to it), so that it does not grow by reallocation and copy
+  if (int rc2 = store_grow(Lf, Sg.used + Sg.used / 4 + ((size_t)1 << 22), st)) {
+    hipFreeAsync(P, st);
+    L0.release(st);
+    return rc2;
+  }
+  double *upd = nullptr;  // update workspace of the column steps, grown as needed
+  size_t upd_cap = 0;
   for (int j = 0; j < T && !rc; ++j) {
     const int ntile = T - j;
     const int ldp = ntile * nb;
@@ -601,10 +626,19 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
         for (int k = 0; k < j; ++k) gsz += (size_t)Lf.reff(tidx(i, k, T)) * Lf.reff(tidx(j, k, T));
       double *Qc = nullptr, *Pc = nullptr, *Gs = nullptr;
       const size_t qn = (size_t)nb * Kj, pn = (size_t)ldp * Kj;
-      if (hipMallocAsync((void **)&Qc, sizeof(double) * (qn + pn + std::max<size_t>(gsz, 1)), st) !=
-          hipSuccess) {
-        hipGetLastError();
-        set_error("TLR: update workspace of %.2f GB failed", (qn + pn + gsz) * 8.0 / 1e9);
+      const size_t need = qn + pn + std::max<size_t>(gsz, 1);
+      if (need > upd_cap) {  // grow-only (x1.5): a new allocation of GBs costs ~0.1 s
+        if (upd) hipFreeAsync(upd, st);
+        upd_cap = std::max(need, upd_cap + upd_cap / 2);
+        if (hipMallocAsync((void **)&upd, sizeof(double) * upd_cap, st) != hipSuccess) {
+          hipGetLastError();
+          upd = nullptr;
+          upd_cap = 0;
+        }
+      }
+      Qc = upd;
+      if (!Qc) {
+        set_error("TLR: update workspace of %.2f GB failed", need * 8.0 / 1e9);
         rc = MVG_ERR_ALLOC;
       } else {
         Pc = Qc + qn;
@@ -639,7 +673,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
           rc = run_gemms(gB, L, st);
           prof_end(h, st);
         }
-        hipFreeAsync(Qc, st);
+
       }
     }
     // (3) diagonal tile: FP64 Cholesky and W_j
@@ -667,6 +701,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
     }
     L.release(st);
   }
+  if (upd) hipFreeAsync(upd, st);
   hipFreeAsync(P, st);
   L0.release(st);
   if (!rc) rc = tlr_upload_meta(A, st);
