@@ -53,6 +53,9 @@ struct CopyTask {
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
                         hipStream_t st);
 int64_t gemm_blocks(const GemmTask &t);
+// C (M x N) -= A (M x K) B^T (B: N x K), column-major, one large product
+int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                       int M, int N, int K, hipStream_t st);
 int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);  // mmax: largest m
 // unpivoted QR in panels (compact WY); tk.tau must hold (n + 8) x 8 doubles (T factors)
 int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);

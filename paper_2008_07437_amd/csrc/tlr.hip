@@ -667,10 +667,10 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
         if (!rc) rc = run_gemms(gG, L, st);
         if (!rc) rc = run_gemms(gP, L, st);
         if (!rc) {
-          std::vector<GemmTask> gB{gemm(Pc, ldp, 0, Qc, nb, 1, P, ldp, ldp, nb, (int)Kj, -1.0, 1.0)};
+          // P -= Pc Qc^T: all earlier columns' updates of this column at once
           const double fl = 2.0 * ldp * nb * (double)Kj;
           int h = prof_begin(MVG_PROF_TRAILING, st, fl, 0.0);
-          rc = run_gemms(gB, L, st);
+          rc = launch_gemm_nt_sub(Pc, ldp, Qc, nb, P, ldp, ldp, nb, (int)Kj, st);
           prof_end(h, st);
         }
 

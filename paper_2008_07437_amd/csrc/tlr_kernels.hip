@@ -120,6 +120,124 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict
       }
 }
 
+// ------------------------------------------- C -= A B^T for one large product
+//
+// The column update of the TLR factorisation: C (M x N) -= A (M x K) B^T
+// (B: N x K), column-major, M up to 2e5, N = the tile size, K = the summed
+// ranks.  128 x 128 blocks (four waves of 64 x 64, 4 x 4 tiles of
+// v_mfma_f64_16x16x4f64), K slices of 16 staged through LDS with the next
+// slice's global loads in flight during the current slice's MFMAs (double
+// buffer), accumulators started from C so that the epilogue is stores only.
+// All loads are issued from clamped, always-valid addresses and zeroed
+// outside the matrix after a scheduling barrier (a load under a branch waits
+// for its value); blocks that lie inside C store without masks.
+constexpr int BG = 128, BK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_nt_sub(const double *__restrict__ A, int lda,
+                                                     const double *__restrict__ B, int ldb,
+                                                     double *__restrict__ C, int ldc, int M, int N,
+                                                     int K, int mblocks) {
+  __shared__ double As[2][BK][BG + 4];
+  __shared__ double Bs[2][BK][BG + 4];
+  const int m0 = (blockIdx.x % mblocks) * BG, n0 = (blockIdx.x / mblocks) * BG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+  // loader: thread t takes rows 2 (t % 64) + {0, 1} of slice columns t / 64 + 4 i
+  const int lr = 2 * (tid & 63), lc = tid >> 6;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = min(k0 + lc + 4 * i, K - 1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        ra[2 * i + h] = A[(int64_t)k * lda + min(m0 + lr + h, M - 1)];
+        rb[2 * i + h] = B[(int64_t)k * ldb + min(n0 + lr + h, N - 1)];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool kok = k0 + lc + 4 * i < K;
+        if (!(kok && m0 + lr + h < M)) ra[2 * i + h] = 0.0;
+        if (!(kok && n0 + lr + h < N)) rb[2 * i + h] = 0.0;
+      }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        As[buf][lc + 4 * i][lr + h] = -ra[2 * i + h];  // C -= A B^T
+        Bs[buf][lc + 4 * i][lr + h] = rb[2 * i + h];
+      }
+  };
+  const bool inside = m0 + BG <= M && n0 + BG <= N;
+  // accumulators from C: tile (ti, tj) element (4 e + lk, l16)
+  dbl4t acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 64 + tj * 16 + l16;
+        acc[ti][tj][e] = C[(int64_t)min(gn, N - 1) * ldc + min(gm, M - 1)];
+      }
+  int buf = 0;
+  if (K > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    if (k0 + BK < K) load(k0 + BK);  // in flight during this slice's MFMAs
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[buf][ks + lk][wr * 64 + i * 16 + l16];
+        b[i] = Bs[buf][ks + lk][wc * 64 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (k0 + BK < K) store(buf ^ 1);  // the other buffer: last read a slice ago
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 64 + tj * 16 + l16;
+        if (inside || (gm < M && gn < N)) C[(int64_t)gn * ldc + gm] = acc[ti][tj][e];
+      }
+}
+
+int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                       int M, int N, int K, hipStream_t st) {
+  if (M <= 0 || N <= 0) return 0;
+  const int64_t mb = (M + BG - 1) / BG, nbk = (N + BG - 1) / BG;
+  if (mb * nbk >= ((int64_t)1 << 31)) {
+    set_error("GEMM: %lld blocks", (long long)(mb * nbk));
+    return MVG_ERR_LIMIT;
+  }
+  hipLaunchKernelGGL(k_gemm_nt_sub, dim3((unsigned)(mb * nbk)), dim3(256), 0, st, A, lda, B, ldb,
+                     C, ldc, M, N, K, (int)mb);
+  return check_launch("gemm_nt_sub");
+}
+
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
                         hipStream_t st) {
   if (ntask <= 0 || nblocks <= 0) return 0;
@@ -606,17 +724,16 @@ int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st
 // itself stays in L2 / HBM (an nb x s sketch is up to 6 MB).
 // Requirements (checked by the launcher): m % 4 == 0, n + PQB <= m <= PQ_MAXM.
 constexpr int PQB = 16;          // panel width
-constexpr int PQ_THREADS = 512;  // panel workgroup
-constexpr int PQ_MAXM = 1536;    // rows: 3 per panel thread
+constexpr int PQ_MAXM = 1536;    // rows: 6 (3) per panel thread of 256 (512)
 constexpr int PAP_CB = 32;       // columns per apply workgroup
 constexpr int PAP_THREADS = 256; // apply workgroup (4 waves)
 
 // T factors in tk.tau: panel p0 at rows p0 .. p0 + PQB - 1 of a PQB-wide
 // row-major array ((n + PQB) x PQB doubles).
-template <int RPT>
-__global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restrict__ tasks, int p0) {
-  __shared__ double red_s[PQ_THREADS / 64];
-  __shared__ double red_d[PQ_THREADS / 64][PQB];
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ tasks, int p0) {
+  __shared__ double red_s[NT / 64];
+  __shared__ double red_d[NT / 64][PQB];
   __shared__ double s_alpha;
   __shared__ double sT[PQB][PQB];
   const QrTask tk = tasks[blockIdx.x];
@@ -631,7 +748,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
   double a[RPT][PQB];
 #pragma unroll
   for (int e = 0; e < RPT; ++e) {
-    const int r = min(p0 + tid + PQ_THREADS * e, m - 1);
+    const int r = min(p0 + tid + NT * e, m - 1);
 #pragma unroll
     for (int c = 0; c < PQB; ++c) a[e][c] = A[(int64_t)min(p0 + c, n - 1) * lda + r];
   }
@@ -640,14 +757,14 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
   for (int e = 0; e < RPT; ++e)
 #pragma unroll
     for (int c = 0; c < PQB; ++c)
-      if (p0 + tid + PQ_THREADS * e >= m || c >= pb) a[e][c] = 0.0;
+      if (p0 + tid + NT * e >= m || c >= pb) a[e][c] = 0.0;
   for (int jj = 0; jj < pb; ++jj) {
     const int j = p0 + jj;
     // squared norm of column jj below row j, and its entry on row j
     double ss = 0.0;
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
-      const int r = p0 + tid + PQ_THREADS * e;
+      const int r = p0 + tid + NT * e;
       double x = 0.0;
 #pragma unroll
       for (int c = 0; c < PQB; ++c)
@@ -660,7 +777,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
     __syncthreads();
     double sigma2 = 0.0;
 #pragma unroll
-    for (int w = 0; w < PQ_THREADS / 64; ++w) sigma2 += red_s[w];
+    for (int w = 0; w < NT / 64; ++w) sigma2 += red_s[w];
     const double alpha = s_alpha;
     double tau = 0.0, scale = 0.0, beta = alpha;
     if (sigma2 > 0.0) {
@@ -675,7 +792,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
     double v[RPT];
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
-      const int r = p0 + tid + PQ_THREADS * e;
+      const int r = p0 + tid + NT * e;
 #pragma unroll
       for (int c = 0; c < PQB; ++c)
         if (c == jj) {
@@ -705,7 +822,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
       double part = 0.0;
       if (lane < PQB)
 #pragma unroll
-        for (int w = 0; w < PQ_THREADS / 64; ++w) part += red_d[w][lane];
+        for (int w = 0; w < NT / 64; ++w) part += red_d[w][lane];
 #pragma unroll
       for (int c = 0; c < PQB; ++c) d[c] = __shfl(part, c);
     }
@@ -734,7 +851,7 @@ __global__ __launch_bounds__(PQ_THREADS) void k_qr_panel(const QrTask *__restric
   // the panel back (R on and above the diagonal, reflectors below), and T
 #pragma unroll
   for (int e = 0; e < RPT; ++e) {
-    const int r = p0 + tid + PQ_THREADS * e;
+    const int r = p0 + tid + NT * e;
     if (r < m)
 #pragma unroll
       for (int c = 0; c < PQB; ++c)
@@ -783,29 +900,38 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
   const int nchunk = (M + 15) / 16;
   // ---- W = V^T X
   dbl4t acc[2] = {dbl4t{0.0, 0.0, 0.0, 0.0}, dbl4t{0.0, 0.0, 0.0, 0.0}};
-  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
-    const int rr = 16 * ch + 4 * lk;          // first of the lane's 4 rows
-    const int rl = min(rr, M - 4);            // in bounds (M >= 4, M % 4 == 0)
-    double vv[4], x0[4], x1[4];
+  // two chunks per iteration (ch and ch + 4 waves), all their loads issued
+  // together; a chunk past the end is read from clamped rows and masked
+  constexpr int NW = PAP_THREADS / 64;
+  for (int ch = wave; ch < nchunk; ch += 2 * NW) {
+    double vv[2][4], x0[2][4], x1[2][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      vv[s] = V[(int64_t)qv * lda + rl + s];
-      x0[s] = X[(int64_t)xc0 * ldx + p0 + rl + s];
-      x1[s] = X[(int64_t)xc1 * ldx + p0 + rl + s];
+    for (int u = 0; u < 2; ++u) {
+      const int rl = min(16 * (ch + u * NW) + 4 * lk, M - 4);  // in bounds (M % 4 == 0)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        vv[u][s] = V[(int64_t)qv * lda + rl + s];
+        x0[u][s] = X[(int64_t)xc0 * ldx + p0 + rl + s];
+        x1[u][s] = X[(int64_t)xc1 * ldx + p0 + rl + s];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = rr + s;
-      const bool rok = r < M;
-      double vq = vv[s];
-      if (r < l16) vq = 0.0;            // above the unit diagonal of V
-      else if (r == l16) vq = 1.0;
-      if (!rok || l16 >= pb) vq = 0.0;
-      const double xa = (rok && xok0) ? x0[s] : 0.0;
-      const double xb = (rok && xok1) ? x1[s] : 0.0;
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xa, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xb, acc[1], 0, 0, 0);
+    for (int u = 0; u < 2; ++u) {
+      const int rr = 16 * (ch + u * NW) + 4 * lk;  // first of the lane's 4 rows
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = rr + s;
+        const bool rok = r < M;
+        double vq = vv[u][s];
+        if (r < l16) vq = 0.0;            // above the unit diagonal of V
+        else if (r == l16) vq = 1.0;
+        if (!rok || l16 >= pb) vq = 0.0;
+        const double xa = (rok && xok0) ? x0[u][s] : 0.0;
+        const double xb = (rok && xok1) ? x1[u][s] : 0.0;
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xa, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, xb, acc[1], 0, 0, 0);
+      }
     }
   }
   // D[q][c] of a 16 x 16 tile: lane c + 16 (q % 4), element q / 4
@@ -839,40 +965,52 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
   // (pivoted form, MODE 0) also the squared norms of the updated columns
   // below the panel's rows (rows p0 + pb ..), for the truncation test
   double css[2] = {0.0, 0.0};
-  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
-    const int r0 = 16 * ch;
-    const int rv = min(r0 + l16, M - 1);      // V row of this lane (A operand)
-    double va[4];
+  double nq[4][2];  // -W' operands of this lane: rows 4 s + lk, columns 16 h + l16
 #pragma unroll
-    for (int s = 0; s < 4; ++s) va[s] = V[(int64_t)min(4 * s + lk, pb - 1) * lda + rv];
-    dbl4t xt[2];
+  for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rx = min(r0 + 4 * e + lk, M - 1);
-      xt[0][e] = X[(int64_t)xc0 * ldx + p0 + rx];
-      xt[1][e] = X[(int64_t)xc1 * ldx + p0 + rx];
+    for (int h = 0; h < 2; ++h) nq[s][h] = sN[4 * s + lk][16 * h + l16];
+  for (int ch = wave; ch < nchunk; ch += 2 * NW) {
+    double va[2][4];
+    dbl4t xt[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r0 = 16 * (ch + u * NW);
+      const int rv = min(r0 + l16, M - 1);      // V row of this lane (A operand)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) va[u][s] = V[(int64_t)min(4 * s + lk, pb - 1) * lda + rv];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rx = min(r0 + 4 * e + lk, M - 1);
+        xt[u][0][e] = X[(int64_t)xc0 * ldx + p0 + rx];
+        xt[u][1][e] = X[(int64_t)xc1 * ldx + p0 + rx];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int q = 4 * s + lk, r = r0 + l16;
-      double vq = va[s];
-      if (r < q) vq = 0.0;
-      else if (r == q) vq = 1.0;
-      if (r >= M || q >= pb) vq = 0.0;
+    for (int u = 0; u < 2; ++u) {
+      const int r0 = 16 * (ch + u * NW);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-        xt[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, sN[q][16 * h + l16], xt[h], 0, 0, 0);
-    }
+      for (int s = 0; s < 4; ++s) {
+        const int q = 4 * s + lk, r = r0 + l16;
+        double vq = va[u][s];
+        if (r < q) vq = 0.0;
+        else if (r == q) vq = 1.0;
+        if (r >= M || q >= pb) vq = 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rx = r0 + 4 * e + lk;
-      if (rx < M) {
-        if (xok0) X[(int64_t)xc0 * ldx + p0 + rx] = xt[0][e];
-        if (xok1) X[(int64_t)xc1 * ldx + p0 + rx] = xt[1][e];
-        if (rx >= pb) {
-          css[0] += xt[0][e] * xt[0][e];
-          css[1] += xt[1][e] * xt[1][e];
+        for (int h = 0; h < 2; ++h)
+          xt[u][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, nq[s][h], xt[u][h], 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rx = r0 + 4 * e + lk;
+        if (rx < M) {
+          if (xok0) X[(int64_t)xc0 * ldx + p0 + rx] = xt[u][0][e];
+          if (xok1) X[(int64_t)xc1 * ldx + p0 + rx] = xt[u][1][e];
+          if (rx >= pb) {
+            css[0] += xt[u][0][e] * xt[u][0][e];
+            css[1] += xt[u][1][e] * xt[u][1][e];
+          }
         }
       }
     }
@@ -1207,6 +1345,39 @@ __global__ void k_qr_qinit(const QrTask *__restrict__ tasks, int nblk) {
       tk.Q[(int64_t)c * tk.ldq + i] = (i == c) ? 1.0 : 0.0;
 }
 
+// Panel workgroup size: 256 threads (rows per thread ceil(m / 256)) or 512
+// (MVG_QR_PANEL_THREADS=512, experiments).
+static int panel_threads() {
+  static const int t = [] {
+    const char *e = getenv("MVG_QR_PANEL_THREADS");
+    return e && atoi(e) == 512 ? 512 : 256;
+  }();
+  return t;
+}
+
+static void launch_panel(const QrTask *d_tasks, int ntask, int mmax, int p0, hipStream_t st) {
+  const dim3 g(ntask);
+  if (panel_threads() == 512) {
+    const int rpt = (mmax + 511) / 512;
+    if (rpt == 1)
+      hipLaunchKernelGGL((k_qr_panel<1, 512>), g, dim3(512), 0, st, d_tasks, p0);
+    else if (rpt == 2)
+      hipLaunchKernelGGL((k_qr_panel<2, 512>), g, dim3(512), 0, st, d_tasks, p0);
+    else
+      hipLaunchKernelGGL((k_qr_panel<3, 512>), g, dim3(512), 0, st, d_tasks, p0);
+    return;
+  }
+  const int rpt = (mmax + 255) / 256;
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_qr_panel<1, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 2: hipLaunchKernelGGL((k_qr_panel<2, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 3: hipLaunchKernelGGL((k_qr_panel<3, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 4: hipLaunchKernelGGL((k_qr_panel<4, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 5: hipLaunchKernelGGL((k_qr_panel<5, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    default: hipLaunchKernelGGL((k_qr_panel<6, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+  }
+}
+
 bool qr_panels_ok(int mmin, int mmax, int nmax) {
   return mmax <= PQ_MAXM && (mmin % 4) == 0 && (mmax % 4) == 0 && nmax + PQB <= mmin;
 }
@@ -1218,14 +1389,8 @@ int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool 
     set_error("QR: %d rows above %d", mmax, PQ_MAXM);
     return MVG_ERR_LIMIT;
   }
-  const int rpt = (mmax + PQ_THREADS - 1) / PQ_THREADS;
   for (int p0 = 0; p0 < nmax; p0 += PQB) {
-    if (rpt == 1)
-      hipLaunchKernelGGL((k_qr_panel<1>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
-    else if (rpt == 2)
-      hipLaunchKernelGGL((k_qr_panel<2>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
-    else
-      hipLaunchKernelGGL((k_qr_panel<3>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    launch_panel(d_tasks, ntask, mmax, p0, st);
     if (int rc = check_launch("qr_panel")) return rc;
     const int rest = nmax - p0 - PQB;
     if (rest > 0) {
@@ -1258,7 +1423,6 @@ int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hip
     set_error("pivoted QR: %d x %d above %d x %d", mmax, nmax, PQ_MAXM, QR_MAXN);
     return MVG_ERR_LIMIT;
   }
-  const int rpt = (mmax + PQ_THREADS - 1) / PQ_THREADS;
   hipLaunchKernelGGL(k_qr_rinit, dim3(ntask), dim3(256), 0, st, d_tasks);
   if (int rc = check_launch("qr_rinit")) return rc;
   for (int p0 = 0; p0 < nmax; p0 += PQB) {
@@ -1267,12 +1431,7 @@ int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hip
     if (int rc = check_launch("qr_sample")) return rc;
     hipLaunchKernelGGL(k_qr_pick, dim3(ntask), dim3(PICK_THREADS), 0, st, d_tasks, p0);
     if (int rc = check_launch("qr_pick")) return rc;
-    if (rpt == 1)
-      hipLaunchKernelGGL((k_qr_panel<1>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
-    else if (rpt == 2)
-      hipLaunchKernelGGL((k_qr_panel<2>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
-    else
-      hipLaunchKernelGGL((k_qr_panel<3>), dim3(ntask), dim3(PQ_THREADS), 0, st, d_tasks, p0);
+    launch_panel(d_tasks, ntask, mmax, p0, st);
     if (int rc = check_launch("qr_panel")) return rc;
     const int rest = nmax - p0 - PQB;
     if (rest > 0) {
