@@ -210,26 +210,31 @@ def tlr_record(args, mvg, dev, synthetic, torch, n, acc, steps, warmup, simplex=
     th = (1.0, 1.0, args.a, 0.5, 1.0, 0.5)
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
-    # Z = L eps at the true theta from the FP64 factor (set-up; 160 GB resident),
-    # and the dense FP64 likelihood of the same inputs from that factor
-    _step("tlr: dense FP64 factor, Z = L eps, n=%d" % n)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    A = mvg.cov_generate(xs, ys, th, {"nb": 1024})
-    if mvg.potrf_tiled(A):
-        raise SystemExit("Sigma(theta) not positive definite")
-    torch.cuda.synchronize()
-    t_fact = time.perf_counter() - t0
-    z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ref = mvg.mvg_mat_loglik(A, z)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t1
-    del A
-    dense = {"seconds": t_fact + t_solve, "evals_per_s": 1.0 / (t_fact + t_solve), "nb": 1024,
-             "loglik": ref["loglik"], "logdet": ref["logdet"], "quad": ref["quad"],
-             "cholesky_tflops": (2.0 * n) ** 3 / 3.0 / t_fact / 1e12}
+    if args.white_z:  # counter runs: Z = eps, no dense factor (kernel work does not depend on Z)
+        z = dev(synthetic.normal_eps(2 * n, args.seed))
+        ref = {"loglik": float("nan"), "logdet": float("nan"), "quad": float("nan")}
+        dense = None
+    else:
+        # Z = L eps at the true theta from the FP64 factor (set-up; 160 GB
+        # resident), and the dense FP64 likelihood of the same inputs from it
+        _step("tlr: dense FP64 factor, Z = L eps, n=%d" % n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = mvg.cov_generate(xs, ys, th, {"nb": 1024})
+        if mvg.potrf_tiled(A):
+            raise SystemExit("Sigma(theta) not positive definite")
+        torch.cuda.synchronize()
+        t_fact = time.perf_counter() - t0
+        z = mvg.mvg_trmv(A, dev(synthetic.normal_eps(2 * n, args.seed)))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ref = mvg.mvg_mat_loglik(A, z)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t1
+        del A
+        dense = {"seconds": t_fact + t_solve, "evals_per_s": 1.0 / (t_fact + t_solve), "nb": 1024,
+                 "loglik": ref["loglik"], "logdet": ref["logdet"], "quad": ref["quad"],
+                 "cholesky_tflops": (2.0 * n) ** 3 / 3.0 / t_fact / 1e12}
     o = {"nb": nb, "precision": mvg.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300}
     _step("tlr: acc %g, %d warm-up + %d timed evaluations" % (acc, warmup, steps))
     for _ in range(warmup):
@@ -251,7 +256,7 @@ def tlr_record(args, mvg, dev, synthetic, torch, n, acc, steps, warmup, simplex=
            "rel_dloglik_vs_fp64": abs(r["loglik"][0] - ref["loglik"]) / abs(ref["loglik"]),
            "rel_dlogdet_vs_fp64": abs(r["logdet"][0] - ref["logdet"]) / abs(ref["logdet"]),
            "rel_dquad_vs_fp64": abs(r["quad"][0] - ref["quad"]) / abs(ref["quad"]),
-           "speedup_vs_dense_fp64": dense["seconds"] / dt,
+           "speedup_vs_dense_fp64": dense["seconds"] / dt if dense else None,
            "phases_ms_per_eval": {"compress": per("gen"), "factor": per("potrf"),
                                   "solve": per("solve"), "update_gemm": per("trailing"),
                                   "all_batched_gemm": per("tlr_gemm"), "qr": per("qr")},
@@ -802,6 +807,8 @@ def main():
                          "launch; serving: request stream; mloe: MLOE/MMOM at N=25,600; "
                          "trivariate: p = 3 at N=17,066; mle: Nelder-Mead at N=22,464")
     ap.add_argument("--accs", default="1e-7", help="TLR accuracy")
+    ap.add_argument("--white-z", action="store_true",
+                    help="tlr: Z = eps without the dense FP64 set-up (counter runs only)")
     ap.add_argument("--no-simplex", action="store_true",
                     help="tlr: skip the 7-point simplex evaluated in one call")
     ap.add_argument("--batch", type=int, default=1024)

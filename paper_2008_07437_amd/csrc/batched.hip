@@ -4,10 +4,11 @@
 // grid of workgroups pulls task indices from a device counter until the list
 // is exhausted; a workgroup evaluates its task alone: the per-theta
 // quadrature table in LDS, the lower triangle of Sigma in its private
-// workspace, a right-looking Cholesky in column blocks of SB (diagonal block
-// in LDS with its inverse, panel by the inverse, trailing update on FP64
-// MFMA), the forward solve folded into the factorisation, and the
-// log-determinant and quadratic form summed in a fixed order.  A task's
+// workspace, a left-looking Cholesky in column blocks of SB (each block
+// column first receives all earlier columns' updates on FP64 MFMA, then its
+// diagonal block is factored in LDS with its inverse and the rows below are
+// solved by that inverse), the forward solve folded into the factorisation,
+// and the log-determinant and quadratic form summed in a fixed order.  A task's
 // arithmetic does not depend on which workgroup runs it or on the other
 // tasks, so results are the same alone and in any batch.
 #include <cmath>
@@ -42,66 +43,97 @@ __device__ __forceinline__ void store_at(double *A, int N, int col, int row, dou
   *(double *)((char *)A + ((unsigned)col * (unsigned)N + (unsigned)row) * 8u) = v;
 }
 
-// C -= L_I L_J^T on one 32 x 32 block of the trailing matrix (2 x 2 tiles of
-// 16 x 16 on MFMA: lane j + 16 (i % 4), element i / 4 of a tile): rows
-// iA.., columns jB.., the panel in columns k0 .. k0 + kb.  Every panel
-// fragment loaded serves two tiles, and all loads are issued before the
-// first wait.  MASK: the block reaches past row N - 1 or kb < SB (masked
-// entries are loaded from clamped addresses and zeroed; stores are guarded).
-template <bool MASK>
-__device__ __forceinline__ void trail_block(double *A, int N, int k0, int kb, int iA, int jB,
-                                            bool diag, int l16, int lk) {
-  dbl4s acc[2][2];
-  double av[2][SB / 4], bv[2][SB / 4];
+// Left-looking update of block column k0 (columns k0 .. k0 + kb - 1, rows
+// k0 .. N - 1): A[r][c] -= sum_{q < k0} L[r][q] L[c][q], on FP64 MFMA.  The
+// rows are cut into 32-row output blocks, one per wave (2 x 2 tiles of
+// 16 x 16: lane j + 16 (i % 4), element i / 4 of a tile); when there are
+// fewer blocks than waves, the q range of a block is split over several
+// waves and their partial tiles are summed in a fixed order through the
+// workgroup's scratch.  Reading the panels L[., < k0] once per block column
+// moves about a third of the bytes of a right-looking update, which reads and
+// writes the trailing matrix at every step.  Every load is from a clamped
+// address inside the task's N x N workspace, masked after the load; the next
+// 8 columns' operands are in flight while the current ones feed the MFMAs.
+__device__ __forceinline__ void left_update(double *A, int N, int k0, int kb, double *part,
+                                            int wave, int lane, int tid) {
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int nout = (N - k0 + 31) / 32;
+  const int splits = nout >= SW ? 1 : SW / nout;
+  const int nitems = nout * splits;
+  const int kc = (k0 / splits + 7) / 8 * 8;  // q per part (a multiple of 8)
+  for (int it = wave; it < nitems; it += SW) {
+    const int b = it / splits, pt = it % splits;
+    const int iA = k0 + 32 * b;
+    const int q0 = min(k0, pt * kc), q1 = min(k0, q0 + kc);
+    dbl4s acc[2][2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+    for (int hi = 0; hi < 2; ++hi)
 #pragma unroll
-    for (int kk = 0; kk < SB / 4; ++kk) {
-      const int q = k0 + (MASK ? min(4 * kk + lk, kb - 1) : 4 * kk + lk);
-      av[h][kk] = MASK ? clamped_load(A, N, q, iA + 16 * h + l16) : load_at(A, N, q, iA + 16 * h + l16);
-      bv[h][kk] = MASK ? clamped_load(A, N, q, jB + 16 * h + l16) : load_at(A, N, q, jB + 16 * h + l16);
-    }
-#pragma unroll
-  for (int hi = 0; hi < 2; ++hi)
-#pragma unroll
-    for (int hj = 0; hj < 2; ++hj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int col = jB + 16 * hj + l16, row = iA + 16 * hi + 4 * e + lk;
-        acc[hi][hj][e] = MASK ? clamped_load(A, N, col, row) : load_at(A, N, col, row);
-      }
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int kk = 0; kk < SB / 4; ++kk) {
-      if (MASK) {
-        const bool okq = 4 * kk + lk < kb;
-        av[h][kk] = (iA + 16 * h + l16 < N && okq) ? -av[h][kk] : 0.0;
-        if (!(jB + 16 * h + l16 < N && okq)) bv[h][kk] = 0.0;
-      } else {
-        av[h][kk] = -av[h][kk];
-      }
-    }
-#pragma unroll
-  for (int hi = 0; hi < 2; ++hi)
-#pragma unroll
-    for (int hj = 0; hj < 2; ++hj) {
-      if (diag && hi < hj) continue;
-      if (MASK) {
+      for (int hj = 0; hj < 2; ++hj)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (!(iA + 16 * hi + 4 * e + lk < N && jB + 16 * hj + l16 < N)) acc[hi][hj][e] = 0.0;
-      }
+          acc[hi][hj][e] = pt == 0 ? clamped_load(A, N, k0 + 16 * hj + l16, iA + 16 * hi + 4 * e + lk)
+                                   : 0.0;
+    double ca[2][2], cb[2][2];  // [h][kk]: rows 16 h + l16, columns q + 4 kk + lk
+    auto fetch = [&](int q, double (&fa)[2][2], double (&fb)[2][2]) {
 #pragma unroll
-      for (int kk = 0; kk < SB / 4; ++kk)
-        acc[hi][hj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[hi][kk], bv[hj][kk], acc[hi][hj], 0, 0, 0);
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gi = iA + 16 * hi + 4 * e + lk, gj = jB + 16 * hj + l16;
-        if (!MASK || (gi < N && gj < N)) store_at(A, N, gj, gi, acc[hi][hj][e]);
-      }
+        for (int kk = 0; kk < 2; ++kk) {
+          fa[h][kk] = clamped_load(A, N, q + 4 * kk + lk, iA + 16 * h + l16);
+          fb[h][kk] = clamped_load(A, N, q + 4 * kk + lk, k0 + 16 * h + l16);
+        }
+    };
+    if (q0 < q1) fetch(q0, ca, cb);
+    for (int q = q0; q < q1; q += 8) {
+      double na[2][2], nb2[2][2];
+      fetch(min(q + 8, q1 - 1), na, nb2);  // next chunk (clamped; unused past q1)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          const bool okq = q + 4 * kk + lk < q1;
+          ca[h][kk] = (okq && iA + 16 * h + l16 < N) ? -ca[h][kk] : 0.0;
+          if (!(okq && 16 * h + l16 < kb)) cb[h][kk] = 0.0;
+        }
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+          for (int hj = 0; hj < 2; ++hj)
+            acc[hi][hj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[hi][kk], cb[hj][kk], acc[hi][hj], 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          ca[h][kk] = na[h][kk];
+          cb[h][kk] = nb2[h][kk];
+        }
     }
+#pragma unroll
+    for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+      for (int hj = 0; hj < 2; ++hj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * hi + 4 * e + lk, c = 16 * hj + l16;
+          if (splits == 1) {
+            if (iA + r < N && c < kb) store_at(A, N, k0 + c, iA + r, acc[hi][hj][e]);
+          } else {
+            part[(int64_t)wave * (SB * SB) + c * SB + r] = acc[hi][hj][e];
+          }
+        }
+  }
+  if (splits > 1) {  // item it ran on wave it (nitems <= SW)
+    __syncthreads();
+    for (int e = tid; e < nout * SB * SB; e += STHREADS) {
+      const int b = e / (SB * SB), idx = e % (SB * SB), r = idx % SB, c = idx / SB;
+      double t = 0.0;
+      for (int p = 0; p < splits; ++p) t += part[(int64_t)(b * splits + p) * (SB * SB) + idx];
+      if (k0 + 32 * b + r < N && c < kb) store_at(A, N, k0 + c, k0 + 32 * b + r, t);
+    }
+  }
 }
 
 __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__restrict__ tasks,
@@ -129,6 +161,7 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
     const int n = (int)tk.n, N = 2 * n;
     double *A = ws;          // N x N, column-major, ld N (lower triangle used)
     double *zv = ws + (int64_t)N * N;  // right-hand side being solved
+    double *part = zv + N;   // SW partial 32 x 32 tiles of the split updates
     // quadrature table
     for (int k = tid; k < QN; k += STHREADS) quad_entry(k, tk.P, sq);
     for (int i = tid; i < N; i += STHREADS) zv[i] = tk.z[i];
@@ -160,6 +193,11 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
     __syncthreads();
     for (int k0 = 0; k0 < N; k0 += SB) {
       const int kb = min(SB, N - k0);
+      // (u) this block column receives all earlier columns' updates at once
+      if (k0 > 0) {
+        left_update(A, N, k0, kb, part, wave, lane, tid);
+        __syncthreads();
+      }
       // (a) diagonal block: Cholesky in LDS (all threads, one column at a time)
       for (int e = tid; e < kb * kb; e += STHREADS) {
         const int r = e % kb, c = e / kb;
@@ -270,22 +308,6 @@ __global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__re
           if (c < kb) zi += v[c] * sy[c];
         zv[i] -= zi;
       }
-      // (c) trailing update A_ij -= L_i L_j^T for k0 + kb <= j <= i, one
-      //     32 x 32 block per wave at a time
-      const int m2 = (N - r0 + 31) / 32;
-      const int nblk = m2 * (m2 + 1) / 2;
-      for (int t = wave; t < nblk; t += SW) {  // block (I2, J2), J2 <= I2, row-major
-        int I2 = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while ((I2 + 1) * (I2 + 2) / 2 <= t) ++I2;  // exact after rounding
-        while (I2 * (I2 + 1) / 2 > t) --I2;
-        const int J2 = t - I2 * (I2 + 1) / 2;
-        const int iA = r0 + 32 * I2, jB = r0 + 32 * J2;
-        const bool diag = I2 == J2;  // its upper-right tile lies above the diagonal
-        if (kb == SB && iA + 32 <= N && jB + 32 <= N)
-          trail_block<false>(A, N, k0, kb, iA, jB, diag, l16, lk);
-        else
-          trail_block<true>(A, N, k0, kb, iA, jB, diag, l16, lk);
-      }
       __syncthreads();
     }
     if (tid == 0) {
@@ -315,7 +337,7 @@ int small_batch_workgroups(int ntask) { return ntask < 2 * 256 ? ntask : 2 * 256
 
 size_t small_workspace_doubles(int64_t nmax) {
   const int64_t N = 2 * nmax;
-  return (size_t)(N * N + N);
+  return (size_t)(N * N + N + SW * SB * SB);  // matrix, right-hand side, split partials
 }
 
 int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *d_counter,

@@ -251,22 +251,47 @@ def test_mixed_fp32_fullsize_model_data_expected_miss(lib, orc, band):
         pytest.xfail("FP32 storage misses |delta loglik| <= 1e-6 at n = 50,000: %.2e" % dl)
 
 
-def test_tlr_fullsize(lib, orc):
-    """TLR on Z = L eps at n = 100,000: |delta loglik| <= 1e-6 relative to
-    the FP64 path on the same data."""
-    n = 100000
-    x, y = _sites(orc, n, 0)
-    _say("full-size TLR: Z = L eps from the FP64 factor, n=%d (200,000^2)" % n)
-    z = _model_z(lib, x, y, TH, 0)
-    _say("full-size TLR: FP64 reference")
-    d64 = lib.loglik(_dev(x), _dev(y), z, TH, {"nb": 1024})
-    _say("full-size TLR: acc 1e-7, tile 1200")
+_tlr = {}
+
+
+def _tlr_fp64(lib, orc):
+    """Z = L eps at n = 100,000 from the FP64 factor (tile 1024) and the FP64
+    likelihood of the same inputs on that factor (mvg_mat_loglik: the solve and
+    log-determinant kernels of loglik)."""
+    if not _tlr:
+        n = 100000
+        x, y = _sites(orc, n, 0)
+        _say("full-size TLR: Z = L eps from the FP64 factor, n=%d (200,000^2)" % n)
+        A = lib.cov_generate(_dev(x), _dev(y), TH, {"nb": 1024})
+        assert lib.potrf_tiled(A) == 0
+        z = lib.mvg_trmv(A, _dev(synthetic.normal_eps(2 * n, 0)))
+        d64 = lib.mvg_mat_loglik(A, z)
+        del A
+        _tlr.update(x=x, y=y, z=z, d64=d64)
+    return _tlr["x"], _tlr["y"], _tlr["z"], _tlr["d64"]
+
+
+@pytest.mark.parametrize("acc", [1e-7, 1e-9, 1e-5])
+def test_tlr_fullsize(lib, orc, acc):
+    """TLR on Z = L eps at n = 100,000 (tile 1200, maximum rank 300) against
+    the FP64 path on the same data, at the three accuracies of Section 5.3:
+    |delta loglik| <= 1e-6 at 1e-7 and 1e-9.  At 1e-5 the compression error
+    of log|Sigma| alone is of the order of the bound (measured 1.0e-6): the
+    regression bound 1e-5 is asserted and a miss of 1e-6 is reported as an
+    expected failure."""
+    x, y, z, d64 = _tlr_fp64(lib, orc)
+    _say("full-size TLR: acc %g, tile 1200" % acc)
     t = lib.loglik(_dev(x), _dev(y), z, TH,
-                   {"nb": 1200, "precision": lib.MVG_TLR, "tlr_acc": 1e-7, "tlr_max_rank": 300})
-    dl = abs(t["loglik"][0] - d64["loglik"][0]) / abs(d64["loglik"][0])
-    _say("  rel dloglik %.2e (loglik %.6f)" % (dl, d64["loglik"][0]))
-    assert d64["status"][0] == 0
-    assert t["status"][0] == 0 and dl <= 1e-6
+                   {"nb": 1200, "precision": lib.MVG_TLR, "tlr_acc": acc, "tlr_max_rank": 300})
+    dl = abs(t["loglik"][0] - d64["loglik"]) / abs(d64["loglik"])
+    _say("  rel dloglik %.2e (loglik %.6f, FP64 %.6f)" % (dl, t["loglik"][0], d64["loglik"]))
+    assert t["status"][0] == 0
+    if acc <= 1e-7:
+        assert dl <= 1e-6
+        return
+    assert dl <= 1e-5
+    if dl > 1e-6:
+        pytest.xfail("TLR at acc 1e-5 misses |delta loglik| <= 1e-6: %.2e" % dl)
 
 
 def test_batched_fullsize_sampled(lib, orc):
