@@ -158,6 +158,16 @@ static bool use_qrcp_panels(int nb, int smax) {
   return mode == 1 || smax >= QR_PANELS_MIN_N;
 }
 
+// the panel kernels' 16-byte loads: even leading dimensions and 16-byte
+// aligned matrices
+static bool panel_tasks_aligned(const std::vector<QrTask> &v) {
+  for (const QrTask &t : v)
+    if ((t.lda & 1) || (t.Q && (t.ldq & 1)) || ((uintptr_t)t.A & 15) || ((uintptr_t)t.Q & 15) ||
+        ((uintptr_t)t.work & 15))
+      return false;
+  return true;
+}
+
 static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostLists &L,
                   hipStream_t st) {
   if (v.empty()) return 0;
@@ -177,7 +187,8 @@ static int run_qr(const std::vector<QrTask> &v, int mmax, bool blocked, HostList
       with_q = with_q || t.Q;
     }
     const int mode = qr_panels_mode();
-    const bool panels = qr_panels_ok(mmin, mx, nmax) && (mode == 1 || (mode != 0 && nmax >= QR_PANELS_MIN_N));
+    const bool panels = qr_panels_ok(mmin, mx, nmax) && panel_tasks_aligned(v) &&
+                        (mode == 1 || (mode != 0 && nmax >= QR_PANELS_MIN_N));
     rc = panels ? launch_qr_panels(d, (int)v.size(), mx, nmax, with_q, st)
                 : launch_qr_blocked(d, (int)v.size(), mmax, st);
   } else {
@@ -308,13 +319,17 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     int smx = 1;
     for (size_t b = 0; b < jobs.size(); ++b) smx = std::max(smx, jobs[b].s);
     const bool rq = use_qrcp_panels(nb, smx);
+    // every block starts at a multiple of 32 doubles and every matrix the
+    // panel kernels read at an even offset (their 16-byte loads; nb is even)
+    auto even = [](size_t x) { return (x + 1) & ~(size_t)1; };
     std::vector<size_t> base(jobs.size());
     size_t tot = 0;
     for (size_t b = 0; b < jobs.size(); ++b) {
       const size_t s = jobs[b].s;
       base[b] = tot;
-      tot += 4 * (size_t)nb * s + 2 * s * s + TW * (s + TW) + s + 1;
+      tot += 4 * (size_t)nb * s + 2 * s * s + TW * (s + TW) + even(s + 1);
       if (rq) tot += (size_t)QRS_ROWS * (nb + s) + s;
+      tot = (tot + 31) & ~(size_t)31;
     }
     const size_t rank_off = tot;
     tot += (jobs.size() + 1) / 2;
@@ -333,7 +348,7 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     auto Tb = [&](size_t b) { return Q3(b) + (size_t)jobs[b].s * jobs[b].s; };
     // T factors of the blocked QR (one block per panel of columns)
     auto Pv = [&](size_t b) { return (int *)(Tb(b) + TW * ((size_t)jobs[b].s + TW)); };
-    auto Wk = [&](size_t b) { return Tb(b) + TW * ((size_t)jobs[b].s + TW) + jobs[b].s + 1; };
+    auto Wk = [&](size_t b) { return Tb(b) + TW * ((size_t)jobs[b].s + TW) + even(jobs[b].s + 1); };
     int *d_ranks = (int *)(ws + rank_off);
     auto Rk = [&](size_t b) { return d_ranks + b; };
     HostLists L;

@@ -1,0 +1,320 @@
+// FP64 GEMMs of the tile-low-rank (TLR) path on gfx950 MFMA: C = alpha
+// op(A) op(B) + beta C over a list of variable-size products (tile
+// expansion, the small V^T V products, triangular applications, sketches),
+// and C -= A B^T for the one large column update of each step of the
+// factorisation.  The TLR driver builds the lists on the host.
+#include <cmath>
+
+#include "tlr.h"
+
+namespace mvg {
+
+typedef double dbl4t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ batched GEMM
+//
+// C = alpha op(A) op(B) + beta C, column-major, op(X) = X or X^T.  One
+// workgroup per 64 x 64 block of C; four waves of 32 x 32 (2 x 2 tiles of
+// v_mfma_f64_16x16x4f64); K slices of 16 staged through LDS with the next
+// slice's global loads in flight during the current slice's MFMAs (one LDS
+// buffer: 19 KB, so that many workgroups share a CU; most products here
+// have a short K).  A block finds its task by binary search over the tasks'
+// first-block offsets, staged in LDS when the list is short.  All
+// operand loads are from clamped, always-valid addresses and masked after a
+// scheduling barrier (ragged edges, the zero triangle of a triangular A); C
+// is read for beta != 0 with all of a lane's loads issued together.
+constexpr int GB = 64, GK = 16;
+constexpr int GTASK_LDS = 256;  // task offsets staged in LDS up to this many tasks
+
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict__ tasks,
+                                                      const int64_t *__restrict__ start, int ntask) {
+  __shared__ double As[GK][GB + 2];
+  __shared__ double Bs[GK][GB + 2];
+  __shared__ int64_t sstart[GTASK_LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t bid = blockIdx.x;
+  int t;
+  if (ntask <= GTASK_LDS) {
+    for (int i = tid; i < ntask; i += 256) sstart[i] = start[i];
+    __syncthreads();
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sstart[mid] <= bid) lo = mid; else hi = mid - 1;
+    }
+    t = lo;
+  } else {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (start[mid] <= bid) lo = mid; else hi = mid - 1;
+    }
+    t = lo;
+  }
+  const GemmTask tk = tasks[t];
+  const int M = tk.M, N = tk.N, K = tk.K;
+  const int mt = (M + GB - 1) / GB;
+  const int64_t local = bid - start[t];
+  const int m0 = (int)(local % mt) * GB, n0 = (int)(local / mt) * GB;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+  // loader coordinates: thread tid takes (m, k) = (tid % 64, tid / 64 + 4 i)
+  // of an untransposed operand, (tid / 16 + 16 i, tid % 16) of a transposed one
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = tk.ta ? (tid >> 4) + 16 * i : (tid & 63);
+      const int k = tk.ta ? (tid & 15) : (tid >> 6) + 4 * i;
+      const int gm = min(m0 + m, M - 1), gk = min(k0 + k, K - 1);
+      ra[i] = tk.ta ? tk.A[(int64_t)gm * tk.lda + gk] : tk.A[(int64_t)gk * tk.lda + gm];
+      const int n = tk.tb ? (tid & 63) : (tid >> 4) + 16 * i;
+      const int kb = tk.tb ? (tid >> 6) + 4 * i : (tid & 15);
+      const int gn = min(n0 + n, N - 1), gkb = min(k0 + kb, K - 1);
+      rb[i] = tk.tb ? tk.B[(int64_t)gkb * tk.ldb + gn] : tk.B[(int64_t)gn * tk.ldb + gkb];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = tk.ta ? (tid >> 4) + 16 * i : (tid & 63);
+      const int k = tk.ta ? (tid & 15) : (tid >> 6) + 4 * i;
+      const int gm = m0 + m, gk = k0 + k;
+      // stored element (row, col) = (gm, gk), or (gk, gm) when transposed
+      const bool zero_tri = tk.tri && (tk.ta ? gm > gk : gk > gm);
+      if (!(gm < M && gk < K) || zero_tri) ra[i] = 0.0;
+      const int n = tk.tb ? (tid & 63) : (tid >> 4) + 16 * i;
+      const int kb = tk.tb ? (tid >> 6) + 4 * i : (tid & 15);
+      if (!(n0 + n < N && k0 + kb < K)) rb[i] = 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!tk.ta) As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
+      else As[tid & 15][(tid >> 4) + 16 * i] = ra[i];
+      if (tk.tb) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
+      else Bs[tid & 15][(tid >> 4) + 16 * i] = rb[i];
+    }
+  };
+  dbl4t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    store();
+    __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);  // in flight during this slice's MFMAs
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[ks + lk][wr * 32 + i * 16 + l16];
+        b[i] = Bs[ks + lk][wc * 32 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[i][j] of a 16 x 16 tile: lane j + 16 (i % 4), element i / 4
+  const double alpha = tk.alpha, beta = tk.beta;
+  double cv[2][2][4];
+  if (beta != 0.0) {  // uniform
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int gm = min(m0 + wr * 32 + i * 16 + 4 * e + lk, M - 1);
+          const int gn = min(n0 + wc * 32 + j * 16 + l16, N - 1);
+          cv[i][j][e] = tk.C[(int64_t)gn * tk.ldc + gm];
+        }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cv[i][j][e] = alpha * acc[i][j][e] + beta * cv[i][j][e];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cv[i][j][e] = alpha * acc[i][j][e];
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 32 + i * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 32 + j * 16 + l16;
+        if (gm < M && gn < N) tk.C[(int64_t)gn * tk.ldc + gm] = cv[i][j][e];
+      }
+}
+
+// ------------------------------------------- C -= A B^T for one large product
+//
+// The column update of the TLR factorisation: C (M x N) -= A (M x K) B^T
+// (B: N x K), column-major, M up to 2e5, N = the tile size, K = the summed
+// ranks.  128 x 128 blocks (four waves of 64 x 64, 4 x 4 tiles of
+// v_mfma_f64_16x16x4f64), K slices of 16 staged through LDS with the next
+// slice's global loads in flight during the current slice's MFMAs (double
+// buffer), accumulators started from C so that the epilogue is stores only.
+// All loads are issued from clamped, always-valid addresses and zeroed
+// outside the matrix after a scheduling barrier (a load under a branch waits
+// for its value); blocks that lie inside C store without masks.
+constexpr int BG = 128, BK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_nt_sub(const double *__restrict__ A, int lda,
+                                                     const double *__restrict__ B, int ldb,
+                                                     double *__restrict__ C, int ldc, int M, int N,
+                                                     int K, int mblocks) {
+  __shared__ double As[2][BK][BG + 4];
+  __shared__ double Bs[2][BK][BG + 4];
+  // Workgroups are dealt to the 8 XCDs in turn (w % 8).  On each XCD the
+  // consecutive workgroups take all column blocks of one row block before
+  // the next row block, so the blocks that read the same rows of A run
+  // together and share that XCD's L2 (A is read about once from HBM instead
+  // of once per column block); row blocks beyond a multiple of 8 follow in
+  // plain order.
+  int blk_r, blk_c;
+  {
+    const int w = blockIdx.x, nbk = (N + BG - 1) / BG;
+    const int full = (mblocks / 8) * 8 * nbk;
+    if (w < full) {
+      const int t = w >> 3;
+      blk_c = t % nbk;
+      blk_r = (t / nbk) * 8 + (w & 7);
+    } else {
+      const int t = w - full;
+      blk_c = t % nbk;
+      blk_r = (mblocks / 8) * 8 + t / nbk;
+    }
+  }
+  const int m0 = blk_r * BG, n0 = blk_c * BG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+  // loader: thread t takes rows 2 (t % 64) + {0, 1} of slice columns t / 64 + 4 i
+  const int lr = 2 * (tid & 63), lc = tid >> 6;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = min(k0 + lc + 4 * i, K - 1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        ra[2 * i + h] = A[(int64_t)k * lda + min(m0 + lr + h, M - 1)];
+        rb[2 * i + h] = B[(int64_t)k * ldb + min(n0 + lr + h, N - 1)];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool kok = k0 + lc + 4 * i < K;
+        if (!(kok && m0 + lr + h < M)) ra[2 * i + h] = 0.0;
+        if (!(kok && n0 + lr + h < N)) rb[2 * i + h] = 0.0;
+      }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        As[buf][lc + 4 * i][lr + h] = -ra[2 * i + h];  // C -= A B^T
+        Bs[buf][lc + 4 * i][lr + h] = rb[2 * i + h];
+      }
+  };
+  const bool inside = m0 + BG <= M && n0 + BG <= N;
+  // accumulators from C: tile (ti, tj) element (4 e + lk, l16)
+  dbl4t acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 64 + tj * 16 + l16;
+        acc[ti][tj][e] = C[(int64_t)min(gn, N - 1) * ldc + min(gm, M - 1)];
+      }
+  int buf = 0;
+  if (K > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    if (k0 + BK < K) load(k0 + BK);  // in flight during this slice's MFMAs
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[buf][ks + lk][wr * 64 + i * 16 + l16];
+        b[i] = Bs[buf][ks + lk][wc * 64 + i * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (k0 + BK < K) store(buf ^ 1);  // the other buffer: last read a slice ago
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+        const int gn = n0 + wc * 64 + tj * 16 + l16;
+        if (inside || (gm < M && gn < N)) C[(int64_t)gn * ldc + gm] = acc[ti][tj][e];
+      }
+}
+
+int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                       int M, int N, int K, hipStream_t st) {
+  if (M <= 0 || N <= 0) return 0;
+  const int64_t mb = (M + BG - 1) / BG, nbk = (N + BG - 1) / BG;
+  if (mb * nbk >= ((int64_t)1 << 31)) {
+    set_error("GEMM: %lld blocks", (long long)(mb * nbk));
+    return MVG_ERR_LIMIT;
+  }
+  hipLaunchKernelGGL(k_gemm_nt_sub, dim3((unsigned)(mb * nbk)), dim3(256), 0, st, A, lda, B, ldb,
+                     C, ldc, M, N, K, (int)mb);
+  return check_launch("gemm_nt_sub");
+}
+
+int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
+                        hipStream_t st) {
+  if (ntask <= 0 || nblocks <= 0) return 0;
+  if (nblocks >= ((int64_t)1 << 31)) {
+    set_error("batched GEMM: %lld blocks", (long long)nblocks);
+    return MVG_ERR_LIMIT;
+  }
+  hipLaunchKernelGGL(k_gemm_batched, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks, d_start,
+                     ntask);
+  return check_launch("gemm_batched");
+}
+
+int64_t gemm_blocks(const GemmTask &t) {
+  if (t.M <= 0 || t.N <= 0) return 0;
+  return (int64_t)((t.M + GB - 1) / GB) * ((t.N + GB - 1) / GB);
+}
+
+}  // namespace mvg

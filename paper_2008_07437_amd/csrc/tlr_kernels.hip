@@ -1,6 +1,6 @@
 // Batched small dense linear algebra for the tile-low-rank (TLR) path on
-// gfx950: FP64 GEMM on MFMA over lists of variable-size products, Householder
-// QR of tall-skinny matrices (one workgroup per matrix, or panels over
+// gfx950 (the GEMMs are in tlr_gemm.hip): Householder QR of tall-skinny
+// matrices (one workgroup per matrix, or panels over
 // several launches; unpivoted, column-pivoted, or with randomized pivots and
 // a Frobenius-tail stop), Gaussian sketch matrices.  One list entry per product / matrix; the TLR
 // driver builds the lists on the host.
@@ -11,249 +11,6 @@
 namespace mvg {
 
 typedef double dbl4t __attribute__((ext_vector_type(4)));
-
-// ------------------------------------------------------------ batched GEMM
-//
-// C = alpha op(A) op(B) + beta C, column-major, op(X) = X or X^T.  One
-// workgroup per 64 x 64 block of C; four waves of 32 x 32 (2 x 2 tiles of
-// v_mfma_f64_16x16x4f64); K slices of 16 staged through LDS with the next
-// slice's global loads in flight during the current slice's MFMAs.  Ragged
-// edges are zero-filled on load and masked on store.
-constexpr int GB = 64, GK = 16;
-
-__device__ __forceinline__ int find_task(const int64_t *__restrict__ start, int n, int64_t b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict__ tasks,
-                                                      const int64_t *__restrict__ start, int ntask) {
-  __shared__ double As[GK][GB + 2];
-  __shared__ double Bs[GK][GB + 2];
-  const int t = find_task(start, ntask, blockIdx.x);
-  const GemmTask tk = tasks[t];
-  const int mt = (tk.M + GB - 1) / GB;
-  const int64_t local = (int64_t)blockIdx.x - start[t];
-  const int m0 = (int)(local % mt) * GB, n0 = (int)(local / mt) * GB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
-  double ra[4], rb[4];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int m, k;
-      if (!tk.ta) { m = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
-      const int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      // stored element (row, col) = (gm, gk), or (gk, gm) when transposed
-      const bool zero_tri = tk.tri && (tk.ta ? gm > gk : gk > gm);
-      if (gm < tk.M && gk < tk.K && !zero_tri)
-        v = tk.ta ? tk.A[(int64_t)gm * tk.lda + gk] : tk.A[(int64_t)gk * tk.lda + gm];
-      ra[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int n, k;
-      if (tk.tb) { n = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; n = (tid >> 4) + 16 * i; }
-      const int gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < tk.N && gk < tk.K)
-        v = tk.tb ? tk.B[(int64_t)gk * tk.ldb + gn] : tk.B[(int64_t)gn * tk.ldb + gk];
-      rb[i] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!tk.ta) As[(tid >> 6) + 4 * i][tid & 63] = ra[i];
-      else As[tid & 15][(tid >> 4) + 16 * i] = ra[i];
-      if (tk.tb) Bs[(tid >> 6) + 4 * i][tid & 63] = rb[i];
-      else Bs[tid & 15][(tid >> 4) + 16 * i] = rb[i];
-    }
-  };
-  dbl4t acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
-  if (tk.K > 0) load(0);
-  for (int k0 = 0; k0 < tk.K; k0 += GK) {
-    store();
-    __syncthreads();
-    if (k0 + GK < tk.K) load(k0 + GK);
-#pragma unroll
-    for (int ks = 0; ks < GK; ks += 4) {
-      double a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[i] = As[ks + lk][wr * 32 + i * 16 + l16];
-        b[i] = Bs[ks + lk][wc * 32 + i * 16 + l16];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // D[i][j] of a 16 x 16 tile: lane j + 16 (i % 4), element i / 4
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * 32 + i * 16 + 4 * e + lk;
-        const int gn = n0 + wc * 32 + j * 16 + l16;
-        if (gm < tk.M && gn < tk.N) {
-          double *c = tk.C + (int64_t)gn * tk.ldc + gm;
-          const double v = tk.alpha * acc[i][j][e];
-          *c = (tk.beta == 0.0) ? v : v + tk.beta * *c;
-        }
-      }
-}
-
-// ------------------------------------------- C -= A B^T for one large product
-//
-// The column update of the TLR factorisation: C (M x N) -= A (M x K) B^T
-// (B: N x K), column-major, M up to 2e5, N = the tile size, K = the summed
-// ranks.  128 x 128 blocks (four waves of 64 x 64, 4 x 4 tiles of
-// v_mfma_f64_16x16x4f64), K slices of 16 staged through LDS with the next
-// slice's global loads in flight during the current slice's MFMAs (double
-// buffer), accumulators started from C so that the epilogue is stores only.
-// All loads are issued from clamped, always-valid addresses and zeroed
-// outside the matrix after a scheduling barrier (a load under a branch waits
-// for its value); blocks that lie inside C store without masks.
-constexpr int BG = 128, BK = 16;
-
-__global__ __launch_bounds__(256) void k_gemm_nt_sub(const double *__restrict__ A, int lda,
-                                                     const double *__restrict__ B, int ldb,
-                                                     double *__restrict__ C, int ldc, int M, int N,
-                                                     int K, int mblocks) {
-  __shared__ double As[2][BK][BG + 4];
-  __shared__ double Bs[2][BK][BG + 4];
-  const int m0 = (blockIdx.x % mblocks) * BG, n0 = (blockIdx.x / mblocks) * BG;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
-  // loader: thread t takes rows 2 (t % 64) + {0, 1} of slice columns t / 64 + 4 i
-  const int lr = 2 * (tid & 63), lc = tid >> 6;
-  double ra[8], rb[8];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = min(k0 + lc + 4 * i, K - 1);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        ra[2 * i + h] = A[(int64_t)k * lda + min(m0 + lr + h, M - 1)];
-        rb[2 * i + h] = B[(int64_t)k * ldb + min(n0 + lr + h, N - 1)];
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const bool kok = k0 + lc + 4 * i < K;
-        if (!(kok && m0 + lr + h < M)) ra[2 * i + h] = 0.0;
-        if (!(kok && n0 + lr + h < N)) rb[2 * i + h] = 0.0;
-      }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        As[buf][lc + 4 * i][lr + h] = -ra[2 * i + h];  // C -= A B^T
-        Bs[buf][lc + 4 * i][lr + h] = rb[2 * i + h];
-      }
-  };
-  const bool inside = m0 + BG <= M && n0 + BG <= N;
-  // accumulators from C: tile (ti, tj) element (4 e + lk, l16)
-  dbl4t acc[4][4];
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
-        const int gn = n0 + wc * 64 + tj * 16 + l16;
-        acc[ti][tj][e] = C[(int64_t)min(gn, N - 1) * ldc + min(gm, M - 1)];
-      }
-  int buf = 0;
-  if (K > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    if (k0 + BK < K) load(k0 + BK);  // in flight during this slice's MFMAs
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[buf][ks + lk][wr * 64 + i * 16 + l16];
-        b[i] = Bs[buf][ks + lk][wc * 64 + i * 16 + l16];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    if (k0 + BK < K) store(buf ^ 1);  // the other buffer: last read a slice ago
-    __syncthreads();
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
-        const int gn = n0 + wc * 64 + tj * 16 + l16;
-        if (inside || (gm < M && gn < N)) C[(int64_t)gn * ldc + gm] = acc[ti][tj][e];
-      }
-}
-
-int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                       int M, int N, int K, hipStream_t st) {
-  if (M <= 0 || N <= 0) return 0;
-  const int64_t mb = (M + BG - 1) / BG, nbk = (N + BG - 1) / BG;
-  if (mb * nbk >= ((int64_t)1 << 31)) {
-    set_error("GEMM: %lld blocks", (long long)(mb * nbk));
-    return MVG_ERR_LIMIT;
-  }
-  hipLaunchKernelGGL(k_gemm_nt_sub, dim3((unsigned)(mb * nbk)), dim3(256), 0, st, A, lda, B, ldb,
-                     C, ldc, M, N, K, (int)mb);
-  return check_launch("gemm_nt_sub");
-}
-
-int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
-                        hipStream_t st) {
-  if (ntask <= 0 || nblocks <= 0) return 0;
-  if (nblocks >= ((int64_t)1 << 31)) {
-    set_error("batched GEMM: %lld blocks", (long long)nblocks);
-    return MVG_ERR_LIMIT;
-  }
-  hipLaunchKernelGGL(k_gemm_batched, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks, d_start,
-                     ntask);
-  return check_launch("gemm_batched");
-}
-
-int64_t gemm_blocks(const GemmTask &t) {
-  if (t.M <= 0 || t.N <= 0) return 0;
-  return (int64_t)((t.M + GB - 1) / GB) * ((t.N + GB - 1) / GB);
-}
 
 // ---------------------------------------------------------- Householder QR
 //
@@ -722,20 +479,145 @@ int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st
 // panel by panel from the last by the same apply kernel.  A panel step costs
 // two workgroup barriers and one wave-reduction of PQB values; the matrix
 // itself stays in L2 / HBM (an nb x s sketch is up to 6 MB).
-// Requirements (checked by the launcher): m % 4 == 0, n + PQB <= m <= PQ_MAXM.
+// Requirements (checked by the launcher): m % 4 == 0, n + PQB <= m <= PQ_MAXM;
+// and (checked where the tasks are built) lda, ldq even and A, Q 16-byte
+// aligned, for the 16-byte loads of the apply and sample kernels.
 constexpr int PQB = 16;          // panel width
 constexpr int PQ_MAXM = 1536;    // rows: 6 (3) per panel thread of 256 (512)
 constexpr int PAP_CB = 32;       // columns per apply workgroup
-constexpr int PAP_THREADS = 256; // apply workgroup (4 waves)
+
+// Cross-lane sums without LDS.  Inside a row of 16 lanes the exchanges are
+// DPP moves: quad_perm [1,0,3,2] pairs lane i with i ^ 1, quad_perm
+// [2,3,0,1] with i ^ 2, row_half_mirror with i ^ 7 and row_mirror with
+// i ^ 15.  Across rows, gfx950's lane swaps exchange whole halves of two
+// registers: v_permlane16_swap swaps the odd rows of its first operand with
+// the even rows of its second, v_permlane32_swap lanes 32-63 of the first
+// with lanes 0-31 of the second.  Each all-reduce step adds a value and its
+// partner's, so a lane and its partner form the same sum in swapped order:
+// every lane of a group ends with bitwise the same result.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_XOR7 = 0x141, DPP_XOR15 = 0x140;
+
+__device__ __forceinline__ double join_d(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// x + y after swapping the odd rows of x with the even rows of y: rows 0, 2
+// get x's rows 0 + 1 and 2 + 3, rows 1, 3 get y's
+__device__ __forceinline__ double swap16_add(double x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false,
+                                                   false);
+  return join_d(lo[0], hi[0]) + join_d(lo[1], hi[1]);
+}
+
+// x + y after swapping lanes 32-63 of x with lanes 0-31 of y: lanes 0-31
+// get x's halves summed, lanes 32-63 y's
+__device__ __forceinline__ double swap32_add(double x, double y) {
+  const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false,
+                                                   false);
+  return join_d(lo[0], hi[0]) + join_d(lo[1], hi[1]);
+}
+
+// sum over the 64 lanes, in every lane
+__device__ __forceinline__ double wave_sum(double s) {
+  s += dpp_d<DPP_XOR15>(s);
+  s += dpp_d<DPP_XOR7>(s);
+  s += dpp_d<DPP_XOR2>(s);
+  s += dpp_d<DPP_XOR1>(s);
+  s = swap16_add(s, s);
+  return swap32_add(s, s);
+}
+
+// Sums over the 64 lanes of 16 values at once, halving the values a lane
+// holds at each step (the lane keeps the half selected by one bit of its
+// index and receives its partner's values of that half): lane i ends with
+// the sum of value ((i >> 2) & 15), the same in the four lanes of a quad.
+// The two cross-row halvings are lane swaps (no selects); the two in-row
+// halvings are DPP moves with selects; the last two steps are all-reduces.
+__device__ __forceinline__ double wave_sum16(const double (&d)[16], int lane) {
+  double h8[8], h4[4], h2[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) h8[k] = swap32_add(d[k], d[k + 8]);   // value k + 8 (lane bit 5)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) h4[k] = swap16_add(h8[k], h8[k + 4]); // + 4 (lane bit 4)
+  const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {  // + 2 (lane bit 3)
+    const double keep = b3 ? h4[k + 2] : h4[k], send = b3 ? h4[k] : h4[k + 2];
+    h2[k] = keep + dpp_d<DPP_XOR15>(send);
+  }
+  double s;
+  {  // + 1 (lane bit 2)
+    const double keep = b2 ? h2[1] : h2[0], send = b2 ? h2[0] : h2[1];
+    s = keep + dpp_d<DPP_XOR7>(send);
+  }
+  s += dpp_d<DPP_XOR2>(s);
+  s += dpp_d<DPP_XOR1>(s);
+  return s;
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+// (b, i) <- the larger of (b, i) and (ob, oi): larger value, ties to the
+// lower index (a total order, so both partners of a step keep the same pair)
+__device__ __forceinline__ void argmax_step(double &b, int &i, double ob, int oi) {
+  if (ob > b || (ob == b && oi < i)) {
+    b = ob;
+    i = oi;
+  }
+}
+
+// the pair with the largest value over the 64 lanes (ties to the lowest
+// index), in every lane
+__device__ __forceinline__ void wave_argmax(double &b, int &i) {
+  argmax_step(b, i, dpp_d<DPP_XOR15>(b), dpp_i<DPP_XOR15>(i));
+  argmax_step(b, i, dpp_d<DPP_XOR7>(b), dpp_i<DPP_XOR7>(i));
+  argmax_step(b, i, dpp_d<DPP_XOR2>(b), dpp_i<DPP_XOR2>(i));
+  argmax_step(b, i, dpp_d<DPP_XOR1>(b), dpp_i<DPP_XOR1>(i));
+  {  // rows 2k and 2k + 1: each lane gets both rows' pairs (its own is one of them)
+    const long long bb = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bb, (unsigned)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bb >> 32), (unsigned)(bb >> 32), false,
+                                                     false);
+    const auto ii = __builtin_amdgcn_permlane16_swap((unsigned)i, (unsigned)i, false, false);
+    b = join_d(lo[0], hi[0]);
+    i = (int)ii[0];
+    argmax_step(b, i, join_d(lo[1], hi[1]), (int)ii[1]);
+  }
+  {  // halves 0-31 and 32-63
+    const long long bb = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bb, (unsigned)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bb >> 32), (unsigned)(bb >> 32), false,
+                                                     false);
+    const auto ii = __builtin_amdgcn_permlane32_swap((unsigned)i, (unsigned)i, false, false);
+    b = join_d(lo[0], hi[0]);
+    i = (int)ii[0];
+    argmax_step(b, i, join_d(lo[1], hi[1]), (int)ii[1]);
+  }
+}
 
 // T factors in tk.tau: panel p0 at rows p0 .. p0 + PQB - 1 of a PQB-wide
 // row-major array ((n + PQB) x PQB doubles).
-template <int RPT, int NT>
+template <int RPT, int NT, bool UNR>
 __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ tasks, int p0) {
   __shared__ double red_s[NT / 64];
   __shared__ double red_d[NT / 64][PQB];
   __shared__ double s_alpha;
-  __shared__ double sT[PQB][PQB];
+  __shared__ double s_tau[PQB];
+  __shared__ double sG[PQB][PQB + 1];  // sG[c][jj] = V[:, c]^T v_jj, c < jj
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, n = tk.n, lda = tk.lda;
   if (p0 >= n) return;  // uniform: this task has no panel here
@@ -743,7 +625,7 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
   const int pb = min(PQB, n - p0);
   double *A = tk.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // rows p0 + tid + 512 e of the panel columns: loaded together from clamped
+  // rows p0 + tid + NT e of the panel columns: loaded together from clamped
   // addresses, zeroed outside the matrix after a scheduling barrier
   double a[RPT][PQB];
 #pragma unroll
@@ -758,7 +640,9 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
 #pragma unroll
     for (int c = 0; c < PQB; ++c)
       if (p0 + tid + NT * e >= m || c >= pb) a[e][c] = 0.0;
-  for (int jj = 0; jj < pb; ++jj) {
+  // one reflector step; with UNR the 16 steps are unrolled so that the column
+  // index jj is a constant in each (no per-element selects on it)
+  auto step = [&](const int jj) __attribute__((always_inline)) {
     const int j = p0 + jj;
     // squared norm of column jj below row j, and its entry on row j
     double ss = 0.0;
@@ -772,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
       if (r > j) ss += x * x;
       if (r == j) s_alpha = x;
     }
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+    ss = wave_sum(ss);
     if (lane == 0) red_s[wave] = ss;
     __syncthreads();
     double sigma2 = 0.0;
@@ -808,47 +692,41 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
 #pragma unroll
       for (int e = 0; e < RPT; ++e) d[c] += a[e][c] * v[e];
     }
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int c = 0; c < PQB; ++c) d[c] += __shfl_xor(d[c], o);
-    if (lane == 0)
-#pragma unroll
-      for (int c = 0; c < PQB; ++c) red_d[wave][c] = d[c];
-    __syncthreads();
     {
-      // lane c < PQB sums the waves' partials of column c in a fixed order,
-      // then every lane takes the sums from those lanes (reading all of
-      // red_d per lane would hold 128 values in registers)
-      double part = 0.0;
-      if (lane < PQB)
-#pragma unroll
-        for (int w = 0; w < NT / 64; ++w) part += red_d[w][lane];
-#pragma unroll
-      for (int c = 0; c < PQB; ++c) d[c] = __shfl(part, c);
+      const double dw = wave_sum16(d, lane);  // this wave's sum of column (lane >> 2) & 15
+      if ((lane & 3) == 0) red_d[wave][lane >> 2] = dw;
     }
-    // rows >= j of the columns right of jj: a -= tau (v^T a) v
+    __syncthreads();
+    // lane c < PQB sums the waves' partials of column c in a fixed order;
+    // every lane reads the 16 sums from those lanes (uniform values)
+    double part = 0.0;
+    if (lane < PQB)
 #pragma unroll
-    for (int e = 0; e < RPT; ++e)
+      for (int w = 0; w < NT / 64; ++w) part += red_d[w][lane];
+    if (tid < jj) sG[tid][jj] = part;  // wave 0: column tid of V against v_jj
+    if (tid == 0) s_tau[jj] = tau;
+    const long long pbits = __double_as_longlong(part);
+    // rows >= j of the columns right of jj: a -= tau (v^T a) v (a zero
+    // multiplier leaves the other columns as they are)
 #pragma unroll
-      for (int c = 0; c < PQB; ++c)
-        if (c > jj) a[e][c] -= tau * d[c] * v[e];
-    // column jj of T (thread c owns row c of T): T_jj = tau,
-    // T[c][jj] = -tau sum_{c <= l < jj} T[c][l] (V[:, l]^T v_jj)
-    if (tid < jj) {
-      double t = 0.0;
-      for (int l = tid; l < jj; ++l) {
-        double dl = 0.0;
+    for (int c = 0; c < PQB; ++c) {
+      const int lo = __builtin_amdgcn_readlane((int)pbits, c);
+      const int hi = __builtin_amdgcn_readlane((int)(pbits >> 32), c);
+      const double dc = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+      if (UNR && c <= jj) continue;  // constant when unrolled
+      const double td = c > jj ? tau * dc : 0.0;
 #pragma unroll
-        for (int c = 0; c < PQB; ++c)
-          if (c == l) dl = d[c];
-        t += sT[tid][l] * dl;
-      }
-      sT[tid][jj] = -tau * t;
-    } else if (tid == jj) {
-      sT[jj][jj] = tau;
+      for (int e = 0; e < RPT; ++e) a[e][c] -= td * v[e];
     }
+  };
+  if constexpr (UNR) {
+#pragma unroll
+    for (int jj = 0; jj < PQB; ++jj)
+      if (jj < pb) step(jj);
+  } else {
+    for (int jj = 0; jj < pb; ++jj) step(jj);
   }
-  // the panel back (R on and above the diagonal, reflectors below), and T
+  // the panel back (R on and above the diagonal, reflectors below)
 #pragma unroll
   for (int e = 0; e < RPT; ++e) {
     const int r = p0 + tid + NT * e;
@@ -857,9 +735,22 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
       for (int c = 0; c < PQB; ++c)
         if (c < pb) A[(int64_t)(p0 + c) * lda + r] = a[e][c];
   }
+  // T, row c by thread c: T_cc = tau_c, T[c][b] = -tau_b sum_{c <= l < b}
+  // T[c][l] (V[:, l]^T v_b) for b > c; zero outside the pb x pb block
+  __syncthreads();
   if (tid < PQB) {
+    double t[PQB];
+#pragma unroll
+    for (int b = 0; b < PQB; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < b; ++l)
+        if (l >= tid) acc += t[l] * sG[l][b];
+      t[b] = (b < tid || tid >= pb || b >= pb) ? 0.0 : (b == tid ? s_tau[b] : -s_tau[b] * acc);
+    }
     double *Tg = tk.tau + (int64_t)(p0 + tid) * PQB;
-    for (int b = 0; b < PQB; ++b) Tg[b] = (tid < pb && b < pb && b >= tid) ? sT[tid][b] : 0.0;
+#pragma unroll
+    for (int b = 0; b < PQB; ++b) Tg[b] = t[b];
   }
 }
 
@@ -872,22 +763,14 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrTask *__restrict__ task
 // in K-step s lane l holds row r0 + 4 (l / 16) + s, so a lane's four rows
 // are consecutive (one 32-byte load per column); then W' = op(T) W in LDS;
 // then X -= V W' on the same MFMA with X tiles as accumulators.
-template <int MODE>
-__global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restrict__ tasks, int p0,
-                                                          int nblk) {
-  __shared__ double sW[PAP_THREADS / 64][PQB][PAP_CB + 1];
+template <int MODE, int NTH>
+__device__ __forceinline__ void apply_panel(const QrTask &tk, const int p0, const int c0) {
+  __shared__ double sW[NTH / 64][PQB][PAP_CB + 1];
   __shared__ double sN[PQB][PAP_CB + 1];  // -op(T) W
   __shared__ double sT[PQB][PQB + 1];
-  __shared__ double sC[PAP_THREADS / 64][PAP_CB];
-  const QrTask tk = tasks[blockIdx.x / nblk];
-  const int b = blockIdx.x % nblk;
+  __shared__ double sC[NTH / 64][PAP_CB];
   const int m = tk.m, n = tk.n, lda = tk.lda;
-  if (p0 >= n) return;
-  if (MODE == 1 && !tk.Q) return;
-  if (tk.rank && *tk.rank <= p0) return;  // pivoted form: truncated before this panel
   const int pb = min(PQB, n - p0);
-  const int c0 = (MODE == 0 ? p0 + pb : p0) + PAP_CB * b;
-  if (c0 >= n) return;  // uniform per workgroup
   double *X = MODE == 0 ? tk.A : tk.Q;
   const int ldx = MODE == 0 ? lda : tk.ldq;
   const int M = m - p0;  // rows of the block (a multiple of 4)
@@ -902,17 +785,26 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
   dbl4t acc[2] = {dbl4t{0.0, 0.0, 0.0, 0.0}, dbl4t{0.0, 0.0, 0.0, 0.0}};
   // two chunks per iteration (ch and ch + 4 waves), all their loads issued
   // together; a chunk past the end is read from clamped rows and masked
-  constexpr int NW = PAP_THREADS / 64;
+  constexpr int NW = NTH / 64;
   for (int ch = wave; ch < nchunk; ch += 2 * NW) {
     double vv[2][4], x0[2][4], x1[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
+      // the lane's 4 rows as two 16-byte loads per column (even offsets:
+      // lda, ldx and p0 are even, rl a multiple of 4)
       const int rl = min(16 * (ch + u * NW) + 4 * lk, M - 4);  // in bounds (M % 4 == 0)
+      const double2 *pv = (const double2 *)(V + (int64_t)qv * lda + rl);
+      const double2 *pa = (const double2 *)(X + (int64_t)xc0 * ldx + p0 + rl);
+      const double2 *pc = (const double2 *)(X + (int64_t)xc1 * ldx + p0 + rl);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        vv[u][s] = V[(int64_t)qv * lda + rl + s];
-        x0[u][s] = X[(int64_t)xc0 * ldx + p0 + rl + s];
-        x1[u][s] = X[(int64_t)xc1 * ldx + p0 + rl + s];
+      for (int h = 0; h < 2; ++h) {
+        const double2 v2 = pv[h], a2 = pa[h], c2 = pc[h];
+        vv[u][2 * h] = v2.x;
+        vv[u][2 * h + 1] = v2.y;
+        x0[u][2 * h] = a2.x;
+        x0[u][2 * h + 1] = a2.y;
+        x1[u][2 * h] = c2.x;
+        x1[u][2 * h + 1] = c2.y;
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -945,15 +837,15 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
   }
   __syncthreads();
   // the four waves' partial sums, in a fixed order
-  for (int o = tid; o < PQB * PAP_CB; o += PAP_THREADS) {
+  for (int o = tid; o < PQB * PAP_CB; o += NTH) {
     const int q = o / PAP_CB, c = o % PAP_CB;
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < PAP_THREADS / 64; ++w) t += sW[w][q][c];
+    for (int w = 0; w < NTH / 64; ++w) t += sW[w][q][c];
     sW[0][q][c] = t;
   }
   __syncthreads();
-  for (int o = tid; o < PQB * PAP_CB; o += PAP_THREADS) {
+  for (int o = tid; o < PQB * PAP_CB; o += NTH) {
     const int q = o / PAP_CB, c = o % PAP_CB;
     double t = 0.0;
 #pragma unroll
@@ -961,79 +853,124 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_apply(const QrTask *__restri
     sN[q][c] = -t;
   }
   __syncthreads();
-  // ---- X -= V W'  (accumulators start from the X tiles); with tk.work
-  // (pivoted form, MODE 0) also the squared norms of the updated columns
-  // below the panel's rows (rows p0 + pb ..), for the truncation test
-  double css[2] = {0.0, 0.0};
-  double nq[4][2];  // -W' operands of this lane: rows 4 s + lk, columns 16 h + l16
+  // ---- X -= V W', as X^T -= W'^T V^T so that a lane's accumulator holds
+  // one row of 8 columns (16 lanes: 16 consecutive rows of a column per
+  // load / store); accumulators start from X.  With tk.work (pivoted form,
+  // MODE 0) also the squared norms of the updated columns below the panel's
+  // rows (rows p0 + pb ..), for the truncation test.
+  double css[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  double nq[4][2];  // -W'^T operands of this lane: q = 4 s + lk, column 16 h + l16
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int h = 0; h < 2; ++h) nq[s][h] = sN[4 * s + lk][16 * h + l16];
+  int xcol[2][4];  // clamped columns of this lane's accumulator elements
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xcol[h][e] = min(c0 + 16 * h + 4 * e + lk, n - 1);
   for (int ch = wave; ch < nchunk; ch += 2 * NW) {
     double va[2][4];
     dbl4t xt[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int r0 = 16 * (ch + u * NW);
-      const int rv = min(r0 + l16, M - 1);      // V row of this lane (A operand)
+      const int rv = min(16 * (ch + u * NW) + l16, M - 1);  // this lane's row
 #pragma unroll
       for (int s = 0; s < 4; ++s) va[u][s] = V[(int64_t)min(4 * s + lk, pb - 1) * lda + rv];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int rx = min(r0 + 4 * e + lk, M - 1);
-        xt[u][0][e] = X[(int64_t)xc0 * ldx + p0 + rx];
-        xt[u][1][e] = X[(int64_t)xc1 * ldx + p0 + rx];
-      }
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xt[u][h][e] = X[(int64_t)xcol[h][e] * ldx + p0 + rv];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int r0 = 16 * (ch + u * NW);
+      const int r = 16 * (ch + u * NW) + l16;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int q = 4 * s + lk, r = r0 + l16;
+        const int q = 4 * s + lk;
         double vq = va[u][s];
         if (r < q) vq = 0.0;
         else if (r == q) vq = 1.0;
         if (r >= M || q >= pb) vq = 0.0;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-          xt[u][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vq, nq[s][h], xt[u][h], 0, 0, 0);
+          xt[u][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(nq[s][h], vq, xt[u][h], 0, 0, 0);
       }
+      if (r < M) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int rx = r0 + 4 * e + lk;
-        if (rx < M) {
-          if (xok0) X[(int64_t)xc0 * ldx + p0 + rx] = xt[u][0][e];
-          if (xok1) X[(int64_t)xc1 * ldx + p0 + rx] = xt[u][1][e];
-          if (rx >= pb) {
-            css[0] += xt[u][0][e] * xt[u][0][e];
-            css[1] += xt[u][1][e] * xt[u][1][e];
-          }
-        }
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c0 + 16 * h + 4 * e + lk < n) X[(int64_t)xcol[h][e] * ldx + p0 + r] = xt[u][h][e];
+        if (r >= pb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) css[h][e] += xt[u][h][e] * xt[u][h][e];
       }
     }
   }
   if (MODE == 0 && tk.work) {
-    // the four lanes of a column (l16 + 16 lk) in a fixed order, then the
-    // waves in a fixed order
+    // the 16 lanes (rows) of a column in a fixed order, then the waves in a
+    // fixed order
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      css[h] += __shfl_xor(css[h], 16);
-      css[h] += __shfl_xor(css[h], 32);
-    }
-    if (lk == 0) {
-      sC[wave][l16] = css[0];
-      sC[wave][16 + l16] = css[1];
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double c = css[h][e];
+        c += dpp_d<DPP_XOR15>(c);
+        c += dpp_d<DPP_XOR7>(c);
+        c += dpp_d<DPP_XOR2>(c);
+        c += dpp_d<DPP_XOR1>(c);
+        if (l16 == 0) sC[wave][16 * h + 4 * e + lk] = c;
+      }
     __syncthreads();
     if (tid < PAP_CB && c0 + tid < n) {
       double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < PAP_THREADS / 64; ++w) t += sC[w][tid];
+      for (int w = 0; w < NTH / 64; ++w) t += sC[w][tid];
       tk.work[(int64_t)QRS_ROWS * (m + n) + c0 + tid] = t;
     }
+  }
+}
+
+template <int MODE, int NTH>
+__global__ __launch_bounds__(NTH) void k_qr_apply(const QrTask *__restrict__ tasks, int p0,
+                                                          int nblk) {
+  const QrTask tk = tasks[blockIdx.x / nblk];
+  const int n = tk.n;
+  if (p0 >= n) return;
+  if (MODE == 1 && !tk.Q) return;
+  if (tk.rank && *tk.rank <= p0) return;  // pivoted form: truncated before this panel
+  const int pb = min(PQB, n - p0);
+  const int c0 = (MODE == 0 ? p0 + pb : p0) + PAP_CB * (blockIdx.x % nblk);
+  if (c0 >= n) return;  // uniform per workgroup
+  apply_panel<MODE, NTH>(tk, p0, c0);
+}
+
+// Q = H_1 ... H_P [I; 0] in one launch: a workgroup owns PAP_CB columns of Q
+// (columns are transformed independently), sets them to [I; 0] and applies
+// the panels' block reflectors from the last to the first.  A panel at p0
+// leaves columns left of p0 unchanged (their rows from p0 down are zero), so
+// the workgroup skips the panels right of its columns; the arithmetic per
+// column is that of the apply kernel launched once per panel.
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_qr_formq(const QrTask *__restrict__ tasks, int nblk) {
+  const QrTask tk = tasks[blockIdx.x / nblk];
+  if (!tk.Q) return;
+  const int n = tk.n, m = tk.m;
+  const int c0 = PAP_CB * (blockIdx.x % nblk);
+  if (c0 >= n) return;  // uniform per workgroup
+  for (int c = c0; c < min(c0 + PAP_CB, n); ++c)
+    for (int i = threadIdx.x; i < m; i += NTH) tk.Q[(int64_t)c * tk.ldq + i] = (i == c) ? 1.0 : 0.0;
+  __syncthreads();
+  const int last = min(n - 1, c0 + PAP_CB - 1);
+  const int plim = tk.rank ? min(n, *tk.rank) : n;  // pivoted form: panels before the rank
+  for (int p0 = ((n - 1) / PQB) * PQB; p0 >= 0; p0 -= PQB) {
+    if (p0 > last || p0 >= plim) continue;  // uniform
+    apply_panel<1, NTH>(tk, p0, c0);
+    __syncthreads();
   }
 }
 
@@ -1064,9 +1001,10 @@ __global__ void k_qr_rinit(const QrTask *__restrict__ tasks) {
 
 // G[:, c] = Omega(0 : m - q0, :)^T A(q0 : m, c) for columns c >= q0, PAP_CB
 // columns per workgroup (same MFMA layout as the first product of k_qr_apply).
-__global__ __launch_bounds__(PAP_THREADS) void k_qr_sample(const QrTask *__restrict__ tasks, int q0,
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_qr_sample(const QrTask *__restrict__ tasks, int q0,
                                                            int nblk) {
-  __shared__ double sW[PAP_THREADS / 64][QRS_ROWS][PAP_CB + 1];
+  __shared__ double sW[NTH / 64][QRS_ROWS][PAP_CB + 1];
   const QrTask tk = tasks[blockIdx.x / nblk];
   const int b = blockIdx.x % nblk;
   const int m = tk.m, n = tk.n, lda = tk.lda;
@@ -1086,16 +1024,27 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_sample(const QrTask *__restr
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
-  for (int ch = wave; ch < nchunk; ch += PAP_THREADS / 64) {
+  for (int ch = wave; ch < nchunk; ch += NTH / 64) {
     const int rr = 16 * ch + 4 * lk;
     const int rl = min(rr, M - 4);
     double o0[4], o1[4], x0[4], x1[4];
+    {  // two 16-byte loads per column (m, lda and q0 even, rl a multiple of 4)
+      const double2 *p0 = (const double2 *)(Om + (int64_t)l16 * m + rl);
+      const double2 *p1 = (const double2 *)(Om + (int64_t)(16 + l16) * m + rl);
+      const double2 *pa = (const double2 *)(tk.A + (int64_t)xc0 * lda + q0 + rl);
+      const double2 *pc = (const double2 *)(tk.A + (int64_t)xc1 * lda + q0 + rl);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      o0[s] = Om[(int64_t)l16 * m + rl + s];
-      o1[s] = Om[(int64_t)(16 + l16) * m + rl + s];
-      x0[s] = tk.A[(int64_t)xc0 * lda + q0 + rl + s];
-      x1[s] = tk.A[(int64_t)xc1 * lda + q0 + rl + s];
+      for (int h = 0; h < 2; ++h) {
+        const double2 a = p0[h], b = p1[h], c = pa[h], d = pc[h];
+        o0[2 * h] = a.x;
+        o0[2 * h + 1] = a.y;
+        o1[2 * h] = b.x;
+        o1[2 * h + 1] = b.y;
+        x0[2 * h] = c.x;
+        x0[2 * h + 1] = c.y;
+        x1[2 * h] = d.x;
+        x1[2 * h + 1] = d.y;
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1117,11 +1066,11 @@ __global__ __launch_bounds__(PAP_THREADS) void k_qr_sample(const QrTask *__restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) sW[wave][16 * i + 4 * e + lk][16 * j + l16] = acc[i][j][e];
   __syncthreads();
-  for (int o = tid; o < QRS_ROWS * PAP_CB; o += PAP_THREADS) {
+  for (int o = tid; o < QRS_ROWS * PAP_CB; o += NTH) {
     const int q = o % QRS_ROWS, c = o / QRS_ROWS;
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < PAP_THREADS / 64; ++w) t += sW[w][q][c];
+    for (int w = 0; w < NTH / 64; ++w) t += sW[w][q][c];
     if (c0 + c < n) G[(int64_t)(c0 + c) * QRS_ROWS + q] = t;
   }
 }
@@ -1140,6 +1089,7 @@ __global__ __launch_bounds__(PICK_THREADS) void k_qr_pick(const QrTask *__restri
   __shared__ double scol[2][QRS_ROWS];  // the two columns of a swap
   __shared__ double sv[QRS_ROWS];
   __shared__ int sswap[PQB];
+  __shared__ int smove[2][2 * PQB];  // positions moved to, and the start of their columns
   __shared__ double s_tau;
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, n = tk.n, lda = tk.lda;
@@ -1176,14 +1126,7 @@ __global__ __launch_bounds__(PICK_THREADS) void k_qr_pick(const QrTask *__restri
         bi = c;
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
+    wave_argmax(best, bi);
     if (lane == 0) {
       s_best[wave] = best;
       s_bidx[wave] = bi;
@@ -1259,24 +1202,40 @@ __global__ __launch_bounds__(PICK_THREADS) void k_qr_pick(const QrTask *__restri
     }
     __syncthreads();  // s_best, scol, sv and s_tau are rewritten next step
   }
-  // the swaps on A and on the column order, in sequence
-  for (int t = 0; t < steps; ++t) {
-    const int pcol = sswap[t];
-    if (pcol != t) {
-      double *ca = tk.A + (int64_t)(p0 + t) * lda, *cb = tk.A + (int64_t)(p0 + pcol) * lda;
-      for (int r = tid; r < m; r += PICK_THREADS) {
-        const double a = ca[r];
-        ca[r] = cb[r];
-        cb[r] = a;
-      }
-      if (tid == 0) {
-        const int a = tk.piv[p0 + t];
-        tk.piv[p0 + t] = tk.piv[p0 + pcol];
-        tk.piv[p0 + pcol] = a;
-      }
+  // The swaps (t, sswap[t]) in sequence, applied at once: every position a
+  // swap touches (t, or sswap[t]) receives the column that started at
+  // src(q), found by undoing the swaps from the last; a thread moves its rows
+  // of all those columns (all loads before any store; repeated positions
+  // move the same value twice), and the column order likewise.
+  if (tid < 2 * steps) {
+    const int q = tid < steps ? tid : sswap[tid - steps];
+    int src = q;
+    for (int t = steps - 1; t >= 0; --t) {
+      const int pc = sswap[t];
+      if (src == t) src = pc;
+      else if (src == pc) src = t;
     }
-    __syncthreads();
+    smove[0][tid] = q;
+    smove[1][tid] = src;
   }
+  __syncthreads();
+  const int nmv = 2 * steps;
+  int pv = 0;
+  if (tid < nmv) pv = tk.piv[p0 + smove[1][tid]];
+  for (int r0 = 0; r0 < m; r0 += PICK_THREADS) {
+    const int r = min(r0 + tid, m - 1);
+    double val[2 * PQB];
+#pragma unroll
+    for (int k = 0; k < 2 * PQB; ++k)
+      val[k] = tk.A[(int64_t)(p0 + smove[1][min(k, nmv - 1)]) * lda + r];
+    __builtin_amdgcn_sched_barrier(0);
+    if (r0 + tid < m)
+#pragma unroll
+      for (int k = 0; k < 2 * PQB; ++k)
+        if (k < nmv) tk.A[(int64_t)(p0 + smove[0][k]) * lda + r] = val[k];
+  }
+  __syncthreads();  // every piv read above precedes the writes
+  if (tid < nmv) tk.piv[p0 + smove[0][tid]] = pv;
 }
 
 // Truncation test after the panel at p0 (one workgroup per task): squared
@@ -1346,7 +1305,8 @@ __global__ void k_qr_qinit(const QrTask *__restrict__ tasks, int nblk) {
 }
 
 // Panel workgroup size: 256 threads (rows per thread ceil(m / 256)) or 512
-// (MVG_QR_PANEL_THREADS=512, experiments).
+// (MVG_QR_PANEL_THREADS=512, experiments); reflector steps unrolled unless
+// MVG_QR_PANEL_UNROLL=0 (experiments).
 static int panel_threads() {
   static const int t = [] {
     const char *e = getenv("MVG_QR_PANEL_THREADS");
@@ -1355,26 +1315,92 @@ static int panel_threads() {
   return t;
 }
 
-static void launch_panel(const QrTask *d_tasks, int ntask, int mmax, int p0, hipStream_t st) {
+static bool panel_unroll() {
+  static const bool u = [] {
+    const char *e = getenv("MVG_QR_PANEL_UNROLL");
+    return !(e && atoi(e) == 0);
+  }();
+  return u;
+}
+
+template <bool UNR>
+static void launch_panel_t(const QrTask *d_tasks, int ntask, int mmax, int p0, hipStream_t st) {
   const dim3 g(ntask);
   if (panel_threads() == 512) {
     const int rpt = (mmax + 511) / 512;
     if (rpt == 1)
-      hipLaunchKernelGGL((k_qr_panel<1, 512>), g, dim3(512), 0, st, d_tasks, p0);
+      hipLaunchKernelGGL((k_qr_panel<1, 512, UNR>), g, dim3(512), 0, st, d_tasks, p0);
     else if (rpt == 2)
-      hipLaunchKernelGGL((k_qr_panel<2, 512>), g, dim3(512), 0, st, d_tasks, p0);
+      hipLaunchKernelGGL((k_qr_panel<2, 512, UNR>), g, dim3(512), 0, st, d_tasks, p0);
     else
-      hipLaunchKernelGGL((k_qr_panel<3, 512>), g, dim3(512), 0, st, d_tasks, p0);
+      hipLaunchKernelGGL((k_qr_panel<3, 512, UNR>), g, dim3(512), 0, st, d_tasks, p0);
     return;
   }
   const int rpt = (mmax + 255) / 256;
   switch (rpt) {
-    case 1: hipLaunchKernelGGL((k_qr_panel<1, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
-    case 2: hipLaunchKernelGGL((k_qr_panel<2, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
-    case 3: hipLaunchKernelGGL((k_qr_panel<3, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
-    case 4: hipLaunchKernelGGL((k_qr_panel<4, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
-    case 5: hipLaunchKernelGGL((k_qr_panel<5, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
-    default: hipLaunchKernelGGL((k_qr_panel<6, 256>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 1: hipLaunchKernelGGL((k_qr_panel<1, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 2: hipLaunchKernelGGL((k_qr_panel<2, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 3: hipLaunchKernelGGL((k_qr_panel<3, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 4: hipLaunchKernelGGL((k_qr_panel<4, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+    case 5: hipLaunchKernelGGL((k_qr_panel<5, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+    default: hipLaunchKernelGGL((k_qr_panel<6, 256, UNR>), g, dim3(256), 0, st, d_tasks, p0); break;
+  }
+}
+
+static void launch_panel(const QrTask *d_tasks, int ntask, int mmax, int p0, hipStream_t st) {
+  if (panel_unroll())
+    launch_panel_t<true>(d_tasks, ntask, mmax, p0, st);
+  else
+    launch_panel_t<false>(d_tasks, ntask, mmax, p0, st);
+}
+
+// Apply / sample workgroup size: 512 threads (8 waves share a column
+// block's rows), or 256 / 1024 (apply; the sample stays at 512) by
+// MVG_QR_APPLY_THREADS (experiments).
+static int apply_threads() {
+  static const int t = [] {
+    const char *e = getenv("MVG_QR_APPLY_THREADS");
+    const int v = e ? atoi(e) : 512;
+    return v == 256 || v == 1024 ? v : 512;
+  }();
+  return t;
+}
+
+template <int MODE>
+static void launch_apply(const QrTask *d_tasks, int ntask, int nblk, int p0, hipStream_t st) {
+  const dim3 g(ntask * nblk);
+  switch (apply_threads()) {
+    case 256: hipLaunchKernelGGL((k_qr_apply<MODE, 256>), g, dim3(256), 0, st, d_tasks, p0, nblk); break;
+    case 1024: hipLaunchKernelGGL((k_qr_apply<MODE, 1024>), g, dim3(1024), 0, st, d_tasks, p0, nblk); break;
+    default: hipLaunchKernelGGL((k_qr_apply<MODE, 512>), g, dim3(512), 0, st, d_tasks, p0, nblk); break;
+  }
+}
+
+// Q formation in one launch (k_qr_formq) unless MVG_QR_FORMQ_FUSED=0
+// (experiments: one apply launch per panel).
+static bool formq_fused() {
+  static const bool f = [] {
+    const char *e = getenv("MVG_QR_FORMQ_FUSED");
+    return !(e && atoi(e) == 0);
+  }();
+  return f;
+}
+
+static void launch_formq(const QrTask *d_tasks, int ntask, int nmax, hipStream_t st) {
+  const int nblk = (nmax + PAP_CB - 1) / PAP_CB;
+  const dim3 g(ntask * nblk);
+  switch (apply_threads()) {
+    case 256: hipLaunchKernelGGL((k_qr_formq<256>), g, dim3(256), 0, st, d_tasks, nblk); break;
+    case 1024: hipLaunchKernelGGL((k_qr_formq<1024>), g, dim3(1024), 0, st, d_tasks, nblk); break;
+    default: hipLaunchKernelGGL((k_qr_formq<512>), g, dim3(512), 0, st, d_tasks, nblk); break;
+  }
+}
+
+static void launch_sample(const QrTask *d_tasks, int ntask, int sblk, int p0, hipStream_t st) {
+  const dim3 g(ntask * sblk);
+  switch (apply_threads()) {
+    case 256: hipLaunchKernelGGL((k_qr_sample<256>), g, dim3(256), 0, st, d_tasks, p0, sblk); break;
+    default: hipLaunchKernelGGL((k_qr_sample<512>), g, dim3(512), 0, st, d_tasks, p0, sblk); break;
   }
 }
 
@@ -1395,19 +1421,21 @@ int launch_qr_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, bool 
     const int rest = nmax - p0 - PQB;
     if (rest > 0) {
       const int nblk = (rest + PAP_CB - 1) / PAP_CB;
-      hipLaunchKernelGGL((k_qr_apply<0>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks,
-                         p0, nblk);
+      launch_apply<0>(d_tasks, ntask, nblk, p0, st);
       if (int rc = check_launch("qr_apply")) return rc;
     }
   }
   if (!with_q) return 0;
+  if (formq_fused()) {
+    launch_formq(d_tasks, ntask, nmax, st);
+    return check_launch("qr_formq");
+  }
   const int qb = (nmax + 63) / 64;
   hipLaunchKernelGGL(k_qr_qinit, dim3(ntask * qb), dim3(256), 0, st, d_tasks, qb);
   if (int rc = check_launch("qr_qinit")) return rc;
   for (int p0 = ((nmax - 1) / PQB) * PQB; p0 >= 0; p0 -= PQB) {
     const int nblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
-    hipLaunchKernelGGL((k_qr_apply<1>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks, p0,
-                       nblk);
+    launch_apply<1>(d_tasks, ntask, nblk, p0, st);
     if (int rc = check_launch("qr_apply")) return rc;
   }
   return 0;
@@ -1427,7 +1455,7 @@ int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hip
   if (int rc = check_launch("qr_rinit")) return rc;
   for (int p0 = 0; p0 < nmax; p0 += PQB) {
     const int sblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
-    hipLaunchKernelGGL(k_qr_sample, dim3(ntask * sblk), dim3(PAP_THREADS), 0, st, d_tasks, p0, sblk);
+    launch_sample(d_tasks, ntask, sblk, p0, st);
     if (int rc = check_launch("qr_sample")) return rc;
     hipLaunchKernelGGL(k_qr_pick, dim3(ntask), dim3(PICK_THREADS), 0, st, d_tasks, p0);
     if (int rc = check_launch("qr_pick")) return rc;
@@ -1436,20 +1464,22 @@ int launch_qrcp_panels(const QrTask *d_tasks, int ntask, int mmax, int nmax, hip
     const int rest = nmax - p0 - PQB;
     if (rest > 0) {
       const int nblk = (rest + PAP_CB - 1) / PAP_CB;
-      hipLaunchKernelGGL((k_qr_apply<0>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks,
-                         p0, nblk);
+      launch_apply<0>(d_tasks, ntask, nblk, p0, st);
       if (int rc = check_launch("qr_apply")) return rc;
     }
     hipLaunchKernelGGL(k_qr_tail, dim3(ntask), dim3(256), 0, st, d_tasks, p0);
     if (int rc = check_launch("qr_tail")) return rc;
+  }
+  if (formq_fused()) {
+    launch_formq(d_tasks, ntask, nmax, st);
+    return check_launch("qr_formq");
   }
   const int qb = (nmax + 63) / 64;
   hipLaunchKernelGGL(k_qr_qinit, dim3(ntask * qb), dim3(256), 0, st, d_tasks, qb);
   if (int rc = check_launch("qr_qinit")) return rc;
   for (int p0 = ((nmax - 1) / PQB) * PQB; p0 >= 0; p0 -= PQB) {
     const int nblk = (nmax - p0 + PAP_CB - 1) / PAP_CB;
-    hipLaunchKernelGGL((k_qr_apply<1>), dim3(ntask * nblk), dim3(PAP_THREADS), 0, st, d_tasks, p0,
-                       nblk);
+    launch_apply<1>(d_tasks, ntask, nblk, p0, st);
     if (int rc = check_launch("qr_apply")) return rc;
   }
   return 0;
