@@ -194,6 +194,8 @@ static std::mutex g_pool_mu;
 static std::vector<PoolEntry> g_pool;
 constexpr size_t POOL_MAX = 4;
 
+static void release_cached(hipStream_t st);
+
 static void *arena_acquire(size_t bytes) {
   int dev = 0;
   hipGetDevice(&dev);
@@ -207,17 +209,37 @@ static void *arena_acquire(size_t bytes) {
       }
   }
   void *p = dev_alloc(bytes);
-  if (!p) {
-    // free the pool and retry once
-    {
-      std::lock_guard<std::mutex> lk(g_pool_mu);
-      for (auto &e : g_pool) dev_free(e.p);
-      g_pool.clear();
-    }
-    hipStreamSynchronize(release_stream());  // the frees have returned their memory
+  if (!p) {  // free the pooled arenas and retry once
+    release_cached(nullptr);
     p = dev_alloc(bytes);
   }
   return p;
+}
+
+// every pooled arena back to the device pool, then the device pool's cached
+// memory back to the device
+static void release_cached(hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &e : g_pool) dev_free(e.p);
+    g_pool.clear();
+  }
+  hipStreamSynchronize(release_stream());
+  if (st) hipStreamSynchronize(st);
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) hipMemPoolTrimTo(pool, 0);
+  hipGetLastError();
+}
+
+hipError_t malloc_async(void **p, size_t bytes, hipStream_t st) {
+  if (hipMallocAsync(p, bytes ? bytes : 8, st) == hipSuccess) return hipSuccess;
+  hipGetLastError();
+  release_cached(st);
+  const hipError_t e = hipMallocAsync(p, bytes ? bytes : 8, st);
+  if (e != hipSuccess) hipGetLastError();
+  return e;
 }
 
 static void arena_release(void *p, size_t bytes) {
@@ -662,7 +684,7 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
   }
   hipStream_t st = (hipStream_t)hip_stream;
   int64_t *d_info = nullptr;
-  if (hipMallocAsync((void **)&d_info, sizeof(int64_t), st) != hipSuccess) {
+  if (malloc_async((void **)&d_info, sizeof(int64_t), st) != hipSuccess) {
     set_error("hipMallocAsync failed");
     return MVG_ERR_ALLOC;
   }
@@ -828,7 +850,7 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
   // zp x sx r yv (Np each) | part (2 nred) | sym (2 nt nb) | scal 8 | out2 | info
   const size_t ws_n = 5 * (size_t)Np + 2 * nred + 2 * (size_t)nt * A->nb + 8 + 2 * n_theta + n_theta;
   double *ws = nullptr;
-  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+  if (malloc_async((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
     hipGetLastError();
     mat_free(S);
     mat_free(A);
@@ -951,7 +973,7 @@ static int run_small(const std::vector<SmallTask> &tasks, int64_t nmax, double *
   char *buf = nullptr;
   const size_t tb = sizeof(SmallTask) * nt, ob = sizeof(double) * 4 * nt;
   const size_t bytes = tb + ob + sizeof(double) * wsd + 256;
-  if (hipMallocAsync((void **)&buf, bytes, st) != hipSuccess) {
+  if (malloc_async((void **)&buf, bytes, st) != hipSuccess) {
     hipGetLastError();
     set_error("batched likelihood workspace of %.2f GB failed", bytes / 1e9);
     return MVG_ERR_ALLOC;
@@ -1180,7 +1202,7 @@ int loglik(const double *d_x, const double *d_y, const double *d_z, int64_t n_lo
   const int nred = (int)((A->N + 4095) / 4096);
   double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2 n_theta) | info (n_theta)
   const size_t ws_n = (size_t)A->Np + 2 * nred + 2 * n_theta + n_theta;
-  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+  if (malloc_async((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
     hipGetLastError();
     mat_free(A);
     set_error("workspace allocation failed");
@@ -1309,7 +1331,7 @@ static int loglik_p_run(const double *d_x, const double *d_y, const double *d_z,
   const int nred = (int)((A->N + 4095) / 4096);
   double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2 n_theta) | info (n_theta)
   const size_t ws_n = (size_t)A->Np + 2 * nred + 2 * n_theta + n_theta;
-  if (hipMallocAsync((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
+  if (malloc_async((void **)&ws, sizeof(double) * ws_n, st) != hipSuccess) {
     hipGetLastError();
     mat_free(A);
     set_error("workspace allocation failed");
@@ -1408,7 +1430,7 @@ int profile_loglik_p(const double *d_x, const double *d_y, const double *d_z, in
   const int p = t.p;
   // marginal variances: Z_i^T R_ii^-1 Z_i / n with R_ii univariate, unit variance (FP64)
   double *zi = nullptr;
-  if (hipMallocAsync((void **)&zi, sizeof(double) * n_loc, st) != hipSuccess) {
+  if (malloc_async((void **)&zi, sizeof(double) * n_loc, st) != hipSuccess) {
     hipGetLastError();
     set_error("workspace allocation failed");
     return MVG_ERR_ALLOC;
@@ -1482,7 +1504,7 @@ int mloe_mmom(const double *d_x, const double *d_y, int64_t n_loc, const mvg_the
   const int64_t Np = A->Np, k2 = 2 * m;
   double *ws = nullptr;  // C0t | X1 | X2 | X3 (Np x 2m) | sT sA dT sQ (2m) | loe mom (m) | info 2
   const size_t wn = 4 * (size_t)Np * k2 + 4 * k2 + 2 * m + 2;
-  if (hipMallocAsync((void **)&ws, sizeof(double) * wn, st) != hipSuccess) {
+  if (malloc_async((void **)&ws, sizeof(double) * wn, st) != hipSuccess) {
     hipGetLastError();
     mat_free(A);
     mat_free(Aa);
@@ -1572,7 +1594,7 @@ int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0,
   const int nchunk = (int)((A->n_loc + 2047) / 2048);
   int hc = prof_begin(MVG_PROF_COKRIGE, st, 0.0, 8.0 * (double)A->N);
   double *part = nullptr;
-  if (hipMallocAsync((void **)&part, sizeof(double) * 2 * m * nchunk, st) != hipSuccess) {
+  if (malloc_async((void **)&part, sizeof(double) * 2 * m * nchunk, st) != hipSuccess) {
     hipGetLastError();
     set_error("workspace allocation failed");
     return MVG_ERR_ALLOC;
@@ -1588,7 +1610,7 @@ int cokrige_predict(const mvg_factor *F, const double *d_x0, const double *d_y0,
   prof_end(hc, st);
   if (!rc && d_mse) {
     double *V = nullptr, *ss = nullptr;
-    if (hipMallocAsync((void **)&V, sizeof(double) * (A->Np * 2 * m + 2 * m), st) != hipSuccess) {
+    if (malloc_async((void **)&V, sizeof(double) * (A->Np * 2 * m + 2 * m), st) != hipSuccess) {
       hipGetLastError();
       set_error("workspace allocation failed");
       return MVG_ERR_ALLOC;
@@ -1636,7 +1658,7 @@ int mvg_mat_loglik(const mvg_mat *L, const double *d_z, double *h_loglik, double
   hipStream_t st = (hipStream_t)hip_stream;
   const int nred = (int)((L->N + 4095) / 4096);
   double *ws = nullptr;  // y (Np) | part (2 nred) | out2 (2)
-  if (hipMallocAsync((void **)&ws, sizeof(double) * ((size_t)L->Np + 2 * nred + 2), st) !=
+  if (malloc_async((void **)&ws, sizeof(double) * ((size_t)L->Np + 2 * nred + 2), st) !=
       hipSuccess) {
     hipGetLastError();
     set_error("workspace allocation failed");

@@ -833,7 +833,7 @@ int dense_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   }
   double *P = nullptr;
   const size_t pbytes = sizeof(double) * (size_t)std::max(1, T - 1) * M.nb * M.nb;
-  if (hipMallocAsync((void **)&P, pbytes, st) != hipSuccess) {
+  if (malloc_async((void **)&P, pbytes, st) != hipSuccess) {
     hipGetLastError();
     set_error("dense_potrf: panel workspace allocation failed");
     return MVG_ERR_ALLOC;
@@ -977,7 +977,7 @@ __global__ __launch_bounds__(256) void k_trmv(TileMap M, const double *__restric
 int launch_trmv(const mvg_mat *A, const double *d_eps, double *d_z, hipStream_t st) {
   // eps is read up to the padded length: stage a zero-padded copy
   double *ep = nullptr;
-  if (hipMallocAsync((void **)&ep, sizeof(double) * A->Np, st) != hipSuccess) {
+  if (malloc_async((void **)&ep, sizeof(double) * A->Np, st) != hipSuccess) {
     hipGetLastError();
     set_error("trmv workspace allocation failed");
     return MVG_ERR_ALLOC;

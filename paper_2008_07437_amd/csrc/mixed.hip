@@ -463,7 +463,7 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   // workspaces: P64 | P32 | P16 | W32
   const size_t bytes = (size_t)nslot * per * (8 + 4 + (bf16 ? 2 : 0)) + (size_t)per * 4;
   char *ws = nullptr;
-  if (hipMallocAsync((void **)&ws, bytes, st) != hipSuccess) {
+  if (malloc_async((void **)&ws, bytes, st) != hipSuccess) {
     hipGetLastError();
     set_error("mixed_potrf: workspace allocation of %.2f GB failed", bytes / 1e9);
     return MVG_ERR_ALLOC;

@@ -63,7 +63,7 @@ int morton_sort(const double *d_x, const double *d_y, int64_t n, int64_t *d_perm
   int64_t P = 1;
   while (P < n) P <<= 1;
   uint64_t *key = nullptr;
-  if (hipMallocAsync((void **)&key, sizeof(uint64_t) * P, st) != hipSuccess) {
+  if (malloc_async((void **)&key, sizeof(uint64_t) * P, st) != hipSuccess) {
     hipGetLastError();
     set_error("morton_order: workspace allocation failed");
     return MVG_ERR_ALLOC;

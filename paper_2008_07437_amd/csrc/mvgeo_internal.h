@@ -226,6 +226,10 @@ hipStream_t side_stream();
 // dev_free once idle.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// hipMallocAsync on st; when the device is out of memory, first returns the
+// memory the library keeps cached (pooled tile arenas, freed stream-ordered
+// memory kept mapped) and tries once more
+hipError_t malloc_async(void **p, size_t bytes, hipStream_t st);
 
 // event timing of launches (diagnostics); handles < 0 mean "not recording"
 int prof_begin(int kind, hipStream_t st, double flops, double bytes);

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_gemv_bwd(TileMap M, int k, double *__re
 
 // Scratch of the per-column solves: the solved tiles (Np x nrhs).
 static int solve_scratch(const mvg_mat *A, int nrhs, double **Y, hipStream_t st) {
-  if (hipMallocAsync((void **)Y, sizeof(double) * A->Np * nrhs, st) != hipSuccess) {
+  if (malloc_async((void **)Y, sizeof(double) * A->Np * nrhs, st) != hipSuccess) {
     hipGetLastError();
     set_error("solve workspace of %.3f GB failed", A->Np * nrhs * 8.0 / 1e9);
     return MVG_ERR_ALLOC;
@@ -260,7 +260,7 @@ static int tile_gemm_solve(const mvg_mat *A, double *X, double *Y, int nrhs, int
 
 static int gemm_solve_inplace(const mvg_mat *A, double *d_V, int nrhs, int mode, hipStream_t st) {
   double *Y = nullptr;
-  if (hipMallocAsync((void **)&Y, sizeof(double) * A->Np * nrhs, st) != hipSuccess) {
+  if (malloc_async((void **)&Y, sizeof(double) * A->Np * nrhs, st) != hipSuccess) {
     hipGetLastError();
     set_error("solve workspace of %.2f GB failed", A->Np * nrhs * 8.0 / 1e9);
     return MVG_ERR_ALLOC;

@@ -50,8 +50,14 @@ struct CopyTask {
   int mode;
 };
 
+// d_start[t]: first block of task t (ascending); d_map (nullable): the task
+// of every block, from launch_gemm_task_map, for lists longer than
+// GEMM_TASKS_LDS (shorter lists are searched in LDS)
+constexpr int GEMM_TASKS_LDS = 256;
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
-                        hipStream_t st);
+                        hipStream_t st, const int *d_map = nullptr);
+int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int *d_map,
+                         hipStream_t st);
 int64_t gemm_blocks(const GemmTask &t);
 // C (M x N) -= A (M x K) B^T (B: N x K), column-major, one large product
 int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
@@ -127,6 +133,7 @@ void store_free(TlrStore &S);
 struct HostLists {
   std::vector<void *> dev;  // device buffers to free at the end
   void *stage(const void *p, size_t bytes, hipStream_t st, int *rc);
+  void *scratch(size_t bytes, hipStream_t st, int *rc);  // device only, freed with the lists
   void release(hipStream_t st);
 };
 

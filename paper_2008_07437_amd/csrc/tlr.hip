@@ -73,7 +73,7 @@ void *HostLists::stage(const void *p, size_t bytes, hipStream_t st, int *rc) {
   }
   memcpy(h, p, bytes);
   void *d = nullptr;
-  if (hipMallocAsync(&d, bytes, st) != hipSuccess) {
+  if (malloc_async(&d, bytes, st) != hipSuccess) {
     hipGetLastError();
     set_error("TLR: staging allocation of %zu bytes failed", bytes);
     *rc = MVG_ERR_ALLOC;
@@ -86,6 +86,18 @@ void *HostLists::stage(const void *p, size_t bytes, hipStream_t st, int *rc) {
     *rc = MVG_ERR_LAUNCH;
     return nullptr;
   }
+  return d;
+}
+
+void *HostLists::scratch(size_t bytes, hipStream_t st, int *rc) {
+  void *d = nullptr;
+  if (malloc_async(&d, bytes ? bytes : 8, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR: device scratch of %zu bytes failed", bytes);
+    *rc = MVG_ERR_ALLOC;
+    return nullptr;
+  }
+  dev.push_back(d);
   return d;
 }
 
@@ -115,8 +127,14 @@ static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t s
   if (rc) return rc;
   double fl = 0.0;
   for (const GemmTask &g : t) fl += 2.0 * g.M * (double)g.N * g.K;
+  int *dmap = nullptr;  // long lists: every block's task, instead of a search in global memory
+  if (t.size() > (size_t)GEMM_TASKS_LDS) {
+    dmap = (int *)L.scratch(sizeof(int) * (size_t)nb, st, &rc);
+    if (!rc) rc = launch_gemm_task_map(ds, (int)t.size(), nb, dmap, st);
+    if (rc) return rc;
+  }
   const int h = prof_begin(MVG_PROF_TLRGEMM, st, fl, 0.0);  // after the task lists' copies
-  rc = launch_gemm_batched(dt, ds, (int)t.size(), nb, st);
+  rc = launch_gemm_batched(dt, ds, (int)t.size(), nb, st, dmap);
   prof_end(h, st);
   return rc;
 }
@@ -209,7 +227,7 @@ static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
   if (S.used + n > S.cap) {
     size_t cap = std::max({S.cap * 2, S.used + n, (size_t)1 << 22});
     double *nbuf = nullptr;
-    if (hipMallocAsync((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
+    if (malloc_async((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
       hipGetLastError();
       set_error("TLR: low-rank store allocation of %.2f GB failed", cap * 8.0 / 1e9);
       return MVG_ERR_ALLOC;
@@ -229,7 +247,7 @@ static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
 static int store_grow(TlrStore &S, size_t cap, hipStream_t st) {
   if (cap <= S.cap) return 0;
   double *nbuf = nullptr;
-  if (hipMallocAsync((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
+  if (malloc_async((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
     hipGetLastError();
     set_error("TLR: low-rank store allocation of %.2f GB failed", cap * 8.0 / 1e9);
     return MVG_ERR_ALLOC;
@@ -252,7 +270,7 @@ static int store_init(TlrStore &S, int T, int nb, int64_t N, hipStream_t st) {
   S.uoff.assign(nt, 0);
   S.used = 0;
   const size_t dbytes = sizeof(double) * (size_t)T * S.nbp * S.nbp;
-  if (hipMallocAsync((void **)&S.diag, dbytes, st) != hipSuccess) {
+  if (malloc_async((void **)&S.diag, dbytes, st) != hipSuccess) {
     hipGetLastError();
     set_error("TLR: diagonal tile allocation of %.2f GB failed", dbytes / 1e9);
     return MVG_ERR_ALLOC;
@@ -334,7 +352,7 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
     const size_t rank_off = tot;
     tot += (jobs.size() + 1) / 2;
     double *ws = nullptr;
-    if (hipMallocAsync((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
+    if (malloc_async((void **)&ws, tot * sizeof(double), st) != hipSuccess) {
       hipGetLastError();
       set_error("TLR: compression workspace of %.2f GB failed", tot * 8.0 / 1e9);
       return MVG_ERR_ALLOC;
@@ -527,7 +545,7 @@ int tlr_build(mvg_mat *A, const mvg_opts &o, hipStream_t st) {
   const int64_t nt = (int64_t)T * (T + 1) / 2;
   double *G = nullptr;
   const int64_t gtiles = std::min<int64_t>(nt, max_tiles);
-  if (hipMallocAsync((void **)&G, tile_bytes * gtiles, st) != hipSuccess) {
+  if (malloc_async((void **)&G, tile_bytes * gtiles, st) != hipSuccess) {
     hipGetLastError();
     set_error("TLR: tile buffer of %.2f GB failed", tile_bytes * gtiles / 1e9);
     return MVG_ERR_ALLOC;
@@ -594,7 +612,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   if (rc) return rc;
   const TileMap Md{(char *)Lf.diag, d_doff, nullptr, T, nbp, T};
   double *P = nullptr;  // dense panel: (T - j) nb x nb, ld (T - j) nb
-  if (hipMallocAsync((void **)&P, sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
+  if (malloc_async((void **)&P, sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
     hipGetLastError();
     L0.release(st);
     set_error("TLR: panel allocation failed");
@@ -645,7 +663,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
       if (need > upd_cap) {  // grow-only (x1.5): a new allocation of GBs costs ~0.1 s
         if (upd) hipFreeAsync(upd, st);
         upd_cap = std::max(need, upd_cap + upd_cap / 2);
-        if (hipMallocAsync((void **)&upd, sizeof(double) * upd_cap, st) != hipSuccess) {
+        if (malloc_async((void **)&upd, sizeof(double) * upd_cap, st) != hipSuccess) {
           hipGetLastError();
           upd = nullptr;
           upd_cap = 0;

@@ -19,22 +19,33 @@ typedef double dbl4t __attribute__((ext_vector_type(4)));
 // slice's global loads in flight during the current slice's MFMAs (one LDS
 // buffer: 19 KB, so that many workgroups share a CU; most products here
 // have a short K).  A block finds its task by binary search over the tasks'
-// first-block offsets, staged in LDS when the list is short.  All
+// first-block offsets staged in LDS when the list is short, else from a
+// block -> task map written by k_gemm_task_map.  All
 // operand loads are from clamped, always-valid addresses and masked after a
 // scheduling barrier (ragged edges, the zero triangle of a triangular A); C
 // is read for beta != 0 with all of a lane's loads issued together.
 constexpr int GB = 64, GK = 16;
-constexpr int GTASK_LDS = 256;  // task offsets staged in LDS up to this many tasks
+
+__global__ void k_gemm_task_map(const int64_t *__restrict__ start, int ntask, int64_t nblocks,
+                                int *__restrict__ map) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const int64_t e = t + 1 < ntask ? start[t + 1] : nblocks;
+  for (int64_t b = start[t]; b < e; ++b) map[b] = t;
+}
 
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict__ tasks,
-                                                      const int64_t *__restrict__ start, int ntask) {
+                                                      const int64_t *__restrict__ start, int ntask,
+                                                      const int *__restrict__ map) {
   __shared__ double As[GK][GB + 2];
   __shared__ double Bs[GK][GB + 2];
-  __shared__ int64_t sstart[GTASK_LDS];
+  __shared__ int64_t sstart[GEMM_TASKS_LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t bid = blockIdx.x;
   int t;
-  if (ntask <= GTASK_LDS) {
+  if (map) {
+    t = map[bid];
+  } else if (ntask <= GEMM_TASKS_LDS) {
     for (int i = tid; i < ntask; i += 256) sstart[i] = start[i];
     __syncthreads();
     int lo = 0, hi = ntask - 1;
@@ -301,15 +312,23 @@ int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, doubl
 }
 
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
-                        hipStream_t st) {
+                        hipStream_t st, const int *d_map) {
   if (ntask <= 0 || nblocks <= 0) return 0;
   if (nblocks >= ((int64_t)1 << 31)) {
     set_error("batched GEMM: %lld blocks", (long long)nblocks);
     return MVG_ERR_LIMIT;
   }
   hipLaunchKernelGGL(k_gemm_batched, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks, d_start,
-                     ntask);
+                     ntask, d_map);
   return check_launch("gemm_batched");
+}
+
+int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int *d_map,
+                         hipStream_t st) {
+  if (ntask <= 0 || nblocks <= 0) return 0;
+  hipLaunchKernelGGL(k_gemm_task_map, dim3((ntask + 255) / 256), dim3(256), 0, st, d_start, ntask,
+                     nblocks, d_map);
+  return check_launch("gemm_task_map");
 }
 
 int64_t gemm_blocks(const GemmTask &t) {
