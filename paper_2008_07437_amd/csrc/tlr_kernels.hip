@@ -1355,13 +1355,13 @@ static void launch_panel(const QrTask *d_tasks, int ntask, int mmax, int p0, hip
 }
 
 // Apply / sample workgroup size: 512 threads (8 waves share a column
-// block's rows), or 256 / 1024 (apply; the sample stays at 512) by
-// MVG_QR_APPLY_THREADS (experiments).
+// block's rows), or 256 by MVG_QR_APPLY_THREADS=256 (experiments).  There is
+// no 1024-thread form: at 128 registers per lane it spills, and a run of it
+// took a GPU memory fault whose cause was not found.
 static int apply_threads() {
   static const int t = [] {
     const char *e = getenv("MVG_QR_APPLY_THREADS");
-    const int v = e ? atoi(e) : 512;
-    return v == 256 || v == 1024 ? v : 512;
+    return e && atoi(e) == 256 ? 256 : 512;
   }();
   return t;
 }
@@ -1371,7 +1371,6 @@ static void launch_apply(const QrTask *d_tasks, int ntask, int nblk, int p0, hip
   const dim3 g(ntask * nblk);
   switch (apply_threads()) {
     case 256: hipLaunchKernelGGL((k_qr_apply<MODE, 256>), g, dim3(256), 0, st, d_tasks, p0, nblk); break;
-    case 1024: hipLaunchKernelGGL((k_qr_apply<MODE, 1024>), g, dim3(1024), 0, st, d_tasks, p0, nblk); break;
     default: hipLaunchKernelGGL((k_qr_apply<MODE, 512>), g, dim3(512), 0, st, d_tasks, p0, nblk); break;
   }
 }
@@ -1391,7 +1390,6 @@ static void launch_formq(const QrTask *d_tasks, int ntask, int nmax, hipStream_t
   const dim3 g(ntask * nblk);
   switch (apply_threads()) {
     case 256: hipLaunchKernelGGL((k_qr_formq<256>), g, dim3(256), 0, st, d_tasks, nblk); break;
-    case 1024: hipLaunchKernelGGL((k_qr_formq<1024>), g, dim3(1024), 0, st, d_tasks, nblk); break;
     default: hipLaunchKernelGGL((k_qr_formq<512>), g, dim3(512), 0, st, d_tasks, nblk); break;
   }
 }
