@@ -658,7 +658,10 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
       for (int i = j; i < T; ++i)
         for (int k = 0; k < j; ++k) gsz += (size_t)Lf.reff(tidx(i, k, T)) * Lf.reff(tidx(j, k, T));
       double *Qc = nullptr, *Pc = nullptr, *Gs = nullptr;
-      const size_t qn = (size_t)nb * Kj, pn = (size_t)ldp * Kj;
+      // K of the column-update GEMM padded with zero columns to a multiple of
+      // 32 (its direct-to-LDS form streams whole slices)
+      const int64_t Kp = (Kj + 31) / 32 * 32;
+      const size_t qn = (size_t)nb * Kp, pn = (size_t)ldp * Kp;
       const size_t need = qn + pn + std::max<size_t>(gsz, 1);
       if (need > upd_cap) {  // grow-only (x1.5): a new allocation of GBs costs ~0.1 s
         if (upd) hipFreeAsync(upd, st);
@@ -697,13 +700,15 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
             go += (size_t)ri * rj;
           }
         rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+        if (!rc && Kp > Kj) rc = launch_fill_f64(Qc + (size_t)nb * Kj, 0.0, (int64_t)nb * (Kp - Kj), st);
+        if (!rc && Kp > Kj) rc = launch_fill_f64(Pc + (size_t)ldp * Kj, 0.0, (int64_t)ldp * (Kp - Kj), st);
         if (!rc) rc = run_gemms(gG, L, st);
         if (!rc) rc = run_gemms(gP, L, st);
         if (!rc) {
           // P -= Pc Qc^T: all earlier columns' updates of this column at once
           const double fl = 2.0 * ldp * nb * (double)Kj;
           int h = prof_begin(MVG_PROF_TRAILING, st, fl, 0.0);
-          rc = launch_gemm_nt_sub(Pc, ldp, Qc, nb, P, ldp, ldp, nb, (int)Kj, st);
+          rc = launch_gemm_nt_sub(Pc, ldp, Qc, nb, P, ldp, ldp, nb, (int)Kp, st);
           prof_end(h, st);
         }
 
