@@ -263,14 +263,15 @@ def tlr_record(args, mvg, dev, synthetic, torch, n, acc, steps, warmup, simplex=
            "update_gemm_tflops": (pr["trailing"]["flops"] / (pr["trailing"]["ms"] * 1e-3) / 1e12
                                   if pr["trailing"]["ms"] > 0 else None)}
     # dominant kernel: the column-update GEMM of the factorisation (one
-    # k_gemm_nt_sub launch per tile column, algorithmic 2 M N K flops); the
-    # other batched GEMMs and the QR launch groups are reported beside it
+    # k_gemm_nt_sub_lds launch per tile column, algorithmic 2 M N K flops with
+    # K the summed ranks, not the zero-padded K); the other batched GEMMs and
+    # the QR launch groups are reported beside it
     g, q, b = pr["trailing"], pr["qr"], pr["tlr_gemm"]
     ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
-    roof = {"kernel": "k_gemm_nt_sub", "bound": "mfma", "achieved": ach,
+    roof = {"kernel": "k_gemm_nt_sub_lds", "bound": "mfma", "achieved": ach,
             "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / FP64_MFMA_PEAK_TFLOPS if ach else None,
-            "traffic": measured_traffic("k_gemm_nt_sub", "tlr_n%d_nb%d" % (n, nb)),
+            "traffic": measured_traffic("k_gemm_nt_sub_lds", "tlr_n%d_nb%d" % (n, nb)),
             "launches": g["launches"], "avg_launch_ms": g["ms"] / max(1, g["launches"]),
             "flops_per_launch": g["flops"] / max(1, g["launches"]),
             "share_of_eval": g["ms"] / steps / (1e3 * dt),

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libmvgeo.so")
 SOURCES = ["capi.hip", "matern.hip", "dense.hip", "solve.hip", "mixed.hip", "morton.hip", "tlr.hip",
-           "tlr_kernels.hip", "tlr_gemm.hip", "batched.hip", "noalloc.hip", "serve.cpp", "mle.cpp"]
+           "tlr_kernels.hip", "tlr_gemm.hip", "tlr_update.hip", "batched.hip", "noalloc.hip", "serve.cpp", "mle.cpp"]
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result", "-Wno-unused-value"]
