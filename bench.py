@@ -377,7 +377,7 @@ def dense_record(args, mvg, dev, synthetic, torch, n, steps, warmup, tune_set):
                          "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": (achieved / FP64_MFMA_PEAK_TFLOPS) if achieved else None,
                          "traffic": measured_traffic("k_update_trailing<%d, 0>" % nb,
-                                                     "cfg1_n%d_nb%d" % (n, nb)),
+                                                     "dense_n%d_nb%d" % (n, nb)),
                          "launches": tr["launches"],
                          "avg_launch_ms": tr["ms"] / max(1, tr["launches"]),
                          "flops_per_launch": tr["flops"] / max(1, tr["launches"])}}, (xs, ys, z, th)
@@ -440,11 +440,11 @@ def run_headline(args, mvg, dev, synthetic, torch):
     acc = float(args.accs.split(",")[0])
     rec = tlr_record(args, mvg, dev, synthetic, torch, n, acc, args.steps, args.warmup,
                      simplex=args.simplex)
-    cfg1 = cfg2 = None
+    dense_rec = mixed_rec = None
     if not args.no_nested:
-        cfg1, _ = dense_record(args, mvg, dev, synthetic, torch, 25600, args.nested_steps, 1,
-                               (256, 512, 768))
-        cfg2 = mixed_record(args, mvg, dev, synthetic, torch, 50000, (0.5, 1.0), 0.5)
+        dense_rec, _ = dense_record(args, mvg, dev, synthetic, torch, 25600, args.nested_steps, 1,
+                                    (256, 512, 768))
+        mixed_rec = mixed_record(args, mvg, dev, synthetic, torch, 50000, (0.5, 1.0), 0.5)
     cpu = None
     if not args.no_cpu:
         _step("oracle timing on the host (bounded sample)")
@@ -459,7 +459,7 @@ def run_headline(args, mvg, dev, synthetic, torch):
            "n_loc": n, "nb": 1200, "precision": "tlr", "parallelism": "single GPU"},
           roofline=rec["roofline"], cpu_baseline=cpu,
           tlr=t, dense_fp64=rec["dense_fp64"], ranks=rec["ranks"], memory=rec["memory"],
-          simplex7=rec.get("simplex7"), dense_n25600=cfg1, mixed_n50000=cfg2)
+          simplex7=rec.get("simplex7"), dense_n25600=dense_rec, mixed_n50000=mixed_rec)
 
 
 def run_batched(args, mvg, dev, synthetic, torch):
