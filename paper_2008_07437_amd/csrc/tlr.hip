@@ -322,9 +322,12 @@ struct CompressJob {
 // tail rule; it keeps at least the ranks of the 2-norm rule s_i > acc).  A
 // rank above s - OVERSAMPLE (the sketch may have missed part of the range)
 // is retried with a wider sketch.
+// W (nullable): the diagonal factor's inverse applied to every V; w_ready
+// (nullable): an event after which W is complete, waited for only before W's
+// first use, so that the sketches and QRs overlap W's computation.
 static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
                          uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t w_ready = nullptr) {
   const int nb = D.nb;
   const int T = D.T;
   const int smax = std::min(nb, QR_MAXN);
@@ -513,7 +516,11 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
         g.push_back(gemm(Zb(b), nb, 0, Q3(b), s, 0, W ? Yb(b) : V, nb, nb, r, s, 1.0, 0.0));
         if (W) g2.push_back(gemm(W, ldw, 0, Yb(b), nb, 0, V, nb, nb, r, nb, 1.0, 0.0));
       }
-      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (W && w_ready && hipStreamWaitEvent(st, w_ready, 0) != hipSuccess) {
+        set_error("TLR: wait for the diagonal factor failed");
+        rc = MVG_ERR_LAUNCH;
+      }
+      if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
       if (!rc) rc = run_gemms(g, L, st);
       if (!rc) rc = run_gemms(g2, L, st);
     }
@@ -628,6 +635,20 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   }
   double *upd = nullptr;  // update workspace of the column steps, grown as needed
   size_t upd_cap = 0;
+  // the diagonal factor of each column runs on the side stream (ordered by
+  // two events per column)
+  hipStream_t dside = side_stream();
+  hipEvent_t ev_upd = nullptr, ev_diag = nullptr;
+  if (!dside || hipEventCreateWithFlags(&ev_upd, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming) != hipSuccess) {
+    hipGetLastError();
+    if (ev_upd) hipEventDestroy(ev_upd);
+    if (upd) hipFreeAsync(upd, st);
+    hipFreeAsync(P, st);
+    L0.release(st);
+    set_error("TLR: side stream or events unavailable");
+    return MVG_ERR_STATE;
+  }
   for (int j = 0; j < T && !rc; ++j) {
     const int ntile = T - j;
     const int ldp = ntile * nb;
@@ -714,15 +735,25 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
 
       }
     }
-    // (3) diagonal tile: FP64 Cholesky and W_j
+    // (3) diagonal tile: FP64 Cholesky and W_j, on the side stream beside
+    // the compression of the sub-diagonal tiles (which reads other rows of P
+    // and needs W_j only for V <- W_j V)
     if (!rc) {
+      if (hipEventRecord(ev_upd, st) != hipSuccess || hipStreamWaitEvent(dside, ev_upd, 0) != hipSuccess) {
+        set_error("TLR: side-stream ordering failed");
+        rc = MVG_ERR_LAUNCH;
+      }
       std::vector<CopyTask> c{CopyTask{P, Lf.diag + (int64_t)j * nbp * nbp, nb, nb, ldp, nbp,
                                        nullptr, COPY_PLAIN}};
-      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
+      if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, dside);
       PivotTol pt = pivot_tol(A);
       pt.gbase = (int64_t)j * nb;
       pt.lreal = nb;
-      if (!rc) rc = diag_factor(Md, j, A->d_winv, d_info, pt, st);
+      if (!rc) rc = diag_factor(Md, j, A->d_winv, d_info, pt, dside);
+      if (!rc && hipEventRecord(ev_diag, dside) != hipSuccess) {
+        set_error("TLR: side-stream event failed");
+        rc = MVG_ERR_LAUNCH;
+      }
     }
     // (4) recompress the sub-diagonal tiles, V <- W_j V
     if (!rc && j + 1 < T) {
@@ -735,10 +766,15 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
                                    (uint64_t)t * 2 + 1});
       }
       rc = compress_jobs(jobs, Lf, o.tlr_acc, o.tlr_max_rank, o.seed ^ 0x5bd1e995u,
-                         A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st);
+                         A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st, ev_diag);
     }
+    // the next column overwrites P and the staged lists: the side stream's
+    // work of this column is complete first (also on an error)
+    hipStreamWaitEvent(st, ev_diag, 0);
     L.release(st);
   }
+  hipEventDestroy(ev_upd);  // both events are complete: st waited for ev_diag each column
+  hipEventDestroy(ev_diag);
   if (upd) hipFreeAsync(upd, st);
   hipFreeAsync(P, st);
   L0.release(st);
