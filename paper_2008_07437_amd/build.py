@@ -34,11 +34,23 @@ def _compile(src: str, verbose: bool) -> None:
     subprocess.check_call(cmd)
 
 
+def _stale(src: str) -> bool:
+    """The object is missing or older than its source or any header (every
+    source includes the shared headers, so a header change rebuilds all)."""
+    obj = _obj(src)
+    if not os.path.exists(obj):
+        return True
+    heads = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    heads += [os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))]
+    newest = max(os.path.getmtime(f) for f in heads + [os.path.join(CSRC, src)])
+    return os.path.getmtime(obj) < newest
+
+
 def build(verbose: bool = False, only=None) -> str:
-    """Compiles the sources (all of them, or those named in `only` when their
-    objects exist) and links libmvgeo.so."""
+    """Compiles the sources (all of them, or those named in `only` plus any
+    whose object is stale) and links libmvgeo.so."""
     os.makedirs(OBJ, exist_ok=True)
-    todo = [s for s in SOURCES if only is None or s in only or not os.path.exists(_obj(s))]
+    todo = [s for s in SOURCES if only is None or s in only or _stale(s)]
     jobs = max(1, min(len(todo), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(jobs) as ex:
         for f in [ex.submit(_compile, s, verbose) for s in todo]:

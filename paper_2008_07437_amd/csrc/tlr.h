@@ -100,6 +100,7 @@ struct TlrStore {
   std::vector<int64_t> uoff;       // element offset of U in buf (V follows U)
   double *buf = nullptr;
   size_t cap = 0, used = 0;        // doubles
+  hipStream_t reader = nullptr;    // a stream that may still read buf (drained before a growth)
   int reff(int64_t t) const { return dense[t] ? nb : rank[t]; }
   const double *U(int64_t t) const { return buf + uoff[t]; }
   const double *V(int64_t t) const { return buf + uoff[t] + (int64_t)nb * reff(t); }

@@ -225,6 +225,7 @@ static GemmTask gemm(const double *A, int lda, int ta, const double *B, int ldb,
 
 static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
   if (S.used + n > S.cap) {
+    if (S.reader) hipStreamSynchronize(S.reader);  // its pending work reads the old buffer
     size_t cap = std::max({S.cap * 2, S.used + n, (size_t)1 << 22});
     double *nbuf = nullptr;
     if (malloc_async((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
@@ -246,6 +247,7 @@ static int store_reserve(TlrStore &S, size_t n, hipStream_t st, int64_t *off) {
 // Capacity of at least cap doubles (contents kept).
 static int store_grow(TlrStore &S, size_t cap, hipStream_t st) {
   if (cap <= S.cap) return 0;
+  if (S.reader) hipStreamSynchronize(S.reader);  // its pending work reads the old buffer
   double *nbuf = nullptr;
   if (malloc_async((void **)&nbuf, cap * sizeof(double), st) != hipSuccess) {
     hipGetLastError();
@@ -618,124 +620,135 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   const int64_t *d_doff = (const int64_t *)L0.stage(doff.data(), doff.size() * 8, st, &rc);
   if (rc) return rc;
   const TileMap Md{(char *)Lf.diag, d_doff, nullptr, T, nbp, T};
-  double *P = nullptr;  // dense panel: (T - j) nb x nb, ld (T - j) nb
-  if (malloc_async((void **)&P, sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
-    hipGetLastError();
-    L0.release(st);
-    set_error("TLR: panel allocation failed");
-    return MVG_ERR_ALLOC;
-  }
+  // Two dense panels ((T - j) nb x nb, ld (T - j) nb): while column j is
+  // compressed on st, column j + 1 is expanded into the other panel and
+  // receives the updates of columns k < j on a second stream (look-ahead);
+  // the update from column j itself follows on st once column j is factored.
+  // Column j's diagonal factor runs on a third stream beside its compression.
+  double *Pbuf[2] = {nullptr, nullptr};
+  for (int q = 0; q < 2 && !rc; ++q)
+    if (malloc_async((void **)&Pbuf[q], sizeof(double) * (size_t)T * nb * nb, st) != hipSuccess) {
+      hipGetLastError();
+      set_error("TLR: panel allocation failed");
+      rc = MVG_ERR_ALLOC;
+    }
   std::vector<int> sguess(T, -1);
   // the factor's store sized up front from the compressed Sigma's (the factor's
   // ranks are close to it), so that it does not grow by reallocation and copy
-  if (int rc2 = store_grow(Lf, Sg.used + Sg.used / 4 + ((size_t)1 << 22), st)) {
-    hipFreeAsync(P, st);
-    L0.release(st);
-    return rc2;
-  }
-  double *upd = nullptr;  // update workspace of the column steps, grown as needed
-  size_t upd_cap = 0;
-  // the diagonal factor of each column runs on the side stream (ordered by
-  // two events per column)
+  if (!rc) rc = store_grow(Lf, Sg.used + Sg.used / 4 + ((size_t)1 << 22), st);
+  double *upd[2] = {nullptr, nullptr};  // update workspaces (look-ahead, own column), grow-only
+  size_t upd_cap[2] = {0, 0};
   hipStream_t dside = side_stream();
-  hipEvent_t ev_upd = nullptr, ev_diag = nullptr;
-  if (!dside || hipEventCreateWithFlags(&ev_upd, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming) != hipSuccess) {
+  hipStream_t look = nullptr;
+  hipEvent_t ev_upd = nullptr, ev_diag = nullptr, ev_look = nullptr;
+  if (!rc && (!dside || hipStreamCreateWithFlags(&look, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&ev_upd, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&ev_look, hipEventDisableTiming) != hipSuccess)) {
     hipGetLastError();
-    if (ev_upd) hipEventDestroy(ev_upd);
-    if (upd) hipFreeAsync(upd, st);
-    hipFreeAsync(P, st);
-    L0.release(st);
-    set_error("TLR: side stream or events unavailable");
-    return MVG_ERR_STATE;
+    set_error("TLR: side streams or events unavailable");
+    rc = MVG_ERR_STATE;
   }
-  for (int j = 0; j < T && !rc; ++j) {
-    const int ntile = T - j;
-    const int ldp = ntile * nb;
-    HostLists L;
-    // (1) expand column j of the compressed Sigma into the panel
-    {
-      std::vector<CopyTask> c{CopyTask{Sg.diag + (int64_t)j * nbp * nbp, P, nb, nb, nbp, ldp,
-                                       nullptr, COPY_PLAIN}};
-      std::vector<GemmTask> g;
-      for (int i = j + 1; i < T; ++i) {
-        const int64_t t = tidx(i, j, T);
-        const int r = Sg.reff(t);
-        g.push_back(gemm(Sg.U(t), nb, 0, Sg.V(t), nb, 1, P + (int64_t)(i - j) * nb, ldp, nb, nb, r,
-                         1.0, 0.0));
-      }
-      rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
-      if (!rc) rc = run_gemms(g, L, st);
-    }
-    // (2) updates from the factor columns k < j
-    int64_t Kj = 0;
-    std::vector<int64_t> koff(j + 1, 0);
-    for (int k = 0; k < j; ++k) {
-      koff[k] = Kj;
-      Kj += Lf.reff(tidx(j, k, T));
-    }
-    if (!rc && Kj > 0) {
-      size_t gsz = 0;
-      for (int i = j; i < T; ++i)
-        for (int k = 0; k < j; ++k) gsz += (size_t)Lf.reff(tidx(i, k, T)) * Lf.reff(tidx(j, k, T));
-      double *Qc = nullptr, *Pc = nullptr, *Gs = nullptr;
-      // K of the column-update GEMM padded with zero columns to a multiple of
-      // 32 (its direct-to-LDS form streams whole slices)
-      const int64_t Kp = (Kj + 31) / 32 * 32;
-      const size_t qn = (size_t)nb * Kp, pn = (size_t)ldp * Kp;
-      const size_t need = qn + pn + std::max<size_t>(gsz, 1);
-      if (need > upd_cap) {  // grow-only (x1.5): a new allocation of GBs costs ~0.1 s
-        if (upd) hipFreeAsync(upd, st);
-        upd_cap = std::max(need, upd_cap + upd_cap / 2);
-        if (malloc_async((void **)&upd, sizeof(double) * upd_cap, st) != hipSuccess) {
-          hipGetLastError();
-          upd = nullptr;
-          upd_cap = 0;
-        }
-      }
-      Qc = upd;
-      if (!Qc) {
-        set_error("TLR: update workspace of %.2f GB failed", need * 8.0 / 1e9);
-        rc = MVG_ERR_ALLOC;
-      } else {
-        Pc = Qc + qn;
-        Gs = Pc + pn;
-        std::vector<CopyTask> c;
-        std::vector<GemmTask> gG, gP;
-        for (int k = 0; k < j; ++k) {
-          const int64_t tj = tidx(j, k, T);
-          const int rj = Lf.reff(tj);
-          if (rj) c.push_back(CopyTask{Lf.U(tj), Qc + koff[k] * nb, nb, rj, nb, nb, nullptr, COPY_PLAIN});
-        }
-        size_t go = 0;
-        for (int i = j; i < T; ++i)
-          for (int k = 0; k < j; ++k) {
-            const int64_t ti = tidx(i, k, T), tj = tidx(j, k, T);
-            const int ri = Lf.reff(ti), rj = Lf.reff(tj);
-            if (!rj) continue;
-            double *Gik = Gs + go;
-            if (ri) gG.push_back(gemm(Lf.V(ti), nb, 1, Lf.V(tj), nb, 0, Gik, ri, ri, rj, nb, 1.0, 0.0));
-            // K = 0 (rank-0 tile) writes zeros into its block of Pc
-            gP.push_back(gemm(Lf.U(ti), nb, 0, Gik, std::max(ri, 1), 0,
-                              Pc + (int64_t)(i - j) * nb + koff[k] * ldp, ldp, nb, rj, ri, 1.0, 0.0));
-            go += (size_t)ri * rj;
-          }
-        rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
-        if (!rc && Kp > Kj) rc = launch_fill_f64(Qc + (size_t)nb * Kj, 0.0, (int64_t)nb * (Kp - Kj), st);
-        if (!rc && Kp > Kj) rc = launch_fill_f64(Pc + (size_t)ldp * Kj, 0.0, (int64_t)ldp * (Kp - Kj), st);
-        if (!rc) rc = run_gemms(gG, L, st);
-        if (!rc) rc = run_gemms(gP, L, st);
-        if (!rc) {
-          // P -= Pc Qc^T: all earlier columns' updates of this column at once
-          const double fl = 2.0 * ldp * nb * (double)Kj;
-          int h = prof_begin(MVG_PROF_TRAILING, st, fl, 0.0);
-          rc = launch_gemm_nt_sub(Pc, ldp, Qc, nb, P, ldp, ldp, nb, (int)Kp, st);
-          prof_end(h, st);
-        }
+  Lf.reader = look;  // a growth of the factor's store first drains the look-ahead
 
+  // column jc of the compressed Sigma into panel Pp, on stream s
+  auto expand = [&](int jc, double *Pp, HostLists &Lx, hipStream_t s) -> int {
+    const int ldp = (T - jc) * nb;
+    std::vector<CopyTask> c{CopyTask{Sg.diag + (int64_t)jc * nbp * nbp, Pp, nb, nb, nbp, ldp,
+                                     nullptr, COPY_PLAIN}};
+    std::vector<GemmTask> g;
+    for (int i = jc + 1; i < T; ++i) {
+      const int64_t t = tidx(i, jc, T);
+      g.push_back(gemm(Sg.U(t), nb, 0, Sg.V(t), nb, 1, Pp + (int64_t)(i - jc) * nb, ldp, nb, nb,
+                       Sg.reff(t), 1.0, 0.0));
+    }
+    int e = run_list<CopyTask, launch_copy_cols>(c, Lx, s);
+    if (!e) e = run_gemms(g, Lx, s);
+    return e;
+  };
+  // panel Pp of column jc -= the updates of factor columns k in [k0, k1):
+  // [U_ik G_ijk]_k [U_jk]_k^T with G_ijk = V_ik^T V_jk, one large GEMM
+  auto update = [&](int jc, int k0, int k1, double *Pp, int w, HostLists &Lx, hipStream_t s) -> int {
+    const int ldp = (T - jc) * nb;
+    int64_t Kj = 0;
+    std::vector<int64_t> koff(T, 0);
+    for (int k = k0; k < k1; ++k) {
+      koff[k] = Kj;
+      Kj += Lf.reff(tidx(jc, k, T));
+    }
+    if (Kj == 0) return 0;
+    size_t gsz = 0;
+    for (int i = jc; i < T; ++i)
+      for (int k = k0; k < k1; ++k) gsz += (size_t)Lf.reff(tidx(i, k, T)) * Lf.reff(tidx(jc, k, T));
+    // K padded with zero columns to a multiple of 32 (the direct-to-LDS
+    // GEMM streams whole slices)
+    const int64_t Kp = (Kj + 31) / 32 * 32;
+    const size_t qn = (size_t)nb * Kp, pn = (size_t)ldp * Kp;
+    const size_t need = qn + pn + std::max<size_t>(gsz, 1);
+    if (need > upd_cap[w]) {  // grow-only (x1.5): a new allocation of GBs costs ~0.1 s
+      if (upd[w]) hipFreeAsync(upd[w], s);
+      upd_cap[w] = std::max(need, upd_cap[w] + upd_cap[w] / 2);
+      if (malloc_async((void **)&upd[w], sizeof(double) * upd_cap[w], s) != hipSuccess) {
+        hipGetLastError();
+        upd[w] = nullptr;
+        upd_cap[w] = 0;
+        set_error("TLR: update workspace of %.2f GB failed", need * 8.0 / 1e9);
+        return MVG_ERR_ALLOC;
       }
     }
-    // (3) diagonal tile: FP64 Cholesky and W_j, on the side stream beside
+    double *Qc = upd[w], *Pc = Qc + qn, *Gs = Pc + pn;
+    std::vector<CopyTask> c;
+    std::vector<GemmTask> gG, gP;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t tj = tidx(jc, k, T);
+      const int rj = Lf.reff(tj);
+      if (rj) c.push_back(CopyTask{Lf.U(tj), Qc + koff[k] * nb, nb, rj, nb, nb, nullptr, COPY_PLAIN});
+    }
+    size_t go = 0;
+    for (int i = jc; i < T; ++i)
+      for (int k = k0; k < k1; ++k) {
+        const int64_t ti = tidx(i, k, T), tj = tidx(jc, k, T);
+        const int ri = Lf.reff(ti), rj = Lf.reff(tj);
+        if (!rj) continue;
+        double *Gik = Gs + go;
+        if (ri) gG.push_back(gemm(Lf.V(ti), nb, 1, Lf.V(tj), nb, 0, Gik, ri, ri, rj, nb, 1.0, 0.0));
+        // K = 0 (rank-0 tile) writes zeros into its block of Pc
+        gP.push_back(gemm(Lf.U(ti), nb, 0, Gik, std::max(ri, 1), 0,
+                          Pc + (int64_t)(i - jc) * nb + koff[k] * ldp, ldp, nb, rj, ri, 1.0, 0.0));
+        go += (size_t)ri * rj;
+      }
+    int e = run_list<CopyTask, launch_copy_cols>(c, Lx, s);
+    if (!e && Kp > Kj) e = launch_fill_f64(Qc + (size_t)nb * Kj, 0.0, (int64_t)nb * (Kp - Kj), s);
+    if (!e && Kp > Kj) e = launch_fill_f64(Pc + (size_t)ldp * Kj, 0.0, (int64_t)ldp * (Kp - Kj), s);
+    if (!e) e = run_gemms(gG, Lx, s);
+    if (!e) e = run_gemms(gP, Lx, s);
+    if (!e) {
+      const double fl = 2.0 * ldp * nb * (double)Kj;
+      const int h = prof_begin(MVG_PROF_TRAILING, s, fl, 0.0);
+      e = launch_gemm_nt_sub(Pc, ldp, Qc, nb, Pp, ldp, ldp, nb, (int)Kp, s);
+      prof_end(h, s);
+    }
+    return e;
+  };
+
+  {  // column 0's panel
+    HostLists L;
+    if (!rc) rc = expand(0, Pbuf[0], L, st);
+    L.release(st);
+  }
+  bool looked = false;  // a look-ahead for the current column was issued
+  for (int j = 0; j < T && !rc; ++j) {
+    const int ldp = (T - j) * nb;
+    double *P = Pbuf[j & 1];
+    HostLists L, L2;
+    // (1) the panel of column j: its look-ahead (expansion and the updates
+    // of columns k < j - 1) is complete; the update of column j - 1 here
+    if (looked && hipStreamWaitEvent(st, ev_look, 0) != hipSuccess) {
+      set_error("TLR: look-ahead ordering failed");
+      rc = MVG_ERR_LAUNCH;
+    }
+    if (!rc && j > 0) rc = update(j, looked ? j - 1 : 0, j, P, 1, L, st);
+    // (2) diagonal tile: FP64 Cholesky and W_j, on the side stream beside
     // the compression of the sub-diagonal tiles (which reads other rows of P
     // and needs W_j only for V <- W_j V)
     if (!rc) {
@@ -755,6 +768,24 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
         rc = MVG_ERR_LAUNCH;
       }
     }
+    // (3) look-ahead on its own stream: column j + 1's panel (the other
+    // buffer, last read by column j - 1's compression, complete on st before
+    // ev_upd) expanded and updated by the factor columns k < j
+    looked = false;
+    if (!rc && j + 1 < T) {
+      if (hipStreamWaitEvent(look, ev_upd, 0) != hipSuccess) {
+        set_error("TLR: look-ahead ordering failed");
+        rc = MVG_ERR_LAUNCH;
+      }
+      double *Pn = Pbuf[(j + 1) & 1];
+      if (!rc) rc = expand(j + 1, Pn, L2, look);
+      if (!rc && j > 0) rc = update(j + 1, 0, j, Pn, 0, L2, look);
+      if (!rc && hipEventRecord(ev_look, look) != hipSuccess) {
+        set_error("TLR: look-ahead event failed");
+        rc = MVG_ERR_LAUNCH;
+      }
+      looked = !rc;
+    }
     // (4) recompress the sub-diagonal tiles, V <- W_j V
     if (!rc && j + 1 < T) {
       std::vector<CompressJob> jobs;
@@ -768,15 +799,25 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
       rc = compress_jobs(jobs, Lf, o.tlr_acc, o.tlr_max_rank, o.seed ^ 0x5bd1e995u,
                          A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st, ev_diag);
     }
-    // the next column overwrites P and the staged lists: the side stream's
-    // work of this column is complete first (also on an error)
-    hipStreamWaitEvent(st, ev_diag, 0);
+    // the staged lists are released only when every stream that reads them
+    // is done (also on an error): the side stream's diagonal factor, then the
+    // look-ahead (synchronised here; the next column needs it anyway)
+    if (ev_diag) hipStreamWaitEvent(st, ev_diag, 0);
+    if (look) L2.release(look);
     L.release(st);
   }
-  hipEventDestroy(ev_upd);  // both events are complete: st waited for ev_diag each column
-  hipEventDestroy(ev_diag);
-  if (upd) hipFreeAsync(upd, st);
-  hipFreeAsync(P, st);
+  Lf.reader = nullptr;
+  if (look) {
+    hipStreamSynchronize(look);
+    hipStreamDestroy(look);
+  }
+  if (ev_upd) hipEventDestroy(ev_upd);  // complete: st waited for every event it ordered
+  if (ev_diag) hipEventDestroy(ev_diag);
+  if (ev_look) hipEventDestroy(ev_look);
+  for (int w = 0; w < 2; ++w)
+    if (upd[w]) hipFreeAsync(upd[w], st);
+  for (int q = 0; q < 2; ++q)
+    if (Pbuf[q]) hipFreeAsync(Pbuf[q], st);
   L0.release(st);
   if (!rc) rc = tlr_upload_meta(A, st);
   return rc;
