@@ -54,11 +54,12 @@ struct CopyTask {
 // of every block, from launch_gemm_task_map, for lists longer than
 // GEMM_TASKS_LDS (shorter lists are searched in LDS)
 constexpr int GEMM_TASKS_LDS = 256;
+// bs: output block size, 64 or 32 (tasks with M, N <= 32)
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
-                        hipStream_t st, const int *d_map = nullptr);
+                        hipStream_t st, const int *d_map = nullptr, int bs = 64);
 int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int *d_map,
                          hipStream_t st);
-int64_t gemm_blocks(const GemmTask &t);
+int64_t gemm_blocks(const GemmTask &t, int bs = 64);
 // C (M x N) -= A (M x K) B^T (B: N x K), column-major, one large product
 int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                        int M, int N, int K, hipStream_t st);

@@ -109,32 +109,44 @@ void HostLists::release(hipStream_t st) {
   g_pinned.off = 0;
 }
 
+// One launch per block size: products with M and N at most 32 (the V^T V of
+// low-rank tiles) on 32 x 32 blocks, the others on 64 x 64.
 static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t st) {
-  std::vector<GemmTask> t;
-  std::vector<int64_t> start;
-  int64_t nb = 0;
-  for (const GemmTask &g : v) {
-    const int64_t b = gemm_blocks(g);
-    if (b == 0) continue;
-    t.push_back(g);
-    start.push_back(nb);
-    nb += b;
-  }
-  if (t.empty()) return 0;
-  int rc = 0;
-  const GemmTask *dt = (const GemmTask *)L.stage(t.data(), t.size() * sizeof(GemmTask), st, &rc);
-  const int64_t *ds = (const int64_t *)L.stage(start.data(), start.size() * 8, st, &rc);
-  if (rc) return rc;
+  struct Part {
+    int bs;
+    int n = 0;
+    int64_t nb = 0;
+    const GemmTask *dt = nullptr;
+    const int64_t *ds = nullptr;
+    int *dmap = nullptr;
+  } parts[2] = {{32}, {64}};
   double fl = 0.0;
-  for (const GemmTask &g : t) fl += 2.0 * g.M * (double)g.N * g.K;
-  int *dmap = nullptr;  // long lists: every block's task, instead of a search in global memory
-  if (t.size() > (size_t)GEMM_TASKS_LDS) {
-    dmap = (int *)L.scratch(sizeof(int) * (size_t)nb, st, &rc);
-    if (!rc) rc = launch_gemm_task_map(ds, (int)t.size(), nb, dmap, st);
+  int rc = 0;
+  for (Part &p : parts) {
+    std::vector<GemmTask> t;
+    std::vector<int64_t> start;
+    for (const GemmTask &g : v) {
+      if ((std::max(g.M, g.N) <= 32) != (p.bs == 32)) continue;
+      const int64_t b = gemm_blocks(g, p.bs);
+      if (b == 0) continue;
+      t.push_back(g);
+      start.push_back(p.nb);
+      p.nb += b;
+      fl += 2.0 * g.M * (double)g.N * g.K;
+    }
+    if (t.empty()) continue;
+    p.n = (int)t.size();
+    p.dt = (const GemmTask *)L.stage(t.data(), t.size() * sizeof(GemmTask), st, &rc);
+    if (!rc) p.ds = (const int64_t *)L.stage(start.data(), start.size() * 8, st, &rc);
+    if (!rc && p.n > GEMM_TASKS_LDS) {  // every block's task, instead of a search in global memory
+      p.dmap = (int *)L.scratch(sizeof(int) * (size_t)p.nb, st, &rc);
+      if (!rc) rc = launch_gemm_task_map(p.ds, p.n, p.nb, p.dmap, st);
+    }
     if (rc) return rc;
   }
   const int h = prof_begin(MVG_PROF_TLRGEMM, st, fl, 0.0);  // after the task lists' copies
-  rc = launch_gemm_batched(dt, ds, (int)t.size(), nb, st, dmap);
+  for (const Part &p : parts)
+    if (!rc && p.n) rc = launch_gemm_batched(p.dt, p.ds, p.n, p.nb, st, p.dmap, p.bs);
   prof_end(h, st);
   return rc;
 }
