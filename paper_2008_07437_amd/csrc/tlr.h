@@ -54,7 +54,7 @@ struct CopyTask {
 // of every block, from launch_gemm_task_map, for lists longer than
 // GEMM_TASKS_LDS (shorter lists are searched in LDS)
 constexpr int GEMM_TASKS_LDS = 256;
-// bs: output block size, 64 or 32 (tasks with M, N <= 32)
+// bs: output blocks of 64 x 64, 32 x 32 (tasks with M, N <= 32) or 128 x 64 (bs = 128)
 int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int ntask, int64_t nblocks,
                         hipStream_t st, const int *d_map = nullptr, int bs = 64);
 int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int *d_map,

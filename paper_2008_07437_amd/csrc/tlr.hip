@@ -109,8 +109,16 @@ void HostLists::release(hipStream_t st) {
   g_pinned.off = 0;
 }
 
-// One launch per block size: products with M and N at most 32 (the V^T V of
-// low-rank tiles) on 32 x 32 blocks, the others on 64 x 64.
+// Output block size of a product: 32 x 32 when M and N are at most 32 (the
+// V^T V of low-rank tiles), 128 x 64 for tall products with a long K (the
+// sketches and V <- W V of 1200-row tiles), 64 x 64 otherwise.
+static int gemm_block_size(const GemmTask &g) {
+  if (std::max(g.M, g.N) <= 32) return 32;
+  if (g.M >= 256 && g.K >= 128) return 128;
+  return 64;
+}
+
+// One launch per block size.
 static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t st) {
   struct Part {
     int bs;
@@ -119,14 +127,14 @@ static int run_gemms(const std::vector<GemmTask> &v, HostLists &L, hipStream_t s
     const GemmTask *dt = nullptr;
     const int64_t *ds = nullptr;
     int *dmap = nullptr;
-  } parts[2] = {{32}, {64}};
+  } parts[3] = {{32}, {64}, {128}};
   double fl = 0.0;
   int rc = 0;
   for (Part &p : parts) {
     std::vector<GemmTask> t;
     std::vector<int64_t> start;
     for (const GemmTask &g : v) {
-      if ((std::max(g.M, g.N) <= 32) != (p.bs == 32)) continue;
+      if (gemm_block_size(g) != p.bs) continue;
       const int64_t b = gemm_blocks(g, p.bs);
       if (b == 0) continue;
       t.push_back(g);

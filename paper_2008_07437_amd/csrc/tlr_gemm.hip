@@ -35,20 +35,25 @@ __global__ void k_gemm_task_map(const int64_t *__restrict__ start, int ntask, in
   for (int64_t b = start[t]; b < e; ++b) map[b] = t;
 }
 
-// BS x BS output blocks (64: four waves of 32 x 32, 2 x 2 MFMA tiles each,
-// K slices of 16; 32: four waves of 16 x 16, one tile each, K slices of 32,
-// for products whose M and N are at most 32, e.g. V^T V of low-rank tiles).
-// A slice holds 1024 values of each operand: four loads per thread.
-template <int BS>
-__global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict__ tasks,
+// BM x BN output blocks, four waves in a 2 x 2 grid, each wave BM/2 x BN/2
+// (BM/32 x BN/32 MFMA tiles), K slices of KS:
+//   64 x 64, KS 16: the general case;
+//   32 x 32, KS 32: products whose M and N are at most 32 (V^T V of low-rank
+//     tiles);
+//   128 x 64, KS 16: tall products with a long K (the sketches C Omega and
+//     C^T Q of 1200-row tiles, V <- W V): twice the MFMAs per LDS fragment.
+// Loader: an operand stored with its row (m or n) index contiguous is read
+// as (idx, k) = (tid % D, tid / D + (256 / D) i), one stored with k
+// contiguous as (tid / KS + (256 / KS) i, tid % KS).
+template <int BM, int BN, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 2 : 4))) void k_gemm_batched(const GemmTask *__restrict__ tasks,
                                                       const int64_t *__restrict__ start, int ntask,
                                                       const int *__restrict__ map) {
-  constexpr int KS = 1024 / BS;   // K slice
-  constexpr int TW = BS / 32;     // MFMA tiles per wave and dimension
-  constexpr int SU = 256 / BS;    // k rows per load step, untransposed loader
-  constexpr int ST = 256 / KS;    // m (n) rows per load step, transposed loader
-  __shared__ double As[KS][BS + 2];
-  __shared__ double Bs[KS][BS + 2];
+  constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
+  constexpr int LA = BM * KS / 256, LB = BN * KS / 256;  // loads per thread and slice
+  static_assert(LA >= 1 && LB >= 1 && 256 % BM == 0 && 256 % BN == 0 && 256 % KS == 0, "shape");
+  __shared__ double As[KS][BM + 2];
+  __shared__ double Bs[KS][BN + 2];
   __shared__ int64_t sstart[GEMM_TASKS_LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t bid = blockIdx.x;
@@ -74,54 +79,49 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict
   }
   const GemmTask tk = tasks[t];
   const int M = tk.M, N = tk.N, K = tk.K;
-  const int mt = (M + BS - 1) / BS;
+  const int mt = (M + BM - 1) / BM;
   const int64_t local = bid - start[t];
-  const int m0 = (int)(local % mt) * BS, n0 = (int)(local / mt) * BS;
+  const int m0 = (int)(local % mt) * BM, n0 = (int)(local / mt) * BN;
   const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
-  // loader coordinates: thread tid takes (m, k) = (tid % BS, tid / BS + SU i)
-  // of an operand stored with m contiguous, (tid / KS + ST i, tid % KS) of
-  // one stored with k contiguous
-  double ra[4], rb[4];
+  auto a_m = [&](int i) { return tk.ta ? tid / KS + (256 / KS) * i : tid % BM; };
+  auto a_k = [&](int i) { return tk.ta ? tid % KS : tid / BM + (256 / BM) * i; };
+  auto b_n = [&](int i) { return tk.tb ? tid % BN : tid / KS + (256 / KS) * i; };
+  auto b_k = [&](int i) { return tk.tb ? tid / BN + (256 / BN) * i : tid % KS; };
+  double ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = tk.ta ? (tid / KS) + ST * i : (tid % BS);
-      const int k = tk.ta ? (tid % KS) : (tid / BS) + SU * i;
-      const int gm = min(m0 + m, M - 1), gk = min(k0 + k, K - 1);
+    for (int i = 0; i < LA; ++i) {
+      const int gm = min(m0 + a_m(i), M - 1), gk = min(k0 + a_k(i), K - 1);
       ra[i] = tk.ta ? tk.A[(int64_t)gm * tk.lda + gk] : tk.A[(int64_t)gk * tk.lda + gm];
-      const int n = tk.tb ? (tid % BS) : (tid / KS) + ST * i;
-      const int kb = tk.tb ? (tid / BS) + SU * i : (tid % KS);
-      const int gn = min(n0 + n, N - 1), gkb = min(k0 + kb, K - 1);
-      rb[i] = tk.tb ? tk.B[(int64_t)gkb * tk.ldb + gn] : tk.B[(int64_t)gn * tk.ldb + gkb];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int gn = min(n0 + b_n(i), N - 1), gk = min(k0 + b_k(i), K - 1);
+      rb[i] = tk.tb ? tk.B[(int64_t)gk * tk.ldb + gn] : tk.B[(int64_t)gn * tk.ldb + gk];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = tk.ta ? (tid / KS) + ST * i : (tid % BS);
-      const int k = tk.ta ? (tid % KS) : (tid / BS) + SU * i;
-      const int gm = m0 + m, gk = k0 + k;
+    for (int i = 0; i < LA; ++i) {
+      const int gm = m0 + a_m(i), gk = k0 + a_k(i);
       // stored element (row, col) = (gm, gk), or (gk, gm) when transposed
       const bool zero_tri = tk.tri && (tk.ta ? gm > gk : gk > gm);
       if (!(gm < M && gk < K) || zero_tri) ra[i] = 0.0;
-      const int n = tk.tb ? (tid % BS) : (tid / KS) + ST * i;
-      const int kb = tk.tb ? (tid / BS) + SU * i : (tid % KS);
-      if (!(n0 + n < N && k0 + kb < K)) rb[i] = 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < LB; ++i)
+      if (!(n0 + b_n(i) < N && k0 + b_k(i) < K)) rb[i] = 0.0;
   };
   auto store = [&]() {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!tk.ta) As[(tid / BS) + SU * i][tid % BS] = ra[i];
-      else As[tid % KS][(tid / KS) + ST * i] = ra[i];
-      if (tk.tb) Bs[(tid / BS) + SU * i][tid % BS] = rb[i];
-      else Bs[tid % KS][(tid / KS) + ST * i] = rb[i];
-    }
+    for (int i = 0; i < LA; ++i) As[a_k(i)][a_m(i)] = ra[i];
+#pragma unroll
+    for (int i = 0; i < LB; ++i) Bs[b_k(i)][b_n(i)] = rb[i];
   };
-  dbl4t acc[TW][TW];
+  dbl4t acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < TW; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TW; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = dbl4t{0.0, 0.0, 0.0, 0.0};
   if (K > 0) load(0);
   for (int k0 = 0; k0 < K; k0 += KS) {
     store();
@@ -129,57 +129,56 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmTask *__restrict
     if (k0 + KS < K) load(k0 + KS);  // in flight during this slice's MFMAs
 #pragma unroll
     for (int ks = 0; ks < KS; ks += 4) {
-      double a[TW], b[TW];
+      double a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TW; ++i) {
-        a[i] = As[ks + lk][wr * (BS / 2) + i * 16 + l16];
-        b[i] = Bs[ks + lk][wc * (BS / 2) + i * 16 + l16];
-      }
+      for (int i = 0; i < TM; ++i) a[i] = As[ks + lk][wr * (BM / 2) + i * 16 + l16];
 #pragma unroll
-      for (int i = 0; i < TW; ++i)
+      for (int j = 0; j < TN; ++j) b[j] = Bs[ks + lk][wc * (BN / 2) + j * 16 + l16];
 #pragma unroll
-        for (int j = 0; j < TW; ++j)
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   // D[i][j] of a 16 x 16 tile: lane j + 16 (i % 4), element i / 4
   const double alpha = tk.alpha, beta = tk.beta;
-  double cv[TW][TW][4];
+  double cv[TM][TN][4];
   if (beta != 0.0) {  // uniform
 #pragma unroll
-    for (int i = 0; i < TW; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TW; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int gm = min(m0 + wr * (BS / 2) + i * 16 + 4 * e + lk, M - 1);
-          const int gn = min(n0 + wc * (BS / 2) + j * 16 + l16, N - 1);
+          const int gm = min(m0 + wr * (BM / 2) + i * 16 + 4 * e + lk, M - 1);
+          const int gn = min(n0 + wc * (BN / 2) + j * 16 + l16, N - 1);
           cv[i][j][e] = tk.C[(int64_t)gn * tk.ldc + gm];
         }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < TW; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TW; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) cv[i][j][e] = alpha * acc[i][j][e] + beta * cv[i][j][e];
   } else {
 #pragma unroll
-    for (int i = 0; i < TW; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TW; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) cv[i][j][e] = alpha * acc[i][j][e];
   }
 #pragma unroll
-  for (int i = 0; i < TW; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TW; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * (BS / 2) + i * 16 + 4 * e + lk;
-        const int gn = n0 + wc * (BS / 2) + j * 16 + l16;
+        const int gm = m0 + wr * (BM / 2) + i * 16 + 4 * e + lk;
+        const int gn = n0 + wc * (BN / 2) + j * 16 + l16;
         if (gm < M && gn < N) tk.C[(int64_t)gn * tk.ldc + gm] = cv[i][j][e];
       }
 }
@@ -192,11 +191,14 @@ int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int nta
     return MVG_ERR_LIMIT;
   }
   if (bs == 32)
-    hipLaunchKernelGGL(k_gemm_batched<32>, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks,
-                       d_start, ntask, d_map);
+    hipLaunchKernelGGL((k_gemm_batched<32, 32, 32>), dim3((unsigned)nblocks), dim3(256), 0, st,
+                       d_tasks, d_start, ntask, d_map);
+  else if (bs == 128)
+    hipLaunchKernelGGL((k_gemm_batched<128, 64, 16>), dim3((unsigned)nblocks), dim3(256), 0, st,
+                       d_tasks, d_start, ntask, d_map);
   else
-    hipLaunchKernelGGL(k_gemm_batched<64>, dim3((unsigned)nblocks), dim3(256), 0, st, d_tasks,
-                       d_start, ntask, d_map);
+    hipLaunchKernelGGL((k_gemm_batched<64, 64, 16>), dim3((unsigned)nblocks), dim3(256), 0, st,
+                       d_tasks, d_start, ntask, d_map);
   return check_launch("gemm_batched");
 }
 
@@ -210,7 +212,8 @@ int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int
 
 int64_t gemm_blocks(const GemmTask &t, int bs) {
   if (t.M <= 0 || t.N <= 0) return 0;
-  return (int64_t)((t.M + bs - 1) / bs) * ((t.N + bs - 1) / bs);
+  const int bm = bs, bn = bs == 128 ? 64 : bs;  // 128: 128 x 64 blocks
+  return (int64_t)((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
 }
 
 }  // namespace mvg
