@@ -18,7 +18,7 @@
 namespace mvg {
 
 constexpr int SB = 32;             // column block
-constexpr int SW = 8;              // waves per workgroup
+constexpr int SW = 4;              // waves per workgroup (two workgroups per CU)
 constexpr int STHREADS = 64 * SW;
 
 typedef double dbl4s __attribute__((ext_vector_type(4)));
@@ -136,11 +136,11 @@ __device__ __forceinline__ void left_update(double *A, int N, int k0, int kb, do
   }
 }
 
-__global__ __launch_bounds__(STHREADS) void k_small_loglik(const SmallTask *__restrict__ tasks,
-                                                           int ntask, int *__restrict__ counter,
-                                                           double *__restrict__ ws_all,
-                                                           int64_t ws_stride,
-                                                           double *__restrict__ out) {
+// Two workgroups per CU (at most 256 registers per lane): one task's
+// generation (FP64 VALU) runs beside another's factorisation (MFMA, memory).
+__global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_small_loglik(
+    const SmallTask *__restrict__ tasks, int ntask, int *__restrict__ counter,
+    double *__restrict__ ws_all, int64_t ws_stride, double *__restrict__ out) {
   __shared__ double sq[4 * QN];
   __shared__ double sD[SB][SB + 1];   // diagonal block -> L_kk
   __shared__ double sW[SB][SB + 1];   // W = L_kk^-1
