@@ -43,6 +43,14 @@ __device__ __forceinline__ void store_at(double *A, int N, int col, int row, dou
   *(double *)((char *)A + ((unsigned)col * (unsigned)N + (unsigned)row) * 8u) = v;
 }
 
+// x of lane l (l uniform) as a uniform value
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Left-looking update of block column k0 (columns k0 .. k0 + kb - 1, rows
 // k0 .. N - 1): A[r][c] -= sum_{q < k0} L[r][q] L[c][q], on FP64 MFMA.  The
 // rows are cut into 32-row output blocks, one per wave (2 x 2 tiles of
@@ -142,7 +150,6 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     const SmallTask *__restrict__ tasks, int ntask, int *__restrict__ counter,
     double *__restrict__ ws_all, int64_t ws_stride, double *__restrict__ out) {
   __shared__ double sq[4 * QN];
-  __shared__ double sD[SB][SB + 1];   // diagonal block -> L_kk
   __shared__ double sW[SB][SB + 1];   // W = L_kk^-1
   __shared__ double sy[SB];
   __shared__ double slg[SB];          // log L_jj of the block
@@ -198,53 +205,71 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         left_update(A, N, k0, kb, part, wave, lane, tid);
         __syncthreads();
       }
-      // (a) diagonal block: Cholesky in LDS (all threads, one column at a time)
-      for (int e = tid; e < kb * kb; e += STHREADS) {
-        const int r = e % kb, c = e / kb;
-        sD[r][c] = (r >= c) ? A[(int64_t)(k0 + c) * N + k0 + r] : 0.0;
-      }
-      if (tid < kb) szk[tid] = zv[k0 + tid];  // final: earlier blocks have updated it
-      __syncthreads();
-      for (int c = 0; c < kb; ++c) {
-        const double d = sD[c][c];
-        const int g = k0 + c;
-        const double tol = (g & 1) ? tk.t1 : tk.t0;
-        if (!(d > tol) || !(d > 0.0)) {
-          if (tid == 0) s_fail = g + 1;
-          break;  // uniform: every thread reads the same d
+      // (a) diagonal block by wave 0 in registers, without workgroup
+      // barriers: lane r holds row r of the block (lanes 32..63 the same rows;
+      // only lanes < 32 write).  Column c's pivot and entries come from their
+      // lanes as uniform values (readlane); then W = L_kk^-1, column c by lane
+      // c, and L_kk back to A.  The arithmetic per entry is that of a
+      // column-by-column Cholesky and a forward substitution per column.
+      if (wave == 0) {
+        const int rr = lane & 31;
+        const bool wl = lane < 32;
+        double a[SB];
+#pragma unroll
+        for (int c = 0; c < SB; ++c) a[c] = clamped_load(A, N, k0 + c, k0 + rr);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < SB; ++c)
+          if (!(c <= rr && rr < kb)) a[c] = 0.0;
+        if (wl && lane < kb) szk[lane] = zv[k0 + lane];  // final: earlier blocks have updated it
+        int fail = 0;
+#pragma unroll
+        for (int c = 0; c < SB; ++c) {
+          if (fail || c >= kb) continue;  // uniform (no break: the loop stays unrolled)
+          const double d = readlane_d(a[c], c);
+          const int g = k0 + c;
+          const double tol = (g & 1) ? tk.t1 : tk.t0;
+          if (!(d > tol) || !(d > 0.0)) {  // uniform
+            fail = g + 1;
+            continue;
+          }
+          const double ljj = sqrt(d);
+          a[c] = rr == c ? ljj : (rr > c ? a[c] / ljj : a[c]);
+#pragma unroll
+          for (int q = c + 1; q < SB; ++q) a[q] -= a[c] * readlane_d(a[c], q);  // rows q <= rr used
         }
-        const double ljj = sqrt(d);
-        __syncthreads();
-        if (tid == 0) sD[c][c] = ljj;
-        for (int r = c + 1 + tid; r < kb; r += STHREADS) sD[r][c] /= ljj;
-        __syncthreads();
-        for (int e = tid; e < kb * kb; e += STHREADS) {
-          const int r = e % kb, q = e / kb;
-          if (q > c && r >= q) sD[r][q] -= sD[r][c] * sD[q][c];
+        if (fail) {
+          if (lane == 0) s_fail = fail;
+        } else {
+          double dg = 0.0;  // this lane's L_rr (static register indices)
+#pragma unroll
+          for (int q = 0; q < SB; ++q)
+            if (q == rr) dg = a[q];
+          if (wl && lane < kb) slg[lane] = log(dg);
+          // column c of W by lane c (rows above c are zeros, so the sums over
+          // q < c add exact zeros); entries outside the kb x kb block are zero
+          const int c = rr;
+          double w[SB];
+#pragma unroll
+          for (int r = 0; r < SB; ++r) {
+            double sacc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < r; ++q) sacc -= readlane_d(a[q], r) * w[q];
+            w[r] = (r >= c && r < kb) ? sacc / readlane_d(a[r], r) : 0.0;
+          }
+          if (wl) {
+#pragma unroll
+            for (int r = 0; r < SB; ++r) sW[r][c] = w[r];
+            // L_kk back to A (the solve of later columns does not need it)
+            if (rr < kb)
+#pragma unroll
+              for (int q = 0; q < SB; ++q)
+                if (q <= rr) A[(int64_t)(k0 + q) * N + k0 + rr] = a[q];
+          }
         }
-        __syncthreads();
       }
       __syncthreads();
       if (s_fail) break;
-      // log L_jj off the column loop's critical path, summed in column order
-      if (tid < kb) slg[tid] = log(sD[tid][tid]);
-      // W = L_kk^-1, column c by thread c with the column in registers (the
-      // rows above c are zeros, so the sums over q < c add exact zeros), then
-      // y_k = W z_k; entries outside the kb x kb block are zero
-      if (tid < SB) {
-        const int c = tid;
-        double w[SB];
-#pragma unroll
-        for (int r = 0; r < SB; ++r) {
-          double s = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-          for (int q = 0; q < r; ++q) s -= sD[r][q] * w[q];
-          w[r] = (r >= c && r < kb) ? s / sD[r][r] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < SB; ++r) sW[r][c] = w[r];
-      }
-      __syncthreads();
       if (tid == 0) {
         double ld = s_logdet;
         for (int c = 0; c < kb; ++c) ld += slg[c];
@@ -262,11 +287,6 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         double q = s_quad;
         for (int c = 0; c < kb; ++c) q += sy[c] * sy[c];
         s_quad = q;
-      }
-      // L_kk back to A (the solve of later columns does not need it)
-      for (int e = tid; e < kb * kb; e += STHREADS) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) A[(int64_t)(k0 + c) * N + k0 + r] = sD[r][c];
       }
       // (b) panel rows i >= k0 + kb: L_i = A_i W^T on MFMA, 16 rows per wave
       //     (a wave reads its rows' A values before it overwrites them)
