@@ -32,7 +32,8 @@ Each function states the passage of the paper it follows:
   (Section 4.4; "DST 40/60" and "DST 70/30" of Experiment 2, Section 6.4.1):
   the tiles far from the diagonal set to zero.
 * ``mixed_cholesky_emulated`` -- not in the paper: the mixed-precision tiled
-  factorisation (FP64 band, FP32 / BF16 off the band) emulated in FP64 with
+  factorisation (FP64 band, FP32 / BF16 / split-BF16 off the band) emulated
+  in FP64 with
   rounding at the operand points, to predict the size of its error (not its
   bits).  Pinned by the defining equations of its rounding points: band
   blocks reproduce S to FP64 rounding, off-band blocks deviate at the
@@ -334,7 +335,11 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
     """Not in the paper.  Right-looking tiled Cholesky of S (padded with an
     identity block to a multiple of nb) where the trailing updates of tiles
     (I, J) with I - J >= band take operands rounded to ``fmt`` ("fp32",
-    "bf16", or "fp64" for no rounding), everything else in FP64.
+    "bf16", "bf16x3", or "fp64" for no rounding), everything else in FP64.
+
+    "bf16x3" (MVG_MIXED_BF16X3) splits each operand value a into
+    a_hi = bf16(fp32(a)) and a_lo = bf16(fp32(a) - a_hi) and forms each product
+    as a_hi b_hi + a_hi b_lo + a_lo b_hi (the a_lo b_lo term dropped).
 
     storage "fp32" (MVG_MIXED_FP32 / BF16): those tiles are stored in FP32:
 
@@ -358,7 +363,8 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
     ``_plant`` exists only for the tests that check the pins of this function
     can fail: "band_operands" rounds the operands of band-target updates too,
     "w32" solves off-band panel tiles against round32(W_k) in FP64 storage.
-    Both are mistakes; the default "" is the definition above."""
+    "x3_hi_only" keeps only a_hi b_hi of a "bf16x3" product.  All three are
+    mistakes; the default "" is the definition above."""
     S = _f64(S)
     N = S.shape[0]
     T = (N + nb - 1) // nb
@@ -375,11 +381,22 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
             return a
         return round_to(a, "fp32") if fmt == "fp32" else round_to(round_to(a, "fp32"), "bf16")
 
-    if fmt not in ("fp32", "bf16", "fp64"):
+    def lowp_product(Li, Lj):
+        """op(L_i) op(L_j)^T, or the three-term product of the BF16 splits."""
+        if fmt != "bf16x3":
+            return op(Li) @ op(Lj).T
+        fi, fj = round_to(Li, "fp32"), round_to(Lj, "fp32")
+        hi_i, hi_j = round_to(fi, "bf16"), round_to(fj, "bf16")
+        lo_i, lo_j = round_to(fi - hi_i, "bf16"), round_to(fj - hi_j, "bf16")
+        if _plant == "x3_hi_only":
+            return hi_i @ hi_j.T
+        return hi_i @ hi_j.T + hi_i @ lo_j.T + lo_i @ hi_j.T
+
+    if fmt not in ("fp32", "bf16", "bf16x3", "fp64"):
         raise ValueError(fmt)
     if storage not in ("fp32", "fp64"):
         raise ValueError(storage)
-    if _plant not in ("", "band_operands", "w32"):
+    if _plant not in ("", "band_operands", "w32", "x3_hi_only"):
         raise ValueError(_plant)
     low = storage == "fp32"
     if low:
@@ -405,13 +422,13 @@ def mixed_cholesky_emulated(S: np.ndarray, nb: int, band: int, fmt: str, storage
             for i in range(j, T):
                 Li, Lj = A[blk(i, k)], A[blk(j, k)]
                 if i - j < band and _plant == "band_operands":
-                    A[blk(i, j)] = A[blk(i, j)] - op(Li) @ op(Lj).T
+                    A[blk(i, j)] = A[blk(i, j)] - lowp_product(Li, Lj)
                 elif i - j < band:
                     A[blk(i, j)] = A[blk(i, j)] - Li @ Lj.T
                 elif low:
-                    A[blk(i, j)] = round_to(A[blk(i, j)] - op(Li) @ op(Lj).T, "fp32")
+                    A[blk(i, j)] = round_to(A[blk(i, j)] - lowp_product(Li, Lj), "fp32")
                 else:
-                    A[blk(i, j)] = A[blk(i, j)] - op(Li) @ op(Lj).T
+                    A[blk(i, j)] = A[blk(i, j)] - lowp_product(Li, Lj)
     return np.tril(A), 0
 
 

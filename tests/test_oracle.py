@@ -424,14 +424,16 @@ def _mixed_pin_violations(orc, S, L, nb, band, fmt, storage):
       rounding (updates into band tiles take the stored values exactly, the
       diagonal tile and its panel solve are FP64): relative residual
       <= 8 u kappa(L_JJ);
-    * off-band blocks: the same residual is at FP32 scale, neither FP64
-      rounding (a missing rounding) nor beyond 2e-2 (bf16) / 1e-6 (fp32);
-      with FP32 storage relative to the block, with FP64 storage relative to
-      the products of the updates it received (J >= 1), where the rounding
-      sits;
+    * off-band blocks: the same residual is at the operand precision's
+      scale, neither FP64 rounding (a missing rounding) nor beyond 2e-2
+      (bf16) / 1e-4 (bf16x3) / 1e-6 (fp32); with FP32 storage relative to
+      the block, with FP64 storage relative to the products of the updates it
+      received (J >= 1), where the rounding sits; with FP64 storage the
+      split-BF16 products (operand error 2^-17) also stay above 3e-7, which
+      FP32 operands (2^-24) do not reach;
     * FP64 storage: every off-band panel tile solves its Schur complement in
-      FP64, L_IJ L_JJ^T = S_IJ - sum_{k < J} op(L_Ik) op(L_Jk)^T with op the
-      operand rounding, to 8 u kappa(L_JJ).
+      FP64, L_IJ L_JJ^T = S_IJ - sum_{k < J} P(L_Ik, L_Jk) with P the
+      rounded-operand product, to 8 u kappa(L_JJ).
     Returns the list of violated pins (empty when all hold)."""
     u = 2.0 ** -53
     N = S.shape[0]
@@ -447,7 +449,19 @@ def _mixed_pin_violations(orc, S, L, nb, band, fmt, storage):
         f = orc.round_to(a, "fp32")
         return f if fmt == "fp32" else orc.round_to(f, "bf16")
 
-    top = 1e-6 if fmt == "fp32" else 2e-2   # u = 2^-24 and 2^-8 per operand
+    def prod_lowp(a, b):
+        """The rounded-operand product: op(a) op(b)^T, or for bf16x3 the
+        three products of the two-term BF16 splits a = a_hi + a_lo."""
+        if fmt != "bf16x3":
+            return op(a) @ op(b).T
+        fa, fb = orc.round_to(a, "fp32"), orc.round_to(b, "fp32")
+        ha, hb = orc.round_to(fa, "bf16"), orc.round_to(fb, "bf16")
+        la, lb = orc.round_to(fa - ha, "bf16"), orc.round_to(fb - hb, "bf16")
+        return ha @ hb.T + ha @ lb.T + la @ hb.T
+
+    # u = 2^-24, 2^-17 and 2^-8 per operand
+    top = {"fp32": 1e-6, "bf16x3": 1e-4, "bf16": 2e-2}[fmt]
+    low64 = 3e-7 if fmt == "bf16x3" else 1e-11
     bad = []
     for J in range(T):
         kap = np.linalg.cond(L[B(J, J)])
@@ -465,10 +479,10 @@ def _mixed_pin_violations(orc, S, L, nb, band, fmt, storage):
             elif J >= 1:   # FP64 storage: the rounding sits in the products alone
                 prod = np.max(sum(np.abs(L[B(I, k)]) @ np.abs(L[B(J, k)]).T for k in range(J)))
                 relp = np.max(np.abs(Sp[B(I, J)] - full)) / prod
-                if not (1e-11 < relp <= top):
+                if not (low64 < relp <= top):
                     bad.append(("offband-scale", I, J, relp))
             if storage == "fp64" and I - J >= band:
-                schur = Sp[B(I, J)] - sum((op(L[B(I, k)]) @ op(L[B(J, k)]).T for k in range(J)),
+                schur = Sp[B(I, J)] - sum((prod_lowp(L[B(I, k)], L[B(J, k)]) for k in range(J)),
                                           np.zeros((nb, nb)))
                 r3 = np.max(np.abs(schur - L[B(I, J)] @ L[B(J, J)].T)) / scale
                 if r3 > 8 * u * kap:
@@ -478,7 +492,7 @@ def _mixed_pin_violations(orc, S, L, nb, band, fmt, storage):
 
 @pytest.mark.parametrize("a", [0.03, 0.1])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
-@pytest.mark.parametrize("fmt", ["fp32", "bf16"])
+@pytest.mark.parametrize("fmt", ["fp32", "bf16", "bf16x3"])
 def test_mixed_emulation_satisfies_its_rounding_definition(orc, a, storage, fmt):
     """Mixed precision is not in the paper: its definition is the placement of
     the rounding points (FP64 band and FP64 diagonal factors; off-band products
@@ -513,6 +527,35 @@ def test_mixed_emulation_pins_catch_missing_offband_rounding(orc):
     assert info == 0
     bad = _mixed_pin_violations(orc, S, L, 32, 2, "fp32", "fp64")
     assert any(b[0] == "offband-scale" for b in bad), bad
+
+
+@pytest.mark.parametrize("plant,fmt_made,fmt_pinned", [("x3_hi_only", "bf16x3", "bf16x3"),
+                                                       ("", "fp32", "bf16x3")])
+def test_mixed_emulation_pins_catch_a_wrong_split(orc, plant, fmt_made, fmt_pinned):
+    """Split-BF16 products (FP64 storage): keeping only a_hi b_hi (plain BF16
+    operands) puts the off-band residuals above the split's scale, and
+    unsplit FP32 operands put them below it; both break the off-band pin."""
+    S = _small_cov(orc, 90, 0.1)
+    L, info = orc.mixed_cholesky_emulated(S, 32, 2, fmt_made, "fp64", _plant=plant)
+    assert info == 0
+    bad = _mixed_pin_violations(orc, S, L, 32, 2, fmt_pinned, "fp64")
+    assert any(b[0] == "offband-scale" for b in bad), bad
+
+
+def test_bf16_split_error_bound(orc):
+    """The two-term BF16 split of an FP32 value f with 2^e <= |f| < 2^(e+1):
+    f_hi = bf16(f) is off by at most 2^(e-8), so the remainder r = f - f_hi
+    (exact in FP32) is a power of two (then exact in BF16) or below 2^(e-8),
+    and bf16(r) is off by at most 2^(e-17): |f - f_hi - f_lo| <= 2^-17 |f|.
+    On BF16-representable values the remainder is 0."""
+    rng = np.random.default_rng(5)
+    f = orc.round_to(rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000)), "fp32")
+    hi = orc.round_to(f, "bf16")
+    lo = orc.round_to(f - hi, "bf16")
+    assert np.all(np.abs(f - hi) <= 2.0 ** -8 * np.abs(f))
+    assert np.all(np.abs(f - hi - lo) <= 2.0 ** -17 * np.abs(f))
+    assert np.max(np.abs(f - hi - lo) / np.abs(f)) > 2.0 ** -24  # not exact in general
+    assert np.all(orc.round_to(hi - orc.round_to(hi, "bf16"), "bf16") == 0.0)
 
 
 def test_tlr_frobenius_rule_keeps_more_and_bounds_tail(orc):
