@@ -6,8 +6,9 @@
 // quadrature table in LDS, the lower triangle of Sigma in its private
 // workspace, a left-looking Cholesky in column blocks of SB (each block
 // column first receives all earlier columns' updates on FP64 MFMA, then its
-// diagonal block is factored in LDS with its inverse and the rows below are
-// solved by that inverse), the forward solve folded into the factorisation,
+// diagonal block is factored by one wave in registers with its inverse and
+// the rows below are solved by that inverse on MFMA), the forward solve
+// folded into the factorisation,
 // and the log-determinant and quadratic form summed in a fixed order.  A task's
 // arithmetic does not depend on which workgroup runs it or on the other
 // tasks, so results are the same alone and in any batch.
@@ -51,94 +52,132 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Left-looking update of block column k0 (columns k0 .. k0 + kb - 1, rows
-// k0 .. N - 1): A[r][c] -= sum_{q < k0} L[r][q] L[c][q], on FP64 MFMA.  The
-// rows are cut into 32-row output blocks, one per wave (2 x 2 tiles of
-// 16 x 16: lane j + 16 (i % 4), element i / 4 of a tile); when there are
-// fewer blocks than waves, the q range of a block is split over several
-// waves and their partial tiles are summed in a fixed order through the
-// workgroup's scratch.  Reading the panels L[., < k0] once per block column
-// moves about a third of the bytes of a right-looking update, which reads and
-// writes the trailing matrix at every step.  Every load is from a clamped
-// address inside the task's N x N workspace, masked after the load; the next
-// 8 columns' operands are in flight while the current ones feed the MFMAs.
-__device__ __forceinline__ void left_update(double *A, int N, int k0, int kb, double *part,
-                                            int wave, int lane, int tid) {
+// Sum of x over the 16 lanes of a DPP row (lanes 16 g .. 16 g + 15), in lane
+// 16 g: pairs, quads, halves of the row (lane i with 7 - i), then the row
+// mirrored (lane i with 15 - i).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_d<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_d<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_d<0x141>(x);  // row_half_mirror
+  x += dpp_d<0x140>(x);  // row_mirror
+  return x;
+}
+
+// Left-looking update of the columns k0 .. k0 + kb - 1 (kb <= 16 NT), rows
+// k0 .. N - 1, by the columns q in [qlo, k0): A[r][c] -= sum_q L[r][q] L[c][q],
+// on FP64 MFMA.  The rows are cut into 32-row output blocks, one per wave
+// (2 x NT tiles of 16 x 16: lane j + 16 (i % 4), element i / 4 of a tile);
+// when there are fewer blocks than waves, the q range of a block is split over
+// several waves and their partial tiles are summed in a fixed order through
+// the workgroup's scratch.  The block columns are updated two at a time
+// (NT = 4: 64 columns by every earlier column, then the second block of the
+// pair by the first one alone, NT = 2), so the panels L[., < k0] are read once
+// per 64 columns: about a sixth of the bytes of a right-looking update, which
+// reads and writes the trailing matrix at every step.  Every load is from a
+// clamped address inside the task's N x N workspace, masked after the load;
+// the next 16 columns' operands are in flight while the current ones feed
+// the MFMAs.  Outputs above the diagonal (the first row block of the second
+// block of a pair) are computed and stored like the others and never read.
+template <int NT>
+__device__ __forceinline__ void left_update(double *A, int N, int k0, int kb, int qlo,
+                                            double *part, int wave, int lane, int tid) {
+  constexpr int BW = 16 * NT;  // output columns of a block
   const int l16 = lane & 15, lk = lane >> 4;
   const int nout = (N - k0 + 31) / 32;
   const int splits = nout >= SW ? 1 : SW / nout;
   const int nitems = nout * splits;
-  const int kc = (k0 / splits + 7) / 8 * 8;  // q per part (a multiple of 8)
+  const int K = k0 - qlo;
+  const int kc = (K / splits + 7) / 8 * 8;  // q per part (a multiple of 8)
   for (int it = wave; it < nitems; it += SW) {
     const int b = it / splits, pt = it % splits;
     const int iA = k0 + 32 * b;
-    const int q0 = min(k0, pt * kc), q1 = min(k0, q0 + kc);
-    dbl4s acc[2][2];
+    const int q0 = qlo + min(K, pt * kc), q1 = qlo + min(K, pt * kc + kc);
+    dbl4s acc[2][NT];
 #pragma unroll
     for (int hi = 0; hi < 2; ++hi)
 #pragma unroll
-      for (int hj = 0; hj < 2; ++hj)
+      for (int hj = 0; hj < NT; ++hj)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           acc[hi][hj][e] = pt == 0 ? clamped_load(A, N, k0 + 16 * hj + l16, iA + 16 * hi + 4 * e + lk)
                                    : 0.0;
-    double ca[2][2], cb[2][2];  // [h][kk]: rows 16 h + l16, columns q + 4 kk + lk
-    auto fetch = [&](int q, double (&fa)[2][2], double (&fb)[2][2]) {
+    double ca[2][2], cb[NT][2];  // [h][kk]: rows 16 h + l16, columns q + 4 kk + lk
+    auto fetch = [&](int q, double (&fa)[2][2], double (&fb)[NT][2]) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          fa[h][kk] = clamped_load(A, N, q + 4 * kk + lk, iA + 16 * h + l16);
-          fb[h][kk] = clamped_load(A, N, q + 4 * kk + lk, k0 + 16 * h + l16);
-        }
+        for (int h = 0; h < 2; ++h) fa[h][kk] = clamped_load(A, N, q + 4 * kk + lk, iA + 16 * h + l16);
+#pragma unroll
+        for (int h = 0; h < NT; ++h) fb[h][kk] = clamped_load(A, N, q + 4 * kk + lk, k0 + 16 * h + l16);
+      }
     };
-    if (q0 < q1) fetch(q0, ca, cb);
+    // two chunks of 8 columns in flight ahead of the one feeding the MFMAs
+    // (addresses clamped to the last column; chunks past q1 are not used)
+    double ma[2][2], mb[NT][2];
+    if (q0 < q1) {
+      fetch(q0, ca, cb);
+      fetch(min(q0 + 8, q1 - 1), ma, mb);
+    }
     for (int q = q0; q < q1; q += 8) {
-      double na[2][2], nb2[2][2];
-      fetch(min(q + 8, q1 - 1), na, nb2);  // next chunk (clamped; unused past q1)
+      double na[2][2], nb2[NT][2];
+      fetch(min(q + 16, q1 - 1), na, nb2);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int kk = 0; kk < 2; ++kk) {
+        const bool okq = q + 4 * kk + lk < q1;
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          const bool okq = q + 4 * kk + lk < q1;
-          ca[h][kk] = (okq && iA + 16 * h + l16 < N) ? -ca[h][kk] : 0.0;
+        for (int h = 0; h < 2; ++h) ca[h][kk] = (okq && iA + 16 * h + l16 < N) ? -ca[h][kk] : 0.0;
+#pragma unroll
+        for (int h = 0; h < NT; ++h)
           if (!(okq && 16 * h + l16 < kb)) cb[h][kk] = 0.0;
-        }
+      }
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
         for (int hi = 0; hi < 2; ++hi)
 #pragma unroll
-          for (int hj = 0; hj < 2; ++hj)
+          for (int hj = 0; hj < NT; ++hj)
             acc[hi][hj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[hi][kk], cb[hj][kk], acc[hi][hj], 0, 0, 0);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          ca[h][kk] = na[h][kk];
-          cb[h][kk] = nb2[h][kk];
+        for (int h = 0; h < 2; ++h) {
+          ca[h][kk] = ma[h][kk];
+          ma[h][kk] = na[h][kk];
         }
+#pragma unroll
+        for (int h = 0; h < NT; ++h) {
+          cb[h][kk] = mb[h][kk];
+          mb[h][kk] = nb2[h][kk];
+        }
+      }
     }
 #pragma unroll
     for (int hi = 0; hi < 2; ++hi)
 #pragma unroll
-      for (int hj = 0; hj < 2; ++hj)
+      for (int hj = 0; hj < NT; ++hj)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = 16 * hi + 4 * e + lk, c = 16 * hj + l16;
           if (splits == 1) {
             if (iA + r < N && c < kb) store_at(A, N, k0 + c, iA + r, acc[hi][hj][e]);
           } else {
-            part[(int64_t)wave * (SB * SB) + c * SB + r] = acc[hi][hj][e];
+            part[(int64_t)wave * (32 * BW) + c * 32 + r] = acc[hi][hj][e];
           }
         }
   }
   if (splits > 1) {  // item it ran on wave it (nitems <= SW)
     __syncthreads();
-    for (int e = tid; e < nout * SB * SB; e += STHREADS) {
-      const int b = e / (SB * SB), idx = e % (SB * SB), r = idx % SB, c = idx / SB;
+    for (int e = tid; e < nout * 32 * BW; e += STHREADS) {
+      const int b = e / (32 * BW), idx = e % (32 * BW), r = idx % 32, c = idx / 32;
       double t = 0.0;
-      for (int p = 0; p < splits; ++p) t += part[(int64_t)(b * splits + p) * (SB * SB) + idx];
+      for (int p = 0; p < splits; ++p) t += part[(int64_t)(b * splits + p) * (32 * BW) + idx];
       if (k0 + 32 * b + r < N && c < kb) store_at(A, N, k0 + c, k0 + 32 * b + r, t);
     }
   }
@@ -168,7 +207,7 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     const int n = (int)tk.n, N = 2 * n;
     double *A = ws;          // N x N, column-major, ld N (lower triangle used)
     double *zv = ws + (int64_t)N * N;  // right-hand side being solved
-    double *part = zv + N;   // SW partial 32 x 32 tiles of the split updates
+    double *part = zv + N;   // SW partial 32 x 64 tiles of the split updates
     // quadrature table
     for (int k = tid; k < QN; k += STHREADS) quad_entry(k, tk.P, sq);
     for (int i = tid; i < N; i += STHREADS) zv[i] = tk.z[i];
@@ -178,17 +217,17 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       s_quad = 0.0;
     }
     __syncthreads();
-    // Sigma: 2 x 2 blocks of the n (n + 1) / 2 location pairs l >= r, pair
-    // p = r (2n - r + 1) / 2 + (l - r), spread evenly over the threads
-    const int npair = n * (n + 1) / 2;
+    // Sigma: 2 x 2 blocks of the n (n + 1) / 2 location pairs l >= r, spread
+    // evenly over the threads.  Column r of the pairs (l = r .. n - 1) and
+    // column n - 1 - r together hold n + 1 pairs, so pair p is entry p % (n + 1)
+    // of folded row p / (n + 1) (for odd n the middle column is the last,
+    // half-filled row); a thread steps its (row, entry) by STHREADS pairs.
+    const int npair = n * (n + 1) / 2, wf = n + 1;
+    int fi = tid / wf, fc = tid % wf;
     for (int pq = tid; pq < npair; pq += STHREADS) {
-      // r = the column whose pairs contain pq (exact integer fix-up after the root)
-      const double nn = 2.0 * n + 1.0;
-      int r = (int)((nn - sqrt(nn * nn - 8.0 * (double)pq)) * 0.5);
-      r = max(0, min(r, n - 1));
-      while (r > 0 && r * (2 * n - r + 1) / 2 > pq) --r;
-      while (r + 1 < n && (r + 1) * (2 * n - r) / 2 <= pq) ++r;
-      const int l = r + (pq - r * (2 * n - r + 1) / 2);
+      const bool first = fc < n - fi;
+      const int r = first ? fi : n - 1 - fi;
+      const int l = first ? fi + fc : r + (fc - (n - fi));
       double c[3];
       cross_cov_block(tk.x[l], tk.y[l], tk.x[r], tk.y[r], tk.P, sq, c);
       double *a = A + (int64_t)(2 * r) * N + 2 * l;
@@ -196,13 +235,23 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       a[1] = c[2];
       a[N] = c[2];
       a[N + 1] = c[1];
+      fc += STHREADS;
+      while (fc >= wf) {
+        fc -= wf;
+        ++fi;
+      }
     }
     __syncthreads();
     for (int k0 = 0; k0 < N; k0 += SB) {
       const int kb = min(SB, N - k0);
       // (u) this block column receives all earlier columns' updates at once
+      // (two at a time: the first block of a pair takes every earlier
+      // column for both blocks, the second then only the first's columns)
       if (k0 > 0) {
-        left_update(A, N, k0, kb, part, wave, lane, tid);
+        if ((k0 / SB) % 2 == 0)
+          left_update<2 * SB / 16>(A, N, k0, min(2 * SB, N - k0), 0, part, wave, lane, tid);
+        else
+          left_update<SB / 16>(A, N, k0, kb, k0 - SB, part, wave, lane, tid);
         __syncthreads();
       }
       // (a) diagonal block by wave 0 in registers, without workgroup
@@ -252,10 +301,12 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           double w[SB];
 #pragma unroll
           for (int r = 0; r < SB; ++r) {
-            double sacc = (r == c) ? 1.0 : 0.0;
+            // (the right-hand side e_c enters as the 1 at r = c, where the sum
+            // is over zeros: no per-lane constant held across the task loop)
+            double sacc = 0.0;
 #pragma unroll
             for (int q = 0; q < r; ++q) sacc -= readlane_d(a[q], r) * w[q];
-            w[r] = (r >= c && r < kb) ? sacc / readlane_d(a[r], r) : 0.0;
+            w[r] = (r >= c && r < kb) ? (r == c ? 1.0 : sacc) / readlane_d(a[r], r) : 0.0;
           }
           if (wl) {
 #pragma unroll
@@ -289,48 +340,60 @@ __global__ __launch_bounds__(STHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         s_quad = q;
       }
       // (b) panel rows i >= k0 + kb: L_i = A_i W^T on MFMA, 16 rows per wave
-      //     (a wave reads its rows' A values before it overwrites them)
+      //     (a wave reads its rows' A values before it overwrites them), and
+      //     the solve's z_i -= L_i y_k from the same accumulators (a row's 16
+      //     columns of a half are in the 16 lanes of one DPP row)
+      //     W's fragments are the same for every tile (registers); the next
+      //     tile's A values are in flight while this one's feed the MFMAs
       const int r0 = k0 + kb;
       const int l16 = lane & 15, lk = lane >> 4;
-      for (int t = wave; t < (N - r0 + 15) / 16; t += SW) {
+      const int ntile = (N - r0 + 15) / 16;
+      double wf[SB / 16][SB / 4];
+#pragma unroll
+      for (int half = 0; half < SB / 16; ++half)
+#pragma unroll
+        for (int kk = 0; kk < SB / 4; ++kk) wf[half][kk] = sW[half * 16 + l16][4 * kk + lk];
+      double avn[SB / 4];
+#pragma unroll
+      for (int kk = 0; kk < SB / 4; ++kk)
+        avn[kk] = clamped_load(A, N, k0 + 4 * kk + lk, r0 + wave * 16 + l16);
+      for (int t = wave; t < ntile; t += SW) {
         const int row = r0 + t * 16 + l16;
         double av[SB / 4];
 #pragma unroll
-        for (int kk = 0; kk < SB / 4; ++kk) av[kk] = clamped_load(A, N, k0 + 4 * kk + lk, row);
+        for (int kk = 0; kk < SB / 4; ++kk) {
+          av[kk] = avn[kk];
+          avn[kk] = clamped_load(A, N, k0 + 4 * kk + lk, row + 16 * SW);  // next tile (clamped)
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kk = 0; kk < SB / 4; ++kk)
           if (!(row < N && 4 * kk + lk < kb)) av[kk] = 0.0;
+        double zp[4] = {0.0, 0.0, 0.0, 0.0};  // rows 4 e + lk of the tile
 #pragma unroll
         for (int half = 0; half < SB / 16; ++half) {
           dbl4s acc = dbl4s{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int kk = 0; kk < SB / 4; ++kk)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], sW[half * 16 + l16][4 * kk + lk], acc,
-                                                       0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], wf[half][kk], acc, 0, 0, 0);
           const int c = half * 16 + l16;
+          const double yc = sy[c];  // zero for c >= kb
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int gi = r0 + t * 16 + 4 * e + lk;
             if (gi < N && c < kb) A[(int64_t)(k0 + c) * N + gi] = acc[e];
+            zp[e] += acc[e] * yc;
           }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double zs = row16_sum(zp[e]);
+          const int gi = r0 + t * 16 + 4 * e + lk;
+          if (l16 == 0 && gi < N) zv[gi] -= zs;
         }
       }
       __syncthreads();
-      for (int i = r0 + tid; i < N; i += STHREADS) {  // z_i -= L_i y_k
-        double v[SB];
-#pragma unroll
-        for (int c = 0; c < SB; ++c) v[c] = clamped_load(A, N, k0 + c, i);
-        __builtin_amdgcn_sched_barrier(0);
-        double zi = 0.0;
-#pragma unroll
-        for (int c = 0; c < SB; ++c)
-          if (c < kb) zi += v[c] * sy[c];
-        zv[i] -= zi;
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
+    }    if (tid == 0) {
       double *o = out + 4 * (int64_t)ti;
       if (s_fail) {
         o[0] = -INFINITY;
@@ -357,7 +420,7 @@ int small_batch_workgroups(int ntask) { return ntask < 2 * 256 ? ntask : 2 * 256
 
 size_t small_workspace_doubles(int64_t nmax) {
   const int64_t N = 2 * nmax;
-  return (size_t)(N * N + N + SW * SB * SB);  // matrix, right-hand side, split partials
+  return (size_t)(N * N + N + SW * SB * 2 * SB);  // matrix, right-hand side, split partials
 }
 
 int launch_small_loglik(const SmallTask *d_tasks, int ntask, int64_t nmax, int *d_counter,
