@@ -57,8 +57,10 @@ enum {
     MVG_TLR = 3,         /* tile low-rank, FP64 (Section 5.3)                       */
     MVG_DST = 4,         /* Diagonal Super Tile (Section 4.4, Experiment 2 of 6.4): */
                          /* exact FP64 with the tiles |I - J| >= band_tiles set to 0 */
-    MVG_MIXED_FP32X = 5  /* FP64 tiles and panel solves; off-band trailing GEMMs on  */
+    MVG_MIXED_FP32X = 5, /* FP64 tiles and panel solves; off-band trailing GEMMs on  */
                          /* FP32 MFMA (operands rounded to FP32), FP64 refinement   */
+    MVG_MIXED_BF16X3 = 6 /* as MVG_MIXED_FP32X, the off-band operands split into two */
+                         /* BF16 terms, three BF16 MFMAs per product, FP32 accum.   */
 };
 
 typedef struct {
@@ -134,8 +136,8 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * (2 n_loc <= MVG_SMALL_MAX_ROWS, FP64, see loglik_many).  keep (nullable, n_theta == 1 only) receives a resident factor for
  * cokrige_predict.  Returns 0, -1..-12 for bad arguments, MVG_ERR_*.
  *
- * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_MIXED_FP32X; not in
- * the paper): Sigma is
+ * Mixed precision (MVG_MIXED_FP32 / MVG_MIXED_BF16 / MVG_MIXED_FP32X /
+ * MVG_MIXED_BF16X3; not in the paper): Sigma is
  * generated once in FP64 and kept for the refinement; the factor has FP64
  * tiles within band_tiles of the diagonal (all diagonal factorisations FP64)
  * and FP32 tiles elsewhere, updated on FP32 (or BF16-operand) MFMA.  The solve
@@ -153,6 +155,12 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * panel) on FP32 MFMA, with 16-product stage sums added to the FP64 tile.
  * The log-determinant then carries only the operand rounding; memory is that
  * of two FP64 copies of Sigma.
+ * MVG_MIXED_BF16X3 (not in the paper) is MVG_MIXED_FP32X with the off-band
+ * operands split as a = a_hi + a_lo (a_hi: BF16 rounding of the FP32 value,
+ * a_lo: BF16 rounding of the remainder) and each product formed as
+ * a_hi b_hi + a_hi b_lo + a_lo b_hi on BF16 MFMA with FP32 accumulation over
+ * the tile's K, added to the FP64 tile once: each operand carries at most
+ * 2^-17 relative error, each product about 2^-15 at most (a_lo b_lo dropped).
  *
  * DST (MVG_DST): Eq. (1) of the Diagonal Super Tile matrix (Section 4.4),
  * Sigma with the tiles |I - J| >= band_tiles set to zero, in FP64; the

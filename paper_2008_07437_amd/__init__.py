@@ -9,6 +9,7 @@ the built library or a GPU every call raises.
 """
 from ._lib import (  # noqa: F401
     MVG_FP64, MVG_MIXED_FP32, MVG_MIXED_BF16, MVG_TLR, MVG_DST, MVG_MIXED_FP32X,
+    MVG_MIXED_BF16X3,
     Opts, Theta, ThetaP, Mat, Factor, MvgError, cov_generate_p, loglik_p, profile_loglik_p,
     mle_fit, MleOpts,
     library_path, morton_order, cov_generate, potrf_tiled, loglik, loglik_many,

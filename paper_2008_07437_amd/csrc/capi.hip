@@ -324,13 +324,13 @@ using namespace mvg;
 
 static bool is_mixed(int precision) {
   return precision == MVG_MIXED_FP32 || precision == MVG_MIXED_BF16 ||
-         precision == MVG_MIXED_FP32X;
+         precision == MVG_MIXED_FP32X || precision == MVG_MIXED_BF16X3;
 }
 
 static int normalize_opts(const mvg_opts *o, mvg_opts *out) {
   mvg_opts d{};
   if (o) d = *o;
-  if (d.precision < MVG_FP64 || d.precision > MVG_MIXED_FP32X) return -1;
+  if (d.precision < MVG_FP64 || d.precision > MVG_MIXED_BF16X3) return -1;
   if (d.nb == 0) d.nb = (d.precision == MVG_TLR) ? 1200 : 512;
   if (d.precision == MVG_TLR) {
     if (d.nb < 64 || d.nb % 2 || d.nb > QR_MAXM) return -2;
@@ -633,7 +633,8 @@ size_t mvg_footprint(int64_t n_loc, const mvg_opts *o) {
     b += layout_bytes(n_loc, f);  // FP64 Sigma kept for the refinement
     b += sizeof(double) * (size_t)T * (T + 1) * d.nb;  // symmetric-product partials
     b += sizeof(double) * (size_t)4 * Np;              // refinement vectors
-    b += (size_t)(T > 1 ? T - 1 : 1) * d.nb * d.nb * (4 + (d.precision == MVG_MIXED_BF16 ? 2 : 0));
+    const int p16b = d.precision == MVG_MIXED_BF16 ? 2 : d.precision == MVG_MIXED_BF16X3 ? 4 : 0;
+    b += (size_t)(T > 1 ? T - 1 : 1) * d.nb * d.nb * (4 + p16b);
   }
   return b;
 }

@@ -15,7 +15,9 @@
 //   the look-ahead stream factors the next diagonal tile in FP64.
 // FP32X keeps every tile in FP64 and solves every panel in FP64; only the
 // off-band trailing GEMMs run on FP32 MFMA (operands rounded from the FP64
-// panel, 16-product stage sums added to the FP64 tile).
+// panel, 16-product stage sums added to the FP64 tile).  BF16X3 is FP32X
+// with each off-band operand split into two BF16 terms and each product
+// formed from three BF16 MFMAs (FP32 accumulation, added to the FP64 tile).
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -307,6 +309,123 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #undef LP_STB
 }
 
+// ------------------------------------------------------ split-BF16 GEMM
+//
+// Off-band update of an FP64 target tile, C -= A B^T, with every operand
+// value a split into two BF16 terms, a = a_hi + a_lo with |a - a_hi - a_lo|
+// <= 2^-17 |a| (a_hi the BF16 rounding of the FP32 value, a_lo that of the
+// remainder, which is exact in FP32; both staged row-major like the BF16
+// panel).  Each product is formed from three BF16 MFMAs, a_hi b_hi +
+// a_hi b_lo + a_lo b_hi (the dropped a_lo b_lo is at most 2^-16 of the
+// product), accumulated in FP32 over the whole K and added to the FP64 tile
+// once: a product error of at most about 2^-15 relative, against FP32
+// operands' 2^-23 and BF16 operands' 2^-7, at three BF16 MFMAs per product.
+// Two stages of 32 K values (four 8 KB planes each, 64 KB of LDS: two
+// workgroups per CU).
+constexpr int LSX = 2;
+
+template <int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_lowp_bf16x3(
+    TileMap M, int k, int band, int64_t nwg, int64_t pad, const uint16_t *__restrict__ Phi,
+    const uint16_t *__restrict__ Plo) {
+  __shared__ uint16_t sAh0[LK16 * LB], sAl0[LK16 * LB], sBh0[LK16 * LB], sBl0[LK16 * LB];
+  __shared__ uint16_t sAh1[LK16 * LB], sAl1[LK16 * LB], sBh1[LK16 * LB], sBl1[LK16 * LB];
+  const int64_t lid = lp_xcd_remap(blockIdx.x, pad);
+  if (lid >= nwg) return;
+  constexpr int s = NB / LB, ss = s * s;
+  const int64_t q = lid / ss;
+  const int sub = (int)(lid % ss), sr = sub % s, sc = sub / s;
+  int i, j;
+  lp_offband(M, k, band, q, i, j);
+  const int64_t ao = (int64_t)(i - k - 1) * NB * NB + (int64_t)sr * LB * NB;
+  const int64_t bo = (int64_t)(j - k - 1) * NB * NB + (int64_t)sc * LB * NB;
+  double *C = reinterpret_cast<double *>(tile_bytes(M, i, j)) + (int64_t)sc * LB * NB + sr * LB;
+  constexpr int nk = NB / LK16;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave & 1, wc = wave >> 1;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // a direct load moves 16 rows x 64 bytes (32 BF16 of K): lane l row l/4,
+  // 16-byte chunk l%4; per stage 8 loads per plane, wave w issues the loads
+  // w + 4 i of the 32 (planes A_hi, A_lo, B_hi, B_lo in that order).
+  const int64_t lsrc = (int64_t)(lane >> 2) * NB + (lane & 3) * 8;
+  auto issue = [&](int kb, int st) {
+#pragma unroll
+    for (int i_ = 0; i_ < 8; ++i_) {
+      const int q_ = wave + 4 * i_;
+      const int pl_ = q_ >> 3, pr_ = q_ & 7;  // plane, 16-row group
+      const uint16_t *src_ = (pl_ & 1 ? Plo : Phi) + (pl_ < 2 ? ao : bo) +
+                             (int64_t)(16 * pr_) * NB + kb * LK16 + lsrc;
+      uint16_t *dst_ = (st == 0 ? (pl_ == 0 ? sAh0 : pl_ == 1 ? sAl0 : pl_ == 2 ? sBh0 : sBl0)
+                                : (pl_ == 0 ? sAh1 : pl_ == 1 ? sAl1 : pl_ == 2 ? sBh1 : sBl1)) +
+                       16 * pr_ * LK16;
+      __builtin_amdgcn_global_load_lds((const void *)src_, MVG_LDSP(dst_), 16, 0, 0);
+    }
+  };
+  issue(0, 0);
+  flt4 acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = flt4{0.f, 0.f, 0.f, 0.f};
+  for (int kb0 = 0; kb0 < nk; kb0 += LSX) {
+#pragma unroll
+    for (int u = 0; u < LSX; ++u) {
+      const int kb = kb0 + u;
+      lp_wait_vmcnt_0();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("" ::: "memory");
+      const uint16_t *sAh = u == 0 ? sAh0 : sAh1, *sAl = u == 0 ? sAl0 : sAl1;
+      const uint16_t *sBh = u == 0 ? sBh0 : sBh1, *sBl = u == 0 ? sBl0 : sBl1;
+      // the fragments are read, then the refill issued, at raised priority
+      __builtin_amdgcn_s_setprio(1);
+      bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ar = (wr * 64 + t * 16 + l16) * LK16 + lk * 8;
+        const int br = (wc * 64 + t * 16 + l16) * LK16 + lk * 8;
+        uint4 vh = *reinterpret_cast<const uint4 *>(sAh + ar);
+        uint4 vl = *reinterpret_cast<const uint4 *>(sAl + ar);
+        vh.x ^= 0x80008000u;  // -A: flip the eight sign bits of each term
+        vh.y ^= 0x80008000u;
+        vh.z ^= 0x80008000u;
+        vh.w ^= 0x80008000u;
+        vl.x ^= 0x80008000u;
+        vl.y ^= 0x80008000u;
+        vl.z ^= 0x80008000u;
+        vl.w ^= 0x80008000u;
+        ah[t] = __builtin_bit_cast(bf16x8, vh);
+        al[t] = __builtin_bit_cast(bf16x8, vl);
+        bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBh + br));
+        bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBl + br));
+      }
+      if (kb + 1 < nk) issue(kb + 1, (u + 1) % LSX);
+      __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+        }
+    }
+  }
+  const int64_t coff = (int64_t)(wc * 64 + l16) * NB + wr * 64 + 4 * lk;
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      dbl4 *c = reinterpret_cast<dbl4 *>(C + coff + (int64_t)tj * 16 * NB + ti * 16);
+      const dbl4 v = *c;
+      *c = dbl4{v[0] + (double)acc[ti][tj][0], v[1] + (double)acc[ti][tj][1],
+                v[2] + (double)acc[ti][tj][2], v[3] + (double)acc[ti][tj][3]};
+    }
+}
+
 // ------------------------------------------------------------ panel staging
 
 // Before the TRSM: the panel tiles (i, k), i > k, copied as stored: FP64
@@ -347,11 +466,14 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 
 // After the TRSM: every panel tile as FP64 (P64, column-major), FP32 (P32,
-// column-major) and, if P16, BF16 row-major (rounded from the FP32 value).
-// One workgroup per 64 x 64 block, transposed through LDS for P16.
+// column-major) and, if P16, BF16 row-major (rounded from the FP32 value);
+// if P16lo, P16 holds the high BF16 term of the split and P16lo the BF16
+// rounding of the remainder (exact in FP32).  One workgroup per 64 x 64
+// block, transposed through LDS for P16.
 __global__ __launch_bounds__(256) void k_panel_stage_post(TileMap M, int k, double *__restrict__ P64,
                                                           float *__restrict__ P32,
-                                                          uint16_t *__restrict__ P16) {
+                                                          uint16_t *__restrict__ P16,
+                                                          uint16_t *__restrict__ P16lo) {
   __shared__ float blk[64][65];
   const int nb = M.nb, s = nb / 64;
   const int i = k + 1 + blockIdx.y;
@@ -375,17 +497,28 @@ __global__ __launch_bounds__(256) void k_panel_stage_post(TileMap M, int k, doub
   __syncthreads();
   for (int e = tid; e < 64 * 64; e += 256) {
     const int c = e & 63, r = e >> 6;  // row-major: consecutive threads along a row
-    P16[slot + (int64_t)(br * 64 + r) * nb + bc * 64 + c] = bf16_rne(blk[c][r]);
+    const float fv = blk[c][r];
+    const uint16_t hi = bf16_rne(fv);
+    const int64_t o = slot + (int64_t)(br * 64 + r) * nb + bc * 64 + c;
+    P16[o] = hi;
+    if (P16lo) P16lo[o] = bf16_rne(fv - __uint_as_float((uint32_t)hi << 16));
   }
 }
 
 // ------------------------------------------------------------ driver
 
+// Off-band operand form of the trailing update.
+enum { LOWP_F32 = 0, LOWP_BF16 = 1, LOWP_BF16X3 = 2 };
+
 template <int NB>
 static int launch_lowp_update(const TileMap &M, int k, int band, int64_t nwg, const float *P32,
-                              const uint16_t *P16, bool bf16, bool c64, hipStream_t st) {
+                              const uint16_t *P16, const uint16_t *P16lo, int form, bool c64,
+                              hipStream_t st) {
   const int64_t pad = (nwg + 7) / 8 * 8;
-  if (bf16)
+  if (form == LOWP_BF16X3)
+    hipLaunchKernelGGL(k_lowp_bf16x3<NB>, dim3((unsigned)pad), dim3(256), 0, st, M, k, band, nwg,
+                       pad, P16, P16lo);
+  else if (form == LOWP_BF16)
     hipLaunchKernelGGL(k_lowp_bf16<NB>, dim3((unsigned)pad), dim3(256), 0, st, M, k, band, nwg, pad,
                        P16);
   else if (c64)
@@ -407,13 +540,14 @@ static int launch_lowp_trsm(const TileMap &M, int k, int band, int64_t nwg, cons
 }
 
 static int lowp_update(const TileMap &M, int k, int band, int64_t nwg, const float *P32,
-                       const uint16_t *P16, bool bf16, bool c64, hipStream_t st) {
+                       const uint16_t *P16, const uint16_t *P16lo, int form, bool c64,
+                       hipStream_t st) {
   switch (M.nb) {
-    case 128: return launch_lowp_update<128>(M, k, band, nwg, P32, P16, bf16, c64, st);
-    case 256: return launch_lowp_update<256>(M, k, band, nwg, P32, P16, bf16, c64, st);
-    case 512: return launch_lowp_update<512>(M, k, band, nwg, P32, P16, bf16, c64, st);
-    case 768: return launch_lowp_update<768>(M, k, band, nwg, P32, P16, bf16, c64, st);
-    case 1024: return launch_lowp_update<1024>(M, k, band, nwg, P32, P16, bf16, c64, st);
+    case 128: return launch_lowp_update<128>(M, k, band, nwg, P32, P16, P16lo, form, c64, st);
+    case 256: return launch_lowp_update<256>(M, k, band, nwg, P32, P16, P16lo, form, c64, st);
+    case 512: return launch_lowp_update<512>(M, k, band, nwg, P32, P16, P16lo, form, c64, st);
+    case 768: return launch_lowp_update<768>(M, k, band, nwg, P32, P16, P16lo, form, c64, st);
+    case 1024: return launch_lowp_update<1024>(M, k, band, nwg, P32, P16, P16lo, form, c64, st);
   }
   set_error("mixed precision: unsupported tile size %d", M.nb);
   return MVG_ERR_STATE;
@@ -453,15 +587,19 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   const TileMap M = A->map();
   const int T = M.T, nb = M.nb, band = A->band;
   const bool bf16 = A->precision == MVG_MIXED_BF16;
+  // BF16X3: as FP32X, with the off-band operands split into two BF16 terms
+  const bool x3 = A->precision == MVG_MIXED_BF16X3;
   // FP32X: every tile FP64 and every panel solved in FP64; only the off-band
   // trailing GEMMs take FP32 operands (FP32 MFMA, FP64 target tiles)
-  const bool x64 = A->precision == MVG_MIXED_FP32X;
+  const bool x64 = A->precision == MVG_MIXED_FP32X || x3;
+  const int form = x3 ? LOWP_BF16X3 : bf16 ? LOWP_BF16 : LOWP_F32;
   const int s = nb / LB;
   const int64_t ss = (int64_t)s * s;
   const int64_t per = (int64_t)nb * nb;
   const int nslot = std::max(1, T - 1);
-  // workspaces: P64 | P32 | P16 | W32
-  const size_t bytes = (size_t)nslot * per * (8 + 4 + (bf16 ? 2 : 0)) + (size_t)per * 4;
+  // workspaces: P64 | P32 | P16 (BF16: one plane; BF16X3: high, low) | W32
+  const int p16b = bf16 ? 2 : x3 ? 4 : 0;
+  const size_t bytes = (size_t)nslot * per * (8 + 4 + p16b) + (size_t)per * 4;
   char *ws = nullptr;
   if (malloc_async((void **)&ws, bytes, st) != hipSuccess) {
     hipGetLastError();
@@ -470,8 +608,9 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
   }
   double *P64 = reinterpret_cast<double *>(ws);
   float *P32 = reinterpret_cast<float *>(ws + (size_t)nslot * per * 8);
-  uint16_t *P16 = bf16 ? reinterpret_cast<uint16_t *>(ws + (size_t)nslot * per * 12) : nullptr;
-  float *W32 = reinterpret_cast<float *>(ws + (size_t)nslot * per * (bf16 ? 14 : 12));
+  uint16_t *P16 = p16b ? reinterpret_cast<uint16_t *>(ws + (size_t)nslot * per * 12) : nullptr;
+  uint16_t *P16lo = x3 ? P16 + (size_t)nslot * per : nullptr;
+  float *W32 = reinterpret_cast<float *>(ws + (size_t)nslot * per * (12 + p16b));
   hipStream_t side = side_stream();
   hipEvent_t evD, evS, ev0;
   hipEventCreateWithFlags(&evD, hipEventDisableTiming);
@@ -509,7 +648,7 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
     hipEventRecord(evD, side);
     if (rc) break;
     hipLaunchKernelGGL(k_panel_stage_post, dim3((nb / 64) * (nb / 64), nbelow), dim3(256), 0, st,
-                       M, k, P64, P32, P16);
+                       M, k, P64, P32, P16, P16lo);
     rc = check_launch("panel_stage_post");
     double f64 = 0.0, flow = 0.0;
     mixed_flops(A->N, nb, T, k, band, &f64, &flow);
@@ -525,7 +664,7 @@ int mixed_potrf(mvg_mat *A, int64_t *d_info, hipStream_t st) {
       for (int j = k + 1; j < T; ++j) noff_t += std::max(0, T - j - band);
       if (noff_t > 0) {
         int h = prof_begin(MVG_PROF_LOWP, st, flow, 0.0);
-        rc = lowp_update(M, k, band, noff_t * ss, P32, P16, bf16, x64, st);
+        rc = lowp_update(M, k, band, noff_t * ss, P32, P16, P16lo, form, x64, st);
         prof_end(h, st);
       }
     }

@@ -70,7 +70,8 @@ def test_mixed_full_band_matches_fp64(lib, orc):
     x, y, z = _data(orc, 700, 4, th)
     _say("mixed full band n=700 nb=128")
     d64 = lib.loglik(_dev(x), _dev(y), _dev(z), th, {"nb": 128})
-    for prec in (lib.MVG_MIXED_FP32, lib.MVG_MIXED_BF16, lib.MVG_MIXED_FP32X):
+    for prec in (lib.MVG_MIXED_FP32, lib.MVG_MIXED_BF16, lib.MVG_MIXED_FP32X,
+                 lib.MVG_MIXED_BF16X3):
         got = lib.loglik(_dev(x), _dev(y), _dev(z), th,
                          {"nb": 128, "precision": prec, "band_tiles": 64})
         assert got["status"][0] == 0
@@ -131,6 +132,42 @@ def test_mixed_fp32x_loglik(lib, orc, a, nb):
         assert abs(dld) <= max(50.0 * abs(eld - ref["logdet"]), 2e-9 * abs(ref["logdet"]))
         assert dl <= 1e-7
     assert dl <= 1e-6
+
+
+@pytest.mark.parametrize("nb", [128, 256])
+@pytest.mark.parametrize("a", [0.03, 0.1, 0.3])
+def test_mixed_bf16x3_loglik(lib, orc, a, nb):
+    """FP64 tiles and panel solves, off-band operands split into two BF16
+    terms (three BF16 MFMAs per product, FP32 accumulation over the tile's
+    K): the likelihood within 1e-6 of the oracle, the refined quadratic form
+    to 1e-9, and the log-determinant error within 10x the oracle's emulation
+    of the same split (which forms the three products exactly; the FP32
+    accumulation adds about 2^-24 sqrt(K) per entry, below the split's
+    2^-17) or 2e-9 relative.  At a = 0.3 (condition number ~1e7 at n = 1000)
+    the split's rounding alone moves log|Sigma| by ~3e-3 in the emulation and
+    the likelihood misses 1e-6 (2.5e-6 measured at nb 128): held to the
+    regression bound 1e-5, then reported as an expected failure."""
+    th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
+    n = 1000
+    x, y, z, ref, eld, einfo = _case(orc, n, 1, th, nb, 2, "bf16x3", "fp64")
+    _say("mixed bf16x3 n=%d nb=%d a=%g" % (n, nb, a))
+    got = lib.loglik(_dev(x), _dev(y), _dev(z), th,
+                     {"nb": nb, "precision": lib.MVG_MIXED_BF16X3})
+    assert einfo == 0 and got["status"][0] == 0
+    st = lib.mvg_ir_stats(0)
+    dl = abs(got["loglik"][0] - ref["loglik"]) / abs(ref["loglik"])
+    dld = got["logdet"][0] - ref["logdet"]
+    _say("  rel dloglik %.2e  dlogdet %.3e (emulated %.3e)  IR %s"
+         % (dl, dld, eld - ref["logdet"], st))
+    assert st["converged"], st
+    assert abs(got["quad"][0] - ref["quad"]) <= 1e-9 * abs(ref["quad"])
+    if a <= 0.1:
+        assert abs(dld) <= max(10.0 * abs(eld - ref["logdet"]), 2e-9 * abs(ref["logdet"]))
+        assert dl <= 1e-6
+        return
+    assert dl <= 1e-5
+    if dl > 1e-6:
+        pytest.xfail("split-BF16 operands miss |delta loglik| <= 1e-6 at a = %g: %.2e" % (a, dl))
 
 
 @pytest.mark.parametrize("a", [0.03, 0.1])
@@ -223,8 +260,9 @@ def test_mixed_rejects_band_below_two(lib, orc):
                    {"nb": 128, "precision": lib.MVG_MIXED_FP32, "band_tiles": 1})
 
 
-@pytest.mark.parametrize("prec,fmt,atol", [(1, "fp32", 1e-5), (2, "bf16", 5e-3)])
-def test_mixed_factor_matches_emulation(lib, orc, prec, fmt, atol):
+@pytest.mark.parametrize("prec,fmt,storage,atol", [(1, "fp32", "fp32", 1e-5), (2, "bf16", "fp32", 5e-3),
+                                                   (6, "bf16x3", "fp64", 2e-5)])
+def test_mixed_factor_matches_emulation(lib, orc, prec, fmt, storage, atol):
     """potrf_tiled on a mixed-layout matrix: the factor entry by entry against
     the oracle's emulation of the same rounding points (FP32 accumulation
     order differs, hence the tolerance); band tiles to FP64 accuracy where no
@@ -237,7 +275,7 @@ def test_mixed_factor_matches_emulation(lib, orc, prec, fmt, atol):
     assert lib.potrf_tiled(A, {"nb": 128, "precision": prec}) == 0
     Lg = A.to_dense().cpu().numpy()
     S = orc.cov_dense(x, y, th)
-    Le, info = orc.mixed_cholesky_emulated(S, 128, 2, fmt)
+    Le, info = orc.mixed_cholesky_emulated(S, 128, 2, fmt, storage)
     assert info == 0
     Le = Le[:600, :600]
     err = np.max(np.abs(Lg - Le))

@@ -13,11 +13,16 @@ Each (cell, mode) asserts the outcome measured and recorded for it:
   then reported as an expected failure of the 1e-6 target;
 * "not SPD": the mixed factor meets a non-positive pivot and the library
   reports it (status > 0, loglik = -inf, FP64 succeeds), reported as an
-  expected failure.
+  expected failure;
+* "FP64 fallback": the mixed factor exists but the FP64 refinement of the
+  solve stops unconverged, so the library evaluates the theta in FP64
+  instead (mvg_ir_stats says so; the result is FP64's, the time that of
+  both), reported as an expected failure.
 
 Modes: MVG_MIXED_FP32X (FP64 tiles and panel solves, FP32 operands in the
-off-band GEMMs), MVG_MIXED_FP32 (FP32 storage off the band), MVG_MIXED_BF16
-(FP32 storage, BF16 operands)."""
+off-band GEMMs), MVG_MIXED_BF16X3 (the same with each off-band operand split
+into two BF16 terms, three BF16 MFMAs per product), MVG_MIXED_FP32 (FP32
+storage off the band), MVG_MIXED_BF16 (FP32 storage, BF16 operands)."""
 import sys
 import time
 
@@ -31,16 +36,16 @@ pytestmark = pytest.mark.gpu
 N_LOC = 50000
 NUS = [(0.5, 0.5), (0.5, 1.5), (1.5, 0.5), (1.5, 1.5)]
 BETAS = [0.0, 0.5, 0.9]
-MEETS, MISS, NOT_SPD = "meets", "miss", "not SPD"
+MEETS, MISS, NOT_SPD, FALLBACK = "meets", "miss", "not SPD", "FP64 fallback"
 
 # recorded outcomes (n = 50,000, seed-1 sites, Z = L eps seed 1); a miss
 # carries its regression bound (about 3x the measured relative delta loglik)
-ROUGH = {0.0: {"fp32x": MEETS, "fp32": MEETS, "bf16": (MISS, 1.5e-3)},
-         0.5: {"fp32x": MEETS, "fp32": MEETS, "bf16": (MISS, 1e-3)},
-         0.9: {"fp32x": MEETS, "fp32": MEETS, "bf16": NOT_SPD}}
-SMOOTH = {0.0: {"fp32x": (MISS, 2e-4), "fp32": NOT_SPD, "bf16": NOT_SPD},
-          0.5: {"fp32x": (MISS, 1e-3), "fp32": NOT_SPD, "bf16": NOT_SPD},
-          0.9: {"fp32x": NOT_SPD, "fp32": NOT_SPD, "bf16": NOT_SPD}}
+ROUGH = {0.0: {"fp32x": MEETS, "bf16x3": MEETS, "fp32": MEETS, "bf16": (MISS, 1.5e-3)},
+         0.5: {"fp32x": MEETS, "bf16x3": MEETS, "fp32": MEETS, "bf16": (MISS, 1e-3)},
+         0.9: {"fp32x": MEETS, "bf16x3": MEETS, "fp32": MEETS, "bf16": NOT_SPD}}
+SMOOTH = {0.0: {"fp32x": FALLBACK, "bf16x3": NOT_SPD, "fp32": NOT_SPD, "bf16": NOT_SPD},
+          0.5: {"fp32x": FALLBACK, "bf16x3": NOT_SPD, "fp32": NOT_SPD, "bf16": NOT_SPD},
+          0.9: {"fp32x": NOT_SPD, "bf16x3": NOT_SPD, "fp32": NOT_SPD, "bf16": NOT_SPD}}
 
 
 def expected(nu, beta, mode):
@@ -100,15 +105,15 @@ def _cell(lib, sites, nu, beta):
 _warm = set()
 
 
-@pytest.mark.parametrize("mode", ["fp32x", "fp32", "bf16"])
+@pytest.mark.parametrize("mode", ["fp32x", "bf16x3", "fp32", "bf16"])
 @pytest.mark.parametrize("beta", BETAS)
 @pytest.mark.parametrize("nu", NUS, ids=lambda nu: "nu%g,%g" % nu)
 def test_mixed_grid_cell(lib, sites, nu, beta, mode):
     import torch
     X, Y = sites
     th, z, ref, t64 = _cell(lib, sites, nu, beta)
-    prec = {"fp32x": lib.MVG_MIXED_FP32X, "fp32": lib.MVG_MIXED_FP32,
-            "bf16": lib.MVG_MIXED_BF16}[mode]
+    prec = {"fp32x": lib.MVG_MIXED_FP32X, "bf16x3": lib.MVG_MIXED_BF16X3,
+            "fp32": lib.MVG_MIXED_FP32, "bf16": lib.MVG_MIXED_BF16}[mode]
     o = {"nb": 1024, "precision": prec, "band_tiles": 2}
     if mode not in _warm:  # the first call of a precision sizes its arena
         lib.loglik(X, Y, z, th, o)
@@ -119,14 +124,20 @@ def test_mixed_grid_cell(lib, sites, nu, beta, mode):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = int(r["status"][0])
+    fell_back = bool(lib.mvg_ir_stats(0)["fp64_fallback"])
     exp = expected(nu, beta, mode)
     dl = abs(r["loglik"][0] - ref["loglik"]) / abs(ref["loglik"]) if st == 0 else None
     _say("  nu=%s beta=%g %-5s: status %d, rel dl %s, %.2f s (FP64 %.2f s), expected %s"
          % (nu, beta, mode, st, "%.2e" % dl if dl is not None else "-", dt, t64, exp))
     if exp == MEETS:
-        assert st == 0 and dl <= 1e-6
+        assert st == 0 and dl <= 1e-6 and not fell_back
         assert dt < t64
         return
+    if exp == FALLBACK:
+        if st == 0 and not fell_back and dl <= 1e-6 and dt < t64:
+            return   # better than recorded
+        assert st == 0 and fell_back and dl <= 1e-9
+        pytest.xfail("refinement unconverged: evaluated in FP64 (%.2f s)" % dt)
     if exp == NOT_SPD:
         if st == 0 and dl <= 1e-6 and dt < t64:
             return   # better than recorded
