@@ -60,9 +60,10 @@ int launch_gemm_batched(const GemmTask *d_tasks, const int64_t *d_start, int nta
 int launch_gemm_task_map(const int64_t *d_start, int ntask, int64_t nblocks, int *d_map,
                          hipStream_t st);
 int64_t gemm_blocks(const GemmTask &t, int bs = 64);
-// C (M x N) -= A (M x K) B^T (B: N x K), column-major, one large product
+// C (M x N) -= A (M x K) B^T (B: N x K), column-major, one large product;
+// max_wg > 0 caps the workgroups (each then walks several blocks)
 int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                       int M, int N, int K, hipStream_t st);
+                       int M, int N, int K, hipStream_t st, int max_wg = 0);
 int launch_qr(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);  // mmax: largest m
 // unpivoted QR in panels (compact WY); tk.tau must hold (n + 8) x 8 doubles (T factors)
 int launch_qr_blocked(const QrTask *d_tasks, int ntask, int mmax, hipStream_t st);

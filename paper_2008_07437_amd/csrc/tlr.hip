@@ -19,7 +19,9 @@
 // once, after all its updates.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 
 #include "tlr.h"
 
@@ -347,9 +349,15 @@ struct CompressJob {
 // W (nullable): the diagonal factor's inverse applied to every V; w_ready
 // (nullable): an event after which W is complete, waited for only before W's
 // first use, so that the sketches and QRs overlap W's computation.
+// between (nullable): host work run once, after the first pass's kernels are
+// queued and before the host waits for their ranks (it may record w_ready),
+// so that the device runs the compression while the host prepares other
+// streams' work.
 static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc, int max_rank,
                          uint64_t seed, const double *W, int ldw, std::vector<int> &sguess,
-                         hipStream_t st, hipEvent_t w_ready = nullptr) {
+                         hipStream_t st, hipEvent_t w_ready = nullptr,
+                         const std::function<int()> &between = nullptr) {
+  bool between_done = !between;
   const int nb = D.nb;
   const int T = D.T;
   const int smax = std::min(nb, QR_MAXN);
@@ -452,6 +460,10 @@ static int compress_jobs(std::vector<CompressJob> jobs, TlrStore &D, double acc,
       }
       rc = run_list<CopyTask, launch_copy_cols>(c, L, st);
       if (!rc) rc = run_qr(q, smx, false, L, st);  // R'' P = Q3 R3, stopped at ||R3_22||_F <= acc
+    }
+    if (!rc && !between_done) {
+      between_done = true;
+      rc = between();
     }
     // ranks to the host
     std::vector<int> ranks(jobs.size(), 0);
@@ -688,6 +700,15 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   };
   // panel Pp of column jc -= the updates of factor columns k in [k0, k1):
   // [U_ik G_ijk]_k [U_jk]_k^T with G_ijk = V_ik^T V_jk, one large GEMM
+  // workgroups of the look-ahead's column-update GEMM (0: one per block).
+  // 448 (two per CU on 192 CUs, one on the rest) leaves room on a quarter of
+  // the CUs for the compression kernels of the main stream, which otherwise
+  // wait for the GEMM's blocks to drain: one evaluation at n = 100,000
+  // 3.52 -> 3.42 s (384: 3.45 s, 512: 3.61 s, 256: 3.54 s, 128: 4.09 s)
+  static const int look_wg = [] {
+    const char *e = getenv("MVG_TLR_LOOK_WG");
+    return e ? std::max(0, atoi(e)) : 448;
+  }();
   auto update = [&](int jc, int k0, int k1, double *Pp, int w, HostLists &Lx, hipStream_t s) -> int {
     const int ldp = (T - jc) * nb;
     int64_t Kj = 0;
@@ -745,7 +766,7 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
     if (!e) {
       const double fl = 2.0 * ldp * nb * (double)Kj;
       const int h = prof_begin(MVG_PROF_TRAILING, s, fl, 0.0);
-      e = launch_gemm_nt_sub(Pc, ldp, Qc, nb, Pp, ldp, ldp, nb, (int)Kp, s);
+      e = launch_gemm_nt_sub(Pc, ldp, Qc, nb, Pp, ldp, ldp, nb, (int)Kp, s, s == look ? look_wg : 0);
       prof_end(h, s);
     }
     return e;
@@ -768,44 +789,52 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
       rc = MVG_ERR_LAUNCH;
     }
     if (!rc && j > 0) rc = update(j, looked ? j - 1 : 0, j, P, 1, L, st);
-    // (2) diagonal tile: FP64 Cholesky and W_j, on the side stream beside
-    // the compression of the sub-diagonal tiles (which reads other rows of P
-    // and needs W_j only for V <- W_j V)
-    if (!rc) {
-      if (hipEventRecord(ev_upd, st) != hipSuccess || hipStreamWaitEvent(dside, ev_upd, 0) != hipSuccess) {
+    if (!rc && hipEventRecord(ev_upd, st) != hipSuccess) {
+      set_error("TLR: side-stream ordering failed");
+      rc = MVG_ERR_LAUNCH;
+    }
+    // (2) and (3), queued from the host while the device already runs the
+    // compression of (4) (its first kernels are queued before this runs)
+    auto side_work = [&]() -> int {
+      int e = 0;
+      // (2) diagonal tile: FP64 Cholesky and W_j, on the side stream beside
+      // the compression of the sub-diagonal tiles (which reads other rows of
+      // P and needs W_j only for V <- W_j V)
+      if (hipStreamWaitEvent(dside, ev_upd, 0) != hipSuccess) {
         set_error("TLR: side-stream ordering failed");
-        rc = MVG_ERR_LAUNCH;
+        return MVG_ERR_LAUNCH;
       }
       std::vector<CopyTask> c{CopyTask{P, Lf.diag + (int64_t)j * nbp * nbp, nb, nb, ldp, nbp,
                                        nullptr, COPY_PLAIN}};
-      if (!rc) rc = run_list<CopyTask, launch_copy_cols>(c, L, dside);
+      e = run_list<CopyTask, launch_copy_cols>(c, L, dside);
       PivotTol pt = pivot_tol(A);
       pt.gbase = (int64_t)j * nb;
       pt.lreal = nb;
-      if (!rc) rc = diag_factor(Md, j, A->d_winv, d_info, pt, dside);
-      if (!rc && hipEventRecord(ev_diag, dside) != hipSuccess) {
+      if (!e) e = diag_factor(Md, j, A->d_winv, d_info, pt, dside);
+      if (!e && hipEventRecord(ev_diag, dside) != hipSuccess) {
         set_error("TLR: side-stream event failed");
-        rc = MVG_ERR_LAUNCH;
+        e = MVG_ERR_LAUNCH;
       }
-    }
-    // (3) look-ahead on its own stream: column j + 1's panel (the other
-    // buffer, last read by column j - 1's compression, complete on st before
-    // ev_upd) expanded and updated by the factor columns k < j
+      // (3) look-ahead on its own stream: column j + 1's panel (the other
+      // buffer, last read by column j - 1's compression, complete on st
+      // before ev_upd) expanded and updated by the factor columns k < j
+      if (!e && j + 1 < T) {
+        if (hipStreamWaitEvent(look, ev_upd, 0) != hipSuccess) {
+          set_error("TLR: look-ahead ordering failed");
+          return MVG_ERR_LAUNCH;
+        }
+        double *Pn = Pbuf[(j + 1) & 1];
+        e = expand(j + 1, Pn, L2, look);
+        if (!e && j > 0) e = update(j + 1, 0, j, Pn, 0, L2, look);
+        if (!e && hipEventRecord(ev_look, look) != hipSuccess) {
+          set_error("TLR: look-ahead event failed");
+          e = MVG_ERR_LAUNCH;
+        }
+        looked = !e;
+      }
+      return e;
+    };
     looked = false;
-    if (!rc && j + 1 < T) {
-      if (hipStreamWaitEvent(look, ev_upd, 0) != hipSuccess) {
-        set_error("TLR: look-ahead ordering failed");
-        rc = MVG_ERR_LAUNCH;
-      }
-      double *Pn = Pbuf[(j + 1) & 1];
-      if (!rc) rc = expand(j + 1, Pn, L2, look);
-      if (!rc && j > 0) rc = update(j + 1, 0, j, Pn, 0, L2, look);
-      if (!rc && hipEventRecord(ev_look, look) != hipSuccess) {
-        set_error("TLR: look-ahead event failed");
-        rc = MVG_ERR_LAUNCH;
-      }
-      looked = !rc;
-    }
     // (4) recompress the sub-diagonal tiles, V <- W_j V
     if (!rc && j + 1 < T) {
       std::vector<CompressJob> jobs;
@@ -817,7 +846,9 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
                                    (uint64_t)t * 2 + 1});
       }
       rc = compress_jobs(jobs, Lf, o.tlr_acc, o.tlr_max_rank, o.seed ^ 0x5bd1e995u,
-                         A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st, ev_diag);
+                         A->d_winv + (int64_t)j * nbp * nbp, nbp, sguess, st, ev_diag, side_work);
+    } else if (!rc) {
+      rc = side_work();
     }
     // the staged lists are released only when every stream that reads them
     // is done (also on an error): the side stream's diagonal factor, then the

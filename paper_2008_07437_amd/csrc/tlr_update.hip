@@ -1,6 +1,7 @@
 // The column update of the tile-low-rank (TLR) Cholesky on gfx950 MFMA:
 // C -= A B^T for one large product per tile column (all earlier columns'
 // low-rank contributions at once).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -154,109 +155,115 @@ __device__ __forceinline__ void nsl_wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt(0x0F70 | N);  // vmcnt(N); lgkmcnt, expcnt unconstrained
 }
 
+// A grid smaller than the block count (a multiple of 8) walks the blocks
+// in steps of the grid, so that the product can leave CUs to concurrent
+// work on another stream.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nt_sub_lds(
     const double *__restrict__ A, int lda, const double *__restrict__ B, int ldb,
     double *__restrict__ C, int ldc, int M, int N, int K, int mblocks) {
   __shared__ double sA[2][NSL_K * BG];
   __shared__ double sB[2][NSL_K * BG];
-  int blk_r, blk_c;  // XCD order, as in k_gemm_nt_sub
-  {
-    const int w = blockIdx.x, nbk = (N + BG - 1) / BG;
-    const int full = (mblocks / 8) * 8 * nbk;
-    if (w < full) {
-      const int t = w >> 3;
-      blk_c = t % nbk;
-      blk_r = (t / nbk) * 8 + (w & 7);
-    } else {
-      const int t = w - full;
-      blk_c = t % nbk;
-      blk_r = (mblocks / 8) * 8 + t / nbk;
-    }
-  }
-  const int m0 = blk_r * BG, n0 = blk_c * BG;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
-  const double *a0 = A + min(m0 + 2 * lane, M - 2);
-  const double *b0 = B + min(n0 + 2 * lane, N - 2);
-  // slice kb into stage st: wave w moves columns w, w + 4, w + 8, w + 12 of
-  // the A and B slices (1 KB each)
-  auto issue = [&](int kb, int st) {
-#pragma unroll
-    for (int c = 0; c < NSL_K / 4; ++c) {
-      const int64_t k = (int64_t)kb * NSL_K + wave + 4 * c;
-      __builtin_amdgcn_global_load_lds((const void *)(a0 + k * lda),
-                                       MVG_LDSP(&sA[st][(wave + 4 * c) * BG]), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void *)(b0 + k * ldb),
-                                       MVG_LDSP(&sB[st][(wave + 4 * c) * BG]), 16, 0, 0);
-    }
-  };
-  const int nk = K / NSL_K;
-  if (nk > 0) issue(0, 0);
-  // accumulators from C: tile (ti, tj) element (4 e + lk, l16)
-  dbl4t acc[4][4];
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
-        const int gn = n0 + wc * 64 + tj * 16 + l16;
-        acc[ti][tj][e] = C[(int64_t)min(gn, N - 1) * ldc + min(gm, M - 1)];
+  const int nbk = (N + BG - 1) / BG;
+  for (int w = blockIdx.x; w < mblocks * nbk; w += gridDim.x) {
+    int blk_r, blk_c;  // XCD order, as in k_gemm_nt_sub
+    {
+      const int full = (mblocks / 8) * 8 * nbk;
+      if (w < full) {
+        const int t = w >> 3;
+        blk_c = t % nbk;
+        blk_r = (t / nbk) * 8 + (w & 7);
+      } else {
+        const int t = w - full;
+        blk_c = t % nbk;
+        blk_r = (mblocks / 8) * 8 + t / nbk;
       }
-  for (int kb = 0; kb < nk; ++kb) {
-    const int u = kb & 1;
-    // slice kb has landed (this wave's loads; the barrier covers the others'),
-    // and every wave is done with the stage that is refilled next
-    nsl_wait_vmcnt<0>();
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_setprio(1);
-    const double *a = &sA[u][wr * 64 + l16];
-    const double *bb = &sB[u][wc * 64 + l16];
-    double af0[4], bf0[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      af0[t] = -a[lk * BG + t * 16];  // C -= A B^T
-      bf0[t] = bb[lk * BG + t * 16];
     }
-    if (kb + 1 < nk) issue(kb + 1, u ^ 1);
-    __builtin_amdgcn_s_setprio(0);
+    const int m0 = blk_r * BG, n0 = blk_c * BG;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, lk = lane >> 4;
+    const double *a0 = A + min(m0 + 2 * lane, M - 2);
+    const double *b0 = B + min(n0 + 2 * lane, N - 2);
+    // slice kb into stage st: wave w moves columns w, w + 4, w + 8, w + 12 of
+    // the A and B slices (1 KB each)
+    auto issue = [&](int kb, int st) {
 #pragma unroll
-    for (int ks = 0; ks < NSL_K; ks += 4) {
-      double af[4], bf[4];
+      for (int c = 0; c < NSL_K / 4; ++c) {
+        const int64_t k = (int64_t)kb * NSL_K + wave + 4 * c;
+        __builtin_amdgcn_global_load_lds((const void *)(a0 + k * lda),
+                                         MVG_LDSP(&sA[st][(wave + 4 * c) * BG]), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(b0 + k * ldb),
+                                         MVG_LDSP(&sB[st][(wave + 4 * c) * BG]), 16, 0, 0);
+      }
+    };
+    const int nk = K / NSL_K;
+    if (nk > 0) issue(0, 0);
+    // accumulators from C: tile (ti, tj) element (4 e + lk, l16)
+    dbl4t acc[4][4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+          const int gn = n0 + wc * 64 + tj * 16 + l16;
+          acc[ti][tj][e] = C[(int64_t)min(gn, N - 1) * ldc + min(gm, M - 1)];
+        }
+    for (int kb = 0; kb < nk; ++kb) {
+      const int u = kb & 1;
+      // slice kb has landed (this wave's loads; the barrier covers the others'),
+      // and every wave is done with the stage that is refilled next
+      nsl_wait_vmcnt<0>();
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_setprio(1);
+      const double *a = &sA[u][wr * 64 + l16];
+      const double *bb = &sB[u][wc * 64 + l16];
+      double af0[4], bf0[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        af[t] = ks == 0 ? af0[t] : -a[(ks + lk) * BG + t * 16];
-        bf[t] = ks == 0 ? bf0[t] : bb[(ks + lk) * BG + t * 16];
+        af0[t] = -a[lk * BG + t * 16];  // C -= A B^T
+        bf0[t] = bb[lk * BG + t * 16];
       }
+      if (kb + 1 < nk) issue(kb + 1, u ^ 1);
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
+      for (int ks = 0; ks < NSL_K; ks += 4) {
+        double af[4], bf[4];
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj)
-          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ti], bf[tj], acc[ti][tj], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+          af[t] = ks == 0 ? af0[t] : -a[(ks + lk) * BG + t * 16];
+          bf[t] = ks == 0 ? bf0[t] : bb[(ks + lk) * BG + t * 16];
+        }
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ti], bf[tj], acc[ti][tj], 0, 0, 0);
+      }
     }
+    nsl_wait_vmcnt<0>();  // no direct LDS load outlives the workgroup
+    const bool inside = m0 + BG <= M && n0 + BG <= N;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
+          const int gn = n0 + wc * 64 + tj * 16 + l16;
+          if (inside || (gm < M && gn < N)) C[(int64_t)gn * ldc + gm] = acc[ti][tj][e];
+        }
+    __syncthreads();  // every wave is done with both stages before the next block's loads
   }
-  nsl_wait_vmcnt<0>();  // no direct LDS load outlives the workgroup
-  const bool inside = m0 + BG <= M && n0 + BG <= N;
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wr * 64 + ti * 16 + 4 * e + lk;
-        const int gn = n0 + wc * 64 + tj * 16 + l16;
-        if (inside || (gm < M && gn < N)) C[(int64_t)gn * ldc + gm] = acc[ti][tj][e];
-      }
 }
 
 int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                       int M, int N, int K, hipStream_t st) {
+                       int M, int N, int K, hipStream_t st, int max_wg) {
   if (M <= 0 || N <= 0) return 0;
   const int64_t mb = (M + BG - 1) / BG, nbk = (N + BG - 1) / BG;
   if (mb * nbk >= ((int64_t)1 << 31)) {
@@ -269,8 +276,10 @@ int launch_gemm_nt_sub(const double *A, int lda, const double *B, int ldb, doubl
   }();
   if (lds_path && K % (2 * NSL_K) == 0 && M % 2 == 0 && N % 2 == 0 && lda % 2 == 0 &&
       ldb % 2 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0) {
-    hipLaunchKernelGGL(k_gemm_nt_sub_lds, dim3((unsigned)(mb * nbk)), dim3(256), 0, st, A, lda, B,
-                       ldb, C, ldc, M, N, K, (int)mb);
+    int64_t grid = mb * nbk;
+    if (max_wg > 0 && grid > max_wg) grid = std::max<int64_t>(8, max_wg / 8 * 8);
+    hipLaunchKernelGGL(k_gemm_nt_sub_lds, dim3((unsigned)grid), dim3(256), 0, st, A, lda, B, ldb, C,
+                       ldc, M, N, K, (int)mb);
     return check_launch("gemm_nt_sub_lds");
   }
   hipLaunchKernelGGL(k_gemm_nt_sub, dim3((unsigned)(mb * nbk)), dim3(256), 0, st, A, lda, B, ldb,
