@@ -84,7 +84,12 @@ def test_footprint_host_logic():
     fx = fp(25600, nb=512, precision=5)
     assert fx > fp(25600, nb=512, precision=1) and 1.9 * dense[2] < fx < 2.3 * dense[2]
     assert fp(1000, nb=128, precision=5, band_tiles=1) == 0
-    assert fp(1000, nb=128, precision=6) == 0         # no such precision
+    # BF16X3: FP32X's layout plus the two BF16 planes of the staged panel
+    # ((T - 1) nb^2 values of 2 + 2 bytes, T = 100)
+    f3 = fp(25600, nb=512, precision=6)
+    assert f3 - fx == 99 * 512 * 512 * 4
+    assert fp(1000, nb=128, precision=6, band_tiles=1) == 0
+    assert fp(1000, nb=128, precision=7) == 0         # no such precision
 
 
 def test_theta_batch_marshalling_rejects_bad_shapes():
