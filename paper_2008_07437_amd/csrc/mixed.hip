@@ -320,16 +320,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // product), accumulated in FP32 over the whole K and added to the FP64 tile
 // once: a product error of at most about 2^-15 relative, against FP32
 // operands' 2^-23 and BF16 operands' 2^-7, at three BF16 MFMAs per product.
-// Two stages of 32 K values (four 8 KB planes each, 64 KB of LDS: two
-// workgroups per CU).
-constexpr int LSX = 2;
+// NS stages of 32 K values (four 8 KB planes each): two stages take 64 KB
+// of LDS (two workgroups per CU), three 96 KB (one).  Measured at n = 50,000
+// (tile 1024): two stages 262 TFLOP/s of useful flops, three 192.
+constexpr int X3_STAGES = 2;
 
-template <int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_lowp_bf16x3(
+template <int NB, int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS == 2 ? 2 : 1, NS == 2 ? 2 : 1))) void k_lowp_bf16x3(
     TileMap M, int k, int band, int64_t nwg, int64_t pad, const uint16_t *__restrict__ Phi,
     const uint16_t *__restrict__ Plo) {
-  __shared__ uint16_t sAh0[LK16 * LB], sAl0[LK16 * LB], sBh0[LK16 * LB], sBl0[LK16 * LB];
-  __shared__ uint16_t sAh1[LK16 * LB], sAl1[LK16 * LB], sBh1[LK16 * LB], sBl1[LK16 * LB];
+  static_assert(NS == 2 || NS == 3, "two or three stages");
+  __shared__ uint16_t sbuf[NS][4][LK16 * LB];  // stage, plane (A_hi, A_lo, B_hi, B_lo)
   const int64_t lid = lp_xcd_remap(blockIdx.x, pad);
   if (lid >= nwg) return;
   constexpr int s = NB / LB, ss = s * s;
@@ -347,7 +348,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int l16 = lane & 15, lk = lane >> 4;
   // a direct load moves 16 rows x 64 bytes (32 BF16 of K): lane l row l/4,
   // 16-byte chunk l%4; per stage 8 loads per plane, wave w issues the loads
-  // w + 4 i of the 32 (planes A_hi, A_lo, B_hi, B_lo in that order).
+  // w + 4 i of the 32 (planes A_hi, A_lo, B_hi, B_lo in that order).  Every
+  // stage issues its 8 loads per wave (a slice past the end reloads the last
+  // one into the stage that is free), so the count in flight is the same at
+  // every wait.
   const int64_t lsrc = (int64_t)(lane >> 2) * NB + (lane & 3) * 8;
   auto issue = [&](int kb, int st) {
 #pragma unroll
@@ -356,64 +360,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int pl_ = q_ >> 3, pr_ = q_ & 7;  // plane, 16-row group
       const uint16_t *src_ = (pl_ & 1 ? Plo : Phi) + (pl_ < 2 ? ao : bo) +
                              (int64_t)(16 * pr_) * NB + kb * LK16 + lsrc;
-      uint16_t *dst_ = (st == 0 ? (pl_ == 0 ? sAh0 : pl_ == 1 ? sAl0 : pl_ == 2 ? sBh0 : sBl0)
-                                : (pl_ == 0 ? sAh1 : pl_ == 1 ? sAl1 : pl_ == 2 ? sBh1 : sBl1)) +
-                       16 * pr_ * LK16;
-      __builtin_amdgcn_global_load_lds((const void *)src_, MVG_LDSP(dst_), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void *)src_,
+                                       MVG_LDSP(&sbuf[st][pl_][16 * pr_ * LK16]), 16, 0, 0);
     }
   };
-  issue(0, 0);
+#pragma unroll
+  for (int p = 0; p < NS - 1; ++p) issue(p < nk ? p : nk - 1, p);
   flt4 acc[4][4];
 #pragma unroll
   for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = flt4{0.f, 0.f, 0.f, 0.f};
-  for (int kb0 = 0; kb0 < nk; kb0 += LSX) {
-#pragma unroll
-    for (int u = 0; u < LSX; ++u) {
-      const int kb = kb0 + u;
+  for (int kb = 0; kb < nk; ++kb) {
+    const int u = kb % NS;
+    // slice kb has landed (the later stage's 8 loads may still be in flight)
+    if (NS == 2)
       lp_wait_vmcnt_0();
-      asm volatile("" ::: "memory");
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_sched_barrier(0);
-      asm volatile("" ::: "memory");
-      const uint16_t *sAh = u == 0 ? sAh0 : sAh1, *sAl = u == 0 ? sAl0 : sAl1;
-      const uint16_t *sBh = u == 0 ? sBh0 : sBh1, *sBl = u == 0 ? sBl0 : sBl1;
-      // the fragments are read, then the refill issued, at raised priority
-      __builtin_amdgcn_s_setprio(1);
-      bf16x8 ah[4], al[4], bh[4], bl[4];
+    else
+      lp_wait_vmcnt_8();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    const uint16_t *sAh = sbuf[u][0], *sAl = sbuf[u][1], *sBh = sbuf[u][2], *sBl = sbuf[u][3];
+    // the fragments are read, then the refill issued, at raised priority
+    __builtin_amdgcn_s_setprio(1);
+    bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int ar = (wr * 64 + t * 16 + l16) * LK16 + lk * 8;
-        const int br = (wc * 64 + t * 16 + l16) * LK16 + lk * 8;
-        uint4 vh = *reinterpret_cast<const uint4 *>(sAh + ar);
-        uint4 vl = *reinterpret_cast<const uint4 *>(sAl + ar);
-        vh.x ^= 0x80008000u;  // -A: flip the eight sign bits of each term
-        vh.y ^= 0x80008000u;
-        vh.z ^= 0x80008000u;
-        vh.w ^= 0x80008000u;
-        vl.x ^= 0x80008000u;
-        vl.y ^= 0x80008000u;
-        vl.z ^= 0x80008000u;
-        vl.w ^= 0x80008000u;
-        ah[t] = __builtin_bit_cast(bf16x8, vh);
-        al[t] = __builtin_bit_cast(bf16x8, vl);
-        bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBh + br));
-        bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBl + br));
-      }
-      if (kb + 1 < nk) issue(kb + 1, (u + 1) % LSX);
-      __builtin_amdgcn_s_setprio(0);
-#pragma unroll
-      for (int ti = 0; ti < 4; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
-          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
-          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
-        }
+    for (int t = 0; t < 4; ++t) {
+      const int ar = (wr * 64 + t * 16 + l16) * LK16 + lk * 8;
+      const int br = (wc * 64 + t * 16 + l16) * LK16 + lk * 8;
+      uint4 vh = *reinterpret_cast<const uint4 *>(sAh + ar);
+      uint4 vl = *reinterpret_cast<const uint4 *>(sAl + ar);
+      vh.x ^= 0x80008000u;  // -A: flip the eight sign bits of each term
+      vh.y ^= 0x80008000u;
+      vh.z ^= 0x80008000u;
+      vh.w ^= 0x80008000u;
+      vl.x ^= 0x80008000u;
+      vl.y ^= 0x80008000u;
+      vl.z ^= 0x80008000u;
+      vl.w ^= 0x80008000u;
+      ah[t] = __builtin_bit_cast(bf16x8, vh);
+      al[t] = __builtin_bit_cast(bf16x8, vl);
+      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBh + br));
+      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(sBl + br));
     }
+    {
+      const int nxt = kb + NS - 1;  // into the stage every wave finished before this barrier
+      issue(nxt < nk ? nxt : nk - 1, nxt % NS);
+    }
+    __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bl[tj], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ti], bh[tj], acc[ti][tj], 0, 0, 0);
+      }
   }
+  lp_wait_vmcnt_0();  // no direct LDS load outlives the workgroup
   const int64_t coff = (int64_t)(wc * 64 + l16) * NB + wr * 64 + 4 * lk;
 #pragma unroll
   for (int ti = 0; ti < 4; ++ti)
@@ -516,8 +523,8 @@ static int launch_lowp_update(const TileMap &M, int k, int band, int64_t nwg, co
                               hipStream_t st) {
   const int64_t pad = (nwg + 7) / 8 * 8;
   if (form == LOWP_BF16X3)
-    hipLaunchKernelGGL(k_lowp_bf16x3<NB>, dim3((unsigned)pad), dim3(256), 0, st, M, k, band, nwg,
-                       pad, P16, P16lo);
+    hipLaunchKernelGGL((k_lowp_bf16x3<NB, X3_STAGES>), dim3((unsigned)pad), dim3(256), 0, st, M, k,
+                       band, nwg, pad, P16, P16lo);
   else if (form == LOWP_BF16)
     hipLaunchKernelGGL(k_lowp_bf16<NB>, dim3((unsigned)pad), dim3(256), 0, st, M, k, band, nwg, pad,
                        P16);
