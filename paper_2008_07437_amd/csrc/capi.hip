@@ -1025,12 +1025,15 @@ int loglik_many(const mvg_task *h_tasks, int n_tasks, double *h_loglik, double *
 }
 
 // Several theta as independent evaluations on concurrent streams (one host
-// thread and stream each, up to TLR_CONCURRENT at a time and as many as the
-// free device memory holds).  A TLR evaluation is bound by its column-by-
-// column critical path (the compressions of a tile column, then a host
-// synchronisation for their ranks), so several together fill the device;
-// each result is the one a single call gives.
+// thread and stream each, up to 4 at a time (MVG_TLR_CONCURRENT, at most 8)
+// and as many as the free device memory holds).  A TLR evaluation is bound
+// by its column-by-column critical path (the compressions of a tile column,
+// then a host synchronisation for their ranks), so several together fill
+// the device better: 7 theta at n = 100,000 in 22.7 s with 4 at a time,
+// 25.7 s with 2, 26.5 s one after another; each result is the one a single
+// call gives.
 constexpr int TLR_CONCURRENT = 8;
+constexpr int TLR_CONCURRENT_DEFAULT = 4;
 
 static int loglik_concurrent(const double *d_x, const double *d_y, const double *d_z,
                              int64_t n_loc, const mvg_theta *th, int n_theta, const mvg_opts &d,
@@ -1045,8 +1048,12 @@ static int loglik_concurrent(const double *d_x, const double *d_y, const double 
   size_t free_b = 0, total_b = 0;
   hipMemGetInfo(&free_b, &total_b);
   const size_t need = std::max<size_t>(1, mvg_footprint(n_loc, &d));
+  static const size_t conc = [] {  // MVG_TLR_CONCURRENT: at most this many at once
+    const char *e = getenv("MVG_TLR_CONCURRENT");
+    return (size_t)(e && atoi(e) > 0 ? std::min(atoi(e), TLR_CONCURRENT) : TLR_CONCURRENT_DEFAULT);
+  }();
   const int nw = (int)std::max<size_t>(
-      1, std::min<size_t>({(size_t)n_theta, (size_t)TLR_CONCURRENT, free_b / need}));
+      1, std::min<size_t>({(size_t)n_theta, conc, free_b / need}));
   std::atomic<int> next{0};
   std::vector<int> rcs(nw, 0);
   std::vector<std::string> errs(nw);
