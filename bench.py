@@ -471,7 +471,7 @@ def run_headline(args, mvg, dev, synthetic, torch):
 def run_batched(args, mvg, dev, synthetic, torch):
     """Many theta on the N = 400 workload (800 x 800) in one persistent launch."""
     n = 400
-    th0 = synthetic.THETA_CFG0
+    th0 = synthetic.THETA_REF
     xr, yr = synthetic.jittered_grid(n, args.seed)
     _, xs, ys = mvg.morton_order(dev(xr), dev(yr), sorted_xy=True)
     A = mvg.cov_generate(xs, ys, th0, {"nb": 128})   # Z = L eps at the true theta (setup)

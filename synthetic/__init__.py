@@ -17,7 +17,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-THETA_CFG0 = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+# the workloads' reference theta (sigma11^2, sigma22^2, a, nu11, nu22, beta)
+THETA_REF = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
 
 
 def rng(seed: int, stream: int = 0) -> np.random.Generator:
@@ -72,7 +73,7 @@ def nelder_mead_simplex(theta0, step: float = 0.10, beta_step: float = 0.05):
     return np.stack(pts)
 
 
-def jittered_thetas(count: int, seed: int, theta0=THETA_CFG0, rel: float = 0.2):
+def jittered_thetas(count: int, seed: int, theta0=THETA_REF, rel: float = 0.2):
     """count parameter vectors theta0 * U(1-rel, 1+rel) per coordinate, beta
     clipped to |beta| < 0.99."""
     g = rng(seed, 4)

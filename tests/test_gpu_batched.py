@@ -38,7 +38,7 @@ def _dataset(orc, n, seed, theta):
     return x, y, z
 
 
-TH0 = synthetic.THETA_CFG0
+TH0 = synthetic.THETA_REF
 
 
 def test_simplex_batch_matches_oracle_and_single_calls(lib, orc):

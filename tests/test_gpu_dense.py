@@ -15,7 +15,7 @@ import synthetic
 
 pytestmark = pytest.mark.gpu
 
-THETA0 = synthetic.THETA_CFG0
+THETA0 = synthetic.THETA_REF
 
 
 def _say(*a):
@@ -115,7 +115,7 @@ def test_potrf_factor_matches_oracle(lib, orc, n, nb, a):
 
 @pytest.mark.parametrize("a", [0.03, 0.1, 0.3])
 @pytest.mark.parametrize("nb", [128, 256])
-def test_loglik_cfg0(lib, orc, a, nb):
+def test_loglik_n400(lib, orc, a, nb):
     """N = 400 jittered 20 x 20 grid, theta of the small workload with a varied."""
     th = (1.0, 1.0, a, 0.5, 1.0, 0.5)
     _say("loglik N=400 a=%g nb=%d" % (a, nb))

@@ -106,7 +106,7 @@ def test_request_that_never_fits_is_rejected(lib, orc):
     z = synthetic.normal_eps(4000, 1)
     S = lib.Server(1 << 20, 2, {"nb": 256})   # 1 MiB budget
     d = S.add_dataset(_dev(x), _dev(y), _dev(z))
-    rid = S.submit(lib.REQ_LOGLIK, d, synthetic.THETA_CFG0)
+    rid = S.submit(lib.REQ_LOGLIK, d, synthetic.THETA_REF)
     r = _collect(S, 1)[rid]
     S.close()
     assert r.status == -104   # MVG_ERR_LIMIT

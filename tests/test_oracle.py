@@ -107,7 +107,7 @@ def test_rho12_closed_form_d2(orc):
         nu12 = 0.5 * (th[3] + th[4])
         ref = th[5] * math.sqrt(th[3] * th[4]) / nu12   # Gamma(v+1)/Gamma(v) = v
         assert abs(orc.rho12(th) - ref) <= 2e-16 * 4
-    assert abs(orc.rho12(synthetic.THETA_CFG0) - 0.4714045207910317) < 1e-16
+    assert abs(orc.rho12(synthetic.THETA_REF) - 0.4714045207910317) < 1e-16
 
 
 def test_theta_check(orc):

@@ -88,7 +88,7 @@ def test_noalloc_rejects_too_many_tasks(lib, orc):
     device work."""
     x, y, z = _dataset(orc, 20, 1)
     X, Y, Z = _dev(x), _dev(y), _dev(z)
-    tasks = [(X, Y, Z, synthetic.THETA_CFG0)] * 4097
+    tasks = [(X, Y, Z, synthetic.THETA_REF)] * 4097
     with pytest.raises(lib.MvgError) as e:
         lib.loglik_many_noalloc(tasks)
     assert e.value.code == -104
