@@ -701,13 +701,20 @@ int tlr_potrf(mvg_mat *A, const mvg_opts &o, int64_t *d_info, hipStream_t st) {
   // panel Pp of column jc -= the updates of factor columns k in [k0, k1):
   // [U_ik G_ijk]_k [U_jk]_k^T with G_ijk = V_ik^T V_jk, one large GEMM
   // workgroups of the look-ahead's column-update GEMM (0: one per block).
-  // 448 (two per CU on 192 CUs, one on the rest) leaves room on a quarter of
-  // the CUs for the compression kernels of the main stream, which otherwise
-  // wait for the GEMM's blocks to drain: one evaluation at n = 100,000
-  // 3.52 -> 3.42 s (384: 3.45 s, 512: 3.61 s, 256: 3.54 s, 128: 4.09 s)
+  // 7/4 of the CU count (448 of 256 CUs: two per CU on three quarters of
+  // them, one on the rest) leaves room on a quarter of the CUs for the
+  // compression kernels of the main stream, which otherwise wait for the
+  // GEMM's blocks to drain: one evaluation at n = 100,000 3.52 -> 3.42 s
+  // (384: 3.45 s, 512: 3.61 s, 256: 3.54 s, 128: 4.09 s)
   static const int look_wg = [] {
     const char *e = getenv("MVG_TLR_LOOK_WG");
-    return e ? std::max(0, atoi(e)) : 448;
+    if (e) return std::max(0, atoi(e));
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      return 0;
+    return 7 * cus / 4;
   }();
   auto update = [&](int jc, int k0, int k1, double *Pp, int w, HostLists &Lx, hipStream_t s) -> int {
     const int ldp = (T - jc) * nb;
@@ -906,29 +913,156 @@ int tlr_upload_meta(mvg_mat *A, hipStream_t st) {
 
 constexpr int TLR_MAXNB = 2048;
 
-// v_k <- W_k v_k (lower triangular W_k, ld nbp)
-__global__ __launch_bounds__(256) void k_tlr_tile_fwd(int nb, int nbp, int k,
+// The forward solve as many small workgroups per step (one workgroup per
+// tile and step kept the offset-1 tile's rank-240 products on one CU, its
+// loads one at a time): per column k,
+//   y_k = W_k v_k           (k_tlr_fwd_diag: 64 rows per workgroup),
+//   g_ik = V_ik^T y_k       (k_tlr_fwd_g: 16 columns of V_ik per workgroup),
+//   v_i -= U_ik g_ik, i > k (k_tlr_fwd_apply: 64 rows of U_ik per workgroup;
+//                            the first tile's workgroups also store y_k as v_k).
+// y and g live in a scratch of nb (y) + (T - 1) nb (g, nb per tile) doubles per
+// right-hand side.  Every sum is in a fixed order.
+constexpr int TLR_FWD_RB = 64;  // rows per workgroup
+constexpr int TLR_FWD_GC = 16;  // columns of V_ik per workgroup
+
+// y_k = W_k v_k (lower triangular W_k, ld nbp, entries above the diagonal not
+// read as values): lane = row, the four waves take every fourth column
+// c <= row with eight columns' loads in flight; the waves' partial sums are
+// added in a fixed order.
+__global__ __launch_bounds__(256) void k_tlr_fwd_diag(int nb, int nbp, int k,
                                                       const double *__restrict__ winv,
-                                                      double *__restrict__ V, int64_t ldv) {
+                                                      const double *__restrict__ V, int64_t ldv,
+                                                      double *__restrict__ scr, int64_t lds) {
   __shared__ double v[TLR_MAXNB];
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  __shared__ double part[4][TLR_FWD_RB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
   const double *W = winv + (int64_t)k * nbp * nbp;
-  for (int r = threadIdx.x; r < nb; r += 256) v[r] = vk[r];
+  const int r0 = blockIdx.x * TLR_FWD_RB, row = r0 + lane;
+  const int cend = min(nb, r0 + TLR_FWD_RB);  // columns c <= the last row
+  for (int i = threadIdx.x; i < cend; i += 256) v[i] = vk[i];
   __syncthreads();
-  double out[TLR_MAXNB / 256];
+  const int rr = min(row, nb - 1);  // clamped row for the loads
+  double acc[8];
 #pragma unroll
-  for (int p = 0; p < TLR_MAXNB / 256; ++p) {
-    const int r = p * 256 + threadIdx.x;
-    double acc = 0.0;
-    if (r < nb)
-      for (int c = 0; c <= r; ++c) acc += W[(int64_t)c * nbp + r] * v[c];
-    out[p] = acc;
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  int c = wave;
+  for (; c + 28 < cend; c += 32) {
+    double w[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[j] = W[(int64_t)(c + 4 * j) * nbp + rr];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (c + 4 * j <= row) acc[j] += w[j] * v[c + 4 * j];
+  }
+  for (; c < cend; c += 4)
+    if (c <= row) acc[0] += W[(int64_t)c * nbp + rr] * v[c];
+  part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (wave == 0 && row < nb)
+    scr[(int64_t)blockIdx.z * lds + row] =
+        (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// g_ik = V_ik^T y_k for tile i = k + 1 + blockIdx.x, columns
+// TLR_FWD_GC blockIdx.y .. + TLR_FWD_GC (four per wave, sixteen loads in
+// flight per wave), each a lane-strided sum reduced across the wave.
+__global__ __launch_bounds__(256) void k_tlr_fwd_g(int T, int nb, int k,
+                                                   const double *__restrict__ buf,
+                                                   const int64_t *__restrict__ uoff,
+                                                   const int *__restrict__ reff,
+                                                   double *__restrict__ scr, int64_t lds) {
+  __shared__ double x[TLR_MAXNB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = k + 1 + blockIdx.x;
+  const int64_t t = tidx(i, k, T);
+  const int r = reff[t];
+  const int c0 = blockIdx.y * TLR_FWD_GC + wave * 4;
+  if (blockIdx.y * TLR_FWD_GC >= r) return;  // uniform over the workgroup
+  double *sc = scr + (int64_t)blockIdx.z * lds;
+  for (int e = threadIdx.x; e < nb; e += 256) x[e] = sc[e];
+  __syncthreads();
+  if (c0 >= r) return;  // uniform over the wave; no barrier follows
+  const double *Vt = buf + uoff[t] + (int64_t)nb * r;
+  const double *col[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) col[j] = Vt + (int64_t)min(c0 + j, r - 1) * nb;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e0 = 0; e0 < nb; e0 += 256) {
+    double a[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = min(e0 + 64 * m + lane, nb - 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[m][j] = col[j][e];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = e0 + 64 * m + lane;
+      if (e < nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += a[m][j] * x[e];
+    }
   }
 #pragma unroll
-  for (int p = 0; p < TLR_MAXNB / 256; ++p) {
-    const int r = p * 256 + threadIdx.x;
-    if (r < nb) vk[r] = out[p];
+  for (int j = 0; j < 4; ++j) {
+    double s = acc[j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && c0 + j < r) sc[nb + (int64_t)(i - k - 1) * nb + c0 + j] = s;
   }
+}
+
+// v_i -= U_ik g_ik for tile i = k + 1 + blockIdx.x, rows TLR_FWD_RB
+// blockIdx.y .. + TLR_FWD_RB (lane = row, the waves take every fourth
+// column with eight loads in flight, partial sums added in a fixed order);
+// the workgroups of the first tile also store y_k as v_k.
+__global__ __launch_bounds__(256) void k_tlr_fwd_apply(int T, int nb, int k,
+                                                       const double *__restrict__ buf,
+                                                       const int64_t *__restrict__ uoff,
+                                                       const int *__restrict__ reff,
+                                                       double *__restrict__ V, int64_t ldv,
+                                                       const double *__restrict__ scr, int64_t lds) {
+  __shared__ double g[TLR_MAXNB];
+  __shared__ double part[4][TLR_FWD_RB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = k + 1 + blockIdx.x;
+  const int64_t t = tidx(i, k, T);
+  const int r = reff[t];
+  const int row = blockIdx.y * TLR_FWD_RB + lane;
+  const double *sc = scr + (int64_t)blockIdx.z * lds;
+  double *vc = V + (int64_t)blockIdx.z * ldv;
+  if (blockIdx.x == 0 && wave == 0 && row < nb) vc[(int64_t)k * nb + row] = sc[row];
+  if (r == 0) return;  // uniform over the workgroup
+  for (int e = threadIdx.x; e < r; e += 256) g[e] = sc[nb + (int64_t)(i - k - 1) * nb + e];
+  __syncthreads();
+  const double *U = buf + uoff[t];
+  const int rr = min(row, nb - 1);
+  double acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+  int c = wave;
+  for (; c + 28 < r; c += 32) {
+    double u[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) u[j] = U[(int64_t)(c + 4 * j) * nb + rr];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] += u[j] * g[c + 4 * j];
+  }
+  for (; c < r; c += 4) acc[0] += U[(int64_t)c * nb + rr] * g[c];
+  part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (wave == 0 && row < nb)
+    vc[(int64_t)i * nb + row] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// v_k = y_k (the last column, which has no tiles below)
+__global__ void k_tlr_fwd_store(int nb, int k, double *__restrict__ V, int64_t ldv,
+                                const double *__restrict__ scr, int64_t lds) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nb) V[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + e] = scr[(int64_t)blockIdx.z * lds + e];
 }
 
 // v_k <- W_k^T v_k
@@ -1000,26 +1134,50 @@ static int tlr_solve_ok(const mvg_mat *A) {
 
 int tlr_trsm_forward(const mvg_mat *A, double *d_V, int nrhs, int64_t ldv, hipStream_t st) {
   if (int rc = tlr_solve_ok(A)) return rc;
-  if (nrhs > 65535) {  // right-hand sides go in gridDim.z
-    for (int c = 0; c < nrhs; c += 65535)
-      if (int rc = tlr_trsm_forward(A, d_V + (int64_t)c * ldv, std::min(65535, nrhs - c), ldv, st))
+  constexpr int RHS_CHUNK = 256;  // right-hand sides per pass (bounds the scratch)
+  if (nrhs > RHS_CHUNK) {
+    for (int c = 0; c < nrhs; c += RHS_CHUNK)
+      if (int rc = tlr_trsm_forward(A, d_V + (int64_t)c * ldv, std::min(RHS_CHUNK, nrhs - c), ldv,
+                                    st))
         return rc;
     return 0;
   }
   const TlrState *S = A->tlr;
   const int T = A->T, nb = A->nb, nbp = S->L.nbp;
-  for (int k = 0; k < T; ++k) {
-    hipLaunchKernelGGL(k_tlr_tile_fwd, dim3(1, 1, nrhs), dim3(256), 0, st, nb, nbp, k,
-                       (const double *)A->d_winv, d_V, ldv);
-    if (int rc = check_launch("tlr_tile_fwd")) return rc;
+  // scratch per right-hand side: y_k (nb) and g_ik of every tile below (nb each)
+  const int64_t lds = (int64_t)T * nb;
+  double *scr = nullptr;
+  if (malloc_async((void **)&scr, sizeof(double) * (size_t)lds * nrhs, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR solve: scratch of %.2f MB failed", lds * nrhs * 8.0 / 1e6);
+    return MVG_ERR_ALLOC;
+  }
+  const unsigned rb = (unsigned)((nb + TLR_FWD_RB - 1) / TLR_FWD_RB);
+  const unsigned gc = (unsigned)((nb + TLR_FWD_GC - 1) / TLR_FWD_GC);
+  int rc = 0;
+  for (int k = 0; k < T && !rc; ++k) {
+    hipLaunchKernelGGL(k_tlr_fwd_diag, dim3(rb, 1, nrhs), dim3(256), 0, st, nb, nbp, k,
+                       (const double *)A->d_winv, (const double *)d_V, ldv, scr, lds);
+    rc = check_launch("tlr_fwd_diag");
+    if (rc) break;
     if (k + 1 < T) {
-      hipLaunchKernelGGL(k_tlr_lr_update<true>, dim3(T - k - 1, 1, nrhs), dim3(256), 0, st, T, nb,
-                         k, (const double *)S->L.buf, (const int64_t *)S->d_uoff,
-                         (const int *)S->d_reff, d_V, ldv);
-      if (int rc = check_launch("tlr_lr_update")) return rc;
+      hipLaunchKernelGGL(k_tlr_fwd_g, dim3(T - k - 1, gc, nrhs), dim3(256), 0, st, T, nb, k,
+                         (const double *)S->L.buf, (const int64_t *)S->d_uoff,
+                         (const int *)S->d_reff, scr, lds);
+      rc = check_launch("tlr_fwd_g");
+      if (rc) break;
+      hipLaunchKernelGGL(k_tlr_fwd_apply, dim3(T - k - 1, rb, nrhs), dim3(256), 0, st, T, nb, k,
+                         (const double *)S->L.buf, (const int64_t *)S->d_uoff,
+                         (const int *)S->d_reff, d_V, ldv, (const double *)scr, lds);
+      rc = check_launch("tlr_fwd_apply");
+    } else {
+      hipLaunchKernelGGL(k_tlr_fwd_store, dim3((nb + 255) / 256, 1, nrhs), dim3(256), 0, st, nb, k,
+                         d_V, ldv, (const double *)scr, lds);
+      rc = check_launch("tlr_fwd_store");
     }
   }
-  return 0;
+  hipFreeAsync(scr, st);
+  return rc;
 }
 
 int tlr_trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {

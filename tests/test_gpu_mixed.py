@@ -225,24 +225,28 @@ def test_mixed_ragged_and_wide_band(lib, orc, mode):
         assert dl <= 1e-5
 
 
-def test_mixed_batch_equals_single_calls(lib, orc):
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_mixed_batch_equals_single_calls(lib, orc, mode):
     th0 = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
     x, y, z = _data(orc, 600, 8, th0)
     ths = synthetic.nelder_mead_simplex(th0)[:3]
-    o = {"nb": 128, "precision": lib.MVG_MIXED_FP32}
+    prec = lib.MVG_MIXED_FP32 if mode == "fp32" else lib.MVG_MIXED_BF16X3
+    o = {"nb": 128, "precision": prec}
     batch = lib.loglik(_dev(x), _dev(y), _dev(z), ths, o)
     for i, t in enumerate(ths):
         one = lib.loglik(_dev(x), _dev(y), _dev(z), t, o)
         assert one["loglik"][0] == batch["loglik"][i]
 
 
-def test_mixed_factor_cokriging(lib, orc):
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_mixed_factor_cokriging(lib, orc, mode):
     """Predictions from a resident mixed factor use the refined Sigma^-1 Z."""
     th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
     x, y, z = _data(orc, 800, 3, th)
     x0, y0 = synthetic.uniform_targets(40, 3)
+    prec = lib.MVG_MIXED_FP32 if mode == "fp32" else lib.MVG_MIXED_BF16X3
     res, F = lib.loglik(_dev(x), _dev(y), _dev(z), th,
-                        {"nb": 128, "precision": lib.MVG_MIXED_FP32}, keep=True)
+                        {"nb": 128, "precision": prec}, keep=True)
     assert F is not None
     zh = lib.cokrige_predict(F, _dev(x0), _dev(y0)).cpu().numpy()
     ref = orc.cokrige(x, y, z, th, x0, y0)
