@@ -913,17 +913,19 @@ int tlr_upload_meta(mvg_mat *A, hipStream_t st) {
 
 constexpr int TLR_MAXNB = 2048;
 
-// The forward solve as many small workgroups per step (one workgroup per
-// tile and step kept the offset-1 tile's rank-240 products on one CU, its
-// loads one at a time): per column k,
+// The triangular solves as many small workgroups per step (one workgroup
+// per tile and step kept the offset-1 tile's rank-240 products on one CU,
+// its loads one at a time).  Forward, per column k:
 //   y_k = W_k v_k           (k_tlr_fwd_diag: 64 rows per workgroup),
-//   g_ik = V_ik^T y_k       (k_tlr_fwd_g: 16 columns of V_ik per workgroup),
-//   v_i -= U_ik g_ik, i > k (k_tlr_fwd_apply: 64 rows of U_ik per workgroup;
+//   g_ik = V_ik^T y_k       (k_tlr_solve_g<true>: 16 columns per workgroup),
+//   v_i -= U_ik g_ik, i > k (k_tlr_solve_apply<true>: 64 rows per workgroup;
 //                            the first tile's workgroups also store y_k as v_k).
+// Backward, per row k from the last: y_k = W_k^T v_k (k_tlr_bwd_diag: 16
+// columns per workgroup), g_kj = U_kj^T y_k and v_j -= V_kj g_kj for j < k.
 // y and g live in a scratch of nb (y) + (T - 1) nb (g, nb per tile) doubles per
 // right-hand side.  Every sum is in a fixed order.
 constexpr int TLR_FWD_RB = 64;  // rows per workgroup
-constexpr int TLR_FWD_GC = 16;  // columns of V_ik per workgroup
+constexpr int TLR_FWD_GC = 16;  // columns per workgroup
 
 // y_k = W_k v_k (lower triangular W_k, ld nbp, entries above the diagonal not
 // read as values): lane = row, the four waves take every fourth column
@@ -965,18 +967,20 @@ __global__ __launch_bounds__(256) void k_tlr_fwd_diag(int nb, int nbp, int k,
         (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
-// g_ik = V_ik^T y_k for tile i = k + 1 + blockIdx.x, columns
-// TLR_FWD_GC blockIdx.y .. + TLR_FWD_GC (four per wave, sixteen loads in
-// flight per wave), each a lane-strided sum reduced across the wave.
-__global__ __launch_bounds__(256) void k_tlr_fwd_g(int T, int nb, int k,
-                                                   const double *__restrict__ buf,
-                                                   const int64_t *__restrict__ uoff,
-                                                   const int *__restrict__ reff,
-                                                   double *__restrict__ scr, int64_t lds) {
+// Forward: g_ik = V_ik^T y_k for tile i = k + 1 + blockIdx.x; backward:
+// g_kj = U_kj^T y_k for tile j = blockIdx.x < k.  Columns TLR_FWD_GC
+// blockIdx.y .. + TLR_FWD_GC (four per wave, sixteen loads in flight per
+// wave), each a lane-strided sum reduced across the wave.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_tlr_solve_g(int T, int nb, int k,
+                                                     const double *__restrict__ buf,
+                                                     const int64_t *__restrict__ uoff,
+                                                     const int *__restrict__ reff,
+                                                     double *__restrict__ scr, int64_t lds) {
   __shared__ double x[TLR_MAXNB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = k + 1 + blockIdx.x;
-  const int64_t t = tidx(i, k, T);
+  const int other = FWD ? k + 1 + blockIdx.x : blockIdx.x;
+  const int64_t t = FWD ? tidx(other, k, T) : tidx(k, other, T);
   const int r = reff[t];
   const int c0 = blockIdx.y * TLR_FWD_GC + wave * 4;
   if (blockIdx.y * TLR_FWD_GC >= r) return;  // uniform over the workgroup
@@ -984,10 +988,10 @@ __global__ __launch_bounds__(256) void k_tlr_fwd_g(int T, int nb, int k,
   for (int e = threadIdx.x; e < nb; e += 256) x[e] = sc[e];
   __syncthreads();
   if (c0 >= r) return;  // uniform over the wave; no barrier follows
-  const double *Vt = buf + uoff[t] + (int64_t)nb * r;
+  const double *right = buf + uoff[t] + (FWD ? (int64_t)nb * r : 0);  // V_ik, or U_kj
   const double *col[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) col[j] = Vt + (int64_t)min(c0 + j, r - 1) * nb;
+  for (int j = 0; j < 4; ++j) col[j] = right + (int64_t)min(c0 + j, r - 1) * nb;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int e0 = 0; e0 < nb; e0 += 256) {
     double a[4][4];
@@ -1010,34 +1014,37 @@ __global__ __launch_bounds__(256) void k_tlr_fwd_g(int T, int nb, int k,
   for (int j = 0; j < 4; ++j) {
     double s = acc[j];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && c0 + j < r) sc[nb + (int64_t)(i - k - 1) * nb + c0 + j] = s;
+    if (lane == 0 && c0 + j < r) sc[nb + (int64_t)blockIdx.x * nb + c0 + j] = s;
   }
 }
 
-// v_i -= U_ik g_ik for tile i = k + 1 + blockIdx.x, rows TLR_FWD_RB
+// Forward: v_i -= U_ik g_ik for tile i = k + 1 + blockIdx.x; backward:
+// v_j -= V_kj g_kj for tile j = blockIdx.x < k.  Rows TLR_FWD_RB
 // blockIdx.y .. + TLR_FWD_RB (lane = row, the waves take every fourth
 // column with eight loads in flight, partial sums added in a fixed order);
 // the workgroups of the first tile also store y_k as v_k.
-__global__ __launch_bounds__(256) void k_tlr_fwd_apply(int T, int nb, int k,
-                                                       const double *__restrict__ buf,
-                                                       const int64_t *__restrict__ uoff,
-                                                       const int *__restrict__ reff,
-                                                       double *__restrict__ V, int64_t ldv,
-                                                       const double *__restrict__ scr, int64_t lds) {
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_tlr_solve_apply(int T, int nb, int k,
+                                                         const double *__restrict__ buf,
+                                                         const int64_t *__restrict__ uoff,
+                                                         const int *__restrict__ reff,
+                                                         double *__restrict__ V, int64_t ldv,
+                                                         const double *__restrict__ scr,
+                                                         int64_t lds) {
   __shared__ double g[TLR_MAXNB];
   __shared__ double part[4][TLR_FWD_RB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = k + 1 + blockIdx.x;
-  const int64_t t = tidx(i, k, T);
+  const int other = FWD ? k + 1 + blockIdx.x : blockIdx.x;
+  const int64_t t = FWD ? tidx(other, k, T) : tidx(k, other, T);
   const int r = reff[t];
   const int row = blockIdx.y * TLR_FWD_RB + lane;
   const double *sc = scr + (int64_t)blockIdx.z * lds;
   double *vc = V + (int64_t)blockIdx.z * ldv;
   if (blockIdx.x == 0 && wave == 0 && row < nb) vc[(int64_t)k * nb + row] = sc[row];
   if (r == 0) return;  // uniform over the workgroup
-  for (int e = threadIdx.x; e < r; e += 256) g[e] = sc[nb + (int64_t)(i - k - 1) * nb + e];
+  for (int e = threadIdx.x; e < r; e += 256) g[e] = sc[nb + (int64_t)blockIdx.x * nb + e];
   __syncthreads();
-  const double *U = buf + uoff[t];
+  const double *U = buf + uoff[t] + (FWD ? 0 : (int64_t)nb * r);  // U_ik, or V_kj
   const int rr = min(row, nb - 1);
   double acc[8];
 #pragma unroll
@@ -1055,7 +1062,51 @@ __global__ __launch_bounds__(256) void k_tlr_fwd_apply(int T, int nb, int k,
   part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   if (wave == 0 && row < nb)
-    vc[(int64_t)i * nb + row] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    vc[(int64_t)other * nb + row] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// y_k = W_k^T v_k: output column c is the dot of column c of W_k (rows
+// r >= c) with v_k; columns TLR_FWD_GC blockIdx.x .. + TLR_FWD_GC, four per
+// wave, sixteen loads in flight per wave, each reduced across the wave.
+__global__ __launch_bounds__(256) void k_tlr_bwd_diag(int nb, int nbp, int k,
+                                                      const double *__restrict__ winv,
+                                                      const double *__restrict__ V, int64_t ldv,
+                                                      double *__restrict__ scr, int64_t lds) {
+  __shared__ double v[TLR_MAXNB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
+  const double *W = winv + (int64_t)k * nbp * nbp;
+  for (int e = threadIdx.x; e < nb; e += 256) v[e] = vk[e];
+  __syncthreads();
+  const int c0 = blockIdx.x * TLR_FWD_GC + wave * 4;
+  if (c0 >= nb) return;  // uniform over the wave; no barrier follows
+  const double *col[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) col[j] = W + (int64_t)min(c0 + j, nb - 1) * nbp;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e0 = c0 - c0 % 64; e0 < nb; e0 += 256) {  // rows from the block of c0
+    double a[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = min(e0 + 64 * m + lane, nb - 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[m][j] = col[j][e];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = e0 + 64 * m + lane;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (e < nb && e >= c0 + j) acc[j] += a[m][j] * v[e];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double s = acc[j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && c0 + j < nb) scr[(int64_t)blockIdx.z * lds + c0 + j] = s;
+  }
 }
 
 // v_k = y_k (the last column, which has no tiles below)
@@ -1063,65 +1114,6 @@ __global__ void k_tlr_fwd_store(int nb, int k, double *__restrict__ V, int64_t l
                                 const double *__restrict__ scr, int64_t lds) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < nb) V[(int64_t)blockIdx.z * ldv + (int64_t)k * nb + e] = scr[(int64_t)blockIdx.z * lds + e];
-}
-
-// v_k <- W_k^T v_k
-__global__ __launch_bounds__(256) void k_tlr_tile_bwd(int nb, int nbp, int k,
-                                                      const double *__restrict__ winv,
-                                                      double *__restrict__ V, int64_t ldv) {
-  __shared__ double v[TLR_MAXNB];
-  __shared__ double out[TLR_MAXNB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double *vk = V + (int64_t)blockIdx.z * ldv + (int64_t)k * nb;
-  const double *W = winv + (int64_t)k * nbp * nbp;
-  for (int r = threadIdx.x; r < nb; r += 256) v[r] = vk[r];
-  __syncthreads();
-  for (int c = wave; c < nb; c += 4) {
-    const double *col = W + (int64_t)c * nbp;
-    double t = 0.0;
-    for (int r = c + lane; r < nb; r += 64) t += col[r] * v[r];
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0) out[c] = t;
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < nb; r += 256) vk[r] = out[r];
-}
-
-// Forward update after v_k: v_i -= U_ik (V_ik^T v_k) for i = k + 1 + blockIdx.x.
-// Backward update after w_k: v_j -= V_kj (U_kj^T w_k) for j = blockIdx.x < k.
-template <bool FWD>
-__global__ __launch_bounds__(256) void k_tlr_lr_update(int T, int nb, int k,
-                                                       const double *__restrict__ buf,
-                                                       const int64_t *__restrict__ uoff,
-                                                       const int *__restrict__ reff,
-                                                       double *__restrict__ V, int64_t ldv) {
-  __shared__ double x[TLR_MAXNB];
-  __shared__ double g[TLR_MAXNB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int other = FWD ? k + 1 + blockIdx.x : blockIdx.x;
-  const int64_t t = FWD ? tidx(other, k, T) : tidx(k, other, T);
-  const int r = reff[t];
-  if (r == 0) return;
-  const double *U = buf + uoff[t];
-  const double *Vt = U + (int64_t)nb * r;
-  const double *left = FWD ? U : Vt;   // applied to g
-  const double *right = FWD ? Vt : U;  // contracted with x
-  double *vc = V + (int64_t)blockIdx.z * ldv;
-  for (int i = threadIdx.x; i < nb; i += 256) x[i] = vc[(int64_t)k * nb + i];
-  __syncthreads();
-  for (int c = wave; c < r; c += 4) {
-    const double *col = right + (int64_t)c * nb;
-    double s = 0.0;
-    for (int i = lane; i < nb; i += 64) s += col[i] * x[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) g[c] = s;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += 256) {
-    double s = 0.0;
-    for (int c = 0; c < r; ++c) s += left[(int64_t)c * nb + i] * g[c];
-    vc[(int64_t)other * nb + i] -= s;
-  }
 }
 
 static int tlr_solve_ok(const mvg_mat *A) {
@@ -1161,12 +1153,13 @@ int tlr_trsm_forward(const mvg_mat *A, double *d_V, int nrhs, int64_t ldv, hipSt
     rc = check_launch("tlr_fwd_diag");
     if (rc) break;
     if (k + 1 < T) {
-      hipLaunchKernelGGL(k_tlr_fwd_g, dim3(T - k - 1, gc, nrhs), dim3(256), 0, st, T, nb, k,
+      hipLaunchKernelGGL(k_tlr_solve_g<true>, dim3(T - k - 1, gc, nrhs), dim3(256), 0, st, T, nb, k,
                          (const double *)S->L.buf, (const int64_t *)S->d_uoff,
                          (const int *)S->d_reff, scr, lds);
       rc = check_launch("tlr_fwd_g");
       if (rc) break;
-      hipLaunchKernelGGL(k_tlr_fwd_apply, dim3(T - k - 1, rb, nrhs), dim3(256), 0, st, T, nb, k,
+      hipLaunchKernelGGL(k_tlr_solve_apply<true>, dim3(T - k - 1, rb, nrhs), dim3(256), 0, st, T, nb,
+                         k,
                          (const double *)S->L.buf, (const int64_t *)S->d_uoff,
                          (const int *)S->d_reff, d_V, ldv, (const double *)scr, lds);
       rc = check_launch("tlr_fwd_apply");
@@ -1184,18 +1177,40 @@ int tlr_trsv_backward(const mvg_mat *A, double *d_v, hipStream_t st) {
   if (int rc = tlr_solve_ok(A)) return rc;
   const TlrState *S = A->tlr;
   const int T = A->T, nb = A->nb, nbp = S->L.nbp;
-  for (int k = T - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_tlr_tile_bwd, dim3(1), dim3(256), 0, st, nb, nbp, k,
-                       (const double *)A->d_winv, d_v, A->Np);
-    if (int rc = check_launch("tlr_tile_bwd")) return rc;
+  // scratch: y_k (nb) and g_kj of every tile left of the diagonal (nb each)
+  const int64_t lds = (int64_t)T * nb;
+  double *scr = nullptr;
+  if (malloc_async((void **)&scr, sizeof(double) * (size_t)lds, st) != hipSuccess) {
+    hipGetLastError();
+    set_error("TLR solve: scratch of %.2f MB failed", lds * 8.0 / 1e6);
+    return MVG_ERR_ALLOC;
+  }
+  const unsigned rb = (unsigned)((nb + TLR_FWD_RB - 1) / TLR_FWD_RB);
+  const unsigned gc = (unsigned)((nb + TLR_FWD_GC - 1) / TLR_FWD_GC);
+  int rc = 0;
+  for (int k = T - 1; k >= 0 && !rc; --k) {
+    hipLaunchKernelGGL(k_tlr_bwd_diag, dim3(gc), dim3(256), 0, st, nb, nbp, k,
+                       (const double *)A->d_winv, (const double *)d_v, A->Np, scr, lds);
+    rc = check_launch("tlr_bwd_diag");
+    if (rc) break;
     if (k > 0) {
-      hipLaunchKernelGGL(k_tlr_lr_update<false>, dim3(k), dim3(256), 0, st, T, nb, k,
+      hipLaunchKernelGGL(k_tlr_solve_g<false>, dim3(k, gc), dim3(256), 0, st, T, nb, k,
                          (const double *)S->L.buf, (const int64_t *)S->d_uoff,
-                         (const int *)S->d_reff, d_v, A->Np);
-      if (int rc = check_launch("tlr_lr_update")) return rc;
+                         (const int *)S->d_reff, scr, lds);
+      rc = check_launch("tlr_bwd_g");
+      if (rc) break;
+      hipLaunchKernelGGL(k_tlr_solve_apply<false>, dim3(k, rb), dim3(256), 0, st, T, nb, k,
+                         (const double *)S->L.buf, (const int64_t *)S->d_uoff,
+                         (const int *)S->d_reff, d_v, A->Np, (const double *)scr, lds);
+      rc = check_launch("tlr_bwd_apply");
+    } else {
+      hipLaunchKernelGGL(k_tlr_fwd_store, dim3((nb + 255) / 256), dim3(256), 0, st, nb, k, d_v,
+                         A->Np, (const double *)scr, lds);
+      rc = check_launch("tlr_bwd_store");
     }
   }
-  return 0;
+  hipFreeAsync(scr, st);
+  return rc;
 }
 
 // {2 sum log L_jj over the N real rows, y^T y}: fixed-order two-stage sums
