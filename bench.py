@@ -756,7 +756,8 @@ def run_dense(args, mvg, dev, synthetic, torch):
         _step("dense: oracle timing on the host (bounded sample)")
         extra["cpu_baseline"] = cpu_baseline(n, args.cpu_sample_n, th, args.seed)
     roof = rec.pop("roofline")
-    _line(METRIC, rec["evals_per_s"], "evals/s", args.steps, args.warmup, rec["ms_per_step"],
+    steps, warmup = rec.pop("steps"), rec.pop("warmup")  # the line's own fields
+    _line(METRIC, rec["evals_per_s"], "evals/s", steps, warmup, rec["ms_per_step"],
           "f64", {"workload": rec.pop("workload"), "n_loc": n, "matrix": 2 * n, "nb": rec["nb"],
                   "precision": "fp64", "parallelism": "single GPU"},
           roofline=roof, **rec, **extra)

@@ -134,12 +134,17 @@ __device__ __forceinline__ void matern_p(double x, const MaternArgsP &P,
                 : x <= qlev_xmax(3) ? 3 : 4;
     const int off = qlev_off(j), cnt = qlev_cnt(j);
     logh = log(qlev_h(j));
-    for (int k = 1; k < cnt; ++k) {
+    // nodes in pairs, the stopping test on the second of each pair
+    for (int k = 1; k < cnt; k += 2) {
       const double e = exp(-x * sq[off + k]);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) s[o] += e * sq[(1 + o) * QN + off + k];
+      if (k + 1 >= cnt) break;
+      const double e2 = exp(-x * sq[off + k + 1]);
       bool small = true;
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
-        const double tt = e * sq[(1 + o) * QN + off + k];
+        const double tt = e2 * sq[(1 + o) * QN + off + k + 1];
         s[o] += tt;
         small = small && tt <= 1e-17 * s[o];
       }
