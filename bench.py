@@ -422,7 +422,8 @@ def mixed_record(args, mvg, dev, synthetic, torch, n, nu, beta, reps=1):
         if prec == mvg.MVG_FP64:
             ref = r
         elif int(r["status"][0]) == 0:
-            # an unconverged refinement makes the library evaluate theta in FP64
+            # a lost pivot or an unconverged refinement makes the library
+            # evaluate theta in FP64
             rec["fp64_fallback"] = bool(mvg.mvg_ir_stats(0)["fp64_fallback"])
             rec["rel_dloglik_vs_fp64"] = abs(r["loglik"][0] - ref["loglik"][0]) / abs(ref["loglik"][0])
             rec["dlogdet_vs_fp64"] = float(r["logdet"][0] - ref["logdet"][0])

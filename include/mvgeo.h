@@ -147,7 +147,11 @@ int potrf_tiled(mvg_mat *A, const mvg_opts *o, int64_t *h_info, void *hip_stream
  * keep is set, since predictions use x itself), ir_max_iter
  * sweeps, or stagnation; h_quad = Z^T x + x^T r (the last residual's
  * first-order correction).  h_logdet is that of the mixed factor (not
- * refined).  Memory: the FP64 lower tiles plus the mixed copy.
+ * refined).  A theta whose mixed factor meets a non-positive pivot, or whose
+ * refinement stops without meeting a criterion, is evaluated again in FP64
+ * (its values, status and, with keep, factor are FP64's; mvg_ir_stats marks
+ * it), so h_status > 0 means that the FP64 factor failed too.
+ * Memory: the FP64 lower tiles plus the mixed copy.
  * Requires band_tiles >= 2.
  * MVG_MIXED_FP32X (not in the paper) keeps every tile in FP64 and solves every
  * panel in FP64; only the trailing updates of tiles band_tiles or more
@@ -485,9 +489,10 @@ int mvg_prof_read(int kind, int64_t *launches, double *total_ms, double *flops, 
  * calling thread, theta index i: *iters = correction sweeps applied,
  * *relres = final ||Z - Sigma x|| / ||Z||, *converged = 1 if a stopping
  * criterion (residual or quadratic form) was met, -1 if the refinement
- * stopped without meeting one (sweep budget or stagnation): loglik then
- * evaluated that theta again in FP64 and returned the FP64 values (and, with
- * keep, the FP64 factor).
+ * stopped without meeting one (sweep budget or stagnation) or the mixed
+ * factor met a non-positive pivot (then *iters = 0 and *relres is NaN):
+ * loglik then evaluated that theta again in FP64 and returned the FP64
+ * values and status (and, with keep, the FP64 factor).
  * Returns 0, or -1 if there is no such record. */
 int mvg_ir_stats(int i, int *iters, double *relres, int *converged);
 

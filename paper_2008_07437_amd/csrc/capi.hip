@@ -929,13 +929,16 @@ static int loglik_mixed(const double *d_x, const double *d_y, const double *d_z,
       if (h_quad) h_quad[i] = out2[2 * i + 1];
     }
   }
-  // a refinement that stopped without meeting a criterion (sweep budget or
-  // stagnation) leaves x = Sigma^-1 Z, and so the quadratic form and a kept
-  // factor's w, unconverged: that theta is evaluated again in FP64 (marked
-  // converged = -1 in mvg_ir_stats)
+  // two outcomes of the mixed factor say nothing about Sigma itself and are
+  // evaluated again in FP64 (marked converged = -1 in mvg_ir_stats): a
+  // non-positive pivot met by the low-precision updates (Sigma may still be
+  // positive definite; the FP64 factor decides, and its pivot is the status),
+  // and a refinement that stopped without meeting a criterion (sweep budget
+  // or stagnation), which leaves x = Sigma^-1 Z, and so the quadratic form
+  // and a kept factor's w, unconverged
   bool redo0 = false;
   for (int i = 0; i < n_theta && !rc; ++i) {
-    if (info[i] != INT64_MAX || g_ir[i].converged) continue;
+    if (info[i] == INT64_MAX && g_ir[i].converged) continue;
     if (i == 0 && F) {
       redo0 = true;
       continue;

@@ -316,3 +316,58 @@ def test_mixed_unconverged_refinement_falls_back_to_fp64(lib, orc):
     a = lib.cokrige_predict(F, _dev(x0), _dev(y0)).cpu().numpy()
     b = lib.cokrige_predict(F64, _dev(x0), _dev(y0)).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_mixed_lost_definiteness_falls_back_to_fp64(lib, orc):
+    """A smooth, strongly correlated field (nu = 1.5 in both variables,
+    a = 0.3; condition number about 5e7 at n = 600) is positive definite in
+    FP64, but BF16 operands in the off-band updates drive the first tile they
+    reach to a non-positive pivot (the emulation fails at pivot 385, the first
+    row of tile 3): loglik evaluates that theta in FP64 instead (the FP64
+    values bitwise, status 0, the FP64 factor with keep), and mvg_ir_stats
+    reports the fall-back with no refinement sweep."""
+    th = (1.0, 1.0, 0.3, 1.5, 1.5, 0.5)
+    n, nb = 600, 128
+    x, y, z = _data(orc, n, 1, th)
+    S = orc.cov_dense(x, y, th)
+    _, info = orc.mixed_cholesky_emulated(S, nb, 2, "bf16", "fp32")
+    assert info > 0
+    X, Y, Z = _dev(x), _dev(y), _dev(z)
+    f64 = lib.loglik(X, Y, Z, th, {"nb": nb})
+    assert f64["status"][0] == 0
+    o = {"nb": nb, "precision": lib.MVG_MIXED_BF16, "band_tiles": 2}
+    got = lib.loglik(X, Y, Z, [th, th], o)
+    for i in range(2):
+        s = lib.mvg_ir_stats(i)
+        assert s["fp64_fallback"] and s["iters"] == 0 and np.isnan(s["relres"]), s
+        assert got["status"][i] == 0
+        for key in ("loglik", "logdet", "quad"):
+            assert got[key][i] == f64[key][0], key
+    res, F = lib.loglik(X, Y, Z, th, o, keep=True)
+    assert lib.mvg_ir_stats(0)["fp64_fallback"] and F is not None
+    assert res["loglik"][0] == f64["loglik"][0]
+    _, F64 = lib.loglik(X, Y, Z, th, {"nb": nb}, keep=True)
+    x0, y0 = synthetic.uniform_targets(7, 4)
+    a = lib.cokrige_predict(F, _dev(x0), _dev(y0)).cpu().numpy()
+    b = lib.cokrige_predict(F64, _dev(x0), _dev(y0)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_mixed_singular_sigma_reports_the_fp64_pivot(lib, orc):
+    """A repeated location makes Sigma singular: the mixed factor fails, the
+    FP64 evaluation fails too, and loglik reports FP64's pivot with
+    loglik = -inf (no kept factor)."""
+    th = (1.0, 1.0, 0.1, 0.5, 1.0, 0.5)
+    n, nb = 600, 128
+    x, y, z = _data(orc, n, 1, th)
+    x, y = x.copy(), y.copy()
+    x[300], y[300] = x[299], y[299]
+    X, Y, Z = _dev(x), _dev(y), _dev(z)
+    f64 = lib.loglik(X, Y, Z, th, {"nb": nb})
+    assert f64["status"][0] > 0
+    for prec in (lib.MVG_MIXED_FP32, lib.MVG_MIXED_BF16X3):
+        res, F = lib.loglik(X, Y, Z, th, {"nb": nb, "precision": prec, "band_tiles": 2},
+                            keep=True)
+        assert lib.mvg_ir_stats(0)["fp64_fallback"]
+        assert res["status"][0] == f64["status"][0] and res["loglik"][0] == -np.inf
+        assert F is None
